@@ -1,0 +1,67 @@
+"""Reference gradients of the differentiable PM forward model (FP64).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Not part of the paper: the forward map white noise -> Zel'dovich ICs -> leapfrog
+PM steps -> CIC counting density -> P(k) -> loss is differentiated exactly by
+reverse-mode automatic differentiation of the oracle's own plain operations
+(``torch.autograd``).  At a CIC kink (a particle exactly on a cell edge) the
+derivative of floor() is taken as zero, i.e. the right derivative of the
+weights, consistently with the assignment.
+
+Loss (reading): L = sum_b (P_b - T_b)^2 / T_b^2 over the bins with T_b > 0.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import cic, estimators, ics, integrate, cosmology as cm
+
+
+def pk_loss(pk: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    sel = target > 0
+    return (((pk[sel] - target[sel]) / target[sel]) ** 2).sum()
+
+
+def forward_pk(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, grad: str = "spectral"):
+    """Final-time P(k) of a Newtonian run started from ``noise``."""
+    pos, mom = ics.zeldovich(noise, p)
+    force = integrate.NewtonForce(p.n, p.cosmo, grad)
+    pos, mom = integrate.run_kdk(pos, mom, a_steps, force, p.n, p.cosmo)
+    delta = cic.deposit_delta(pos, p.n)
+    return estimators.power_spectrum(delta, p.box, n_bins)
+
+
+def loss(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, target: torch.Tensor,
+         grad: str = "spectral") -> torch.Tensor:
+    _, pk, _ = forward_pk(noise, p, a_steps, n_bins, grad)
+    return pk_loss(pk, target)
+
+
+def loss_and_grad(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, target: torch.Tensor,
+                  grad: str = "spectral"):
+    """(L, dL/dnoise) by reverse-mode differentiation of the FP64 forward model."""
+    w = noise.detach().to(torch.float64).clone().requires_grad_(True)
+    val = loss(w, p, a_steps, n_bins, target, grad)
+    (g,) = torch.autograd.grad(val, w)
+    return float(val.detach()), g
+
+
+def vjp(fn, primals, cotangent):
+    """Vector-Jacobian product of ``fn`` at ``primals`` (a tuple of tensors)."""
+    xs = tuple(t.detach().clone().requires_grad_(True) for t in primals)
+    out = fn(*xs)
+    gs = torch.autograd.grad(out, xs, grad_outputs=cotangent, allow_unused=True)
+    return tuple(torch.zeros_like(x) if g is None else g for x, g in zip(xs, gs))
+
+
+def step_vjp(pos, mom, kick: float, drift: float, n: int, cosmo: cm.Cosmo, lam_pos, lam_mom, grad="spectral"):
+    """Cotangents (lam_pos_in, lam_mom_in) of one force-kick-drift cycle."""
+    force = integrate.NewtonForce(n, cosmo, grad)
+
+    def cycle(x, p):
+        x1, p1 = integrate.force_then_kick_drift(x, p, kick, drift, force, 0.0, n)
+        return torch.cat([x1.reshape(-1), p1.reshape(-1)])
+
+    ct = torch.cat([lam_pos.reshape(-1), lam_mom.reshape(-1)])
+    return vjp(cycle, (pos, mom), ct)

@@ -1,0 +1,132 @@
+"""Power-spectrum and FFT-bispectrum estimators (FP64).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Definitions: eq. powerspectrum, <delta(k1) delta(k2)> = (2 pi)^3 delta_D(k1+k2) P(k1),
+and eq. bispectre, <delta(k1) delta(k2) delta(k3)> = (2 pi)^3 delta_D(k1+k2+k3) B.
+With the continuum amplitude (V/N^3) dhat and (2 pi)^3 delta_D(0) = V,
+
+    P = (V / N^6) <|dhat|^2>_shell,     B = (V^2 / N^9) <dhat dhat dhat>_closed triangles.
+
+Power-spectrum bins (binning is not stated in the paper; reading): bin width
+w = (N/2)/n_bins in units of k_f, bin b holds the modes with
+w (b + 1/2) <= |n| < w (b + 3/2), decided in integers as
+N^2 (2b+1)^2 <= 16 n_bins^2 |n|^2 < N^2 (2b+3)^2.  k = 0 and corner modes beyond
+the last bin are dropped.  The raw estimator is returned: no shot-noise
+subtraction and no CIC deconvolution.
+
+Bispectrum (FFT shell estimator): for shells S_i with centre c_i and width w
+(units of k_f; membership (2c - w)^2 <= 4|n|^2 < (2c + w)^2 evaluated in
+float64), delta_i = IDFT(dhat 1_{S_i}) and I_i = IDFT(1_{S_i}); then
+    sum_x delta_a delta_b delta_c = N^-6 sum_{n1+n2+n3=0} dhat dhat dhat,
+    sum_x I_a I_b I_c             = N^-6 N_tri,
+so B = (V^2/N^9) sum_x delta_a delta_b delta_c / sum_x I_a I_b I_c.  The paper's
+squeezed configurations fix k3 = 4 k_f (Sec. 4.2).
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import fourier
+
+
+def mode_norm_sq(n: int) -> torch.Tensor:
+    """|n|^2 (integer) on the r2c grid, int64 [N,N,N/2+1]."""
+    nx, ny, nz = fourier.int_freqs(n)
+    return (nx * nx + ny * ny + nz * nz).expand(n, n, n // 2 + 1)
+
+
+def pk_bin_index(n: int, n_bins: int) -> torch.Tensor:
+    """Bin of each r2c mode (-1 if in no bin), decided in integers."""
+    s = 16 * n_bins * n_bins * mode_norm_sq(n)
+    out = torch.full(s.shape, -1, dtype=torch.long)
+    for b in range(n_bins):
+        lo = n * n * (2 * b + 1) ** 2
+        hi = n * n * (2 * b + 3) ** 2
+        out = torch.where((s >= lo) & (s < hi), torch.full_like(out, b), out)
+    return out
+
+
+def power_spectrum_from_k(dhat: torch.Tensor, n: int, box: float, n_bins: int):
+    """(k_mean [h/Mpc], P [(Mpc/h)^3], n_modes) from r2c amplitudes."""
+    b = pk_bin_index(n, n_bins).reshape(-1)
+    wt = fourier.r2c_weights(n).expand(n, n, n // 2 + 1).reshape(-1)
+    p2 = (dhat.real ** 2 + dhat.imag ** 2).reshape(-1)
+    kmag = torch.sqrt(mode_norm_sq(n).double()).reshape(-1)
+    sel = b >= 0
+    cnt = torch.zeros(n_bins, dtype=torch.float64).index_add(0, b[sel], wt[sel])
+    sp = torch.zeros(n_bins, dtype=torch.float64).index_add(0, b[sel], (wt * p2)[sel])
+    sk = torch.zeros(n_bins, dtype=torch.float64).index_add(0, b[sel], (wt * kmag)[sel])
+    kf = 2.0 * math.pi / box
+    vol = box ** 3
+    safe = torch.where(cnt > 0, cnt, torch.ones_like(cnt))
+    pk = torch.where(cnt > 0, vol / n ** 6 * sp / safe, torch.zeros_like(cnt))
+    km = torch.where(cnt > 0, kf * sk / safe, torch.zeros_like(cnt))
+    return km, pk, cnt.round().long()
+
+
+def power_spectrum(delta: torch.Tensor, box: float, n_bins: int):
+    """Raw P(k) of a real density-contrast mesh (eq. powerspectrum)."""
+    n = delta.shape[0]
+    return power_spectrum_from_k(fourier.rfft3(delta), n, box, n_bins)
+
+
+def shell_mask(n: int, centre: float, width: float) -> torch.Tensor:
+    """1_{S}: (2c - w)^2 <= 4|n|^2 < (2c + w)^2 on the r2c grid (float64 decision)."""
+    s4 = 4.0 * mode_norm_sq(n).double()
+    lo = (2.0 * centre - width) ** 2
+    hi = (2.0 * centre + width) ** 2
+    return ((s4 >= lo) & (s4 < hi)).double()
+
+
+def bispectrum(delta: torch.Tensor, box: float, centres, width: float, triangles):
+    """FFT shell estimator.  ``triangles`` lists (a, b, c) shell ids.
+    Returns (B [(Mpc/h)^6], N_tri float64 (sum_x I_a I_b I_c times N^6))."""
+    n = delta.shape[0]
+    dhat = fourier.rfft3(delta)
+    used = sorted({s for tri in triangles for s in tri})
+    fields, inds = {}, {}
+    for s in used:
+        m = shell_mask(n, centres[s], width)
+        fields[s] = fourier.irfft3(dhat * m, n)
+        inds[s] = fourier.irfft3(m.to(torch.complex128), n)
+    vol = box ** 3
+    bk, ntri = [], []
+    for a, b, c in triangles:
+        num = float((fields[a] * fields[b] * fields[c]).sum())
+        den = float((inds[a] * inds[b] * inds[c]).sum())
+        bk.append(vol ** 2 / n ** 9 * num / den if den != 0.0 else 0.0)
+        ntri.append(den * n ** 6)
+    return torch.tensor(bk, dtype=torch.float64), torch.tensor(ntri, dtype=torch.float64)
+
+
+def brute_bispectrum(delta: torch.Tensor, box: float, centres, width: float, triangles):
+    """Direct sum over closed triangles of full-cube modes (pin for tiny meshes)."""
+    n = delta.shape[0]
+    full = torch.fft.fftn(delta.to(torch.complex128))
+    f = torch.fft.fftfreq(n, d=1.0 / n).round().long().tolist()
+    modes = [(a, b, c) for a in f for b in f for c in f]
+    def inshell(m, s):
+        r2 = 4.0 * (m[0] ** 2 + m[1] ** 2 + m[2] ** 2)
+        return (2 * centres[s] - width) ** 2 <= r2 < (2 * centres[s] + width) ** 2
+    def fold(v):
+        v = v % n
+        return v - n if v >= n // 2 else v
+    vol = box ** 3
+    out_b, out_n = [], []
+    for a, b, c in triangles:
+        sa = [m for m in modes if inshell(m, a)]
+        sb = [m for m in modes if inshell(m, b)]
+        tot, cnt = 0.0 + 0.0j, 0
+        for m1 in sa:
+            for m2 in sb:
+                m3 = tuple(fold(-(m1[d] + m2[d])) for d in range(3))
+                if inshell(m3, c):
+                    tot += complex(full[m1[0] % n, m1[1] % n, m1[2] % n] * full[m2[0] % n, m2[1] % n, m2[2] % n]
+                                   * full[m3[0] % n, m3[1] % n, m3[2] % n])
+                    cnt += 1
+        out_b.append(vol ** 2 / n ** 9 * tot.real / cnt if cnt else 0.0)
+        out_n.append(float(cnt))
+    return torch.tensor(out_b, dtype=torch.float64), torch.tensor(out_n, dtype=torch.float64)

@@ -1,0 +1,162 @@
+"""Zel'dovich initial conditions for the Newtonian and Poisson-gauge particle sets (FP64).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+The paper starts all runs from the same random phases (Sec. 2 and Sec. 3),
+with second-order initial conditions at z = 50 (Sec. 3).  This oracle uses the
+first-order (Zel'dovich) displacement, as the benchmark configurations ask:
+
+  * white noise w (unit variance per cell) is an input;
+  * linear density: delta_L_hat(n) = DFT(w)(n) sqrt(P(k)/dx^3) D(a_i)/D(a_norm),
+    with k = k_f |n|, k_f = 2 pi / L, the k = 0 mode and every Nyquist plane zeroed;
+  * displacement: Psi_hat = i k_g delta_L_hat / k_g^2 (so -div Psi = delta_L),
+    evaluated on the Lagrangian lattice q = (i + 1/2, j + 1/2, l + 1/2) by the
+    phase factor exp(i k_g . (1/2, 1/2, 1/2));
+  * Newtonian set: x = wrap(q + Psi), p = a^2 E(a) f(a) Psi  (grid units).
+
+Poisson-gauge set (linear reading of eqs. physical_density, b1 and bgr): the
+counting density of matter in Poisson gauge is, at linear order,
+delta_N (1 + (3 f + (9/2) Omega_m(a)) H^2 / k^2), which is produced by the
+extra displacement
+    xi_lin_hat(n, a) = i k_g g(a) delta_L_hat(n) / k_g^4,
+    g(a) = (3 f(a) + (9/2) Omega_m(a)) calH_g(a)^2 D(a)/D(a_i),
+evaluated on the same lattice.  The relativistic set starts at
+x_GR = wrap(x_N + xi_lin(a_i)), p_GR = p_N + a^2 E d xi_lin / d ln a.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import cic, cosmology as cm, fourier
+
+
+@dataclass(frozen=True)
+class ICParams:
+    n: int                    # particles per axis = mesh cells per axis
+    box: float                # L, Mpc/h
+    a_init: float             # scale factor of the initial conditions
+    power: cm.PowerSpec       # linear P(k) (Mpc/h)^3 at a_norm
+    a_norm: float = 1.0       # scale factor at which ``power`` is the linear spectrum
+    cosmo: cm.Cosmo = cm.FIDUCIAL
+
+    @property
+    def dx(self) -> float:
+        return self.box / self.n
+
+
+def _power_on_grid(p: ICParams) -> torch.Tensor:
+    """P(k_f |n|) on the r2c grid, evaluated once per distinct |n|^2."""
+    nx, ny, nz = fourier.int_freqs(p.n)
+    n2 = (nx * nx + ny * ny + nz * nz)
+    uniq, inv = torch.unique(n2.reshape(-1), return_inverse=True)
+    kf = 2.0 * math.pi / p.box
+    vals = torch.tensor([p.power(kf * math.sqrt(float(u))) for u in uniq.tolist()], dtype=torch.float64)
+    return vals[inv].reshape(n2.shape)
+
+
+def linear_delta_k(noise: torch.Tensor, p: ICParams) -> torch.Tensor:
+    """delta_L_hat at a_init on the r2c grid (k = 0 and Nyquist planes zeroed)."""
+    w_hat = fourier.rfft3(noise.to(torch.float64))
+    growth = cm.growth_d(p.cosmo, p.a_init) / cm.growth_d(p.cosmo, p.a_norm)
+    amp = torch.sqrt(_power_on_grid(p) / p.dx ** 3) * growth
+    mx, my, mz = fourier.nyquist_masks(p.n)
+    keep = ~(mx | my | mz)
+    nx, ny, nz = fourier.int_freqs(p.n)
+    keep = keep & ((nx != 0) | (ny != 0) | (nz != 0))
+    return torch.where(keep, w_hat * amp, torch.zeros_like(w_hat))
+
+
+def _lattice_phase(n: int) -> torch.Tensor:
+    kx, ky, kz = fourier.kgrid(n)
+    ph = 0.5 * (kx + ky + kz)
+    return torch.complex(torch.cos(ph), torch.sin(ph))
+
+
+def _vector_field_on_lattice(scalar_hat: torch.Tensor, n: int, power_of_k2: int) -> torch.Tensor:
+    """IDFT of i k_g scalar_hat / k_g^(2 p) with the half-cell lattice phase -> [3, N^3]."""
+    kx, ky, kz = fourier.kgrid(n)
+    k2 = kx * kx + ky * ky + kz * kz
+    inv = torch.where(k2 > 0, 1.0 / torch.where(k2 > 0, k2, torch.ones_like(k2)) ** power_of_k2,
+                      torch.zeros_like(k2))
+    base = scalar_hat * inv * _lattice_phase(n)
+    comps = []
+    for k in (kx, ky, kz):
+        comps.append(fourier.irfft3(torch.complex(torch.zeros_like(k), k) * base, n).reshape(-1))
+    return torch.stack(comps)
+
+
+def lagrangian_lattice(n: int) -> torch.Tensor:
+    """q_j = (i + 1/2, j + 1/2, l + 1/2) for particle (i N + j) N + l -> [3, N^3]."""
+    q = torch.arange(n, dtype=torch.float64) + 0.5
+    gx, gy, gz = torch.meshgrid(q, q, q, indexing="ij")
+    return torch.stack([gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)])
+
+
+def za_displacement(noise: torch.Tensor, p: ICParams) -> torch.Tensor:
+    """Psi(q) at a_init, [3, N^3] in cells."""
+    return _vector_field_on_lattice(linear_delta_k(noise, p), p.n, 1)
+
+
+def zeldovich(noise: torch.Tensor, p: ICParams):
+    """Newtonian set: (pos, mom), each [3, N^3] float64."""
+    psi = za_displacement(noise, p)
+    a = p.a_init
+    pos = cic.wrap(lagrangian_lattice(p.n) + psi, p.n)
+    mom = a * a * cm.hubble_e(p.cosmo, a) * cm.growth_f(p.cosmo, a) * psi
+    return pos, mom
+
+
+def gr_shift_coefficients(p: ICParams, a: float):
+    """(g(a), dg/dlna) of the linear Poisson-gauge displacement at scale factor a."""
+    c = p.cosmo
+    calh2 = cm.conformal_hubble_grid(c, a, p.dx) ** 2
+    om = cm.omega_m_of_a(c, a)
+    f = cm.growth_f(c, a)
+    fp = cm.growth_f_dlna(c, a)
+    dratio = cm.growth_d(c, a) / cm.growth_d(c, p.a_init)
+    s = 3.0 * f + 4.5 * om
+    g = s * calh2 * dratio
+    # d/dlna: s' = 3 f' + 4.5 Om', Om' = -3 Om (1 - Om); calH^2' = calH^2 (2 - 3 Om); D' = f D
+    sp = 3.0 * fp - 13.5 * om * (1.0 - om)
+    gp = calh2 * dratio * (sp + s * (2.0 - 3.0 * om + f))
+    return g, gp
+
+
+def xi_linear(noise: torch.Tensor, p: ICParams, a: float):
+    """(xi_lin(a), d xi_lin / d ln a) on the lattice, each [3, N^3]."""
+    base = _vector_field_on_lattice(linear_delta_k(noise, p), p.n, 2)
+    g, gp = gr_shift_coefficients(p, a)
+    return g * base, gp * base
+
+
+def zeldovich_pair(noise: torch.Tensor, p: ICParams):
+    """Newtonian and Poisson-gauge sets from the same noise:
+    (pos_N, mom_N, pos_GR, mom_GR)."""
+    pos_n, mom_n = zeldovich(noise, p)
+    xi, dxi = xi_linear(noise, p, p.a_init)
+    a = p.a_init
+    pos_gr = cic.wrap(pos_n + xi, p.n)
+    mom_gr = mom_n + a * a * cm.hubble_e(p.cosmo, a) * dxi
+    return pos_n, mom_n, pos_gr, mom_gr
+
+
+def powerlaw_for_rms_displacement(n: int, box: float, rms_cells: float, index: float = -2.0) -> cm.PowerSpec:
+    """P(k) = A k^index with A chosen so that the expected 3-D rms Zel'dovich
+    displacement over the discrete (non-Nyquist, n != 0) mode set is ``rms_cells``.
+
+    By Parseval, E <|Psi|^2> = N^-3 sum_n P(k)/(dx^3 k_g^2) over the full cube, and with
+    P = A k^index = A (k_g/dx)^index:  A = rms^2 dx^3 N^3 / sum_n dx^-index k_g^(index-2)."""
+    dx = box / n
+    f = torch.fft.fftfreq(n, d=1.0 / n).round()
+    nx, ny, nz = torch.meshgrid(f, f, f, indexing="ij")
+    keep = (nx.abs() < n // 2) & (ny.abs() < n // 2) & (nz.abs() < n // 2)
+    keep = keep & ((nx != 0) | (ny != 0) | (nz != 0))
+    kg2 = (2.0 * math.pi / n) ** 2 * (nx * nx + ny * ny + nz * nz)
+    terms = torch.where(keep, torch.where(keep, kg2, torch.ones_like(kg2)) ** ((index - 2.0) / 2.0),
+                        torch.zeros_like(kg2))
+    s = float(terms.sum()) * dx ** (-index)
+    amp = rms_cells ** 2 * dx ** 3 * n ** 3 / s
+    return cm.PowerSpec("powerlaw", amp, index)

@@ -1,0 +1,273 @@
+"""Pins of the oracle's initial conditions and leapfrog integrator."""
+import math
+
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import cic, cosmology as cm, fourier, ics, integrate, solve
+
+C65 = cm.Cosmo(n_s=0.965)
+
+
+def _ic(n, box, a_i=0.02, rms=None, power=None, a_norm=None):
+    if power is None:
+        power = ics.powerlaw_for_rms_displacement(n, box, rms)
+        a_norm = a_i
+    return ics.ICParams(n=n, box=box, a_init=a_i, power=power, a_norm=a_norm if a_norm else 1.0)
+
+
+def test_za_divergence_is_minus_linear_density():
+    n, box = 16, 500.0
+    p = _ic(n, box, rms=0.3)
+    noise = torch.from_numpy(si.white_noise(n, 4))
+    dl = ics.linear_delta_k(noise, p)
+    psi = ics.za_displacement(noise, p).reshape(3, n, n, n)
+    # spectral divergence of the lattice field, compared to delta_L shifted by half a cell
+    ks = fourier.kgrid(n)
+    div = sum(torch.complex(torch.zeros_like(k), k) * fourier.rfft3(psi[d]) for d, k in enumerate(ks))
+    kx, ky, kz = ks
+    ph = 0.5 * (kx + ky + kz)
+    want = dl * torch.complex(torch.cos(ph), torch.sin(ph))
+    assert torch.allclose(-div, want, atol=1e-10 * float(want.abs().max()))
+
+
+def test_za_lattice_phase_by_direct_evaluation():
+    # Psi(q) = N^-3 sum_n i k delta_L(n)/k^2 exp(i k.q) evaluated directly at q = node + 1/2.
+    n, box = 6, 300.0
+    p = _ic(n, box, rms=0.3)
+    noise = torch.from_numpy(si.white_noise(n, 9))
+    dl_field = fourier.irfft3(ics.linear_delta_k(noise, p), n)
+    full = torch.fft.fftn(dl_field.to(torch.complex128))
+    f = torch.fft.fftfreq(n, d=1.0 / n)
+    psi = ics.za_displacement(noise, p)
+    for j in [0, 7, 100, n ** 3 - 1]:
+        i3 = (j // (n * n), (j // n) % n, j % n)
+        q = [c + 0.5 for c in i3]
+        acc = [0j, 0j, 0j]
+        for a in range(n):
+            for b in range(n):
+                for c in range(n):
+                    kv = [2 * math.pi * float(f[a]) / n, 2 * math.pi * float(f[b]) / n, 2 * math.pi * float(f[c]) / n]
+                    k2 = sum(v * v for v in kv)
+                    if k2 == 0:
+                        continue
+                    e = complex(math.cos(sum(kk * qq for kk, qq in zip(kv, q))),
+                                math.sin(sum(kk * qq for kk, qq in zip(kv, q))))
+                    amp = complex(full[a, b, c]) / k2 * e
+                    for d in range(3):
+                        acc[d] += 1j * kv[d] * amp
+        for d in range(3):
+            assert abs(acc[d].real / n ** 3 - float(psi[d, j])) < 1e-12
+            assert abs(acc[d].imag) / n ** 3 < 1e-12
+
+
+def test_powerlaw_rms_displacement_in_expectation():
+    n, box = 16, 1000.0
+    p = _ic(n, box, rms=0.2)
+    vals = []
+    for seed in range(24):
+        psi = ics.za_displacement(torch.from_numpy(si.white_noise(n, 1000 + seed)), p)
+        vals.append(float((psi ** 2).sum(0).mean()))
+    assert math.sqrt(sum(vals) / len(vals)) == pytest.approx(0.2, rel=0.08)
+
+
+def test_sigma8_of_generated_field():
+    # A field drawn with the sigma8-normalised spectrum, smoothed with an 8 Mpc/h top hat, has
+    # variance sigma8^2 (minus the small power outside the mesh's k-range).
+    n, box = 64, 256.0
+    ps = cm.eh98_normalised(C65, 0.965, 0.81)
+    p = ics.ICParams(n=n, box=box, a_init=1.0, power=ps, a_norm=1.0, cosmo=C65)
+    vals = []
+    for seed in range(3):
+        dl = ics.linear_delta_k(torch.from_numpy(si.white_noise(n, 50 + seed)), p)
+        nx, ny, nz = fourier.int_freqs(n)
+        k = 2 * math.pi / box * torch.sqrt((nx * nx + ny * ny + nz * nz).double())
+        x = k * 8.0
+        w = torch.where(x > 1e-8, 3 * (torch.sin(x) - x * torch.cos(x)) / torch.where(x > 1e-8, x, torch.ones_like(x)) ** 3,
+                        torch.ones_like(x))
+        sm = fourier.irfft3(dl * w, n)
+        vals.append(float((sm ** 2).mean()))
+    assert math.sqrt(sum(vals) / 3) == pytest.approx(0.81, rel=0.05)
+
+
+def _plane_wave_ics(n, amp_frac, a_i, cosmo):
+    """1-D Zel'dovich plane wave along x with k = k_f, amplitude a fraction of shell crossing at a=1."""
+    q = ics.lagrangian_lattice(n)
+    k = 2 * math.pi / n
+    g = cm.growth_d(cosmo, 1.0) / cm.growth_d(cosmo, a_i)
+    b = amp_frac / (k * g)
+    psi = torch.zeros_like(q)
+    psi[0] = b * torch.sin(k * q[0])
+    pos = cic.wrap(q + psi, n)
+    mom = a_i * a_i * cm.hubble_e(cosmo, a_i) * cm.growth_f(cosmo, a_i) * psi
+    return q, psi, pos, mom
+
+
+@pytest.mark.slow
+def test_zeldovich_plane_wave_growth_second_order():
+    c = cm.FIDUCIAL
+    a_i, steps = 0.02, 40
+    errs = []
+    for n in (32, 64):
+        q, psi, pos, mom = _plane_wave_ics(n, 0.01, a_i, c)
+        a_s = cm.log_steps(a_i, 1.0, steps)
+        pos1, _ = integrate.run_kdk(pos, mom, a_s, integrate.NewtonForce(n, c), n, c)
+        g = cm.growth_d(c, 1.0) / cm.growth_d(c, a_i)
+        disp = pos1[0] - q[0]
+        disp = disp - n * torch.round(disp / n)
+        errs.append(float(torch.linalg.norm(disp - g * psi[0]) / torch.linalg.norm(g * psi[0])))
+    # PM growth deficit of the exact Zel'dovich solution: ~1.5% at 32^3, converging with
+    # the mesh spacing (close to second order).
+    assert errs[0] < 0.02
+    assert errs[1] < errs[0] / 2.2
+
+
+def test_force_free_drift_bookkeeping():
+    n = 8
+    c = cm.FIDUCIAL
+    pos = torch.from_numpy(si.uniform_particles(n, 50, seed=1))
+    mom = torch.from_numpy(si.rng(2).standard_normal((3, 50))) * 0.01
+    a_s = cm.log_steps(0.1, 1.0, 7)
+    pos1, mom1 = integrate.run_kdk(pos, mom, a_s, lambda x, a: torch.zeros_like(x), n, c)
+    total = sum(cm.drift_factor(c, a0, a1) for a0, a1 in zip(a_s[:-1], a_s[1:]))
+    assert torch.equal(mom1, mom)
+    want = cic.wrap(pos + mom * total, n)
+    diff = (pos1 - want + n / 2) % n - n / 2
+    assert float(diff.abs().max()) < 1e-12
+
+
+def test_momentum_conservation_and_fused_chain():
+    n = 16
+    c = cm.FIDUCIAL
+    p = _ic(n, 400.0, rms=0.4)
+    pos, mom = ics.zeldovich(torch.from_numpy(si.white_noise(n, 3)), p)
+    a_s = cm.log_steps(0.02, 0.2, 5)
+    f = integrate.NewtonForce(n, c)
+    pos1, mom1 = integrate.run_kdk(pos, mom, a_s, f, n, c)
+    assert float(mom1.sum(1).abs().max()) < 1e-10 * float(mom1.abs().sum())
+    # the same run as a chain of force-kick-drift cycles with merged half kicks
+    x, v = pos.clone(), mom.clone()
+    k2_prev = 0.0
+    for a0, a1 in zip(a_s[:-1], a_s[1:]):
+        k1, dr, k2 = integrate.kdk_factors(c, a0, a1)
+        x, v = integrate.force_then_kick_drift(x, v, k2_prev + k1, dr, f, a0, n)
+        k2_prev = k2
+    x, v = integrate.force_then_kick_drift(x, v, k2_prev, 0.0, f, a_s[-1], n)
+    dx = (x - pos1 + n / 2) % n - n / 2
+    assert float(dx.abs().max()) < 1e-11
+    assert torch.allclose(v, mom1, atol=1e-12)
+
+
+def test_time_reversibility():
+    n = 16
+    c = cm.FIDUCIAL
+    p = _ic(n, 400.0, rms=0.4)
+    pos, mom = ics.zeldovich(torch.from_numpy(si.white_noise(n, 5)), p)
+    a_s = cm.log_steps(0.05, 0.1, 4)
+    f = integrate.NewtonForce(n, c)
+    # forward chain, then the reversed chain with negated momenta
+    x, v = pos.clone(), mom.clone()
+    facs = [integrate.kdk_factors(c, a0, a1) for a0, a1 in zip(a_s[:-1], a_s[1:])]
+    for k1, dr, k2 in facs:
+        v = v + k1 * f(x, 0)
+        x = cic.wrap(x + dr * v, n)
+        v = v + k2 * f(x, 0)
+    v = -v
+    for k1, dr, k2 in reversed(facs):
+        v = v + k2 * f(x, 0)
+        x = cic.wrap(x + dr * v, n)
+        v = v + k1 * f(x, 0)
+    dx = (x - pos + n / 2) % n - n / 2
+    assert float(dx.abs().max()) < 1e-9
+    assert torch.allclose(-v, mom, atol=1e-9)
+
+
+def test_linear_growth_of_za_run():
+    # Small-amplitude ICs: the displacement grows as D(a)/D(a_i) (no decaying mode in the ICs).
+    n = 32
+    c = cm.FIDUCIAL
+    p = _ic(n, 1600.0, rms=0.01)
+    noise = torch.from_numpy(si.white_noise(n, 6))
+    pos, mom = ics.zeldovich(noise, p)
+    psi = ics.za_displacement(noise, p)
+    q = ics.lagrangian_lattice(n)
+    a_s = cm.log_steps(0.02, 0.2, 20)
+    pos1, _ = integrate.run_kdk(pos, mom, a_s, integrate.NewtonForce(n, c), n, c)
+    g = cm.growth_d(c, 0.2) / cm.growth_d(c, 0.02)
+    disp = (pos1 - q + n / 2) % n - n / 2
+    # compare the best-resolved modes (|n| <= sqrt 2); near Nyquist the CIC-smoothed PM force
+    # lags linear growth, which the mesh-convergence pin above covers.
+    nx, ny, nz = fourier.int_freqs(n)
+    low = (nx * nx + ny * ny + nz * nz) <= 2
+    dh = torch.stack([fourier.rfft3(disp[d].reshape(n, n, n)) for d in range(3)])
+    ph = torch.stack([fourier.rfft3(psi[d].reshape(n, n, n)) for d in range(3)])
+    num = float(((dh - g * ph).abs() ** 2 * low).sum())
+    den = float(((g * ph).abs() ** 2 * low).sum())
+    assert math.sqrt(num / den) < 0.03
+
+
+# ---------------------------------------------------------------------------
+# Poisson-gauge set
+# ---------------------------------------------------------------------------
+
+def test_gauge_ics_density_ratio_at_low_k():
+    # eqs. physical_density + b1: delta_count,P = delta_N (1 + (3 f + 9/2 Om) H^2/k^2) at linear order.
+    n, box, a = 16, 6000.0, 0.5
+    c = cm.FIDUCIAL
+    p = ics.ICParams(n=n, box=box, a_init=a, power=ics.powerlaw_for_rms_displacement(n, box, 1e-4), a_norm=a)
+    noise = torch.from_numpy(si.white_noise(n, 12))
+    pn, _, pg, _ = ics.zeldovich_pair(noise, p)
+    dn = fourier.rfft3(cic.deposit_delta(pn, n))
+    dg = fourier.rfft3(cic.deposit_delta(pg, n))
+    calh = cm.conformal_hubble_grid(c, a, box / n)
+    coef = 3 * cm.growth_f(c, a) + 4.5 * cm.omega_m_of_a(c, a)
+    for idx in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1)]:
+        k2 = sum((2 * math.pi * i / n) ** 2 for i in idx)
+        want = 1 + coef * calh ** 2 / k2
+        got = complex(dg[idx]) / complex(dn[idx])
+        assert abs(got - want) < 2e-3 * want, (idx, got, want)
+
+
+def test_gauge_run_equals_newton_run_for_infinite_c():
+    n = 16
+    c = cm.FIDUCIAL
+    p = _ic(n, 500.0, rms=0.3)
+    pos, mom = ics.zeldovich(torch.from_numpy(si.white_noise(n, 21)), p)
+    a_s = cm.log_steps(0.02, 0.1, 4)
+    xn, vn = integrate.run_kdk(pos, mom, a_s, integrate.NewtonForce(n, c), n, c)
+    gf = integrate.GaugeForce(n, 500.0 / n, c, c_g_override=1e9)
+    xg, vg = integrate.run_kdk(pos, mom, a_s, gf, n, c)
+    assert float(((xg - xn + n / 2) % n - n / 2).abs().max()) < 1e-8
+    assert torch.allclose(vg, vn, rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.slow
+def test_gauge_run_keeps_linear_displacement():
+    # Linear regime, horizon-size box: x_GR - x_N follows xi_lin(a) (percent level; the
+    # backward-Euler metric update is first order in the step).
+    n, box = 16, 30000.0
+    c = cm.FIDUCIAL
+    a_i = 0.1
+    p = ics.ICParams(n=n, box=box, a_init=a_i, power=ics.powerlaw_for_rms_displacement(n, box, 1e-5), a_norm=a_i)
+    noise = torch.from_numpy(si.white_noise(n, 31))
+    pn, mn, pg, mg = ics.zeldovich_pair(noise, p)
+    a_s = cm.log_steps(a_i, 1.0, 40)
+    xn, _ = integrate.run_kdk(pn, mn, a_s, integrate.NewtonForce(n, c), n, c)
+    xg, _ = integrate.run_kdk(pg, mg, a_s, integrate.GaugeForce(n, box / n, c), n, c)
+    xi = (xg - xn + n / 2) % n - n / 2
+    want, _ = ics.xi_linear(noise, p, 1.0)
+    err = float(torch.linalg.norm(xi - want) / torch.linalg.norm(want))
+    assert err < 0.015, err
+
+
+@pytest.mark.parametrize("a", [0.02, 0.1, 0.5, 1.0])
+def test_gauge_shift_is_constant_in_time(a):
+    # Both sets feel the same linear potential at the same Lagrangian point, so xi obeys
+    # xi'' + H xi' = 0 with no source: the non-decaying linear xi must be constant.  The
+    # coefficient g(a) = (3 f + 9/2 Om(a)) H^2 D is therefore constant and dg/dlna = 0.
+    p = ics.ICParams(n=16, box=3000.0, a_init=0.02, power=cm.PowerSpec("powerlaw", 1.0, -2.0))
+    g0, _ = ics.gr_shift_coefficients(p, 0.02)
+    g, gp = ics.gr_shift_coefficients(p, a)
+    assert g == pytest.approx(g0, rel=1e-9)
+    assert abs(gp) < 1e-8 * g
