@@ -1,0 +1,175 @@
+"""Benchmark of the PM hot path on one MI355X.
+
+Workload (default): the fine Newtonian run of the displacement-combination
+configuration -- 1024^3 particles on a 1024^3 mesh, periodic box L = 4000 Mpc/h,
+seeded Gaussian white noise, Eisenstein-Hu no-wiggle LCDM spectrum (n_s = 0.965,
+sigma_8 = 0.81) with Zel'dovich initial conditions at a = 0.02, 50 steps log-spaced
+in a to a = 1, FP32.  A "step" is one force-kick-drift cycle of the leapfrog: CIC
+deposit -> r2c FFT -> fused k-space Poisson solve and gradient -> three inverse
+FFTs -> CIC gather fused with kick and drift.  The W warmup steps are the first W
+steps of the schedule; the K timed steps follow them.
+
+Prints one JSON line with particle-updates/s, the roofline of the dominant kernel
+(per-kernel HIP event timing on the library's stream during the timed region) and
+the FP64 CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "PM particle-updates/s at 1024^3 mesh + % HBM roofline; adjoint/forward time ratio"
+
+
+def algorithmic_bytes(n: int, np_: int, es: int = 4):
+    """Minimum HBM bytes per launch of each kernel kind (FP32 unless es = 8)."""
+    n3 = n ** 3
+    c = n * n * (n // 2 + 1)          # complex elements of one spectrum
+    cs = 2 * es                       # bytes per complex
+    return {
+        "fill": es * n3,
+        "deposit": 3 * es * np_ + es * n3,                  # read positions, write the mesh once
+        "fft_r2c_rows": es * n3 + cs * c,
+        "fft_cols_fwd_axis1": 2 * cs * c,
+        "fft_solve_axis0": cs * c + 3 * cs * c,             # read delta_hat, write 3 force spectra
+        "fft_cols_inv_axis1": 3 * 2 * cs * c,
+        "fft_c2r_rows": 3 * cs * c + 3 * es * n3,
+        "gather_kick_drift": 12 * es * np_ + 3 * es * n3,   # x, p read and written; force read once
+    }
+
+
+def cpu_baseline(n_sample: int, seed: int = 5):
+    """One force-kick-drift cycle of the FP64 oracle on n_sample^3 particles."""
+    import torch
+    import synth_inputs as si
+    from oracle import integrate
+    x = torch.from_numpy(si.lattice_jitter_particles(n_sample, seed, 0.8))
+    v = torch.zeros_like(x)
+    force = integrate.NewtonForce(n_sample)
+    t0 = time.perf_counter()
+    integrate.force_then_kick_drift(x, v, 0.01, 0.01, force, 0.5, n_sample)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample ** 3 / dt, "unit": "particle-updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"one force-kick-drift cycle of the FP64 CPU oracle (plain PyTorch) on {n_sample}^3 particles "
+                      f"and a {n_sample}^3 mesh ({dt:.1f} s), scaled per particle-update"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=48)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--box", type=float, default=4000.0)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2404_02783_amd as pm
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, box = args.n, args.box
+    t_setup = time.perf_counter()
+    plan = pm.Plan(n, box, torch.float32, dev)
+    pos = torch.empty((3, n ** 3), dtype=torch.float32, device=dev)
+    mom = torch.empty_like(pos)
+    disp = plan.mesh(3)
+    noise = torch.from_numpy(si.white_noise(n, args.seed, dtype=np.float32)).to(dev)
+    print(f"[bench] noise {n}^3 ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965,
+                      a_init=0.02, a_norm=1.0, cosmo=pm.FIDUCIAL)
+    pm.pm_ic_zeldovich(plan, noise, icp, disp, pos, mom)
+    del noise, disp
+    torch.cuda.synchronize()
+    print(f"[bench] initial conditions ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    total = max(50, args.warmup + args.steps)
+    a_s = pm.sim.log_steps(0.02, 1.0, total)
+    run = pm.sim.Run(plan, pos, mom)
+    k2_prev = 0.0
+
+    def cycle(j):
+        nonlocal k2_prev
+        k1, dr, k2 = pm.kdk_factors(a_s[j], a_s[j + 1])
+        run.cycle(a_s[j], k2_prev + k1, dr)
+        k2_prev = k2
+
+    for j in range(args.warmup):
+        cycle(j)
+    torch.cuda.synchronize()
+    pm.pm_profile_enable(plan, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(args.warmup, args.warmup + args.steps):
+        cycle(j)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = pm.pm_profile_read(plan)
+    pm.pm_profile_enable(plan, False)
+    pm.pm_check(plan)
+    print(f"[bench] timed {args.steps} steps in {t1 - t0:.3f}s", file=sys.stderr, flush=True)
+
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    value = n ** 3 / (ms_step / 1000.0)
+    alg = algorithmic_bytes(n, n ** 3)
+    kernels = {}
+    for name, (ms, cnt) in prof.items():
+        avg = ms / cnt
+        b = alg.get(name)
+        kernels[name] = {"avg_ms": round(avg, 4), "launches": cnt,
+                         "alg_GBps": round(b / (avg / 1000.0) / 1e9, 1) if b else None}
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    dom_avg = prof[dom][0] / prof[dom][1]
+    dom_gbs = alg[dom] / (dom_avg / 1000.0) / 1e9
+    step_bytes = sum(alg.values())
+    step_gbs = step_bytes / (ms_step / 1000.0) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussian white noise -> Zel'dovich ICs)",
+        "config": {"workload": f"Newtonian PM run, {n}^3 particles on a {n}^3 mesh, L={box:g} Mpc/h, EH98 no-wiggle "
+                               f"LCDM ICs at a=0.02, {total} log steps to a=1 (steps {args.warmup}..."
+                               f"{args.warmup + args.steps - 1} timed)",
+                   "n_mesh": n, "n_particles": n ** 3, "box_mpch": box, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBps": round(step_gbs, 1),
+                          "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+        "kernels": kernels,
+        "adjoint_forward_ratio": None,
+    }
+    if not args.no_cpu_baseline:
+        print(f"[bench] CPU oracle baseline at {args.cpu_sample}^3 ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

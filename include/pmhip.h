@@ -1,0 +1,249 @@
+/*
+ * pmhip -- particle-mesh hot path of the relativistic-plus-Newtonian combination
+ * method (Montandon, Hahn & Stahl, arXiv:2404.02783) as hand-written HIP kernels for
+ * AMD MI355X (gfx950).
+ *
+ * C ABI.  Conventions shared by every entry point:
+ *   - Status: every call returns 0 (PM_OK) or a negative PM_ERR_* code.  Argument
+ *     errors are detected before anything is enqueued.  pm_last_error() returns a
+ *     thread-local message describing the last failure.
+ *   - Memory: every array argument is a DEVICE pointer allocated and owned by the
+ *     caller unless the comment says "host".  The library never frees a caller
+ *     pointer and keeps none past the call.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     All device work is enqueued asynchronously on it; results are valid once the
+ *     stream has been synchronised.  Calls on one plan must not run concurrently.
+ *   - Precision: a plan computes in float (PM_F32) or double (PM_F64); every real
+ *     array of a call on that plan uses the plan's type ("real" below), complex
+ *     arrays are interleaved (re, im) pairs of it.
+ *   - Units (grid units): positions lie in [0, N) cells; momenta are
+ *     p = a^2 (dx/dt) / H0 in cells; a kick adds kick * F, a drift adds drift * p.
+ *   - Layouts: particle arrays are structure-of-arrays [3][np] (x block, y block,
+ *     z block); particle j of an N^3 lattice run has Lagrangian index
+ *     j = (i N + k) N + l.  Real meshes are [N][N][N] row-major (last index
+ *     fastest); spectra are [N][N][N/2+1] complex with the forward transform
+ *     unnormalised (dhat(n) = sum_x d(x) exp(-2 pi i n.x/N)).
+ *   - Supported mesh sizes N: 8, 16, 32, 64, 128, 192, 256, 512, 1024.
+ */
+#ifndef PMHIP_H
+#define PMHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PM_OK = 0,
+  PM_ERR_ARG = -1,    /* bad argument (null pointer, negative size, mismatch) */
+  PM_ERR_SIZE = -2,   /* unsupported mesh size */
+  PM_ERR_NOMEM = -3,  /* workspace too small or device allocation failed */
+  PM_ERR_HIP = -4,    /* a HIP runtime call failed */
+  PM_ERR_STATE = -5   /* a device-side guard tripped (non-finite or out-of-box particle) */
+};
+
+enum { PM_F32 = 0, PM_F64 = 1 };
+
+/* Potential solve kinds. */
+enum { PM_NEWTON = 0, PM_POISSON_GAUGE = 1 };
+
+/* Gradient symbols D_d(n) used for F = -grad(phi) in Fourier space. */
+enum {
+  PM_GRAD_SPECTRAL = 0, /* i k_d, zero on the Nyquist plane of axis d */
+  PM_GRAD_FD2 = 1,      /* i sin(k_d): second-order central difference */
+  PM_GRAD_FD1 = 2       /* exp(i k_d) - 1: first-order one-sided difference */
+};
+
+typedef struct pm_plan pm_plan;
+
+/* Scalars of one force evaluation.
+ * PM_NEWTON (Sec. 2: the N-body-gauge equations are the Newtonian ones):
+ *   laplacian(phi) = (3/2) omega_m delta; uses omega_m only.
+ * PM_POISSON_GAUGE (weak-field scalar sector; the paper gives the linear relation
+ *   delta_count = delta_phys - 3 phi, eq. physical_density, and its consequences,
+ *   eqs. b1 and bgr; the field equation is the linear 00 Einstein equation with
+ *   psi = phi and a backward difference for phi'):
+ *   phi_new = [(3/2) calh^2 om_a dhat_c - 3 calh inv_dtau phi_old]
+ *           / [-k^2 - 3 calh^2 - 3 calh inv_dtau - (9/2) calh^2 om_a],
+ *   force = -grad(a c_g^2 phi_new).  calh: conformal Hubble rate in 1/cells;
+ *   c_g: speed of light in cells per (1/H0); inv_dtau: 1/(conformal time since the
+ *   previous evaluation, cells), 0 for a quasi-static first solve. */
+typedef struct {
+  int kind;        /* PM_NEWTON | PM_POISSON_GAUGE */
+  int grad;        /* PM_GRAD_* */
+  double omega_m;  /* Omega_m today (Newtonian prefactor) */
+  double a;        /* scale factor of the evaluation */
+  double om_a;     /* Omega_m(a) */
+  double calh;     /* conformal Hubble rate, 1/cells */
+  double c_g;      /* speed of light, cells per (1/H0) */
+  double inv_dtau; /* 1 / conformal-time step, 1/cells; 0 = quasi-static */
+} pm_solve_params;
+
+/* One force-kick-drift cycle: F = force(x); p += kick * F(x); x = wrap(x + drift * p).
+ * A kick-drift-kick leapfrog is a chain of cycles with kick = K2(previous step) +
+ * K1(this step) and a closing cycle with drift = 0 (see pm_kdk_factors). */
+typedef struct {
+  double kick;
+  double drift;
+  pm_solve_params solve;
+} pm_step_params;
+
+/* Flat LCDM background without radiation (Sec. 3 of the paper). */
+typedef struct {
+  double omega_m;
+  double omega_b;
+  double h;
+  double t_cmb;
+} pm_cosmology;
+
+/* Linear power spectrum at a = a_norm: P(k) = amp * k^index * T(k)^2 with k in h/Mpc,
+ * T = 1 (kind 0, power law) or the Eisenstein & Hu (1998) no-wiggle transfer (kind 1). */
+enum { PM_PK_POWERLAW = 0, PM_PK_EH98 = 1 };
+
+typedef struct {
+  int pk_kind;
+  double amp;
+  double index;
+  double a_init;        /* scale factor of the initial conditions */
+  double a_norm;        /* scale factor at which the spectrum above is linear */
+  pm_cosmology cosmo;
+} pm_ic_params;
+
+/* ---------------------------------------------------------------- plans ------ */
+
+/* Bytes of device workspace a plan of mesh size n and dtype needs: three
+ * [N][N][N/2+1] complex buffers (spectra of the density and the force components). */
+size_t pm_plan_workspace_bytes(int n_mesh, int dtype);
+
+/* Create a plan for an N^3 mesh of a periodic box of side box_mpch (Mpc/h).
+ * workspace: caller device buffer of ws_bytes >= pm_plan_workspace_bytes(), or NULL
+ * to let the plan allocate (and free) its own.  The plan also allocates a few KB of
+ * twiddle tables and counters.  Errors: PM_ERR_SIZE for an unsupported N,
+ * PM_ERR_NOMEM if ws_bytes is too small, PM_ERR_HIP if an allocation fails. */
+int pm_plan_create(pm_plan** out, int n_mesh, double box_mpch, int dtype, void* workspace, size_t ws_bytes);
+int pm_plan_destroy(pm_plan* plan);
+
+/* Reads and clears the device guard counters (synchronises `stream`).
+ * Returns PM_ERR_STATE if, since the last check, the deposit met a non-finite
+ * position (skipped) or a position outside [0, N) (wrapped back in). */
+int pm_check(pm_plan* plan, void* stream);
+
+/* Thread-local description of the last error ("" if none). */
+const char* pm_last_error(void);
+
+/* Per-kernel timing.  While enabled, every kernel launch of the plan is bracketed by
+ * a pair of HIP events recorded on the call's stream (so it also times work inside a
+ * graph-free stream sequence).  Off by default; enabling costs two event records per
+ * launch. */
+int pm_profile_enable(pm_plan* plan, int on);
+/* Sums the recorded launch durations per kernel kind and clears them (waits for the
+ * recorded events).  names: host char[n_max][32]; ms: host double[n_max] (total
+ * milliseconds); count: host int64[n_max] (launches).  Returns the number of kinds
+ * written, or a negative error code (PM_ERR_ARG if profiling is off). */
+int pm_profile_read(pm_plan* plan, int n_max, char* names, double* ms, int64_t* count);
+
+/* ----------------------------------------------------------- hot path ------- */
+
+/* CIC counting density (Sec. 4: counting density of a cloud-in-cell assignment):
+ * delta(c) = sum_p W(x_p - c) / nbar - 1, nbar = np / N^3, with trilinear weights
+ * (1 - t, t) per axis around the base node floor(x).  pos: [3][np] real in [0, N);
+ * delta: [N][N][N] real, overwritten.  np may be 0 (delta = -1).  Summation order
+ * is that of device atomics (not bitwise reproducible; the assignment is). */
+int pm_deposit(pm_plan* plan, const void* pos, int64_t np, void* delta, void* stream);
+
+/* Potential solve and PM force meshes for a density contrast mesh.
+ * delta: [N][N][N] real (read only); force: [3][N][N][N] real, written with
+ * F_d = IDFT(-D_d(n) phi_hat(n)).  phi_state: [N][N][N/2+1] complex potential
+ * phi_hat carried between calls for PM_POISSON_GAUGE (read, then overwritten with
+ * phi_new); ignored (may be NULL) for PM_NEWTON. */
+int pm_solve(pm_plan* plan, const void* delta, const pm_solve_params* sp, void* phi_state, void* force,
+             void* stream);
+
+/* CIC interpolation of the three force meshes to the particles (same weights as the
+ * deposit): acc[d][p] = sum_c W(x_p - c) force[d](c).  acc: [3][np]. */
+int pm_gather(pm_plan* plan, const void* force, const void* pos, int64_t np, void* acc, void* stream);
+
+/* One force-kick-drift cycle in place on (pos, mom) [3][np]: deposit -> solve ->
+ * gather -> kick -> drift, with the periodic wrap x <- x - N floor(x/N) and a result
+ * equal to N set to 0.  force_scratch: [3][N][N][N] real (holds the force meshes on
+ * return); phi_state as in pm_solve. */
+int pm_step(pm_plan* plan, void* pos, void* mom, int64_t np, const pm_step_params* st, void* force_scratch,
+            void* phi_state, void* stream);
+
+/* eq. xiGR and eq. combined: xi = minimum-image (x_gr - x_newton) on the coarse
+ * lattice (n_coarse^3 particles, coarse cells), interpolated with CIC weights in
+ * Lagrangian coordinates to the fine lattice (n_fine^3 particles; fine particle j
+ * per axis sits at coarse coordinate ((2j+1) n_c - n_f)/(2 n_f)), scaled to fine
+ * cells and added: x_out = wrap(x_fine + (n_f/n_c) xi_f).  Requires n_fine to be a
+ * multiple of n_coarse.  x_out may alias x_fine.  All arrays [3][n^3] of `dtype`. */
+int displacement_combine(const void* x_gr, const void* x_newton, int n_coarse, const void* x_fine, int n_fine,
+                         int dtype, void* x_out, void* stream);
+
+/* Power spectrum (eq. powerspectrum), raw estimator without shot-noise subtraction or
+ * deconvolution.  Bin width w = (N/2)/n_bins (units of k_f = 2 pi/L); bin b holds
+ * modes with N^2 (2b+1)^2 <= 16 n_bins^2 |n|^2 < N^2 (2b+3)^2 (integer decision).
+ * Outputs (device, n_bins each): k_mean [h/Mpc] (double), pk [(Mpc/h)^3] (double),
+ * n_modes (int64, modes of the full cube).  delta: [N][N][N] real. */
+int pk_estimate(pm_plan* plan, const void* delta, int n_bins, double* k_mean, double* pk, int64_t* n_modes,
+                void* stream);
+
+/* FFT bispectrum estimator (eq. bispectre).  Shell s holds modes with
+ * (2c_s - w)^2 <= 4|n|^2 < (2c_s + w)^2 (float64 decision, c_s and w in units of k_f).
+ * For triangle t = (a, b, c): B_t = (V^2/N^9) sum_x d_a d_b d_c / sum_x I_a I_b I_c
+ * with d_s = IDFT(dhat 1_s), I_s = IDFT(1_s); ntri_t = N^6 sum_x I_a I_b I_c.
+ * shell_center_kf: host [n_shells]; tri: host [n_tri][3] shell ids; bk, ntri_out:
+ * device double [n_tri].  shell_ws: device scratch for cached shell fields of
+ * shell_ws_bytes >= 3 N^3 sizeof(real) (more bytes = fewer recomputed shells).
+ * If ntri_known is non-NULL (device double [n_tri] from an earlier call with the same
+ * N, shells and triangles) the indicator pass is skipped and it is copied to ntri_out. */
+int bk_estimate(pm_plan* plan, const void* delta, int n_shells, const double* shell_center_kf,
+                double shell_width_kf, const int32_t* tri, int n_tri, double* bk, double* ntri_out,
+                const double* ntri_known, void* shell_ws, size_t shell_ws_bytes, void* stream);
+
+/* ------------------------------------------------- initial conditions ------- */
+
+/* Zel'dovich initial conditions on the half-cell-offset lattice (same random phases
+ * for every run, Secs. 2 and 3; first-order displacement).  noise: [N][N][N] real
+ * unit white noise (read only).  delta_L_hat = DFT(noise) sqrt(P(k)/dx^3)
+ * D(a_init)/D(a_norm), zero at k = 0 and on every Nyquist plane; Psi_hat =
+ * i k delta_L_hat / k^2 evaluated at q = (i,j,l) + 1/2; pos = wrap(q + Psi),
+ * mom = a^2 E f Psi.  disp_scratch: [3][N][N][N] real, overwritten with Psi. */
+int pm_ic_zeldovich(pm_plan* plan, const void* noise, const pm_ic_params* ic, void* disp_scratch, void* pos,
+                    void* mom, void* stream);
+
+/* Poisson-gauge partner set of pm_ic_zeldovich's output (linear reading of eqs.
+ * physical_density, b1, bgr): xi_hat = i k g(a_init) delta_L_hat / k^4 on the same
+ * lattice with g = (3f + (9/2) Omega_m(a)) calh^2; pos_gr = wrap(pos_n + xi),
+ * mom_gr = mom_n + a^2 E (dg/dlna / g) xi.  disp_scratch as above. */
+int pm_ic_gauge(pm_plan* plan, const void* noise, const pm_ic_params* ic, void* disp_scratch,
+                const void* pos_n, const void* mom_n, void* pos_gr, void* mom_gr, void* stream);
+
+/* --------------------------------------------------- host cosmology --------- */
+/* Host-side double-precision scalars that parameterise the kernels.  Growth D(a) is
+ * the Heath integral (5 Om/2) E(a) int_0^a da'/(a' E)^3; f = dlnD/dlna.  Kick and
+ * drift factors: K = int da/(a^2 E), Dr = int da/(a^3 E). */
+double pm_cosmo_hubble_e(const pm_cosmology* c, double a);
+double pm_cosmo_omega_m_a(const pm_cosmology* c, double a);
+double pm_cosmo_growth(const pm_cosmology* c, double a);
+double pm_cosmo_growth_rate(const pm_cosmology* c, double a);
+double pm_cosmo_kick(const pm_cosmology* c, double a0, double a1);
+double pm_cosmo_drift(const pm_cosmology* c, double a0, double a1);
+/* Leapfrog factors of one step a0 -> a1 with half step sqrt(a0 a1): out[0] = K(a0, ah),
+ * out[1] = Dr(a0, a1), out[2] = K(ah, a1). */
+void pm_kdk_factors(const pm_cosmology* c, double a0, double a1, double out[3]);
+/* Solve parameters of a Poisson-gauge evaluation at a (box side box_mpch, mesh n);
+ * a_prev <= 0 marks the first (quasi-static) evaluation. */
+void pm_gauge_params(const pm_cosmology* c, double box_mpch, int n_mesh, double a, double a_prev,
+                     pm_solve_params* out);
+/* Amplitude of the EH98 no-wiggle spectrum with sigma(8 Mpc/h) = sigma8 at a = 1. */
+double pm_power_eh98_amplitude(const pm_cosmology* c, double n_s, double sigma8);
+/* Amplitude of P = A k^index giving an expected 3-D rms Zel'dovich displacement of
+ * rms_cells over the discrete non-Nyquist modes of an N^3 box of side box_mpch. */
+double pm_power_law_amplitude(int n_mesh, double box_mpch, double rms_cells, double index);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMHIP_H */

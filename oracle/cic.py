@@ -21,9 +21,11 @@ import torch
 
 
 def wrap(x: torch.Tensor, n: int) -> torch.Tensor:
-    """Periodic wrap into [0, N): x - N floor(x/N), and a result that rounds up
-    to exactly N is set to 0 (the wrap-rule reading for finite precision)."""
+    """Periodic wrap into [0, N): x - N floor(x/N); a rounded quotient that
+    overshoots (N not a power of two) is corrected by +N, and a result that rounds
+    up to exactly N is set to 0 (the wrap-rule reading for finite precision)."""
     y = x - n * torch.floor(x / n)
+    y = torch.where(y < 0, y + n, y)
     return torch.where(y >= n, torch.zeros_like(y), y)
 
 

@@ -150,7 +150,7 @@ def powerlaw_for_rms_displacement(n: int, box: float, rms_cells: float, index: f
     By Parseval, E <|Psi|^2> = N^-3 sum_n P(k)/(dx^3 k_g^2) over the full cube, and with
     P = A k^index = A (k_g/dx)^index:  A = rms^2 dx^3 N^3 / sum_n dx^-index k_g^(index-2)."""
     dx = box / n
-    f = torch.fft.fftfreq(n, d=1.0 / n).round()
+    f = torch.fft.fftfreq(n, d=1.0 / n, dtype=torch.float64).round()
     nx, ny, nz = torch.meshgrid(f, f, f, indexing="ij")
     keep = (nx.abs() < n // 2) & (ny.abs() < n // 2) & (nz.abs() < n // 2)
     keep = keep & ((nx != 0) | (ny != 0) | (nz != 0))

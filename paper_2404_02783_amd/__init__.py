@@ -1,0 +1,312 @@
+"""pmhip: particle-mesh hot path of arXiv:2404.02783 as hand-written HIP kernels (gfx950).
+
+Thin Python binding of the C ABI in ``include/pmhip.h`` (``libpmhip.so``): every
+function below only marshals torch tensors (device memory) and the current HIP
+stream into the library call of the same name.  There is no fallback: if the
+library is missing or a call fails, a ``PMError`` is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "PMError", "lib", "SolveParams", "StepParams", "Cosmology", "ICParams", "Plan",
+    "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "pk_estimate", "bk_estimate",
+    "pm_ic_zeldovich", "pm_ic_gauge", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
+    "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
+    "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH",
+    "PM_F32", "PM_F64", "PM_NEWTON", "PM_POISSON_GAUGE", "PM_GRAD_SPECTRAL", "PM_GRAD_FD2", "PM_GRAD_FD1",
+    "PM_PK_POWERLAW", "PM_PK_EH98",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpmhip.so")
+
+PM_OK, PM_ERR_ARG, PM_ERR_SIZE, PM_ERR_NOMEM, PM_ERR_HIP, PM_ERR_STATE = 0, -1, -2, -3, -4, -5
+PM_F32, PM_F64 = 0, 1
+PM_NEWTON, PM_POISSON_GAUGE = 0, 1
+PM_GRAD_SPECTRAL, PM_GRAD_FD2, PM_GRAD_FD1 = 0, 1, 2
+PM_PK_POWERLAW, PM_PK_EH98 = 0, 1
+
+_c_int, _c_double, _c_void_p, _c_int64, _c_size_t = (
+    ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t)
+
+
+class PMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pmhip error {code}: {msg}")
+        self.code = code
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("kind", _c_int), ("grad", _c_int), ("omega_m", _c_double), ("a", _c_double),
+                ("om_a", _c_double), ("calh", _c_double), ("c_g", _c_double), ("inv_dtau", _c_double)]
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("kick", _c_double), ("drift", _c_double), ("solve", SolveParams)]
+
+
+class Cosmology(ctypes.Structure):
+    _fields_ = [("omega_m", _c_double), ("omega_b", _c_double), ("h", _c_double), ("t_cmb", _c_double)]
+
+
+class ICParams(ctypes.Structure):
+    _fields_ = [("pk_kind", _c_int), ("amp", _c_double), ("index", _c_double), ("a_init", _c_double),
+                ("a_norm", _c_double), ("cosmo", Cosmology)]
+
+
+# Flat LCDM of the paper's simulation setup (Sec. 3), no radiation.
+FIDUCIAL = Cosmology(omega_m=0.263771 + 0.0482754, omega_b=0.0482754, h=0.67556, t_cmb=2.7255)
+
+_LIB = None
+
+
+def _declare(l):
+    P = ctypes.POINTER
+    sig = {
+        "pm_last_error": (ctypes.c_char_p, []),
+        "pm_plan_workspace_bytes": (_c_size_t, [_c_int, _c_int]),
+        "pm_plan_create": (_c_int, [P(_c_void_p), _c_int, _c_double, _c_int, _c_void_p, _c_size_t]),
+        "pm_plan_destroy": (_c_int, [_c_void_p]),
+        "pm_check": (_c_int, [_c_void_p, _c_void_p]),
+        "pm_profile_enable": (_c_int, [_c_void_p, _c_int]),
+        "pm_profile_read": (_c_int, [_c_void_p, _c_int, ctypes.c_char_p, P(_c_double), P(_c_int64)]),
+        "pm_deposit": (_c_int, [_c_void_p, _c_void_p, _c_int64, _c_void_p, _c_void_p]),
+        "pm_solve": (_c_int, [_c_void_p, _c_void_p, P(SolveParams), _c_void_p, _c_void_p, _c_void_p]),
+        "pm_gather": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int64, _c_void_p, _c_void_p]),
+        "pm_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int64, P(StepParams), _c_void_p, _c_void_p,
+                             _c_void_p]),
+        "displacement_combine": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_int, _c_int, _c_void_p,
+                                          _c_void_p]),
+        "pk_estimate": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+        "bk_estimate": (_c_int, [_c_void_p, _c_void_p, _c_int, P(_c_double), _c_double, P(ctypes.c_int32), _c_int,
+                                 _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_size_t, _c_void_p]),
+        "pm_ic_zeldovich": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+        "pm_ic_gauge": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                 _c_void_p, _c_void_p]),
+        "pm_cosmo_hubble_e": (_c_double, [P(Cosmology), _c_double]),
+        "pm_cosmo_omega_m_a": (_c_double, [P(Cosmology), _c_double]),
+        "pm_cosmo_growth": (_c_double, [P(Cosmology), _c_double]),
+        "pm_cosmo_growth_rate": (_c_double, [P(Cosmology), _c_double]),
+        "pm_cosmo_kick": (_c_double, [P(Cosmology), _c_double, _c_double]),
+        "pm_cosmo_drift": (_c_double, [P(Cosmology), _c_double, _c_double]),
+        "pm_kdk_factors": (None, [P(Cosmology), _c_double, _c_double, P(_c_double)]),
+        "pm_gauge_params": (None, [P(Cosmology), _c_double, _c_int, _c_double, _c_double, P(SolveParams)]),
+        "pm_power_eh98_amplitude": (_c_double, [P(Cosmology), _c_double, _c_double]),
+        "pm_power_law_amplitude": (_c_double, [_c_int, _c_double, _c_double, _c_double]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(l, name)
+        fn.restype = res
+        fn.argtypes = args
+    return l
+
+
+def lib():
+    """The loaded ``libpmhip.so`` (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise PMError(PM_ERR_ARG, f"{LIB_PATH} not built (run python -m paper_2404_02783_amd.build)")
+        _LIB = _declare(ctypes.CDLL(LIB_PATH))
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != PM_OK:
+        raise PMError(rc, lib().pm_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise PMError(PM_ERR_ARG, f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise PMError(PM_ERR_ARG, f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise PMError(PM_ERR_ARG, f"{name} has dtype {t.dtype}, expected {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """An N^3 mesh plan; the spectrum workspace is a torch device buffer."""
+
+    def __init__(self, n: int, box: float, dtype=torch.float32, device=None):
+        self.n = int(n)
+        self.box = float(box)
+        self.dtype = dtype
+        self.cdtype = PM_F32 if dtype == torch.float32 else PM_F64
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        nbytes = lib().pm_plan_workspace_bytes(self.n, self.cdtype)
+        if nbytes == 0:
+            raise PMError(PM_ERR_SIZE, f"unsupported mesh size {n}")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = _c_void_p()
+        _check(lib().pm_plan_create(ctypes.byref(h), self.n, self.box, self.cdtype,
+                                    ctypes.c_void_p(self.workspace.data_ptr()), nbytes))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().pm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # allocation helpers (torch device memory)
+    def mesh(self, ncomp: int = 0):
+        shape = (self.n,) * 3 if ncomp == 0 else (ncomp,) + (self.n,) * 3
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
+
+    def spectrum(self):
+        cd = torch.complex64 if self.dtype == torch.float32 else torch.complex128
+        return torch.zeros((self.n, self.n, self.n // 2 + 1), dtype=cd, device=self.device)
+
+
+def pm_check(plan: Plan):
+    _check(lib().pm_check(plan.handle, _stream()))
+
+
+def pm_profile_enable(plan: Plan, on: bool = True):
+    _check(lib().pm_profile_enable(plan.handle, int(bool(on))))
+
+
+def pm_profile_read(plan: Plan):
+    """{kernel kind: (total ms, launches)} since the last read."""
+    nmax = 32
+    names = ctypes.create_string_buffer(32 * nmax)
+    ms = (ctypes.c_double * nmax)()
+    cnt = (ctypes.c_int64 * nmax)()
+    w = lib().pm_profile_read(plan.handle, nmax, names, ms, cnt)
+    if w < 0:
+        _check(w)
+    raw = names.raw
+    return {raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode(): (ms[i], cnt[i]) for i in range(w)}
+
+
+def pm_deposit(plan: Plan, pos, delta=None):
+    delta = plan.mesh() if delta is None else delta
+    _check(lib().pm_deposit(plan.handle, _ptr(pos, plan.dtype, "pos"), pos.shape[-1], _ptr(delta, plan.dtype, "delta"),
+                            _stream()))
+    return delta
+
+
+def pm_solve(plan: Plan, delta, sp: SolveParams, phi_state=None, force=None):
+    force = plan.mesh(3) if force is None else force
+    _check(lib().pm_solve(plan.handle, _ptr(delta, plan.dtype, "delta"), ctypes.byref(sp), _ptr(phi_state),
+                          _ptr(force, plan.dtype, "force"), _stream()))
+    return force
+
+
+def pm_gather(plan: Plan, force, pos, acc=None):
+    acc = torch.empty_like(pos) if acc is None else acc
+    _check(lib().pm_gather(plan.handle, _ptr(force, plan.dtype, "force"), _ptr(pos, plan.dtype, "pos"), pos.shape[-1],
+                           _ptr(acc, plan.dtype, "acc"), _stream()))
+    return acc
+
+
+def pm_step(plan: Plan, pos, mom, st: StepParams, force_scratch, phi_state=None):
+    _check(lib().pm_step(plan.handle, _ptr(pos, plan.dtype, "pos"), _ptr(mom, plan.dtype, "mom"), pos.shape[-1],
+                         ctypes.byref(st), _ptr(force_scratch, plan.dtype, "force_scratch"), _ptr(phi_state),
+                         _stream()))
+
+
+def displacement_combine(x_gr, x_newton, n_coarse: int, x_fine, n_fine: int, x_out=None):
+    x_out = torch.empty_like(x_fine) if x_out is None else x_out
+    dt = PM_F32 if x_fine.dtype == torch.float32 else PM_F64
+    _check(lib().displacement_combine(_ptr(x_gr, x_fine.dtype, "x_gr"), _ptr(x_newton, x_fine.dtype, "x_newton"),
+                                      int(n_coarse), _ptr(x_fine, x_fine.dtype, "x_fine"), int(n_fine), dt,
+                                      _ptr(x_out, x_fine.dtype, "x_out"), _stream()))
+    return x_out
+
+
+def pk_estimate(plan: Plan, delta, n_bins: int):
+    k = torch.empty(n_bins, dtype=torch.float64, device=plan.device)
+    p = torch.empty(n_bins, dtype=torch.float64, device=plan.device)
+    c = torch.empty(n_bins, dtype=torch.int64, device=plan.device)
+    _check(lib().pk_estimate(plan.handle, _ptr(delta, plan.dtype, "delta"), int(n_bins), _ptr(k), _ptr(p), _ptr(c),
+                             _stream()))
+    return k, p, c
+
+
+def bk_estimate(plan: Plan, delta, centres, width: float, triangles, shell_ws=None, ntri_known=None):
+    cen = (ctypes.c_double * len(centres))(*[float(c) for c in centres])
+    flat = [int(s) for t in triangles for s in t]
+    tri = (ctypes.c_int32 * len(flat))(*flat)
+    nt = len(triangles)
+    if shell_ws is None:
+        nsh = len({s for s in flat})
+        shell_ws = torch.empty((max(3, nsh),) + (plan.n,) * 3, dtype=plan.dtype, device=plan.device)
+    bk = torch.empty(nt, dtype=torch.float64, device=plan.device)
+    ntri = torch.empty(nt, dtype=torch.float64, device=plan.device)
+    _check(lib().bk_estimate(plan.handle, _ptr(delta, plan.dtype, "delta"), len(centres), cen, float(width), tri, nt,
+                             _ptr(bk), _ptr(ntri), _ptr(ntri_known, torch.float64, "ntri_known"),
+                             _ptr(shell_ws, plan.dtype, "shell_ws"), shell_ws.numel() * shell_ws.element_size(),
+                             _stream()))
+    return bk, ntri
+
+
+def pm_ic_zeldovich(plan: Plan, noise, ic: ICParams, disp_scratch, pos, mom):
+    _check(lib().pm_ic_zeldovich(plan.handle, _ptr(noise, plan.dtype, "noise"), ctypes.byref(ic),
+                                 _ptr(disp_scratch, plan.dtype, "disp_scratch"), _ptr(pos, plan.dtype, "pos"),
+                                 _ptr(mom, plan.dtype, "mom"), _stream()))
+
+
+def pm_ic_gauge(plan: Plan, noise, ic: ICParams, disp_scratch, pos_n, mom_n, pos_gr, mom_gr):
+    _check(lib().pm_ic_gauge(plan.handle, _ptr(noise, plan.dtype, "noise"), ctypes.byref(ic),
+                             _ptr(disp_scratch, plan.dtype, "disp_scratch"), _ptr(pos_n, plan.dtype, "pos_n"),
+                             _ptr(mom_n, plan.dtype, "mom_n"), _ptr(pos_gr, plan.dtype, "pos_gr"),
+                             _ptr(mom_gr, plan.dtype, "mom_gr"), _stream()))
+
+
+# ------------------------------------------------------------ host cosmology --
+
+def cosmo_hubble_e(a, c=FIDUCIAL): return lib().pm_cosmo_hubble_e(ctypes.byref(c), a)
+def cosmo_omega_m_a(a, c=FIDUCIAL): return lib().pm_cosmo_omega_m_a(ctypes.byref(c), a)
+def cosmo_growth(a, c=FIDUCIAL): return lib().pm_cosmo_growth(ctypes.byref(c), a)
+def cosmo_growth_rate(a, c=FIDUCIAL): return lib().pm_cosmo_growth_rate(ctypes.byref(c), a)
+def cosmo_kick(a0, a1, c=FIDUCIAL): return lib().pm_cosmo_kick(ctypes.byref(c), a0, a1)
+def cosmo_drift(a0, a1, c=FIDUCIAL): return lib().pm_cosmo_drift(ctypes.byref(c), a0, a1)
+
+
+def kdk_factors(a0, a1, c=FIDUCIAL):
+    out = (ctypes.c_double * 3)()
+    lib().pm_kdk_factors(ctypes.byref(c), a0, a1, out)
+    return out[0], out[1], out[2]
+
+
+def gauge_params(box, n, a, a_prev=0.0, c=FIDUCIAL) -> SolveParams:
+    sp = SolveParams()
+    lib().pm_gauge_params(ctypes.byref(c), float(box), int(n), float(a), float(a_prev), ctypes.byref(sp))
+    return sp
+
+
+def newton_params(c=FIDUCIAL, grad=PM_GRAD_SPECTRAL) -> SolveParams:
+    return SolveParams(kind=PM_NEWTON, grad=grad, omega_m=c.omega_m)
+
+
+def power_eh98_amplitude(n_s, sigma8, c=FIDUCIAL):
+    return lib().pm_power_eh98_amplitude(ctypes.byref(c), n_s, sigma8)
+
+
+def power_law_amplitude(n, box, rms, index=-2.0):
+    return lib().pm_power_law_amplitude(int(n), float(box), float(rms), float(index))
+
+
+from . import sim  # noqa: E402,F401

@@ -1,0 +1,420 @@
+// C ABI of the pmhip library: argument checking, plans and the orchestration of the
+// kernels of fft.hip, particles.hip and spectra.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pm_common.h"
+#include "pm_plan.h"
+
+namespace pm {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PM_OK;
+  return set_error(PM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static size_t complex_bytes(int n, int dtype) {
+  const size_t es = dtype == PM_F32 ? 4 : 8;
+  return align256((size_t)n * n * (n / 2 + 1) * 2 * es);
+}
+
+static int check_plan(const pm_plan* p) {
+  if (!p) return set_error(PM_ERR_ARG, "null plan");
+  return PM_OK;
+}
+
+// ------------------------------------------------------------ profiling ----
+static const char* kProfNames[PK_COUNT] = {
+    "fill",          "deposit",        "fft_r2c_rows",   "fft_cols_fwd_axis1", "fft_cols_fwd_axis0",
+    "fft_solve_axis0", "fft_cols_inv_axis0", "fft_cols_inv_axis1", "fft_c2r_rows", "gather",
+    "gather_kick_drift", "combine",    "ic",             "pk",                 "bk"};
+
+struct ProfRec {
+  int kind;
+  hipEvent_t start, stop;
+};
+
+struct ProfState {
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  int open_kind = -1;
+  hipEvent_t open_start = nullptr;
+  double ms[PK_COUNT] = {0};
+  int64_t count[PK_COUNT] = {0};
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+
+void prof_begin(const pm_plan* p, int kind, hipStream_t s) {
+  ProfState* ps = p->prof;
+  if (ps->open_kind >= 0) return;  // nested scope: the outer one times it
+  ps->open_kind = kind;
+  ps->open_start = ps->take();
+  (void)hipEventRecord(ps->open_start, s);
+}
+
+void prof_end(const pm_plan* p, hipStream_t s) {
+  ProfState* ps = p->prof;
+  if (ps->open_kind < 0) return;
+  hipEvent_t stop = ps->take();
+  (void)hipEventRecord(stop, s);
+  ps->recs.push_back(ProfRec{ps->open_kind, ps->open_start, stop});
+  ps->open_kind = -1;
+  // Fold completed records so the list stays short in long runs.
+  if (ps->recs.size() > 4096) {
+    for (auto& r : ps->recs) {
+      (void)hipEventSynchronize(r.stop);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, r.start, r.stop);
+      ps->ms[r.kind] += ms;
+      ps->count[r.kind] += 1;
+      ps->pool.push_back(r.start);
+      ps->pool.push_back(r.stop);
+    }
+    ps->recs.clear();
+  }
+}
+
+}  // namespace pm
+
+using namespace pm;
+
+#define PM_TRY(expr)             \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != PM_OK) return _rc; \
+  } while (0)
+
+extern "C" {
+
+const char* pm_last_error(void) { return g_err; }
+
+size_t pm_plan_workspace_bytes(int n_mesh, int dtype) {
+  if (!mesh_supported(n_mesh) || (dtype != PM_F32 && dtype != PM_F64)) return 0;
+  return 3 * complex_bytes(n_mesh, dtype);
+}
+
+int pm_plan_create(pm_plan** out, int n_mesh, double box_mpch, int dtype, void* workspace, size_t ws_bytes) {
+  g_err[0] = 0;
+  if (!out) return set_error(PM_ERR_ARG, "pm_plan_create: null output pointer");
+  *out = nullptr;
+  if (!mesh_supported(n_mesh)) return set_error(PM_ERR_SIZE, "pm_plan_create: unsupported mesh size %d", n_mesh);
+  if (dtype != PM_F32 && dtype != PM_F64) return set_error(PM_ERR_ARG, "pm_plan_create: bad dtype %d", dtype);
+  if (!(box_mpch > 0.0)) return set_error(PM_ERR_ARG, "pm_plan_create: box must be positive");
+  const size_t need = pm_plan_workspace_bytes(n_mesh, dtype);
+  if (workspace && ws_bytes < need)
+    return set_error(PM_ERR_NOMEM, "pm_plan_create: workspace of %zu bytes < %zu needed", ws_bytes, need);
+  pm_plan* p = new (std::nothrow) pm_plan();
+  if (!p) return set_error(PM_ERR_NOMEM, "pm_plan_create: host allocation failed");
+  p->n = n_mesh;
+  p->dtype = dtype;
+  p->box = box_mpch;
+  p->esize = dtype == PM_F32 ? 4 : 8;
+  p->cbytes = complex_bytes(n_mesh, dtype);
+  (void)hipGetDevice(&p->device);
+  int rc = PM_OK;
+  if (workspace) {
+    p->ws = workspace;
+    p->ws_bytes = ws_bytes;
+    p->own_ws = false;
+  } else {
+    if (hipMalloc(&p->ws, need) != hipSuccess) rc = set_error(PM_ERR_NOMEM, "pm_plan_create: workspace allocation");
+    p->ws_bytes = need;
+    p->own_ws = true;
+  }
+  // twiddle table W_N^m = exp(-2 pi i m / N)
+  if (rc == PM_OK) {
+    std::vector<double> twd(2 * (size_t)n_mesh);
+    for (int m = 0; m < n_mesh; ++m) {
+      // exact quarter-turn values, double-precision trig elsewhere
+      const double ang = 2.0 * kPi * (double)m / (double)n_mesh;
+      double c = std::cos(ang), s = -std::sin(ang);
+      if ((4 * m) % n_mesh == 0) {
+        const int q = (4 * m) / n_mesh;
+        c = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+        s = q == 1 ? -1.0 : (q == 3 ? 1.0 : 0.0);
+      }
+      twd[2 * m] = c;
+      twd[2 * m + 1] = s;
+    }
+    const size_t tb = 2 * (size_t)n_mesh * p->esize;
+    if (hipMalloc(&p->tw, tb) != hipSuccess) {
+      rc = set_error(PM_ERR_NOMEM, "pm_plan_create: twiddle allocation");
+    } else if (dtype == PM_F32) {
+      std::vector<float> twf(twd.begin(), twd.end());
+      rc = hip_check(hipMemcpy(p->tw, twf.data(), tb, hipMemcpyHostToDevice), "pm_plan_create: twiddle upload");
+    } else {
+      rc = hip_check(hipMemcpy(p->tw, twd.data(), tb, hipMemcpyHostToDevice), "pm_plan_create: twiddle upload");
+    }
+  }
+  if (rc == PM_OK) {
+    if (hipMalloc(&p->guard, 4 * sizeof(unsigned)) != hipSuccess)
+      rc = set_error(PM_ERR_NOMEM, "pm_plan_create: guard allocation");
+    else
+      rc = hip_check(hipMemset(p->guard, 0, 4 * sizeof(unsigned)), "pm_plan_create: guard init");
+  }
+  if (rc == PM_OK) {
+    p->sums_cap = 3 * (size_t)std::max(n_mesh, 512) + 2 * 4096;
+    if (hipMalloc(&p->sums, p->sums_cap * sizeof(double)) != hipSuccess)
+      rc = set_error(PM_ERR_NOMEM, "pm_plan_create: reduction scratch allocation");
+  }
+  if (rc != PM_OK) {
+    pm_plan_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return PM_OK;
+}
+
+int pm_profile_enable(pm_plan* p, int on) {
+  PM_TRY(check_plan(p));
+  if (on && !p->prof) {
+    p->prof = new (std::nothrow) ProfState();
+    if (!p->prof) return set_error(PM_ERR_NOMEM, "pm_profile_enable: host allocation");
+  } else if (!on && p->prof) {
+    for (auto& r : p->prof->recs) {
+      (void)hipEventSynchronize(r.stop);
+      (void)hipEventDestroy(r.start);
+      (void)hipEventDestroy(r.stop);
+    }
+    for (auto e : p->prof->pool) (void)hipEventDestroy(e);
+    delete p->prof;
+    p->prof = nullptr;
+  }
+  return PM_OK;
+}
+
+int pm_profile_read(pm_plan* p, int n_max, char* names, double* ms, int64_t* count) {
+  PM_TRY(check_plan(p));
+  if (!p->prof) return set_error(PM_ERR_ARG, "pm_profile_read: profiling is off");
+  if (n_max < 0 || (n_max > 0 && (!names || !ms || !count))) return set_error(PM_ERR_ARG, "pm_profile_read: bad output");
+  ProfState* ps = p->prof;
+  for (auto& r : ps->recs) {
+    PM_TRY(hip_check(hipEventSynchronize(r.stop), "pm_profile_read: event"));
+    float t = 0.f;
+    PM_TRY(hip_check(hipEventElapsedTime(&t, r.start, r.stop), "pm_profile_read: elapsed"));
+    ps->ms[r.kind] += t;
+    ps->count[r.kind] += 1;
+    ps->pool.push_back(r.start);
+    ps->pool.push_back(r.stop);
+  }
+  ps->recs.clear();
+  int w = 0;
+  for (int k = 0; k < PK_COUNT && w < n_max; ++k) {
+    if (ps->count[k] == 0) continue;
+    std::snprintf(names + 32 * (size_t)w, 32, "%s", kProfNames[k]);
+    ms[w] = ps->ms[k];
+    count[w] = ps->count[k];
+    ++w;
+  }
+  for (int k = 0; k < PK_COUNT; ++k) {
+    ps->ms[k] = 0.0;
+    ps->count[k] = 0;
+  }
+  return w;
+}
+
+int pm_plan_destroy(pm_plan* p) {
+  if (!p) return PM_OK;
+  if (p->prof) pm_profile_enable(p, 0);
+  if (p->own_ws && p->ws) (void)hipFree(p->ws);
+  if (p->tw) (void)hipFree(p->tw);
+  if (p->guard) (void)hipFree(p->guard);
+  if (p->sums) (void)hipFree(p->sums);
+  delete p;
+  return PM_OK;
+}
+
+int pm_check(pm_plan* p, void* stream) {
+  PM_TRY(check_plan(p));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned h[4] = {0, 0, 0, 0};
+  static const unsigned zeros[4] = {0, 0, 0, 0};
+  PM_TRY(hip_check(hipMemcpyAsync(h, p->guard, sizeof(h), hipMemcpyDeviceToHost, s), "pm_check: read guards"));
+  PM_TRY(hip_check(hipMemcpyAsync(p->guard, zeros, sizeof(zeros), hipMemcpyHostToDevice, s), "pm_check: reset"));
+  PM_TRY(hip_check(hipStreamSynchronize(s), "pm_check: synchronise"));
+  if (h[0] || h[1])
+    return set_error(PM_ERR_STATE, "pm_check: %u non-finite positions skipped, %u positions outside [0,N) wrapped",
+                     h[0], h[1]);
+  return PM_OK;
+}
+
+// ------------------------------------------------------------- hot path ----
+
+int pm_deposit(pm_plan* p, const void* pos, int64_t np, void* delta, void* stream) {
+  PM_TRY(check_plan(p));
+  if (np < 0) return set_error(PM_ERR_ARG, "pm_deposit: negative particle count");
+  if (!delta || (np > 0 && !pos)) return set_error(PM_ERR_ARG, "pm_deposit: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n3 = (int64_t)p->n * p->n * p->n;
+  PM_TRY(launch_fill(p, delta, n3, -1.0, s));
+  return launch_deposit(p, pos, np, delta, s);
+}
+
+static int solve_from_c0(pm_plan* p, const pm_solve_params* sp, void* phi, void* force, hipStream_t s) {
+  PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, -1, 1, 0, s));
+  PM_TRY(fft_pass_solve(p, sp, phi, s));
+  const int64_t cstride = (int64_t)(p->cbytes / (2 * p->esize));
+  PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, 1, 3, cstride, s));
+  return fft_pass_rows_c2r(p, 3, cbuf(p, 0), cstride, force, s);
+}
+
+static int check_solve_params(const pm_solve_params* sp, const void* phi, const char* who) {
+  if (!sp) return set_error(PM_ERR_ARG, "%s: null solve parameters", who);
+  if (sp->kind != PM_NEWTON && sp->kind != PM_POISSON_GAUGE) return set_error(PM_ERR_ARG, "%s: bad kind", who);
+  if (sp->grad < PM_GRAD_SPECTRAL || sp->grad > PM_GRAD_FD1) return set_error(PM_ERR_ARG, "%s: bad gradient", who);
+  if (sp->kind == PM_POISSON_GAUGE) {
+    if (!phi) return set_error(PM_ERR_ARG, "%s: Poisson-gauge solve needs phi_state", who);
+    if (!(sp->c_g > 0.0)) return set_error(PM_ERR_ARG, "%s: c_g must be positive", who);
+  }
+  return PM_OK;
+}
+
+int pm_solve(pm_plan* p, const void* delta, const pm_solve_params* sp, void* phi_state, void* force, void* stream) {
+  PM_TRY(check_plan(p));
+  if (!delta || !force) return set_error(PM_ERR_ARG, "pm_solve: null pointer");
+  PM_TRY(check_solve_params(sp, phi_state, "pm_solve"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PM_TRY(fft_pass_rows_r2c(p, delta, cbuf(p, 0), s));
+  return solve_from_c0(p, sp, phi_state, force, s);
+}
+
+int pm_gather(pm_plan* p, const void* force, const void* pos, int64_t np, void* acc, void* stream) {
+  PM_TRY(check_plan(p));
+  if (np < 0) return set_error(PM_ERR_ARG, "pm_gather: negative particle count");
+  if (np > 0 && (!force || !pos || !acc)) return set_error(PM_ERR_ARG, "pm_gather: null pointer");
+  return launch_gather(p, force, pos, np, acc, static_cast<hipStream_t>(stream));
+}
+
+int pm_step(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* st, void* force_scratch,
+            void* phi_state, void* stream) {
+  PM_TRY(check_plan(p));
+  if (np < 0) return set_error(PM_ERR_ARG, "pm_step: negative particle count");
+  if (!st || !force_scratch || (np > 0 && (!pos || !mom))) return set_error(PM_ERR_ARG, "pm_step: null pointer");
+  PM_TRY(check_solve_params(&st->solve, phi_state, "pm_step"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n3 = (int64_t)p->n * p->n * p->n;
+  void* delta = cbuf(p, 1);  // the density mesh lives in the second spectrum buffer
+  PM_TRY(launch_fill(p, delta, n3, -1.0, s));
+  PM_TRY(launch_deposit(p, pos, np, delta, s));
+  PM_TRY(fft_pass_rows_r2c(p, delta, cbuf(p, 0), s));
+  PM_TRY(solve_from_c0(p, &st->solve, phi_state, force_scratch, s));
+  return launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, s);
+}
+
+int displacement_combine(const void* x_gr, const void* x_newton, int n_coarse, const void* x_fine, int n_fine,
+                         int dtype, void* x_out, void* stream) {
+  g_err[0] = 0;
+  if (!x_gr || !x_newton || !x_fine || !x_out) return set_error(PM_ERR_ARG, "displacement_combine: null pointer");
+  if (n_coarse <= 0 || n_fine <= 0 || n_fine % n_coarse != 0)
+    return set_error(PM_ERR_ARG, "displacement_combine: n_fine (%d) must be a positive multiple of n_coarse (%d)",
+                     n_fine, n_coarse);
+  if (n_fine > 4096) return set_error(PM_ERR_SIZE, "displacement_combine: n_fine too large");
+  if (dtype != PM_F32 && dtype != PM_F64) return set_error(PM_ERR_ARG, "displacement_combine: bad dtype");
+  return launch_combine(x_gr, x_newton, n_coarse, x_fine, n_fine, dtype, x_out, static_cast<hipStream_t>(stream));
+}
+
+int pk_estimate(pm_plan* p, const void* delta, int n_bins, double* k_mean, double* pk, int64_t* n_modes,
+                void* stream) {
+  PM_TRY(check_plan(p));
+  if (!delta || !k_mean || !pk || !n_modes) return set_error(PM_ERR_ARG, "pk_estimate: null pointer");
+  if (n_bins <= 0 || 3 * (size_t)n_bins > p->sums_cap || n_bins > 4 * p->n)
+    return set_error(PM_ERR_ARG, "pk_estimate: n_bins %d out of range", n_bins);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PM_TRY(fft3_r2c(p, delta, cbuf(p, 0), s));
+  PM_TRY(launch_zero_doubles(p->sums, 3 * (int64_t)n_bins, s));
+  PM_TRY(launch_pk_reduce(p, cbuf(p, 0), n_bins, s));
+  return launch_pk_finalize(p, n_bins, k_mean, pk, n_modes, s);
+}
+
+int bk_estimate(pm_plan* p, const void* delta, int n_shells, const double* centre, double width, const int32_t* tri,
+                int n_tri, double* bk, double* ntri_out, const double* ntri_known, void* shell_ws,
+                size_t shell_ws_bytes, void* stream) {
+  PM_TRY(check_plan(p));
+  if (!delta || !centre || !tri || !bk || !ntri_out || !shell_ws) return set_error(PM_ERR_ARG, "bk_estimate: null pointer");
+  if (n_shells <= 0 || n_tri <= 0 || !(width > 0.0)) return set_error(PM_ERR_ARG, "bk_estimate: bad sizes");
+  if (2 * (size_t)n_tri > p->sums_cap) return set_error(PM_ERR_ARG, "bk_estimate: too many triangles");
+  for (int t = 0; t < 3 * n_tri; ++t)
+    if (tri[t] < 0 || tri[t] >= n_shells) return set_error(PM_ERR_ARG, "bk_estimate: shell id out of range");
+  const size_t fbytes = align256((size_t)p->n * p->n * p->n * p->esize);
+  const int slots = (int)std::min<size_t>(shell_ws_bytes / fbytes, 1 << 20);
+  if (slots < 3) return set_error(PM_ERR_NOMEM, "bk_estimate: shell workspace holds %d fields, 3 needed", slots);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PM_TRY(fft3_r2c(p, delta, cbuf(p, 0), s));
+  PM_TRY(launch_zero_doubles(p->sums, 2 * (int64_t)n_tri, s));
+  const int passes = ntri_known ? 1 : 2;
+  for (int pass = 0; pass < passes; ++pass) {
+    std::vector<int> slot_shell(slots, -1);
+    for (int t = 0; t < n_tri; ++t) {
+      int sl[3];
+      for (int j = 0; j < 3; ++j) {
+        const int sh = tri[3 * t + j];
+        int found = -1;
+        for (int k = 0; k < slots; ++k)
+          if (slot_shell[k] == sh) found = k;
+        if (found < 0) {
+          // evict the cached shell whose next use is farthest (never if used by this triangle)
+          int best = -1;
+          long best_next = -1;
+          for (int k = 0; k < slots; ++k) {
+            const int cs = slot_shell[k];
+            if (cs < 0) {
+              best = k;
+              break;
+            }
+            if (cs == tri[3 * t] || cs == tri[3 * t + 1] || cs == tri[3 * t + 2]) continue;
+            long next = (long)n_tri * 3 + 1;
+            for (int u = t + 1; u < n_tri && next > (long)n_tri * 3; ++u)
+              if (tri[3 * u] == cs || tri[3 * u + 1] == cs || tri[3 * u + 2] == cs) next = u;
+            if (next > best_next) {
+              best_next = next;
+              best = k;
+            }
+          }
+          const double c = centre[sh];
+          const double lo = (2.0 * c - width) * (2.0 * c - width);
+          const double hi = (2.0 * c + width) * (2.0 * c + width);
+          PM_TRY(launch_shell_mask(p, pass == 0 ? cbuf(p, 0) : nullptr, cbuf(p, 1), lo, hi, s));
+          void* dst = static_cast<char*>(shell_ws) + (size_t)best * fbytes;
+          PM_TRY(fft3_c2r(p, 1, cbuf(p, 1), 0, dst, s));
+          slot_shell[best] = sh;
+          found = best;
+        }
+        sl[j] = found;
+      }
+      const char* base = static_cast<const char*>(shell_ws);
+      PM_TRY(launch_triple_sum(p, base + (size_t)sl[0] * fbytes, base + (size_t)sl[1] * fbytes,
+                               base + (size_t)sl[2] * fbytes, p->sums + (size_t)pass * n_tri + t, s));
+    }
+  }
+  return launch_bk_finalize(p, n_tri, p->sums, bk, ntri_out, ntri_known, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+// Launchers of the hand-written FFT passes (see fft_kernels.h).
+#include <algorithm>
+
+#include "fft_kernels.h"
+#include "pm_plan.h"
+
+namespace pm {
+
+namespace {
+
+template <typename T>
+int cols_per_block(int n) {
+  const Shape sh = shape_for(n);
+  const int tpc = std::max(sh.L1, sh.L2);
+  int b = 256 / tpc;
+  const int by_lds = 65536 / (n * (int)sizeof(cx<T>));
+  b = std::min(b, std::max(by_lds, 1));
+  const int h = n / 2 + 1;
+  int cap = 1;
+  while (cap < h) cap <<= 1;
+  b = std::min(b, cap);
+  int p2 = 1;
+  while (p2 * 2 <= b) p2 <<= 1;
+  return p2;
+}
+
+template <typename T, int L1, int L2>
+void launch_cols_t(cx<T>* data, const ColArgs& g, int dir, int ncomp, int outer, const cx<T>* tw, hipStream_t s) {
+  const int tpc = std::max(L1, L2);
+  dim3 grid((unsigned)(outer * g.groups), (unsigned)ncomp);
+  dim3 block((unsigned)(g.bcols * tpc));
+  size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
+  if (dir < 0)
+    hipLaunchKernelGGL((k_fft_cols<T, L1, L2, -1>), grid, block, shm, s, data, g, tw);
+  else
+    hipLaunchKernelGGL((k_fft_cols<T, L1, L2, 1>), grid, block, shm, s, data, g, tw);
+}
+
+template <typename T, int L1, int L2>
+void launch_r2c_t(const T* in, cx<T>* out, const RowArgs& g, const cx<T>* tw, hipStream_t s) {
+  constexpr int M = L1 * L2;
+  constexpr int TPC = L1 > L2 ? L1 : L2;
+  constexpr int XS = L1 * (L2 + 1);
+  constexpr int RS = XS > M ? XS : M;
+  const int R = 256 / TPC;
+  dim3 grid((unsigned)((g.nrows + R - 1) / R), 1);
+  dim3 block((unsigned)(R * TPC));
+  hipLaunchKernelGGL((k_fft_rows_r2c<T, L1, L2>), grid, block, (size_t)R * RS * sizeof(cx<T>), s, in, out, g, tw);
+}
+
+template <typename T, int L1, int L2>
+void launch_c2r_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx<T>* tw, hipStream_t s) {
+  constexpr int M = L1 * L2;
+  constexpr int TPC = L1 > L2 ? L1 : L2;
+  constexpr int XS = L1 * (L2 + 1);
+  constexpr int RS = XS > (M + 1) ? XS : (M + 1);
+  const int R = 256 / TPC;
+  dim3 grid((unsigned)((g.nrows + R - 1) / R), (unsigned)ncomp);
+  dim3 block((unsigned)(R * TPC));
+  hipLaunchKernelGGL((k_fft_rows_c2r<T, L1, L2>), grid, block, (size_t)R * RS * sizeof(cx<T>), s, in, out, g, tw);
+}
+
+template <typename T, int L1, int L2>
+void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* o2, cx<T>* phi, const ColArgs& g, const SolveArgs& a, int outer,
+                    const cx<T>* tw, hipStream_t s) {
+  const int tpc = std::max(L1, L2);
+  dim3 grid((unsigned)(outer * g.groups), 1);
+  dim3 block((unsigned)(g.bcols * tpc));
+  size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
+  hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2>), grid, block, shm, s, data, o1, o2, phi, g, a, tw);
+}
+
+// Dispatch on a transform length L to the compile-time (L1, L2) instantiation.
+#define PM_DISPATCH_LEN(L, FN, ...)                  \
+  switch (L) {                                       \
+    case 4: FN<T, 2, 2>(__VA_ARGS__); break;         \
+    case 8: FN<T, 4, 2>(__VA_ARGS__); break;         \
+    case 16: FN<T, 4, 4>(__VA_ARGS__); break;        \
+    case 32: FN<T, 8, 4>(__VA_ARGS__); break;        \
+    case 64: FN<T, 8, 8>(__VA_ARGS__); break;        \
+    case 96: FN<T, 8, 12>(__VA_ARGS__); break;       \
+    case 128: FN<T, 16, 8>(__VA_ARGS__); break;      \
+    case 192: FN<T, 16, 12>(__VA_ARGS__); break;     \
+    case 256: FN<T, 16, 16>(__VA_ARGS__); break;     \
+    case 512: FN<T, 16, 32>(__VA_ARGS__); break;     \
+    case 1024: FN<T, 32, 32>(__VA_ARGS__); break;    \
+    default: return set_error(PM_ERR_SIZE, "unsupported transform length %d", (int)(L)); \
+  }
+
+ColArgs col_args(int n, int axis, int bcols) {
+  const int64_t h = n / 2 + 1;
+  ColArgs g;
+  g.stride = axis == 1 ? h : (int64_t)n * h;
+  g.outer_stride = axis == 1 ? (int64_t)n * h : h;
+  g.comp_stride = 0;
+  g.ncols = (int)h;
+  g.bcols = bcols;
+  g.groups = (int)((h + bcols - 1) / bcols);
+  g.tw_step = 1;
+  return g;
+}
+
+template <typename T>
+int cols_t(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s) {
+  const int n = p->n;
+  ColArgs g = col_args(n, axis, cols_per_block<T>(n));
+  g.comp_stride = comp_stride;
+  cx<T>* d = static_cast<cx<T>*>(data);
+  const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
+  PM_DISPATCH_LEN(n, launch_cols_t, d, g, dir, ncomp, n, tw, s)
+  return hip_check(hipGetLastError(), "fft column pass");
+}
+
+template <typename T>
+int r2c_t(const pm_plan* p, const void* in, void* out, hipStream_t s) {
+  const int n = p->n;
+  RowArgs g;
+  g.nrows = (int64_t)n * n;
+  g.in_comp = 0;
+  g.out_comp = 0;
+  g.n = n;
+  const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
+  PM_DISPATCH_LEN(n / 2, launch_r2c_t, static_cast<const T*>(in), static_cast<cx<T>*>(out), g, tw, s)
+  return hip_check(hipGetLastError(), "fft r2c rows");
+}
+
+template <typename T>
+int c2r_t(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* out, hipStream_t s) {
+  const int n = p->n;
+  RowArgs g;
+  g.nrows = (int64_t)n * n;
+  g.in_comp = in_comp;
+  g.out_comp = (int64_t)n * n * n;
+  g.n = n;
+  const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
+  PM_DISPATCH_LEN(n / 2, launch_c2r_t, static_cast<const cx<T>*>(in), static_cast<T*>(out), g, ncomp, tw, s)
+  return hip_check(hipGetLastError(), "fft c2r rows");
+}
+
+template <typename T>
+int solve_t(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t s) {
+  const int n = p->n;
+  ColArgs g = col_args(n, 0, cols_per_block<T>(n));
+  SolveArgs a;
+  const double n3 = (double)n * n * n;
+  a.n = n;
+  a.kind = sp->kind;
+  a.grad = sp->grad;
+  a.newton = 1.5 * sp->omega_m / n3;
+  a.a_c2 = sp->a * sp->c_g * sp->c_g / n3;
+  a.h = sp->calh;
+  a.h2 = sp->calh * sp->calh;
+  a.om_a = sp->om_a;
+  a.inv_dtau = sp->inv_dtau;
+  cx<T>* c0 = static_cast<cx<T>*>(cbuf(p, 0));
+  cx<T>* c1 = static_cast<cx<T>*>(cbuf(p, 1));
+  cx<T>* c2 = static_cast<cx<T>*>(cbuf(p, 2));
+  const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
+  PM_DISPATCH_LEN(n, launch_solve_t, c0, c1, c2, static_cast<cx<T>*>(phi), g, a, n, tw, s)
+  return hip_check(hipGetLastError(), "fft solve pass");
+}
+
+}  // namespace
+
+int fft_pass_cols(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s) {
+  const int kind = axis == 1 ? (dir < 0 ? PK_COLS_FWD_AXIS1 : PK_COLS_INV_AXIS1)
+                             : (dir < 0 ? PK_COLS_FWD_AXIS0 : PK_COLS_INV_AXIS0);
+  ProfScope ps(p, kind, s);
+  return p->dtype == PM_F32 ? cols_t<float>(p, data, axis, dir, ncomp, comp_stride, s)
+                            : cols_t<double>(p, data, axis, dir, ncomp, comp_stride, s);
+}
+
+int fft_pass_rows_r2c(const pm_plan* p, const void* in, void* out, hipStream_t s) {
+  ProfScope ps(p, PK_R2C_ROWS, s);
+  return p->dtype == PM_F32 ? r2c_t<float>(p, in, out, s) : r2c_t<double>(p, in, out, s);
+}
+
+int fft_pass_rows_c2r(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* out, hipStream_t s) {
+  ProfScope ps(p, PK_C2R_ROWS, s);
+  return p->dtype == PM_F32 ? c2r_t<float>(p, ncomp, in, in_comp, out, s) : c2r_t<double>(p, ncomp, in, in_comp, out, s);
+}
+
+int fft_pass_solve(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t s) {
+  ProfScope ps(p, PK_SOLVE_AXIS0, s);
+  return p->dtype == PM_F32 ? solve_t<float>(p, sp, phi, s) : solve_t<double>(p, sp, phi, s);
+}
+
+int fft3_r2c(const pm_plan* p, const void* real_in, void* cplx_out, hipStream_t s) {
+  int rc = fft_pass_rows_r2c(p, real_in, cplx_out, s);
+  if (rc) return rc;
+  rc = fft_pass_cols(p, cplx_out, 1, -1, 1, 0, s);
+  if (rc) return rc;
+  return fft_pass_cols(p, cplx_out, 0, -1, 1, 0, s);
+}
+
+int fft3_c2r(const pm_plan* p, int ncomp, void* cplx_in, int64_t comp_stride, void* real_out, hipStream_t s) {
+  int rc = fft_pass_cols(p, cplx_in, 0, 1, ncomp, comp_stride, s);
+  if (rc) return rc;
+  rc = fft_pass_cols(p, cplx_in, 1, 1, ncomp, comp_stride, s);
+  if (rc) return rc;
+  return fft_pass_rows_c2r(p, ncomp, cplx_in, comp_stride, real_out, s);
+}
+
+}  // namespace pm

@@ -1,0 +1,326 @@
+// Hand-written 3-D FFT building blocks for gfx950.
+//
+// A 3-D transform of an N^3 real mesh is three 1-D passes over a [N][N][N/2+1]
+// complex spectrum kept in natural order:
+//   rows   (last axis, contiguous): real-to-complex / complex-to-real, N/2-point
+//          complex transform of packed even/odd samples plus the split step;
+//   cols   (axes 1 and 0, strided): batches of B adjacent columns per workgroup so
+//          every global access is a B*sizeof(complex)-byte contiguous segment.
+// Every 1-D transform of length L = L1*L2 is a four-step transform: each of L2
+// threads transforms L1 strided values in registers (compile-time twiddles), the
+// inter-stage twiddles come from the plan's table W_N^m = exp(-2 pi i m/N), one LDS
+// exchange, then each of L1 threads transforms L2 values in registers.
+#pragma once
+
+#include "pm_common.h"
+
+namespace pm {
+
+// Table twiddle W_L^m for a length-L transform on a plan of mesh size N (N/L = step).
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> tw_mul(cx<T> a, const cx<T>* tw, int m_times_step) {
+  return twiddle<INV>(a, tw[m_times_step]);
+}
+
+
+struct ColArgs {
+  int64_t stride;        // element stride along the transform axis
+  int64_t outer_stride;  // stride between outer indices
+  int64_t comp_stride;   // stride between components (blockIdx.y)
+  int ncols;             // columns per outer index
+  int bcols;             // columns per workgroup
+  int groups;            // ceil(ncols / bcols)
+  int tw_step;           // N / L
+};
+
+// Column exchange buffer [L1][L2][B]: the j2 index is XOR-swizzled with the low bits
+// of k1 so that the stage-2 reads (threads spread over k1) fall on different banks.
+template <typename T, int L1, int L2>
+__device__ __forceinline__ int col_lds_index(int k1, int j2, int b, int B) {
+  constexpr int SW = L2 >= 4 ? 3 : L2 - 1;
+  return (k1 * L2 + (j2 ^ (k1 & SW))) * B + b;
+}
+
+// Plain strided complex-to-complex pass, in place.  DIR = -1 forward, +1 inverse
+// (unnormalised).  blockDim.x = B * max(L1, L2).
+template <typename T, int L1, int L2, int DIR>
+__global__ void __launch_bounds__(256) k_fft_cols(cx<T>* __restrict__ data, ColArgs g, const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr bool INV = DIR > 0;
+  const int B = g.bcols;
+  const int t = threadIdx.x;
+  const int b = t % B, u = t / B;
+  const int64_t outer = blockIdx.x / g.groups;
+  const int col = (blockIdx.x % g.groups) * B + b;
+  const bool valid = col < g.ncols;
+  cx<T>* base = data + (int64_t)blockIdx.y * g.comp_stride + outer * g.outer_stride + col;
+
+  if (u < L2) {
+    cx<T> a[L1];
+#pragma unroll
+    for (int j1 = 0; j1 < L1; ++j1) a[j1] = valid ? ldc(base + (int64_t)(u + L2 * j1) * g.stride) : mk(T(0), T(0));
+    RegDFT<T, L1, DIR>::run(a);
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) {
+      cx<T> v = k1 == 0 ? a[k1] : tw_mul<INV>(a[k1], tw, u * k1 * g.tw_step);
+      lds[col_lds_index<T, L1, L2>(k1, u, b, B)] = v;
+    }
+  }
+  __syncthreads();
+  if (u < L1) {
+    cx<T> c[L2];
+#pragma unroll
+    for (int j2 = 0; j2 < L2; ++j2) c[j2] = lds[col_lds_index<T, L1, L2>(u, j2, b, B)];
+    RegDFT<T, L2, DIR>::run(c);
+    if (valid) {
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) stc(base + (int64_t)(u + L1 * k2) * g.stride, c[k2]);
+    }
+  }
+}
+
+// Real-to-complex along the contiguous axis: rows of N reals -> rows of N/2+1
+// complex.  M = N/2 = L1*L2 complex points z[n] = x[2n] + i x[2n+1];
+// X[k] = E[k] + W_N^k O[k] with E = (Z[k] + conj Z[M-k])/2, O = -i (Z[k] - conj Z[M-k])/2.
+// blockDim.x = R * max(L1, L2), R rows per workgroup.  in_row_stride / out_row_stride
+// in elements; blockIdx.y selects a component (strides in_comp / out_comp).
+struct RowArgs {
+  int64_t nrows;
+  int64_t in_comp, out_comp;  // component strides (elements of the in/out type)
+  int n;                      // N (real row length)
+};
+
+template <typename T, int L1, int L2>
+__global__ void __launch_bounds__(256) k_fft_rows_r2c(const T* __restrict__ in, cx<T>* __restrict__ out, RowArgs g,
+                                                    const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int M = L1 * L2;
+  constexpr int TPC = L1 > L2 ? L1 : L2;
+  constexpr int XS = L1 * (L2 + 1);  // exchange row size (padded)
+  constexpr int RS = XS > M ? XS : M;
+  const int t = threadIdx.x;
+  const int r = t / TPC, u = t % TPC;
+  const int R = blockDim.x / TPC;
+  const int64_t row = (int64_t)blockIdx.x * R + r;
+  const bool valid = row < g.nrows;
+  const int N = g.n;
+  const int H = M + 1;
+  const T* src = in + (int64_t)blockIdx.y * g.in_comp + row * N;
+  cx<T>* dst = out + (int64_t)blockIdx.y * g.out_comp + row * H;
+  cx<T>* my = lds + r * RS;
+
+  if (u < L2) {
+    cx<T> a[L1];
+    const cx<T>* zsrc = reinterpret_cast<const cx<T>*>(src);
+#pragma unroll
+    for (int j1 = 0; j1 < L1; ++j1) a[j1] = valid ? ldc(zsrc + u + L2 * j1) : mk(T(0), T(0));
+    RegDFT<T, L1, -1>::run(a);
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) my[k1 * (L2 + 1) + u] = k1 == 0 ? a[k1] : tw_mul<false>(a[k1], tw, 2 * u * k1);
+  }
+  __syncthreads();
+  cx<T> c[L2];
+  if (u < L1) {
+#pragma unroll
+    for (int j2 = 0; j2 < L2; ++j2) c[j2] = my[u * (L2 + 1) + j2];
+    RegDFT<T, L2, -1>::run(c);
+  }
+  __syncthreads();
+  if (u < L1) {
+#pragma unroll
+    for (int k2 = 0; k2 < L2; ++k2) my[u + L1 * k2] = c[k2];
+  }
+  __syncthreads();
+  if (valid) {
+    for (int k = u; k <= M; k += TPC) {
+      cx<T> zk = my[k == M ? 0 : k];
+      cx<T> zm = conjg(my[k == 0 ? 0 : M - k]);
+      cx<T> e = scale(zk + zm, T(0.5));
+      cx<T> d = zk - zm;
+      cx<T> o = mk(T(0.5) * d.y, T(-0.5) * d.x);  // -i d / 2
+      cx<T> w = k == M ? mk(T(-1), T(0)) : tw[k];
+      stc(dst + k, e + w * o);
+    }
+  }
+}
+
+// Complex-to-real along the contiguous axis (unnormalised inverse:
+// x[n] = sum_{k in full row} X[k] exp(+2 pi i n k / N)).
+// Z[k] = (X[k] + conj X[M-k]) + i conj(W_N^k) (X[k] - conj X[M-k]), z = IDFT_M(Z),
+// x[2n] = Re z[n], x[2n+1] = Im z[n].
+template <typename T, int L1, int L2>
+__global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ in, T* __restrict__ out, RowArgs g,
+                                                    const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int M = L1 * L2;
+  constexpr int TPC = L1 > L2 ? L1 : L2;
+  constexpr int XS = L1 * (L2 + 1);
+  constexpr int RS = XS > (M + 1) ? XS : (M + 1);
+  const int t = threadIdx.x;
+  const int r = t / TPC, u = t % TPC;
+  const int R = blockDim.x / TPC;
+  const int64_t row = (int64_t)blockIdx.x * R + r;
+  const bool valid = row < g.nrows;
+  const int N = g.n;
+  const int H = M + 1;
+  const cx<T>* src = in + (int64_t)blockIdx.y * g.in_comp + row * H;
+  T* dst = out + (int64_t)blockIdx.y * g.out_comp + row * N;
+  cx<T>* my = lds + r * RS;
+
+  for (int k = u; k <= M; k += TPC) my[k] = valid ? ldc(src + k) : mk(T(0), T(0));
+  __syncthreads();
+  cx<T> a[L1];
+  if (u < L2) {
+#pragma unroll
+    for (int j1 = 0; j1 < L1; ++j1) {
+      const int k = u + L2 * j1;
+      cx<T> xk = my[k];
+      cx<T> xm = conjg(my[M - k]);
+      cx<T> s = xk + xm;
+      cx<T> d = twiddle<true>(xk - xm, tw[k]);  // d * conj(W_N^k)
+      a[j1] = mk(s.x - d.y, s.y + d.x);         // s + i d
+    }
+    RegDFT<T, L1, 1>::run(a);
+  }
+  __syncthreads();
+  if (u < L2) {
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) my[k1 * (L2 + 1) + u] = k1 == 0 ? a[k1] : tw_mul<true>(a[k1], tw, 2 * u * k1);
+  }
+  __syncthreads();
+  if (u < L1) {
+    cx<T> c[L2];
+#pragma unroll
+    for (int j2 = 0; j2 < L2; ++j2) c[j2] = my[u * (L2 + 1) + j2];
+    RegDFT<T, L2, 1>::run(c);
+    if (valid) {
+      cx<T>* zdst = reinterpret_cast<cx<T>*>(dst);
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) stc(zdst + u + L1 * k2, c[k2]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// Fused k-space solve along axis 0: forward column transform, per-mode potential
+// and gradient symbols for the three force components, inverse column transform
+// of each component.  Component 0 is written in place; 1 and 2 go to out1/out2.
+// ------------------------------------------------------------------------
+struct SolveArgs {
+  int n;            // N
+  int kind;         // PM_NEWTON | PM_POISSON_GAUGE
+  int grad;         // PM_GRAD_*
+  double newton;    // (3/2) Omega_m / N^3
+  double a_c2;      // a c_g^2 / N^3
+  double h, h2, om_a, inv_dtau;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> grad_symbol(int nd, int n, int grad, const cx<T>* tw) {
+  // nd in [-N/2, N/2], k = 2 pi nd / N
+  if (grad == PM_GRAD_SPECTRAL) {
+    if (nd == -n / 2 || nd == n / 2) return mk(T(0), T(0));
+    return mk(T(0), T(2.0 * kPi / n) * T(nd));
+  }
+  const int m = nd < 0 ? nd + n : nd;
+  const cx<T> w = tw[m];  // (cos k, -sin k)
+  if (grad == PM_GRAD_FD2) return mk(T(0), -w.y);
+  return mk(w.x - T(1), -w.y);  // PM_GRAD_FD1
+}
+
+template <typename T, int L1, int L2>
+__global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data, cx<T>* __restrict__ out1,
+                                                      cx<T>* __restrict__ out2, cx<T>* __restrict__ phi, ColArgs g,
+                                                      SolveArgs s, const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int B = g.bcols;
+  const int t = threadIdx.x;
+  const int b = t % B, u = t / B;
+  const int64_t outer = blockIdx.x / g.groups;  // iy
+  const int col = (blockIdx.x % g.groups) * B + b;  // iz
+  const bool valid = col < g.ncols;
+  const int64_t off = outer * g.outer_stride + col;
+  const int N = s.n;
+
+  // forward along axis 0
+  if (u < L2) {
+    cx<T> a[L1];
+#pragma unroll
+    for (int j1 = 0; j1 < L1; ++j1) a[j1] = valid ? ldc(data + off + (int64_t)(u + L2 * j1) * g.stride) : mk(T(0), T(0));
+    RegDFT<T, L1, -1>::run(a);
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1)
+      lds[col_lds_index<T, L1, L2>(k1, u, b, B)] = k1 == 0 ? a[k1] : tw_mul<false>(a[k1], tw, u * k1 * g.tw_step);
+  }
+  __syncthreads();
+  cx<T> X[L2];
+  if (u < L1) {
+#pragma unroll
+    for (int j2 = 0; j2 < L2; ++j2) X[j2] = lds[col_lds_index<T, L1, L2>(u, j2, b, B)];
+    RegDFT<T, L2, -1>::run(X);
+    // per-mode scalar factor: force_d = D_d * X[k2] after this
+    const int ny = outer < N / 2 ? (int)outer : (int)outer - N;
+    const int nz = col;
+    const T ky = T(2.0 * kPi / N) * T(ny), kz = T(2.0 * kPi / N) * T(nz);
+    const T kyz2 = ky * ky + kz * kz;
+#pragma unroll
+    for (int k2 = 0; k2 < L2; ++k2) {
+      const int ix = u + L1 * k2;
+      const int nx = ix < N / 2 ? ix : ix - N;
+      const T kx = T(2.0 * kPi / N) * T(nx);
+      const T k2s = kx * kx + kyz2;
+      const bool zero = (nx == 0 && ny == 0 && nz == 0);
+      if (s.kind == PM_NEWTON) {
+        const T f = zero ? T(0) : T(s.newton) / k2s;
+        X[k2] = scale(X[k2], f);
+      } else {
+        const int64_t pidx = off + (int64_t)ix * g.stride;
+        const T h = T(s.h), h2 = T(s.h2);
+        const cx<T> pold = valid ? ldc(phi + pidx) : mk(T(0), T(0));
+        const T den = -k2s - T(3) * h2 - T(3) * h * T(s.inv_dtau) - T(4.5) * h2 * T(s.om_a);
+        const cx<T> num = scale(X[k2], T(1.5) * h2 * T(s.om_a)) - scale(pold, T(3) * h * T(s.inv_dtau));
+        cx<T> pnew = zero ? mk(T(0), T(0)) : scale(num, T(1) / den);
+        if (valid) stc(phi + pidx, pnew);
+        X[k2] = scale(pnew, -T(s.a_c2));
+      }
+    }
+  }
+  // three inverse transforms
+#pragma unroll 1
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();  // previous component's LDS reads are complete
+    if (u < L1) {
+      cx<T> Y[L2];
+      const int ny = outer < N / 2 ? (int)outer : (int)outer - N;
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) {
+        const int ix = u + L1 * k2;
+        const int nx = ix < N / 2 ? ix : ix - N;
+        const int nd = d == 0 ? nx : (d == 1 ? ny : col);
+        Y[k2] = grad_symbol<T>(nd, N, s.grad, tw) * X[k2];
+      }
+      RegDFT<T, L2, 1>::run(Y);
+#pragma unroll
+      for (int ja = 0; ja < L2; ++ja)
+        lds[col_lds_index<T, L1, L2>(u, ja, b, B)] = ja == 0 ? Y[ja] : tw_mul<true>(Y[ja], tw, u * ja * g.tw_step);
+    }
+    __syncthreads();
+    if (u < L2) {
+      cx<T> c[L1];
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) c[k1] = lds[col_lds_index<T, L1, L2>(k1, u, b, B)];
+      RegDFT<T, L1, 1>::run(c);
+      cx<T>* o = d == 0 ? data : (d == 1 ? out1 : out2);
+      if (valid) {
+#pragma unroll
+        for (int jb = 0; jb < L1; ++jb) stc(o + off + (int64_t)(u + L2 * jb) * g.stride, c[jb]);
+      }
+    }
+  }
+}
+
+}  // namespace pm

@@ -1,0 +1,316 @@
+// Particle kernels: CIC deposit, CIC gather fused with kick and drift, the
+// GR-minus-Newton displacement combination and the lattice step of the initial
+// conditions.  One thread per particle; particles are in Lagrangian order, so
+// neighbouring threads touch neighbouring cells and blocks are mapped XCD-contiguous.
+#include <math.h>
+
+#include "pm_common.h"
+#include "pm_plan.h"
+
+namespace pm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, int64_t count, T v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+// Periodic wrap into [0, N): x - N floor(x/N); a rounded quotient that overshoots
+// (possible when N is not a power of two) is corrected by +N, and a result that
+// rounds to N becomes 0.  Non-finite input maps to 0, so every derived cell index
+// stays inside the mesh.
+template <typename T>
+__device__ __forceinline__ T wrap(T x, int n) {
+  const T fn = T(n);
+  T y = x - fn * floor(x / fn);
+  if (y < T(0)) y += fn;
+  return (y >= fn || !(y >= T(0))) ? T(0) : y;
+}
+
+// CIC base node and weights of one coordinate (x in [0, N)).
+template <typename T>
+struct Axis {
+  int i0, i1;
+  T w0, w1;
+};
+template <typename T>
+__device__ __forceinline__ Axis<T> cic_axis(T x, int n) {
+  Axis<T> a;
+  const T f = floor(x);
+  a.i0 = (int)f;
+  a.i1 = a.i0 + 1 == n ? 0 : a.i0 + 1;
+  a.w1 = x - f;
+  a.w0 = T(1) - a.w1;
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ void atomic_add(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_deposit(const T* __restrict__ pos, int64_t np, T* __restrict__ mesh, int n,
+                                                    T w_scale, unsigned* __restrict__ guard) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = blk * kBlock + threadIdx.x;
+  if (i >= np) return;
+  T x = pos[i], y = pos[np + i], z = pos[2 * np + i];
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+    atomicAdd(&guard[0], 1u);
+    return;
+  }
+  const T fn = T(n);
+  if (!(x >= T(0) && x < fn && y >= T(0) && y < fn && z >= T(0) && z < fn)) {
+    atomicAdd(&guard[1], 1u);
+    x = wrap(x, n);
+    y = wrap(y, n);
+    z = wrap(z, n);
+  }
+  const Axis<T> ax = cic_axis(x, n), ay = cic_axis(y, n), az = cic_axis(z, n);
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t r00 = ax.i0 * n2 + (int64_t)ay.i0 * n, r01 = ax.i0 * n2 + (int64_t)ay.i1 * n;
+  const int64_t r10 = ax.i1 * n2 + (int64_t)ay.i0 * n, r11 = ax.i1 * n2 + (int64_t)ay.i1 * n;
+  const T wxy00 = ax.w0 * ay.w0 * w_scale, wxy01 = ax.w0 * ay.w1 * w_scale;
+  const T wxy10 = ax.w1 * ay.w0 * w_scale, wxy11 = ax.w1 * ay.w1 * w_scale;
+  atomic_add(mesh + r00 + az.i0, wxy00 * az.w0);
+  atomic_add(mesh + r00 + az.i1, wxy00 * az.w1);
+  atomic_add(mesh + r01 + az.i0, wxy01 * az.w0);
+  atomic_add(mesh + r01 + az.i1, wxy01 * az.w1);
+  atomic_add(mesh + r10 + az.i0, wxy10 * az.w0);
+  atomic_add(mesh + r10 + az.i1, wxy10 * az.w1);
+  atomic_add(mesh + r11 + az.i0, wxy11 * az.w0);
+  atomic_add(mesh + r11 + az.i1, wxy11 * az.w1);
+}
+
+// sum over the 8 CIC corners of the three force components
+template <typename T>
+__device__ __forceinline__ void cic_interp3(const T* __restrict__ f, int n, T x, T y, T z, T& fx, T& fy, T& fz) {
+  const Axis<T> ax = cic_axis(x, n), ay = cic_axis(y, n), az = cic_axis(z, n);
+  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
+  const int64_t r[4] = {ax.i0 * n2 + (int64_t)ay.i0 * n, ax.i0 * n2 + (int64_t)ay.i1 * n,
+                        ax.i1 * n2 + (int64_t)ay.i0 * n, ax.i1 * n2 + (int64_t)ay.i1 * n};
+  const T w[4] = {ax.w0 * ay.w0, ax.w0 * ay.w1, ax.w1 * ay.w0, ax.w1 * ay.w1};
+  T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t a0 = r[c] + az.i0, a1 = r[c] + az.i1;
+    const T w0 = w[c] * az.w0, w1 = w[c] * az.w1;
+    sx += w0 * f[a0] + w1 * f[a1];
+    sy += w0 * f[n3 + a0] + w1 * f[n3 + a1];
+    sz += w0 * f[2 * n3 + a0] + w1 * f[2 * n3 + a1];
+  }
+  fx = sx;
+  fy = sy;
+  fz = sz;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gather(const T* __restrict__ force, const T* __restrict__ pos, int64_t np,
+                                                   int n, T* __restrict__ acc) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = blk * kBlock + threadIdx.x;
+  if (i >= np) return;
+  T fx, fy, fz;
+  cic_interp3(force, n, wrap(pos[i], n), wrap(pos[np + i], n), wrap(pos[2 * np + i], n), fx, fy, fz);
+  acc[i] = fx;
+  acc[np + i] = fy;
+  acc[2 * np + i] = fz;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gather_kdk(const T* __restrict__ force, T* __restrict__ pos,
+                                                       T* __restrict__ mom, int64_t np, int n, T kick, T drift) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = blk * kBlock + threadIdx.x;
+  if (i >= np) return;
+  T x = wrap(pos[i], n), y = wrap(pos[np + i], n), z = wrap(pos[2 * np + i], n);
+  T fx, fy, fz;
+  cic_interp3(force, n, x, y, z, fx, fy, fz);
+  T px = mom[i] + kick * fx, py = mom[np + i] + kick * fy, pz = mom[2 * np + i] + kick * fz;
+  mom[i] = px;
+  mom[np + i] = py;
+  mom[2 * np + i] = pz;
+  pos[i] = wrap(x + drift * px, n);
+  pos[np + i] = wrap(y + drift * py, n);
+  pos[2 * np + i] = wrap(z + drift * pz, n);
+}
+
+// eq. xiGR (minimum image, coarse cells) interpolated in Lagrangian coordinates to
+// the fine lattice and added to the fine positions (eq. combined).
+template <typename T>
+__device__ __forceinline__ T min_image(T d, int n) {
+  const T fn = T(n);
+  const T s = d + T(0.5) * fn;
+  return s - fn * floor(s / fn) - T(0.5) * fn;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, const T* __restrict__ xn, int nc,
+                                                    const T* __restrict__ xf, int nf, T* __restrict__ out) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t j = blk * kBlock + threadIdx.x;
+  const int64_t npf = (int64_t)nf * nf * nf;
+  if (j >= npf) return;
+  const int64_t npc = (int64_t)nc * nc * nc;
+  const int jf[3] = {(int)(j / ((int64_t)nf * nf)), (int)((j / nf) % nf), (int)(j % nf)};
+  int i0[3], i1[3];
+  T t[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    // u = ((2j+1) nc - nf) / (2 nf): integer floor division and exact remainder
+    const int64_t num = (int64_t)(2 * jf[d] + 1) * nc - nf;
+    const int64_t den = 2 * (int64_t)nf;
+    int64_t q = num >= 0 ? num / den : -((-num + den - 1) / den);
+    const int64_t rem = num - q * den;
+    i0[d] = (int)((q % nc + nc) % nc);
+    i1[d] = i0[d] + 1 == nc ? 0 : i0[d] + 1;
+    t[d] = T(rem) / T(den);
+  }
+  T xi[3] = {0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int cx_ = (c >> 2) & 1, cy_ = (c >> 1) & 1, cz_ = c & 1;
+    const int64_t id = ((int64_t)(cx_ ? i1[0] : i0[0]) * nc + (cy_ ? i1[1] : i0[1])) * nc + (cz_ ? i1[2] : i0[2]);
+    const T w = (cx_ ? t[0] : T(1) - t[0]) * (cy_ ? t[1] : T(1) - t[1]) * (cz_ ? t[2] : T(1) - t[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xi[d] += w * min_image(xg[d * npc + id] - xn[d * npc + id], nc);
+  }
+  const T ratio = T(nf) / T(nc);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) out[d * npf + j] = wrap(xf[d * npf + j] + ratio * xi[d], nf);
+}
+
+// Lattice step of the initial conditions: pos = wrap(q + disp), mom = c * disp,
+// q = (i, j, l) + 1/2 for particle (i N + j) N + l.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ic_lattice(const T* __restrict__ disp, T* __restrict__ pos,
+                                                       T* __restrict__ mom, int n, T mom_factor) {
+  const int64_t np = (int64_t)n * n * n;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= np) return;
+  const int q[3] = {(int)(j / ((int64_t)n * n)), (int)((j / n) % n), (int)(j % n)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const T s = disp[d * np + j];
+    pos[d * np + j] = wrap(T(q[d]) + T(0.5) + s, n);
+    mom[d * np + j] = mom_factor * s;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ic_gauge_lattice(const T* __restrict__ xi, const T* __restrict__ pn,
+                                                             const T* __restrict__ mn, T* __restrict__ pg,
+                                                             T* __restrict__ mg, int n, T mom_factor) {
+  const int64_t np = (int64_t)n * n * n;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= np) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const T s = xi[d * np + j];
+    pg[d * np + j] = wrap(pn[d * np + j] + s, n);
+    mg[d * np + j] = mn[d * np + j] + mom_factor * s;
+  }
+}
+
+}  // namespace
+
+int launch_fill(const pm_plan* p, void* mesh, int64_t count, double value, hipStream_t s) {
+  ProfScope ps(p, PK_FILL, s);
+  if (count <= 0) return PM_OK;
+  const unsigned g = (unsigned)std::min<int64_t>((count + kBlock - 1) / kBlock, 65536);
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(kBlock), 0, s, static_cast<float*>(mesh), count, (float)value);
+  else
+    hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kBlock), 0, s, static_cast<double*>(mesh), count, value);
+  return hip_check(hipGetLastError(), "fill");
+}
+
+int launch_deposit(const pm_plan* p, const void* pos, int64_t np, void* mesh, hipStream_t s) {
+  ProfScope ps(p, PK_DEPOSIT, s);
+  if (np <= 0) return PM_OK;
+  const double n3 = (double)p->n * p->n * p->n;
+  const double w = n3 / (double)np;  // 1 / nbar
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_deposit<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(pos), np,
+                       static_cast<float*>(mesh), p->n, (float)w, p->guard);
+  else
+    hipLaunchKernelGGL(k_deposit<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(pos), np,
+                       static_cast<double*>(mesh), p->n, w, p->guard);
+  return hip_check(hipGetLastError(), "deposit");
+}
+
+int launch_gather(const pm_plan* p, const void* force, const void* pos, int64_t np, void* acc, hipStream_t s) {
+  ProfScope ps(p, PK_GATHER, s);
+  if (np <= 0) return PM_OK;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_gather<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(force),
+                       static_cast<const float*>(pos), np, p->n, static_cast<float*>(acc));
+  else
+    hipLaunchKernelGGL(k_gather<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(force),
+                       static_cast<const double*>(pos), np, p->n, static_cast<double*>(acc));
+  return hip_check(hipGetLastError(), "gather");
+}
+
+int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom, int64_t np, double kick,
+                      double drift, hipStream_t s) {
+  ProfScope ps(p, PK_GATHER_KDK, s);
+  if (np <= 0) return PM_OK;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_gather_kdk<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(force),
+                       static_cast<float*>(pos), static_cast<float*>(mom), np, p->n, (float)kick, (float)drift);
+  else
+    hipLaunchKernelGGL(k_gather_kdk<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(force),
+                       static_cast<double*>(pos), static_cast<double*>(mom), np, p->n, kick, drift);
+  return hip_check(hipGetLastError(), "gather-kick-drift");
+}
+
+int launch_combine(const void* x_gr, const void* x_n, int nc, const void* x_f, int nf, int dtype, void* x_out,
+                   hipStream_t s) {
+  const int64_t npf = (int64_t)nf * nf * nf;
+  if (dtype == PM_F32)
+    hipLaunchKernelGGL(k_combine<float>, dim3(nblocks(npf)), dim3(kBlock), 0, s, static_cast<const float*>(x_gr),
+                       static_cast<const float*>(x_n), nc, static_cast<const float*>(x_f), nf,
+                       static_cast<float*>(x_out));
+  else
+    hipLaunchKernelGGL(k_combine<double>, dim3(nblocks(npf)), dim3(kBlock), 0, s, static_cast<const double*>(x_gr),
+                       static_cast<const double*>(x_n), nc, static_cast<const double*>(x_f), nf,
+                       static_cast<double*>(x_out));
+  return hip_check(hipGetLastError(), "displacement combine");
+}
+
+int launch_ic_lattice(const pm_plan* p, const void* disp, void* pos, void* mom, double mom_factor, hipStream_t s) {
+  ProfScope ps(p, PK_IC, s);
+  const int64_t np = (int64_t)p->n * p->n * p->n;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_ic_lattice<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(disp),
+                       static_cast<float*>(pos), static_cast<float*>(mom), p->n, (float)mom_factor);
+  else
+    hipLaunchKernelGGL(k_ic_lattice<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(disp),
+                       static_cast<double*>(pos), static_cast<double*>(mom), p->n, mom_factor);
+  return hip_check(hipGetLastError(), "ic lattice");
+}
+
+int launch_ic_gauge_lattice(const pm_plan* p, const void* xi, const void* pos_n, const void* mom_n, void* pos_gr,
+                            void* mom_gr, double mom_factor, hipStream_t s) {
+  ProfScope ps(p, PK_IC, s);
+  const int64_t np = (int64_t)p->n * p->n * p->n;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_ic_gauge_lattice<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(xi),
+                       static_cast<const float*>(pos_n), static_cast<const float*>(mom_n),
+                       static_cast<float*>(pos_gr), static_cast<float*>(mom_gr), p->n, (float)mom_factor);
+  else
+    hipLaunchKernelGGL(k_ic_gauge_lattice<double>, dim3(nblocks(np)), dim3(kBlock), 0, s,
+                       static_cast<const double*>(xi), static_cast<const double*>(pos_n),
+                       static_cast<const double*>(mom_n), static_cast<double*>(pos_gr), static_cast<double*>(mom_gr),
+                       p->n, mom_factor);
+  return hip_check(hipGetLastError(), "ic gauge lattice");
+}
+
+}  // namespace pm

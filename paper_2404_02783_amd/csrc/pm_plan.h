@@ -1,0 +1,122 @@
+// Plan object and internal launch entry points of the pmhip library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pmhip.h"
+
+namespace pm {
+// Kernel kinds timed by the optional per-plan profiler.
+enum ProfKind {
+  PK_FILL = 0,
+  PK_DEPOSIT,
+  PK_R2C_ROWS,
+  PK_COLS_FWD_AXIS1,
+  PK_COLS_FWD_AXIS0,
+  PK_SOLVE_AXIS0,
+  PK_COLS_INV_AXIS0,
+  PK_COLS_INV_AXIS1,
+  PK_C2R_ROWS,
+  PK_GATHER,
+  PK_GATHER_KDK,
+  PK_COMBINE,
+  PK_IC,
+  PK_PK,
+  PK_BK,
+  PK_COUNT
+};
+struct ProfState;
+}  // namespace pm
+
+struct pm_plan {
+  pm::ProfState* prof;  // null unless profiling is enabled
+  int n;             // mesh cells per axis
+  int dtype;         // PM_F32 | PM_F64
+  double box;        // Mpc/h
+  size_t esize;      // sizeof(real)
+  void* ws;          // workspace: three [N][N][N/2+1] complex buffers
+  size_t ws_bytes;
+  size_t cbytes;     // bytes of one complex buffer (256-byte aligned)
+  bool own_ws;
+  void* tw;          // device twiddle table W_N^m, m < N, complex of the plan's type
+  unsigned* guard;   // device counters: [0] non-finite positions, [1] wrapped positions
+  double* sums;      // device reduction scratch (estimators)
+  size_t sums_cap;   // doubles in `sums`
+  int device;
+};
+
+namespace pm {
+
+// Error helpers (api.cpp)
+int set_error(int code, const char* fmt, ...);
+int hip_check(hipError_t e, const char* what);
+
+inline void* cbuf(const pm_plan* p, int i) { return static_cast<char*>(p->ws) + (size_t)i * p->cbytes; }
+
+// Records a start/stop HIP event pair around the launches in its scope when the
+// plan's profiler is on (api.cpp).
+void prof_begin(const pm_plan* p, int kind, hipStream_t s);
+void prof_end(const pm_plan* p, hipStream_t s);
+struct ProfScope {
+  const pm_plan* p;
+  hipStream_t s;
+  ProfScope(const pm_plan* plan, int kind, hipStream_t stream) : p(plan), s(stream) {
+    if (p && p->prof) prof_begin(p, kind, s);
+  }
+  ~ProfScope() {
+    if (p && p->prof) prof_end(p, s);
+  }
+};
+
+// ---------------------------------------------------------------- fft.hip --
+// Forward 3-D r2c: real [N][N][N] -> complex [N][N][N/2+1] (unnormalised).
+int fft3_r2c(const pm_plan* p, const void* real_in, void* cplx_out, hipStream_t s);
+// Inverse 3-D c2r of `ncomp` spectra spaced comp_stride complex elements apart
+// (destroyed) -> ncomp real meshes spaced N^3 apart (unnormalised: N^3 times the
+// inverse DFT).
+int fft3_c2r(const pm_plan* p, int ncomp, void* cplx_in, int64_t comp_stride, void* real_out, hipStream_t s);
+// Forward column pass along axis 0 only (used after r2c rows + axis-1 pass).
+int fft_pass_cols(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s);
+int fft_pass_rows_r2c(const pm_plan* p, const void* in, void* out, hipStream_t s);
+int fft_pass_rows_c2r(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* out, hipStream_t s);
+// Fused solve pass along axis 0 on cbuf(0): writes force spectra to cbuf 0, 1, 2.
+int fft_pass_solve(const pm_plan* p, const pm_solve_params* sp, void* phi_state, hipStream_t s);
+
+// ---------------------------------------------------------- particles.hip --
+int launch_fill(const pm_plan* p, void* mesh, int64_t count, double value, hipStream_t s);
+int launch_deposit(const pm_plan* p, const void* pos, int64_t np, void* mesh, hipStream_t s);
+int launch_gather(const pm_plan* p, const void* force, const void* pos, int64_t np, void* acc, hipStream_t s);
+int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom, int64_t np, double kick,
+                      double drift, hipStream_t s);
+int launch_combine(const void* x_gr, const void* x_n, int nc, const void* x_f, int nf, int dtype, void* x_out,
+                   hipStream_t s);
+int launch_ic_lattice(const pm_plan* p, const void* disp, void* pos, void* mom, double mom_factor, hipStream_t s);
+int launch_ic_gauge_lattice(const pm_plan* p, const void* xi, const void* pos_n, const void* mom_n, void* pos_gr,
+                            void* mom_gr, double mom_factor, hipStream_t s);
+
+// ------------------------------------------------------------ spectra.hip --
+struct IcSymbol {
+  int pk_kind;
+  double amp, index;         // P(k) = amp k^index T(k)^2
+  double om, ob, h, tcmb;    // cosmology for T(k)
+  double kf;                 // 2 pi / L (h/Mpc)
+  double inv_dx3;            // 1 / dx^3
+  double growth;             // D(a_init)/D(a_norm)
+  double coef;               // multiplies the displacement symbol (includes 1/N^3)
+  int kpow;                  // 1: i k / k^2 (Zel'dovich), 2: i k / k^4 (gauge shift)
+};
+// cbuf(0) holds DFT(noise); writes the three displacement spectra to cbuf 0, 1, 2.
+int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, hipStream_t s);
+int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s);
+int launch_pk_finalize(const pm_plan* p, int n_bins, double* k_mean, double* pk, int64_t* n_modes, hipStream_t s);
+// dst = src * 1_S (src may be NULL: indicator); shell membership (2c-w)^2 <= 4|n|^2 < (2c+w)^2.
+int launch_shell_mask(const pm_plan* p, const void* src, void* dst, double lo4, double hi4, hipStream_t s);
+// sums[slot] += sum_x a*b*c (real meshes of N^3)
+int launch_triple_sum(const pm_plan* p, const void* a, const void* b, const void* c, double* slot, hipStream_t s);
+int launch_bk_finalize(const pm_plan* p, int n_tri, const double* sums, double* bk, double* ntri_out,
+                       const double* ntri_known, hipStream_t s);
+int launch_zero_doubles(double* d, int64_t n, hipStream_t s);
+
+}  // namespace pm

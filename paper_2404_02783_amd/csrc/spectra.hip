@@ -1,0 +1,315 @@
+// Fourier-space kernels that are not FFT passes: the initial-condition symbol,
+// the power-spectrum shell reduction and the bispectrum shell filter / triple sums.
+#include <math.h>
+
+#include "pm_common.h"
+#include "pm_plan.h"
+
+namespace pm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int signed_freq(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// Eisenstein & Hu (1998) no-wiggle transfer function (their sound-horizon fit, the
+// alpha_Gamma suppression, the effective shape Gamma and T0(q)); k in h/Mpc.
+__device__ double eh98_transfer(double k, double om, double ob, double h, double tcmb) {
+  const double omh2 = om * h * h, obh2 = ob * h * h, fb = ob / om, th = tcmb / 2.7;
+  const double s = 44.5 * log(9.83 / omh2) / sqrt(1.0 + 10.0 * pow(obh2, 0.75));
+  const double al = 1.0 - 0.328 * log(431.0 * omh2) * fb + 0.38 * log(22.3 * omh2) * fb * fb;
+  const double ks = 0.43 * k * h * s;
+  const double gam = om * h * (al + (1.0 - al) / (1.0 + ks * ks * ks * ks));
+  const double q = k * th * th / gam;
+  const double l0 = log(2.0 * 2.718281828459045235360287 + 1.8 * q);
+  const double c0 = 14.2 + 731.0 / (1.0 + 62.5 * q);
+  return l0 / (l0 + c0 * q * q);
+}
+
+// Zel'dovich / gauge-shift symbol on the natural [N][N][N/2+1] layout.  Input
+// cbuf(0) = DFT(noise).  delta_L = w_hat sqrt(P(k)/dx^3) growth (zero at k = 0 and on
+// Nyquist planes); output component d = coef * i k_d delta_L / k^(2 kpow) *
+// exp(i (k_x + k_y + k_z)/2) into cbuf(d).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx<T>* __restrict__ c1,
+                                                      cx<T>* __restrict__ c2, int n, IcSymbol sy) {
+  const int h = n / 2 + 1;
+  const int64_t total = (int64_t)n * n * h;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= total) return;
+  const int iz = (int)(idx % h);
+  const int iy = (int)((idx / h) % n);
+  const int ix = (int)(idx / ((int64_t)h * n));
+  const int nx = signed_freq(ix, n), ny = signed_freq(iy, n), nz = iz;
+  const bool nyq = (nx == -n / 2) || (ny == -n / 2) || (nz == n / 2);
+  const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
+  cx<T> out[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+  if (!nyq && n2 > 0) {
+    const double kmag = sy.kf * sqrt((double)n2);
+    double pk = sy.amp * pow(kmag, sy.index);
+    if (sy.pk_kind == PM_PK_EH98) {
+      const double tk = eh98_transfer(kmag, sy.om, sy.ob, sy.h, sy.tcmb);
+      pk *= tk * tk;
+    }
+    const double amp = sqrt(pk * sy.inv_dx3) * sy.growth;
+    const double s = 2.0 * kPi / n;
+    const double kx = s * nx, ky = s * ny, kz = s * nz;
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double inv = sy.kpow == 1 ? 1.0 / k2 : 1.0 / (k2 * k2);
+    double sn, cs;
+    sincos(0.5 * (kx + ky + kz), &sn, &cs);
+    const cx<T> w = ldc(c0 + idx);
+    // base = w * amp * inv * coef * e^{i phase}; component d = i k_d base
+    const double f = amp * inv * sy.coef;
+    const double br = f * ((double)w.x * cs - (double)w.y * sn);
+    const double bi = f * ((double)w.x * sn + (double)w.y * cs);
+    const double kd[3] = {kx, ky, kz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[d] = mk(T(-kd[d] * bi), T(kd[d] * br));
+  }
+  stc(c0 + idx, out[0]);
+  stc(c1 + idx, out[1]);
+  stc(c2 + idx, out[2]);
+}
+
+// Power-spectrum shell reduction.  Bin b of mode n: N^2 (2b+1)^2 <= 16 nb^2 |n|^2 <
+// N^2 (2b+3)^2, found from a floating estimate and settled with integer tests.
+// Per block: LDS accumulators (sum w |dhat|^2, sum w |n|, count); then one global
+// atomic per touched bin.  sums layout: [0, nb) power, [nb, 2nb) |n| sums,
+// [2nb, 3nb) counts (as unsigned 64-bit integers reinterpreted).
+__device__ __forceinline__ int pk_bin(int64_t n2, int n, int nb) {
+  const int64_t s = 16LL * nb * nb * n2;
+  const int64_t nn = (int64_t)n * n;
+  // (2b+1) <= 4 nb |n| / N  -> b ~ floor((4 nb |n|/N - 1)/2)
+  int b = (int)floor((4.0 * nb * sqrt((double)n2) / n - 1.0) * 0.5);
+  if (b < 0) b = 0;
+  for (int it = 0; it < 3; ++it) {
+    const int64_t lo = nn * (2LL * b + 1) * (2LL * b + 1);
+    const int64_t hi = nn * (2LL * b + 3) * (2LL * b + 3);
+    if (s < lo) {
+      if (b == 0) return -1;
+      --b;
+    } else if (s >= hi) {
+      ++b;
+    } else {
+      return b < nb ? b : -1;
+    }
+  }
+  return -1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ dhat, int n, int nb,
+                                                      double* __restrict__ sums) {
+  extern __shared__ double sh[];
+  double* sp = sh;
+  double* sk = sh + nb;
+  unsigned long long* sc = reinterpret_cast<unsigned long long*>(sh + 2 * nb);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    sp[b] = 0.0;
+    sk[b] = 0.0;
+    sc[b] = 0ull;
+  }
+  __syncthreads();
+  const int h = n / 2 + 1;
+  const int64_t total = (int64_t)n * n * h;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // Each thread walks modes; runs of the same bin are merged in registers.
+  int cur = -1;
+  double ap = 0.0, ak = 0.0;
+  unsigned long long ac = 0;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int iz = (int)(idx % h);
+    const int iy = (int)((idx / h) % n);
+    const int ix = (int)(idx / ((int64_t)h * n));
+    const int nx = signed_freq(ix, n), ny = signed_freq(iy, n);
+    const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)iz * iz;
+    const int b = n2 > 0 ? pk_bin(n2, n, nb) : -1;
+    if (b < 0) continue;
+    const int wgt = (iz == 0 || iz == n / 2) ? 1 : 2;
+    const cx<T> v = ldc(dhat + idx);
+    const double p2 = (double)v.x * v.x + (double)v.y * v.y;
+    if (b != cur) {
+      if (cur >= 0) {
+        atomicAdd(&sp[cur], ap);
+        atomicAdd(&sk[cur], ak);
+        atomicAdd(&sc[cur], ac);
+      }
+      cur = b;
+      ap = ak = 0.0;
+      ac = 0;
+    }
+    ap += wgt * p2;
+    ak += wgt * sqrt((double)n2);
+    ac += (unsigned long long)wgt;
+  }
+  if (cur >= 0) {
+    atomicAdd(&sp[cur], ap);
+    atomicAdd(&sk[cur], ak);
+    atomicAdd(&sc[cur], ac);
+  }
+  __syncthreads();
+  unsigned long long* gc = reinterpret_cast<unsigned long long*>(sums + 2 * nb);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    if (sc[b] == 0ull) continue;
+    atomicAdd(&sums[b], sp[b]);
+    atomicAdd(&sums[nb + b], sk[b]);
+    atomicAdd(&gc[b], sc[b]);
+  }
+}
+
+__global__ void k_pk_finalize(const double* __restrict__ sums, int nb, int n, double box, double* __restrict__ k_mean,
+                              double* __restrict__ pk, int64_t* __restrict__ n_modes) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const unsigned long long c = reinterpret_cast<const unsigned long long*>(sums + 2 * nb)[b];
+  const double kf = 2.0 * kPi / box;
+  const double vol = box * box * box;
+  const double n6 = (double)n * n * n * (double)n * n * n;
+  k_mean[b] = c ? kf * sums[nb + b] / (double)c : 0.0;
+  pk[b] = c ? vol / n6 * sums[b] / (double)c : 0.0;
+  n_modes[b] = (int64_t)c;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_shell_mask(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n,
+                                                       double lo4, double hi4) {
+  const int h = n / 2 + 1;
+  const int64_t total = (int64_t)n * n * h;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= total) return;
+  const int iz = (int)(idx % h);
+  const int iy = (int)((idx / h) % n);
+  const int ix = (int)(idx / ((int64_t)h * n));
+  const int nx = signed_freq(ix, n), ny = signed_freq(iy, n);
+  const double r4 = 4.0 * (double)((int64_t)nx * nx + (int64_t)ny * ny + (int64_t)iz * iz);
+  const bool in = r4 >= lo4 && r4 < hi4;
+  cx<T> v = mk(T(0), T(0));
+  if (in) v = src ? ldc(src + idx) : mk(T(1), T(0));
+  stc(dst + idx, v);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_triple_sum(const T* __restrict__ a, const T* __restrict__ b,
+                                                       const T* __restrict__ c, int64_t count, double scale,
+                                                       double* __restrict__ slot) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    acc += (double)a[i] * (double)b[i] * (double)c[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(slot, red[0] * scale);
+}
+
+__global__ void k_bk_finalize(const double* __restrict__ sums, int n_tri, int n, double box, double* __restrict__ bk,
+                              double* __restrict__ ntri_out, const double* __restrict__ ntri_known) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tri) return;
+  // sums[t]: sum_x d_a d_b d_c with fields scaled to the unnormalised inverse (x N^3 each);
+  // sums[n_tri + t]: same for the indicator fields, unless ntri_known is given.
+  const double n3 = (double)n * n * n;
+  const double n9 = n3 * n3 * n3;
+  const double ntri = ntri_known ? ntri_known[t] : sums[n_tri + t] / n3;  // N^6 sum_x I I I (I = IDFT(1_S))
+  const double num = sums[t] / (n3 * n3 * n3);                             // sum_x d d d (d = IDFT(...))
+  const double den = ntri / (n3 * n3);
+  const double vol = box * box * box;
+  bk[t] = den != 0.0 ? vol * vol / n9 * num / den : 0.0;
+  ntri_out[t] = ntri;
+}
+
+__global__ void k_zero_d(double* __restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = 0.0;
+}
+
+}  // namespace
+
+int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, hipStream_t s) {
+  ProfScope ps(p, PK_IC, s);
+  const int n = p->n;
+  const int64_t total = (int64_t)n * n * (n / 2 + 1);
+  const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_ic_symbol<float>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<float>*>(cbuf(p, 0)),
+                       static_cast<cx<float>*>(cbuf(p, 1)), static_cast<cx<float>*>(cbuf(p, 2)), n, sym);
+  else
+    hipLaunchKernelGGL(k_ic_symbol<double>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<double>*>(cbuf(p, 0)),
+                       static_cast<cx<double>*>(cbuf(p, 1)), static_cast<cx<double>*>(cbuf(p, 2)), n, sym);
+  return hip_check(hipGetLastError(), "ic symbol");
+}
+
+int launch_zero_doubles(double* d, int64_t n, hipStream_t s) {
+  if (n <= 0) return PM_OK;
+  hipLaunchKernelGGL(k_zero_d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, n);
+  return hip_check(hipGetLastError(), "zero");
+}
+
+int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s) {
+  ProfScope ps(p, PK_PK, s);
+  const int n = p->n;
+  const int64_t total = (int64_t)n * n * (n / 2 + 1);
+  int64_t g = (total + kBlock * 16 - 1) / (kBlock * 16);  // ~16 modes per thread
+  if (g < 1) g = 1;
+  if (g > 65535) g = 65535;
+  const size_t shm = (size_t)n_bins * 3 * sizeof(double);
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_pk_reduce<float>, dim3((unsigned)g), dim3(kBlock), shm, s,
+                       static_cast<const cx<float>*>(dhat), n, n_bins, p->sums);
+  else
+    hipLaunchKernelGGL(k_pk_reduce<double>, dim3((unsigned)g), dim3(kBlock), shm, s,
+                       static_cast<const cx<double>*>(dhat), n, n_bins, p->sums);
+  return hip_check(hipGetLastError(), "pk reduce");
+}
+
+int launch_pk_finalize(const pm_plan* p, int n_bins, double* k_mean, double* pk, int64_t* n_modes, hipStream_t s) {
+  ProfScope ps(p, PK_PK, s);
+  hipLaunchKernelGGL(k_pk_finalize, dim3((unsigned)((n_bins + 63) / 64)), dim3(64), 0, s, p->sums, n_bins, p->n, p->box,
+                     k_mean, pk, n_modes);
+  return hip_check(hipGetLastError(), "pk finalize");
+}
+
+int launch_shell_mask(const pm_plan* p, const void* src, void* dst, double lo4, double hi4, hipStream_t s) {
+  ProfScope ps(p, PK_BK, s);
+  const int n = p->n;
+  const int64_t total = (int64_t)n * n * (n / 2 + 1);
+  const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_shell_mask<float>, dim3(g), dim3(kBlock), 0, s, static_cast<const cx<float>*>(src),
+                       static_cast<cx<float>*>(dst), n, lo4, hi4);
+  else
+    hipLaunchKernelGGL(k_shell_mask<double>, dim3(g), dim3(kBlock), 0, s, static_cast<const cx<double>*>(src),
+                       static_cast<cx<double>*>(dst), n, lo4, hi4);
+  return hip_check(hipGetLastError(), "shell mask");
+}
+
+int launch_triple_sum(const pm_plan* p, const void* a, const void* b, const void* c, double* slot, hipStream_t s) {
+  ProfScope ps(p, PK_BK, s);
+  const int64_t count = (int64_t)p->n * p->n * p->n;
+  int64_t g = (count + kBlock * 8 - 1) / (kBlock * 8);
+  if (g < 1) g = 1;
+  if (g > 16384) g = 16384;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_triple_sum<float>, dim3((unsigned)g), dim3(kBlock), 0, s, static_cast<const float*>(a),
+                       static_cast<const float*>(b), static_cast<const float*>(c), count, 1.0, slot);
+  else
+    hipLaunchKernelGGL(k_triple_sum<double>, dim3((unsigned)g), dim3(kBlock), 0, s, static_cast<const double*>(a),
+                       static_cast<const double*>(b), static_cast<const double*>(c), count, 1.0, slot);
+  return hip_check(hipGetLastError(), "triple sum");
+}
+
+int launch_bk_finalize(const pm_plan* p, int n_tri, const double* sums, double* bk, double* ntri_out,
+                       const double* ntri_known, hipStream_t s) {
+  ProfScope ps(p, PK_BK, s);
+  hipLaunchKernelGGL(k_bk_finalize, dim3((unsigned)((n_tri + 63) / 64)), dim3(64), 0, s, sums, n_tri, p->n, p->box, bk,
+                     ntri_out, ntri_known);
+  return hip_check(hipGetLastError(), "bk finalize");
+}
+
+}  // namespace pm

@@ -1,0 +1,78 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry point,
+and its host-side cosmology agrees with the oracle (no GPU calls here)."""
+import math
+import os
+import re
+
+import pytest
+
+import paper_2404_02783_amd as pm
+from oracle import cosmology as ocm, ics as oics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pmhip.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", txt, flags=re.M)
+    return sorted({n for n in names if n not in ("if", "while", "for", "sizeof")})
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    l = pm.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(l, n), n
+
+
+def test_error_message_is_thread_local_string():
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = pm.lib().pm_plan_create(ctypes.byref(h), 100, 1.0, 0, None, 0)    # unsupported N: no device work
+    assert rc == -2
+    assert b"unsupported" in pm.lib().pm_last_error()
+    assert pm.lib().pm_plan_workspace_bytes(100, 0) == 0
+    assert pm.lib().pm_plan_workspace_bytes(64, 0) >= 3 * 64 * 64 * 33 * 8
+
+
+C = ocm.FIDUCIAL
+
+
+@pytest.mark.parametrize("a", [0.02, 0.1, 0.5, 1.0])
+def test_host_background_matches_oracle(a):
+    assert pm.cosmo_hubble_e(a) == pytest.approx(ocm.hubble_e(C, a), rel=1e-14)
+    assert pm.cosmo_omega_m_a(a) == pytest.approx(ocm.omega_m_of_a(C, a), rel=1e-13)
+    assert pm.cosmo_growth(a) == pytest.approx(ocm.growth_d(C, a), rel=1e-12)
+    assert pm.cosmo_growth_rate(a) == pytest.approx(ocm.growth_f(C, a), rel=1e-11)
+
+
+@pytest.mark.parametrize("a0,a1", [(0.02, 0.03), (0.05, 0.2), (0.5, 1.0)])
+def test_host_kick_drift_match_oracle(a0, a1):
+    k1, dr, k2 = pm.kdk_factors(a0, a1)
+    o1, odr, o2 = (ocm.kick_factor(C, a0, math.sqrt(a0 * a1)), ocm.drift_factor(C, a0, a1),
+                   ocm.kick_factor(C, math.sqrt(a0 * a1), a1))
+    assert (k1, dr, k2) == pytest.approx((o1, odr, o2), rel=1e-12)
+
+
+def test_host_gauge_params_match_oracle():
+    box, n, a, ap = 4000.0, 256, 0.3, 0.28
+    sp = pm.gauge_params(box, n, a, ap)
+    dx = box / n
+    cg = ocm.c_grid(dx)
+    assert sp.kind == pm.PM_POISSON_GAUGE
+    assert sp.c_g == pytest.approx(cg, rel=1e-14)
+    assert sp.calh == pytest.approx(ocm.conformal_hubble_grid(C, a, dx), rel=1e-13)
+    assert sp.om_a == pytest.approx(ocm.omega_m_of_a(C, a), rel=1e-13)
+    assert sp.inv_dtau == pytest.approx(1.0 / (cg * ocm.kick_factor(C, ap, a)), rel=1e-12)
+    assert pm.gauge_params(box, n, a, 0.0).inv_dtau == 0.0
+
+
+def test_host_power_amplitudes_match_oracle():
+    c65 = ocm.Cosmo(n_s=0.965)
+    amp = pm.power_eh98_amplitude(0.965, 0.81)
+    assert amp == pytest.approx(ocm.eh98_normalised(c65, 0.965, 0.81).amp, rel=1e-8)
+    a_pl = pm.power_law_amplitude(16, 1000.0, 0.2, -2.0)
+    assert a_pl == pytest.approx(oics.powerlaw_for_rms_displacement(16, 1000.0, 0.2).amp, rel=1e-12)

@@ -1,0 +1,334 @@
+"""Parity of every C-ABI entry point against the FP64 oracle on identical inputs.
+
+Bar: FP64 plans agree to ~1e-10 relative L2 (rounding order only); FP32 plans agree
+to 1e-5 relative L2 on fields; integer decisions (cell and shell assignment, mode
+counts) are bit-exact.  Sizes span several workgroups and ragged tails.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import cic, combine as ocomb, cosmology as ocm, estimators, ics as oics, integrate, solve as osolve
+
+gpu = pytest.mark.gpu
+pytestmark = gpu
+
+pm = pytest.importorskip("paper_2404_02783_amd")
+
+F32_TOL = 1e-5
+F64_TOL = 1e-10
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda")
+
+
+def _tol(dt):
+    return F32_TOL if dt == torch.float32 else F64_TOL
+
+
+def rel_l2(a, b):
+    a = torch.as_tensor(a).double().cpu()
+    b = torch.as_tensor(b).double().cpu()
+    return float(torch.linalg.norm((a - b).reshape(-1)) / max(float(torch.linalg.norm(b.reshape(-1))), 1e-300))
+
+
+def min_image(d, n):
+    return (d + n / 2) % n - n / 2
+
+
+DTYPES = [torch.float32, torch.float64]
+
+
+# ----------------------------------------------------------------- deposit --
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n,np_,kind", [(32, 32 ** 3, "lattice"), (64, 100003, "clustered"), (16, 777, "uniform")])
+def test_deposit(dt, n, np_, kind):
+    dev = _dev()
+    if kind == "lattice":
+        x = si.lattice_jitter_particles(n, 3, 0.7, dtype=np.float64)
+    elif kind == "clustered":
+        x = si.clustered_particles(n, np_, 4)
+    else:
+        x = si.uniform_particles(n, np_, 5)
+    pos = torch.from_numpy(x).to(dt).to(dev).contiguous()
+    plan = pm.Plan(n, 100.0, dt)
+    d = pm.pm_deposit(plan, pos)
+    torch.cuda.synchronize()
+    want = cic.deposit_delta(pos.double().cpu(), n)
+    assert rel_l2(d, want) < _tol(dt)
+    pm.pm_check(plan)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_deposit_assignment_bit_exact_on_nodes(dt):
+    # particles exactly on nodes put all their weight in one cell: the integer assignment
+    # decides the result, which must match the oracle exactly.
+    dev = _dev()
+    n = 16
+    g = si.rng(8)
+    x = g.integers(0, n, size=(3, 5000)).astype(np.float64)
+    x[:, :3] = [[0, 15, 7], [15, 0, 7], [0, 15, 7]]
+    pos = torch.from_numpy(x).to(dt).to(dev)
+    plan = pm.Plan(n, 100.0, dt)
+    d = pm.pm_deposit(plan, pos).double().cpu()
+    want = cic.deposit_delta(torch.from_numpy(x), n)
+    # counts are integers times N^3/Np: compare the counts exactly
+    scale = 5000 / n ** 3
+    assert torch.equal(torch.round((d + 1) * scale), torch.round((want + 1) * scale))
+
+
+def test_deposit_empty_and_guards():
+    dev = _dev()
+    n = 8
+    plan = pm.Plan(n, 10.0, torch.float32)
+    d = pm.pm_deposit(plan, torch.empty((3, 0), dtype=torch.float32, device=dev))
+    assert torch.all(d == -1)
+    pm.pm_check(plan)
+    pos = torch.tensor([[1.5, float("nan"), 9.5], [1.5, 2.0, 1.0], [1.5, 2.0, 1.0]], device=dev)
+    pm.pm_deposit(plan, pos)
+    with pytest.raises(pm.PMError) as e:
+        pm.pm_check(plan)
+    assert e.value.code == -5
+    pm.pm_check(plan)   # counters were cleared
+
+
+# ------------------------------------------------------------------- solve --
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 192])
+def test_newton_solve_random_field(dt, n):
+    dev = _dev()
+    delta = torch.from_numpy(si.random_real_mesh(n, 100 + n))
+    plan = pm.Plan(n, 500.0, dt)
+    f = pm.pm_solve(plan, delta.to(dt).to(dev), pm.newton_params())
+    torch.cuda.synchronize()
+    want = osolve.newton_forces(delta.to(dt).double(), ocm.FIDUCIAL.omega_m)
+    assert rel_l2(f, want) < _tol(dt)
+
+
+@pytest.mark.parametrize("grad", [pm.PM_GRAD_FD2, pm.PM_GRAD_FD1])
+def test_newton_solve_fd_gradients(grad):
+    dev = _dev()
+    n = 32
+    delta = torch.from_numpy(si.random_real_mesh(n, 7))
+    plan = pm.Plan(n, 500.0, torch.float64)
+    f = pm.pm_solve(plan, delta.to(dev), pm.newton_params(grad=grad))
+    want = osolve.newton_forces(delta, ocm.FIDUCIAL.omega_m, {1: "fd2", 2: "fd1"}[grad])
+    assert rel_l2(f, want) < F64_TOL
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_plane_wave_force_closed_form(dt):
+    dev = _dev()
+    n = 64
+    x = torch.arange(n, dtype=torch.float64)
+    gx, gy, gz = torch.meshgrid(x, x, x, indexing="ij")
+    m = (3, -5, 7)
+    k = [2 * math.pi * v / n for v in m]
+    arg = k[0] * gx + k[1] * gy + k[2] * gz
+    delta = 0.2 * torch.cos(arg)
+    plan = pm.Plan(n, 500.0, dt)
+    f = pm.pm_solve(plan, delta.to(dt).to(dev), pm.newton_params()).double().cpu()
+    k2 = sum(v * v for v in k)
+    for d in range(3):
+        want = -1.5 * ocm.FIDUCIAL.omega_m * 0.2 * k[d] * torch.sin(arg) / k2
+        assert rel_l2(f[d], want) < _tol(dt)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n", [16, 64])
+def test_poisson_gauge_solve(dt, n):
+    dev = _dev()
+    box = 8000.0
+    delta = torch.from_numpy(si.random_real_mesh(n, 300 + n)) * 0.05
+    # the carried potential is the spectrum of a real field (Hermitian on the n_z = 0, N/2 planes)
+    phi0 = torch.fft.rfftn(torch.from_numpy(si.random_real_mesh(n, 301)) * 1e-6)
+    phi0[0, 0, 0] = 0
+    sp = pm.gauge_params(box, n, 0.4, 0.35)
+    plan = pm.Plan(n, box, dt)
+    cd = torch.complex64 if dt == torch.float32 else torch.complex128
+    phi = phi0.to(cd).to(dev).clone().contiguous()
+    f = pm.pm_solve(plan, delta.to(dt).to(dev), sp, phi_state=phi)
+    torch.cuda.synchronize()
+    gp = osolve.GaugeParams(a=sp.a, om_a=sp.om_a, calh=sp.calh, c_g=sp.c_g, inv_dtau=sp.inv_dtau)
+    wf, wphi = osolve.poisson_gauge_forces(delta.to(dt).double(), phi0.to(cd).to(torch.complex128), gp)
+    assert rel_l2(f, wf) < _tol(dt)
+    got_phi = phi.cpu().to(torch.complex128)
+    assert rel_l2(torch.view_as_real(got_phi), torch.view_as_real(wphi)) < _tol(dt)
+
+
+# ------------------------------------------------------------------ gather --
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_gather(dt):
+    dev = _dev()
+    n = 32
+    force = torch.from_numpy(np.stack([si.random_real_mesh(n, s) for s in (1, 2, 3)]))
+    x = torch.from_numpy(si.clustered_particles(n, 50001, 6))
+    plan = pm.Plan(n, 100.0, dt)
+    xd = x.to(dt).to(dev).contiguous()
+    acc = pm.pm_gather(plan, force.to(dt).to(dev).contiguous(), xd)
+    want = cic.gather(force.to(dt).double(), xd.double().cpu())
+    assert rel_l2(acc, want) < _tol(dt)
+
+
+# -------------------------------------------------------------------- step --
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_step_matches_force_kick_drift(dt):
+    dev = _dev()
+    n = 32
+    x = torch.from_numpy(si.lattice_jitter_particles(n, 9, 0.8))
+    v = torch.from_numpy(si.rng(10).standard_normal((3, n ** 3))) * 0.05
+    plan = pm.Plan(n, 200.0, dt)
+    pos, mom = x.to(dt).to(dev).contiguous(), v.to(dt).to(dev).contiguous()
+    pos0, mom0 = pos.double().cpu().clone(), mom.double().cpu().clone()
+    st = pm.StepParams(kick=0.7, drift=1.3, solve=pm.newton_params())
+    force = plan.mesh(3)
+    pm.pm_step(plan, pos, mom, st, force)
+    torch.cuda.synchronize()
+    f = integrate.NewtonForce(n)
+    wx, wv = integrate.force_then_kick_drift(pos0, mom0, 0.7, 1.3, f, 0.0, n)
+    assert rel_l2(mom, wv) < _tol(dt)
+    d = min_image(pos.double().cpu() - wx, n)
+    assert float(torch.linalg.norm(d)) / float(torch.linalg.norm(wx)) < _tol(dt)
+
+
+# ----------------------------------------------------------------- combine --
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("nc,nf", [(8, 32), (16, 16), (16, 32)])
+def test_displacement_combine(dt, nc, nf):
+    dev = _dev()
+    xn = torch.from_numpy(si.lattice_jitter_particles(nc, 11, 0.9))
+    xg = cic.wrap(xn + 0.3 * torch.from_numpy(si.rng(12).standard_normal((3, nc ** 3))), nc)
+    xf = torch.from_numpy(si.lattice_jitter_particles(nf, 13, 0.9))
+    a, b, c = (t.to(dt).to(dev).contiguous() for t in (xg, xn, xf))
+    out = pm.displacement_combine(a, b, nc, c, nf)
+    want = ocomb.combine(a.double().cpu(), b.double().cpu(), nc, c.double().cpu(), nf)
+    d = min_image(out.double().cpu() - want, nf)
+    tol = 1e-6 if dt == torch.float32 else 1e-12
+    assert float(d.abs().max()) < tol * nf
+
+
+# ------------------------------------------------------------------- P(k) --
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n,nb", [(32, 16), (64, 32), (64, 13), (192, 96)])
+def test_pk_estimate(dt, n, nb):
+    dev = _dev()
+    delta = torch.from_numpy(si.random_real_mesh(n, 40 + nb))
+    plan = pm.Plan(n, 1000.0, dt)
+    k, p, c = pm.pk_estimate(plan, delta.to(dt).to(dev), nb)
+    wk, wp, wc = estimators.power_spectrum(delta.to(dt).double(), 1000.0, nb)
+    assert torch.equal(c.cpu(), wc)
+    assert rel_l2(p, wp) < _tol(dt)
+    assert rel_l2(k, wk) < 1e-12
+
+
+# ------------------------------------------------------------------- B(k) --
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_bk_estimate(dt):
+    dev = _dev()
+    n = 32
+    pos = torch.from_numpy(si.clustered_particles(n, 40000, 14, n_clumps=40, width=1.0))
+    delta = cic.deposit_delta(pos, n)
+    centres = [float(m) for m in range(1, 9)] + [4.0]
+    tris = [(i, i, i) for i in range(8)] + [(i, i, 8) for i in range(2, 8)] + [(1, 2, 2), (2, 3, 4)]
+    plan = pm.Plan(n, 500.0, dt)
+    bk, ntri = pm.bk_estimate(plan, delta.to(dt).to(dev), centres, 1.0, tris)
+    wb, wn = estimators.bispectrum(delta.to(dt).double(), 500.0, centres, 1.0, tris)
+    assert rel_l2(ntri, wn) < _tol(dt)
+    assert rel_l2(bk, wb) < (1e-4 if dt == torch.float32 else F64_TOL)
+    # cached indicator counts reproduce the same result
+    bk2, ntri2 = pm.bk_estimate(plan, delta.to(dt).to(dev), centres, 1.0, tris, ntri_known=ntri)
+    assert torch.allclose(bk2, bk, rtol=1e-12, atol=0)
+    assert torch.equal(ntri2, ntri)
+
+
+# ---------------------------------------------------------------- ICs ------
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("kind", ["powerlaw", "eh98"])
+def test_initial_conditions(dt, kind):
+    dev = _dev()
+    n, box, a_i = 32, 1000.0, 0.02
+    c = ocm.Cosmo(n_s=0.965)
+    if kind == "powerlaw":
+        power = oics.powerlaw_for_rms_displacement(n, box, 0.2)
+        a_norm = a_i
+        icp = pm.ICParams(pk_kind=pm.PM_PK_POWERLAW, amp=pm.power_law_amplitude(n, box, 0.2), index=-2.0,
+                          a_init=a_i, a_norm=a_norm, cosmo=pm.FIDUCIAL)
+    else:
+        power = ocm.eh98_normalised(c, 0.965, 0.81)
+        a_norm = 1.0
+        icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965,
+                          a_init=a_i, a_norm=a_norm, cosmo=pm.FIDUCIAL)
+    noise = torch.from_numpy(si.white_noise(n, 77))
+    p = oics.ICParams(n=n, box=box, a_init=a_i, power=power, a_norm=a_norm, cosmo=c)
+    wpn, wmn, wpg, wmg = oics.zeldovich_pair(noise.to(dt).double(), p)
+    plan = pm.Plan(n, box, dt)
+    disp = plan.mesh(3)
+    pos = torch.empty((3, n ** 3), dtype=dt, device=dev)
+    mom = torch.empty_like(pos)
+    pm.pm_ic_zeldovich(plan, noise.to(dt).to(dev), icp, disp, pos, mom)
+    pg = torch.empty_like(pos)
+    mg = torch.empty_like(pos)
+    pm.pm_ic_gauge(plan, noise.to(dt).to(dev), icp, disp, pos, mom, pg, mg)
+    torch.cuda.synchronize()
+    q = oics.lagrangian_lattice(n)
+    tol = _tol(dt)
+    assert rel_l2(min_image(pos.double().cpu() - q, n), min_image(wpn - q, n)) < tol
+    assert rel_l2(mom, wmn) < tol
+    assert rel_l2(min_image(pg.double().cpu() - pos.double().cpu(), n), min_image(wpg - wpn, n)) < 10 * tol
+    assert float((mg.double().cpu() - wmg).abs().max()) < 10 * tol * float(wmn.abs().max())
+
+
+# ------------------------------------------------------- end-to-end FP64 ----
+
+@pytest.mark.slow
+def test_config1_paired_run_fp64():
+    """32^3 particles, L = 1000 Mpc/h, power law with rms displacement 0.2 cell at a = 0.02,
+    10 log steps to a = 0.1, Newtonian and Poisson-gauge sets, P(k) in 16 bins."""
+    dev = _dev()
+    n, box, a_i, a_f, steps = 32, 1000.0, 0.02, 0.1, 10
+    power = oics.powerlaw_for_rms_displacement(n, box, 0.2)
+    p = oics.ICParams(n=n, box=box, a_init=a_i, power=power, a_norm=a_i)
+    noise = torch.from_numpy(si.white_noise(n, 1))
+    wpn, wmn, wpg, wmg = oics.zeldovich_pair(noise, p)
+    a_s = ocm.log_steps(a_i, a_f, steps)
+    xn, vn = integrate.run_kdk(wpn, wmn, a_s, integrate.NewtonForce(n), n)
+    xg, vg = integrate.run_kdk(wpg, wmg, a_s, integrate.GaugeForce(n, box / n), n)
+
+    plan = pm.Plan(n, box, torch.float64)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_POWERLAW, amp=pm.power_law_amplitude(n, box, 0.2), index=-2.0,
+                      a_init=a_i, a_norm=a_i, cosmo=pm.FIDUCIAL)
+    disp = plan.mesh(3)
+    pos = torch.empty((3, n ** 3), dtype=torch.float64, device=dev)
+    mom = torch.empty_like(pos)
+    pm.pm_ic_zeldovich(plan, noise.to(dev), icp, disp, pos, mom)
+    pg, mg = torch.empty_like(pos), torch.empty_like(pos)
+    pm.pm_ic_gauge(plan, noise.to(dev), icp, disp, pos, mom, pg, mg)
+    rn = pm.sim.Run(plan, pos, mom)
+    rn.leapfrog(pm.sim.log_steps(a_i, a_f, steps))
+    rg = pm.sim.Run(plan, pg, mg, gauge=True)
+    rg.leapfrog(pm.sim.log_steps(a_i, a_f, steps))
+    torch.cuda.synchronize()
+    for got, want in ((pos, xn), (pg, xg)):
+        d = min_image(got.cpu() - want, n)
+        assert float(d.abs().max()) < 1e-9
+    assert rel_l2(mom, vn) < 1e-10
+    assert rel_l2(mg, vg) < 1e-10
+    for x in (pos, pg):
+        _, pk, cnt = pm.pk_estimate(plan, pm.pm_deposit(plan, x), 16)
+        _, wpk, wcnt = estimators.power_spectrum(cic.deposit_delta(x.cpu(), n), box, 16)
+        assert torch.equal(cnt.cpu(), wcnt)
+        assert rel_l2(pk, wpk) < 1e-10
