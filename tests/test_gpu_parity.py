@@ -280,15 +280,22 @@ def test_initial_conditions(dt, kind):
     pos = torch.empty((3, n ** 3), dtype=dt, device=dev)
     mom = torch.empty_like(pos)
     pm.pm_ic_zeldovich(plan, noise.to(dt).to(dev), icp, disp, pos, mom)
+    psi = disp.reshape(3, -1).double().cpu().clone()
     pg = torch.empty_like(pos)
     mg = torch.empty_like(pos)
     pm.pm_ic_gauge(plan, noise.to(dt).to(dev), icp, disp, pos, mom, pg, mg)
     torch.cuda.synchronize()
-    q = oics.lagrangian_lattice(n)
+    xi = disp.reshape(3, -1).double().cpu()
     tol = _tol(dt)
-    assert rel_l2(min_image(pos.double().cpu() - q, n), min_image(wpn - q, n)) < tol
+    # fields: displacement and shift meshes, momenta
+    assert rel_l2(psi, oics.za_displacement(noise.to(dt).double(), p)) < tol
+    assert rel_l2(xi, oics.xi_linear(noise.to(dt).double(), p, a_i)[0]) < tol
     assert rel_l2(mom, wmn) < tol
-    assert rel_l2(min_image(pg.double().cpu() - pos.double().cpu(), n), min_image(wpg - wpn, n)) < 10 * tol
+    # positions: q + Psi rounded to the plan's precision (a displacement of 1e-3 cells is
+    # only resolved to ulp(N)/1e-3 in float32), so they are compared in ulps of N
+    ulp = float(torch.finfo(dt).eps) * n
+    assert float(min_image(pos.double().cpu() - wpn, n).abs().max()) < 4 * ulp
+    assert float(min_image(pg.double().cpu() - wpg, n).abs().max()) < 8 * ulp
     assert float((mg.double().cpu() - wmg).abs().max()) < 10 * tol * float(wmn.abs().max())
 
 
