@@ -1,10 +1,11 @@
-// Particle kernels: CIC deposit, CIC gather fused with kick and drift, the
+// Particle kernels: fill, CIC gather (plain and fused with kick and drift), the
 // GR-minus-Newton displacement combination and the lattice step of the initial
 // conditions.  One thread per particle; particles are in Lagrangian order, so
-// neighbouring threads touch neighbouring cells and blocks are mapped XCD-contiguous.
+// neighbouring threads touch neighbouring cells, and blocks are mapped
+// XCD-contiguous so each XCD's L2 sees a contiguous slab of the mesh.
 #include <math.h>
 
-#include "pm_common.h"
+#include "pm_particles.h"
 #include "pm_plan.h"
 
 namespace pm {
@@ -19,74 +20,6 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, int64_t count, T v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
-}
-
-// Periodic wrap into [0, N): x - N floor(x/N); a rounded quotient that overshoots
-// (possible when N is not a power of two) is corrected by +N, and a result that
-// rounds to N becomes 0.  Non-finite input maps to 0, so every derived cell index
-// stays inside the mesh.
-template <typename T>
-__device__ __forceinline__ T wrap(T x, int n) {
-  const T fn = T(n);
-  T y = x - fn * floor(x / fn);
-  if (y < T(0)) y += fn;
-  return (y >= fn || !(y >= T(0))) ? T(0) : y;
-}
-
-// CIC base node and weights of one coordinate (x in [0, N)).
-template <typename T>
-struct Axis {
-  int i0, i1;
-  T w0, w1;
-};
-template <typename T>
-__device__ __forceinline__ Axis<T> cic_axis(T x, int n) {
-  Axis<T> a;
-  const T f = floor(x);
-  a.i0 = (int)f;
-  a.i1 = a.i0 + 1 == n ? 0 : a.i0 + 1;
-  a.w1 = x - f;
-  a.w0 = T(1) - a.w1;
-  return a;
-}
-
-template <typename T>
-__device__ __forceinline__ void atomic_add(T* p, T v) {
-  unsafeAtomicAdd(p, v);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_deposit(const T* __restrict__ pos, int64_t np, T* __restrict__ mesh, int n,
-                                                    T w_scale, unsigned* __restrict__ guard) {
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = blk * kBlock + threadIdx.x;
-  if (i >= np) return;
-  T x = pos[i], y = pos[np + i], z = pos[2 * np + i];
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-    atomicAdd(&guard[0], 1u);
-    return;
-  }
-  const T fn = T(n);
-  if (!(x >= T(0) && x < fn && y >= T(0) && y < fn && z >= T(0) && z < fn)) {
-    atomicAdd(&guard[1], 1u);
-    x = wrap(x, n);
-    y = wrap(y, n);
-    z = wrap(z, n);
-  }
-  const Axis<T> ax = cic_axis(x, n), ay = cic_axis(y, n), az = cic_axis(z, n);
-  const int64_t n2 = (int64_t)n * n;
-  const int64_t r00 = ax.i0 * n2 + (int64_t)ay.i0 * n, r01 = ax.i0 * n2 + (int64_t)ay.i1 * n;
-  const int64_t r10 = ax.i1 * n2 + (int64_t)ay.i0 * n, r11 = ax.i1 * n2 + (int64_t)ay.i1 * n;
-  const T wxy00 = ax.w0 * ay.w0 * w_scale, wxy01 = ax.w0 * ay.w1 * w_scale;
-  const T wxy10 = ax.w1 * ay.w0 * w_scale, wxy11 = ax.w1 * ay.w1 * w_scale;
-  atomic_add(mesh + r00 + az.i0, wxy00 * az.w0);
-  atomic_add(mesh + r00 + az.i1, wxy00 * az.w1);
-  atomic_add(mesh + r01 + az.i0, wxy01 * az.w0);
-  atomic_add(mesh + r01 + az.i1, wxy01 * az.w1);
-  atomic_add(mesh + r10 + az.i0, wxy10 * az.w0);
-  atomic_add(mesh + r10 + az.i1, wxy10 * az.w1);
-  atomic_add(mesh + r11 + az.i0, wxy11 * az.w0);
-  atomic_add(mesh + r11 + az.i1, wxy11 * az.w1);
 }
 
 // sum over the 8 CIC corners of the three force components
@@ -230,20 +163,6 @@ int launch_fill(const pm_plan* p, void* mesh, int64_t count, double value, hipSt
   else
     hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kBlock), 0, s, static_cast<double*>(mesh), count, value);
   return hip_check(hipGetLastError(), "fill");
-}
-
-int launch_deposit(const pm_plan* p, const void* pos, int64_t np, void* mesh, hipStream_t s) {
-  ProfScope ps(p, PK_DEPOSIT, s);
-  if (np <= 0) return PM_OK;
-  const double n3 = (double)p->n * p->n * p->n;
-  const double w = n3 / (double)np;  // 1 / nbar
-  if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_deposit<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(pos), np,
-                       static_cast<float*>(mesh), p->n, (float)w, p->guard);
-  else
-    hipLaunchKernelGGL(k_deposit<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(pos), np,
-                       static_cast<double*>(mesh), p->n, w, p->guard);
-  return hip_check(hipGetLastError(), "deposit");
 }
 
 int launch_gather(const pm_plan* p, const void* force, const void* pos, int64_t np, void* acc, hipStream_t s) {

@@ -48,16 +48,24 @@ DTYPES = [torch.float32, torch.float64]
 # ----------------------------------------------------------------- deposit --
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("n,np_,kind", [(32, 32 ** 3, "lattice"), (64, 100003, "clustered"), (16, 777, "uniform")])
+@pytest.mark.parametrize("n,np_,kind", [(32, 32 ** 3, "lattice"), (64, 100003, "clustered"), (16, 777, "uniform"),
+                                         (128, 128 ** 3, "lattice"), (128, 128 ** 3, "lattice_far"),
+                                         (256, 256 ** 3, "lattice")])
 def test_deposit(dt, n, np_, kind):
+    # N^3 lattice runs at N >= 128 take the LDS-window path in FP32; "lattice_far" moves
+    # particles up to 5 cells, beyond the window halo, so the global fallback runs too.
     dev = _dev()
     if kind == "lattice":
         x = si.lattice_jitter_particles(n, 3, 0.7, dtype=np.float64)
+    elif kind == "lattice_far":
+        x = si.lattice_jitter_particles(n, 4, 5.0, dtype=np.float64)
     elif kind == "clustered":
         x = si.clustered_particles(n, np_, 4)
     else:
         x = si.uniform_particles(n, np_, 5)
-    pos = torch.from_numpy(x).to(dt).to(dev).contiguous()
+    pos = torch.from_numpy(x).to(dt)
+    pos[pos >= n] = 0          # a coordinate just below N can round up to N in float32
+    pos = pos.to(dev).contiguous()
     plan = pm.Plan(n, 100.0, dt)
     d = pm.pm_deposit(plan, pos)
     torch.cuda.synchronize()
