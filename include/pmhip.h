@@ -113,8 +113,9 @@ typedef struct {
 
 /* ---------------------------------------------------------------- plans ------ */
 
-/* Bytes of device workspace a plan of mesh size n and dtype needs: three
- * [N][N][N/2+1] complex buffers (spectra of the density and the force components). */
+/* Bytes of device workspace a plan of mesh size n and dtype needs: three complex
+ * spectrum buffers (density and force components), each [N][N][hp] with the row
+ * length N/2+1 padded to a 128-byte multiple hp; the layout is internal. */
 size_t pm_plan_workspace_bytes(int n_mesh, int dtype);
 
 /* Create a plan for an N^3 mesh of a periodic box of side box_mpch (Mpc/h).

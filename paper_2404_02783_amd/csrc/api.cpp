@@ -34,7 +34,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 static size_t complex_bytes(int n, int dtype) {
   const size_t es = dtype == PM_F32 ? 4 : 8;
-  return align256((size_t)n * n * (n / 2 + 1) * 2 * es);
+  return align256((size_t)n * n * padded_half(n, (int)es) * 2 * es);
 }
 
 static int check_plan(const pm_plan* p) {
@@ -138,6 +138,7 @@ int pm_plan_create(pm_plan** out, int n_mesh, double box_mpch, int dtype, void* 
   p->box = box_mpch;
   p->esize = dtype == PM_F32 ? 4 : 8;
   p->cbytes = complex_bytes(n_mesh, dtype);
+  p->hp = padded_half(n_mesh, (int)p->esize);
   (void)hipGetDevice(&p->device);
   int rc = PM_OK;
   if (workspace) {

@@ -53,11 +53,11 @@ void launch_c2r_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx
   constexpr int M = L1 * L2;
   constexpr int TPC = L1 > L2 ? L1 : L2;
   constexpr int XS = L1 * (L2 + 1);
-  constexpr int RS = XS > (M + 1) ? XS : (M + 1);
+  (void)M;
   const int R = 256 / TPC;
   dim3 grid((unsigned)((g.nrows + R - 1) / R), (unsigned)ncomp);
   dim3 block((unsigned)(R * TPC));
-  hipLaunchKernelGGL((k_fft_rows_c2r<T, L1, L2>), grid, block, (size_t)R * RS * sizeof(cx<T>), s, in, out, g, tw);
+  hipLaunchKernelGGL((k_fft_rows_c2r<T, L1, L2>), grid, block, (size_t)R * XS * sizeof(cx<T>), s, in, out, g, tw);
 }
 
 template <typename T, int L1, int L2>
@@ -67,7 +67,17 @@ void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* o2, cx<T>* phi, const ColArgs
   dim3 grid((unsigned)(outer * g.groups), 1);
   dim3 block((unsigned)(g.bcols * tpc));
   size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
-  hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2>), grid, block, shm, s, data, o1, o2, phi, g, a, tw);
+  // y/z components first (they also update the carried potential), then the x
+  // component, written over the spectrum the first launch still reads
+  if (a.kind == PM_NEWTON) {
+    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_NEWTON, 1>), grid, block, shm, s, data, o1, o2, phi, g, a, tw);
+    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_NEWTON, 0>), grid, block, shm, s, data, o1, o2, phi, g, a, tw);
+  } else {
+    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_POISSON_GAUGE, 1>), grid, block, shm, s, data, o1, o2, phi, g,
+                       a, tw);
+    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_POISSON_GAUGE, 0>), grid, block, shm, s, data, o1, o2, phi, g,
+                       a, tw);
+  }
 }
 
 // Dispatch on a transform length L to the compile-time (L1, L2) instantiation.
@@ -87,11 +97,13 @@ void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* o2, cx<T>* phi, const ColArgs
     default: return set_error(PM_ERR_SIZE, "unsupported transform length %d", (int)(L)); \
   }
 
-ColArgs col_args(int n, int axis, int bcols) {
+// Strides of the internal spectrum [N][N][hp] (hp = padded N/2+1) for a pass along
+// axis 1 (columns (ix, iz)) or axis 0 (columns (iy, iz)); N/2+1 columns are valid.
+ColArgs col_args(int n, int hp, int axis, int bcols) {
   const int64_t h = n / 2 + 1;
   ColArgs g;
-  g.stride = axis == 1 ? h : (int64_t)n * h;
-  g.outer_stride = axis == 1 ? (int64_t)n * h : h;
+  g.stride = axis == 1 ? hp : (int64_t)n * hp;
+  g.outer_stride = axis == 1 ? (int64_t)n * hp : hp;
   g.comp_stride = 0;
   g.ncols = (int)h;
   g.bcols = bcols;
@@ -103,7 +115,7 @@ ColArgs col_args(int n, int axis, int bcols) {
 template <typename T>
 int cols_t(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s) {
   const int n = p->n;
-  ColArgs g = col_args(n, axis, cols_per_block<T>(n));
+  ColArgs g = col_args(n, p->hp, axis, cols_per_block<T>(n));
   g.comp_stride = comp_stride;
   cx<T>* d = static_cast<cx<T>*>(data);
   const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
@@ -119,6 +131,7 @@ int r2c_t(const pm_plan* p, const void* in, void* out, hipStream_t s) {
   g.in_comp = 0;
   g.out_comp = 0;
   g.n = n;
+  g.hs = p->hp;
   const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
   PM_DISPATCH_LEN(n / 2, launch_r2c_t, static_cast<const T*>(in), static_cast<cx<T>*>(out), g, tw, s)
   return hip_check(hipGetLastError(), "fft r2c rows");
@@ -132,6 +145,7 @@ int c2r_t(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* ou
   g.in_comp = in_comp;
   g.out_comp = (int64_t)n * n * n;
   g.n = n;
+  g.hs = p->hp;
   const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
   PM_DISPATCH_LEN(n / 2, launch_c2r_t, static_cast<const cx<T>*>(in), static_cast<T*>(out), g, ncomp, tw, s)
   return hip_check(hipGetLastError(), "fft c2r rows");
@@ -140,7 +154,7 @@ int c2r_t(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* ou
 template <typename T>
 int solve_t(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t s) {
   const int n = p->n;
-  ColArgs g = col_args(n, 0, cols_per_block<T>(n));
+  ColArgs g = col_args(n, p->hp, 0, cols_per_block<T>(n));
   SolveArgs a;
   const double n3 = (double)n * n * n;
   a.n = n;

@@ -51,8 +51,10 @@ __global__ void __launch_bounds__(256) k_fft_cols(cx<T>* __restrict__ data, ColA
   const int B = g.bcols;
   const int t = threadIdx.x;
   const int b = t % B, u = t / B;
-  const int64_t outer = blockIdx.x / g.groups;
-  const int col = (blockIdx.x % g.groups) * B + b;
+  // adjacent column groups share cache lines: keep them on one XCD (one L2)
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t outer = lb / g.groups;
+  const int col = (int)(lb % g.groups) * B + b;
   const bool valid = col < g.ncols;
   cx<T>* base = data + (int64_t)blockIdx.y * g.comp_stride + outer * g.outer_stride + col;
 
@@ -89,6 +91,7 @@ struct RowArgs {
   int64_t nrows;
   int64_t in_comp, out_comp;  // component strides (elements of the in/out type)
   int n;                      // N (real row length)
+  int hs;                     // spectrum row stride (complex elements, >= N/2+1)
 };
 
 template <typename T, int L1, int L2>
@@ -106,9 +109,8 @@ __global__ void __launch_bounds__(256) k_fft_rows_r2c(const T* __restrict__ in, 
   const int64_t row = (int64_t)blockIdx.x * R + r;
   const bool valid = row < g.nrows;
   const int N = g.n;
-  const int H = M + 1;
   const T* src = in + (int64_t)blockIdx.y * g.in_comp + row * N;
-  cx<T>* dst = out + (int64_t)blockIdx.y * g.out_comp + row * H;
+  cx<T>* dst = out + (int64_t)blockIdx.y * g.out_comp + row * g.hs;
   cx<T>* my = lds + r * RS;
 
   if (u < L2) {
@@ -158,34 +160,31 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ 
   constexpr int M = L1 * L2;
   constexpr int TPC = L1 > L2 ? L1 : L2;
   constexpr int XS = L1 * (L2 + 1);
-  constexpr int RS = XS > (M + 1) ? XS : (M + 1);
   const int t = threadIdx.x;
   const int r = t / TPC, u = t % TPC;
   const int R = blockDim.x / TPC;
   const int64_t row = (int64_t)blockIdx.x * R + r;
   const bool valid = row < g.nrows;
   const int N = g.n;
-  const int H = M + 1;
-  const cx<T>* src = in + (int64_t)blockIdx.y * g.in_comp + row * H;
+  const cx<T>* src = in + (int64_t)blockIdx.y * g.in_comp + row * g.hs;
   T* dst = out + (int64_t)blockIdx.y * g.out_comp + row * N;
-  cx<T>* my = lds + r * RS;
+  cx<T>* my = lds + r * XS;
 
-  for (int k = u; k <= M; k += TPC) my[k] = valid ? ldc(src + k) : mk(T(0), T(0));
-  __syncthreads();
   cx<T> a[L1];
   if (u < L2) {
+    // X[k] and its mirror X[M-k] come straight from the row (the mirrored loads hit
+    // the lines the neighbouring lanes fetch)
 #pragma unroll
     for (int j1 = 0; j1 < L1; ++j1) {
       const int k = u + L2 * j1;
-      cx<T> xk = my[k];
-      cx<T> xm = conjg(my[M - k]);
-      cx<T> s = xk + xm;
-      cx<T> d = twiddle<true>(xk - xm, tw[k]);  // d * conj(W_N^k)
-      a[j1] = mk(s.x - d.y, s.y + d.x);         // s + i d
+      const cx<T> xk = valid ? ldc(src + k) : mk(T(0), T(0));
+      const cx<T> xm = valid ? conjg(ldc(src + (M - k))) : mk(T(0), T(0));
+      const cx<T> s = xk + xm;
+      const cx<T> d = twiddle<true>(xk - xm, tw[k]);  // d * conj(W_N^k)
+      a[j1] = mk(s.x - d.y, s.y + d.x);               // s + i d
     }
     RegDFT<T, L1, 1>::run(a);
   }
-  __syncthreads();
   if (u < L2) {
 #pragma unroll
     for (int k1 = 0; k1 < L1; ++k1) my[k1 * (L2 + 1) + u] = k1 == 0 ? a[k1] : tw_mul<true>(a[k1], tw, 2 * u * k1);
@@ -218,20 +217,23 @@ struct SolveArgs {
   double h, h2, om_a, inv_dtau;
 };
 
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+
 template <typename T>
-__device__ __forceinline__ cx<T> grad_symbol(int nd, int n, int grad, const cx<T>* tw) {
+__device__ __forceinline__ cx<T> grad_symbol(int nd, int n, int grad) {
   // nd in [-N/2, N/2], k = 2 pi nd / N
   if (grad == PM_GRAD_SPECTRAL) {
     if (nd == -n / 2 || nd == n / 2) return mk(T(0), T(0));
     return mk(T(0), T(2.0 * kPi / n) * T(nd));
   }
-  const int m = nd < 0 ? nd + n : nd;
-  const cx<T> w = tw[m];  // (cos k, -sin k)
-  if (grad == PM_GRAD_FD2) return mk(T(0), -w.y);
-  return mk(w.x - T(1), -w.y);  // PM_GRAD_FD1
+  T sk, ck;
+  sin_cos(T(2.0 * kPi / n) * T(nd), &sk, &ck);
+  if (grad == PM_GRAD_FD2) return mk(T(0), sk);
+  return mk(ck - T(1), sk);  // PM_GRAD_FD1
 }
 
-template <typename T, int L1, int L2>
+template <typename T, int L1, int L2, int KIND, int PASS>
 __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data, cx<T>* __restrict__ out1,
                                                       cx<T>* __restrict__ out2, cx<T>* __restrict__ phi, ColArgs g,
                                                       SolveArgs s, const cx<T>* __restrict__ tw) {
@@ -240,8 +242,9 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
   const int B = g.bcols;
   const int t = threadIdx.x;
   const int b = t % B, u = t / B;
-  const int64_t outer = blockIdx.x / g.groups;  // iy
-  const int col = (blockIdx.x % g.groups) * B + b;  // iz
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t outer = lb / g.groups;             // iy
+  const int col = (int)(lb % g.groups) * B + b;    // iz
   const bool valid = col < g.ncols;
   const int64_t off = outer * g.outer_stride + col;
   const int N = s.n;
@@ -274,50 +277,64 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
       const T kx = T(2.0 * kPi / N) * T(nx);
       const T k2s = kx * kx + kyz2;
       const bool zero = (nx == 0 && ny == 0 && nz == 0);
-      if (s.kind == PM_NEWTON) {
+      if (KIND == PM_NEWTON) {
         const T f = zero ? T(0) : T(s.newton) / k2s;
         X[k2] = scale(X[k2], f);
       } else {
-        const int64_t pidx = off + (int64_t)ix * g.stride;
-        const T h = T(s.h), h2 = T(s.h2);
-        const cx<T> pold = valid ? ldc(phi + pidx) : mk(T(0), T(0));
-        const T den = -k2s - T(3) * h2 - T(3) * h * T(s.inv_dtau) - T(4.5) * h2 * T(s.om_a);
-        const cx<T> num = scale(X[k2], T(1.5) * h2 * T(s.om_a)) - scale(pold, T(3) * h * T(s.inv_dtau));
-        cx<T> pnew = zero ? mk(T(0), T(0)) : scale(num, T(1) / den);
-        if (valid) stc(phi + pidx, pnew);
+        // the carried potential keeps the unpadded [N][N][N/2+1] layout of the C ABI
+        const int64_t pidx = ((int64_t)ix * N + outer) * (N / 2 + 1) + col;
+        const cx<T> pstored = valid ? ldc(phi + pidx) : mk(T(0), T(0));
+        cx<T> pnew;
+        if (PASS == 1) {  // first launch: update phi_old -> phi_new
+          const T h = T(s.h), h2 = T(s.h2);
+          const T den = -k2s - T(3) * h2 - T(3) * h * T(s.inv_dtau) - T(4.5) * h2 * T(s.om_a);
+          const cx<T> num = scale(X[k2], T(1.5) * h2 * T(s.om_a)) - scale(pstored, T(3) * h * T(s.inv_dtau));
+          pnew = zero ? mk(T(0), T(0)) : scale(num, T(1) / den);
+          if (valid) stc(phi + pidx, pnew);
+        } else {  // second launch: phi already holds phi_new
+          pnew = pstored;
+        }
         X[k2] = scale(pnew, -T(s.a_c2));
       }
     }
   }
-  // three inverse transforms
-#pragma unroll 1
-  for (int d = 0; d < 3; ++d) {
-    __syncthreads();  // previous component's LDS reads are complete
-    if (u < L1) {
-      cx<T> Y[L2];
-      const int ny = outer < N / 2 ? (int)outer : (int)outer - N;
+  // Inverse transform.  Along axis 0 the y and z gradient symbols are constants, so
+  //   F_x = IDFT(D_x G),  F_y = D_y IDFT(G),  F_z = D_z IDFT(G).
+  // PASS 1 (launched first) writes F_y, F_z to out1, out2; PASS 0 (launched second,
+  // after the spectrum in `data` is no longer needed) writes F_x in place.
+  __syncthreads();  // every thread has read its forward data from LDS
+  if (u < L1) {
+    if (PASS == 0) {
 #pragma unroll
       for (int k2 = 0; k2 < L2; ++k2) {
         const int ix = u + L1 * k2;
-        const int nx = ix < N / 2 ? ix : ix - N;
-        const int nd = d == 0 ? nx : (d == 1 ? ny : col);
-        Y[k2] = grad_symbol<T>(nd, N, s.grad, tw) * X[k2];
+        X[k2] = grad_symbol<T>(ix < N / 2 ? ix : ix - N, N, s.grad) * X[k2];
       }
-      RegDFT<T, L2, 1>::run(Y);
-#pragma unroll
-      for (int ja = 0; ja < L2; ++ja)
-        lds[col_lds_index<T, L1, L2>(u, ja, b, B)] = ja == 0 ? Y[ja] : tw_mul<true>(Y[ja], tw, u * ja * g.tw_step);
     }
-    __syncthreads();
-    if (u < L2) {
-      cx<T> c[L1];
+    RegDFT<T, L2, 1>::run(X);
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) c[k1] = lds[col_lds_index<T, L1, L2>(k1, u, b, B)];
-      RegDFT<T, L1, 1>::run(c);
-      cx<T>* o = d == 0 ? data : (d == 1 ? out1 : out2);
-      if (valid) {
+    for (int ja = 0; ja < L2; ++ja)
+      lds[col_lds_index<T, L1, L2>(u, ja, b, B)] = ja == 0 ? X[ja] : tw_mul<true>(X[ja], tw, u * ja * g.tw_step);
+  }
+  __syncthreads();
+  if (u < L2) {
+    cx<T> c[L1];
 #pragma unroll
-        for (int jb = 0; jb < L1; ++jb) stc(o + off + (int64_t)(u + L2 * jb) * g.stride, c[jb]);
+    for (int k1 = 0; k1 < L1; ++k1) c[k1] = lds[col_lds_index<T, L1, L2>(k1, u, b, B)];
+    RegDFT<T, L1, 1>::run(c);
+    if (valid) {
+      if (PASS == 0) {
+#pragma unroll
+        for (int jb = 0; jb < L1; ++jb) stc(data + off + (int64_t)(u + L2 * jb) * g.stride, c[jb]);
+      } else {
+        const int ny = outer < N / 2 ? (int)outer : (int)outer - N;
+        const cx<T> dy = grad_symbol<T>(ny, N, s.grad), dz = grad_symbol<T>(col, N, s.grad);
+#pragma unroll
+        for (int jb = 0; jb < L1; ++jb) {
+          const int64_t o = off + (int64_t)(u + L2 * jb) * g.stride;
+          stc(out1 + o, dy * c[jb]);
+          stc(out2 + o, dz * c[jb]);
+        }
       }
     }
   }

@@ -75,6 +75,147 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk(const T* __restrict__ for
   pos[2 * np + i] = wrap(z + drift * pz, n);
 }
 
+// Gather + kick + drift for a full Lagrangian lattice run (np = N^3).  A workgroup
+// owns a Lagrangian tile of GTX x GTY x GTZ particles, loads the three force meshes
+// over the bounding box of the tile's CIC cells into LDS with row-contiguous loads
+// (neighbouring tiles on the same XCD re-read overlapping rows from L2), and
+// interpolates from LDS.  If the box exceeds the LDS capacity, a GWF^3 box around
+// the mean base cell is staged and particles outside it read the meshes directly.
+// Weights and arithmetic are those of k_gather_kdk.
+constexpr int GTX = 4, GTY = 8, GTZ = 32;
+constexpr int GPP = GTX * GTY * GTZ / kBlock;  // particles per thread
+constexpr int GCAP = 4096;                     // staged cells (x3 components, float)
+constexpr int GWF = 16;                        // fallback box side (GWF^3 <= GCAP)
+
+__global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
+                                                             float* __restrict__ mom, int n, float kick,
+                                                             float drift) {
+  __shared__ float win[3 * GCAP];
+  __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
+  __shared__ float wsum[kBlock / 64][3];
+  const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  const int tpy = n / GTY, tpz = n / GTZ;
+  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
+  const int org[3] = {ti * GTX, tk * GTY, tl * GTZ};
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  float x[GPP], y[GPP], z[GPP];
+  int64_t jj[GPP];
+  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+  float sum[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int p = 0; p < GPP; ++p) {
+    const int loc = t + kBlock * p;
+    const int li = loc / (GTY * GTZ), lk = (loc / GTZ) % GTY, ll = loc % GTZ;
+    jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
+    x[p] = wrap(pos[jj[p]], n);
+    y[p] = wrap(pos[np + jj[p]], n);
+    z[p] = wrap(pos[2 * np + jj[p]], n);
+  }
+#pragma unroll
+  for (int p = 0; p < GPP; ++p) {
+    const int r[3] = {idiff((int)floorf(x[p]), org[0], n), idiff((int)floorf(y[p]), org[1], n),
+                      idiff((int)floorf(z[p]), org[2], n)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], r[d]);
+      hi[d] = max(hi[d], r[d]);
+      sum[d] += float(r[d]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], off, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], off, 64));
+      sum[d] += __shfl_xor(sum[d], off, 64);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      wlo[wave][d] = lo[d];
+      whi[wave][d] = hi[d];
+      wsum[wave][d] = sum[d];
+    }
+  }
+  __syncthreads();
+  int o[3], W[3];
+  int64_t vol = 1;
+  float mean[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int a = wlo[0][d], b = whi[0][d];
+    float s = wsum[0][d];
+    for (int w = 1; w < kBlock / 64; ++w) {
+      a = min(a, wlo[w][d]);
+      b = max(b, whi[w][d]);
+      s += wsum[w][d];
+    }
+    o[d] = a;
+    W[d] = b - a + 2;
+    vol *= W[d];
+    mean[d] = s * (1.f / float(GTX * GTY * GTZ));
+  }
+  if (vol > GCAP) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      o[d] = (int)rintf(mean[d]) - GWF / 2;
+      W[d] = GWF;
+    }
+  }
+  const int wtot = W[0] * W[1] * W[2];
+  const int sy = W[2], sx = W[1] * W[2];
+  // stage the force window (row-contiguous along z)
+  for (int c = t; c < wtot; c += kBlock) {
+    const int a = c / sx, b = (c / sy) % W[1], cz = c % sy;
+    const int64_t idx = ((int64_t)fold(org[0] + o[0] + a, n) * n + fold(org[1] + o[1] + b, n)) * n +
+                        fold(org[2] + o[2] + cz, n);
+    win[c] = force[idx];
+    win[GCAP + c] = force[np + idx];
+    win[2 * GCAP + c] = force[2 * np + idx];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < GPP; ++p) {
+    const Axis<float> ax = cic_axis(x[p], n), ay = cic_axis(y[p], n), az = cic_axis(z[p], n);
+    const int rx = idiff(ax.i0, org[0], n) - o[0], ry = idiff(ay.i0, org[1], n) - o[1],
+              rz = idiff(az.i0, org[2], n) - o[2];
+    const float w[4] = {ax.w0 * ay.w0, ax.w0 * ay.w1, ax.w1 * ay.w0, ax.w1 * ay.w1};
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    if (rx >= 0 && rx <= W[0] - 2 && ry >= 0 && ry <= W[1] - 2 && rz >= 0 && rz <= W[2] - 2) {
+      const int base = rx * sx + ry * sy + rz;
+      const int r[4] = {base, base + sy, base + sx, base + sx + sy};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float w0 = w[c] * az.w0, w1 = w[c] * az.w1;
+        fx += w0 * win[r[c]] + w1 * win[r[c] + 1];
+        fy += w0 * win[GCAP + r[c]] + w1 * win[GCAP + r[c] + 1];
+        fz += w0 * win[2 * GCAP + r[c]] + w1 * win[2 * GCAP + r[c] + 1];
+      }
+    } else {
+      const int64_t r[4] = {ax.i0 * n2 + (int64_t)ay.i0 * n, ax.i0 * n2 + (int64_t)ay.i1 * n,
+                            ax.i1 * n2 + (int64_t)ay.i0 * n, ax.i1 * n2 + (int64_t)ay.i1 * n};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t a0 = r[c] + az.i0, a1 = r[c] + az.i1;
+        const float w0 = w[c] * az.w0, w1 = w[c] * az.w1;
+        fx += w0 * force[a0] + w1 * force[a1];
+        fy += w0 * force[np + a0] + w1 * force[np + a1];
+        fz += w0 * force[2 * np + a0] + w1 * force[2 * np + a1];
+      }
+    }
+    const int64_t j = jj[p];
+    const float px = mom[j] + kick * fx, py = mom[np + j] + kick * fy, pz = mom[2 * np + j] + kick * fz;
+    mom[j] = px;
+    mom[np + j] = py;
+    mom[2 * np + j] = pz;
+    pos[j] = wrap(x[p] + drift * px, n);
+    pos[np + j] = wrap(y[p] + drift * py, n);
+    pos[2 * np + j] = wrap(z[p] + drift * pz, n);
+  }
+}
+
 // eq. xiGR (minimum image, coarse cells) interpolated in Lagrangian coordinates to
 // the fine lattice and added to the fine positions (eq. combined).
 template <typename T>
@@ -181,7 +322,12 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
                       double drift, hipStream_t s) {
   ProfScope ps(p, PK_GATHER_KDK, s);
   if (np <= 0) return PM_OK;
-  if (p->dtype == PM_F32)
+  const int n = p->n;
+  if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % GTZ == 0) {
+    const unsigned tiles = (unsigned)((n / GTX) * (n / GTY) * (n / GTZ));
+    hipLaunchKernelGGL(k_gather_kdk_tiled, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(force),
+                       static_cast<float*>(pos), static_cast<float*>(mom), n, (float)kick, (float)drift);
+  } else if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_gather_kdk<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(force),
                        static_cast<float*>(pos), static_cast<float*>(mom), np, p->n, (float)kick, (float)drift);
   else

@@ -228,6 +228,15 @@ __host__ __device__ constexpr Shape shape_for(int L) {
                      : Shape{0, 0, 0};
 }
 
+// Row stride (complex elements) of the library's internal [N][N][N/2+1] spectra: N/2+1
+// rounded up to a 128-byte multiple, so every row starts on a cache-line boundary and
+// a batch of adjacent columns maps onto whole lines.
+__host__ __device__ inline int padded_half(int n, int esize) {
+  const int per_line = 128 / (2 * esize);
+  const int h = n / 2 + 1;
+  return (h + per_line - 1) / per_line * per_line;
+}
+
 __host__ __device__ inline bool mesh_supported(int n) {
   return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 192 || n == 256 || n == 512 || n == 1024;
 }

@@ -39,6 +39,7 @@ struct pm_plan {
   void* ws;          // workspace: three [N][N][N/2+1] complex buffers
   size_t ws_bytes;
   size_t cbytes;     // bytes of one complex buffer (256-byte aligned)
+  int hp;            // row stride of the internal spectra (padded N/2+1)
   bool own_ws;
   void* tw;          // device twiddle table W_N^m, m < N, complex of the plan's type
   unsigned* guard;   // device counters: [0] non-finite positions, [1] wrapped positions

@@ -33,12 +33,13 @@ __device__ double eh98_transfer(double k, double om, double ob, double h, double
 // exp(i (k_x + k_y + k_z)/2) into cbuf(d).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx<T>* __restrict__ c1,
-                                                      cx<T>* __restrict__ c2, int n, IcSymbol sy) {
-  const int h = n / 2 + 1;
+                                                      cx<T>* __restrict__ c2, int n, int hp, IcSymbol sy) {
+  const int h = hp;  // padded row stride; columns iz > N/2 are padding
   const int64_t total = (int64_t)n * n * h;
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= total) return;
   const int iz = (int)(idx % h);
+  if (iz > n / 2) return;
   const int iy = (int)((idx / h) % n);
   const int ix = (int)(idx / ((int64_t)h * n));
   const int nx = signed_freq(ix, n), ny = signed_freq(iy, n), nz = iz;
@@ -100,7 +101,7 @@ __device__ __forceinline__ int pk_bin(int64_t n2, int n, int nb) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ dhat, int n, int nb,
+__global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ dhat, int n, int hp, int nb,
                                                       double* __restrict__ sums) {
   extern __shared__ double sh[];
   double* sp = sh;
@@ -112,7 +113,7 @@ __global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ 
     sc[b] = 0ull;
   }
   __syncthreads();
-  const int h = n / 2 + 1;
+  const int h = hp;  // padded row stride; columns iz > N/2 are padding
   const int64_t total = (int64_t)n * n * h;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   // Each thread walks modes; runs of the same bin are merged in registers.
@@ -121,6 +122,7 @@ __global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ 
   unsigned long long ac = 0;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
     const int iz = (int)(idx % h);
+    if (iz > n / 2) continue;
     const int iy = (int)((idx / h) % n);
     const int ix = (int)(idx / ((int64_t)h * n));
     const int nx = signed_freq(ix, n), ny = signed_freq(iy, n);
@@ -174,12 +176,13 @@ __global__ void k_pk_finalize(const double* __restrict__ sums, int nb, int n, do
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_shell_mask(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n,
-                                                       double lo4, double hi4) {
-  const int h = n / 2 + 1;
+                                                       int hp, double lo4, double hi4) {
+  const int h = hp;  // padded row stride; columns iz > N/2 are padding
   const int64_t total = (int64_t)n * n * h;
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= total) return;
   const int iz = (int)(idx % h);
+  if (iz > n / 2) return;
   const int iy = (int)((idx / h) % n);
   const int ix = (int)(idx / ((int64_t)h * n));
   const int nx = signed_freq(ix, n), ny = signed_freq(iy, n);
@@ -234,14 +237,14 @@ __global__ void k_zero_d(double* __restrict__ d, int64_t n) {
 int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, hipStream_t s) {
   ProfScope ps(p, PK_IC, s);
   const int n = p->n;
-  const int64_t total = (int64_t)n * n * (n / 2 + 1);
+  const int64_t total = (int64_t)n * n * p->hp;
   const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
   if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_ic_symbol<float>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<float>*>(cbuf(p, 0)),
-                       static_cast<cx<float>*>(cbuf(p, 1)), static_cast<cx<float>*>(cbuf(p, 2)), n, sym);
+                       static_cast<cx<float>*>(cbuf(p, 1)), static_cast<cx<float>*>(cbuf(p, 2)), n, p->hp, sym);
   else
     hipLaunchKernelGGL(k_ic_symbol<double>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<double>*>(cbuf(p, 0)),
-                       static_cast<cx<double>*>(cbuf(p, 1)), static_cast<cx<double>*>(cbuf(p, 2)), n, sym);
+                       static_cast<cx<double>*>(cbuf(p, 1)), static_cast<cx<double>*>(cbuf(p, 2)), n, p->hp, sym);
   return hip_check(hipGetLastError(), "ic symbol");
 }
 
@@ -254,17 +257,17 @@ int launch_zero_doubles(double* d, int64_t n, hipStream_t s) {
 int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s) {
   ProfScope ps(p, PK_PK, s);
   const int n = p->n;
-  const int64_t total = (int64_t)n * n * (n / 2 + 1);
+  const int64_t total = (int64_t)n * n * p->hp;
   int64_t g = (total + kBlock * 16 - 1) / (kBlock * 16);  // ~16 modes per thread
   if (g < 1) g = 1;
   if (g > 65535) g = 65535;
   const size_t shm = (size_t)n_bins * 3 * sizeof(double);
   if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_pk_reduce<float>, dim3((unsigned)g), dim3(kBlock), shm, s,
-                       static_cast<const cx<float>*>(dhat), n, n_bins, p->sums);
+                       static_cast<const cx<float>*>(dhat), n, p->hp, n_bins, p->sums);
   else
     hipLaunchKernelGGL(k_pk_reduce<double>, dim3((unsigned)g), dim3(kBlock), shm, s,
-                       static_cast<const cx<double>*>(dhat), n, n_bins, p->sums);
+                       static_cast<const cx<double>*>(dhat), n, p->hp, n_bins, p->sums);
   return hip_check(hipGetLastError(), "pk reduce");
 }
 
@@ -278,14 +281,14 @@ int launch_pk_finalize(const pm_plan* p, int n_bins, double* k_mean, double* pk,
 int launch_shell_mask(const pm_plan* p, const void* src, void* dst, double lo4, double hi4, hipStream_t s) {
   ProfScope ps(p, PK_BK, s);
   const int n = p->n;
-  const int64_t total = (int64_t)n * n * (n / 2 + 1);
+  const int64_t total = (int64_t)n * n * p->hp;
   const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
   if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_shell_mask<float>, dim3(g), dim3(kBlock), 0, s, static_cast<const cx<float>*>(src),
-                       static_cast<cx<float>*>(dst), n, lo4, hi4);
+                       static_cast<cx<float>*>(dst), n, p->hp, lo4, hi4);
   else
     hipLaunchKernelGGL(k_shell_mask<double>, dim3(g), dim3(kBlock), 0, s, static_cast<const cx<double>*>(src),
-                       static_cast<cx<double>*>(dst), n, lo4, hi4);
+                       static_cast<cx<double>*>(dst), n, p->hp, lo4, hi4);
   return hip_check(hipGetLastError(), "shell mask");
 }
 

@@ -190,10 +190,12 @@ def test_gather(dt):
 # -------------------------------------------------------------------- step --
 
 @pytest.mark.parametrize("dt", DTYPES)
-def test_step_matches_force_kick_drift(dt):
+@pytest.mark.parametrize("n,amp", [(32, 0.8), (128, 0.8), (128, 6.0)])
+def test_step_matches_force_kick_drift(dt, n, amp):
+    # FP32 N^3 lattice runs at N >= 64 stage forces through LDS windows; amp = 6 pushes
+    # tiles past the window capacity so the direct-read fallback runs too.
     dev = _dev()
-    n = 32
-    x = torch.from_numpy(si.lattice_jitter_particles(n, 9, 0.8))
+    x = torch.from_numpy(si.lattice_jitter_particles(n, 9, amp))
     v = torch.from_numpy(si.rng(10).standard_normal((3, n ** 3))) * 0.05
     plan = pm.Plan(n, 200.0, dt)
     pos, mom = x.to(dt).to(dev).contiguous(), v.to(dt).to(dev).contiguous()
