@@ -67,6 +67,35 @@ def cpu_baseline(n_sample: int, seed: int = 5, min_seconds: float = 10.0, max_cy
                       f"particles and a {n_sample}^3 mesh ({dt:.1f} s), scaled per particle-update"}
 
 
+def adjoint_ratio(pm, plan, noise, icp, n_cycles: int, ckpt: int, n_bins: int):
+    """Times the differentiable forward model (ICs, n_cycles leapfrog cycles of the
+    schedule's start, deposit, P(k)) and its reverse pass (P(k) adjoint, checkpoint
+    recomputation, adjoint cycles, IC adjoint) on the same plan.  Returns
+    (forward s, backward s, per-kernel profile of the reverse pass)."""
+    import torch
+    from paper_2404_02783_amd import diff
+    a_s = pm.sim.log_steps(0.02, 1.0, 50)
+    dpk = torch.linspace(-1.0, 1.0, n_bins, dtype=torch.float64, device=plan.device)
+    # warm the adjoint kernels once on a single cycle
+    _, tape = diff.forward(plan, noise, icp, diff.Schedule(a_s[:2]), n_bins, 1)
+    diff.backward(tape, dpk)
+    del tape
+    torch.cuda.synchronize()
+    sched = diff.Schedule(a_s[:n_cycles + 1])
+    t0 = time.perf_counter()
+    _, tape = diff.forward(plan, noise, icp, sched, n_bins, ckpt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pm.pm_profile_enable(plan, True)
+    g = diff.backward(tape, dpk)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prof = pm.pm_profile_read(plan)
+    pm.pm_profile_enable(plan, False)
+    del tape, g
+    return t1 - t0, t2 - t1, prof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +106,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-cycles", type=int, default=4,
+                    help="leapfrog cycles of the differentiable run timed for the adjoint/forward ratio (0: skip)")
+    ap.add_argument("--adjoint-ckpt", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -109,7 +141,7 @@ def main():
     icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965,
                       a_init=0.02, a_norm=1.0, cosmo=pm.FIDUCIAL)
     pm.pm_ic_zeldovich(plan, noise, icp, disp, pos, mom)
-    del noise, disp
+    del disp
     torch.cuda.synchronize()
     print(f"[bench] initial conditions ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
@@ -177,6 +209,20 @@ def main():
         "kernels": kernels,
         "adjoint_forward_ratio": None,
     }
+    if args.adjoint_cycles > 0:
+        del run, pos, mom
+        torch.cuda.synchronize()
+        print(f"[bench] adjoint: {args.adjoint_cycles} cycles, checkpoint every {args.adjoint_ckpt}",
+              file=sys.stderr, flush=True)
+        t_fwd, t_bwd, aprof = adjoint_ratio(pm, plan, noise, icp, args.adjoint_cycles, args.adjoint_ckpt, 256)
+        out["adjoint_forward_ratio"] = round(t_bwd / t_fwd, 3)
+        out["adjoint"] = {
+            "workload": f"d loss/d noise through Zel'dovich ICs, {args.adjoint_cycles} leapfrog cycles (a=0.02 start of "
+                        f"the same schedule), CIC deposit and P(k) in 256 bins at {n}^3; checkpoints every "
+                        f"{args.adjoint_ckpt} cycles",
+            "forward_s": round(t_fwd, 4), "backward_s": round(t_bwd, 4),
+            "kernels": {k: {"avg_ms": round(ms / c, 4), "launches": c} for k, (ms, c) in aprof.items()}}
+    del noise
     if not args.no_cpu_baseline:
         print(f"[bench] CPU oracle baseline at {args.cpu_sample}^3 ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -173,6 +173,28 @@ int pm_gather(pm_plan* plan, const void* force, const void* pos, int64_t np, voi
 int pm_step(pm_plan* plan, void* pos, void* mom, int64_t np, const pm_step_params* st, void* force_scratch,
             void* phi_state, void* stream);
 
+/* Reverse-mode (adjoint) of one Newtonian pm_step; not in the paper: the exact
+ * vector-Jacobian product of the discrete cycle x -> (x', p') defined by pm_step
+ * (Sec. 2's particle-mesh force; deposit, Green's function and gradient, gather,
+ * kick, drift).  With F(x) the gathered force and (lam_pos, lam_mom) the cotangents
+ * of the cycle's outputs on entry:
+ *   lam_mom <- lam_mom + Dr lam_pos,   v = K lam_mom,
+ *   lam_pos <- lam_pos + (dF/dx)^T v
+ * where (dF/dx)^T v has a force-field part (gradient of the CIC interpolation
+ * weights against the force meshes) and a density part (v deposited with the CIC
+ * weights, the transposed Green's/gradient operator applied in Fourier space, and
+ * the result differentiated through the CIC weights of the deposit, scaled by
+ * 1/nbar).  CIC weight derivatives are right derivatives at cell edges.
+ * pos: [3][np] the positions the forward cycle started from (read only).
+ * st: the forward cycle's parameters; st->solve.kind must be PM_NEWTON (PM_ERR_ARG
+ * otherwise).  force: [3][N][N][N] the force meshes the forward cycle used (as left
+ * in pm_step's force_scratch), or NULL to recompute them from pos.  mesh_scratch:
+ * device real scratch of 3 N^3 elements, or 6 N^3 when force is NULL.
+ * lam_pos, lam_mom: [3][np] cotangents, updated in place.  Summation order of the
+ * deposit of v is that of device atomics. */
+int pm_step_adjoint(pm_plan* plan, const void* pos, int64_t np, const pm_step_params* st, const void* force,
+                    void* mesh_scratch, void* lam_pos, void* lam_mom, void* stream);
+
 /* eq. xiGR and eq. combined: xi = minimum-image (x_gr - x_newton) on the coarse
  * lattice (n_coarse^3 particles, coarse cells), interpolated with CIC weights in
  * Lagrangian coordinates to the fine lattice (n_fine^3 particles; fine particle j
@@ -189,6 +211,15 @@ int displacement_combine(const void* x_gr, const void* x_newton, int n_coarse, c
  * n_modes (int64, modes of the full cube).  delta: [N][N][N] real. */
 int pk_estimate(pm_plan* plan, const void* delta, int n_bins, double* k_mean, double* pk, int64_t* n_modes,
                 void* stream);
+
+/* Adjoint of positions -> CIC counting density -> pk_estimate (eq. powerspectrum);
+ * not in the paper.  dpk: device double [n_bins], the cotangent dL/dP_b.  Writes
+ * lam_pos[d][p] = dL/dx_{p,d} (overwritten): the spectrum of the particles' density
+ * is weighted per bin by 2 V dP_b / (N^6 count_b), transformed back, and
+ * differentiated through the CIC weights (right derivatives at cell edges) with the
+ * factor 1/nbar.  pos: [3][np]; n_bins and binning as pk_estimate. */
+int pk_adjoint(pm_plan* plan, const void* pos, int64_t np, int n_bins, const double* dpk, void* lam_pos,
+               void* stream);
 
 /* FFT bispectrum estimator (eq. bispectre).  Shell s holds modes with
  * (2c_s - w)^2 <= 4|n|^2 < (2c_s + w)^2 (float64 decision, c_s and w in units of k_f).
@@ -213,6 +244,15 @@ int bk_estimate(pm_plan* plan, const void* delta, int n_shells, const double* sh
  * mom = a^2 E f Psi.  disp_scratch: [3][N][N][N] real, overwritten with Psi. */
 int pm_ic_zeldovich(pm_plan* plan, const void* noise, const pm_ic_params* ic, void* disp_scratch, void* pos,
                     void* mom, void* stream);
+
+/* Adjoint of pm_ic_zeldovich with respect to the noise; not in the paper.  The
+ * forward map noise -> (pos, mom) is affine: pos = wrap(q + Psi), mom = m Psi with
+ * Psi_d = IDFT(S_d DFT(noise)).  Given the cotangents lam_pos, lam_mom [3][N^3]
+ * (read only), writes lam_noise [N][N][N] = sum_d IDFT(conj(S_d) DFT(lam_pos_d +
+ * m lam_mom_d)) scaled as the transpose of the forward map.  disp_scratch:
+ * [3][N][N][N] real, overwritten. */
+int pm_ic_zeldovich_adjoint(pm_plan* plan, const pm_ic_params* ic, const void* lam_pos, const void* lam_mom,
+                            void* disp_scratch, void* lam_noise, void* stream);
 
 /* Poisson-gauge partner set of pm_ic_zeldovich's output (linear reading of eqs.
  * physical_density, b1, bgr): xi_hat = i k g(a_init) delta_L_hat / k^4 on the same

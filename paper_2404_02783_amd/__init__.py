@@ -17,6 +17,7 @@ import torch
 __all__ = [
     "PMError", "lib", "SolveParams", "StepParams", "Cosmology", "ICParams", "Plan",
     "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "pk_estimate", "bk_estimate",
+    "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint",
     "pm_ic_zeldovich", "pm_ic_gauge", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
     "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH",
@@ -86,7 +87,12 @@ def _declare(l):
         "pk_estimate": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "bk_estimate": (_c_int, [_c_void_p, _c_void_p, _c_int, P(_c_double), _c_double, P(ctypes.c_int32), _c_int,
                                  _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_size_t, _c_void_p]),
+        "pm_step_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int64, P(StepParams), _c_void_p, _c_void_p, _c_void_p,
+                                     _c_void_p, _c_void_p]),
+        "pk_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int64, _c_int, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_zeldovich": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+        "pm_ic_zeldovich_adjoint": (_c_int, [_c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                             _c_void_p]),
         "pm_ic_gauge": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                                  _c_void_p, _c_void_p]),
         "pm_cosmo_hubble_e": (_c_double, [P(Cosmology), _c_double]),
@@ -227,6 +233,41 @@ def pm_step(plan: Plan, pos, mom, st: StepParams, force_scratch, phi_state=None)
                          _stream()))
 
 
+def _need(t, numel: int, name: str):
+    if t.numel() < numel:
+        raise PMError(PM_ERR_ARG, f"{name} holds {t.numel()} elements, {numel} needed")
+
+
+def pm_step_adjoint(plan: Plan, pos, st: StepParams, lam_pos, lam_mom, force=None, mesh_scratch=None):
+    """Cotangents of one pm_step pulled back in place: (lam_pos, lam_mom) of the
+    cycle's outputs -> those of its inputs.  ``pos`` are the positions the forward
+    cycle started from; ``force`` the force meshes it used (or None to recompute)."""
+    n3 = plan.n ** 3
+    need = 3 * n3 if force is not None else 6 * n3
+    if mesh_scratch is None:
+        mesh_scratch = torch.empty(need, dtype=plan.dtype, device=plan.device)
+    _need(mesh_scratch, need, "mesh_scratch")
+    if force is not None:
+        _need(force, 3 * n3, "force")
+    np_ = pos.shape[-1]
+    for t, nm in ((lam_pos, "lam_pos"), (lam_mom, "lam_mom")):
+        _need(t, 3 * np_, nm)
+    _check(lib().pm_step_adjoint(plan.handle, _ptr(pos, plan.dtype, "pos"), np_, ctypes.byref(st),
+                                 _ptr(force, plan.dtype, "force"), _ptr(mesh_scratch, plan.dtype, "mesh_scratch"),
+                                 _ptr(lam_pos, plan.dtype, "lam_pos"), _ptr(lam_mom, plan.dtype, "lam_mom"),
+                                 _stream()))
+
+
+def pk_adjoint(plan: Plan, pos, n_bins: int, dpk, lam_pos=None):
+    """dL/dpos of a loss with cotangent ``dpk`` = dL/dP (device float64 [n_bins])
+    through the CIC density and the P(k) estimator."""
+    lam_pos = torch.empty_like(pos) if lam_pos is None else lam_pos
+    _need(dpk, n_bins, "dpk")
+    _check(lib().pk_adjoint(plan.handle, _ptr(pos, plan.dtype, "pos"), pos.shape[-1], int(n_bins),
+                            _ptr(dpk, torch.float64, "dpk"), _ptr(lam_pos, plan.dtype, "lam_pos"), _stream()))
+    return lam_pos
+
+
 def displacement_combine(x_gr, x_newton, n_coarse: int, x_fine, n_fine: int, x_out=None):
     x_out = torch.empty_like(x_fine) if x_out is None else x_out
     dt = PM_F32 if x_fine.dtype == torch.float32 else PM_F64
@@ -266,6 +307,22 @@ def pm_ic_zeldovich(plan: Plan, noise, ic: ICParams, disp_scratch, pos, mom):
     _check(lib().pm_ic_zeldovich(plan.handle, _ptr(noise, plan.dtype, "noise"), ctypes.byref(ic),
                                  _ptr(disp_scratch, plan.dtype, "disp_scratch"), _ptr(pos, plan.dtype, "pos"),
                                  _ptr(mom, plan.dtype, "mom"), _stream()))
+
+
+def pm_ic_zeldovich_adjoint(plan: Plan, ic: ICParams, lam_pos, lam_mom, disp_scratch=None, lam_noise=None):
+    """dL/dnoise from the cotangents of the Zel'dovich (pos, mom)."""
+    n3 = plan.n ** 3
+    disp_scratch = plan.mesh(3) if disp_scratch is None else disp_scratch
+    lam_noise = plan.mesh() if lam_noise is None else lam_noise
+    _need(disp_scratch, 3 * n3, "disp_scratch")
+    _need(lam_noise, n3, "lam_noise")
+    _need(lam_pos, 3 * n3, "lam_pos")
+    _need(lam_mom, 3 * n3, "lam_mom")
+    _check(lib().pm_ic_zeldovich_adjoint(plan.handle, ctypes.byref(ic), _ptr(lam_pos, plan.dtype, "lam_pos"),
+                                         _ptr(lam_mom, plan.dtype, "lam_mom"),
+                                         _ptr(disp_scratch, plan.dtype, "disp_scratch"),
+                                         _ptr(lam_noise, plan.dtype, "lam_noise"), _stream()))
+    return lam_noise
 
 
 def pm_ic_gauge(plan: Plan, noise, ic: ICParams, disp_scratch, pos_n, mom_n, pos_gr, mom_gr):

@@ -23,7 +23,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
-SOURCES = ["fft.hip", "deposit.hip", "particles.hip", "spectra.hip", "api.cpp", "cosmo.cpp"]
+SOURCES = ["fft.hip", "deposit.hip", "particles.hip", "spectra.hip", "adjoint.hip", "api.cpp", "cosmo.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -1,0 +1,198 @@
+// Kernels of the reverse-mode (adjoint) PM step and of the initial-condition and
+// power-spectrum adjoints.  The forward map of one cycle is
+//   F(x) = gather_x( A deposit(x) ),  p' = p + K F(x),  x' = wrap(x + Dr p'),
+// with A the linear mesh operator density -> force meshes (Green's function and
+// gradient in Fourier space).  Given cotangents (lx', lp') of (x', p'):
+//   lp = lp' + Dr lx',   v = K lp,
+//   lx = lx' + sum_d v_d grad(F_d)(x)                       (force-field term)
+//           + (1/nbar) grad_x( W * h )(x),  h = A^T deposit_v (density term)
+// where deposit_v spreads each particle's v with the CIC weights (the adjoint of
+// the gather) and grad_x(W * h) differentiates the CIC weights (the adjoint of the
+// deposit).  CIC weight derivatives are the right derivatives at cell edges,
+// consistent with the floor() in the assignment.  One thread per particle.
+#include <math.h>
+
+#include "fft_kernels.h"
+#include "pm_particles.h"
+#include "pm_plan.h"
+
+namespace pm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Adjoint of gather + kick + drift: updates (lam_pos, lam_mom) by the force-field
+// term and deposits v = kick (lam_mom + drift lam_pos) into g ([3][N^3], pre-zeroed).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_gather_kdk(const T* __restrict__ force, const T* __restrict__ pos,
+                                                           int64_t np, int n, T kick, T drift, T* __restrict__ lam_pos,
+                                                           T* __restrict__ lam_mom, T* __restrict__ g) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = blk * kBlock + threadIdx.x;
+  if (i >= np) return;
+  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
+  const Axis<T> ax = cic_axis(wrap(pos[i], n), n), ay = cic_axis(wrap(pos[np + i], n), n),
+                az = cic_axis(wrap(pos[2 * np + i], n), n);
+  T lx[3], lp[3], v[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lx[d] = lam_pos[d * np + i];
+    lp[d] = lam_mom[d * np + i] + drift * lx[d];
+    v[d] = kick * lp[d];
+  }
+  T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+    const int64_t idx = (bx ? ax.i1 : ax.i0) * n2 + (int64_t)(by ? ay.i1 : ay.i0) * n + (bz ? az.i1 : az.i0);
+    const T wx = bx ? ax.w1 : ax.w0, wy = by ? ay.w1 : ay.w0, wz = bz ? az.w1 : az.w0;
+    const T s = v[0] * force[idx] + v[1] * force[n3 + idx] + v[2] * force[2 * n3 + idx];
+    // d/dx of the weight: -1 at the base node, +1 at the next one
+    gx += (bx ? s : -s) * wy * wz;
+    gy += (by ? s : -s) * wx * wz;
+    gz += (bz ? s : -s) * wx * wy;
+    const T w = wx * wy * wz;
+    atomic_add(g + idx, w * v[0]);
+    atomic_add(g + n3 + idx, w * v[1]);
+    atomic_add(g + 2 * n3 + idx, w * v[2]);
+  }
+  lam_mom[i] = lp[0];
+  lam_mom[np + i] = lp[1];
+  lam_mom[2 * np + i] = lp[2];
+  lam_pos[i] = lx[0] + gx;
+  lam_pos[np + i] = lx[1] + gy;
+  lam_pos[2 * np + i] = lx[2] + gz;
+}
+
+// lam_pos (+)= scale * grad_x sum_c W(x - c) h(c): the adjoint of the CIC deposit
+// applied to a cotangent mesh h.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_grad_gather(const T* __restrict__ h, const T* __restrict__ pos, int64_t np,
+                                                        int n, T scale, T* __restrict__ lam_pos, int accumulate) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = blk * kBlock + threadIdx.x;
+  if (i >= np) return;
+  const int64_t n2 = (int64_t)n * n;
+  const Axis<T> ax = cic_axis(wrap(pos[i], n), n), ay = cic_axis(wrap(pos[np + i], n), n),
+                az = cic_axis(wrap(pos[2 * np + i], n), n);
+  T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+    const int64_t idx = (bx ? ax.i1 : ax.i0) * n2 + (int64_t)(by ? ay.i1 : ay.i0) * n + (bz ? az.i1 : az.i0);
+    const T wx = bx ? ax.w1 : ax.w0, wy = by ? ay.w1 : ay.w0, wz = bz ? az.w1 : az.w0;
+    const T s = h[idx];
+    gx += (bx ? s : -s) * wy * wz;
+    gy += (by ? s : -s) * wx * wz;
+    gz += (bz ? s : -s) * wx * wy;
+  }
+  const T gs[3] = {scale * gx, scale * gy, scale * gz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) lam_pos[d * np + i] = accumulate ? lam_pos[d * np + i] + gs[d] : gs[d];
+}
+
+// Transposed Newtonian force operator on three spectra (natural [N][N][hp] layout):
+// c0 <- coef / k^2 * sum_d conj(D_d(n)) c_d, zero at k = 0.  The forward operator
+// multiplies by D_d coef / k^2 (coef = (3/2) Omega_m / N^3, which also carries the
+// 1/N^3 of the inverse transform); its transpose multiplies by the conjugate.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_div_newton(cx<T>* __restrict__ c0, const cx<T>* __restrict__ c1,
+                                                       const cx<T>* __restrict__ c2, int n, int hp, int grad, T coef) {
+  const int64_t total = (int64_t)n * n * hp;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= total) return;
+  const int iz = (int)(idx % hp);
+  if (iz > n / 2) return;
+  const int iy = (int)((idx / hp) % n);
+  const int ix = (int)(idx / ((int64_t)hp * n));
+  const int nx = ix < n / 2 ? ix : ix - n, ny = iy < n / 2 ? iy : iy - n, nz = iz;
+  const T kx = T(2.0 * kPi / n) * T(nx), ky = T(2.0 * kPi / n) * T(ny), kz = T(2.0 * kPi / n) * T(nz);
+  const T k2s = kx * kx + ky * ky + kz * kz;
+  cx<T> out = mk(T(0), T(0));
+  if (nx != 0 || ny != 0 || nz != 0) {
+    const cx<T> dx = conjg(grad_symbol<T>(nx, n, grad)), dy = conjg(grad_symbol<T>(ny, n, grad)),
+                dz = conjg(grad_symbol<T>(nz, n, grad));
+    const cx<T> s = dx * ldc(c0 + idx) + dy * ldc(c1 + idx) + dz * ldc(c2 + idx);
+    out = scale(s, coef / k2s);
+  }
+  stc(c0 + idx, out);
+}
+
+// Cotangent of the Zel'dovich displacement from those of (pos, mom):
+// lam_psi = lam_pos + mom_factor lam_mom.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ic_lattice_adj(const T* __restrict__ lam_pos, const T* __restrict__ lam_mom,
+                                                           T* __restrict__ lam_psi, int64_t count, T mom_factor) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= count) return;
+  lam_psi[j] = lam_pos[j] + mom_factor * lam_mom[j];
+}
+
+}  // namespace
+
+int launch_adj_gather_kdk(const pm_plan* p, const void* force, const void* pos, int64_t np, double kick, double drift,
+                          void* lam_pos, void* lam_mom, void* g, hipStream_t s) {
+  ProfScope ps(p, PK_ADJ_GATHER, s);
+  if (np <= 0) return PM_OK;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_adj_gather_kdk<float>, dim3(nblocks(np)), dim3(kBlock), 0, s,
+                       static_cast<const float*>(force), static_cast<const float*>(pos), np, p->n, (float)kick,
+                       (float)drift, static_cast<float*>(lam_pos), static_cast<float*>(lam_mom),
+                       static_cast<float*>(g));
+  else
+    hipLaunchKernelGGL(k_adj_gather_kdk<double>, dim3(nblocks(np)), dim3(kBlock), 0, s,
+                       static_cast<const double*>(force), static_cast<const double*>(pos), np, p->n, kick, drift,
+                       static_cast<double*>(lam_pos), static_cast<double*>(lam_mom), static_cast<double*>(g));
+  return hip_check(hipGetLastError(), "adjoint gather-kick-drift");
+}
+
+int launch_grad_gather(const pm_plan* p, const void* h, const void* pos, int64_t np, double scale, void* lam_pos,
+                       bool accumulate, hipStream_t s) {
+  ProfScope ps(p, PK_GRAD_GATHER, s);
+  if (np <= 0) return PM_OK;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_grad_gather<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(h),
+                       static_cast<const float*>(pos), np, p->n, (float)scale, static_cast<float*>(lam_pos),
+                       accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_grad_gather<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(h),
+                       static_cast<const double*>(pos), np, p->n, scale, static_cast<double*>(lam_pos),
+                       accumulate ? 1 : 0);
+  return hip_check(hipGetLastError(), "gradient gather");
+}
+
+int launch_div_newton(const pm_plan* p, int grad, double coef, hipStream_t s) {
+  ProfScope ps(p, PK_ADJ_SYMBOL, s);
+  const int n = p->n;
+  const int64_t total = (int64_t)n * n * p->hp;
+  const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_div_newton<float>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<float>*>(cbuf(p, 0)),
+                       static_cast<const cx<float>*>(cbuf(p, 1)), static_cast<const cx<float>*>(cbuf(p, 2)), n, p->hp,
+                       grad, (float)coef);
+  else
+    hipLaunchKernelGGL(k_div_newton<double>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<double>*>(cbuf(p, 0)),
+                       static_cast<const cx<double>*>(cbuf(p, 1)), static_cast<const cx<double>*>(cbuf(p, 2)), n,
+                       p->hp, grad, coef);
+  return hip_check(hipGetLastError(), "adjoint force symbol");
+}
+
+int launch_ic_lattice_adj(const pm_plan* p, const void* lam_pos, const void* lam_mom, void* lam_psi,
+                          double mom_factor, hipStream_t s) {
+  ProfScope ps(p, PK_IC, s);
+  const int64_t count = 3 * (int64_t)p->n * p->n * p->n;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_ic_lattice_adj<float>, dim3(nblocks(count)), dim3(kBlock), 0, s,
+                       static_cast<const float*>(lam_pos), static_cast<const float*>(lam_mom),
+                       static_cast<float*>(lam_psi), count, (float)mom_factor);
+  else
+    hipLaunchKernelGGL(k_ic_lattice_adj<double>, dim3(nblocks(count)), dim3(kBlock), 0, s,
+                       static_cast<const double*>(lam_pos), static_cast<const double*>(lam_mom),
+                       static_cast<double*>(lam_psi), count, mom_factor);
+  return hip_check(hipGetLastError(), "ic lattice adjoint");
+}
+
+}  // namespace pm

@@ -46,7 +46,8 @@ static int check_plan(const pm_plan* p) {
 static const char* kProfNames[PK_COUNT] = {
     "fill",          "deposit",        "fft_r2c_rows",   "fft_cols_fwd_axis1", "fft_cols_fwd_axis0",
     "fft_solve_axis0", "fft_cols_inv_axis0", "fft_cols_inv_axis1", "fft_c2r_rows", "gather",
-    "gather_kick_drift", "combine",    "ic",             "pk",                 "bk"};
+    "gather_kick_drift", "combine",    "ic",             "pk",                 "bk",
+    "adjoint_gather_kick_drift", "grad_gather", "adjoint_symbol"};
 
 struct ProfRec {
   int kind;
@@ -328,6 +329,57 @@ int pm_step(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* 
   PM_TRY(fft_pass_rows_r2c(p, delta, cbuf(p, 0), s));
   PM_TRY(solve_from_c0(p, &st->solve, phi_state, force_scratch, s));
   return launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, s);
+}
+
+int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, const void* force,
+                    void* mesh_scratch, void* lam_pos, void* lam_mom, void* stream) {
+  PM_TRY(check_plan(p));
+  if (np < 0) return set_error(PM_ERR_ARG, "pm_step_adjoint: negative particle count");
+  if (!st || !mesh_scratch || (np > 0 && (!pos || !lam_pos || !lam_mom)))
+    return set_error(PM_ERR_ARG, "pm_step_adjoint: null pointer");
+  if (st->solve.kind != PM_NEWTON)
+    return set_error(PM_ERR_ARG, "pm_step_adjoint: only the Newtonian step has an adjoint");
+  PM_TRY(check_solve_params(&st->solve, nullptr, "pm_step_adjoint"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n3 = (int64_t)p->n * p->n * p->n;
+  const size_t mesh_bytes = (size_t)n3 * p->esize;
+  char* g = static_cast<char*>(mesh_scratch);
+  if (!force) {
+    void* fs = g + 3 * mesh_bytes;
+    void* delta = cbuf(p, 1);
+    PM_TRY(launch_fill(p, delta, n3, -1.0, s));
+    PM_TRY(launch_deposit(p, pos, np, delta, s));
+    PM_TRY(fft_pass_rows_r2c(p, delta, cbuf(p, 0), s));
+    PM_TRY(solve_from_c0(p, &st->solve, nullptr, fs, s));
+    force = fs;
+  }
+  if (np == 0) return PM_OK;
+  PM_TRY(launch_fill(p, g, 3 * n3, 0.0, s));
+  PM_TRY(launch_adj_gather_kdk(p, force, pos, np, st->kick, st->drift, lam_pos, lam_mom, g, s));
+  for (int d = 0; d < 3; ++d) PM_TRY(fft3_r2c(p, g + d * mesh_bytes, cbuf(p, d), s));
+  PM_TRY(launch_div_newton(p, st->solve.grad, 1.5 * st->solve.omega_m / (double)n3, s));
+  PM_TRY(fft3_c2r(p, 1, cbuf(p, 0), 0, g, s));
+  return launch_grad_gather(p, g, pos, np, (double)n3 / (double)np, lam_pos, true, s);
+}
+
+int pk_adjoint(pm_plan* p, const void* pos, int64_t np, int n_bins, const double* dpk, void* lam_pos, void* stream) {
+  PM_TRY(check_plan(p));
+  if (np < 0) return set_error(PM_ERR_ARG, "pk_adjoint: negative particle count");
+  if (!dpk || (np > 0 && (!pos || !lam_pos))) return set_error(PM_ERR_ARG, "pk_adjoint: null pointer");
+  if (n_bins <= 0 || 3 * (size_t)n_bins > p->sums_cap || n_bins > 4 * p->n)
+    return set_error(PM_ERR_ARG, "pk_adjoint: n_bins %d out of range", n_bins);
+  if (np == 0) return PM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n3 = (int64_t)p->n * p->n * p->n;
+  void* delta = cbuf(p, 1);
+  PM_TRY(launch_fill(p, delta, n3, -1.0, s));
+  PM_TRY(launch_deposit(p, pos, np, delta, s));
+  PM_TRY(fft3_r2c(p, delta, cbuf(p, 0), s));
+  PM_TRY(launch_zero_doubles(p->sums, 3 * (int64_t)n_bins, s));
+  PM_TRY(launch_pk_reduce(p, cbuf(p, 0), n_bins, s));
+  PM_TRY(launch_pk_adjoint_weight(p, cbuf(p, 0), n_bins, dpk, s));
+  PM_TRY(fft3_c2r(p, 1, cbuf(p, 0), 0, delta, s));
+  return launch_grad_gather(p, delta, pos, np, (double)n3 / (double)np, lam_pos, false, s);
 }
 
 int displacement_combine(const void* x_gr, const void* x_newton, int n_coarse, const void* x_fine, int n_fine,

@@ -183,11 +183,8 @@ double pm_power_law_amplitude(int n, double box, double rms, double index) {
 
 // ----------------------------------------------------- initial conditions ----
 
-static int ic_common(pm_plan* p, const void* noise, const pm_ic_params* ic, void* disp, int kpow, double coef,
-                     hipStream_t s) {
+static pm::IcSymbol ic_symbol_of(const pm_plan* p, const pm_ic_params* ic, int kpow, double coef) {
   using namespace pm;
-  int rc = fft3_r2c(p, noise, cbuf(p, 0), s);
-  if (rc) return rc;
   IcSymbol sy;
   sy.pk_kind = ic->pk_kind;
   sy.amp = ic->amp;
@@ -202,7 +199,15 @@ static int ic_common(pm_plan* p, const void* noise, const pm_ic_params* ic, void
   sy.growth = pm_cosmo_growth(&ic->cosmo, ic->a_init) / pm_cosmo_growth(&ic->cosmo, ic->a_norm);
   sy.coef = coef / ((double)p->n * p->n * p->n);
   sy.kpow = kpow;
-  rc = launch_ic_symbol(p, sy, s);
+  return sy;
+}
+
+static int ic_common(pm_plan* p, const void* noise, const pm_ic_params* ic, void* disp, int kpow, double coef,
+                     hipStream_t s) {
+  using namespace pm;
+  int rc = fft3_r2c(p, noise, cbuf(p, 0), s);
+  if (rc) return rc;
+  rc = launch_ic_symbol(p, ic_symbol_of(p, ic, kpow, coef), false, s);
   if (rc) return rc;
   const int64_t cstride = (int64_t)(p->cbytes / (2 * p->esize));
   return fft3_c2r(p, 3, cbuf(p, 0), cstride, disp, s);
@@ -229,6 +234,30 @@ int pm_ic_zeldovich(pm_plan* p, const void* noise, const pm_ic_params* ic, void*
   const double a = ic->a_init;
   const double fac = a * a * pm_cosmo_hubble_e(&ic->cosmo, a) * pm_cosmo_growth_rate(&ic->cosmo, a);
   return launch_ic_lattice(p, disp, pos, mom, fac, s);
+}
+
+int pm_ic_zeldovich_adjoint(pm_plan* p, const pm_ic_params* ic, const void* lam_pos, const void* lam_mom,
+                            void* disp_scratch, void* lam_noise, void* stream) {
+  using namespace pm;
+  if (!p) return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: null plan");
+  if (!ic || !lam_pos || !lam_mom || !disp_scratch || !lam_noise)
+    return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: null pointer");
+  if (ic->pk_kind != PM_PK_POWERLAW && ic->pk_kind != PM_PK_EH98)
+    return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: bad pk_kind");
+  if (!(ic->a_init > 0.0) || !(ic->a_norm > 0.0))
+    return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: bad scale factors");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double a = ic->a_init;
+  const double fac = a * a * pm_cosmo_hubble_e(&ic->cosmo, a) * pm_cosmo_growth_rate(&ic->cosmo, a);
+  int rc = launch_ic_lattice_adj(p, lam_pos, lam_mom, disp_scratch, fac, s);
+  if (rc) return rc;
+  const size_t mesh_bytes = (size_t)p->n * p->n * p->n * p->esize;
+  for (int d = 0; d < 3 && rc == PM_OK; ++d)
+    rc = fft3_r2c(p, static_cast<const char*>(disp_scratch) + d * mesh_bytes, cbuf(p, d), s);
+  if (rc) return rc;
+  rc = launch_ic_symbol(p, ic_symbol_of(p, ic, 1, 1.0), true, s);
+  if (rc) return rc;
+  return fft3_c2r(p, 1, cbuf(p, 0), 0, lam_noise, s);
 }
 
 int pm_ic_gauge(pm_plan* p, const void* noise, const pm_ic_params* ic, void* disp, const void* pos_n,

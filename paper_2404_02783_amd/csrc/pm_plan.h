@@ -25,6 +25,9 @@ enum ProfKind {
   PK_IC,
   PK_PK,
   PK_BK,
+  PK_ADJ_GATHER,
+  PK_GRAD_GATHER,
+  PK_ADJ_SYMBOL,
   PK_COUNT
 };
 struct ProfState;
@@ -108,8 +111,9 @@ struct IcSymbol {
   double coef;               // multiplies the displacement symbol (includes 1/N^3)
   int kpow;                  // 1: i k / k^2 (Zel'dovich), 2: i k / k^4 (gauge shift)
 };
-// cbuf(0) holds DFT(noise); writes the three displacement spectra to cbuf 0, 1, 2.
-int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, hipStream_t s);
+// Forward: cbuf(0) holds DFT(noise); writes the three displacement spectra S_d w_hat
+// to cbuf 0, 1, 2.  Adjoint: cbuf(0) <- sum_d conj(S_d) cbuf(d).
+int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, bool adjoint, hipStream_t s);
 int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s);
 int launch_pk_finalize(const pm_plan* p, int n_bins, double* k_mean, double* pk, int64_t* n_modes, hipStream_t s);
 // dst = src * 1_S (src may be NULL: indicator); shell membership (2c-w)^2 <= 4|n|^2 < (2c+w)^2.
@@ -119,5 +123,19 @@ int launch_triple_sum(const pm_plan* p, const void* a, const void* b, const void
 int launch_bk_finalize(const pm_plan* p, int n_tri, const double* sums, double* bk, double* ntri_out,
                        const double* ntri_known, hipStream_t s);
 int launch_zero_doubles(double* d, int64_t n, hipStream_t s);
+// dhat <- beta_b dhat with beta from dP (device [n_bins]) and the counts of the last reduction.
+int launch_pk_adjoint_weight(const pm_plan* p, void* dhat, int n_bins, const double* dpk, hipStream_t s);
+
+// ------------------------------------------------------------ adjoint.hip --
+// Adjoint of gather + kick + drift (see adjoint.hip); g: [3][N^3] pre-zeroed.
+int launch_adj_gather_kdk(const pm_plan* p, const void* force, const void* pos, int64_t np, double kick, double drift,
+                          void* lam_pos, void* lam_mom, void* g, hipStream_t s);
+// lam_pos (+)= scale * grad_x (W * h)(x_p)
+int launch_grad_gather(const pm_plan* p, const void* h, const void* pos, int64_t np, double scale, void* lam_pos,
+                       bool accumulate, hipStream_t s);
+// cbuf(0) <- coef/k^2 sum_d conj(D_d) cbuf(d)
+int launch_div_newton(const pm_plan* p, int grad, double coef, hipStream_t s);
+int launch_ic_lattice_adj(const pm_plan* p, const void* lam_pos, const void* lam_mom, void* lam_psi,
+                          double mom_factor, hipStream_t s);
 
 }  // namespace pm

@@ -30,8 +30,10 @@ __device__ double eh98_transfer(double k, double om, double ob, double h, double
 // Zel'dovich / gauge-shift symbol on the natural [N][N][N/2+1] layout.  Input
 // cbuf(0) = DFT(noise).  delta_L = w_hat sqrt(P(k)/dx^3) growth (zero at k = 0 and on
 // Nyquist planes); output component d = coef * i k_d delta_L / k^(2 kpow) *
-// exp(i (k_x + k_y + k_z)/2) into cbuf(d).
-template <typename T>
+// exp(i (k_x + k_y + k_z)/2) into cbuf(d), i.e. S_d(n) w_hat(n).
+// ADJ: the transposed map, cbuf(0) <- sum_d conj(S_d(n)) cbuf(d) (inputs are the
+// spectra of the displacement cotangents).
+template <typename T, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx<T>* __restrict__ c1,
                                                       cx<T>* __restrict__ c2, int n, int hp, IcSymbol sy) {
   const int h = hp;  // padded row stride; columns iz > N/2 are padding
@@ -60,18 +62,33 @@ __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx
     const double inv = sy.kpow == 1 ? 1.0 / k2 : 1.0 / (k2 * k2);
     double sn, cs;
     sincos(0.5 * (kx + ky + kz), &sn, &cs);
-    const cx<T> w = ldc(c0 + idx);
-    // base = w * amp * inv * coef * e^{i phase}; component d = i k_d base
     const double f = amp * inv * sy.coef;
-    const double br = f * ((double)w.x * cs - (double)w.y * sn);
-    const double bi = f * ((double)w.x * sn + (double)w.y * cs);
     const double kd[3] = {kx, ky, kz};
+    if (ADJ) {
+      // sum_d conj(i k_d f e^{i phase}) c_d = f e^{-i phase} (-i) sum_d k_d c_d
+      const cx<T> cd[3] = {ldc(c0 + idx), ldc(c1 + idx), ldc(c2 + idx)};
+      double qr = 0.0, qi = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) out[d] = mk(T(-kd[d] * bi), T(kd[d] * br));
+      for (int d = 0; d < 3; ++d) {
+        qr += kd[d] * (double)cd[d].x;
+        qi += kd[d] * (double)cd[d].y;
+      }
+      const double rr = qi, ri = -qr;  // -i q
+      out[0] = mk(T(f * (rr * cs + ri * sn)), T(f * (ri * cs - rr * sn)));
+    } else {
+      const cx<T> w = ldc(c0 + idx);
+      // base = w * amp * inv * coef * e^{i phase}; component d = i k_d base
+      const double br = f * ((double)w.x * cs - (double)w.y * sn);
+      const double bi = f * ((double)w.x * sn + (double)w.y * cs);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) out[d] = mk(T(-kd[d] * bi), T(kd[d] * br));
+    }
   }
   stc(c0 + idx, out[0]);
-  stc(c1 + idx, out[1]);
-  stc(c2 + idx, out[2]);
+  if (!ADJ) {
+    stc(c1 + idx, out[1]);
+    stc(c2 + idx, out[2]);
+  }
 }
 
 // Power-spectrum shell reduction.  Bin b of mode n: N^2 (2b+1)^2 <= 16 nb^2 |n|^2 <
@@ -174,6 +191,34 @@ __global__ void k_pk_finalize(const double* __restrict__ sums, int nb, int n, do
   n_modes[b] = (int64_t)c;
 }
 
+// Cotangent of the binned power spectrum pulled back to the spectrum:
+// dhat(n) <- beta_b dhat(n), beta_b = 2 V dP_b / (N^6 count_b) for the bin b of n and
+// 0 outside every bin (P_b is a quadratic form in dhat; the factor 2 and the full-cube
+// count come from summing |dhat|^2 over n and -n).  Counts are those left in `sums` by
+// the reduction of the same spectrum.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pk_adjoint_weight(cx<T>* __restrict__ dhat, int n, int hp, int nb,
+                                                              const double* __restrict__ sums,
+                                                              const double* __restrict__ dpk, double coef) {
+  const int64_t total = (int64_t)n * n * hp;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= total) return;
+  const int iz = (int)(idx % hp);
+  if (iz > n / 2) return;
+  const int iy = (int)((idx / hp) % n);
+  const int ix = (int)(idx / ((int64_t)hp * n));
+  const int nx = signed_freq(ix, n), ny = signed_freq(iy, n);
+  const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)iz * iz;
+  const int b = n2 > 0 ? pk_bin(n2, n, nb) : -1;
+  double beta = 0.0;
+  if (b >= 0) {
+    const unsigned long long c = reinterpret_cast<const unsigned long long*>(sums + 2 * nb)[b];
+    beta = c ? coef * dpk[b] / (double)c : 0.0;
+  }
+  const cx<T> v = ldc(dhat + idx);
+  stc(dhat + idx, mk(T(beta * (double)v.x), T(beta * (double)v.y)));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_shell_mask(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n,
                                                        int hp, double lo4, double hi4) {
@@ -234,17 +279,23 @@ __global__ void k_zero_d(double* __restrict__ d, int64_t n) {
 
 }  // namespace
 
-int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, hipStream_t s) {
+int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, bool adjoint, hipStream_t s) {
   ProfScope ps(p, PK_IC, s);
   const int n = p->n;
   const int64_t total = (int64_t)n * n * p->hp;
   const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
-  if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_ic_symbol<float>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<float>*>(cbuf(p, 0)),
-                       static_cast<cx<float>*>(cbuf(p, 1)), static_cast<cx<float>*>(cbuf(p, 2)), n, p->hp, sym);
+  cx<float>* f[3] = {static_cast<cx<float>*>(cbuf(p, 0)), static_cast<cx<float>*>(cbuf(p, 1)),
+                     static_cast<cx<float>*>(cbuf(p, 2))};
+  cx<double>* d[3] = {static_cast<cx<double>*>(cbuf(p, 0)), static_cast<cx<double>*>(cbuf(p, 1)),
+                      static_cast<cx<double>*>(cbuf(p, 2))};
+  if (p->dtype == PM_F32 && adjoint)
+    hipLaunchKernelGGL((k_ic_symbol<float, true>), dim3(g), dim3(kBlock), 0, s, f[0], f[1], f[2], n, p->hp, sym);
+  else if (p->dtype == PM_F32)
+    hipLaunchKernelGGL((k_ic_symbol<float, false>), dim3(g), dim3(kBlock), 0, s, f[0], f[1], f[2], n, p->hp, sym);
+  else if (adjoint)
+    hipLaunchKernelGGL((k_ic_symbol<double, true>), dim3(g), dim3(kBlock), 0, s, d[0], d[1], d[2], n, p->hp, sym);
   else
-    hipLaunchKernelGGL(k_ic_symbol<double>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<double>*>(cbuf(p, 0)),
-                       static_cast<cx<double>*>(cbuf(p, 1)), static_cast<cx<double>*>(cbuf(p, 2)), n, p->hp, sym);
+    hipLaunchKernelGGL((k_ic_symbol<double, false>), dim3(g), dim3(kBlock), 0, s, d[0], d[1], d[2], n, p->hp, sym);
   return hip_check(hipGetLastError(), "ic symbol");
 }
 
@@ -276,6 +327,22 @@ int launch_pk_finalize(const pm_plan* p, int n_bins, double* k_mean, double* pk,
   hipLaunchKernelGGL(k_pk_finalize, dim3((unsigned)((n_bins + 63) / 64)), dim3(64), 0, s, p->sums, n_bins, p->n, p->box,
                      k_mean, pk, n_modes);
   return hip_check(hipGetLastError(), "pk finalize");
+}
+
+int launch_pk_adjoint_weight(const pm_plan* p, void* dhat, int n_bins, const double* dpk, hipStream_t s) {
+  ProfScope ps(p, PK_PK, s);
+  const int n = p->n;
+  const int64_t total = (int64_t)n * n * p->hp;
+  const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
+  const double n3 = (double)n * n * n;
+  const double coef = 2.0 * p->box * p->box * p->box / (n3 * n3);
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_pk_adjoint_weight<float>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<float>*>(dhat), n,
+                       p->hp, n_bins, p->sums, dpk, coef);
+  else
+    hipLaunchKernelGGL(k_pk_adjoint_weight<double>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<double>*>(dhat), n,
+                       p->hp, n_bins, p->sums, dpk, coef);
+  return hip_check(hipGetLastError(), "pk adjoint weight");
 }
 
 int launch_shell_mask(const pm_plan* p, const void* src, void* dst, double lo4, double hi4, hipStream_t s) {
