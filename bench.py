@@ -46,6 +46,39 @@ def algorithmic_bytes(n: int, np_: int, es: int = 4):
     }
 
 
+def kernel_source_digest() -> str:
+    """sha256 over the HIP/C++ sources of the library (any kernel change alters it)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2404_02783_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, n: int):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter's reading for
+    a plain device copy), or None when there is none for this kernel and mesh or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_{n}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return int(float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(n_sample: int, seed: int = 5, min_seconds: float = 10.0, max_cycles: int = 4):
     """Force-kick-drift cycles of the FP64 oracle on n_sample^3 particles, repeated
     until about ``min_seconds`` of CPU work (at most ``max_cycles``)."""
@@ -203,7 +236,8 @@ def main():
                                f"{args.warmup + args.steps - 1} timed)",
                    "n_mesh": n, "n_particles": n ** 3, "box_mpch": box, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, n), "alg_bytes_per_launch": alg[dom]},
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBps": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "kernels": kernels,
