@@ -126,6 +126,27 @@ size_t pm_plan_workspace_bytes(int n_mesh, int dtype);
 int pm_plan_create(pm_plan** out, int n_mesh, double box_mpch, int dtype, void* workspace, size_t ws_bytes);
 int pm_plan_destroy(pm_plan* plan);
 
+/* Batched plans: n_batch independent periodic boxes of the same mesh and side (an
+ * ensemble of realisations, as used for the paper's ensemble error bars; batching is
+ * not in the paper).  Every box is advanced by the same launches (the box index is a
+ * grid dimension), so a group of small boxes fills the GPU like one large box.
+ * Entry points that accept a batched plan and their layouts:
+ *   pm_deposit       pos [n_batch][3][np], delta [n_batch][N][N][N]
+ *   pm_solve         delta [n_batch][N^3] -> force [3][n_batch][N^3];
+ *                    phi_state [n_batch][N][N][N/2+1]
+ *   pm_step          pos, mom [n_batch][3][N^3] (np must be N^3 when n_batch > 1),
+ *                    force_scratch [3][n_batch][N^3]
+ *   pk_estimate      delta [n_batch][N^3] -> k_mean, pk, n_modes [n_batch][n_bins]
+ *   pm_ic_zeldovich  noise [n_batch][N^3] -> disp_scratch [3][n_batch][N^3],
+ *                    pos, mom [n_batch][3][N^3]
+ * Every other entry point requires n_batch == 1 (PM_ERR_ARG otherwise).  All boxes of
+ * a call share its scalar parameters (kick, drift, solve, IC parameters).
+ * n_batch in [1, 4096]; workspace bytes from pm_plan_workspace_bytes_batch (0 for an
+ * unsupported N, dtype or n_batch).  pm_plan_create is the n_batch = 1 case. */
+size_t pm_plan_workspace_bytes_batch(int n_mesh, int dtype, int n_batch);
+int pm_plan_create_batch(pm_plan** out, int n_mesh, double box_mpch, int dtype, int n_batch, void* workspace,
+                         size_t ws_bytes);
+
 /* Reads and clears the device guard counters (synchronises `stream`).
  * Returns PM_ERR_STATE if, since the last check, the deposit met a non-finite
  * position (skipped) or a position outside [0, N) (wrapped back in). */

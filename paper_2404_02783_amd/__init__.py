@@ -73,6 +73,8 @@ def _declare(l):
         "pm_last_error": (ctypes.c_char_p, []),
         "pm_plan_workspace_bytes": (_c_size_t, [_c_int, _c_int]),
         "pm_plan_create": (_c_int, [P(_c_void_p), _c_int, _c_double, _c_int, _c_void_p, _c_size_t]),
+        "pm_plan_workspace_bytes_batch": (_c_size_t, [_c_int, _c_int, _c_int]),
+        "pm_plan_create_batch": (_c_int, [P(_c_void_p), _c_int, _c_double, _c_int, _c_int, _c_void_p, _c_size_t]),
         "pm_plan_destroy": (_c_int, [_c_void_p]),
         "pm_check": (_c_int, [_c_void_p, _c_void_p]),
         "pm_profile_enable": (_c_int, [_c_void_p, _c_int]),
@@ -146,22 +148,29 @@ def _ptr(t, dtype=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
-class Plan:
-    """An N^3 mesh plan; the spectrum workspace is a torch device buffer."""
+def _need(t, numel: int, name: str):
+    if t.numel() < numel:
+        raise PMError(PM_ERR_ARG, f"{name} holds {t.numel()} elements, {numel} needed")
 
-    def __init__(self, n: int, box: float, dtype=torch.float32, device=None):
+
+class Plan:
+    """An N^3 mesh plan of ``batch`` equal boxes (default one); the spectrum
+    workspace is a torch device buffer."""
+
+    def __init__(self, n: int, box: float, dtype=torch.float32, device=None, batch: int = 1):
         self.n = int(n)
         self.box = float(box)
         self.dtype = dtype
+        self.batch = int(batch)
         self.cdtype = PM_F32 if dtype == torch.float32 else PM_F64
         self.device = torch.device("cuda") if device is None else torch.device(device)
-        nbytes = lib().pm_plan_workspace_bytes(self.n, self.cdtype)
+        nbytes = lib().pm_plan_workspace_bytes_batch(self.n, self.cdtype, self.batch)
         if nbytes == 0:
-            raise PMError(PM_ERR_SIZE, f"unsupported mesh size {n}")
+            raise PMError(PM_ERR_SIZE, f"unsupported mesh size {n} or batch {batch}")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = _c_void_p()
-        _check(lib().pm_plan_create(ctypes.byref(h), self.n, self.box, self.cdtype,
-                                    ctypes.c_void_p(self.workspace.data_ptr()), nbytes))
+        _check(lib().pm_plan_create_batch(ctypes.byref(h), self.n, self.box, self.cdtype, self.batch,
+                                          ctypes.c_void_p(self.workspace.data_ptr()), nbytes))
         self.handle = h
 
     def close(self):
@@ -177,12 +186,23 @@ class Plan:
 
     # allocation helpers (torch device memory)
     def mesh(self, ncomp: int = 0):
-        shape = (self.n,) * 3 if ncomp == 0 else (ncomp,) + (self.n,) * 3
+        """[N,N,N] ([batch,N,N,N] for a batch), or [ncomp, ...] of those."""
+        shape = (self.n,) * 3 if self.batch == 1 else (self.batch,) + (self.n,) * 3
+        if ncomp:
+            shape = (ncomp,) + shape
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
+
+    def particles(self):
+        """Empty [3, N^3] ([batch, 3, N^3] for a batch) particle array."""
+        shape = (3, self.n ** 3) if self.batch == 1 else (self.batch, 3, self.n ** 3)
         return torch.empty(shape, dtype=self.dtype, device=self.device)
 
     def spectrum(self):
         cd = torch.complex64 if self.dtype == torch.float32 else torch.complex128
-        return torch.zeros((self.n, self.n, self.n // 2 + 1), dtype=cd, device=self.device)
+        shape = (self.n, self.n, self.n // 2 + 1)
+        if self.batch > 1:
+            shape = (self.batch,) + shape
+        return torch.zeros(shape, dtype=cd, device=self.device)
 
 
 def pm_check(plan: Plan):
@@ -208,6 +228,8 @@ def pm_profile_read(plan: Plan):
 
 def pm_deposit(plan: Plan, pos, delta=None):
     delta = plan.mesh() if delta is None else delta
+    _need(delta, plan.batch * plan.n ** 3, "delta")
+    _need(pos, plan.batch * 3 * pos.shape[-1], "pos")
     _check(lib().pm_deposit(plan.handle, _ptr(pos, plan.dtype, "pos"), pos.shape[-1], _ptr(delta, plan.dtype, "delta"),
                             _stream()))
     return delta
@@ -215,6 +237,10 @@ def pm_deposit(plan: Plan, pos, delta=None):
 
 def pm_solve(plan: Plan, delta, sp: SolveParams, phi_state=None, force=None):
     force = plan.mesh(3) if force is None else force
+    _need(delta, plan.batch * plan.n ** 3, "delta")
+    _need(force, 3 * plan.batch * plan.n ** 3, "force")
+    if phi_state is not None:
+        _need(phi_state, plan.batch * plan.n ** 2 * (plan.n // 2 + 1), "phi_state")
     _check(lib().pm_solve(plan.handle, _ptr(delta, plan.dtype, "delta"), ctypes.byref(sp), _ptr(phi_state),
                           _ptr(force, plan.dtype, "force"), _stream()))
     return force
@@ -228,14 +254,15 @@ def pm_gather(plan: Plan, force, pos, acc=None):
 
 
 def pm_step(plan: Plan, pos, mom, st: StepParams, force_scratch, phi_state=None):
+    np_ = pos.shape[-1]
+    _need(pos, plan.batch * 3 * np_, "pos")
+    _need(mom, plan.batch * 3 * np_, "mom")
+    _need(force_scratch, 3 * plan.batch * plan.n ** 3, "force_scratch")
+    if phi_state is not None:
+        _need(phi_state, plan.batch * plan.n ** 2 * (plan.n // 2 + 1), "phi_state")
     _check(lib().pm_step(plan.handle, _ptr(pos, plan.dtype, "pos"), _ptr(mom, plan.dtype, "mom"), pos.shape[-1],
                          ctypes.byref(st), _ptr(force_scratch, plan.dtype, "force_scratch"), _ptr(phi_state),
                          _stream()))
-
-
-def _need(t, numel: int, name: str):
-    if t.numel() < numel:
-        raise PMError(PM_ERR_ARG, f"{name} holds {t.numel()} elements, {numel} needed")
 
 
 def pm_step_adjoint(plan: Plan, pos, st: StepParams, lam_pos, lam_mom, force=None, mesh_scratch=None):
@@ -278,9 +305,12 @@ def displacement_combine(x_gr, x_newton, n_coarse: int, x_fine, n_fine: int, x_o
 
 
 def pk_estimate(plan: Plan, delta, n_bins: int):
-    k = torch.empty(n_bins, dtype=torch.float64, device=plan.device)
-    p = torch.empty(n_bins, dtype=torch.float64, device=plan.device)
-    c = torch.empty(n_bins, dtype=torch.int64, device=plan.device)
+    """(k_mean, P, n_modes), each [n_bins] ([batch, n_bins] for a batch)."""
+    shape = (n_bins,) if plan.batch == 1 else (plan.batch, n_bins)
+    _need(delta, plan.batch * plan.n ** 3, "delta")
+    k = torch.empty(shape, dtype=torch.float64, device=plan.device)
+    p = torch.empty(shape, dtype=torch.float64, device=plan.device)
+    c = torch.empty(shape, dtype=torch.int64, device=plan.device)
     _check(lib().pk_estimate(plan.handle, _ptr(delta, plan.dtype, "delta"), int(n_bins), _ptr(k), _ptr(p), _ptr(c),
                              _stream()))
     return k, p, c
@@ -304,6 +334,11 @@ def bk_estimate(plan: Plan, delta, centres, width: float, triangles, shell_ws=No
 
 
 def pm_ic_zeldovich(plan: Plan, noise, ic: ICParams, disp_scratch, pos, mom):
+    n3 = plan.batch * plan.n ** 3
+    _need(noise, n3, "noise")
+    _need(disp_scratch, 3 * n3, "disp_scratch")
+    _need(pos, 3 * n3, "pos")
+    _need(mom, 3 * n3, "mom")
     _check(lib().pm_ic_zeldovich(plan.handle, _ptr(noise, plan.dtype, "noise"), ctypes.byref(ic),
                                  _ptr(disp_scratch, plan.dtype, "disp_scratch"), _ptr(pos, plan.dtype, "pos"),
                                  _ptr(mom, plan.dtype, "mom"), _stream()))

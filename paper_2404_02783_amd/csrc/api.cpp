@@ -42,6 +42,13 @@ static int check_plan(const pm_plan* p) {
   return PM_OK;
 }
 
+// Entry points that work on one box only.
+static int check_single(const pm_plan* p, const char* who) {
+  if (!p) return set_error(PM_ERR_ARG, "%s: null plan", who);
+  if (p->nb != 1) return set_error(PM_ERR_ARG, "%s: needs a single-box plan (this plan holds %d boxes)", who, p->nb);
+  return PM_OK;
+}
+
 // ------------------------------------------------------------ profiling ----
 static const char* kProfNames[PK_COUNT] = {
     "fill",          "deposit",        "fft_r2c_rows",   "fft_cols_fwd_axis1", "fft_cols_fwd_axis0",
@@ -117,24 +124,34 @@ extern "C" {
 
 const char* pm_last_error(void) { return g_err; }
 
-size_t pm_plan_workspace_bytes(int n_mesh, int dtype) {
-  if (!mesh_supported(n_mesh) || (dtype != PM_F32 && dtype != PM_F64)) return 0;
-  return 3 * complex_bytes(n_mesh, dtype);
+size_t pm_plan_workspace_bytes_batch(int n_mesh, int dtype, int n_batch) {
+  if (!mesh_supported(n_mesh) || (dtype != PM_F32 && dtype != PM_F64) || n_batch < 1 || n_batch > kMaxBatch) return 0;
+  return 3 * (size_t)n_batch * complex_bytes(n_mesh, dtype);
 }
 
+size_t pm_plan_workspace_bytes(int n_mesh, int dtype) { return pm_plan_workspace_bytes_batch(n_mesh, dtype, 1); }
+
 int pm_plan_create(pm_plan** out, int n_mesh, double box_mpch, int dtype, void* workspace, size_t ws_bytes) {
+  return pm_plan_create_batch(out, n_mesh, box_mpch, dtype, 1, workspace, ws_bytes);
+}
+
+int pm_plan_create_batch(pm_plan** out, int n_mesh, double box_mpch, int dtype, int n_batch, void* workspace,
+                         size_t ws_bytes) {
   g_err[0] = 0;
   if (!out) return set_error(PM_ERR_ARG, "pm_plan_create: null output pointer");
   *out = nullptr;
   if (!mesh_supported(n_mesh)) return set_error(PM_ERR_SIZE, "pm_plan_create: unsupported mesh size %d", n_mesh);
   if (dtype != PM_F32 && dtype != PM_F64) return set_error(PM_ERR_ARG, "pm_plan_create: bad dtype %d", dtype);
   if (!(box_mpch > 0.0)) return set_error(PM_ERR_ARG, "pm_plan_create: box must be positive");
-  const size_t need = pm_plan_workspace_bytes(n_mesh, dtype);
+  if (n_batch < 1 || n_batch > kMaxBatch)
+    return set_error(PM_ERR_ARG, "pm_plan_create: batch of %d boxes outside [1, %d]", n_batch, kMaxBatch);
+  const size_t need = pm_plan_workspace_bytes_batch(n_mesh, dtype, n_batch);
   if (workspace && ws_bytes < need)
     return set_error(PM_ERR_NOMEM, "pm_plan_create: workspace of %zu bytes < %zu needed", ws_bytes, need);
   pm_plan* p = new (std::nothrow) pm_plan();
   if (!p) return set_error(PM_ERR_NOMEM, "pm_plan_create: host allocation failed");
   p->n = n_mesh;
+  p->nb = n_batch;
   p->dtype = dtype;
   p->box = box_mpch;
   p->esize = dtype == PM_F32 ? 4 : 8;
@@ -183,7 +200,7 @@ int pm_plan_create(pm_plan** out, int n_mesh, double box_mpch, int dtype, void* 
       rc = hip_check(hipMemset(p->guard, 0, 4 * sizeof(unsigned)), "pm_plan_create: guard init");
   }
   if (rc == PM_OK) {
-    p->sums_cap = 3 * (size_t)std::max(n_mesh, 512) + 2 * 4096;
+    p->sums_cap = (size_t)n_batch * 3 * (size_t)std::max(n_mesh, 512) + 2 * 4096;
     if (hipMalloc(&p->sums, p->sums_cap * sizeof(double)) != hipSuccess)
       rc = set_error(PM_ERR_NOMEM, "pm_plan_create: reduction scratch allocation");
   }
@@ -276,16 +293,17 @@ int pm_deposit(pm_plan* p, const void* pos, int64_t np, void* delta, void* strea
   if (!delta || (np > 0 && !pos)) return set_error(PM_ERR_ARG, "pm_deposit: null pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n3 = (int64_t)p->n * p->n * p->n;
-  PM_TRY(launch_fill(p, delta, n3, -1.0, s));
+  PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
   return launch_deposit(p, pos, np, delta, s);
 }
 
+// cbuf(0) holds the nb spectra after the row pass; writes force [3][nb][N^3].
 static int solve_from_c0(pm_plan* p, const pm_solve_params* sp, void* phi, void* force, hipStream_t s) {
-  PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, -1, 1, 0, s));
+  const int64_t cs = cstride(p);
+  PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, -1, p->nb, cs, s));
   PM_TRY(fft_pass_solve(p, sp, phi, s));
-  const int64_t cstride = (int64_t)(p->cbytes / (2 * p->esize));
-  PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, 1, 3, cstride, s));
-  return fft_pass_rows_c2r(p, 3, cbuf(p, 0), cstride, force, s);
+  PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, 1, 3 * p->nb, cs, s));
+  return fft_pass_rows_c2r(p, 3 * p->nb, cbuf(p, 0), cs, force, s);
 }
 
 static int check_solve_params(const pm_solve_params* sp, const void* phi, const char* who) {
@@ -304,12 +322,12 @@ int pm_solve(pm_plan* p, const void* delta, const pm_solve_params* sp, void* phi
   if (!delta || !force) return set_error(PM_ERR_ARG, "pm_solve: null pointer");
   PM_TRY(check_solve_params(sp, phi_state, "pm_solve"));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  PM_TRY(fft_pass_rows_r2c(p, delta, cbuf(p, 0), s));
+  PM_TRY(fft_pass_rows_r2c(p, p->nb, delta, cbuf(p, 0), s));
   return solve_from_c0(p, sp, phi_state, force, s);
 }
 
 int pm_gather(pm_plan* p, const void* force, const void* pos, int64_t np, void* acc, void* stream) {
-  PM_TRY(check_plan(p));
+  PM_TRY(check_single(p, "pm_gather"));
   if (np < 0) return set_error(PM_ERR_ARG, "pm_gather: negative particle count");
   if (np > 0 && (!force || !pos || !acc)) return set_error(PM_ERR_ARG, "pm_gather: null pointer");
   return launch_gather(p, force, pos, np, acc, static_cast<hipStream_t>(stream));
@@ -323,17 +341,18 @@ int pm_step(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* 
   PM_TRY(check_solve_params(&st->solve, phi_state, "pm_step"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n3 = (int64_t)p->n * p->n * p->n;
-  void* delta = cbuf(p, 1);  // the density mesh lives in the second spectrum buffer
-  PM_TRY(launch_fill(p, delta, n3, -1.0, s));
+  if (p->nb > 1 && np != n3) return set_error(PM_ERR_ARG, "pm_step: a batch needs N^3 particles per box");
+  void* delta = cbuf(p, 1);  // the density meshes live in the second spectrum region
+  PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
   PM_TRY(launch_deposit(p, pos, np, delta, s));
-  PM_TRY(fft_pass_rows_r2c(p, delta, cbuf(p, 0), s));
+  PM_TRY(fft_pass_rows_r2c(p, p->nb, delta, cbuf(p, 0), s));
   PM_TRY(solve_from_c0(p, &st->solve, phi_state, force_scratch, s));
   return launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, s);
 }
 
 int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, const void* force,
                     void* mesh_scratch, void* lam_pos, void* lam_mom, void* stream) {
-  PM_TRY(check_plan(p));
+  PM_TRY(check_single(p, "pm_step_adjoint"));
   if (np < 0) return set_error(PM_ERR_ARG, "pm_step_adjoint: negative particle count");
   if (!st || !mesh_scratch || (np > 0 && (!pos || !lam_pos || !lam_mom)))
     return set_error(PM_ERR_ARG, "pm_step_adjoint: null pointer");
@@ -349,7 +368,7 @@ int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_param
     void* delta = cbuf(p, 1);
     PM_TRY(launch_fill(p, delta, n3, -1.0, s));
     PM_TRY(launch_deposit(p, pos, np, delta, s));
-    PM_TRY(fft_pass_rows_r2c(p, delta, cbuf(p, 0), s));
+    PM_TRY(fft_pass_rows_r2c(p, 1, delta, cbuf(p, 0), s));
     PM_TRY(solve_from_c0(p, &st->solve, nullptr, fs, s));
     force = fs;
   }
@@ -363,7 +382,7 @@ int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_param
 }
 
 int pk_adjoint(pm_plan* p, const void* pos, int64_t np, int n_bins, const double* dpk, void* lam_pos, void* stream) {
-  PM_TRY(check_plan(p));
+  PM_TRY(check_single(p, "pk_adjoint"));
   if (np < 0) return set_error(PM_ERR_ARG, "pk_adjoint: negative particle count");
   if (!dpk || (np > 0 && (!pos || !lam_pos))) return set_error(PM_ERR_ARG, "pk_adjoint: null pointer");
   if (n_bins <= 0 || 3 * (size_t)n_bins > p->sums_cap || n_bins > 4 * p->n)
@@ -398,11 +417,11 @@ int pk_estimate(pm_plan* p, const void* delta, int n_bins, double* k_mean, doubl
                 void* stream) {
   PM_TRY(check_plan(p));
   if (!delta || !k_mean || !pk || !n_modes) return set_error(PM_ERR_ARG, "pk_estimate: null pointer");
-  if (n_bins <= 0 || 3 * (size_t)n_bins > p->sums_cap || n_bins > 4 * p->n)
+  if (n_bins <= 0 || 3 * (size_t)n_bins * p->nb > p->sums_cap || n_bins > 4 * p->n)
     return set_error(PM_ERR_ARG, "pk_estimate: n_bins %d out of range", n_bins);
   hipStream_t s = static_cast<hipStream_t>(stream);
   PM_TRY(fft3_r2c(p, delta, cbuf(p, 0), s));
-  PM_TRY(launch_zero_doubles(p->sums, 3 * (int64_t)n_bins, s));
+  PM_TRY(launch_zero_doubles(p->sums, 3 * (int64_t)n_bins * p->nb, s));
   PM_TRY(launch_pk_reduce(p, cbuf(p, 0), n_bins, s));
   return launch_pk_finalize(p, n_bins, k_mean, pk, n_modes, s);
 }
@@ -410,7 +429,7 @@ int pk_estimate(pm_plan* p, const void* delta, int n_bins, double* k_mean, doubl
 int bk_estimate(pm_plan* p, const void* delta, int n_shells, const double* centre, double width, const int32_t* tri,
                 int n_tri, double* bk, double* ntri_out, const double* ntri_known, void* shell_ws,
                 size_t shell_ws_bytes, void* stream) {
-  PM_TRY(check_plan(p));
+  PM_TRY(check_single(p, "bk_estimate"));
   if (!delta || !centre || !tri || !bk || !ntri_out || !shell_ws) return set_error(PM_ERR_ARG, "bk_estimate: null pointer");
   if (n_shells <= 0 || n_tri <= 0 || !(width > 0.0)) return set_error(PM_ERR_ARG, "bk_estimate: bad sizes");
   if (2 * (size_t)n_tri > p->sums_cap) return set_error(PM_ERR_ARG, "bk_estimate: too many triangles");

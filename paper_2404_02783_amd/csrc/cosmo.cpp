@@ -209,8 +209,7 @@ static int ic_common(pm_plan* p, const void* noise, const pm_ic_params* ic, void
   if (rc) return rc;
   rc = launch_ic_symbol(p, ic_symbol_of(p, ic, kpow, coef), false, s);
   if (rc) return rc;
-  const int64_t cstride = (int64_t)(p->cbytes / (2 * p->esize));
-  return fft3_c2r(p, 3, cbuf(p, 0), cstride, disp, s);
+  return fft3_c2r(p, 3 * p->nb, cbuf(p, 0), cstride(p), disp, s);
 }
 
 static int check_ic(pm_plan* p, const void* noise, const pm_ic_params* ic, const void* disp, const char* who) {
@@ -240,6 +239,7 @@ int pm_ic_zeldovich_adjoint(pm_plan* p, const pm_ic_params* ic, const void* lam_
                             void* disp_scratch, void* lam_noise, void* stream) {
   using namespace pm;
   if (!p) return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: null plan");
+  if (p->nb != 1) return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: needs a single-box plan");
   if (!ic || !lam_pos || !lam_mom || !disp_scratch || !lam_noise)
     return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: null pointer");
   if (ic->pk_kind != PM_PK_POWERLAW && ic->pk_kind != PM_PK_EH98)
@@ -265,6 +265,7 @@ int pm_ic_gauge(pm_plan* p, const void* noise, const pm_ic_params* ic, void* dis
   using namespace pm;
   int rc = check_ic(p, noise, ic, disp, "pm_ic_gauge");
   if (rc) return rc;
+  if (p->nb != 1) return set_error(PM_ERR_ARG, "pm_ic_gauge: needs a single-box plan");
   if (!pos_n || !mom_n || !pos_gr || !mom_gr) return set_error(PM_ERR_ARG, "pm_ic_gauge: null pointer");
   const pm_cosmology* c = &ic->cosmo;
   const double a = ic->a_init;

@@ -26,6 +26,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit(const T* __restrict__ pos, i
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = blk * kBlock + threadIdx.x;
   if (i >= np) return;
+  pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
+  mesh += (int64_t)blockIdx.y * n * n * n;
   T x = pos[i], y = pos[np + i], z = pos[2 * np + i];
   if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
     atomicAdd(&guard[0], 1u);
@@ -85,6 +87,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
   __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
   __shared__ float wsum[kBlock / 64][3];
   const int64_t np = (int64_t)n * n * n;
+  pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
+  mesh += (int64_t)blockIdx.y * np;
   const int tpx = n / TX, tpy = n / TY, tpz = n / TZ;
   const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
   const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
@@ -226,13 +230,13 @@ int launch_deposit(const pm_plan* p, const void* pos, int64_t np, void* mesh, hi
   const double w = n3 / (double)np;  // 1 / nbar
   if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % TZ == 0 && n % TX == 0) {
     const unsigned tiles = (unsigned)((n / TX) * (n / TY) * (n / TZ));
-    hipLaunchKernelGGL(k_deposit_tiled, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(pos),
+    hipLaunchKernelGGL(k_deposit_tiled, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const float*>(pos),
                        static_cast<float*>(mesh), n, w, p->guard);
   } else if (p->dtype == PM_F32) {
-    hipLaunchKernelGGL(k_deposit<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(pos), np,
+    hipLaunchKernelGGL(k_deposit<float>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const float*>(pos), np,
                        static_cast<float*>(mesh), n, (float)w, p->guard);
   } else {
-    hipLaunchKernelGGL(k_deposit<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(pos), np,
+    hipLaunchKernelGGL(k_deposit<double>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const double*>(pos), np,
                        static_cast<double*>(mesh), n, w, p->guard);
   }
   return hip_check(hipGetLastError(), "deposit");

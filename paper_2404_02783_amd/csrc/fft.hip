@@ -37,13 +37,13 @@ void launch_cols_t(cx<T>* data, const ColArgs& g, int dir, int ncomp, int outer,
 }
 
 template <typename T, int L1, int L2>
-void launch_r2c_t(const T* in, cx<T>* out, const RowArgs& g, const cx<T>* tw, hipStream_t s) {
+void launch_r2c_t(const T* in, cx<T>* out, const RowArgs& g, int ncomp, const cx<T>* tw, hipStream_t s) {
   constexpr int M = L1 * L2;
   constexpr int TPC = L1 > L2 ? L1 : L2;
   constexpr int XS = L1 * (L2 + 1);
   constexpr int RS = XS > M ? XS : M;
   const int R = 256 / TPC;
-  dim3 grid((unsigned)((g.nrows + R - 1) / R), 1);
+  dim3 grid((unsigned)((g.nrows + R - 1) / R), (unsigned)ncomp);
   dim3 block((unsigned)(R * TPC));
   hipLaunchKernelGGL((k_fft_rows_r2c<T, L1, L2>), grid, block, (size_t)R * RS * sizeof(cx<T>), s, in, out, g, tw);
 }
@@ -64,7 +64,7 @@ template <typename T, int L1, int L2>
 void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* o2, cx<T>* phi, const ColArgs& g, const SolveArgs& a, int outer,
                     const cx<T>* tw, hipStream_t s) {
   const int tpc = std::max(L1, L2);
-  dim3 grid((unsigned)(outer * g.groups), 1);
+  dim3 grid((unsigned)(outer * g.groups), (unsigned)a.nbox);
   dim3 block((unsigned)(g.bcols * tpc));
   size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
   // y/z components first (they also update the carried potential), then the x
@@ -124,16 +124,16 @@ int cols_t(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t c
 }
 
 template <typename T>
-int r2c_t(const pm_plan* p, const void* in, void* out, hipStream_t s) {
+int r2c_t(const pm_plan* p, int count, const void* in, void* out, hipStream_t s) {
   const int n = p->n;
   RowArgs g;
   g.nrows = (int64_t)n * n;
-  g.in_comp = 0;
-  g.out_comp = 0;
+  g.in_comp = (int64_t)n * n * n;
+  g.out_comp = cstride(p);
   g.n = n;
   g.hs = p->hp;
   const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
-  PM_DISPATCH_LEN(n / 2, launch_r2c_t, static_cast<const T*>(in), static_cast<cx<T>*>(out), g, tw, s)
+  PM_DISPATCH_LEN(n / 2, launch_r2c_t, static_cast<const T*>(in), static_cast<cx<T>*>(out), g, count, tw, s)
   return hip_check(hipGetLastError(), "fft r2c rows");
 }
 
@@ -166,6 +166,9 @@ int solve_t(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t 
   a.h2 = sp->calh * sp->calh;
   a.om_a = sp->om_a;
   a.inv_dtau = sp->inv_dtau;
+  a.nbox = p->nb;
+  a.box_stride = cstride(p);
+  a.phi_stride = (int64_t)n * n * (n / 2 + 1);
   cx<T>* c0 = static_cast<cx<T>*>(cbuf(p, 0));
   cx<T>* c1 = static_cast<cx<T>*>(cbuf(p, 1));
   cx<T>* c2 = static_cast<cx<T>*>(cbuf(p, 2));
@@ -184,9 +187,9 @@ int fft_pass_cols(const pm_plan* p, void* data, int axis, int dir, int ncomp, in
                             : cols_t<double>(p, data, axis, dir, ncomp, comp_stride, s);
 }
 
-int fft_pass_rows_r2c(const pm_plan* p, const void* in, void* out, hipStream_t s) {
+int fft_pass_rows_r2c(const pm_plan* p, int count, const void* in, void* out, hipStream_t s) {
   ProfScope ps(p, PK_R2C_ROWS, s);
-  return p->dtype == PM_F32 ? r2c_t<float>(p, in, out, s) : r2c_t<double>(p, in, out, s);
+  return p->dtype == PM_F32 ? r2c_t<float>(p, count, in, out, s) : r2c_t<double>(p, count, in, out, s);
 }
 
 int fft_pass_rows_c2r(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* out, hipStream_t s) {
@@ -199,12 +202,16 @@ int fft_pass_solve(const pm_plan* p, const pm_solve_params* sp, void* phi, hipSt
   return p->dtype == PM_F32 ? solve_t<float>(p, sp, phi, s) : solve_t<double>(p, sp, phi, s);
 }
 
+int fft3_r2c_n(const pm_plan* p, int count, const void* real_in, void* cplx_out, hipStream_t s) {
+  int rc = fft_pass_rows_r2c(p, count, real_in, cplx_out, s);
+  if (rc) return rc;
+  rc = fft_pass_cols(p, cplx_out, 1, -1, count, cstride(p), s);
+  if (rc) return rc;
+  return fft_pass_cols(p, cplx_out, 0, -1, count, cstride(p), s);
+}
+
 int fft3_r2c(const pm_plan* p, const void* real_in, void* cplx_out, hipStream_t s) {
-  int rc = fft_pass_rows_r2c(p, real_in, cplx_out, s);
-  if (rc) return rc;
-  rc = fft_pass_cols(p, cplx_out, 1, -1, 1, 0, s);
-  if (rc) return rc;
-  return fft_pass_cols(p, cplx_out, 0, -1, 1, 0, s);
+  return fft3_r2c_n(p, p->nb, real_in, cplx_out, s);
 }
 
 int fft3_c2r(const pm_plan* p, int ncomp, void* cplx_in, int64_t comp_stride, void* real_out, hipStream_t s) {

@@ -215,6 +215,9 @@ struct SolveArgs {
   double newton;    // (3/2) Omega_m / N^3
   double a_c2;      // a c_g^2 / N^3
   double h, h2, om_a, inv_dtau;
+  int nbox;            // boxes (blockIdx.y)
+  int64_t box_stride;  // complex elements between the boxes' spectra
+  int64_t phi_stride;  // complex elements between the boxes' potentials
 };
 
 __device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
@@ -248,6 +251,13 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
   const bool valid = col < g.ncols;
   const int64_t off = outer * g.outer_stride + col;
   const int N = s.n;
+  {
+    const int64_t bo = (int64_t)blockIdx.y * s.box_stride;
+    data += bo;
+    out1 += bo;
+    out2 += bo;
+    if (KIND != PM_NEWTON) phi += (int64_t)blockIdx.y * s.phi_stride;
+  }
 
   // forward along axis 0
   if (u < L2) {

@@ -23,10 +23,12 @@ __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, int64_t coun
 }
 
 // sum over the 8 CIC corners of the three force components
+// f: three meshes n3 = fstride elements apart
 template <typename T>
-__device__ __forceinline__ void cic_interp3(const T* __restrict__ f, int n, T x, T y, T z, T& fx, T& fy, T& fz) {
+__device__ __forceinline__ void cic_interp3(const T* __restrict__ f, int n, int64_t n3, T x, T y, T z, T& fx, T& fy,
+                                            T& fz) {
   const Axis<T> ax = cic_axis(x, n), ay = cic_axis(y, n), az = cic_axis(z, n);
-  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
+  const int64_t n2 = (int64_t)n * n;
   const int64_t r[4] = {ax.i0 * n2 + (int64_t)ay.i0 * n, ax.i0 * n2 + (int64_t)ay.i1 * n,
                         ax.i1 * n2 + (int64_t)ay.i0 * n, ax.i1 * n2 + (int64_t)ay.i1 * n};
   const T w[4] = {ax.w0 * ay.w0, ax.w0 * ay.w1, ax.w1 * ay.w0, ax.w1 * ay.w1};
@@ -51,21 +53,28 @@ __global__ void __launch_bounds__(kBlock) k_gather(const T* __restrict__ force, 
   const int64_t i = blk * kBlock + threadIdx.x;
   if (i >= np) return;
   T fx, fy, fz;
-  cic_interp3(force, n, wrap(pos[i], n), wrap(pos[np + i], n), wrap(pos[2 * np + i], n), fx, fy, fz);
+  cic_interp3(force, n, (int64_t)n * n * n, wrap(pos[i], n), wrap(pos[np + i], n), wrap(pos[2 * np + i], n), fx, fy,
+              fz);
   acc[i] = fx;
   acc[np + i] = fy;
   acc[2 * np + i] = fz;
 }
 
+// Box blockIdx.y of a batch: particles [3][np] at pos/mom + 3 np box, force components
+// fstride elements apart, box offset N^3.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gather_kdk(const T* __restrict__ force, T* __restrict__ pos,
-                                                       T* __restrict__ mom, int64_t np, int n, T kick, T drift) {
+                                                       T* __restrict__ mom, int64_t np, int n, int64_t fstride, T kick,
+                                                       T drift) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = blk * kBlock + threadIdx.x;
   if (i >= np) return;
+  pos += (int64_t)blockIdx.y * 3 * np;
+  mom += (int64_t)blockIdx.y * 3 * np;
+  force += (int64_t)blockIdx.y * n * n * n;
   T x = wrap(pos[i], n), y = wrap(pos[np + i], n), z = wrap(pos[2 * np + i], n);
   T fx, fy, fz;
-  cic_interp3(force, n, x, y, z, fx, fy, fz);
+  cic_interp3(force, n, fstride, x, y, z, fx, fy, fz);
   T px = mom[i] + kick * fx, py = mom[np + i] + kick * fy, pz = mom[2 * np + i] + kick * fz;
   mom[i] = px;
   mom[np + i] = py;
@@ -88,12 +97,15 @@ constexpr int GCAP = 4096;                     // staged cells (x3 components, f
 constexpr int GWF = 16;                        // fallback box side (GWF^3 <= GCAP)
 
 __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
-                                                             float* __restrict__ mom, int n, float kick,
-                                                             float drift) {
+                                                             float* __restrict__ mom, int n, int64_t fstride,
+                                                             float kick, float drift) {
   __shared__ float win[3 * GCAP];
   __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
   __shared__ float wsum[kBlock / 64][3];
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
+  mom += (int64_t)blockIdx.y * 3 * np;
+  force += (int64_t)blockIdx.y * np;
   const int tpy = n / GTY, tpz = n / GTZ;
   const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
   const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
@@ -172,8 +184,8 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
     const int64_t idx = ((int64_t)fold(org[0] + o[0] + a, n) * n + fold(org[1] + o[1] + b, n)) * n +
                         fold(org[2] + o[2] + cz, n);
     win[c] = force[idx];
-    win[GCAP + c] = force[np + idx];
-    win[2 * GCAP + c] = force[2 * np + idx];
+    win[GCAP + c] = force[fstride + idx];
+    win[2 * GCAP + c] = force[2 * fstride + idx];
   }
   __syncthreads();
 #pragma unroll
@@ -201,8 +213,8 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
         const int64_t a0 = r[c] + az.i0, a1 = r[c] + az.i1;
         const float w0 = w[c] * az.w0, w1 = w[c] * az.w1;
         fx += w0 * force[a0] + w1 * force[a1];
-        fy += w0 * force[np + a0] + w1 * force[np + a1];
-        fz += w0 * force[2 * np + a0] + w1 * force[2 * np + a1];
+        fy += w0 * force[fstride + a0] + w1 * force[fstride + a1];
+        fz += w0 * force[2 * fstride + a0] + w1 * force[2 * fstride + a1];
       }
     }
     const int64_t j = jj[p];
@@ -263,16 +275,21 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, co
 
 // Lattice step of the initial conditions: pos = wrap(q + disp), mom = c * disp,
 // q = (i, j, l) + 1/2 for particle (i N + j) N + l.
+// Box blockIdx.y of a batch of gridDim.y: disp is [3][nbox][N^3], pos/mom [nbox][3][N^3].
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ic_lattice(const T* __restrict__ disp, T* __restrict__ pos,
                                                        T* __restrict__ mom, int n, T mom_factor) {
   const int64_t np = (int64_t)n * n * n;
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= np) return;
+  const int64_t dstride = (int64_t)gridDim.y * np;
+  disp += (int64_t)blockIdx.y * np;
+  pos += (int64_t)blockIdx.y * 3 * np;
+  mom += (int64_t)blockIdx.y * 3 * np;
   const int q[3] = {(int)(j / ((int64_t)n * n)), (int)((j / n) % n), (int)(j % n)};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const T s = disp[d * np + j];
+    const T s = disp[d * dstride + j];
     pos[d * np + j] = wrap(T(q[d]) + T(0.5) + s, n);
     mom[d * np + j] = mom_factor * s;
   }
@@ -323,16 +340,20 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
   ProfScope ps(p, PK_GATHER_KDK, s);
   if (np <= 0) return PM_OK;
   const int n = p->n;
+  const int64_t fstride = (int64_t)p->nb * n * n * n;  // force meshes are [3][nb][N^3]
   if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % GTZ == 0) {
     const unsigned tiles = (unsigned)((n / GTX) * (n / GTY) * (n / GTZ));
-    hipLaunchKernelGGL(k_gather_kdk_tiled, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(force),
-                       static_cast<float*>(pos), static_cast<float*>(mom), n, (float)kick, (float)drift);
+    hipLaunchKernelGGL(k_gather_kdk_tiled, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s,
+                       static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), n, fstride,
+                       (float)kick, (float)drift);
   } else if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_gather_kdk<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(force),
-                       static_cast<float*>(pos), static_cast<float*>(mom), np, p->n, (float)kick, (float)drift);
+    hipLaunchKernelGGL(k_gather_kdk<float>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s,
+                       static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), np, p->n,
+                       fstride, (float)kick, (float)drift);
   else
-    hipLaunchKernelGGL(k_gather_kdk<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(force),
-                       static_cast<double*>(pos), static_cast<double*>(mom), np, p->n, kick, drift);
+    hipLaunchKernelGGL(k_gather_kdk<double>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s,
+                       static_cast<const double*>(force), static_cast<double*>(pos), static_cast<double*>(mom), np, p->n,
+                       fstride, kick, drift);
   return hip_check(hipGetLastError(), "gather-kick-drift");
 }
 
@@ -353,11 +374,12 @@ int launch_combine(const void* x_gr, const void* x_n, int nc, const void* x_f, i
 int launch_ic_lattice(const pm_plan* p, const void* disp, void* pos, void* mom, double mom_factor, hipStream_t s) {
   ProfScope ps(p, PK_IC, s);
   const int64_t np = (int64_t)p->n * p->n * p->n;
+  const dim3 grid(nblocks(np), (unsigned)p->nb);
   if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_ic_lattice<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(disp),
+    hipLaunchKernelGGL(k_ic_lattice<float>, grid, dim3(kBlock), 0, s, static_cast<const float*>(disp),
                        static_cast<float*>(pos), static_cast<float*>(mom), p->n, (float)mom_factor);
   else
-    hipLaunchKernelGGL(k_ic_lattice<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(disp),
+    hipLaunchKernelGGL(k_ic_lattice<double>, grid, dim3(kBlock), 0, s, static_cast<const double*>(disp),
                        static_cast<double*>(pos), static_cast<double*>(mom), p->n, mom_factor);
   return hip_check(hipGetLastError(), "ic lattice");
 }

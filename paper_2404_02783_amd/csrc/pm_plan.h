@@ -8,6 +8,8 @@
 #include "../../include/pmhip.h"
 
 namespace pm {
+// Largest batch of equal-size boxes in one plan (grid.y of the batched launches).
+constexpr int kMaxBatch = 4096;
 // Kernel kinds timed by the optional per-plan profiler.
 enum ProfKind {
   PK_FILL = 0,
@@ -36,10 +38,11 @@ struct ProfState;
 struct pm_plan {
   pm::ProfState* prof;  // null unless profiling is enabled
   int n;             // mesh cells per axis
+  int nb;            // boxes of the batch (all of side n), >= 1
   int dtype;         // PM_F32 | PM_F64
   double box;        // Mpc/h
   size_t esize;      // sizeof(real)
-  void* ws;          // workspace: three [N][N][N/2+1] complex buffers
+  void* ws;          // workspace: three regions of nb [N][N][hp] complex spectra
   size_t ws_bytes;
   size_t cbytes;     // bytes of one complex buffer (256-byte aligned)
   int hp;            // row stride of the internal spectra (padded N/2+1)
@@ -57,7 +60,12 @@ namespace pm {
 int set_error(int code, const char* fmt, ...);
 int hip_check(hipError_t e, const char* what);
 
-inline void* cbuf(const pm_plan* p, int i) { return static_cast<char*>(p->ws) + (size_t)i * p->cbytes; }
+// Region i (0..2) of the workspace: nb spectra of cbytes each, box b at + b * cbytes.
+inline void* cbuf(const pm_plan* p, int i) {
+  return static_cast<char*>(p->ws) + (size_t)i * (size_t)p->nb * p->cbytes;
+}
+// Complex elements between consecutive spectra of the workspace.
+inline int64_t cstride(const pm_plan* p) { return (int64_t)(p->cbytes / (2 * p->esize)); }
 
 // Records a start/stop HIP event pair around the launches in its scope when the
 // plan's profiler is on (api.cpp).
@@ -75,17 +83,21 @@ struct ProfScope {
 };
 
 // ---------------------------------------------------------------- fft.hip --
-// Forward 3-D r2c: real [N][N][N] -> complex [N][N][N/2+1] (unnormalised).
+// Forward 3-D r2c of the plan's nb boxes: real [nb][N][N][N] -> complex [nb][N][N][hp]
+// spaced cstride apart (unnormalised).
 int fft3_r2c(const pm_plan* p, const void* real_in, void* cplx_out, hipStream_t s);
+// Same for `count` boxes (1 <= count <= nb).
+int fft3_r2c_n(const pm_plan* p, int count, const void* real_in, void* cplx_out, hipStream_t s);
 // Inverse 3-D c2r of `ncomp` spectra spaced comp_stride complex elements apart
 // (destroyed) -> ncomp real meshes spaced N^3 apart (unnormalised: N^3 times the
 // inverse DFT).
 int fft3_c2r(const pm_plan* p, int ncomp, void* cplx_in, int64_t comp_stride, void* real_out, hipStream_t s);
 // Forward column pass along axis 0 only (used after r2c rows + axis-1 pass).
 int fft_pass_cols(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s);
-int fft_pass_rows_r2c(const pm_plan* p, const void* in, void* out, hipStream_t s);
+int fft_pass_rows_r2c(const pm_plan* p, int count, const void* in, void* out, hipStream_t s);
 int fft_pass_rows_c2r(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* out, hipStream_t s);
-// Fused solve pass along axis 0 on cbuf(0): writes force spectra to cbuf 0, 1, 2.
+// Fused solve pass along axis 0 on cbuf(0) (all nb boxes): writes force spectra to
+// cbuf 0, 1, 2; phi_state holds nb unpadded [N][N][N/2+1] potentials.
 int fft_pass_solve(const pm_plan* p, const pm_solve_params* sp, void* phi_state, hipStream_t s);
 
 // ---------------------------------------------------------- particles.hip --

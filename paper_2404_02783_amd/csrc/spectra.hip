@@ -35,11 +35,14 @@ __device__ double eh98_transfer(double k, double om, double ob, double h, double
 // spectra of the displacement cotangents).
 template <typename T, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx<T>* __restrict__ c1,
-                                                      cx<T>* __restrict__ c2, int n, int hp, IcSymbol sy) {
+                                                      cx<T>* __restrict__ c2, int n, int hp, int64_t cs, IcSymbol sy) {
   const int h = hp;  // padded row stride; columns iz > N/2 are padding
   const int64_t total = (int64_t)n * n * h;
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= total) return;
+  c0 += (int64_t)blockIdx.y * cs;  // box of the batch (spectra cs elements apart)
+  c1 += (int64_t)blockIdx.y * cs;
+  c2 += (int64_t)blockIdx.y * cs;
   const int iz = (int)(idx % h);
   if (iz > n / 2) return;
   const int iy = (int)((idx / h) % n);
@@ -118,9 +121,11 @@ __device__ __forceinline__ int pk_bin(int64_t n2, int n, int nb) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ dhat, int n, int hp, int nb,
-                                                      double* __restrict__ sums) {
+__global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ dhat, int n, int hp, int64_t cs,
+                                                      int nb, double* __restrict__ sums) {
   extern __shared__ double sh[];
+  dhat += (int64_t)blockIdx.y * cs;  // box of the batch
+  sums += (int64_t)blockIdx.y * 3 * nb;
   double* sp = sh;
   double* sk = sh + nb;
   unsigned long long* sc = reinterpret_cast<unsigned long long*>(sh + 2 * nb);
@@ -182,6 +187,10 @@ __global__ void k_pk_finalize(const double* __restrict__ sums, int nb, int n, do
                               double* __restrict__ pk, int64_t* __restrict__ n_modes) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
+  sums += (int64_t)blockIdx.y * 3 * nb;  // box of the batch
+  k_mean += (int64_t)blockIdx.y * nb;
+  pk += (int64_t)blockIdx.y * nb;
+  n_modes += (int64_t)blockIdx.y * nb;
   const unsigned long long c = reinterpret_cast<const unsigned long long*>(sums + 2 * nb)[b];
   const double kf = 2.0 * kPi / box;
   const double vol = box * box * box;
@@ -283,19 +292,20 @@ int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, bool adjoint, hipStr
   ProfScope ps(p, PK_IC, s);
   const int n = p->n;
   const int64_t total = (int64_t)n * n * p->hp;
-  const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
+  const dim3 g((unsigned)((total + kBlock - 1) / kBlock), (unsigned)p->nb);
+  const int64_t cs = cstride(p);
   cx<float>* f[3] = {static_cast<cx<float>*>(cbuf(p, 0)), static_cast<cx<float>*>(cbuf(p, 1)),
                      static_cast<cx<float>*>(cbuf(p, 2))};
   cx<double>* d[3] = {static_cast<cx<double>*>(cbuf(p, 0)), static_cast<cx<double>*>(cbuf(p, 1)),
                       static_cast<cx<double>*>(cbuf(p, 2))};
   if (p->dtype == PM_F32 && adjoint)
-    hipLaunchKernelGGL((k_ic_symbol<float, true>), dim3(g), dim3(kBlock), 0, s, f[0], f[1], f[2], n, p->hp, sym);
+    hipLaunchKernelGGL((k_ic_symbol<float, true>), g, dim3(kBlock), 0, s, f[0], f[1], f[2], n, p->hp, cs, sym);
   else if (p->dtype == PM_F32)
-    hipLaunchKernelGGL((k_ic_symbol<float, false>), dim3(g), dim3(kBlock), 0, s, f[0], f[1], f[2], n, p->hp, sym);
+    hipLaunchKernelGGL((k_ic_symbol<float, false>), g, dim3(kBlock), 0, s, f[0], f[1], f[2], n, p->hp, cs, sym);
   else if (adjoint)
-    hipLaunchKernelGGL((k_ic_symbol<double, true>), dim3(g), dim3(kBlock), 0, s, d[0], d[1], d[2], n, p->hp, sym);
+    hipLaunchKernelGGL((k_ic_symbol<double, true>), g, dim3(kBlock), 0, s, d[0], d[1], d[2], n, p->hp, cs, sym);
   else
-    hipLaunchKernelGGL((k_ic_symbol<double, false>), dim3(g), dim3(kBlock), 0, s, d[0], d[1], d[2], n, p->hp, sym);
+    hipLaunchKernelGGL((k_ic_symbol<double, false>), g, dim3(kBlock), 0, s, d[0], d[1], d[2], n, p->hp, cs, sym);
   return hip_check(hipGetLastError(), "ic symbol");
 }
 
@@ -313,18 +323,20 @@ int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t
   if (g < 1) g = 1;
   if (g > 65535) g = 65535;
   const size_t shm = (size_t)n_bins * 3 * sizeof(double);
+  const dim3 grid((unsigned)g, (unsigned)p->nb);
   if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_pk_reduce<float>, dim3((unsigned)g), dim3(kBlock), shm, s,
-                       static_cast<const cx<float>*>(dhat), n, p->hp, n_bins, p->sums);
+    hipLaunchKernelGGL(k_pk_reduce<float>, grid, dim3(kBlock), shm, s, static_cast<const cx<float>*>(dhat), n, p->hp,
+                       cstride(p), n_bins, p->sums);
   else
-    hipLaunchKernelGGL(k_pk_reduce<double>, dim3((unsigned)g), dim3(kBlock), shm, s,
-                       static_cast<const cx<double>*>(dhat), n, p->hp, n_bins, p->sums);
+    hipLaunchKernelGGL(k_pk_reduce<double>, grid, dim3(kBlock), shm, s, static_cast<const cx<double>*>(dhat), n,
+                       p->hp, cstride(p), n_bins, p->sums);
   return hip_check(hipGetLastError(), "pk reduce");
 }
 
 int launch_pk_finalize(const pm_plan* p, int n_bins, double* k_mean, double* pk, int64_t* n_modes, hipStream_t s) {
   ProfScope ps(p, PK_PK, s);
-  hipLaunchKernelGGL(k_pk_finalize, dim3((unsigned)((n_bins + 63) / 64)), dim3(64), 0, s, p->sums, n_bins, p->n, p->box,
+  hipLaunchKernelGGL(k_pk_finalize, dim3((unsigned)((n_bins + 63) / 64), (unsigned)p->nb), dim3(64), 0, s, p->sums,
+                     n_bins, p->n, p->box,
                      k_mean, pk, n_modes);
   return hip_check(hipGetLastError(), "pk finalize");
 }
