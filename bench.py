@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -129,6 +131,136 @@ def adjoint_ratio(pm, plan, noise, icp, n_cycles: int, ckpt: int, n_bins: int):
     return t1 - t0, t2 - t1, prof
 
 
+def config3_estimators(pm, plan, pos, n_bins=256):
+    """Timings of the estimator and combination calls of the displacement-combination
+    configuration on the final 1024^3 positions: deposit + P(k) in 256 bins, B(k)
+    on 64 triangles (32 equilateral k = m*16 k_f, 32 squeezed with k3 = 4 k_f; shell
+    width 2 k_f), and the combination of a 256^3 pair into the 1024^3 run."""
+    import torch
+    import synth_inputs as si
+    out = {}
+    n = plan.n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    delta = pm.pm_deposit(plan, pos)
+    k, pk, cnt = pm.pk_estimate(plan, delta, n_bins)
+    torch.cuda.synchronize()
+    out["deposit_pk_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    # B(k): shells m*16 k_f (m = 1..32) and the squeezed shell at 4 k_f
+    centres = [16.0 * m for m in range(1, 33)] + [4.0]
+    tris = [(m, m, m) for m in range(32)] + [(m, m, 32) for m in range(32)]
+    shell_ws = torch.empty((8,) + (n,) * 3, dtype=plan.dtype, device=plan.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bk, ntri = pm.bk_estimate(plan, delta, centres, 2.0, tris, shell_ws=shell_ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bk2, _ = pm.bk_estimate(plan, delta, centres, 2.0, tris, shell_ws=shell_ws, ntri_known=ntri)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["bk_first_call_ms"] = round((t1 - t0) * 1e3, 1)
+    out["bk_cached_counts_ms"] = round((t2 - t1) * 1e3, 1)
+    del shell_ws, bk, bk2, ntri
+    # combination: a coarse 256^3 Newtonian/Poisson-gauge pair (L = 4000 Mpc/h, 50 log steps)
+    nc = 256
+    cplan = pm.Plan(nc, plan.box, plan.dtype, plan.device)
+    noise = torch.from_numpy(si.white_noise(nc, 3003, dtype=np.float32)).to(plan.device)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=0.02,
+                      a_norm=1.0, cosmo=pm.FIDUCIAL)
+    xn, pn, xg, pg = (torch.empty((3, nc ** 3), dtype=plan.dtype, device=plan.device) for _ in range(4))
+    disp = cplan.mesh(3)
+    pm.pm_ic_zeldovich(cplan, noise, icp, disp, xn, pn)
+    pm.pm_ic_gauge(cplan, noise, icp, disp, xn, pn, xg, pg)
+    a_s = pm.sim.log_steps(0.02, 1.0, 50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm.sim.Run(cplan, xn, pn).leapfrog(a_s, close=False)
+    pm.sim.Run(cplan, xg, pg, gauge=True).leapfrog(a_s, close=False)
+    torch.cuda.synchronize()
+    out["coarse_pair_256_50steps_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    x_out = torch.empty_like(pos)
+    pm.displacement_combine(xg, xn, nc, pos, n, x_out)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm.displacement_combine(xg, xn, nc, pos, n, x_out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["combine_ms"] = round(dt * 1e3, 2)
+    out["combine_GBps_alg"] = round(24 * n ** 3 / dt / 1e9, 1)  # read x_fine, write x_out
+    out["note"] = ("coarse noise is an independent 256^3 seed (timing only); B(k) keeps 8 shell fields resident "
+                   "and recomputes evicted shells")
+    del x_out, xn, pn, xg, pg, disp, cplan, delta
+    return out
+
+
+def config5_adjoint(pm, n=128, box=1000.0, n_steps=20, ckpt=5, n_bins=64):
+    """Adjoint/forward time of the differentiable configuration: 128^3, L = 1000 Mpc/h,
+    20 log steps a = 0.05 -> 1, P(k) in 64 bins, checkpoints every 5 cycles."""
+    import torch
+    import synth_inputs as si
+    from paper_2404_02783_amd import diff
+    dev = torch.device("cuda:0")
+    plan = pm.Plan(n, box, torch.float32, dev)
+    noise = torch.from_numpy(si.white_noise(n, 5, dtype=np.float32)).to(dev)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=0.05,
+                      a_norm=1.0, cosmo=pm.FIDUCIAL)
+    sched = diff.Schedule(pm.sim.log_steps(0.05, 1.0, n_steps))
+    dpk = torch.linspace(-1.0, 1.0, n_bins, dtype=torch.float64, device=dev)
+    best = None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, tape = diff.forward(plan, noise, icp, sched, n_bins, ckpt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        diff.backward(tape, dpk)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if best is None or (t2 - t1) + (t1 - t0) < best[0] + best[1]:
+            best = (t1 - t0, t2 - t1)
+    return {"workload": f"{n}^3, L={box:g} Mpc/h, {n_steps} log steps a=0.05->1, P(k) in {n_bins} bins, "
+                        f"checkpoints every {ckpt}", "forward_ms": round(best[0] * 1e3, 2),
+            "backward_ms": round(best[1] * 1e3, 2), "ratio": round(best[1] / best[0], 3)}
+
+
+def ensemble_leg(pm):
+    """64-box ensemble (16 x 64^3, 24 x 128^3, 16 x 192^3, 8 x 256^3; 30 log steps
+    a = 0.02 -> 1; per-box P(k)): one captured graph over the batched groups vs
+    the same boxes run one by one on single-box plans with eager launches."""
+    import torch
+    import synth_inputs as si
+    from paper_2404_02783_amd import ensemble
+    dev = torch.device("cuda:0")
+    groups = ensemble.default_groups()
+    noise_fn = lambda n, s: si.white_noise(n, s)  # noqa: E731
+    ens = ensemble.Ensemble(groups, noise_fn, 0.02, 1.0, 30, torch.float32, dev)
+    ens.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.replay()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ens.run()
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    pk_batched = [o[1].clone() for o in ens.power_spectra()]
+    plans = {(g.n, g.box): pm.Plan(g.n, g.box, torch.float32, dev) for g in groups}
+    noises = {s: st.noise[i] for st in ens.states for i, s in enumerate(st.group.seeds)}
+    one = [ensemble.Group(g.n, g.box, g.seeds[:1]) for g in groups]
+    ensemble.run_sequential(one, noise_fn, 0.02, 1.0, 30, torch.float32, dev, plans, noises)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pk_seq = ensemble.run_sequential(groups, noise_fn, 0.02, 1.0, 30, torch.float32, dev, plans, noises)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    worst = max(float(((a - b).abs() / b.abs().clamp_min(1e-30)).max()) for a, b in zip(pk_batched, pk_seq))
+    return {"boxes": sum(len(g.seeds) for g in groups), "graph_s": round(t_graph, 4),
+            "batched_eager_s": round(t_eager, 4), "sequential_s": round(t_seq, 4),
+            "speedup_graph_vs_sequential": round(t_seq / t_graph, 2),
+            "max_rel_pk_diff_batched_vs_sequential": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +274,8 @@ def main():
     ap.add_argument("--adjoint-cycles", type=int, default=4,
                     help="leapfrog cycles of the differentiable run timed for the adjoint/forward ratio (0: skip)")
     ap.add_argument("--adjoint-ckpt", type=int, default=2)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the estimator/combination timings, the 128^3 adjoint and the ensemble legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -243,6 +377,9 @@ def main():
         "kernels": kernels,
         "adjoint_forward_ratio": None,
     }
+    if not args.no_extras:
+        print("[bench] estimators and combination at 1024^3", file=sys.stderr, flush=True)
+        out["config3"] = config3_estimators(pm, plan, pos)
     if args.adjoint_cycles > 0:
         del run, pos, mom
         torch.cuda.synchronize()
@@ -256,7 +393,13 @@ def main():
                         f"{args.adjoint_ckpt} cycles",
             "forward_s": round(t_fwd, 4), "backward_s": round(t_bwd, 4),
             "kernels": {k: {"avg_ms": round(ms / c, 4), "launches": c} for k, (ms, c) in aprof.items()}}
-    del noise
+    del noise, plan
+    if not args.no_extras:
+        torch.cuda.empty_cache()
+        print("[bench] 128^3 adjoint configuration", file=sys.stderr, flush=True)
+        out["adjoint_128"] = config5_adjoint(pm)
+        print("[bench] 64-box ensemble", file=sys.stderr, flush=True)
+        out["ensemble"] = ensemble_leg(pm)
     if not args.no_cpu_baseline:
         print(f"[bench] CPU oracle baseline at {args.cpu_sample}^3 ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

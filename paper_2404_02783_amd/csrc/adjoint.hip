@@ -67,6 +67,211 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_kdk(const T* __restrict__
   lam_pos[2 * np + i] = lx[2] + gz;
 }
 
+// Full-lattice (np = N^3, FP32) variants.  The force-field term is computed per
+// Lagrangian tile of AX x AY x AZ particles with the three force meshes staged in LDS
+// over the tile's CIC bounding box (as in the forward gather); the deposit of v is
+// split off into k_deposit_vec, which works like the counting-density deposit: an
+// LDS window per tile in signed 64-bit fixed point with a per-tile, per-component
+// scale (so the window sums carry ~41 bits relative to the tile's largest |v|), then
+// one global atomic per non-empty window cell.
+constexpr int AX = 4, AY = 8, AZ = 32;
+constexpr int APP = AX * AY * AZ / kBlock;
+constexpr int ACAP = 4096;
+constexpr int AWF = 16;
+
+__global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __restrict__ force, const float* __restrict__ pos,
+                                                             int n, float kick, float drift, float* __restrict__ lam_pos,
+                                                             float* __restrict__ lam_mom) {
+  __shared__ float win[3 * ACAP];
+  __shared__ int wlo[4][3], whi[4][3];
+  __shared__ float wsum[4][3];
+  const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  const int tpy = n / AY, tpz = n / AZ;
+  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
+  const int org[3] = {ti * AX, tk * AY, tl * AZ};
+  const int t = threadIdx.x;
+  float x[APP], y[APP], z[APP];
+  int64_t jj[APP];
+#pragma unroll
+  for (int p = 0; p < APP; ++p) {
+    const int loc = t + kBlock * p;
+    const int li = loc / (AY * AZ), lk = (loc / AZ) % AY, ll = loc % AZ;
+    jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
+    x[p] = wrap(pos[jj[p]], n);
+    y[p] = wrap(pos[np + jj[p]], n);
+    z[p] = wrap(pos[2 * np + jj[p]], n);
+  }
+  const TileWindow tw = tile_window<APP>(x, y, z, n, org, ACAP, AWF, AX * AY * AZ, wlo, whi, wsum);
+  const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
+  const int sy = W2, sx = W1 * W2;
+  const int wtot = W0 * W1 * W2;
+  for (int c = t; c < wtot; c += kBlock) {
+    const int a = c / sx, b = (c / sy) % W1, cz = c % sy;
+    const int64_t idx = ((int64_t)fold(org[0] + tw.o[0] + a, n) * n + fold(org[1] + tw.o[1] + b, n)) * n +
+                        fold(org[2] + tw.o[2] + cz, n);
+    win[c] = force[idx];
+    win[ACAP + c] = force[np + idx];
+    win[2 * ACAP + c] = force[2 * np + idx];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < APP; ++p) {
+    const int64_t j = jj[p];
+    float lx[3], lp[3], v[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lx[d] = lam_pos[d * np + j];
+      lp[d] = lam_mom[d * np + j] + drift * lx[d];
+      v[d] = kick * lp[d];
+    }
+    const Axis<float> ax = cic_axis(x[p], n), ay = cic_axis(y[p], n), az = cic_axis(z[p], n);
+    const int rx = idiff(ax.i0, org[0], n) - tw.o[0], ry = idiff(ay.i0, org[1], n) - tw.o[1],
+              rz = idiff(az.i0, org[2], n) - tw.o[2];
+    const bool inside = rx >= 0 && rx <= W0 - 2 && ry >= 0 && ry <= W1 - 2 && rz >= 0 && rz <= W2 - 2;
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+      float s;
+      if (inside) {
+        const int w = (rx + bx) * sx + (ry + by) * sy + rz + bz;
+        s = v[0] * win[w] + v[1] * win[ACAP + w] + v[2] * win[2 * ACAP + w];
+      } else {
+        const int64_t idx = (bx ? ax.i1 : ax.i0) * n2 + (int64_t)(by ? ay.i1 : ay.i0) * n + (bz ? az.i1 : az.i0);
+        s = v[0] * force[idx] + v[1] * force[np + idx] + v[2] * force[2 * np + idx];
+      }
+      const float wx = bx ? ax.w1 : ax.w0, wy = by ? ay.w1 : ay.w0, wz = bz ? az.w1 : az.w0;
+      gx += (bx ? s : -s) * wy * wz;
+      gy += (by ? s : -s) * wx * wz;
+      gz += (bz ? s : -s) * wx * wy;
+    }
+    lam_mom[j] = lp[0];
+    lam_mom[np + j] = lp[1];
+    lam_mom[2 * np + j] = lp[2];
+    lam_pos[j] = lx[0] + gx;
+    lam_pos[np + j] = lx[1] + gy;
+    lam_pos[2 * np + j] = lx[2] + gz;
+  }
+}
+
+constexpr int VX = 8, VY = 8, VZ = 16;
+constexpr int VPP = VX * VY * VZ / kBlock;
+constexpr int VCAP = 4096;
+constexpr int VWF = 16;
+// g[d] += sum_p W(x_p - c) v_{p,d}, v = kick * lam_mom, one tile per block: the
+// window is accumulated in LDS and added to g with one global atomic per non-empty
+// cell; particles outside their tile's window go to global atomics directly.
+__global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict__ pos, const float* __restrict__ lam_mom,
+                                                        float kick, int n, float* __restrict__ g) {
+  __shared__ unsigned long long win[VCAP];
+  __shared__ int wlo[4][3], whi[4][3];
+  __shared__ float wsum[4][3];
+  __shared__ float wmax[4][3];
+  const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  const int tpy = n / VY, tpz = n / VZ;
+  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
+  const int org[3] = {ti * VX, tk * VY, tl * VZ};
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  float x[VPP], y[VPP], z[VPP], v[3][VPP];
+  int64_t jj[VPP];
+  float vmax[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int p = 0; p < VPP; ++p) {
+    const int loc = t + kBlock * p;
+    const int li = loc / (VY * VZ), lk = (loc / VZ) % VY, ll = loc % VZ;
+    jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
+    x[p] = wrap(pos[jj[p]], n);
+    y[p] = wrap(pos[np + jj[p]], n);
+    z[p] = wrap(pos[2 * np + jj[p]], n);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      v[d][p] = kick * lam_mom[d * np + jj[p]];
+      vmax[d] = fmaxf(vmax[d], fabsf(v[d][p]));
+    }
+  }
+  const TileWindow tw = tile_window<VPP>(x, y, z, n, org, VCAP, VWF, VX * VY * VZ, wlo, whi, wsum);
+  // per-component fixed-point scale 2^(40 - e), |v| < 2^e over the tile
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    for (int off = 32; off > 0; off >>= 1) vmax[d] = fmaxf(vmax[d], __shfl_xor(vmax[d], off, 64));
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) wmax[wave][d] = vmax[d];
+  }
+  __syncthreads();
+  double scale[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float m = fmaxf(fmaxf(wmax[0][d], wmax[1][d]), fmaxf(wmax[2][d], wmax[3][d]));
+    int e = 0;
+    (void)frexpf(m, &e);  // m < 2^e
+    scale[d] = m > 0.f ? ldexp(1.0, 40 - e) : 0.0;
+  }
+  const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
+  const int wtot = W0 * W1 * W2;
+  const int sy = W2, sx = W1 * W2;
+  // which particles fit the window
+  bool inside[VPP];
+  int base[VPP];
+  Axis<float> axs[VPP], ays[VPP], azs[VPP];
+#pragma unroll
+  for (int p = 0; p < VPP; ++p) {
+    axs[p] = cic_axis(x[p], n);
+    ays[p] = cic_axis(y[p], n);
+    azs[p] = cic_axis(z[p], n);
+    const int rx = idiff(axs[p].i0, org[0], n) - tw.o[0], ry = idiff(ays[p].i0, org[1], n) - tw.o[1],
+              rz = idiff(azs[p].i0, org[2], n) - tw.o[2];
+    inside[p] = rx >= 0 && rx <= W0 - 2 && ry >= 0 && ry <= W1 - 2 && rz >= 0 && rz <= W2 - 2;
+    base[p] = inside[p] ? rx * sx + ry * sy + rz : 0;
+    if (!inside[p]) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+        const int64_t idx = (bx ? axs[p].i1 : axs[p].i0) * n2 + (int64_t)(by ? ays[p].i1 : ays[p].i0) * n +
+                            (bz ? azs[p].i1 : azs[p].i0);
+        const float w = (bx ? axs[p].w1 : axs[p].w0) * (by ? ays[p].w1 : ays[p].w0) * (bz ? azs[p].w1 : azs[p].w0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) atomic_add(g + d * np + idx, w * v[d][p]);
+      }
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    for (int c = t; c < wtot; c += kBlock) win[c] = 0ull;
+    __syncthreads();
+    if (scale[d] > 0.0) {
+#pragma unroll
+      for (int p = 0; p < VPP; ++p) {
+        if (!inside[p]) continue;
+        const double vs = (double)v[d][p] * scale[d];
+        const float wxy[4] = {axs[p].w0 * ays[p].w0, axs[p].w0 * ays[p].w1, axs[p].w1 * ays[p].w0,
+                              axs[p].w1 * ays[p].w1};
+        const int off[4] = {0, sy, sx, sx + sy};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          atomicAdd(win + base[p] + off[q], (unsigned long long)llrint((double)(wxy[q] * azs[p].w0) * vs));
+          atomicAdd(win + base[p] + off[q] + 1, (unsigned long long)llrint((double)(wxy[q] * azs[p].w1) * vs));
+        }
+      }
+    }
+    __syncthreads();
+    if (scale[d] > 0.0) {
+      const double inv = 1.0 / scale[d];
+      float* gd = g + (int64_t)d * np;
+      for (int c = t; c < wtot; c += kBlock) {
+        const long long q = (long long)win[c];
+        if (q == 0) continue;
+        const int a = c / sx, b = (c / sy) % W1, cz = c % sy;
+        const int64_t idx = ((int64_t)fold(org[0] + tw.o[0] + a, n) * n + fold(org[1] + tw.o[1] + b, n)) * n +
+                            fold(org[2] + tw.o[2] + cz, n);
+        atomic_add(gd + idx, (float)((double)q * inv));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // lam_pos (+)= scale * grad_x sum_c W(x - c) h(c): the adjoint of the CIC deposit
 // applied to a cotangent mesh h.
 template <typename T>
@@ -135,8 +340,23 @@ __global__ void __launch_bounds__(kBlock) k_ic_lattice_adj(const T* __restrict__
 
 int launch_adj_gather_kdk(const pm_plan* p, const void* force, const void* pos, int64_t np, double kick, double drift,
                           void* lam_pos, void* lam_mom, void* g, hipStream_t s) {
-  ProfScope ps(p, PK_ADJ_GATHER, s);
   if (np <= 0) return PM_OK;
+  const int n = p->n;
+  if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % AZ == 0) {
+    {
+      ProfScope ps(p, PK_ADJ_GATHER, s);
+      const unsigned tiles = (unsigned)((n / AX) * (n / AY) * (n / AZ));
+      hipLaunchKernelGGL(k_adj_gather_tiled, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(force),
+                         static_cast<const float*>(pos), n, (float)kick, (float)drift, static_cast<float*>(lam_pos),
+                         static_cast<float*>(lam_mom));
+    }
+    ProfScope ps(p, PK_ADJ_DEPOSIT, s);
+    const unsigned tiles = (unsigned)((n / VX) * (n / VY) * (n / VZ));
+    hipLaunchKernelGGL(k_deposit_vec, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(pos),
+                       static_cast<const float*>(lam_mom), (float)kick, n, static_cast<float*>(g));
+    return hip_check(hipGetLastError(), "adjoint gather-kick-drift");
+  }
+  ProfScope ps(p, PK_ADJ_GATHER, s);
   if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_adj_gather_kdk<float>, dim3(nblocks(np)), dim3(kBlock), 0, s,
                        static_cast<const float*>(force), static_cast<const float*>(pos), np, p->n, (float)kick,

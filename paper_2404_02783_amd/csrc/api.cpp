@@ -54,7 +54,7 @@ static const char* kProfNames[PK_COUNT] = {
     "fill",          "deposit",        "fft_r2c_rows",   "fft_cols_fwd_axis1", "fft_cols_fwd_axis0",
     "fft_solve_axis0", "fft_cols_inv_axis0", "fft_cols_inv_axis1", "fft_c2r_rows", "gather",
     "gather_kick_drift", "combine",    "ic",             "pk",                 "bk",
-    "adjoint_gather_kick_drift", "grad_gather", "adjoint_symbol"};
+    "adjoint_gather_kick_drift", "adjoint_deposit", "grad_gather", "adjoint_symbol"};
 
 struct ProfRec {
   int kind;
@@ -375,7 +375,7 @@ int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_param
   if (np == 0) return PM_OK;
   PM_TRY(launch_fill(p, g, 3 * n3, 0.0, s));
   PM_TRY(launch_adj_gather_kdk(p, force, pos, np, st->kick, st->drift, lam_pos, lam_mom, g, s));
-  for (int d = 0; d < 3; ++d) PM_TRY(fft3_r2c(p, g + d * mesh_bytes, cbuf(p, d), s));
+  PM_TRY(fft3_r2c_n(p, 3, g, cbuf(p, 0), s));  // the three components in one set of launches
   PM_TRY(launch_div_newton(p, st->solve.grad, 1.5 * st->solve.omega_m / (double)n3, s));
   PM_TRY(fft3_c2r(p, 1, cbuf(p, 0), 0, g, s));
   return launch_grad_gather(p, g, pos, np, (double)n3 / (double)np, lam_pos, true, s);

@@ -251,9 +251,7 @@ int pm_ic_zeldovich_adjoint(pm_plan* p, const pm_ic_params* ic, const void* lam_
   const double fac = a * a * pm_cosmo_hubble_e(&ic->cosmo, a) * pm_cosmo_growth_rate(&ic->cosmo, a);
   int rc = launch_ic_lattice_adj(p, lam_pos, lam_mom, disp_scratch, fac, s);
   if (rc) return rc;
-  const size_t mesh_bytes = (size_t)p->n * p->n * p->n * p->esize;
-  for (int d = 0; d < 3 && rc == PM_OK; ++d)
-    rc = fft3_r2c(p, static_cast<const char*>(disp_scratch) + d * mesh_bytes, cbuf(p, d), s);
+  rc = fft3_r2c_n(p, 3, disp_scratch, cbuf(p, 0), s);  // the three components in one set of launches
   if (rc) return rc;
   rc = launch_ic_symbol(p, ic_symbol_of(p, ic, 1, 1.0), true, s);
   if (rc) return rc;

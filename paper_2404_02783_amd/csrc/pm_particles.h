@@ -50,4 +50,78 @@ __device__ __forceinline__ int idiff(int a, int b, int n) {
   return d;
 }
 
+// Window of a Lagrangian tile (one 256-thread block, PP particles per thread): the
+// bounding box of the particles' CIC base cells floor(x), relative to the tile
+// origin `org` (minimum image), widened by one cell so the +1 CIC neighbours fit:
+// cells [o_d, o_d + W_d).  If its volume exceeds `cap` cells, a side^3 box around the
+// mean base cell is used instead.  Particles with x < 0 are skipped.  Block-wide
+// (every thread must call); wlo/whi/wsum are __shared__ [4][3] scratch.
+struct TileWindow {
+  int o[3], W[3];
+};
+template <int PP>
+__device__ __forceinline__ TileWindow tile_window(const float (&x)[PP], const float (&y)[PP], const float (&z)[PP],
+                                                  int n, const int (&org)[3], int cap, int side, int count,
+                                                  int (*wlo)[3], int (*whi)[3], float (*wsum)[3]) {
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+  float sum[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int p = 0; p < PP; ++p) {
+    if (x[p] < 0.f) continue;
+    const int r[3] = {idiff((int)floorf(x[p]), org[0], n), idiff((int)floorf(y[p]), org[1], n),
+                      idiff((int)floorf(z[p]), org[2], n)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], r[d]);
+      hi[d] = max(hi[d], r[d]);
+      sum[d] += float(r[d]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], off, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], off, 64));
+      sum[d] += __shfl_xor(sum[d], off, 64);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      wlo[wave][d] = lo[d];
+      whi[wave][d] = hi[d];
+      wsum[wave][d] = sum[d];
+    }
+  }
+  __syncthreads();
+  TileWindow w;
+  int64_t vol = 1;
+  float mean[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int a = wlo[0][d], b = whi[0][d];
+    float s = wsum[0][d];
+    for (int k = 1; k < 4; ++k) {
+      a = min(a, wlo[k][d]);
+      b = max(b, whi[k][d]);
+      s += wsum[k][d];
+    }
+    if (b < a) a = b = 0;  // no particle: an empty 2-cell box at the origin
+    w.o[d] = a;
+    w.W[d] = b - a + 2;
+    vol *= w.W[d];
+    mean[d] = s / float(count);
+  }
+  if (vol > cap) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      w.o[d] = (int)rintf(mean[d]) - side / 2;
+      w.W[d] = side;
+    }
+  }
+  __syncthreads();  // the scratch may be reused after return
+  return w;
+}
+
 }  // namespace pm

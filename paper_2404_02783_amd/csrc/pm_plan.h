@@ -28,6 +28,7 @@ enum ProfKind {
   PK_PK,
   PK_BK,
   PK_ADJ_GATHER,
+  PK_ADJ_DEPOSIT,
   PK_GRAD_GATHER,
   PK_ADJ_SYMBOL,
   PK_COUNT

@@ -45,6 +45,18 @@ def _randn(shape, seed):
 @pytest.mark.parametrize("n,amp", [(16, 0.8), (32, 3.0)])
 @pytest.mark.parametrize("cached_force", [True, False])
 def test_step_adjoint_matches_oracle_vjp(dt, n, amp, cached_force):
+    _step_adjoint_case(dt, n, amp, cached_force)
+
+
+@pytest.mark.parametrize("amp", [0.8, 6.0, 20.0])
+def test_step_adjoint_lattice_tiles(amp):
+    """A full 128^3 FP32 lattice takes the tiled adjoint gather and the tiled
+    fixed-point deposit of v; amplitudes 6 and 20 overflow the LDS windows, so the
+    fallback boxes and the direct global paths run too."""
+    _step_adjoint_case(torch.float32, 128, amp, True)
+
+
+def _step_adjoint_case(dt, n, amp, cached_force):
     dev = _dev()
     kick, drift = 0.37, 0.55
     pos0 = torch.from_numpy(si.lattice_jitter_particles(n, 11, amp))

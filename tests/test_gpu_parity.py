@@ -50,15 +50,19 @@ DTYPES = [torch.float32, torch.float64]
 @pytest.mark.parametrize("dt", DTYPES)
 @pytest.mark.parametrize("n,np_,kind", [(32, 32 ** 3, "lattice"), (64, 100003, "clustered"), (16, 777, "uniform"),
                                          (128, 128 ** 3, "lattice"), (128, 128 ** 3, "lattice_far"),
-                                         (256, 256 ** 3, "lattice")])
+                                         (128, 128 ** 3, "lattice_vfar"), (256, 256 ** 3, "lattice")])
 def test_deposit(dt, n, np_, kind):
-    # N^3 lattice runs at N >= 128 take the LDS-window path in FP32; "lattice_far" moves
-    # particles up to 5 cells, beyond the window halo, so the global fallback runs too.
+    # N^3 lattice runs at N >= 128 take the LDS-window path in FP32 (tiles in 64 colour
+    # classes, windows added without atomics); "lattice_far" moves particles up to 5
+    # cells, so tile windows exceed the LDS capacity and the overflow list runs too;
+    # "lattice_vfar" moves them up to 20 cells, beyond the colour confinement box.
     dev = _dev()
     if kind == "lattice":
         x = si.lattice_jitter_particles(n, 3, 0.7, dtype=np.float64)
     elif kind == "lattice_far":
         x = si.lattice_jitter_particles(n, 4, 5.0, dtype=np.float64)
+    elif kind == "lattice_vfar":
+        x = si.lattice_jitter_particles(n, 6, 20.0, dtype=np.float64)
     elif kind == "clustered":
         x = si.clustered_particles(n, np_, 4)
     else:
@@ -72,6 +76,20 @@ def test_deposit(dt, n, np_, kind):
     want = cic.deposit_delta(pos.double().cpu(), n)
     assert rel_l2(d, want) < _tol(dt)
     pm.pm_check(plan)
+
+
+def test_deposit_batched_boxes():
+    """A batch of three 128^3 lattice boxes (coloured path) against the oracle per box."""
+    dev = _dev()
+    n = 128
+    xs = [si.lattice_jitter_particles(n, 40 + b, 0.7 + 3 * b, dtype=np.float64) for b in range(3)]
+    pos = torch.from_numpy(np.stack(xs)).to(torch.float32)
+    pos[pos >= n] = 0
+    plan = pm.Plan(n, 100.0, torch.float32, dev, batch=3)
+    d = pm.pm_deposit(plan, pos.to(dev).contiguous())
+    torch.cuda.synchronize()
+    for b in range(3):
+        assert rel_l2(d[b], cic.deposit_delta(pos[b].double(), n)) < F32_TOL
 
 
 @pytest.mark.parametrize("dt", DTYPES)
