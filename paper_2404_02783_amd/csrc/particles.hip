@@ -237,25 +237,27 @@ __device__ __forceinline__ T min_image(T d, int n) {
   return s - fn * floor(s / fn) - T(0.5) * fn;
 }
 
+// Grid (ceil(nf / 256), nf, nf): thread (x, y, z) handles fine particle
+// (blockIdx.z, blockIdx.y, x) with 32-bit index arithmetic (nf <= 4096).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, const T* __restrict__ xn, int nc,
                                                     const T* __restrict__ xf, int nf, T* __restrict__ out) {
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t j = blk * kBlock + threadIdx.x;
+  const int jz = blockIdx.x * kBlock + threadIdx.x;
+  if (jz >= nf) return;
+  const int jf[3] = {(int)blockIdx.z, (int)blockIdx.y, jz};
   const int64_t npf = (int64_t)nf * nf * nf;
-  if (j >= npf) return;
+  const int64_t j = ((int64_t)jf[0] * nf + jf[1]) * nf + jz;
   const int64_t npc = (int64_t)nc * nc * nc;
-  const int jf[3] = {(int)(j / ((int64_t)nf * nf)), (int)((j / nf) % nf), (int)(j % nf)};
   int i0[3], i1[3];
   T t[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     // u = ((2j+1) nc - nf) / (2 nf): integer floor division and exact remainder
-    const int64_t num = (int64_t)(2 * jf[d] + 1) * nc - nf;
-    const int64_t den = 2 * (int64_t)nf;
-    int64_t q = num >= 0 ? num / den : -((-num + den - 1) / den);
-    const int64_t rem = num - q * den;
-    i0[d] = (int)((q % nc + nc) % nc);
+    const int num = (2 * jf[d] + 1) * nc - nf;
+    const int den = 2 * nf;
+    const int q = num >= 0 ? num / den : -((-num + den - 1) / den);
+    const int rem = num - q * den;
+    i0[d] = q < 0 ? q + nc : (q >= nc ? q - nc : q);
     i1[d] = i0[d] + 1 == nc ? 0 : i0[d] + 1;
     t[d] = T(rem) / T(den);
   }
@@ -359,13 +361,13 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
 
 int launch_combine(const void* x_gr, const void* x_n, int nc, const void* x_f, int nf, int dtype, void* x_out,
                    hipStream_t s) {
-  const int64_t npf = (int64_t)nf * nf * nf;
+  const dim3 grid((unsigned)((nf + kBlock - 1) / kBlock), (unsigned)nf, (unsigned)nf);
   if (dtype == PM_F32)
-    hipLaunchKernelGGL(k_combine<float>, dim3(nblocks(npf)), dim3(kBlock), 0, s, static_cast<const float*>(x_gr),
+    hipLaunchKernelGGL(k_combine<float>, grid, dim3(kBlock), 0, s, static_cast<const float*>(x_gr),
                        static_cast<const float*>(x_n), nc, static_cast<const float*>(x_f), nf,
                        static_cast<float*>(x_out));
   else
-    hipLaunchKernelGGL(k_combine<double>, dim3(nblocks(npf)), dim3(kBlock), 0, s, static_cast<const double*>(x_gr),
+    hipLaunchKernelGGL(k_combine<double>, grid, dim3(kBlock), 0, s, static_cast<const double*>(x_gr),
                        static_cast<const double*>(x_n), nc, static_cast<const double*>(x_f), nf,
                        static_cast<double*>(x_out));
   return hip_check(hipGetLastError(), "displacement combine");

@@ -23,7 +23,8 @@ import torch
 from . import (FIDUCIAL, ICParams, PM_GRAD_SPECTRAL, Plan, StepParams, kdk_factors, newton_params, pk_adjoint,
                pk_estimate, pm_deposit, pm_ic_zeldovich, pm_ic_zeldovich_adjoint, pm_step, pm_step_adjoint)
 
-__all__ = ["Schedule", "ForwardTape", "forward", "backward", "PowerSpectrumModel", "power_spectrum_model"]
+__all__ = ["Schedule", "ForwardTape", "forward", "backward", "GraphedModel", "PowerSpectrumModel",
+           "power_spectrum_model"]
 
 
 @dataclass
@@ -102,6 +103,85 @@ def backward(tape: ForwardTape, dpk: torch.Tensor) -> torch.Tensor:
                             mesh_scratch=scratch)
             xs[j - s0] = fs[j - s0] = None
     return pm_ic_zeldovich_adjoint(plan, tape.ic, lam_pos, lam_mom)
+
+
+class GraphedModel:
+    """The same forward model and reverse pass with every buffer allocated once and
+    both passes captured as HIP graphs (``torch.cuda.CUDAGraph``), for sizes where
+    launch and host overheads dominate (e.g. 128^3).  ``forward(noise)`` returns P(k);
+    ``backward(dpk)`` returns dL/dnoise for the last forward.  Memory is that of the
+    eager model with every checkpoint and one segment resident."""
+
+    def __init__(self, plan: Plan, ic: ICParams, schedule: Schedule, n_bins: int, ckpt_every: int = 5):
+        self.plan, self.ic, self.n_bins, self.ckpt = plan, ic, n_bins, ckpt_every
+        self.steps = schedule.cycles()
+        n3 = plan.n ** 3
+        dev, dt = plan.device, plan.dtype
+        part = lambda: torch.empty((3, n3), dtype=dt, device=dev)  # noqa: E731
+        self.noise = plan.mesh()
+        self.pos, self.mom, self.disp, self.force = part(), part(), plan.mesh(3), plan.mesh(3)
+        self.delta = plan.mesh()
+        self.starts = list(range(0, len(self.steps), ckpt_every))
+        self.ckpts = {s0: (part(), part()) for s0 in self.starts}
+        self.seg_x = [part() for _ in range(ckpt_every)]
+        self.seg_f = [plan.mesh(3) for _ in range(ckpt_every)]
+        self.wpos, self.wmom = part(), part()
+        self.lam_pos, self.lam_mom = part(), part()
+        self.scratch = torch.empty(3 * n3, dtype=dt, device=dev)
+        self.dpk = torch.zeros(n_bins, dtype=torch.float64, device=dev)
+        self.lam_noise = plan.mesh()
+        self.out = None
+        self.g_fwd = self.g_bwd = None
+
+    def _forward(self):
+        pm_ic_zeldovich(self.plan, self.noise, self.ic, self.disp, self.pos, self.mom)
+        for j, st in enumerate(self.steps):
+            if j in self.ckpts:
+                self.ckpts[j][0].copy_(self.pos)
+                self.ckpts[j][1].copy_(self.mom)
+            pm_step(self.plan, self.pos, self.mom, st, self.force)
+        pm_deposit(self.plan, self.pos, self.delta)
+        self.out = pk_estimate(self.plan, self.delta, self.n_bins)
+
+    def _backward(self):
+        plan = self.plan
+        pk_adjoint(plan, self.pos, self.n_bins, self.dpk, self.lam_pos)
+        self.lam_mom.zero_()
+        nsteps = len(self.steps)
+        for s0 in reversed(self.starts):
+            s1 = min(s0 + self.ckpt, nsteps)
+            self.wpos.copy_(self.ckpts[s0][0])
+            self.wmom.copy_(self.ckpts[s0][1])
+            for j in range(s0, s1):
+                self.seg_x[j - s0].copy_(self.wpos)
+                pm_step(plan, self.wpos, self.wmom, self.steps[j], self.seg_f[j - s0])
+            for j in reversed(range(s0, s1)):
+                pm_step_adjoint(plan, self.seg_x[j - s0], self.steps[j], self.lam_pos, self.lam_mom,
+                                force=self.seg_f[j - s0], mesh_scratch=self.scratch)
+        pm_ic_zeldovich_adjoint(plan, self.ic, self.lam_pos, self.lam_mom, self.disp, self.lam_noise)
+
+    def capture(self):
+        """Warm both passes eagerly, then capture each into its own graph."""
+        self._forward()
+        self._backward()
+        torch.cuda.synchronize()
+        self.g_fwd = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.g_fwd):
+            self._forward()
+        self.g_bwd = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.g_bwd):
+            self._backward()
+        return self
+
+    def forward(self, noise):
+        self.noise.copy_(noise.reshape(self.noise.shape))
+        self.g_fwd.replay()
+        return self.out[1]
+
+    def backward(self, dpk):
+        self.dpk.copy_(dpk)
+        self.g_bwd.replay()
+        return self.lam_noise
 
 
 class PowerSpectrumModel(torch.autograd.Function):
