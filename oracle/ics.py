@@ -69,6 +69,26 @@ def linear_delta_k(noise: torch.Tensor, p: ICParams) -> torch.Tensor:
     return torch.where(keep, w_hat * amp, torch.zeros_like(w_hat))
 
 
+def truncate_noise(noise: torch.Tensor, n_coarse: int) -> torch.Tensor:
+    """White noise of a coarse run that shares the fine run's random phases (Secs. 2
+    and 3 use the same initial phases for every simulation; reading for runs of
+    different resolution): keep the fine modes with |n_i| < N_c/2 on every axis,
+    scale by (N_c/N_f)^(3/2) so that the physical field (V/N^3) delta_hat is the same
+    on the shared modes, drop the coarse Nyquist planes, transform back."""
+    nf = noise.shape[-1]
+    if nf % n_coarse != 0 or n_coarse > nf:
+        raise ValueError("n_coarse must divide the fine mesh size")
+    w_hat = fourier.rfft3(noise.to(torch.float64))
+    out = torch.zeros((n_coarse, n_coarse, n_coarse // 2 + 1), dtype=torch.complex128)
+    h = n_coarse // 2
+    idx = torch.cat([torch.arange(0, h), torch.arange(nf - h + 1, nf)])          # n in (-N_c/2, N_c/2)
+    cidx = torch.cat([torch.arange(0, h), torch.arange(n_coarse - h + 1, n_coarse)])
+    sub = w_hat[idx][:, idx][:, :, :h]                                          # n_z in [0, N_c/2)
+    out[cidx.view(-1, 1, 1), cidx.view(1, -1, 1), torch.arange(h).view(1, 1, -1)] = sub
+    out *= (n_coarse / nf) ** 1.5
+    return fourier.irfft3(out, n_coarse)
+
+
 def _lattice_phase(n: int) -> torch.Tensor:
     kx, ky, kz = fourier.kgrid(n)
     ph = 0.5 * (kx + ky + kz)

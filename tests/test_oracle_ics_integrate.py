@@ -271,3 +271,45 @@ def test_gauge_shift_is_constant_in_time(a):
     g, gp = ics.gr_shift_coefficients(p, a)
     assert g == pytest.approx(g0, rel=1e-9)
     assert abs(gp) < 1e-8 * g
+
+
+def test_truncated_noise_keeps_the_physical_field_on_shared_modes():
+    """Reading for runs of different resolution sharing their phases: delta_L(k) of the
+    coarse run equals that of the fine run on every mode both grids resolve."""
+    nf, nc, box = 32, 8, 500.0
+    w = torch.from_numpy(si.white_noise(nf, 21))
+    wc = ics.truncate_noise(w, nc)
+    power = cm.eh98_normalised(cm.Cosmo(n_s=0.965), 0.965, 0.81)
+    pf = ics.ICParams(n=nf, box=box, a_init=0.02, power=power)
+    pc = ics.ICParams(n=nc, box=box, a_init=0.02, power=power)
+    df = ics.linear_delta_k(w, pf) * (box ** 3 / nf ** 3)
+    dc = ics.linear_delta_k(wc, pc) * (box ** 3 / nc ** 3)
+    h = nc // 2
+    for ix in list(range(0, h)) + list(range(nc - h + 1, nc)):
+        for iy in list(range(0, h)) + list(range(nc - h + 1, nc)):
+            fx = ix if ix < h else ix - nc + nf
+            fy = iy if iy < h else iy - nc + nf
+            a, b = dc[ix, iy, :h], df[fx, fy, :h]
+            assert torch.allclose(a, b, rtol=1e-12, atol=1e-12 * float(df.abs().max()))
+    # the coarse Nyquist planes carry nothing
+    assert float(dc[h].abs().max()) == 0.0 and float(dc[:, :, h].abs().max()) == 0.0
+
+
+def test_truncated_noise_identity_and_variance():
+    nf = 16
+    w = torch.from_numpy(si.white_noise(nf, 22))
+    same = ics.truncate_noise(w, nf)
+    # at equal resolution only the Nyquist planes are removed: the rest of the field is unchanged
+    wh = torch.fft.rfftn(w)
+    wh[nf // 2] = 0
+    wh[:, nf // 2] = 0
+    wh[:, :, nf // 2] = 0
+    assert torch.allclose(same, torch.fft.irfftn(wh, s=(nf,) * 3), atol=1e-13)
+    # unit-variance fine noise -> variance (1 - 1/N_c)^3 per coarse cell in expectation
+    nc = 8
+    v = [float(ics.truncate_noise(torch.from_numpy(si.white_noise(nf, 100 + s)), nc).var(unbiased=False))
+         for s in range(40)]
+    want = (1 - 1 / nc) ** 3
+    mean = sum(v) / len(v)
+    sd = (sum((x - mean) ** 2 for x in v) / (len(v) - 1)) ** 0.5 / len(v) ** 0.5
+    assert abs(mean - want) < 4 * sd + 1e-3
