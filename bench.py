@@ -131,7 +131,7 @@ def adjoint_ratio(pm, plan, noise, icp, n_cycles: int, ckpt: int, n_bins: int):
     return t1 - t0, t2 - t1, prof
 
 
-def config3_estimators(pm, plan, pos, n_bins=256):
+def config3_estimators(pm, plan, pos, fine_noise, n_bins=256):
     """Timings of the estimator and combination calls of the displacement-combination
     configuration on the final 1024^3 positions: deposit + P(k) in 256 bins, B(k)
     on 64 triangles (32 equilateral k = m*16 k_f, 32 squeezed with k3 = 4 k_f; shell
@@ -164,7 +164,7 @@ def config3_estimators(pm, plan, pos, n_bins=256):
     # combination: a coarse 256^3 Newtonian/Poisson-gauge pair (L = 4000 Mpc/h, 50 log steps)
     nc = 256
     cplan = pm.Plan(nc, plan.box, plan.dtype, plan.device)
-    noise = torch.from_numpy(si.white_noise(nc, 3003, dtype=np.float32)).to(plan.device)
+    noise = pm.pm_noise_truncate(plan, fine_noise, cplan)  # same phases as the fine run
     icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=0.02,
                       a_norm=1.0, cosmo=pm.FIDUCIAL)
     xn, pn, xg, pg = (torch.empty((3, nc ** 3), dtype=plan.dtype, device=plan.device) for _ in range(4))
@@ -187,8 +187,8 @@ def config3_estimators(pm, plan, pos, n_bins=256):
     dt = time.perf_counter() - t0
     out["combine_ms"] = round(dt * 1e3, 2)
     out["combine_GBps_alg"] = round(24 * n ** 3 / dt / 1e9, 1)  # read x_fine, write x_out
-    out["note"] = ("coarse noise is an independent 256^3 seed (timing only); B(k) keeps 8 shell fields resident "
-                   "and recomputes evicted shells")
+    out["note"] = ("coarse noise is the Fourier truncation of the fine noise (shared phases); B(k) keeps 8 shell "
+                   "fields resident and recomputes evicted shells")
     del x_out, xn, pn, xg, pg, disp, cplan, delta
     return out
 
@@ -271,10 +271,32 @@ def ensemble_leg(pm):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     worst = max(float(((a - b).abs() / b.abs().clamp_min(1e-30)).max()) for a, b in zip(pk_batched, pk_seq))
-    return {"boxes": sum(len(g.seeds) for g in groups), "graph_s": round(t_graph, 4),
-            "batched_eager_s": round(t_eager, 4), "sequential_s": round(t_seq, 4),
-            "speedup_graph_vs_sequential": round(t_seq / t_graph, 2),
-            "max_rel_pk_diff_batched_vs_sequential": worst}
+    out = {"boxes": sum(len(g.seeds) for g in groups), "graph_s": round(t_graph, 4),
+           "batched_eager_s": round(t_eager, 4), "sequential_s": round(t_seq, 4),
+           "speedup_graph_vs_sequential": round(t_seq / t_graph, 2),
+           "max_rel_pk_diff_batched_vs_sequential": worst}
+    del ens, plans, noises
+    # the same comparison for 64 small boxes only (64^3, L = 500 Mpc/h), where launches dominate
+    small = [ensemble.Group(64, 500.0, list(range(200, 264)))]
+    ens = ensemble.Ensemble(small, noise_fn, 0.02, 1.0, 30, torch.float32, dev)
+    ens.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.replay()
+    torch.cuda.synchronize()
+    ts_graph = time.perf_counter() - t0
+    plans = {(64, 500.0): pm.Plan(64, 500.0, torch.float32, dev)}
+    noises = {s: ens.states[0].noise[i] for i, s in enumerate(small[0].seeds)}
+    ensemble.run_sequential([ensemble.Group(64, 500.0, [200])], noise_fn, 0.02, 1.0, 30, torch.float32, dev, plans,
+                            noises)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ensemble.run_sequential(small, noise_fn, 0.02, 1.0, 30, torch.float32, dev, plans, noises)
+    torch.cuda.synchronize()
+    ts_seq = time.perf_counter() - t0
+    out["small_boxes_64x64^3"] = {"graph_s": round(ts_graph, 4), "sequential_s": round(ts_seq, 4),
+                                  "speedup_graph_vs_sequential": round(ts_seq / ts_graph, 2)}
+    return out
 
 
 def main():
@@ -395,7 +417,7 @@ def main():
     }
     if not args.no_extras:
         print("[bench] estimators and combination at 1024^3", file=sys.stderr, flush=True)
-        out["config3"] = config3_estimators(pm, plan, pos)
+        out["config3"] = config3_estimators(pm, plan, pos, noise)
     if args.adjoint_cycles > 0:
         del run, pos, mom
         torch.cuda.synchronize()

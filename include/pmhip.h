@@ -275,6 +275,16 @@ int pm_ic_zeldovich(pm_plan* plan, const void* noise, const pm_ic_params* ic, vo
 int pm_ic_zeldovich_adjoint(pm_plan* plan, const pm_ic_params* ic, const void* lam_pos, const void* lam_mom,
                             void* disp_scratch, void* lam_noise, void* stream);
 
+/* White noise of a coarser run sharing the fine run's random phases (Secs. 2 and 3:
+ * every simulation starts from the same phases; reading for runs of different
+ * resolution).  DFT(noise_coarse)(n) = DFT(noise_fine)(n) (Nc/Nf)^(3/2) for every mode
+ * with all |n_i| < Nc/2, zero on the coarse Nyquist planes, so that the physical
+ * linear field (V/N^3) delta_hat is the same on the shared modes.  noise_fine:
+ * [Nf][Nf][Nf] (read only); noise_coarse: [Nc][Nc][Nc] (written).  Both plans
+ * single-box, same dtype, Nc dividing Nf (PM_ERR_ARG otherwise); uses both plans'
+ * workspaces. */
+int pm_noise_truncate(pm_plan* fine, const void* noise_fine, pm_plan* coarse, void* noise_coarse, void* stream);
+
 /* Poisson-gauge partner set of pm_ic_zeldovich's output (linear reading of eqs.
  * physical_density, b1, bgr): xi_hat = i k g(a_init) delta_L_hat / k^4 on the same
  * lattice with g = (3f + (9/2) Omega_m(a)) calh^2; pos_gr = wrap(pos_n + xi),

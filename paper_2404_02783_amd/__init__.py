@@ -17,7 +17,7 @@ import torch
 __all__ = [
     "PMError", "lib", "SolveParams", "StepParams", "Cosmology", "ICParams", "Plan",
     "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "pk_estimate", "bk_estimate",
-    "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint",
+    "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
     "pm_ic_zeldovich", "pm_ic_gauge", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
     "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH",
@@ -95,6 +95,7 @@ def _declare(l):
         "pm_ic_zeldovich": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_zeldovich_adjoint": (_c_int, [_c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                                              _c_void_p]),
+        "pm_noise_truncate": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_gauge": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                                  _c_void_p, _c_void_p]),
         "pm_cosmo_hubble_e": (_c_double, [P(Cosmology), _c_double]),
@@ -358,6 +359,16 @@ def pm_ic_zeldovich_adjoint(plan: Plan, ic: ICParams, lam_pos, lam_mom, disp_scr
                                          _ptr(disp_scratch, plan.dtype, "disp_scratch"),
                                          _ptr(lam_noise, plan.dtype, "lam_noise"), _stream()))
     return lam_noise
+
+
+def pm_noise_truncate(fine: Plan, noise_fine, coarse: Plan, noise_coarse=None):
+    """Coarse white noise sharing the fine noise's phases on the shared modes."""
+    noise_coarse = coarse.mesh() if noise_coarse is None else noise_coarse
+    _need(noise_fine, fine.n ** 3, "noise_fine")
+    _need(noise_coarse, coarse.n ** 3, "noise_coarse")
+    _check(lib().pm_noise_truncate(fine.handle, _ptr(noise_fine, fine.dtype, "noise_fine"), coarse.handle,
+                                   _ptr(noise_coarse, coarse.dtype, "noise_coarse"), _stream()))
+    return noise_coarse
 
 
 def pm_ic_gauge(plan: Plan, noise, ic: ICParams, disp_scratch, pos_n, mom_n, pos_gr, mom_gr):

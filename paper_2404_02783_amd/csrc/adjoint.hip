@@ -106,13 +106,28 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
   const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
   const int sy = W2, sx = W1 * W2;
   const int wtot = W0 * W1 * W2;
-  for (int c = t; c < wtot; c += kBlock) {
-    const int a = c / sx, b = (c / sy) % W1, cz = c % sy;
-    const int64_t idx = ((int64_t)fold(org[0] + tw.o[0] + a, n) * n + fold(org[1] + tw.o[1] + b, n)) * n +
-                        fold(org[2] + tw.o[2] + cz, n);
-    win[c] = force[idx];
-    win[ACAP + c] = force[np + idx];
-    win[2 * ACAP + c] = force[2 * np + idx];
+  // stage the window: all of a thread's loads in flight before its first LDS store
+  float fa[ACAP / kBlock], fb[ACAP / kBlock], fc[ACAP / kBlock];
+#pragma unroll
+  for (int k = 0; k < ACAP / kBlock; ++k) {
+    const int c = t + kBlock * k;
+    if (c < wtot) {
+      const int a = c / sx, b = (c / sy) % W1, cz = c % sy;
+      const int64_t idx = ((int64_t)fold(org[0] + tw.o[0] + a, n) * n + fold(org[1] + tw.o[1] + b, n)) * n +
+                          fold(org[2] + tw.o[2] + cz, n);
+      fa[k] = force[idx];
+      fb[k] = force[np + idx];
+      fc[k] = force[2 * np + idx];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < ACAP / kBlock; ++k) {
+    const int c = t + kBlock * k;
+    if (c < wtot) {
+      win[c] = fa[k];
+      win[ACAP + c] = fb[k];
+      win[2 * ACAP + c] = fc[k];
+    }
   }
   __syncthreads();
 #pragma unroll

@@ -258,6 +258,22 @@ int pm_ic_zeldovich_adjoint(pm_plan* p, const pm_ic_params* ic, const void* lam_
   return fft3_c2r(p, 1, cbuf(p, 0), 0, lam_noise, s);
 }
 
+int pm_noise_truncate(pm_plan* fine, const void* noise_fine, pm_plan* coarse, void* noise_coarse, void* stream) {
+  using namespace pm;
+  if (!fine || !coarse) return set_error(PM_ERR_ARG, "pm_noise_truncate: null plan");
+  if (!noise_fine || !noise_coarse) return set_error(PM_ERR_ARG, "pm_noise_truncate: null pointer");
+  if (fine->nb != 1 || coarse->nb != 1) return set_error(PM_ERR_ARG, "pm_noise_truncate: needs single-box plans");
+  if (fine->dtype != coarse->dtype) return set_error(PM_ERR_ARG, "pm_noise_truncate: plans differ in dtype");
+  if (coarse->n > fine->n || fine->n % coarse->n != 0)
+    return set_error(PM_ERR_ARG, "pm_noise_truncate: coarse N (%d) must divide fine N (%d)", coarse->n, fine->n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = fft3_r2c(fine, noise_fine, cbuf(fine, 0), s);
+  if (rc) return rc;
+  rc = launch_truncate_spectrum(fine, coarse, s);
+  if (rc) return rc;
+  return fft3_c2r(coarse, 1, cbuf(coarse, 0), 0, noise_coarse, s);
+}
+
 int pm_ic_gauge(pm_plan* p, const void* noise, const pm_ic_params* ic, void* disp, const void* pos_n,
                 const void* mom_n, void* pos_gr, void* mom_gr, void* stream) {
   using namespace pm;

@@ -178,14 +178,37 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
   }
   const int wtot = W[0] * W[1] * W[2];
   const int sy = W[2], sx = W[1] * W[2];
-  // stage the force window (row-contiguous along z)
-  for (int c = t; c < wtot; c += kBlock) {
-    const int a = c / sx, b = (c / sy) % W[1], cz = c % sy;
-    const int64_t idx = ((int64_t)fold(org[0] + o[0] + a, n) * n + fold(org[1] + o[1] + b, n)) * n +
-                        fold(org[2] + o[2] + cz, n);
-    win[c] = force[idx];
-    win[GCAP + c] = force[fstride + idx];
-    win[2 * GCAP + c] = force[2 * fstride + idx];
+  // the momenta are needed only after the window: start their loads now
+  float mx[GPP], my[GPP], mz[GPP];
+#pragma unroll
+  for (int p = 0; p < GPP; ++p) {
+    mx[p] = mom[jj[p]];
+    my[p] = mom[np + jj[p]];
+    mz[p] = mom[2 * np + jj[p]];
+  }
+  // stage the force window (row-contiguous along z): all of a thread's loads are
+  // issued before its first LDS store, so they are in flight together
+  float fa[GCAP / kBlock], fb[GCAP / kBlock], fc[GCAP / kBlock];
+#pragma unroll
+  for (int k = 0; k < GCAP / kBlock; ++k) {
+    const int c = t + kBlock * k;
+    if (c < wtot) {
+      const int a = c / sx, b = (c / sy) % W[1], cz = c % sy;
+      const int64_t idx = ((int64_t)fold(org[0] + o[0] + a, n) * n + fold(org[1] + o[1] + b, n)) * n +
+                          fold(org[2] + o[2] + cz, n);
+      fa[k] = force[idx];
+      fb[k] = force[fstride + idx];
+      fc[k] = force[2 * fstride + idx];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < GCAP / kBlock; ++k) {
+    const int c = t + kBlock * k;
+    if (c < wtot) {
+      win[c] = fa[k];
+      win[GCAP + c] = fb[k];
+      win[2 * GCAP + c] = fc[k];
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -218,7 +241,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
       }
     }
     const int64_t j = jj[p];
-    const float px = mom[j] + kick * fx, py = mom[np + j] + kick * fy, pz = mom[2 * np + j] + kick * fz;
+    const float px = mx[p] + kick * fx, py = my[p] + kick * fy, pz = mz[p] + kick * fz;
     mom[j] = px;
     mom[np + j] = py;
     mom[2 * np + j] = pz;
@@ -237,38 +260,59 @@ __device__ __forceinline__ T min_image(T d, int n) {
   return s - fn * floor(s / fn) - T(0.5) * fn;
 }
 
-// Grid (ceil(nf / 256), nf, nf): thread (x, y, z) handles fine particle
-// (blockIdx.z, blockIdx.y, x) with 32-bit index arithmetic (nf <= 4096).
+// Coarse-lattice coordinate of fine particle j along one axis:
+// u = ((2j+1) nc - nf) / (2 nf), base node i0 = floor(u) (in [-1, nc)), weight t = u - i0,
+// from an integer floor division and its exact remainder.
+template <typename T>
+__device__ __forceinline__ int lagr_base(int j, int nc, int nf, T& t) {
+  const int num = (2 * j + 1) * nc - nf;
+  const int den = 2 * nf;
+  const int q = num >= 0 ? num / den : -((-num + den - 1) / den);
+  t = T(num - q * den) / T(den);
+  return q;
+}
+
+// Block (x, y, z) of 256 threads handles fine particles (z, y, 256 x + t): one run
+// along the fine z axis, whose CIC corners lie on four coarse z-rows.  The block
+// first stages xi = min-image (x_gr - x_newton) on those rows (the coarse cells its
+// particles touch, zc cells per row) in LDS, then interpolates; the weights and the
+// summation order are those of a direct per-particle evaluation.
+constexpr int kCombineZ = kBlock + 4;  // staged coarse cells per row (nc <= nf)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, const T* __restrict__ xn, int nc,
                                                     const T* __restrict__ xf, int nf, T* __restrict__ out) {
-  const int jz = blockIdx.x * kBlock + threadIdx.x;
-  if (jz >= nf) return;
-  const int jf[3] = {(int)blockIdx.z, (int)blockIdx.y, jz};
-  const int64_t npf = (int64_t)nf * nf * nf;
-  const int64_t j = ((int64_t)jf[0] * nf + jf[1]) * nf + jz;
-  const int64_t npc = (int64_t)nc * nc * nc;
-  int i0[3], i1[3];
-  T t[3];
+  __shared__ T xs[3][4][kCombineZ];
+  const int jx = blockIdx.z, jy = blockIdx.y, jz0 = blockIdx.x * kBlock;
+  const int jz = jz0 + threadIdx.x;
+  const int64_t npf = (int64_t)nf * nf * nf, npc = (int64_t)nc * nc * nc;
+  T tx, ty, tz;
+  const int qx = lagr_base(jx, nc, nf, tx), qy = lagr_base(jy, nc, nf, ty);
+  const int ix[2] = {qx < 0 ? qx + nc : qx, qx + 1 >= nc ? qx + 1 - nc : (qx + 1 < 0 ? qx + 1 + nc : qx + 1)};
+  const int iy[2] = {qy < 0 ? qy + nc : qy, qy + 1 >= nc ? qy + 1 - nc : (qy + 1 < 0 ? qy + 1 + nc : qy + 1)};
+  T tdummy;
+  const int zlo = lagr_base(jz0, nc, nf, tdummy);
+  const int jlast = min(jz0 + kBlock, nf) - 1;
+  const int zc = lagr_base(jlast, nc, nf, tdummy) - zlo + 2;  // <= 256 nc/nf + 2
+  for (int e = threadIdx.x; e < 4 * zc; e += kBlock) {
+    const int r = e / zc, k = e - r * zc;
+    int zi = zlo + k;
+    zi = zi < 0 ? zi + nc : (zi >= nc ? zi - nc : zi);
+    const int64_t id = ((int64_t)ix[r >> 1] * nc + iy[r & 1]) * nc + zi;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    // u = ((2j+1) nc - nf) / (2 nf): integer floor division and exact remainder
-    const int num = (2 * jf[d] + 1) * nc - nf;
-    const int den = 2 * nf;
-    const int q = num >= 0 ? num / den : -((-num + den - 1) / den);
-    const int rem = num - q * den;
-    i0[d] = q < 0 ? q + nc : (q >= nc ? q - nc : q);
-    i1[d] = i0[d] + 1 == nc ? 0 : i0[d] + 1;
-    t[d] = T(rem) / T(den);
+    for (int d = 0; d < 3; ++d) xs[d][r][k] = min_image(xg[d * npc + id] - xn[d * npc + id], nc);
   }
+  __syncthreads();
+  if (jz >= nf) return;
+  const int kz = lagr_base(jz, nc, nf, tz) - zlo;
+  const int64_t j = ((int64_t)jx * nf + jy) * nf + jz;
+  const T t[3] = {tx, ty, tz};
   T xi[3] = {0, 0, 0};
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int cx_ = (c >> 2) & 1, cy_ = (c >> 1) & 1, cz_ = c & 1;
-    const int64_t id = ((int64_t)(cx_ ? i1[0] : i0[0]) * nc + (cy_ ? i1[1] : i0[1])) * nc + (cz_ ? i1[2] : i0[2]);
     const T w = (cx_ ? t[0] : T(1) - t[0]) * (cy_ ? t[1] : T(1) - t[1]) * (cz_ ? t[2] : T(1) - t[2]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xi[d] += w * min_image(xg[d * npc + id] - xn[d * npc + id], nc);
+    for (int d = 0; d < 3; ++d) xi[d] += w * xs[d][cx_ * 2 + cy_][kz + cz_];
   }
   const T ratio = T(nf) / T(nc);
 #pragma unroll

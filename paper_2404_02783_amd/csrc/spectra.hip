@@ -228,6 +228,28 @@ __global__ void __launch_bounds__(kBlock) k_pk_adjoint_weight(cx<T>* __restrict_
   stc(dhat + idx, mk(T(beta * (double)v.x), T(beta * (double)v.y)));
 }
 
+// Coarse spectrum from a fine one on the natural layouts: coarse mode n (signed, all
+// |n_i| < Nc/2) takes fine mode n times `scale`; the coarse Nyquist planes are zero.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_truncate_spectrum(const cx<T>* __restrict__ fine, int nf, int hpf,
+                                                              cx<T>* __restrict__ coarse, int nc, int hpc, T scale) {
+  const int64_t total = (int64_t)nc * nc * hpc;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= total) return;
+  const int iz = (int)(idx % hpc);
+  if (iz > nc / 2) return;
+  const int iy = (int)((idx / hpc) % nc);
+  const int ix = (int)(idx / ((int64_t)hpc * nc));
+  const int nx = signed_freq(ix, nc), ny = signed_freq(iy, nc);
+  cx<T> v = mk(T(0), T(0));
+  if (nx != -nc / 2 && ny != -nc / 2 && iz != nc / 2) {
+    const int fx = nx < 0 ? nx + nf : nx, fy = ny < 0 ? ny + nf : ny;
+    const cx<T> w = ldc(fine + ((int64_t)fx * nf + fy) * hpf + iz);
+    v = mk(w.x * scale, w.y * scale);
+  }
+  stc(coarse + idx, v);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_shell_mask(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n,
                                                        int hp, double lo4, double hi4) {
@@ -355,6 +377,24 @@ int launch_pk_adjoint_weight(const pm_plan* p, void* dhat, int n_bins, const dou
     hipLaunchKernelGGL(k_pk_adjoint_weight<double>, dim3(g), dim3(kBlock), 0, s, static_cast<cx<double>*>(dhat), n,
                        p->hp, n_bins, p->sums, dpk, coef);
   return hip_check(hipGetLastError(), "pk adjoint weight");
+}
+
+int launch_truncate_spectrum(const pm_plan* fine, const pm_plan* coarse, hipStream_t s) {
+  ProfScope ps(coarse, PK_IC, s);
+  const int nc = coarse->n, nf = fine->n;
+  const int64_t total = (int64_t)nc * nc * coarse->hp;
+  const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
+  // (Nc/Nf)^(3/2) keeps the physical field on the shared modes; 1/Nc^3 is the inverse transform's
+  const double scale = std::pow((double)nc / nf, 1.5) / ((double)nc * nc * nc);
+  if (fine->dtype == PM_F32)
+    hipLaunchKernelGGL(k_truncate_spectrum<float>, dim3(g), dim3(kBlock), 0, s,
+                       static_cast<const cx<float>*>(cbuf(fine, 0)), nf, fine->hp,
+                       static_cast<cx<float>*>(cbuf(coarse, 0)), nc, coarse->hp, (float)scale);
+  else
+    hipLaunchKernelGGL(k_truncate_spectrum<double>, dim3(g), dim3(kBlock), 0, s,
+                       static_cast<const cx<double>*>(cbuf(fine, 0)), nf, fine->hp,
+                       static_cast<cx<double>*>(cbuf(coarse, 0)), nc, coarse->hp, scale);
+  return hip_check(hipGetLastError(), "truncate spectrum");
 }
 
 int launch_shell_mask(const pm_plan* p, const void* src, void* dst, double lo4, double hi4, hipStream_t s) {

@@ -232,7 +232,7 @@ def test_step_matches_force_kick_drift(dt, n, amp):
 # ----------------------------------------------------------------- combine --
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("nc,nf", [(8, 32), (16, 16), (16, 32)])
+@pytest.mark.parametrize("nc,nf", [(8, 32), (16, 16), (16, 32), (32, 288)])
 def test_displacement_combine(dt, nc, nf):
     dev = _dev()
     xn = torch.from_numpy(si.lattice_jitter_particles(nc, 11, 0.9))
@@ -325,6 +325,17 @@ def test_initial_conditions(dt, kind):
     assert float(min_image(pos.double().cpu() - wpn, n).abs().max()) < 4 * ulp
     assert float(min_image(pg.double().cpu() - wpg, n).abs().max()) < 8 * ulp
     assert float((mg.double().cpu() - wmg).abs().max()) < 10 * tol * float(wmn.abs().max())
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("nf,nc", [(64, 16), (32, 32), (128, 32)])
+def test_noise_truncate(dt, nf, nc):
+    dev = _dev()
+    w = torch.from_numpy(si.white_noise(nf, 5 + nf))
+    fine, coarse = pm.Plan(nf, 1000.0, dt), pm.Plan(nc, 1000.0, dt)
+    got = pm.pm_noise_truncate(fine, w.to(dt).to(dev).contiguous(), coarse)
+    torch.cuda.synchronize()
+    assert rel_l2(got, oics.truncate_noise(w.to(dt).double(), nc)) < _tol(dt)
 
 
 # ------------------------------------------------------- end-to-end FP64 ----
