@@ -67,17 +67,12 @@ void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* o2, cx<T>* phi, const ColArgs
   dim3 grid((unsigned)(outer * g.groups), (unsigned)a.nbox);
   dim3 block((unsigned)(g.bcols * tpc));
   size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
-  // y/z components first (they also update the carried potential), then the x
-  // component, written over the spectrum the first launch still reads
-  if (a.kind == PM_NEWTON) {
-    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_NEWTON, 1>), grid, block, shm, s, data, o1, o2, phi, g, a, tw);
-    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_NEWTON, 0>), grid, block, shm, s, data, o1, o2, phi, g, a, tw);
-  } else {
-    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_POISSON_GAUGE, 1>), grid, block, shm, s, data, o1, o2, phi, g,
+  // one launch: forward transform, symbol, both inverse transforms
+  if (a.kind == PM_NEWTON)
+    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_NEWTON, 2>), grid, block, shm, s, data, o1, o2, phi, g, a, tw);
+  else
+    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_POISSON_GAUGE, 2>), grid, block, shm, s, data, o1, o2, phi, g,
                        a, tw);
-    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_POISSON_GAUGE, 0>), grid, block, shm, s, data, o1, o2, phi, g,
-                       a, tw);
-  }
 }
 
 // Dispatch on a transform length L to the compile-time (L1, L2) instantiation.

@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
         const int64_t pidx = ((int64_t)ix * N + outer) * (N / 2 + 1) + col;
         const cx<T> pstored = valid ? ldc(phi + pidx) : mk(T(0), T(0));
         cx<T> pnew;
-        if (PASS == 1) {  // first launch: update phi_old -> phi_new
+        if (PASS != 0) {  // update phi_old -> phi_new (the second launch of the split form reads it)
           const T h = T(s.h), h2 = T(s.h2);
           const T den = -k2s - T(3) * h2 - T(3) * h * T(s.inv_dtau) - T(4.5) * h2 * T(s.om_a);
           const cx<T> num = scale(X[k2], T(1.5) * h2 * T(s.om_a)) - scale(pstored, T(3) * h * T(s.inv_dtau));
@@ -310,9 +310,36 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
   }
   // Inverse transform.  Along axis 0 the y and z gradient symbols are constants, so
   //   F_x = IDFT(D_x G),  F_y = D_y IDFT(G),  F_z = D_z IDFT(G).
-  // PASS 1 (launched first) writes F_y, F_z to out1, out2; PASS 0 (launched second,
-  // after the spectrum in `data` is no longer needed) writes F_x in place.
-  __syncthreads();  // every thread has read its forward data from LDS
+  // PASS 2: one launch does both inverse transforms (F_x in place first, then F_y, F_z).
+  // Split form: PASS 1 (launched first) writes F_y, F_z to out1, out2; PASS 0
+  // (launched second, after the spectrum in `data` is no longer needed) writes F_x.
+  if (PASS == 2) {
+    __syncthreads();  // every thread has read its forward data from LDS
+    if (u < L1) {
+      cx<T> Y[L2];
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) {
+        const int ix = u + L1 * k2;
+        Y[k2] = grad_symbol<T>(ix < N / 2 ? ix : ix - N, N, s.grad) * X[k2];
+      }
+      RegDFT<T, L2, 1>::run(Y);
+#pragma unroll
+      for (int ja = 0; ja < L2; ++ja)
+        lds[col_lds_index<T, L1, L2>(u, ja, b, B)] = ja == 0 ? Y[ja] : tw_mul<true>(Y[ja], tw, u * ja * g.tw_step);
+    }
+    __syncthreads();
+    if (u < L2) {
+      cx<T> c[L1];
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) c[k1] = lds[col_lds_index<T, L1, L2>(k1, u, b, B)];
+      RegDFT<T, L1, 1>::run(c);
+      if (valid) {
+#pragma unroll
+        for (int jb = 0; jb < L1; ++jb) stc(data + off + (int64_t)(u + L2 * jb) * g.stride, c[jb]);
+      }
+    }
+  }
+  __syncthreads();  // every thread has read its forward data (or the F_x exchange) from LDS
   if (u < L1) {
     if (PASS == 0) {
 #pragma unroll
