@@ -131,7 +131,7 @@ def adjoint_ratio(pm, plan, noise, icp, n_cycles: int, ckpt: int, n_bins: int):
     return t1 - t0, t2 - t1, prof
 
 
-def config3_estimators(pm, plan, pos, fine_noise, n_bins=256):
+def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
     """Timings of the estimator and combination calls of the displacement-combination
     configuration on the final 1024^3 positions: deposit + P(k) in 256 bins, B(k)
     on 64 triangles (32 equilateral k = m*16 k_f, 32 squeezed with k3 = 4 k_f; shell
@@ -193,7 +193,7 @@ def config3_estimators(pm, plan, pos, fine_noise, n_bins=256):
     return out
 
 
-def config5_adjoint(pm, n=128, box=1000.0, n_steps=20, ckpt=5, n_bins=64):
+def adjoint_small(pm, n=128, box=1000.0, n_steps=20, ckpt=5, n_bins=64):
     """Adjoint/forward time of the differentiable configuration: 128^3, L = 1000 Mpc/h,
     20 log steps a = 0.05 -> 1, P(k) in 64 bins, checkpoints every 5 cycles."""
     import torch
@@ -318,7 +318,7 @@ def main():
                     help="run a plain 1 GiB device copy first (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: the multi-GPU (sharded) path is not implemented",
               file=sys.stderr)
         sys.exit(2)
 
@@ -417,7 +417,7 @@ def main():
     }
     if not args.no_extras:
         print("[bench] estimators and combination at 1024^3", file=sys.stderr, flush=True)
-        out["config3"] = config3_estimators(pm, plan, pos, noise)
+        out["estimators_combination_1024"] = estimators_and_combination(pm, plan, pos, noise)
     if args.adjoint_cycles > 0:
         del run, pos, mom
         torch.cuda.synchronize()
@@ -435,7 +435,7 @@ def main():
     if not args.no_extras:
         torch.cuda.empty_cache()
         print("[bench] 128^3 adjoint configuration", file=sys.stderr, flush=True)
-        out["adjoint_128"] = config5_adjoint(pm)
+        out["adjoint_128"] = adjoint_small(pm)
         print("[bench] 64-box ensemble", file=sys.stderr, flush=True)
         out["ensemble"] = ensemble_leg(pm)
     if not args.no_cpu_baseline:

@@ -13,7 +13,7 @@ Module map (paper passages in each function's docstring):
   fourier     -- DFT conventions, wavenumber grids, brute-force DFT for pins
   solve       -- Newtonian Poisson solve and the Poisson-gauge weak-field solve
   ics         -- Zel'dovich initial conditions (Newtonian and Poisson-gauge sets)
-  integrate   -- kick-drift-kick leapfrog driver
+  integrate   -- kick-drift-kick leapfrog loop
   combine     -- GR-minus-Newton displacement and its addition to a fine run
   estimators  -- power spectrum and FFT bispectrum estimators
   adjoint     -- loss on P(k) and its reference gradient

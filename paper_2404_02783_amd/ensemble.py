@@ -1,4 +1,4 @@
-"""Batched ensembles of independent periodic boxes with uneven meshes (host driver
+"""Batched ensembles of independent periodic boxes with uneven meshes (host loop
 over the C ABI; every step runs in the library's kernels).
 
 Boxes of equal mesh size form one batched plan, so each kernel of a leapfrog cycle

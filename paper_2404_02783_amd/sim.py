@@ -1,4 +1,4 @@
-"""Leapfrog driver over the C ABI (host loop only; every step runs in the kernels).
+"""Leapfrog over the C ABI (host loop only; every step runs in the kernels).
 
 A kick-drift-kick leapfrog from a_0 to a_n with half steps at sqrt(a_j a_{j+1}) is
 issued as n+1 ``pm_step`` cycles (force at a_j, kick, drift): the cycle at a_j

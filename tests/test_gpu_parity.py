@@ -341,7 +341,7 @@ def test_noise_truncate(dt, nf, nc):
 # ------------------------------------------------------- end-to-end FP64 ----
 
 @pytest.mark.slow
-def test_config1_paired_run_fp64():
+def test_paired_run_32_fp64():
     """32^3 particles, L = 1000 Mpc/h, power law with rms displacement 0.2 cell at a = 0.02,
     10 log steps to a = 0.1, Newtonian and Poisson-gauge sets, P(k) in 16 bins."""
     dev = _dev()
