@@ -48,14 +48,21 @@ def algorithmic_bytes(n: int, np_: int, es: int = 4):
     }
 
 
-def kernel_source_digest() -> str:
-    """sha256 over the HIP/C++ sources of the library (any kernel change alters it)."""
+# Source files that define each timed kernel (its translation unit and the headers it includes).
+KERNEL_SOURCES = {
+    "gather_kick_drift": ["paper_2404_02783_amd/csrc/particles.hip", "paper_2404_02783_amd/csrc/pm_particles.h",
+                          "paper_2404_02783_amd/csrc/pm_common.h", "paper_2404_02783_amd/csrc/pm_plan.h",
+                          "include/pmhip.h"],
+}
+
+
+def kernel_source_digest(kernel: str = "gather_kick_drift") -> str:
+    """sha256 over the sources that define ``kernel`` (any change to them alters it)."""
     import hashlib
-    d = os.path.join(ROOT, "paper_2404_02783_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        with open(os.path.join(d, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+    for rel in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
@@ -65,7 +72,7 @@ def measured_traffic(kernel: str, n: int):
     a plain device copy), or None when there is none for this kernel and mesh or the
     kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_{n}.md")
-    if not os.path.exists(path):
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
         return None
     vals = {}
     with open(path) as f:
@@ -73,7 +80,7 @@ def measured_traffic(kernel: str, n: int):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_sha256") != kernel_source_digest():
+    if vals.get("source_sha256") != kernel_source_digest(kernel):
         return None
     try:
         return int(float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"]))
