@@ -45,15 +45,15 @@ def algorithmic_bytes(n: int, np_: int, es: int = 4):
         "fft_cols_inv_axis1": 3 * 2 * cs * c,
         "fft_c2r_rows": 3 * cs * c + 3 * es * n3,
         "gather_kick_drift": 12 * es * np_ + 3 * es * n3,   # x, p read and written; force read once
+        # the same plus the next cycle's density written once (positions still in registers)
+        "gather_kick_drift_deposit": 12 * es * np_ + 3 * es * n3 + es * n3,
     }
 
 
 # Source files that define each timed kernel (its translation unit and the headers it includes).
-KERNEL_SOURCES = {
-    "gather_kick_drift": ["paper_2404_02783_amd/csrc/particles.hip", "paper_2404_02783_amd/csrc/pm_particles.h",
-                          "paper_2404_02783_amd/csrc/pm_common.h", "paper_2404_02783_amd/csrc/pm_plan.h",
-                          "include/pmhip.h"],
-}
+_PARTICLE_SOURCES = ["paper_2404_02783_amd/csrc/particles.hip", "paper_2404_02783_amd/csrc/pm_particles.h",
+                     "paper_2404_02783_amd/csrc/pm_common.h", "paper_2404_02783_amd/csrc/pm_plan.h", "include/pmhip.h"]
+KERNEL_SOURCES = {"gather_kick_drift": _PARTICLE_SOURCES, "gather_kick_drift_deposit": _PARTICLE_SOURCES}
 
 
 def kernel_source_digest(kernel: str = "gather_kick_drift") -> str:
@@ -395,7 +395,8 @@ def main():
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
     dom_avg = prof[dom][0] / prof[dom][1]
     dom_gbs = alg[dom] / (dom_avg / 1000.0) / 1e9
-    step_bytes = sum(alg.values())
+    # algorithmic bytes of the kernels the timed steps actually launched, per step
+    step_bytes = sum(alg[k] * cnt for k, (_, cnt) in prof.items() if k in alg) // args.steps
     step_gbs = step_bytes / (ms_step / 1000.0) / 1e9
     out = {
         "metric": METRIC,

@@ -83,11 +83,24 @@ typedef struct {
 
 /* One force-kick-drift cycle: F = force(x); p += kick * F(x); x = wrap(x + drift * p).
  * A kick-drift-kick leapfrog is a chain of cycles with kick = K2(previous step) +
- * K1(this step) and a closing cycle with drift = 0 (see pm_kdk_factors). */
+ * K1(this step) and a closing cycle with drift = 0 (see pm_kdk_factors).
+ * flags (0 = plain cycle):
+ *   PM_STEP_DEPOSIT_NEXT  after the drift, also deposit the new positions into the
+ *                         plan's density buffer (fused into the gather where the
+ *                         layout allows), for the next cycle;
+ *   PM_STEP_DENSITY_READY the plan's density buffer already holds the density of
+ *                         `pos`, left by the previous pm_step on this plan with the
+ *                         same pos pointer and PM_STEP_DEPOSIT_NEXT; the caller
+ *                         asserts the positions were not modified since.  If the
+ *                         plan holds no such density the call fails with
+ *                         PM_ERR_STATE.  Every other call on the plan discards it. */
+#define PM_STEP_DEPOSIT_NEXT 1
+#define PM_STEP_DENSITY_READY 2
 typedef struct {
   double kick;
   double drift;
   pm_solve_params solve;
+  int flags;
 } pm_step_params;
 
 /* Flat LCDM background without radiation (Sec. 3 of the paper). */

@@ -22,7 +22,7 @@ __all__ = [
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
     "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH",
     "PM_F32", "PM_F64", "PM_NEWTON", "PM_POISSON_GAUGE", "PM_GRAD_SPECTRAL", "PM_GRAD_FD2", "PM_GRAD_FD1",
-    "PM_PK_POWERLAW", "PM_PK_EH98",
+    "PM_PK_POWERLAW", "PM_PK_EH98", "PM_STEP_DEPOSIT_NEXT", "PM_STEP_DENSITY_READY",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpmhip.so")
@@ -48,8 +48,11 @@ class SolveParams(ctypes.Structure):
                 ("om_a", _c_double), ("calh", _c_double), ("c_g", _c_double), ("inv_dtau", _c_double)]
 
 
+PM_STEP_DEPOSIT_NEXT, PM_STEP_DENSITY_READY = 1, 2
+
+
 class StepParams(ctypes.Structure):
-    _fields_ = [("kick", _c_double), ("drift", _c_double), ("solve", SolveParams)]
+    _fields_ = [("kick", _c_double), ("drift", _c_double), ("solve", SolveParams), ("flags", _c_int)]
 
 
 class Cosmology(ctypes.Structure):

@@ -42,6 +42,12 @@ static int check_plan(const pm_plan* p) {
   return PM_OK;
 }
 
+// Every entry point other than pm_step may reuse the workspace: the density left for
+// the next cycle is discarded.
+static void drop_density(pm_plan* p) {
+  if (p) p->dens_valid = false;
+}
+
 // Entry points that work on one box only.
 static int check_single(const pm_plan* p, const char* who) {
   if (!p) return set_error(PM_ERR_ARG, "%s: null plan", who);
@@ -53,7 +59,7 @@ static int check_single(const pm_plan* p, const char* who) {
 static const char* kProfNames[PK_COUNT] = {
     "fill",          "deposit",        "fft_r2c_rows",   "fft_cols_fwd_axis1", "fft_cols_fwd_axis0",
     "fft_solve_axis0", "fft_cols_inv_axis0", "fft_cols_inv_axis1", "fft_c2r_rows", "gather",
-    "gather_kick_drift", "combine",    "ic",             "pk",                 "bk",
+    "gather_kick_drift", "gather_kick_drift_deposit", "combine", "ic", "pk", "bk",
     "adjoint_gather_kick_drift", "adjoint_deposit", "grad_gather", "adjoint_symbol"};
 
 struct ProfRec {
@@ -289,6 +295,7 @@ int pm_check(pm_plan* p, void* stream) {
 
 int pm_deposit(pm_plan* p, const void* pos, int64_t np, void* delta, void* stream) {
   PM_TRY(check_plan(p));
+  drop_density(p);
   if (np < 0) return set_error(PM_ERR_ARG, "pm_deposit: negative particle count");
   if (!delta || (np > 0 && !pos)) return set_error(PM_ERR_ARG, "pm_deposit: null pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -319,6 +326,7 @@ static int check_solve_params(const pm_solve_params* sp, const void* phi, const 
 
 int pm_solve(pm_plan* p, const void* delta, const pm_solve_params* sp, void* phi_state, void* force, void* stream) {
   PM_TRY(check_plan(p));
+  drop_density(p);
   if (!delta || !force) return set_error(PM_ERR_ARG, "pm_solve: null pointer");
   PM_TRY(check_solve_params(sp, phi_state, "pm_solve"));
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -328,6 +336,7 @@ int pm_solve(pm_plan* p, const void* delta, const pm_solve_params* sp, void* phi
 
 int pm_gather(pm_plan* p, const void* force, const void* pos, int64_t np, void* acc, void* stream) {
   PM_TRY(check_single(p, "pm_gather"));
+  drop_density(p);
   if (np < 0) return set_error(PM_ERR_ARG, "pm_gather: negative particle count");
   if (np > 0 && (!force || !pos || !acc)) return set_error(PM_ERR_ARG, "pm_gather: null pointer");
   return launch_gather(p, force, pos, np, acc, static_cast<hipStream_t>(stream));
@@ -339,20 +348,43 @@ int pm_step(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* 
   if (np < 0) return set_error(PM_ERR_ARG, "pm_step: negative particle count");
   if (!st || !force_scratch || (np > 0 && (!pos || !mom))) return set_error(PM_ERR_ARG, "pm_step: null pointer");
   PM_TRY(check_solve_params(&st->solve, phi_state, "pm_step"));
+  if (st->flags & ~(PM_STEP_DEPOSIT_NEXT | PM_STEP_DENSITY_READY)) return set_error(PM_ERR_ARG, "pm_step: bad flags");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n3 = (int64_t)p->n * p->n * p->n;
   if (p->nb > 1 && np != n3) return set_error(PM_ERR_ARG, "pm_step: a batch needs N^3 particles per box");
   void* delta = cbuf(p, 1);  // the density meshes live in the second spectrum region
-  PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
-  PM_TRY(launch_deposit(p, pos, np, delta, s));
+  const bool ready = p->dens_valid && p->dens_pos == pos && p->dens_np == np;
+  if ((st->flags & PM_STEP_DENSITY_READY) && !ready) {
+    p->dens_valid = false;
+    return set_error(PM_ERR_STATE, "pm_step: the plan holds no density of these positions from a previous step");
+  }
+  p->dens_valid = false;
+  if (!(st->flags & PM_STEP_DENSITY_READY)) {
+    PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
+    PM_TRY(launch_deposit(p, pos, np, delta, s));
+  }
   PM_TRY(fft_pass_rows_r2c(p, p->nb, delta, cbuf(p, 0), s));
   PM_TRY(solve_from_c0(p, &st->solve, phi_state, force_scratch, s));
-  return launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, s);
+  if (!(st->flags & PM_STEP_DEPOSIT_NEXT))
+    return launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, nullptr, s);
+  // the second region is free again once the inverse transforms have run
+  PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
+  if (gather_kdk_can_deposit(p, np)) {
+    PM_TRY(launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, delta, s));
+  } else {
+    PM_TRY(launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, nullptr, s));
+    PM_TRY(launch_deposit(p, pos, np, delta, s));
+  }
+  p->dens_valid = true;
+  p->dens_pos = pos;
+  p->dens_np = np;
+  return PM_OK;
 }
 
 int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, const void* force,
                     void* mesh_scratch, void* lam_pos, void* lam_mom, void* stream) {
   PM_TRY(check_single(p, "pm_step_adjoint"));
+  drop_density(p);
   if (np < 0) return set_error(PM_ERR_ARG, "pm_step_adjoint: negative particle count");
   if (!st || !mesh_scratch || (np > 0 && (!pos || !lam_pos || !lam_mom)))
     return set_error(PM_ERR_ARG, "pm_step_adjoint: null pointer");
@@ -383,6 +415,7 @@ int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_param
 
 int pk_adjoint(pm_plan* p, const void* pos, int64_t np, int n_bins, const double* dpk, void* lam_pos, void* stream) {
   PM_TRY(check_single(p, "pk_adjoint"));
+  drop_density(p);
   if (np < 0) return set_error(PM_ERR_ARG, "pk_adjoint: negative particle count");
   if (!dpk || (np > 0 && (!pos || !lam_pos))) return set_error(PM_ERR_ARG, "pk_adjoint: null pointer");
   if (n_bins <= 0 || 3 * (size_t)n_bins > p->sums_cap || n_bins > 4 * p->n)
@@ -416,6 +449,7 @@ int displacement_combine(const void* x_gr, const void* x_newton, int n_coarse, c
 int pk_estimate(pm_plan* p, const void* delta, int n_bins, double* k_mean, double* pk, int64_t* n_modes,
                 void* stream) {
   PM_TRY(check_plan(p));
+  drop_density(p);
   if (!delta || !k_mean || !pk || !n_modes) return set_error(PM_ERR_ARG, "pk_estimate: null pointer");
   if (n_bins <= 0 || 3 * (size_t)n_bins * p->nb > p->sums_cap || n_bins > 4 * p->n)
     return set_error(PM_ERR_ARG, "pk_estimate: n_bins %d out of range", n_bins);
@@ -430,6 +464,7 @@ int bk_estimate(pm_plan* p, const void* delta, int n_shells, const double* centr
                 int n_tri, double* bk, double* ntri_out, const double* ntri_known, void* shell_ws,
                 size_t shell_ws_bytes, void* stream) {
   PM_TRY(check_single(p, "bk_estimate"));
+  drop_density(p);
   if (!delta || !centre || !tri || !bk || !ntri_out || !shell_ws) return set_error(PM_ERR_ARG, "bk_estimate: null pointer");
   if (n_shells <= 0 || n_tri <= 0 || !(width > 0.0)) return set_error(PM_ERR_ARG, "bk_estimate: bad sizes");
   if (2 * (size_t)n_tri > p->sums_cap) return set_error(PM_ERR_ARG, "bk_estimate: too many triangles");

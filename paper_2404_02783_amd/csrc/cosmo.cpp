@@ -226,6 +226,7 @@ int pm_ic_zeldovich(pm_plan* p, const void* noise, const pm_ic_params* ic, void*
   using namespace pm;
   int rc = check_ic(p, noise, ic, disp, "pm_ic_zeldovich");
   if (rc) return rc;
+  p->dens_valid = false;
   if (!pos || !mom) return set_error(PM_ERR_ARG, "pm_ic_zeldovich: null pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   rc = ic_common(p, noise, ic, disp, 1, 1.0, s);
@@ -240,6 +241,7 @@ int pm_ic_zeldovich_adjoint(pm_plan* p, const pm_ic_params* ic, const void* lam_
   using namespace pm;
   if (!p) return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: null plan");
   if (p->nb != 1) return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: needs a single-box plan");
+  p->dens_valid = false;
   if (!ic || !lam_pos || !lam_mom || !disp_scratch || !lam_noise)
     return set_error(PM_ERR_ARG, "pm_ic_zeldovich_adjoint: null pointer");
   if (ic->pk_kind != PM_PK_POWERLAW && ic->pk_kind != PM_PK_EH98)
@@ -266,6 +268,7 @@ int pm_noise_truncate(pm_plan* fine, const void* noise_fine, pm_plan* coarse, vo
   if (fine->dtype != coarse->dtype) return set_error(PM_ERR_ARG, "pm_noise_truncate: plans differ in dtype");
   if (coarse->n > fine->n || fine->n % coarse->n != 0)
     return set_error(PM_ERR_ARG, "pm_noise_truncate: coarse N (%d) must divide fine N (%d)", coarse->n, fine->n);
+  fine->dens_valid = coarse->dens_valid = false;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc = fft3_r2c(fine, noise_fine, cbuf(fine, 0), s);
   if (rc) return rc;
@@ -279,6 +282,7 @@ int pm_ic_gauge(pm_plan* p, const void* noise, const pm_ic_params* ic, void* dis
   using namespace pm;
   int rc = check_ic(p, noise, ic, disp, "pm_ic_gauge");
   if (rc) return rc;
+  p->dens_valid = false;
   if (p->nb != 1) return set_error(PM_ERR_ARG, "pm_ic_gauge: needs a single-box plan");
   if (!pos_n || !mom_n || !pos_gr || !mom_gr) return set_error(PM_ERR_ARG, "pm_ic_gauge: null pointer");
   const pm_cosmology* c = &ic->cosmo;

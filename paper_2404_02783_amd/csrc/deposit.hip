@@ -61,11 +61,6 @@ constexpr int TX = 8, TY = 8, TZ = 16;
 constexpr int TPP = TX * TY * TZ / kBlock;  // particles per thread
 constexpr int WCAP = 4096;                  // LDS window cells (u64)
 constexpr int WF = 16;                      // fallback window side (WF^3 <= WCAP)
-constexpr double kFix = 4294967296.0;       // fixed-point scale 2^32
-
-__device__ __forceinline__ unsigned long long to_fix(float w) {
-  return (unsigned long long)((double)w * kFix + 0.5);
-}
 
 template <typename F>
 __device__ __forceinline__ int wave_reduce_i(int v, F op) {

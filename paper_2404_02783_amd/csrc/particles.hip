@@ -96,16 +96,27 @@ constexpr int GPP = GTX * GTY * GTZ / kBlock;  // particles per thread
 constexpr int GCAP = 4096;                     // staged cells (x3 components, float)
 constexpr int GWF = 16;                        // fallback box side (GWF^3 <= GCAP)
 
+// DEPOSIT: after the drift, the tile's new positions are also deposited into `dens`
+// (pre-filled with -1, box offset N^3) exactly as the standalone tiled deposit does --
+// an LDS window over the bounding box of their CIC cells in 64-bit fixed point (the
+// force window's LDS is reused: DCAP cells), one global atomic per non-empty cell,
+// global atomics for particles outside the window -- so the next cycle need not read
+// the positions again.
+constexpr int DCAP = 3 * GCAP * (int)sizeof(float) / (int)sizeof(unsigned long long);
+constexpr int DWF = 18;  // fallback deposit box side (DWF^3 <= DCAP)
+template <bool DEPOSIT>
 __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
                                                              float* __restrict__ mom, int n, int64_t fstride,
-                                                             float kick, float drift) {
-  __shared__ float win[3 * GCAP];
+                                                             float kick, float drift, float* __restrict__ dens,
+                                                             float w_scale, unsigned* __restrict__ guard) {
+  __shared__ __attribute__((aligned(16))) float win[3 * GCAP];
   __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
   __shared__ float wsum[kBlock / 64][3];
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
   pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
   mom += (int64_t)blockIdx.y * 3 * np;
   force += (int64_t)blockIdx.y * np;
+  if (DEPOSIT) dens += (int64_t)blockIdx.y * np;
   const int tpy = n / GTY, tpz = n / GTZ;
   const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
   const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
@@ -245,9 +256,64 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
     mom[j] = px;
     mom[np + j] = py;
     mom[2 * np + j] = pz;
-    pos[j] = wrap(x[p] + drift * px, n);
-    pos[np + j] = wrap(y[p] + drift * py, n);
-    pos[2 * np + j] = wrap(z[p] + drift * pz, n);
+    const float ux = x[p] + drift * px, uy = y[p] + drift * py, uz = z[p] + drift * pz;
+    if (DEPOSIT && !(isfinite(ux) && isfinite(uy) && isfinite(uz))) atomicAdd(&guard[0], 1u);
+    // the new positions replace the old ones in registers (used by the deposit below)
+    x[p] = wrap(ux, n);
+    y[p] = wrap(uy, n);
+    z[p] = wrap(uz, n);
+    pos[j] = x[p];
+    pos[np + j] = y[p];
+    pos[2 * np + j] = z[p];
+  }
+  if (!DEPOSIT) return;
+  __syncthreads();  // every thread is done with the force window
+  unsigned long long* dwin = reinterpret_cast<unsigned long long*>(win);
+  const TileWindow dw = tile_window<GPP>(x, y, z, n, org, DCAP, DWF, GTX * GTY * GTZ, wlo, whi, wsum);
+  const int D0 = dw.W[0], D1 = dw.W[1], D2 = dw.W[2];
+  const int dtot = D0 * D1 * D2;
+  for (int c = t; c < dtot; c += kBlock) dwin[c] = 0ull;
+  __syncthreads();
+  const int dsy = D2, dsx = D1 * D2;
+#pragma unroll
+  for (int p = 0; p < GPP; ++p) {
+    const Axis<float> ax = cic_axis(x[p], n), ay = cic_axis(y[p], n), az = cic_axis(z[p], n);
+    const int rx = idiff(ax.i0, org[0], n) - dw.o[0], ry = idiff(ay.i0, org[1], n) - dw.o[1],
+              rz = idiff(az.i0, org[2], n) - dw.o[2];
+    const float wxy00 = ax.w0 * ay.w0, wxy01 = ax.w0 * ay.w1;
+    const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
+    if (rx >= 0 && rx <= D0 - 2 && ry >= 0 && ry <= D1 - 2 && rz >= 0 && rz <= D2 - 2) {
+      unsigned long long* w = dwin + rx * dsx + ry * dsy + rz;
+      atomicAdd(w, to_fix(wxy00 * az.w0));
+      atomicAdd(w + 1, to_fix(wxy00 * az.w1));
+      atomicAdd(w + dsy, to_fix(wxy01 * az.w0));
+      atomicAdd(w + dsy + 1, to_fix(wxy01 * az.w1));
+      atomicAdd(w + dsx, to_fix(wxy10 * az.w0));
+      atomicAdd(w + dsx + 1, to_fix(wxy10 * az.w1));
+      atomicAdd(w + dsx + dsy, to_fix(wxy11 * az.w0));
+      atomicAdd(w + dsx + dsy + 1, to_fix(wxy11 * az.w1));
+    } else {
+      const int64_t r00 = ax.i0 * n2 + (int64_t)ay.i0 * n, r01 = ax.i0 * n2 + (int64_t)ay.i1 * n;
+      const int64_t r10 = ax.i1 * n2 + (int64_t)ay.i0 * n, r11 = ax.i1 * n2 + (int64_t)ay.i1 * n;
+      atomic_add(dens + r00 + az.i0, wxy00 * az.w0 * w_scale);
+      atomic_add(dens + r00 + az.i1, wxy00 * az.w1 * w_scale);
+      atomic_add(dens + r01 + az.i0, wxy01 * az.w0 * w_scale);
+      atomic_add(dens + r01 + az.i1, wxy01 * az.w1 * w_scale);
+      atomic_add(dens + r10 + az.i0, wxy10 * az.w0 * w_scale);
+      atomic_add(dens + r10 + az.i1, wxy10 * az.w1 * w_scale);
+      atomic_add(dens + r11 + az.i0, wxy11 * az.w0 * w_scale);
+      atomic_add(dens + r11 + az.i1, wxy11 * az.w1 * w_scale);
+    }
+  }
+  __syncthreads();
+  const double scale = (double)w_scale / kFix;
+  for (int c = t; c < dtot; c += kBlock) {
+    const unsigned long long v = dwin[c];
+    if (v == 0ull) continue;
+    const int a = c / dsx, b = (c / dsy) % D1, cz = c % dsy;
+    const int64_t idx = ((int64_t)fold(org[0] + dw.o[0] + a, n) * n + fold(org[1] + dw.o[1] + b, n)) * n +
+                        fold(org[2] + dw.o[2] + cz, n);
+    atomic_add(dens + idx, (float)((double)v * scale));
   }
 }
 
@@ -381,17 +447,29 @@ int launch_gather(const pm_plan* p, const void* force, const void* pos, int64_t 
   return hip_check(hipGetLastError(), "gather");
 }
 
+bool gather_kdk_can_deposit(const pm_plan* p, int64_t np) {
+  const int n = p->n;
+  return p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % GTZ == 0;
+}
+
 int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom, int64_t np, double kick,
-                      double drift, hipStream_t s) {
-  ProfScope ps(p, PK_GATHER_KDK, s);
+                      double drift, void* dens, hipStream_t s) {
+  ProfScope ps(p, dens ? PK_GATHER_KDK_DEPOSIT : PK_GATHER_KDK, s);
   if (np <= 0) return PM_OK;
   const int n = p->n;
   const int64_t fstride = (int64_t)p->nb * n * n * n;  // force meshes are [3][nb][N^3]
+  if (dens && !gather_kdk_can_deposit(p, np)) return set_error(PM_ERR_ARG, "fused deposit needs a full FP32 lattice");
   if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % GTZ == 0) {
     const unsigned tiles = (unsigned)((n / GTX) * (n / GTY) * (n / GTZ));
-    hipLaunchKernelGGL(k_gather_kdk_tiled, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s,
-                       static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), n, fstride,
-                       (float)kick, (float)drift);
+    const float w = (float)((double)n * n * n / (double)np);  // 1 / nbar
+    if (dens)
+      hipLaunchKernelGGL(k_gather_kdk_tiled<true>, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s,
+                         static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), n,
+                         fstride, (float)kick, (float)drift, static_cast<float*>(dens), w, p->guard);
+    else
+      hipLaunchKernelGGL(k_gather_kdk_tiled<false>, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s,
+                         static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), n,
+                         fstride, (float)kick, (float)drift, nullptr, 0.f, nullptr);
   } else if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_gather_kdk<float>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s,
                        static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), np, p->n,

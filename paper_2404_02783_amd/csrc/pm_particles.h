@@ -40,6 +40,14 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
+// LDS deposit windows accumulate CIC weights (<= 1) as 64-bit fixed point with scale
+// 2^32: integer LDS atomics are much faster than float ones on gfx950, and a window
+// cell cannot overflow (at most 2^31 particles per tile).
+constexpr double kFix = 4294967296.0;
+__device__ __forceinline__ unsigned long long to_fix(float w) {
+  return (unsigned long long)((double)w * kFix + 0.5);
+}
+
 // v in (-N, 2N) -> [0, N)
 __device__ __forceinline__ int fold(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 // minimum-image difference of two cell indices in [0, N): result in [-N/2, N/2]

@@ -23,6 +23,7 @@ enum ProfKind {
   PK_C2R_ROWS,
   PK_GATHER,
   PK_GATHER_KDK,
+  PK_GATHER_KDK_DEPOSIT,
   PK_COMBINE,
   PK_IC,
   PK_PK,
@@ -53,6 +54,11 @@ struct pm_plan {
   double* sums;      // device reduction scratch (estimators)
   size_t sums_cap;   // doubles in `sums`
   int device;
+  // density of which positions the second workspace region holds (left by a
+  // pm_step with PM_STEP_DEPOSIT_NEXT); any other use of the workspace clears it
+  const void* dens_pos;
+  int64_t dens_np;
+  bool dens_valid;
 };
 
 namespace pm {
@@ -105,8 +111,11 @@ int fft_pass_solve(const pm_plan* p, const pm_solve_params* sp, void* phi_state,
 int launch_fill(const pm_plan* p, void* mesh, int64_t count, double value, hipStream_t s);
 int launch_deposit(const pm_plan* p, const void* pos, int64_t np, void* mesh, hipStream_t s);
 int launch_gather(const pm_plan* p, const void* force, const void* pos, int64_t np, void* acc, hipStream_t s);
+// Gather + kick + drift; with dens non-NULL (pre-filled with -1; requires
+// gather_kdk_can_deposit) the new positions are also deposited into it.
 int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom, int64_t np, double kick,
-                      double drift, hipStream_t s);
+                      double drift, void* dens, hipStream_t s);
+bool gather_kdk_can_deposit(const pm_plan* p, int64_t np);
 int launch_combine(const void* x_gr, const void* x_n, int nc, const void* x_f, int nf, int dtype, void* x_out,
                    hipStream_t s);
 int launch_ic_lattice(const pm_plan* p, const void* disp, void* pos, void* mom, double mom_factor, hipStream_t s);

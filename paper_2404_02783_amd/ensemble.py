@@ -17,8 +17,8 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import (FIDUCIAL, ICParams, PM_PK_EH98, Plan, StepParams, kdk_factors, newton_params, pk_estimate,
-               pm_deposit, pm_ic_zeldovich, pm_step, power_eh98_amplitude)
+from . import (FIDUCIAL, ICParams, PM_PK_EH98, PM_STEP_DENSITY_READY, PM_STEP_DEPOSIT_NEXT, Plan, StepParams,
+               kdk_factors, newton_params, pk_estimate, pm_deposit, pm_ic_zeldovich, pm_step, power_eh98_amplitude)
 from .sim import log_steps
 
 __all__ = ["Group", "Ensemble", "default_groups", "schedule", "run_sequential"]
@@ -96,9 +96,12 @@ class Ensemble:
         leapfrog cycles (without the final half kick) and P(k) at a_end."""
         for st in self.states:
             pm_ic_zeldovich(st.plan, st.noise, self.ic, st.disp, st.pos, st.mom)
-        for cyc in self.cycles:
+        for j, cyc in enumerate(self.cycles):
+            # each cycle leaves the density of the drifted positions for the next one
+            fl = (PM_STEP_DENSITY_READY if j > 0 else 0) | (PM_STEP_DEPOSIT_NEXT if j + 1 < len(self.cycles) else 0)
+            c = StepParams(kick=cyc.kick, drift=cyc.drift, solve=cyc.solve, flags=fl)
             for st in self.states:
-                pm_step(st.plan, st.pos, st.mom, cyc, st.force)
+                pm_step(st.plan, st.pos, st.mom, c, st.force)
         for st in self.states:
             pm_deposit(st.plan, st.pos, st.delta)
             st.out = pk_estimate(st.plan, st.delta, st.group.bins())
@@ -139,8 +142,9 @@ def run_sequential(groups, noise_fn, a_start=0.02, a_end=1.0, n_steps=30, dtype=
         for s in g.seeds:
             noise = noises[s] if noises else torch.from_numpy(noise_fn(g.n, s)).to(dtype).to(dev)
             pm_ic_zeldovich(plan, noise, ic, disp, pos, mom)
-            for cyc in cycles:
-                pm_step(plan, pos, mom, cyc, force)
+            for j, cyc in enumerate(cycles):
+                fl = (PM_STEP_DENSITY_READY if j > 0 else 0) | (PM_STEP_DEPOSIT_NEXT if j + 1 < len(cycles) else 0)
+                pm_step(plan, pos, mom, StepParams(kick=cyc.kick, drift=cyc.drift, solve=cyc.solve, flags=fl), force)
             pm_deposit(plan, pos, delta)
             ps.append(pk_estimate(plan, delta, g.bins())[1])
         outs.append(torch.stack(ps))

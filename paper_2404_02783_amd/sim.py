@@ -11,7 +11,8 @@ from __future__ import annotations
 
 import math
 
-from . import (FIDUCIAL, PM_GRAD_SPECTRAL, Plan, StepParams, gauge_params, kdk_factors, newton_params, pm_step)
+from . import (FIDUCIAL, PM_GRAD_SPECTRAL, PM_STEP_DENSITY_READY, PM_STEP_DEPOSIT_NEXT, Plan, StepParams,
+               gauge_params, kdk_factors, newton_params, pm_step)
 
 __all__ = ["log_steps", "Run"]
 
@@ -23,13 +24,20 @@ def log_steps(a_start: float, a_end: float, n_steps: int):
 
 class Run:
     """Particles (pos, mom) of one set on one plan.  ``gauge=True`` selects the
-    Poisson-gauge force; otherwise Newtonian."""
+    Poisson-gauge force; otherwise Newtonian.  Consecutive cycles hand the density of
+    the drifted positions to the next cycle (PM_STEP_DEPOSIT_NEXT / DENSITY_READY);
+    call ``invalidate()`` after changing ``pos`` or using the plan for anything else
+    between cycles."""
 
     def __init__(self, plan: Plan, pos, mom, cosmo=FIDUCIAL, gauge: bool = False, grad: int = PM_GRAD_SPECTRAL):
         self.plan, self.pos, self.mom, self.cosmo, self.gauge, self.grad = plan, pos, mom, cosmo, gauge, grad
         self.force = plan.mesh(3)
         self.phi = plan.spectrum() if gauge else None
         self.a_prev = 0.0
+        self.dens_ready = False
+
+    def invalidate(self):
+        self.dens_ready = False
 
     def solve_params(self, a: float):
         if self.gauge:
@@ -39,9 +47,12 @@ class Run:
             sp = newton_params(self.cosmo, self.grad)
         return sp
 
-    def cycle(self, a: float, kick: float, drift: float):
-        st = StepParams(kick=kick, drift=drift, solve=self.solve_params(a))
+    def cycle(self, a: float, kick: float, drift: float, last: bool = False):
+        flags = (PM_STEP_DENSITY_READY if self.dens_ready else 0) | (0 if last else PM_STEP_DEPOSIT_NEXT)
+        st = StepParams(kick=kick, drift=drift, solve=self.solve_params(a), flags=flags)
+        self.dens_ready = False
         pm_step(self.plan, self.pos, self.mom, st, self.force, self.phi)
+        self.dens_ready = not last
         self.a_prev = a
 
     def leapfrog(self, a_steps, close: bool = True, on_cycle=None):
@@ -54,4 +65,6 @@ class Run:
             if on_cycle is not None:
                 on_cycle(j)
         if close:
-            self.cycle(a_steps[-1], k2_prev, 0.0)
+            self.cycle(a_steps[-1], k2_prev, 0.0, last=True)
+        else:
+            self.invalidate()

@@ -378,3 +378,68 @@ def test_paired_run_32_fp64():
         _, wpk, wcnt = estimators.power_spectrum(cic.deposit_delta(x.cpu(), n), box, 16)
         assert torch.equal(cnt.cpu(), wcnt)
         assert rel_l2(pk, wpk) < 1e-10
+
+
+# ------------------------------------------- density handed to the next cycle --
+
+@pytest.mark.parametrize("dt,n,amp", [(torch.float32, 128, 0.8), (torch.float32, 64, 6.0), (torch.float64, 32, 0.8)])
+def test_step_density_handoff_matches_plain_cycles(dt, n, amp):
+    """Cycles that leave the drifted positions' density for the next cycle (fused into
+    the gather for full FP32 lattices, a separate deposit otherwise) reproduce plain
+    cycles."""
+    dev = _dev()
+    x0 = torch.from_numpy(si.lattice_jitter_particles(n, 81, amp)).to(dt)
+    x0[x0 >= n] = 0
+    p0 = (0.2 * torch.from_numpy(si.rng(82).standard_normal((3, n ** 3)))).to(dt)
+    plan = pm.Plan(n, 300.0, dt)
+    force = plan.mesh(3)
+    res = []
+    for fused in (False, True):
+        x, p = x0.clone().to(dev).contiguous(), p0.clone().to(dev).contiguous()
+        for j in range(3):
+            fl = 0
+            if fused:
+                fl = (pm.PM_STEP_DENSITY_READY if j > 0 else 0) | (pm.PM_STEP_DEPOSIT_NEXT if j < 2 else 0)
+            pm.pm_step(plan, x, p, pm.StepParams(kick=0.3, drift=0.4, solve=pm.newton_params(), flags=fl), force)
+        torch.cuda.synchronize()
+        pm.pm_check(plan)
+        res.append((x.double().cpu(), p.double().cpu()))
+    tol = 1e-6 if dt == torch.float32 else 1e-12
+    assert float(min_image(res[1][0] - res[0][0], n).abs().max()) < tol * n
+    assert rel_l2(res[1][1], res[0][1]) < tol
+
+
+def test_step_density_ready_is_checked():
+    dev = _dev()
+    n = 64
+    plan = pm.Plan(n, 300.0, torch.float32)
+    x = torch.from_numpy(si.lattice_jitter_particles(n, 83, 0.5)).to(torch.float32).to(dev).contiguous()
+    p = torch.zeros_like(x)
+    force = plan.mesh(3)
+    sp = pm.newton_params()
+    ready, nxt = pm.PM_STEP_DENSITY_READY, pm.PM_STEP_DEPOSIT_NEXT
+    with pytest.raises(pm.PMError) as e:            # nothing deposited yet
+        pm.pm_step(plan, x, p, pm.StepParams(kick=0.1, drift=0.1, solve=sp, flags=ready), force)
+    assert e.value.code == -5
+    pm.pm_step(plan, x, p, pm.StepParams(kick=0.1, drift=0.1, solve=sp, flags=nxt), force)
+    pm.pm_deposit(plan, x)                          # any other call discards the density
+    with pytest.raises(pm.PMError):
+        pm.pm_step(plan, x, p, pm.StepParams(kick=0.1, drift=0.1, solve=sp, flags=ready), force)
+    pm.pm_step(plan, x, p, pm.StepParams(kick=0.1, drift=0.1, solve=sp, flags=nxt), force)
+    with pytest.raises(pm.PMError):                 # other positions
+        pm.pm_step(plan, x.clone(), p, pm.StepParams(kick=0.1, drift=0.1, solve=sp, flags=ready), force)
+    torch.cuda.synchronize()
+
+
+def test_step_fused_deposit_counts_non_finite_positions():
+    dev = _dev()
+    n = 64
+    plan = pm.Plan(n, 300.0, torch.float32)
+    x = torch.from_numpy(si.lattice_jitter_particles(n, 84, 0.5)).to(torch.float32).to(dev).contiguous()
+    p = torch.zeros_like(x)
+    p[0, 5] = float("nan")
+    st = pm.StepParams(kick=0.1, drift=0.1, solve=pm.newton_params(), flags=pm.PM_STEP_DEPOSIT_NEXT)
+    pm.pm_step(plan, x, p, st, plan.mesh(3))
+    with pytest.raises(pm.PMError) as e:
+        pm.pm_check(plan)
+    assert e.value.code == -5
