@@ -104,25 +104,18 @@ constexpr int GWF = 16;                        // fallback box side (GWF^3 <= GC
 // the positions again.
 constexpr int DCAP = 3 * GCAP * (int)sizeof(float) / (int)sizeof(unsigned long long);
 constexpr int DWF = 18;  // fallback deposit box side (DWF^3 <= DCAP)
-template <bool DEPOSIT>
-__global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
-                                                             float* __restrict__ mom, int n, int64_t fstride,
-                                                             float kick, float drift, float* __restrict__ dens,
-                                                             float w_scale, unsigned* __restrict__ guard) {
-  __shared__ __attribute__((aligned(16))) float win[3 * GCAP];
-  __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
-  __shared__ float wsum[kBlock / 64][3];
+// Gather + kick + drift of one GTX x GTY x GTZ Lagrangian tile at `org` (block-wide):
+// stages the three force meshes over the tile's CIC bounding box in `win`, updates
+// (pos, mom) and leaves the drifted, wrapped positions in (x, y, z).  GUARD counts
+// non-finite drifted positions in guard[0].
+template <bool GUARD>
+__device__ __forceinline__ void gather_tile(const float* __restrict__ force, float* __restrict__ pos,
+                                            float* __restrict__ mom, int n, int64_t fstride, float kick, float drift,
+                                            const int (&org)[3], float* win, int (*wlo)[3], int (*whi)[3],
+                                            float (*wsum)[3], float (&x)[GPP], float (&y)[GPP], float (&z)[GPP],
+                                            unsigned* __restrict__ guard) {
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
-  pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
-  mom += (int64_t)blockIdx.y * 3 * np;
-  force += (int64_t)blockIdx.y * np;
-  if (DEPOSIT) dens += (int64_t)blockIdx.y * np;
-  const int tpy = n / GTY, tpz = n / GTZ;
-  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
-  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
-  const int org[3] = {ti * GTX, tk * GTY, tl * GTZ};
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  float x[GPP], y[GPP], z[GPP];
   int64_t jj[GPP];
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
   float sum[3] = {0.f, 0.f, 0.f};
@@ -257,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
     mom[np + j] = py;
     mom[2 * np + j] = pz;
     const float ux = x[p] + drift * px, uy = y[p] + drift * py, uz = z[p] + drift * pz;
-    if (DEPOSIT && !(isfinite(ux) && isfinite(uy) && isfinite(uz))) atomicAdd(&guard[0], 1u);
+    if (GUARD && !(isfinite(ux) && isfinite(uy) && isfinite(uz))) atomicAdd(&guard[0], 1u);
     // the new positions replace the old ones in registers (used by the deposit below)
     x[p] = wrap(ux, n);
     y[p] = wrap(uy, n);
@@ -266,17 +259,54 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
     pos[np + j] = y[p];
     pos[2 * np + j] = z[p];
   }
+}
+
+// One workgroup per NT tiles adjacent along x (NT = 2 with DEPOSIT: their deposit
+// windows are merged, so the halo they share is flushed once).
+template <bool DEPOSIT>
+__global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
+                                                             float* __restrict__ mom, int n, int64_t fstride,
+                                                             float kick, float drift, float* __restrict__ dens,
+                                                             float w_scale, unsigned* __restrict__ guard) {
+  constexpr int NT = DEPOSIT ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) float win[3 * GCAP];
+  __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
+  __shared__ float wsum[kBlock / 64][3];
+  const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
+  mom += (int64_t)blockIdx.y * 3 * np;
+  force += (int64_t)blockIdx.y * np;
+  if (DEPOSIT) dens += (int64_t)blockIdx.y * np;
+  const int tpy = n / GTY, tpz = n / GTZ;
+  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
+  const int t = threadIdx.x;
+  float x[NT * GPP], y[NT * GPP], z[NT * GPP];
+#pragma unroll
+  for (int sub = 0; sub < NT; ++sub) {
+    const int orgs[3] = {(ti * NT + sub) * GTX, tk * GTY, tl * GTZ};
+    float xs[GPP], ys[GPP], zs[GPP];
+    if (sub > 0) __syncthreads();  // the previous tile is done with the window
+    gather_tile<DEPOSIT>(force, pos, mom, n, fstride, kick, drift, orgs, win, wlo, whi, wsum, xs, ys, zs, guard);
+#pragma unroll
+    for (int p = 0; p < GPP; ++p) {
+      x[sub * GPP + p] = xs[p];
+      y[sub * GPP + p] = ys[p];
+      z[sub * GPP + p] = zs[p];
+    }
+  }
   if (!DEPOSIT) return;
   __syncthreads();  // every thread is done with the force window
   unsigned long long* dwin = reinterpret_cast<unsigned long long*>(win);
-  const TileWindow dw = tile_window<GPP>(x, y, z, n, org, DCAP, DWF, GTX * GTY * GTZ, wlo, whi, wsum);
+  const int org[3] = {ti * NT * GTX, tk * GTY, tl * GTZ};
+  const TileWindow dw = tile_window<NT * GPP>(x, y, z, n, org, DCAP, DWF, NT * GTX * GTY * GTZ, wlo, whi, wsum);
   const int D0 = dw.W[0], D1 = dw.W[1], D2 = dw.W[2];
   const int dtot = D0 * D1 * D2;
   for (int c = t; c < dtot; c += kBlock) dwin[c] = 0ull;
   __syncthreads();
   const int dsy = D2, dsx = D1 * D2;
 #pragma unroll
-  for (int p = 0; p < GPP; ++p) {
+  for (int p = 0; p < NT * GPP; ++p) {
     const Axis<float> ax = cic_axis(x[p], n), ay = cic_axis(y[p], n), az = cic_axis(z[p], n);
     const int rx = idiff(ax.i0, org[0], n) - dw.o[0], ry = idiff(ay.i0, org[1], n) - dw.o[1],
               rz = idiff(az.i0, org[2], n) - dw.o[2];
@@ -463,7 +493,7 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
     const unsigned tiles = (unsigned)((n / GTX) * (n / GTY) * (n / GTZ));
     const float w = (float)((double)n * n * n / (double)np);  // 1 / nbar
     if (dens)
-      hipLaunchKernelGGL(k_gather_kdk_tiled<true>, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL(k_gather_kdk_tiled<true>, dim3(tiles / 2, (unsigned)p->nb), dim3(kBlock), 0, s,
                          static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), n,
                          fstride, (float)kick, (float)drift, static_cast<float*>(dens), w, p->guard);
     else
