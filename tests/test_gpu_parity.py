@@ -280,6 +280,11 @@ def test_bk_estimate(dt):
     bk2, ntri2 = pm.bk_estimate(plan, delta.to(dt).to(dev), centres, 1.0, tris, ntri_known=ntri)
     assert torch.allclose(bk2, bk, rtol=1e-12, atol=0)
     assert torch.equal(ntri2, ntri)
+    # with room for only three shell fields, shells are evicted and recomputed between batches
+    ws3 = torch.empty((3, n, n, n), dtype=dt, device=dev)
+    bk3, ntri3 = pm.bk_estimate(plan, delta.to(dt).to(dev), centres, 1.0, tris, shell_ws=ws3)
+    assert rel_l2(ntri3, wn) < _tol(dt)
+    assert rel_l2(bk3, wb) < (1e-4 if dt == torch.float32 else F64_TOL)
 
 
 # ---------------------------------------------------------------- ICs ------
