@@ -17,6 +17,8 @@ Module map (paper passages in each function's docstring):
   combine     -- GR-minus-Newton displacement and its addition to a fine run
   estimators  -- power spectrum and FFT bispectrum estimators
   adjoint     -- loss on P(k) and its reference gradient
+  planar      -- the Newtonian cycle of a plane-parallel lattice reduced to one
+                 dimension (expected values of full-size runs, sampled per particle)
 
 Parity status: every function is pinned by a closed form, an invariant, a
 brute-force evaluation or a statistical expectation in ``tests/test_oracle_*``,
@@ -24,4 +26,4 @@ except the Eisenstein-Hu no-wiggle transfer-function constants, which are
 recalled from the published fitting formula and only pinned by their limits
 ("parity unpinned" for the constants themselves).
 """
-from . import cosmology, cic, fourier, solve, ics, integrate, combine, estimators, adjoint  # noqa: F401
+from . import cosmology, cic, fourier, solve, ics, integrate, combine, estimators, adjoint, planar  # noqa: F401

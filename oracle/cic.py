@@ -73,3 +73,16 @@ def gather(mesh: torch.Tensor, pos: torch.Tensor) -> torch.Tensor:
         term = flat[..., idx] * w
         out = term if out is None else out + term
     return out
+
+
+def rho_at_nodes(nodes: torch.Tensor, pos: torch.Tensor, n: int) -> torch.Tensor:
+    """rho(c) = sum_p W(x_p - c) at the nodes ``nodes`` ([3, M] integer) from the
+    particles ``pos`` ([3, Np]) only, written as the product over axes of the
+    periodic tent max(0, 1 - |x_d - c_d|) (minimum-image distance).  This is the
+    CIC weight above seen from the node: a particle within one cell of the node
+    along every axis gives it 1 - |x_d - c_d| per axis.  Returns [M]."""
+    c = nodes.to(torch.float64).unsqueeze(-1)          # [3, M, 1]
+    x = pos.to(torch.float64).unsqueeze(1)             # [3, 1, Np]
+    d = torch.remainder(x - c + n / 2, n) - n / 2
+    w = torch.clamp(1.0 - d.abs(), min=0.0).prod(dim=0)
+    return w.sum(dim=-1)
