@@ -63,3 +63,20 @@ def combine(x_gr: torch.Tensor, x_n: torch.Tensor, n_c: int, x_fine: torch.Tenso
     xi = xi_min_image(x_gr, x_n, n_c)
     xi_f = xi if n_f == n_c else interpolate_lagrangian(xi, n_c, n_f)
     return cic.wrap(x_fine + (n_f / n_c) * xi_f, n_f)
+
+
+def combine_at(x_gr: torch.Tensor, x_n: torch.Tensor, n_c: int, x_fine: torch.Tensor, j_fine: torch.Tensor,
+               n_f: int) -> torch.Tensor:
+    """``combine`` for a sample of fine particles only: j_fine [3, M] are their
+    lattice indices per axis, x_fine [3, M] their positions.  xi is evaluated at the
+    eight coarse particles around each fine lattice point (same weights and wrap)."""
+    i0_ax, t_ax = fine_to_coarse_axis(n_c, n_f)
+    i0 = torch.stack([i0_ax[j_fine[d]] for d in range(3)])
+    t = torch.stack([t_ax[j_fine[d]] for d in range(3)])
+    xi_f = torch.zeros(x_fine.shape, dtype=torch.float64)
+    for dx, dy, dz in itertools.product((0, 1), repeat=3):
+        c = [(i0[0] + dx) % n_c, (i0[1] + dy) % n_c, (i0[2] + dz) % n_c]
+        idx = (c[0] * n_c + c[1]) * n_c + c[2]
+        w = (t[0] if dx else 1.0 - t[0]) * (t[1] if dy else 1.0 - t[1]) * (t[2] if dz else 1.0 - t[2])
+        xi_f = xi_f + xi_min_image(x_gr[:, idx], x_n[:, idx], n_c) * w
+    return cic.wrap(x_fine + (n_f / n_c) * xi_f, n_f)

@@ -130,3 +130,96 @@ def brute_bispectrum(delta: torch.Tensor, box: float, centres, width: float, tri
         out_b.append(vol ** 2 / n ** 9 * tot.real / cnt if cnt else 0.0)
         out_n.append(float(cnt))
     return torch.tensor(out_b, dtype=torch.float64), torch.tensor(out_n, dtype=torch.float64)
+
+
+def power_spectrum_sparse(modes: torch.Tensor, values: torch.Tensor, n: int, box: float, n_bins: int):
+    """``power_spectrum_from_k`` of an r2c spectrum that vanishes except at the stored
+    modes ``modes`` ([M, 3]: n_x, n_y in [-N/2, N/2), n_z in [0, N/2]) with amplitudes
+    ``values``.  Mode counts and mean |k| run over every mode, one n_x plane at a time,
+    so no N^3 array is formed."""
+    full = torch.fft.fftfreq(n, d=1.0 / n).round().long()
+    nz = torch.arange(n // 2 + 1, dtype=torch.long)
+    wz = torch.full((n // 2 + 1,), 2.0, dtype=torch.float64)
+    wz[0] = 1.0
+    wz[n // 2] = 1.0
+    cnt = torch.zeros(n_bins, dtype=torch.float64)
+    sk = torch.zeros(n_bins, dtype=torch.float64)
+
+    def bin_of(s):
+        # the b with N^2 (2b+1)^2 <= 16 n_bins^2 |n|^2 < N^2 (2b+3)^2: a float guess of
+        # b = floor((4 n_bins |n| / N - 1) / 2), then the integer inequalities settle it
+        q = 16 * n_bins * n_bins * s
+        b = torch.floor((4.0 * n_bins * torch.sqrt(s.double()) / n - 1.0) / 2.0).long()
+        for _ in range(2):
+            b = torch.where(n * n * (2 * b + 1) ** 2 > q, b - 1, b)
+            b = torch.where(n * n * (2 * b + 3) ** 2 <= q, b + 1, b)
+        return torch.where((b >= 0) & (b < n_bins), b, torch.full_like(b, -1))
+
+    yz = full.view(n, 1) ** 2 + nz.view(1, n // 2 + 1) ** 2
+    w_plane = wz.view(1, -1).expand(n, n // 2 + 1).reshape(-1)
+    # planes n_x and -n_x hold the same |n|: visit |n_x| once with its multiplicity
+    for ax in range(n // 2 + 1):
+        mult = 1.0 if ax in (0, n // 2) else 2.0
+        s = (ax * ax + yz).reshape(-1)
+        b = bin_of(s)
+        sel = b >= 0
+        cnt.index_add_(0, b[sel], mult * w_plane[sel])
+        sk.index_add_(0, b[sel], (mult * w_plane * torch.sqrt(s.double()))[sel])
+    m = modes.long()
+    s = (m * m).sum(dim=1)
+    b = bin_of(s)
+    wt = wz[m[:, 2]]
+    p2 = values.real ** 2 + values.imag ** 2
+    sp = torch.zeros(n_bins, dtype=torch.float64)
+    sel = b >= 0
+    sp.index_add_(0, b[sel], (wt * p2)[sel])
+    kf = 2.0 * math.pi / box
+    safe = torch.where(cnt > 0, cnt, torch.ones_like(cnt))
+    pk = torch.where(cnt > 0, box ** 3 / n ** 6 * sp / safe, torch.zeros_like(cnt))
+    km = torch.where(cnt > 0, kf * sk / safe, torch.zeros_like(cnt))
+    return km, pk, cnt.round().long()
+
+
+def _in_shell(m: torch.Tensor, centre: float, width: float) -> torch.Tensor:
+    # the float64 decision of shell_mask on integer modes [..., 3]
+    s4 = 4.0 * (m * m).sum(dim=-1).double()
+    return (s4 >= (2.0 * centre - width) ** 2) & (s4 < (2.0 * centre + width) ** 2)
+
+
+def _fold(v: torch.Tensor, n: int) -> torch.Tensor:
+    return torch.remainder(v + n // 2, n) - n // 2
+
+
+def shell_modes(n: int, centre: float, width: float) -> torch.Tensor:
+    """Full-cube modes (components in [-N/2, N/2)) of the shell used by ``shell_mask``, [K, 3]."""
+    r = min(int(math.ceil(centre + 0.5 * width)) + 1, n // 2)
+    ax = torch.arange(-r, min(r, n // 2 - 1) + 1, dtype=torch.long)
+    g = torch.stack(torch.meshgrid(ax, ax, ax, indexing="ij"), dim=-1).reshape(-1, 3)
+    return g[_in_shell(g, centre, width)]
+
+
+def triangle_count(n: int, centres, width: float, tri) -> int:
+    """N_tri of ``bispectrum``: ordered (p, q, r) in S_a x S_b x S_c with p + q + r = 0
+    modulo N, counted by brute force (enumerating the two smallest shells)."""
+    shells = [shell_modes(n, centres[s], width) for s in tri]
+    order = sorted(range(3), key=lambda i: shells[i].shape[0])
+    sp, sq = shells[order[0]], shells[order[1]]
+    ck = centres[tri[order[2]]]
+    total = 0
+    for i0 in range(0, sp.shape[0], 256):
+        p = sp[i0:i0 + 256]
+        r = _fold(-(p.unsqueeze(1) + sq.unsqueeze(0)), n)
+        total += int(_in_shell(r, ck, width).sum())
+    return total
+
+
+def bispectrum_numerator_sparse(modes: torch.Tensor, values: torch.Tensor, n: int, centres, width: float, tri):
+    """sum over ordered closed triples (p + q + r = 0 modulo N) with p in S_a, q in S_b,
+    r in S_c of dhat(p) dhat(q) dhat(r), for a full-cube spectrum that vanishes except
+    at ``modes`` (components in [-N/2, N/2)) with amplitudes ``values``."""
+    m = modes.long()
+    ia, ib, ic = (_in_shell(m, centres[s], width) for s in tri)
+    closed = (_fold(m.view(-1, 1, 1, 3) + m.view(1, -1, 1, 3) + m.view(1, 1, -1, 3), n) == 0).all(dim=-1)
+    mask = closed & ia.view(-1, 1, 1) & ib.view(1, -1, 1) & ic.view(1, 1, -1)
+    prod = values.view(-1, 1, 1) * values.view(1, -1, 1) * values.view(1, 1, -1)
+    return complex(prod[mask].sum()) if bool(mask.any()) else 0j

@@ -70,3 +70,42 @@ def brute_dft3(d: torch.Tensor) -> torch.Tensor:
     phase = -2.0 * math.pi * (k @ x.T) / n
     mat = torch.complex(torch.cos(phase), torch.sin(phase))
     return (mat @ d.reshape(-1).to(torch.complex128)).reshape(n, n, n)
+
+
+def plane_wave_modes(waves, n: int):
+    """Stored r2c modes of sum_j A_j cos(2 pi m_j . x / N + phase_j): the DFT of a cosine
+    is (N^3 A / 2) e^{+i phase} at +m and its conjugate at -m; the r2c half keeps the
+    partner with n_z in (0, N/2), and both partners when n_z = 0 or N/2.  Returns
+    (modes [M, 3] int64: n_x, n_y in [-N/2, N/2), n_z in [0, N/2]; values [M]
+    complex128); wavevectors are reduced modulo N and coinciding modes are summed."""
+    acc = {}
+
+    def add(m, v):
+        key = (((int(m[0]) + n // 2) % n) - n // 2, ((int(m[1]) + n // 2) % n) - n // 2, int(m[2]) % n)
+        if key[2] > n // 2:
+            return  # the conjugate partner is the stored one
+        acc[key] = acc.get(key, 0j) + v
+
+    for amp, m, ph in waves:
+        v = 0.5 * amp * n ** 3 * complex(math.cos(ph), math.sin(ph))
+        add(m, v)
+        add(tuple(-c for c in m), v.conjugate())
+    keys = sorted(acc)
+    modes = torch.tensor(keys, dtype=torch.long).view(-1, 3)
+    vals = torch.tensor([acc[k] for k in keys], dtype=torch.complex128)
+    return modes, vals
+
+
+def plane_wave_modes_full(waves, n: int):
+    """Full-cube DFT of sum_j A_j cos(2 pi m_j . x / N + phase_j): (N^3 A / 2) e^{+i phase}
+    at +m and its conjugate at -m, components reduced to [-N/2, N/2), coinciding
+    modes summed.  Returns (modes [M, 3] int64, values [M] complex128)."""
+    acc = {}
+    for amp, m, ph in waves:
+        v = 0.5 * amp * n ** 3 * complex(math.cos(ph), math.sin(ph))
+        for sgn, val in ((1, v), (-1, v.conjugate())):
+            key = tuple(((sgn * int(c) + n // 2) % n) - n // 2 for c in m)
+            acc[key] = acc.get(key, 0j) + val
+    keys = sorted(acc)
+    return (torch.tensor(keys, dtype=torch.long).view(-1, 3),
+            torch.tensor([acc[k] for k in keys], dtype=torch.complex128))

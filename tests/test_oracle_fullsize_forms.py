@@ -1,0 +1,159 @@
+"""Pins of the oracle's forms for full-size (1024^3) parity, where the oracle
+evaluates sampled outputs one by one: the node-centred CIC density, the
+plane-parallel reduction of the cycle, the combination at sampled particles, the
+spectrum of a sum of plane waves and the P(k) estimator of a sparse spectrum.
+Each is pinned against the independent dense oracle (corner-enumerated deposit;
+3-D Fourier solve, gather, kick and drift; dense combine; 3-D DFT; dense
+estimator) on small meshes, where the two must agree to rounding."""
+import math
+
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import cic, cosmology as ocm, integrate, planar, solve
+
+
+def test_rho_at_nodes_equals_corner_deposit():
+    n = 8
+    x = torch.from_numpy(si.uniform_particles(n, 300, 4))
+    rho = cic.deposit_rho(x, n)
+    g = torch.arange(n)
+    nodes = torch.stack(torch.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    got = cic.rho_at_nodes(nodes, x, n)
+    assert torch.allclose(got, rho.reshape(-1), atol=1e-12)
+    assert float(got.sum()) == pytest.approx(300.0, rel=1e-13)
+
+
+def test_rho_at_nodes_wraps_and_ignores_far_particles():
+    n = 16
+    # a particle at 15.25 along x shares its weight between nodes 15 (0.75) and 0 (0.25)
+    x = torch.tensor([[15.25, 7.0], [3.0, 7.0], [4.0, 7.0]], dtype=torch.float64)
+    nodes = torch.tensor([[15, 0, 14, 7], [3, 3, 3, 7], [4, 4, 4, 7]])
+    got = cic.rho_at_nodes(nodes, x, n)
+    assert got.tolist() == pytest.approx([0.75, 0.25, 0.0, 1.0], abs=1e-15)
+
+
+def _planar_case(n, axis, seed, offset):
+    coord, mom = si.planar_profile(n, axis, seed, amp_log2=1, mom_log2=-1)
+    coord[(axis + 1) % 3] = offset
+    c = coord.double() * si.QUANTUM
+    m = mom.double() * si.QUANTUM
+    pos, p3 = si.expand_planar(coord, mom, n, axis, dtype=torch.float64)
+    return c, m, pos, p3
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("grad", ["spectral", "fd2", "fd1"])
+def test_planar_cycle_equals_3d_oracle(axis, grad):
+    n = 16
+    om = ocm.FIDUCIAL.omega_m
+    c, m, pos, p3 = _planar_case(n, axis, 20 + axis, 3 * 8192 + 77)
+    kick, drift = 0.8, 1.7
+    c1, m1, f1 = planar.cycle_line(c, m, axis, kick, drift, n, om, grad)
+
+    meshes = solve.newton_forces(cic.deposit_delta(pos, n), om, grad)
+    want = torch.zeros_like(meshes)
+    shape = [1, 1, 1]
+    shape[axis] = n
+    want[axis] = f1.view(shape).expand(n, n, n)
+    assert torch.allclose(meshes, want, atol=1e-12)
+
+    wx, wv = integrate.force_then_kick_drift(pos, p3, kick, drift, integrate.NewtonForce(n, grad=grad), 0.0, n)
+    g = torch.arange(n)
+    q = torch.stack(torch.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    got_x = planar.particle_coords(c1, axis, n, q)
+    d = torch.remainder(got_x - wx + n / 2, n) - n / 2
+    assert float(d.abs().max()) < 1e-12
+    assert torch.allclose(m1[:, q[axis]], wv, atol=1e-12)
+
+
+def test_planar_density_is_mass_conserving_and_uniform_lattice_is_force_free():
+    n = 32
+    om = ocm.FIDUCIAL.omega_m
+    x = torch.arange(n, dtype=torch.float64) + 0.5
+    assert torch.allclose(planar.deposit_delta_line(x, n), torch.zeros(n, dtype=torch.float64), atol=1e-15)
+    coord, _ = si.planar_profile(n, 0, 3)
+    d = planar.deposit_delta_line(coord[0].double() * si.QUANTUM, n)
+    assert abs(float(d.sum())) < 1e-12
+    assert float(planar.newton_force_line(d, om).sum()) == pytest.approx(0.0, abs=1e-12)
+
+
+# ------------------------------------------------------------- sampled forms --
+
+def test_combine_at_equals_dense_combine():
+    from oracle import combine as ocomb
+    for nc, nf in ((8, 32), (8, 8), (4, 12)):
+        xg = torch.from_numpy(si.lattice_jitter_particles(nc, 3, 1.7))
+        xn = torch.from_numpy(si.lattice_jitter_particles(nc, 4, 1.7))
+        xf = torch.from_numpy(si.lattice_jitter_particles(nf, 5, 0.9))
+        want = ocomb.combine(xg, xn, nc, xf, nf)
+        idx = torch.arange(0, nf ** 3, 7)
+        j = torch.stack([idx // (nf * nf), (idx // nf) % nf, idx % nf])
+        got = ocomb.combine_at(xg, xn, nc, xf[:, idx], j, nf)
+        assert torch.allclose(got, want[:, idx], atol=1e-12)
+
+
+def test_plane_wave_modes_equal_rfft():
+    from oracle import fourier
+    n = 8
+    waves = [(0.3, (1, -2, 3), 0.4), (0.2, (4, 0, 0), 1.1), (0.1, (0, 3, 4), 2.0), (0.05, (-3, 1, 0), 0.3),
+             (0.07, (1, 2, -3), 0.9)]
+    x = torch.arange(n, dtype=torch.float64)
+    g = torch.stack(torch.meshgrid(x, x, x, indexing="ij"))
+    d = sum(a * torch.cos(2 * math.pi * (m[0] * g[0] + m[1] * g[1] + m[2] * g[2]) / n + ph) for a, m, ph in waves)
+    dh = fourier.rfft3(d)
+    modes, vals = fourier.plane_wave_modes(waves, n)
+    want = torch.zeros_like(dh)
+    for (mx, my, mz), v in zip(modes.tolist(), vals.tolist()):
+        want[mx % n, my % n, mz] += v
+    assert torch.allclose(dh, want, atol=1e-9)
+
+
+@pytest.mark.parametrize("n,nb", [(16, 8), (32, 16), (24, 5)])
+def test_power_spectrum_sparse_equals_dense(n, nb):
+    from oracle import estimators, fourier
+    g = torch.Generator().manual_seed(n)
+    dh = torch.zeros((n, n, n // 2 + 1), dtype=torch.complex128)
+    pick = torch.randint(0, n * n * (n // 2 + 1), (40,), generator=g)
+    vals = torch.randn(40, generator=g, dtype=torch.float64) + 1j * torch.randn(40, generator=g, dtype=torch.float64)
+    dh.view(-1)[pick] = vals
+    nxf, nyf, nzf = fourier.int_freqs(n)
+    flat = torch.nonzero(dh.abs().reshape(-1) > 0).view(-1)
+    ix, iy, iz = flat // (n * (n // 2 + 1)), (flat // (n // 2 + 1)) % n, flat % (n // 2 + 1)
+    modes = torch.stack([nxf.view(-1)[ix], nyf.view(-1)[iy], nzf.view(-1)[iz]], 1)
+    km, pk, cnt = estimators.power_spectrum_sparse(modes, dh.reshape(-1)[flat], n, 700.0, nb)
+    wkm, wpk, wcnt = estimators.power_spectrum_from_k(dh, n, 700.0, nb)
+    assert torch.equal(cnt, wcnt)
+    assert torch.allclose(km, wkm, rtol=1e-12)
+    assert torch.allclose(pk, wpk, rtol=1e-12, atol=0)
+
+
+def test_sparse_bispectrum_pieces_equal_dense_estimator():
+    from oracle import estimators, fourier
+    n, box = 16, 300.0
+    waves = [(0.3, (3, 0, 0), 0.2), (0.25, (-1, 3, 0), 0.9), (0.2, (-2, -3, 0), 1.7), (0.1, (7, 1, -1), 0.4),
+             (0.1, (-7, 6, 1), 2.2), (0.05, (0, -7, 0), 0.0),
+             # closes only modulo N: (7,0,0) + (7,1,0) + (2,-1,0) = (16,0,0)
+             (0.1, (7, 0, 0), 0.5), (0.12, (7, 1, 0), 1.3), (0.08, (2, -1, 0), 2.9)]
+    x = torch.arange(n, dtype=torch.float64)
+    g = torch.stack(torch.meshgrid(x, x, x, indexing="ij"))
+    d = sum(a * torch.cos(2 * math.pi * (m[0] * g[0] + m[1] * g[1] + m[2] * g[2]) / n + ph) for a, m, ph in waves)
+    centres, width = [3.0, 7.0, 5.0], 2.0
+    tris = [(0, 0, 0), (1, 1, 1), (0, 0, 2), (1, 1, 0), (2, 1, 1)]
+    wb, wn = estimators.bispectrum(d, box, centres, width, tris)
+    modes, vals = fourier.plane_wave_modes_full(waves, n)
+    full = torch.fft.fftn(d.to(torch.complex128))
+    got_full = torch.zeros_like(full)
+    for (a, b, c), v in zip(modes.tolist(), vals.tolist()):
+        got_full[a % n, b % n, c % n] += v
+    assert torch.allclose(full, got_full, atol=1e-9)
+    nonzero = 0
+    for t, tri in enumerate(tris):
+        cnt = estimators.triangle_count(n, centres, width, tri)
+        assert cnt == pytest.approx(float(wn[t]), abs=1e-6)
+        num = estimators.bispectrum_numerator_sparse(modes, vals, n, centres, width, tri)
+        want = box ** 6 / n ** 9 * num.real / cnt if cnt else 0.0
+        assert want == pytest.approx(float(wb[t]), rel=1e-9, abs=1e-9 * float(wb.abs().max()))
+        nonzero += abs(num) > 0
+    assert nonzero >= 2   # the direct triangle in shell 0 and the aliased one in (1, 1, 0)
