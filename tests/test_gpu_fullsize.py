@@ -12,7 +12,15 @@ at a time, or a property that holds at any size:
     positions, sampled momenta and force nodes;
   * step on a generic lattice: the total kick vanishes (deposit and gather share
     their weights and the gradient symbol is odd), and the density handed between
-    cycles reproduces the density of a fresh deposit.
+    cycles reproduces the density of a fresh deposit;
+  * P(k) in 256 bins of a plane-wave field: bit-exact mode counts, mean |k| and
+    powers against the oracle's estimator of the sparse spectrum;
+  * B(k) on the benchmark's 64 triangle configurations of a field of plane waves
+    that close triangles in several of them: the triple sums against the oracle's
+    sum over the sparse modes, and the triangle counts of the smaller shells against
+    brute force;
+  * the combination of a 256^3 pair into a 1024^3 run: sampled fine particles
+    against the oracle's combination at those particles.
 Inputs are multiples of 2^-13 cells, exact in FP32 and FP64, so the oracle sees the
 very numbers the kernels see.
 """
@@ -22,7 +30,7 @@ import pytest
 import torch
 
 import synth_inputs as si
-from oracle import cic, cosmology as ocm, planar
+from oracle import cic, combine as ocomb, cosmology as ocm, estimators, fourier, planar
 
 gpu = pytest.mark.gpu
 pytestmark = gpu
@@ -231,3 +239,79 @@ def test_step_full_size_generic_lattice_properties(plan):
     den = sum(float(torch.sum(p1[d].double() ** 2)) for d in range(3))
     assert math.sqrt(num / den) < 1e-6
     del pos, mom, p1, force
+
+
+def min_image(d, n):
+    return (d + n / 2) % n - n / 2
+
+
+# -------------------------------------------------------------- estimators --
+
+def test_pk_full_size_plane_waves(plan):
+    dev = plan.device
+    delta = si.plane_wave_mesh(N, WAVES, device=dev, dtype=torch.float32)
+    k, p, c = pm.pk_estimate(plan, delta, 256)
+    torch.cuda.synchronize()
+    del delta
+    modes, vals = fourier.plane_wave_modes(WAVES, N)
+    wk, wp, wc = estimators.power_spectrum_sparse(modes, vals, N, BOX, 256)
+    assert torch.equal(c.cpu(), wc)
+    assert rel_l2(k, wk) < 1e-12
+    assert rel_l2(p, wp) < F32_TOL
+
+
+# plane waves closing triangles (modulo N) in the shells of the benchmark's B(k)
+# configurations: shell m (m = 0..31) at 16 (m + 1) k_f, shell 32 at 4 k_f, width 2
+BWAVES = [(0.10, (16, 0, 0), 0.3), (0.09, (-8, 14, 0), 1.1), (0.08, (-8, -14, 0), 2.0),       # (0, 0, 0)
+          (0.07, (0, 15, -2), 0.6), (0.07, (0, -15, -2), 1.9), (0.06, (0, 0, 4), 0.2),        # (0, 0, 32)
+          (0.05, (0, 32, -2), 2.4), (0.05, (0, -32, -2), 0.8),                                 # (1, 1, 32)
+          (0.06, (32, 0, 0), 1.4), (0.05, (-16, 28, 0), 0.1), (0.05, (-16, -28, 0), 2.7),     # (1, 1, 1)
+          (0.04, (511, 0, 0), 0.9), (0.04, (-256, 443, 0), 1.6), (0.04, (-255, -443, 0), 0.4)]  # (31, 31, 31)
+
+
+def test_bk_full_size_benchmark_triangles(plan):
+    dev = plan.device
+    centres = [16.0 * m for m in range(1, 33)] + [4.0]
+    tris = [(m, m, m) for m in range(32)] + [(m, m, 32) for m in range(32)]
+    width = 2.0
+    delta = si.plane_wave_mesh(N, BWAVES, device=dev, dtype=torch.float32)
+    shell_ws = torch.empty((8,) + (N,) * 3, dtype=torch.float32, device=dev)
+    bk, ntri = pm.bk_estimate(plan, delta, centres, width, tris, shell_ws=shell_ws)
+    torch.cuda.synchronize()
+    del delta, shell_ws
+    bk, ntri = bk.double().cpu(), ntri.double().cpu()
+    modes, vals = fourier.plane_wave_modes_full(BWAVES, N)
+    vol2 = BOX ** 6
+    want_num = torch.tensor([estimators.bispectrum_numerator_sparse(modes, vals, N, centres, width, t).real
+                             for t in tris], dtype=torch.float64)
+    got_num = bk * ntri * (float(N) ** 9 / vol2)
+    scale = float(want_num.abs().max())
+    closed = [tris.index(t) for t in ((0, 0, 0), (1, 1, 1), (31, 31, 31), (0, 0, 32), (1, 1, 32))]
+    assert all(abs(float(want_num[i])) > 1e-3 * scale for i in closed)
+    assert float((got_num - want_num).abs().max()) < 1e-4 * scale
+    for t in ((0, 0, 0), (0, 0, 32), (1, 1, 32), (2, 2, 32)):
+        i = tris.index(t)
+        cnt = estimators.triangle_count(N, centres, width, t)
+        assert abs(float(ntri[i]) - cnt) <= F32_TOL * cnt
+        want_b = vol2 / N ** 9 * float(want_num[i]) / cnt
+        assert abs(float(bk[i]) - want_b) <= 1e-4 * max(abs(want_b), 1e-3 * vol2 / N ** 9 * scale / cnt)
+
+
+# ----------------------------------------------------------------- combine --
+
+def test_combine_full_size_sampled_particles(plan):
+    dev = plan.device
+    nc = 256
+    xg = torch.from_numpy(si.lattice_jitter_particles(nc, 61, 1.5)).float()
+    xn = torch.from_numpy(si.lattice_jitter_particles(nc, 62, 1.5)).float()
+    xg[xg >= nc] = 0
+    xn[xn >= nc] = 0
+    xf = si.hashed_lattice_particles(N, 63, amp_log2=1, device=dev, dtype=torch.float32)
+    out = pm.displacement_combine(xg.to(dev), xn.to(dev), nc, xf, N)
+    torch.cuda.synchronize()
+    idx = _sample_particles(4096, 65)
+    got = out[:, idx.to(dev)].double().cpu()
+    del out, xf
+    want = ocomb.combine_at(xg.double(), xn.double(), nc, si.hashed_lattice_particles(N, 63, 1, index=idx),
+                            _lattice_index(idx), N)
+    assert float(min_image(got - want, N).abs().max()) < 1e-6 * N
