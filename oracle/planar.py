@@ -94,3 +94,22 @@ def particle_coords(coord: torch.Tensor, axis: int, n: int, q: torch.Tensor) -> 
         else:
             out[b] = cic.wrap(q[b].double() + 0.5 + coord[b][qa], n)
     return out
+
+
+def cycle_line_vjp(coord: torch.Tensor, mom: torch.Tensor, axis: int, kick: float, drift: float, n: int,
+                   omega_m: float, lam_coord: torch.Tensor, lam_mom: torch.Tensor, grad: str = "spectral"):
+    """Reverse-mode derivative of ``cycle_line``: cotangents (lam_coord [3, N],
+    lam_mom [3, N]) of its outputs (coord', mom') -> cotangents of (coord, mom), by
+    autograd through the one-dimensional cycle (floor has zero derivative, so CIC
+    weights are differentiated from the right at cell edges).
+
+    For a plane-parallel lattice and cotangents that are constant on each lattice
+    plane, this is also the cotangent of every single particle of the plane in the
+    3-D cycle: moving one particle changes the transverse mean of the density by
+    1/N^2 of what moving its plane does, the transverse forces it induces average
+    to zero over a plane, and each plane's N^2 particles share the cotangent."""
+    c = coord.detach().clone().requires_grad_(True)
+    m = mom.detach().clone().requires_grad_(True)
+    c1, m1, _ = cycle_line(c, m, axis, kick, drift, n, omega_m, grad)
+    gc, gm = torch.autograd.grad((c1, m1), (c, m), grad_outputs=(lam_coord, lam_mom), allow_unused=True)
+    return (torch.zeros_like(c) if gc is None else gc), (torch.zeros_like(m) if gm is None else gm)

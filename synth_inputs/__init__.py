@@ -37,6 +37,7 @@ __all__ = [
     "hashed_lattice_particles",
     "planar_profile",
     "expand_planar",
+    "broadcast_planes",
     "plane_wave_mesh",
 ]
 
@@ -237,11 +238,19 @@ def expand_planar(coord: torch.Tensor, mom: torch.Tensor | None, n: int, axis: i
             view.copy_(tab.t().contiguous().view(shp).expand(n, n, n))
     if mom is None:
         return pos, None
-    m = torch.empty((3, n ** 3), dtype=dtype, device=device)
-    mom = mom.to(device)
+    return pos, broadcast_planes(mom.to(torch.float64) * QUANTUM, n, axis, device=device, dtype=dtype)
+
+
+def broadcast_planes(values: torch.Tensor, n: int, axis: int, device=None, dtype=torch.float32) -> torch.Tensor:
+    """[3, N^3] particle array (Lagrangian order) whose entry for the particle with
+    lattice index q is values[:, q_axis] (``values`` [3, N], one column per plane)."""
+    shape = [1, 1, 1]
+    shape[axis] = n
+    out = torch.empty((3, n ** 3), dtype=dtype, device=device)
+    values = values.to(device)
     for c in range(3):
-        m[c].view(n, n, n).copy_((mom[c].to(dtype) * QUANTUM).view(shape).expand(n, n, n))
-    return pos, m
+        out[c].view(n, n, n).copy_(values[c].to(dtype).view(shape).expand(n, n, n))
+    return out
 
 
 def plane_wave_mesh(n: int, waves, device=None, dtype=torch.float32) -> torch.Tensor:

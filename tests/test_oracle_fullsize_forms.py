@@ -157,3 +157,22 @@ def test_sparse_bispectrum_pieces_equal_dense_estimator():
         assert want == pytest.approx(float(wb[t]), rel=1e-9, abs=1e-9 * float(wb.abs().max()))
         nonzero += abs(num) > 0
     assert nonzero >= 2   # the direct triangle in shell 0 and the aliased one in (1, 1, 0)
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_planar_vjp_equals_3d_oracle_vjp(axis):
+    from oracle import adjoint as oadj
+    n = 16
+    om = ocm.FIDUCIAL.omega_m
+    c, m, pos, p3 = _planar_case(n, axis, 50 + axis, 2 * 8192 + 5)
+    g = torch.Generator().manual_seed(7 + axis)
+    lc = torch.randn((3, n), generator=g, dtype=torch.float64)
+    lm = torch.randn((3, n), generator=g, dtype=torch.float64)
+    kick, drift = 0.37, 0.55
+    gc, gm = planar.cycle_line_vjp(c, m, axis, kick, drift, n, om, lc, lm)
+    lx3 = si.broadcast_planes(lc, n, axis, dtype=torch.float64)
+    lp3 = si.broadcast_planes(lm, n, axis, dtype=torch.float64)
+    wx, wp = oadj.step_vjp(pos, p3, kick, drift, n, ocm.FIDUCIAL, lx3, lp3)
+    assert torch.allclose(si.broadcast_planes(gc, n, axis, dtype=torch.float64), wx, atol=1e-11)
+    assert torch.allclose(si.broadcast_planes(gm, n, axis, dtype=torch.float64), wp, atol=1e-11)
+    assert float((gc[axis] - lc[axis]).abs().max()) > 1e-3   # the force term contributes
