@@ -20,7 +20,10 @@ at a time, or a property that holds at any size:
     sum over the sparse modes, and the triangle counts of the smaller shells against
     brute force;
   * the combination of a 256^3 pair into a 1024^3 run: sampled fine particles
-    against the oracle's combination at those particles.
+    against the oracle's combination at those particles;
+  * the adjoint cycle on a plane-parallel lattice with cotangents constant on
+    lattice planes: sampled particles against the reverse-mode derivative of the
+    plane-parallel reduction.
 Inputs are multiples of 2^-13 cells, exact in FP32 and FP64, so the oracle sees the
 very numbers the kernels see.
 """
@@ -315,3 +318,42 @@ def test_combine_full_size_sampled_particles(plan):
     want = ocomb.combine_at(xg.double(), xn.double(), nc, si.hashed_lattice_particles(N, 63, 1, index=idx),
                             _lattice_index(idx), N)
     assert float(min_image(got - want, N).abs().max()) < 1e-6 * N
+
+
+# ----------------------------------------------------------------- adjoint --
+
+@pytest.mark.parametrize("cached_force", [True, False])
+def test_step_adjoint_full_size_plane_parallel_lattice(plan, cached_force):
+    dev = plan.device
+    axis = 1
+    om = ocm.FIDUCIAL.omega_m
+    kick, drift = 0.37, 0.55
+    coord_q, mom_q = si.planar_profile(N, axis, 70, amp_log2=1, mom_log2=0)
+    pos, mom = si.expand_planar(coord_q, mom_q, N, axis, device=dev, dtype=torch.float32)
+    _, lam_q = si.planar_profile(N, axis, 71, mom_log2=0)
+    _, lamp_q = si.planar_profile(N, axis, 72, mom_log2=0)
+    lc, lm = lam_q.double() * si.QUANTUM, lamp_q.double() * si.QUANTUM
+    st = pm.StepParams(kick=kick, drift=drift, solve=pm.newton_params())
+    force = None
+    if cached_force:
+        force = plan.mesh(3)
+        x1, m1 = pos.clone(), mom.clone()
+        pm.pm_step(plan, x1, m1, st, force)
+        del x1, m1
+    del mom
+    glx = si.broadcast_planes(lc, N, axis, device=dev, dtype=torch.float32)
+    glp = si.broadcast_planes(lm, N, axis, device=dev, dtype=torch.float32)
+    pm.pm_step_adjoint(plan, pos, st, glx, glp, force=force)
+    torch.cuda.synchronize()
+    pm.pm_check(plan)
+    del pos, force
+    gc, gm = planar.cycle_line_vjp(coord_q.double() * si.QUANTUM, mom_q.double() * si.QUANTUM, axis, kick, drift,
+                                   N, om, lc, lm)
+    idx = _sample_particles(4096, 73)
+    qa = _lattice_index(idx)[axis]
+    got_x = glx[:, idx.to(dev)].double().cpu()
+    got_p = glp[:, idx.to(dev)].double().cpu()
+    assert rel_l2(got_x, gc[:, qa]) < F32_TOL
+    assert rel_l2(got_p, gm[:, qa]) < F32_TOL
+    # the force term moves the axis cotangent well beyond FP32 rounding
+    assert float((gc[axis] - lc[axis]).abs().max()) > 1e-2
