@@ -23,17 +23,21 @@ at a time, or a property that holds at any size:
     against the oracle's combination at those particles;
   * the adjoint cycle on a plane-parallel lattice with cotangents constant on
     lattice planes: sampled particles against the reverse-mode derivative of the
-    plane-parallel reduction.
+    plane-parallel reduction;
+  * the coarse 256^3 pair of the combination configuration (Zel'dovich and
+    Poisson-gauge sets from EH98 ICs at a = 0.02, L = 4000 Mpc/h), whole, through
+    the leapfrog host loop, against the dense oracle.
 Inputs are multiples of 2^-13 cells, exact in FP32 and FP64, so the oracle sees the
 very numbers the kernels see.
 """
 import math
 
+import numpy as np
 import pytest
 import torch
 
 import synth_inputs as si
-from oracle import cic, combine as ocomb, cosmology as ocm, estimators, fourier, planar
+from oracle import cic, combine as ocomb, cosmology as ocm, estimators, fourier, ics as oics, integrate, planar
 
 gpu = pytest.mark.gpu
 pytestmark = gpu
@@ -357,3 +361,40 @@ def test_step_adjoint_full_size_plane_parallel_lattice(plan, cached_force):
     assert rel_l2(got_p, gm[:, qa]) < F32_TOL
     # the force term moves the axis cotangent well beyond FP32 rounding
     assert float((gc[axis] - lc[axis]).abs().max()) > 1e-2
+
+
+# ----------------------------------------------------- coarse pair at 256^3 --
+
+def test_coarse_pair_256_ics_and_leapfrog():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dev = torch.device("cuda")
+    nc, a_i = 256, 0.02
+    c = ocm.Cosmo(n_s=0.965)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=a_i,
+                      a_norm=1.0, cosmo=pm.FIDUCIAL)
+    p = oics.ICParams(n=nc, box=BOX, a_init=a_i, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    noise = torch.from_numpy(si.white_noise(nc, 90, dtype=np.float32))
+    cplan = pm.Plan(nc, BOX, torch.float32)
+    disp = cplan.mesh(3)
+    pos, mom, pg, mg = (torch.empty((3, nc ** 3), dtype=torch.float32, device=dev) for _ in range(4))
+    pm.pm_ic_zeldovich(cplan, noise.to(dev), icp, disp, pos, mom)
+    pm.pm_ic_gauge(cplan, noise.to(dev), icp, disp, pos, mom, pg, mg)
+    torch.cuda.synchronize()
+    wpn, wmn, wpg, wmg = oics.zeldovich_pair(noise.double(), p)
+    ulp = float(torch.finfo(torch.float32).eps) * nc
+    assert float(min_image(pos.double().cpu() - wpn, nc).abs().max()) < 4 * ulp
+    assert float(min_image(pg.double().cpu() - wpg, nc).abs().max()) < 8 * ulp
+    assert rel_l2(mom, wmn) < F32_TOL
+    # the first step of the benchmark's 50-step schedule (two cycles), both sets, host loop
+    a_s = ocm.log_steps(a_i, 1.0, 50)[:2]
+    pm.sim.Run(cplan, pos, mom).leapfrog(a_s)
+    pm.sim.Run(cplan, pg, mg, gauge=True).leapfrog(a_s)
+    torch.cuda.synchronize()
+    pm.pm_check(cplan)
+    xn, vn = integrate.run_kdk(wpn, wmn, a_s, integrate.NewtonForce(nc), nc)
+    xg, vg = integrate.run_kdk(wpg, wmg, a_s, integrate.GaugeForce(nc, BOX / nc), nc)
+    for got, want in ((pos, xn), (pg, xg)):
+        assert float(min_image(got.double().cpu() - want, nc).abs().max()) < 8 * ulp
+    assert rel_l2(mom, vn) < F32_TOL
+    assert rel_l2(mg, vg) < F32_TOL
