@@ -109,3 +109,13 @@ def plane_wave_modes_full(waves, n: int):
     keys = sorted(acc)
     return (torch.tensor(keys, dtype=torch.long).view(-1, 3),
             torch.tensor([acc[k] for k in keys], dtype=torch.complex128))
+
+
+def idft_at(modes: torch.Tensor, values: torch.Tensor, n: int, points: torch.Tensor) -> torch.Tensor:
+    """Inverse DFT (with 1/N^3) of a full-cube spectrum that vanishes except at
+    ``modes`` ([M, 3]) with amplitudes ``values``, evaluated at ``points`` ([3, P],
+    grid coordinates, not necessarily integers).  Returns complex128 [P]."""
+    k = (2.0 * math.pi / n) * modes.to(torch.float64)                   # [M, 3]
+    arg = k @ points.to(torch.float64)                                 # [M, P]
+    e = torch.complex(torch.cos(arg), torch.sin(arg))
+    return (values.view(-1, 1) * e).sum(dim=0) / n ** 3

@@ -180,3 +180,47 @@ def powerlaw_for_rms_displacement(n: int, box: float, rms_cells: float, index: f
     s = float(terms.sum()) * dx ** (-index)
     amp = rms_cells ** 2 * dx ** 3 * n ** 3 / s
     return cm.PowerSpec("powerlaw", amp, index)
+
+
+def _linear_delta_sparse(modes: torch.Tensor, w_hat: torch.Tensor, p: ICParams) -> torch.Tensor:
+    """``linear_delta_k`` at the full-cube modes ``modes`` ([M, 3], components in
+    [-N/2, N/2)) of a noise spectrum that vanishes elsewhere."""
+    growth = cm.growth_d(p.cosmo, p.a_init) / cm.growth_d(p.cosmo, p.a_norm)
+    kf = 2.0 * math.pi / p.box
+    out = torch.zeros_like(w_hat)
+    for i, m in enumerate(modes.tolist()):
+        if all(c == 0 for c in m) or any(c == -(p.n // 2) for c in m):
+            continue   # k = 0 and the Nyquist planes carry no linear density
+        amp = math.sqrt(p.power(kf * math.sqrt(sum(c * c for c in m))) / p.dx ** 3) * growth
+        out[i] = w_hat[i] * amp
+    return out
+
+
+def zeldovich_pair_sparse(modes: torch.Tensor, w_hat: torch.Tensor, p: ICParams, q_index: torch.Tensor):
+    """``zeldovich_pair`` for white noise whose full-cube spectrum vanishes except at
+    ``modes`` with amplitudes ``w_hat``, evaluated for the particles with lattice
+    indices q_index ([3, P]) only: (pos_N, mom_N, pos_GR, mom_GR), each [3, P]."""
+    n = p.n
+    dl = _linear_delta_sparse(modes, w_hat, p)
+    kg = (2.0 * math.pi / n) * modes.to(torch.float64)
+    k2 = (kg * kg).sum(dim=1)
+    inv = torch.where(k2 > 0, 1.0 / torch.where(k2 > 0, k2, torch.ones_like(k2)), torch.zeros_like(k2))
+    q = q_index.to(torch.float64) + 0.5           # the lattice point carries the half-cell phase
+    psi = torch.stack([fourier.idft_at(modes, 1j * kg[:, d] * dl * inv, n, q).real for d in range(3)])
+    base = torch.stack([fourier.idft_at(modes, 1j * kg[:, d] * dl * inv * inv, n, q).real for d in range(3)])
+    a = p.a_init
+    pos_n = cic.wrap(q + psi, n)
+    mom_n = a * a * cm.hubble_e(p.cosmo, a) * cm.growth_f(p.cosmo, a) * psi
+    g, gp = gr_shift_coefficients(p, a)
+    pos_gr = cic.wrap(pos_n + g * base, n)
+    mom_gr = mom_n + a * a * cm.hubble_e(p.cosmo, a) * gp * base
+    return pos_n, mom_n, pos_gr, mom_gr
+
+
+def truncate_noise_sparse(modes: torch.Tensor, w_hat: torch.Tensor, n_fine: int, n_coarse: int):
+    """``truncate_noise`` of a fine noise spectrum that vanishes except at ``modes``:
+    the coarse spectrum's non-zero modes (|n_i| < N_c/2 kept, scaled by
+    (N_c/N_f)^(3/2)) as (modes [K, 3], values [K])."""
+    h = n_coarse // 2
+    keep = (modes.abs() < h).all(dim=1)
+    return modes[keep].clone(), w_hat[keep] * (n_coarse / n_fine) ** 1.5

@@ -176,3 +176,56 @@ def test_planar_vjp_equals_3d_oracle_vjp(axis):
     assert torch.allclose(si.broadcast_planes(gc, n, axis, dtype=torch.float64), wx, atol=1e-11)
     assert torch.allclose(si.broadcast_planes(gm, n, axis, dtype=torch.float64), wp, atol=1e-11)
     assert float((gc[axis] - lc[axis]).abs().max()) > 1e-3   # the force term contributes
+
+
+NOISE_WAVES = [(0.02, (1, 0, 0), 0.3), (0.05, (2, -3, 1), 1.2), (0.3, (5, 5, -7), 2.2), (0.4, (-7, 2, 3), 0.7),
+               (0.2, (8, 1, 0), 0.1)]
+
+
+def _cosine_mesh(waves, n):
+    x = torch.arange(n, dtype=torch.float64)
+    g = torch.stack(torch.meshgrid(x, x, x, indexing="ij"))
+    return sum(a * torch.cos(2 * math.pi * (m[0] * g[0] + m[1] * g[1] + m[2] * g[2]) / n + ph) for a, m, ph in waves)
+
+
+def test_idft_at_equals_inverse_fft():
+    from oracle import fourier
+    n = 8
+    modes, vals = fourier.plane_wave_modes_full(NOISE_WAVES, n)
+    g = torch.arange(n)
+    pts = torch.stack(torch.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    got = fourier.idft_at(modes, vals, n, pts).real
+    assert torch.allclose(got, _cosine_mesh(NOISE_WAVES, n).reshape(-1), atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["powerlaw", "eh98"])
+def test_zeldovich_pair_sparse_equals_dense(kind):
+    from oracle import fourier, ics as oics
+    n, box = 16, 500.0
+    c = ocm.Cosmo(n_s=0.965)
+    power = oics.powerlaw_for_rms_displacement(n, box, 0.5) if kind == "powerlaw" else ocm.eh98_normalised(c, 0.965, 0.81)
+    p = oics.ICParams(n=n, box=box, a_init=0.05, power=power, a_norm=1.0, cosmo=c)
+    noise = _cosine_mesh(NOISE_WAVES, n)
+    want = oics.zeldovich_pair(noise, p)
+    modes, vals = fourier.plane_wave_modes_full(NOISE_WAVES, n)
+    g = torch.arange(n)
+    q = torch.stack(torch.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    got = oics.zeldovich_pair_sparse(modes, vals, p, q)
+    for a, b in zip(got, want):
+        assert float(torch.remainder(a - b + n / 2, n).sub(n / 2).abs().max()) < 1e-11
+    disp = torch.remainder(want[0] - (q + 0.5) + n / 2, n) - n / 2
+    assert float(disp.abs().max()) > 1e-3   # a displacement that is not trivially zero
+
+
+def test_truncate_noise_sparse_equals_dense():
+    from oracle import fourier, ics as oics
+    nf, nc = 16, 8
+    noise = _cosine_mesh(NOISE_WAVES, nf)
+    want = oics.truncate_noise(noise, nc)
+    modes, vals = fourier.plane_wave_modes_full(NOISE_WAVES, nf)
+    cm_, cv = oics.truncate_noise_sparse(modes, vals, nf, nc)
+    g = torch.arange(nc)
+    pts = torch.stack(torch.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    got = fourier.idft_at(cm_, cv, nc, pts).real
+    assert torch.allclose(got, want.reshape(-1), atol=1e-12)
+    assert float(want.abs().max()) > 0.1
