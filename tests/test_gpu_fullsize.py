@@ -24,6 +24,10 @@ at a time, or a property that holds at any size:
   * the adjoint cycle on a plane-parallel lattice with cotangents constant on
     lattice planes: sampled particles against the reverse-mode derivative of the
     plane-parallel reduction;
+  * Zel'dovich and Poisson-gauge ICs at 1024^3 (EH98, a = 0.02) from a white-noise
+    field made of plane waves (one on a Nyquist plane, which the ICs drop):
+    sampled particles against the oracle's ICs of the sparse noise spectrum; the
+    truncation of that noise to 256^3, whole, against the sparse truncation;
   * the coarse 256^3 pair of the combination configuration (Zel'dovich and
     Poisson-gauge sets from EH98 ICs at a = 0.02, L = 4000 Mpc/h), whole, through
     the leapfrog host loop, against the dense oracle.
@@ -398,3 +402,66 @@ def test_coarse_pair_256_ics_and_leapfrog():
         assert float(min_image(got.double().cpu() - want, nc).abs().max()) < 8 * ulp
     assert rel_l2(mom, vn) < F32_TOL
     assert rel_l2(mg, vg) < F32_TOL
+
+
+# -------------------------------------------------------- ICs and the noise --
+
+# noise made of plane waves, amplitudes chosen for displacements of about a cell;
+# (512, 3, 0) lies on a Nyquist plane and carries no linear density
+NWAVES = [(0.02, (1, 0, 0), 0.3), (0.1, (3, -2, 5), 1.2), (1.0, (40, 17, -9), 2.2), (10.0, (-150, 200, 31), 0.7),
+          (50.0, (300, -5, 400), 0.1), (10.0, (100, 90, -80), 1.9), (1.0, (512, 3, 0), 0.4),
+          (50.0, (500, -400, 200), 2.6), (5.0, (-60, 127, 2), 1.0)]
+
+
+def _eh98_ics():
+    c = ocm.Cosmo(n_s=0.965)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=0.02,
+                      a_norm=1.0, cosmo=pm.FIDUCIAL)
+    return icp, c
+
+
+def test_ics_full_size_sampled_particles(plan):
+    dev = plan.device
+    icp, c = _eh98_ics()
+    noise = si.plane_wave_mesh(N, NWAVES, device=dev, dtype=torch.float32)
+    disp = plan.mesh(3)
+    pos, mom, pg, mg = (plan.particles() for _ in range(4))
+    pm.pm_ic_zeldovich(plan, noise, icp, disp, pos, mom)
+    pm.pm_ic_gauge(plan, noise, icp, disp, pos, mom, pg, mg)
+    torch.cuda.synchronize()
+    del noise, disp
+    idx = _sample_particles(4096, 81)
+    idx_d = idx.to(dev)
+    got = [t[:, idx_d].double().cpu() for t in (pos, mom, pg, mg)]
+    del pos, mom, pg, mg
+    p = oics.ICParams(n=N, box=BOX, a_init=0.02, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    modes, vals = fourier.plane_wave_modes_full(NWAVES, N)
+    wpn, wmn, wpg, wmg = oics.zeldovich_pair_sparse(modes, vals, p, _lattice_index(idx))
+    ulp = float(torch.finfo(torch.float32).eps) * N
+    assert float(min_image(got[0] - wpn, N).abs().max()) < 4 * ulp
+    assert float(min_image(got[2] - wpg, N).abs().max()) < 8 * ulp
+    assert rel_l2(got[1], wmn) < F32_TOL
+    assert rel_l2(got[3], wmg) < F32_TOL
+    # displacements of order a cell, and a Poisson-gauge shift that is not negligible
+    assert float(min_image(wpn - (_lattice_index(idx).double() + 0.5), N).abs().max()) > 1.0
+    assert float(min_image(wpg - wpn, N).abs().max()) > 1.0
+
+
+def test_noise_truncate_full_size(plan):
+    dev = plan.device
+    nc = 256
+    noise = si.plane_wave_mesh(N, NWAVES, device=dev, dtype=torch.float32)
+    cplan = pm.Plan(nc, BOX, torch.float32)
+    coarse = pm.pm_noise_truncate(plan, noise, cplan)
+    torch.cuda.synchronize()
+    del noise
+    got = coarse.double().cpu().reshape(-1)
+    modes, vals = fourier.plane_wave_modes_full(NWAVES, N)
+    cmodes, cvals = oics.truncate_noise_sparse(modes, vals, N, nc)
+    assert 0 < cmodes.shape[0] < modes.shape[0]   # some waves kept, some dropped
+    g = torch.arange(nc)
+    want = torch.empty(nc ** 3, dtype=torch.float64)
+    for i0 in range(0, nc, 16):
+        pts = torch.stack(torch.meshgrid(g[i0:i0 + 16], g, g, indexing="ij")).reshape(3, -1)
+        want[i0 * nc * nc:(i0 + 16) * nc * nc] = fourier.idft_at(cmodes, cvals, nc, pts).real
+    assert rel_l2(got, want) < F32_TOL
