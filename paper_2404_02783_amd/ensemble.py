@@ -104,7 +104,9 @@ class Ensemble:
                 pm_step(st.plan, st.pos, st.mom, c, st.force)
         for st in self.states:
             pm_deposit(st.plan, st.pos, st.delta)
-            st.out = pk_estimate(st.plan, st.delta, st.group.bins())
+            out = pk_estimate(st.plan, st.delta, st.group.bins())
+            # a one-box group has an unbatched plan: keep the [boxes, bins] shape
+            st.out = out if st.plan.batch > 1 else tuple(t.unsqueeze(0) for t in out)
 
     def capture(self):
         """Capture run() into one HIP graph (after one eager warm-up run)."""

@@ -98,3 +98,45 @@ def test_single_box_entry_points_reject_batches():
         pm.pm_gather(plan, force, pos[0].contiguous())
     with pytest.raises(pm.PMError):
         pm.pk_adjoint(plan, pos[0].contiguous(), 8, torch.zeros(8, dtype=torch.float64, device=dev))
+
+
+# ------------------------------------------- the benchmark's ensemble config --
+
+def test_benchmark_ensemble_graph_matches_single_boxes():
+    """The benchmark's 64-box ensemble (16 x 64^3, 24 x 128^3, 16 x 192^3, 8 x 256^3,
+    30 log steps a = 0.02 -> 1, FP32) replayed from one captured graph: every box's
+    P(k) against its own single-box eager run.  The two differ only in the order of
+    the float atomics that flush the fused deposit, amplified over 30 steps."""
+    dev = _dev()
+    groups = ensemble.default_groups()
+    ens = ensemble.Ensemble(groups, _noise, 0.02, 1.0, 30, torch.float32, dev)
+    ens.capture()
+    ens.replay()
+    torch.cuda.synchronize()
+    got = [o[1].double().cpu() for o in ens.power_spectra()]
+    noises = {s: st.noise[i] for st in ens.states for i, s in enumerate(st.group.seeds)}
+    seq = ensemble.run_sequential(groups, _noise, 0.02, 1.0, 30, torch.float32, dev, noises=noises)
+    torch.cuda.synchronize()
+    for g, s in zip(got, seq):
+        s = s.double().cpu()
+        assert g.shape == s.shape
+        for b in range(g.shape[0]):
+            assert rel(g[b], s[b]) < 1e-5
+            assert float(((g[b] - s[b]).abs() / s[b].abs().clamp_min(1e-30)).max()) < 1e-4
+
+
+def test_benchmark_schedule_fp64_box_matches_oracle():
+    """A 64^3 box of the benchmark ensemble (L = 500 Mpc/h, seed 100) over the whole
+    30-step schedule to a = 1, in FP64, against the oracle's ICs -> leapfrog -> P(k)."""
+    dev = _dev()
+    n, box = 64, 500.0
+    groups = [ensemble.Group(n, box, [100])]
+    ens = ensemble.Ensemble(groups, _noise, 0.02, 1.0, 30, torch.float64, dev)
+    ens.run()
+    torch.cuda.synchronize()
+    _, pk_b, _ = ens.power_spectra()[0]
+    assert pk_b.shape == (1, n // 2)   # [boxes, bins] also for a one-box group
+    c = ocm.Cosmo(n_s=0.965)
+    p = oics.ICParams(n=n, box=box, a_init=0.02, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    _, want, _ = oadj.forward_pk(torch.from_numpy(_noise(n, 100)), p, ocm.log_steps(0.02, 1.0, 30), n // 2)
+    assert rel(pk_b[0], want) < 1e-9
