@@ -79,6 +79,7 @@ constexpr int APP = AX * AY * AZ / kBlock;
 constexpr int ACAP = 4096;
 constexpr int AWF = 16;
 
+template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __restrict__ force, const float* __restrict__ pos,
                                                              int n, float kick, float drift, float* __restrict__ lam_pos,
                                                              float* __restrict__ lam_mom) {
@@ -98,9 +99,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     const int loc = t + kBlock * p;
     const int li = loc / (AY * AZ), lk = (loc / AZ) % AY, ll = loc % AZ;
     jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
-    x[p] = wrap(pos[jj[p]], n);
-    y[p] = wrap(pos[np + jj[p]], n);
-    z[p] = wrap(pos[2 * np + jj[p]], n);
+    x[p] = wrap_n<P2>(pos[jj[p]], n);
+    y[p] = wrap_n<P2>(pos[np + jj[p]], n);
+    z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
   }
   const TileWindow tw = tile_window<APP>(x, y, z, n, org, ACAP, AWF, AX * AY * AZ, wlo, whi, wsum);
   const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
@@ -108,11 +109,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
   const int wtot = W0 * W1 * W2;
   // stage the window: all of a thread's loads in flight before its first LDS store
   float fa[ACAP / kBlock], fb[ACAP / kBlock], fc[ACAP / kBlock];
+  const WinDiv qsx(sx), qsy(sy);
 #pragma unroll
   for (int k = 0; k < ACAP / kBlock; ++k) {
     const int c = t + kBlock * k;
     if (c < wtot) {
-      const int a = c / sx, b = (c / sy) % W1, cz = c % sy;
+      int a, b, cz;
+      win_cell(c, qsx, qsy, a, b, cz);
       const int64_t idx = ((int64_t)fold(org[0] + tw.o[0] + a, n) * n + fold(org[1] + tw.o[1] + b, n)) * n +
                           fold(org[2] + tw.o[2] + cz, n);
       fa[k] = force[idx];
@@ -177,6 +180,7 @@ constexpr int VWF = 16;
 // g[d] += sum_p W(x_p - c) v_{p,d}, v = kick * lam_mom, one tile per block: the
 // window is accumulated in LDS and added to g with one global atomic per non-empty
 // cell; particles outside their tile's window go to global atomics directly.
+template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict__ pos, const float* __restrict__ lam_mom,
                                                         float kick, int n, float* __restrict__ g) {
   __shared__ unsigned long long win[VCAP];
@@ -197,9 +201,9 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
     const int loc = t + kBlock * p;
     const int li = loc / (VY * VZ), lk = (loc / VZ) % VY, ll = loc % VZ;
     jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
-    x[p] = wrap(pos[jj[p]], n);
-    y[p] = wrap(pos[np + jj[p]], n);
-    z[p] = wrap(pos[2 * np + jj[p]], n);
+    x[p] = wrap_n<P2>(pos[jj[p]], n);
+    y[p] = wrap_n<P2>(pos[np + jj[p]], n);
+    z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       v[d][p] = kick * lam_mom[d * np + jj[p]];
@@ -274,10 +278,12 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
     if (scale[d] > 0.0) {
       const double inv = 1.0 / scale[d];
       float* gd = g + (int64_t)d * np;
+      const WinDiv qsx(sx), qsy(sy);
       for (int c = t; c < wtot; c += kBlock) {
         const long long q = (long long)win[c];
         if (q == 0) continue;
-        const int a = c / sx, b = (c / sy) % W1, cz = c % sy;
+        int a, b, cz;
+        win_cell(c, qsx, qsy, a, b, cz);
         const int64_t idx = ((int64_t)fold(org[0] + tw.o[0] + a, n) * n + fold(org[1] + tw.o[1] + b, n)) * n +
                             fold(org[2] + tw.o[2] + cz, n);
         atomic_add(gd + idx, (float)((double)q * inv));
@@ -289,15 +295,15 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
 
 // lam_pos (+)= scale * grad_x sum_c W(x - c) h(c): the adjoint of the CIC deposit
 // applied to a cotangent mesh h.
-template <typename T>
+template <typename T, bool P2>
 __global__ void __launch_bounds__(kBlock) k_grad_gather(const T* __restrict__ h, const T* __restrict__ pos, int64_t np,
                                                         int n, T scale, T* __restrict__ lam_pos, int accumulate) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = blk * kBlock + threadIdx.x;
   if (i >= np) return;
   const int64_t n2 = (int64_t)n * n;
-  const Axis<T> ax = cic_axis(wrap(pos[i], n), n), ay = cic_axis(wrap(pos[np + i], n), n),
-                az = cic_axis(wrap(pos[2 * np + i], n), n);
+  const Axis<T> ax = cic_axis(wrap_n<P2>(pos[i], n), n), ay = cic_axis(wrap_n<P2>(pos[np + i], n), n),
+                az = cic_axis(wrap_n<P2>(pos[2 * np + i], n), n);
   T gx = 0, gy = 0, gz = 0;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -361,13 +367,16 @@ int launch_adj_gather_kdk(const pm_plan* p, const void* force, const void* pos, 
     {
       ProfScope ps(p, PK_ADJ_GATHER, s);
       const unsigned tiles = (unsigned)((n / AX) * (n / AY) * (n / AZ));
-      hipLaunchKernelGGL(k_adj_gather_tiled, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(force),
+      // a power-of-two N wraps without a division (same results)
+      auto kern = (n & (n - 1)) == 0 ? k_adj_gather_tiled<true> : k_adj_gather_tiled<false>;
+      hipLaunchKernelGGL(kern, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(force),
                          static_cast<const float*>(pos), n, (float)kick, (float)drift, static_cast<float*>(lam_pos),
                          static_cast<float*>(lam_mom));
     }
     ProfScope ps(p, PK_ADJ_DEPOSIT, s);
     const unsigned tiles = (unsigned)((n / VX) * (n / VY) * (n / VZ));
-    hipLaunchKernelGGL(k_deposit_vec, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(pos),
+    auto kern = (n & (n - 1)) == 0 ? k_deposit_vec<true> : k_deposit_vec<false>;
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(pos),
                        static_cast<const float*>(lam_mom), (float)kick, n, static_cast<float*>(g));
     return hip_check(hipGetLastError(), "adjoint gather-kick-drift");
   }
@@ -388,14 +397,18 @@ int launch_grad_gather(const pm_plan* p, const void* h, const void* pos, int64_t
                        bool accumulate, hipStream_t s) {
   ProfScope ps(p, PK_GRAD_GATHER, s);
   if (np <= 0) return PM_OK;
-  if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_grad_gather<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(h),
+  const bool p2 = (p->n & (p->n - 1)) == 0;  // a power-of-two N wraps without a division
+  if (p->dtype == PM_F32) {
+    auto kern = p2 ? k_grad_gather<float, true> : k_grad_gather<float, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(h),
                        static_cast<const float*>(pos), np, p->n, (float)scale, static_cast<float*>(lam_pos),
                        accumulate ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_grad_gather<double>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(h),
+  } else {
+    auto kern = p2 ? k_grad_gather<double, true> : k_grad_gather<double, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const double*>(h),
                        static_cast<const double*>(pos), np, p->n, scale, static_cast<double*>(lam_pos),
                        accumulate ? 1 : 0);
+  }
   return hip_check(hipGetLastError(), "gradient gather");
 }
 

@@ -76,6 +76,7 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // bounding box of the tile's CIC cells when it fits in WCAP cells, else a WF^3 box
 // around the mean base cell; particles whose cells fall outside the window go to
 // global atomics.  All window arithmetic is integer on the base nodes floor(x).
+template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restrict__ pos, float* __restrict__ mesh,
                                                           int n, double w_scale, unsigned* __restrict__ guard) {
   __shared__ unsigned long long win[WCAP];
@@ -112,9 +113,9 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
     }
     if (!(x[p] >= 0.f && x[p] < fn && y[p] >= 0.f && y[p] < fn && z[p] >= 0.f && z[p] < fn)) {
       atomicAdd(&guard[1], 1u);
-      x[p] = wrap(x[p], n);
-      y[p] = wrap(y[p], n);
-      z[p] = wrap(z[p], n);
+      x[p] = wrap_n<P2>(x[p], n);
+      y[p] = wrap_n<P2>(y[p], n);
+      z[p] = wrap_n<P2>(z[p], n);
     }
     const int r[3] = {idiff((int)floorf(x[p]), org[0], n), idiff((int)floorf(y[p]), org[1], n),
                       idiff((int)floorf(z[p]), org[2], n)};
@@ -203,10 +204,12 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
   }
   __syncthreads();
   const double scale = w_scale / kFix;
+  const WinDiv qsx(sx), qsy(sy);
   for (int c = t; c < wtot; c += kBlock) {
     const unsigned long long v = win[c];
     if (v == 0ull) continue;
-    const int a = c / sx, b = (c / sy) % W[1], cz = c % sy;
+    int a, b, cz;
+    win_cell(c, qsx, qsy, a, b, cz);
     const int64_t idx = ((int64_t)fold(org[0] + o[0] + a, n) * n + fold(org[1] + o[1] + b, n)) * n +
                         fold(org[2] + o[2] + cz, n);
     atomic_add(mesh + idx, (float)((double)v * scale));
@@ -225,7 +228,9 @@ int launch_deposit(const pm_plan* p, const void* pos, int64_t np, void* mesh, hi
   const double w = n3 / (double)np;  // 1 / nbar
   if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % TZ == 0 && n % TX == 0) {
     const unsigned tiles = (unsigned)((n / TX) * (n / TY) * (n / TZ));
-    hipLaunchKernelGGL(k_deposit_tiled, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const float*>(pos),
+    // a power-of-two N wraps without a division (same results)
+    auto kern = (n & (n - 1)) == 0 ? k_deposit_tiled<true> : k_deposit_tiled<false>;
+    hipLaunchKernelGGL(kern, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const float*>(pos),
                        static_cast<float*>(mesh), n, w, p->guard);
   } else if (p->dtype == PM_F32) {
     hipLaunchKernelGGL(k_deposit<float>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const float*>(pos), np,

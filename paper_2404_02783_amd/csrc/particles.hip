@@ -108,7 +108,7 @@ constexpr int DWF = 18;  // fallback deposit box side (DWF^3 <= DCAP)
 // stages the three force meshes over the tile's CIC bounding box in `win`, updates
 // (pos, mom) and leaves the drifted, wrapped positions in (x, y, z).  GUARD counts
 // non-finite drifted positions in guard[0].
-template <bool GUARD>
+template <bool GUARD, bool P2>
 __device__ __forceinline__ void gather_tile(const float* __restrict__ force, float* __restrict__ pos,
                                             float* __restrict__ mom, int n, int64_t fstride, float kick, float drift,
                                             const int (&org)[3], float* win, int (*wlo)[3], int (*whi)[3],
@@ -124,9 +124,9 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
     const int loc = t + kBlock * p;
     const int li = loc / (GTY * GTZ), lk = (loc / GTZ) % GTY, ll = loc % GTZ;
     jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
-    x[p] = wrap(pos[jj[p]], n);
-    y[p] = wrap(pos[np + jj[p]], n);
-    z[p] = wrap(pos[2 * np + jj[p]], n);
+    x[p] = wrap_n<P2>(pos[jj[p]], n);
+    y[p] = wrap_n<P2>(pos[np + jj[p]], n);
+    z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
   }
 #pragma unroll
   for (int p = 0; p < GPP; ++p) {
@@ -193,11 +193,13 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
   // stage the force window (row-contiguous along z): all of a thread's loads are
   // issued before its first LDS store, so they are in flight together
   float fa[GCAP / kBlock], fb[GCAP / kBlock], fc[GCAP / kBlock];
+  const WinDiv qsx(sx), qsy(sy);
 #pragma unroll
   for (int k = 0; k < GCAP / kBlock; ++k) {
     const int c = t + kBlock * k;
     if (c < wtot) {
-      const int a = c / sx, b = (c / sy) % W[1], cz = c % sy;
+      int a, b, cz;
+      win_cell(c, qsx, qsy, a, b, cz);
       const int64_t idx = ((int64_t)fold(org[0] + o[0] + a, n) * n + fold(org[1] + o[1] + b, n)) * n +
                           fold(org[2] + o[2] + cz, n);
       fa[k] = force[idx];
@@ -252,9 +254,9 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
     const float ux = x[p] + drift * px, uy = y[p] + drift * py, uz = z[p] + drift * pz;
     if (GUARD && !(isfinite(ux) && isfinite(uy) && isfinite(uz))) atomicAdd(&guard[0], 1u);
     // the new positions replace the old ones in registers (used by the deposit below)
-    x[p] = wrap(ux, n);
-    y[p] = wrap(uy, n);
-    z[p] = wrap(uz, n);
+    x[p] = wrap_n<P2>(ux, n);
+    y[p] = wrap_n<P2>(uy, n);
+    z[p] = wrap_n<P2>(uz, n);
     pos[j] = x[p];
     pos[np + j] = y[p];
     pos[2 * np + j] = z[p];
@@ -263,7 +265,7 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
 
 // One workgroup per NT tiles adjacent along x (NT = 2 with DEPOSIT: their deposit
 // windows are merged, so the halo they share is flushed once).
-template <bool DEPOSIT>
+template <bool DEPOSIT, bool P2>
 __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
                                                              float* __restrict__ mom, int n, int64_t fstride,
                                                              float kick, float drift, float* __restrict__ dens,
@@ -287,7 +289,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
     const int orgs[3] = {(ti * NT + sub) * GTX, tk * GTY, tl * GTZ};
     float xs[GPP], ys[GPP], zs[GPP];
     if (sub > 0) __syncthreads();  // the previous tile is done with the window
-    gather_tile<DEPOSIT>(force, pos, mom, n, fstride, kick, drift, orgs, win, wlo, whi, wsum, xs, ys, zs, guard);
+    gather_tile<DEPOSIT, P2>(force, pos, mom, n, fstride, kick, drift, orgs, win, wlo, whi, wsum, xs, ys, zs, guard);
 #pragma unroll
     for (int p = 0; p < GPP; ++p) {
       x[sub * GPP + p] = xs[p];
@@ -337,10 +339,12 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
   }
   __syncthreads();
   const double scale = (double)w_scale / kFix;
+  const WinDiv qsx(dsx), qsy(dsy);
   for (int c = t; c < dtot; c += kBlock) {
     const unsigned long long v = dwin[c];
     if (v == 0ull) continue;
-    const int a = c / dsx, b = (c / dsy) % D1, cz = c % dsy;
+    int a, b, cz;
+    win_cell(c, qsx, qsy, a, b, cz);
     const int64_t idx = ((int64_t)fold(org[0] + dw.o[0] + a, n) * n + fold(org[1] + dw.o[1] + b, n)) * n +
                         fold(org[2] + dw.o[2] + cz, n);
     atomic_add(dens + idx, (float)((double)v * scale));
@@ -492,14 +496,14 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
   if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % GTZ == 0) {
     const unsigned tiles = (unsigned)((n / GTX) * (n / GTY) * (n / GTZ));
     const float w = (float)((double)n * n * n / (double)np);  // 1 / nbar
-    if (dens)
-      hipLaunchKernelGGL(k_gather_kdk_tiled<true>, dim3(tiles / 2, (unsigned)p->nb), dim3(kBlock), 0, s,
-                         static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), n,
-                         fstride, (float)kick, (float)drift, static_cast<float*>(dens), w, p->guard);
-    else
-      hipLaunchKernelGGL(k_gather_kdk_tiled<false>, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s,
-                         static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), n,
-                         fstride, (float)kick, (float)drift, nullptr, 0.f, nullptr);
+    // a power-of-two N wraps without a division (same results)
+    const bool p2 = (n & (n - 1)) == 0;
+    const dim3 grid(dens ? tiles / 2 : tiles, (unsigned)p->nb);
+    auto kern = dens ? (p2 ? k_gather_kdk_tiled<true, true> : k_gather_kdk_tiled<true, false>)
+                     : (p2 ? k_gather_kdk_tiled<false, true> : k_gather_kdk_tiled<false, false>);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, static_cast<const float*>(force), static_cast<float*>(pos),
+                       static_cast<float*>(mom), n, fstride, (float)kick, (float)drift,
+                       dens ? static_cast<float*>(dens) : nullptr, dens ? w : 0.f, dens ? p->guard : nullptr);
   } else if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_gather_kdk<float>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s,
                        static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), np, p->n,

@@ -17,6 +17,21 @@ __device__ __forceinline__ T wrap(T x, int n) {
   return (y >= fn || !(y >= T(0))) ? T(0) : y;
 }
 
+// wrap for a power-of-two N: x / N is exact as x 2^-log2(N), so the same result
+// without a division
+template <typename T>
+__device__ __forceinline__ T wrap_pow2(T x, int n) {
+  const T fn = T(n);
+  T y = x - fn * floor(ldexp(x, -(int)__builtin_ctz((unsigned)n)));
+  if (y < T(0)) y += fn;
+  return (y >= fn || !(y >= T(0))) ? T(0) : y;
+}
+template <bool P2, typename T>
+__device__ __forceinline__ T wrap_n(T x, int n) {
+  if constexpr (P2) return wrap_pow2(x, n);
+  else return wrap(x, n);
+}
+
 // CIC base node and weights of one coordinate (x in [0, N)): node floor(x) gets
 // 1 - t and node floor(x) + 1 (mod N) gets t = x - floor(x).
 template <typename T>
@@ -44,8 +59,38 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
 // 2^32: integer LDS atomics are much faster than float ones on gfx950, and a window
 // cell cannot overflow (at most 2^31 particles per tile).
 constexpr double kFix = 4294967296.0;
+// round-half-up of w 2^32 for w in [0, 1], from the float's fields: w = m 2^(e - 150)
+// with the 24-bit significand m, so w 2^32 = m 2^s, s = e - 118 <= 9; a left shift is
+// exact, a right shift by -s adds half of the last kept unit first, and below
+// 2^-26 (s < -25) the value is under one half.  Zero and subnormal w give 0.  Equal
+// to floor(w 2^32 + 1/2) for every float in [0, 1].
 __device__ __forceinline__ unsigned long long to_fix(float w) {
-  return (unsigned long long)((double)w * kFix + 0.5);
+  const unsigned b = __float_as_uint(w);
+  const int s = (int)(b >> 23) - 118;
+  const unsigned long long m = (unsigned long long)((b & 0x7FFFFFu) | 0x800000u);
+  if (s >= 0) return m << s;
+  const int r = -s;
+  return r > 25 ? 0ull : (m + (1ull << (r - 1))) >> r;
+}
+
+// Window cells are numbered c = (a W1 + b) W2 + cz.  Their decomposition divides by
+// runtime extents, which a high multiply does exactly in the range windows use
+// (2 <= d < 2^13, 0 <= c < 2^13): with m = floor((2^32 - 1) / d) + 1 the product
+// c m / 2^32 exceeds c / d by less than c / 2^32 < 2^-19, while c / d stays at least
+// 1/d >= 2^-13 below the next integer, so floor(c m / 2^32) = floor(c / d).
+struct WinDiv {
+  unsigned d, m;
+  __device__ __forceinline__ explicit WinDiv(int dd) : d((unsigned)dd), m(0xFFFFFFFFu / (unsigned)dd + 1u) {}
+  __device__ __forceinline__ unsigned quot(unsigned c) const { return __umulhi(c, m); }
+};
+// c -> (a, b, cz) for the strides sx = W1 W2 (in qx) and sy = W2 (in qy)
+__device__ __forceinline__ void win_cell(int c, const WinDiv& qx, const WinDiv& qy, int& a, int& b, int& cz) {
+  const unsigned ua = qx.quot((unsigned)c);
+  const unsigned r = (unsigned)c - ua * qx.d;
+  const unsigned ub = qy.quot(r);
+  a = (int)ua;
+  b = (int)ub;
+  cz = (int)(r - ub * qy.d);
 }
 
 // v in (-N, 2N) -> [0, N)
