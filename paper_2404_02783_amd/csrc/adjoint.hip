@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     y[p] = wrap_n<P2>(pos[np + jj[p]], n);
     z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
   }
-  const TileWindow tw = tile_window<APP>(x, y, z, n, org, ACAP, AWF, AX * AY * AZ, wlo, whi, wsum);
+  const TileWindow tw = tile_window<APP, P2>(x, y, z, n, org, ACAP, AWF, AX * AY * AZ, wlo, whi, wsum);
   const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
   const int sy = W2, sx = W1 * W2;
   const int wtot = W0 * W1 * W2;
@@ -116,8 +116,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     if (c < wtot) {
       int a, b, cz;
       win_cell(c, qsx, qsy, a, b, cz);
-      const int64_t idx = ((int64_t)fold(org[0] + tw.o[0] + a, n) * n + fold(org[1] + tw.o[1] + b, n)) * n +
-                          fold(org[2] + tw.o[2] + cz, n);
+      const int64_t idx = ((int64_t)fold_n<P2>(org[0] + tw.o[0] + a, n) * n + fold_n<P2>(org[1] + tw.o[1] + b, n)) * n +
+                          fold_n<P2>(org[2] + tw.o[2] + cz, n);
       fa[k] = force[idx];
       fb[k] = force[np + idx];
       fc[k] = force[2 * np + idx];
@@ -143,9 +143,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
       lp[d] = lam_mom[d * np + j] + drift * lx[d];
       v[d] = kick * lp[d];
     }
-    const Axis<float> ax = cic_axis(x[p], n), ay = cic_axis(y[p], n), az = cic_axis(z[p], n);
-    const int rx = idiff(ax.i0, org[0], n) - tw.o[0], ry = idiff(ay.i0, org[1], n) - tw.o[1],
-              rz = idiff(az.i0, org[2], n) - tw.o[2];
+    const Axis<float> ax = cic_axis_n<P2>(x[p], n), ay = cic_axis_n<P2>(y[p], n), az = cic_axis_n<P2>(z[p], n);
+    const int rx = idiff_n<P2>(ax.i0, org[0], n) - tw.o[0], ry = idiff_n<P2>(ay.i0, org[1], n) - tw.o[1],
+              rz = idiff_n<P2>(az.i0, org[2], n) - tw.o[2];
     const bool inside = rx >= 0 && rx <= W0 - 2 && ry >= 0 && ry <= W1 - 2 && rz >= 0 && rz <= W2 - 2;
     float gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
       vmax[d] = fmaxf(vmax[d], fabsf(v[d][p]));
     }
   }
-  const TileWindow tw = tile_window<VPP>(x, y, z, n, org, VCAP, VWF, VX * VY * VZ, wlo, whi, wsum);
+  const TileWindow tw = tile_window<VPP, P2>(x, y, z, n, org, VCAP, VWF, VX * VY * VZ, wlo, whi, wsum);
   // per-component fixed-point scale 2^(40 - e), |v| < 2^e over the tile
 #pragma unroll
   for (int d = 0; d < 3; ++d)
@@ -237,11 +237,11 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
   Axis<float> axs[VPP], ays[VPP], azs[VPP];
 #pragma unroll
   for (int p = 0; p < VPP; ++p) {
-    axs[p] = cic_axis(x[p], n);
-    ays[p] = cic_axis(y[p], n);
-    azs[p] = cic_axis(z[p], n);
-    const int rx = idiff(axs[p].i0, org[0], n) - tw.o[0], ry = idiff(ays[p].i0, org[1], n) - tw.o[1],
-              rz = idiff(azs[p].i0, org[2], n) - tw.o[2];
+    axs[p] = cic_axis_n<P2>(x[p], n);
+    ays[p] = cic_axis_n<P2>(y[p], n);
+    azs[p] = cic_axis_n<P2>(z[p], n);
+    const int rx = idiff_n<P2>(axs[p].i0, org[0], n) - tw.o[0], ry = idiff_n<P2>(ays[p].i0, org[1], n) - tw.o[1],
+              rz = idiff_n<P2>(azs[p].i0, org[2], n) - tw.o[2];
     inside[p] = rx >= 0 && rx <= W0 - 2 && ry >= 0 && ry <= W1 - 2 && rz >= 0 && rz <= W2 - 2;
     base[p] = inside[p] ? rx * sx + ry * sy + rz : 0;
     if (!inside[p]) {
@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
         if (q == 0) continue;
         int a, b, cz;
         win_cell(c, qsx, qsy, a, b, cz);
-        const int64_t idx = ((int64_t)fold(org[0] + tw.o[0] + a, n) * n + fold(org[1] + tw.o[1] + b, n)) * n +
-                            fold(org[2] + tw.o[2] + cz, n);
+        const int64_t idx = ((int64_t)fold_n<P2>(org[0] + tw.o[0] + a, n) * n + fold_n<P2>(org[1] + tw.o[1] + b, n)) * n +
+                            fold_n<P2>(org[2] + tw.o[2] + cz, n);
         atomic_add(gd + idx, (float)((double)q * inv));
       }
     }
@@ -302,8 +302,8 @@ __global__ void __launch_bounds__(kBlock) k_grad_gather(const T* __restrict__ h,
   const int64_t i = blk * kBlock + threadIdx.x;
   if (i >= np) return;
   const int64_t n2 = (int64_t)n * n;
-  const Axis<T> ax = cic_axis(wrap_n<P2>(pos[i], n), n), ay = cic_axis(wrap_n<P2>(pos[np + i], n), n),
-                az = cic_axis(wrap_n<P2>(pos[2 * np + i], n), n);
+  const Axis<T> ax = cic_axis_n<P2>(wrap_n<P2>(pos[i], n), n), ay = cic_axis_n<P2>(wrap_n<P2>(pos[np + i], n), n),
+                az = cic_axis_n<P2>(wrap_n<P2>(pos[2 * np + i], n), n);
   T gx = 0, gy = 0, gz = 0;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {

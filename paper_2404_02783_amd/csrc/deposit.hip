@@ -117,8 +117,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
       y[p] = wrap_n<P2>(y[p], n);
       z[p] = wrap_n<P2>(z[p], n);
     }
-    const int r[3] = {idiff((int)floorf(x[p]), org[0], n), idiff((int)floorf(y[p]), org[1], n),
-                      idiff((int)floorf(z[p]), org[2], n)};
+    const int r[3] = {idiff_n<P2>((int)floorf(x[p]), org[0], n), idiff_n<P2>((int)floorf(y[p]), org[1], n),
+                      idiff_n<P2>((int)floorf(z[p]), org[2], n)};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       lo[d] = min(lo[d], r[d]);
@@ -173,9 +173,9 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
 #pragma unroll
   for (int p = 0; p < TPP; ++p) {
     if (x[p] < 0.f) continue;
-    const Axis<float> ax = cic_axis(x[p], n), ay = cic_axis(y[p], n), az = cic_axis(z[p], n);
-    const int rx = idiff(ax.i0, org[0], n) - o[0], ry = idiff(ay.i0, org[1], n) - o[1],
-              rz = idiff(az.i0, org[2], n) - o[2];
+    const Axis<float> ax = cic_axis_n<P2>(x[p], n), ay = cic_axis_n<P2>(y[p], n), az = cic_axis_n<P2>(z[p], n);
+    const int rx = idiff_n<P2>(ax.i0, org[0], n) - o[0], ry = idiff_n<P2>(ay.i0, org[1], n) - o[1],
+              rz = idiff_n<P2>(az.i0, org[2], n) - o[2];
     const float wxy00 = ax.w0 * ay.w0, wxy01 = ax.w0 * ay.w1;
     const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
     if (rx >= 0 && rx <= W[0] - 2 && ry >= 0 && ry <= W[1] - 2 && rz >= 0 && rz <= W[2] - 2) {
@@ -210,8 +210,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
     if (v == 0ull) continue;
     int a, b, cz;
     win_cell(c, qsx, qsy, a, b, cz);
-    const int64_t idx = ((int64_t)fold(org[0] + o[0] + a, n) * n + fold(org[1] + o[1] + b, n)) * n +
-                        fold(org[2] + o[2] + cz, n);
+    const int64_t idx = ((int64_t)fold_n<P2>(org[0] + o[0] + a, n) * n + fold_n<P2>(org[1] + o[1] + b, n)) * n +
+                        fold_n<P2>(org[2] + o[2] + cz, n);
     atomic_add(mesh + idx, (float)((double)v * scale));
   }
 }

@@ -130,8 +130,8 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
   }
 #pragma unroll
   for (int p = 0; p < GPP; ++p) {
-    const int r[3] = {idiff((int)floorf(x[p]), org[0], n), idiff((int)floorf(y[p]), org[1], n),
-                      idiff((int)floorf(z[p]), org[2], n)};
+    const int r[3] = {idiff_n<P2>((int)floorf(x[p]), org[0], n), idiff_n<P2>((int)floorf(y[p]), org[1], n),
+                      idiff_n<P2>((int)floorf(z[p]), org[2], n)};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       lo[d] = min(lo[d], r[d]);
@@ -200,8 +200,8 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
     if (c < wtot) {
       int a, b, cz;
       win_cell(c, qsx, qsy, a, b, cz);
-      const int64_t idx = ((int64_t)fold(org[0] + o[0] + a, n) * n + fold(org[1] + o[1] + b, n)) * n +
-                          fold(org[2] + o[2] + cz, n);
+      const int64_t idx = ((int64_t)fold_n<P2>(org[0] + o[0] + a, n) * n + fold_n<P2>(org[1] + o[1] + b, n)) * n +
+                          fold_n<P2>(org[2] + o[2] + cz, n);
       fa[k] = force[idx];
       fb[k] = force[fstride + idx];
       fc[k] = force[2 * fstride + idx];
@@ -219,9 +219,9 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
   __syncthreads();
 #pragma unroll
   for (int p = 0; p < GPP; ++p) {
-    const Axis<float> ax = cic_axis(x[p], n), ay = cic_axis(y[p], n), az = cic_axis(z[p], n);
-    const int rx = idiff(ax.i0, org[0], n) - o[0], ry = idiff(ay.i0, org[1], n) - o[1],
-              rz = idiff(az.i0, org[2], n) - o[2];
+    const Axis<float> ax = cic_axis_n<P2>(x[p], n), ay = cic_axis_n<P2>(y[p], n), az = cic_axis_n<P2>(z[p], n);
+    const int rx = idiff_n<P2>(ax.i0, org[0], n) - o[0], ry = idiff_n<P2>(ay.i0, org[1], n) - o[1],
+              rz = idiff_n<P2>(az.i0, org[2], n) - o[2];
     const float w[4] = {ax.w0 * ay.w0, ax.w0 * ay.w1, ax.w1 * ay.w0, ax.w1 * ay.w1};
     float fx = 0.f, fy = 0.f, fz = 0.f;
     if (rx >= 0 && rx <= W[0] - 2 && ry >= 0 && ry <= W[1] - 2 && rz >= 0 && rz <= W[2] - 2) {
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
   __syncthreads();  // every thread is done with the force window
   unsigned long long* dwin = reinterpret_cast<unsigned long long*>(win);
   const int org[3] = {ti * NT * GTX, tk * GTY, tl * GTZ};
-  const TileWindow dw = tile_window<NT * GPP>(x, y, z, n, org, DCAP, DWF, NT * GTX * GTY * GTZ, wlo, whi, wsum);
+  const TileWindow dw = tile_window<NT * GPP, P2>(x, y, z, n, org, DCAP, DWF, NT * GTX * GTY * GTZ, wlo, whi, wsum);
   const int D0 = dw.W[0], D1 = dw.W[1], D2 = dw.W[2];
   const int dtot = D0 * D1 * D2;
   for (int c = t; c < dtot; c += kBlock) dwin[c] = 0ull;
@@ -309,9 +309,9 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
   const int dsy = D2, dsx = D1 * D2;
 #pragma unroll
   for (int p = 0; p < NT * GPP; ++p) {
-    const Axis<float> ax = cic_axis(x[p], n), ay = cic_axis(y[p], n), az = cic_axis(z[p], n);
-    const int rx = idiff(ax.i0, org[0], n) - dw.o[0], ry = idiff(ay.i0, org[1], n) - dw.o[1],
-              rz = idiff(az.i0, org[2], n) - dw.o[2];
+    const Axis<float> ax = cic_axis_n<P2>(x[p], n), ay = cic_axis_n<P2>(y[p], n), az = cic_axis_n<P2>(z[p], n);
+    const int rx = idiff_n<P2>(ax.i0, org[0], n) - dw.o[0], ry = idiff_n<P2>(ay.i0, org[1], n) - dw.o[1],
+              rz = idiff_n<P2>(az.i0, org[2], n) - dw.o[2];
     const float wxy00 = ax.w0 * ay.w0, wxy01 = ax.w0 * ay.w1;
     const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
     if (rx >= 0 && rx <= D0 - 2 && ry >= 0 && ry <= D1 - 2 && rz >= 0 && rz <= D2 - 2) {
@@ -345,8 +345,8 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
     if (v == 0ull) continue;
     int a, b, cz;
     win_cell(c, qsx, qsy, a, b, cz);
-    const int64_t idx = ((int64_t)fold(org[0] + dw.o[0] + a, n) * n + fold(org[1] + dw.o[1] + b, n)) * n +
-                        fold(org[2] + dw.o[2] + cz, n);
+    const int64_t idx = ((int64_t)fold_n<P2>(org[0] + dw.o[0] + a, n) * n + fold_n<P2>(org[1] + dw.o[1] + b, n)) * n +
+                        fold_n<P2>(org[2] + dw.o[2] + cz, n);
     atomic_add(dens + idx, (float)((double)v * scale));
   }
 }

@@ -49,6 +49,20 @@ __device__ __forceinline__ Axis<T> cic_axis(T x, int n) {
   a.w0 = T(1) - a.w1;
   return a;
 }
+template <bool P2, typename T>
+__device__ __forceinline__ Axis<T> cic_axis_n(T x, int n) {
+  if constexpr (P2) {
+    Axis<T> a;
+    const T f = floor(x);
+    a.i0 = (int)f;
+    a.i1 = (a.i0 + 1) & (n - 1);
+    a.w1 = x - f;
+    a.w0 = T(1) - a.w1;
+    return a;
+  } else {
+    return cic_axis(x, n);
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ void atomic_add(T* p, T v) {
@@ -102,6 +116,20 @@ __device__ __forceinline__ int idiff(int a, int b, int n) {
   else if (d < -n / 2) d += n;
   return d;
 }
+// The same for a power-of-two N (P2) with masks instead of compares and selects.
+// idiff_n<true> returns [-N/2, N/2) (a difference of exactly N/2 comes out as -N/2):
+// a kernel uses one of the two forms throughout, so tile-relative coordinates stay
+// consistent.
+template <bool P2>
+__device__ __forceinline__ int fold_n(int v, int n) {
+  if constexpr (P2) return (v + n) & (n - 1);
+  else return fold(v, n);
+}
+template <bool P2>
+__device__ __forceinline__ int idiff_n(int a, int b, int n) {
+  if constexpr (P2) return ((a - b + n / 2) & (n - 1)) - n / 2;
+  else return idiff(a, b, n);
+}
 
 // Window of a Lagrangian tile (one 256-thread block, PP particles per thread): the
 // bounding box of the particles' CIC base cells floor(x), relative to the tile
@@ -112,7 +140,7 @@ __device__ __forceinline__ int idiff(int a, int b, int n) {
 struct TileWindow {
   int o[3], W[3];
 };
-template <int PP>
+template <int PP, bool P2>
 __device__ __forceinline__ TileWindow tile_window(const float (&x)[PP], const float (&y)[PP], const float (&z)[PP],
                                                   int n, const int (&org)[3], int cap, int side, int count,
                                                   int (*wlo)[3], int (*whi)[3], float (*wsum)[3]) {
@@ -122,8 +150,8 @@ __device__ __forceinline__ TileWindow tile_window(const float (&x)[PP], const fl
 #pragma unroll
   for (int p = 0; p < PP; ++p) {
     if (x[p] < 0.f) continue;
-    const int r[3] = {idiff((int)floorf(x[p]), org[0], n), idiff((int)floorf(y[p]), org[1], n),
-                      idiff((int)floorf(z[p]), org[2], n)};
+    const int r[3] = {idiff_n<P2>((int)floorf(x[p]), org[0], n), idiff_n<P2>((int)floorf(y[p]), org[1], n),
+                      idiff_n<P2>((int)floorf(z[p]), org[2], n)};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       lo[d] = min(lo[d], r[d]);
