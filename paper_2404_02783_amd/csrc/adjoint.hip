@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
   for (int p = 0; p < APP; ++p) {
     const int loc = t + kBlock * p;
     const int li = loc / (AY * AZ), lk = (loc / AZ) % AY, ll = loc % AZ;
-    jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
+    jj[p] = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
     x[p] = wrap_n<P2>(pos[jj[p]], n);
     y[p] = wrap_n<P2>(pos[np + jj[p]], n);
     z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
@@ -116,8 +116,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     if (c < wtot) {
       int a, b, cz;
       win_cell(c, qsx, qsy, a, b, cz);
-      const int64_t idx = ((int64_t)fold_n<P2>(org[0] + tw.o[0] + a, n) * n + fold_n<P2>(org[1] + tw.o[1] + b, n)) * n +
-                          fold_n<P2>(org[2] + tw.o[2] + cz, n);
+      const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + tw.o[0] + a, n), fold_n<P2>(org[1] + tw.o[1] + b, n),
+                                          fold_n<P2>(org[2] + tw.o[2] + cz, n), n);
       fa[k] = force[idx];
       fb[k] = force[np + idx];
       fc[k] = force[2 * np + idx];
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
   for (int p = 0; p < VPP; ++p) {
     const int loc = t + kBlock * p;
     const int li = loc / (VY * VZ), lk = (loc / VZ) % VY, ll = loc % VZ;
-    jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
+    jj[p] = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
     x[p] = wrap_n<P2>(pos[jj[p]], n);
     y[p] = wrap_n<P2>(pos[np + jj[p]], n);
     z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
         if (q == 0) continue;
         int a, b, cz;
         win_cell(c, qsx, qsy, a, b, cz);
-        const int64_t idx = ((int64_t)fold_n<P2>(org[0] + tw.o[0] + a, n) * n + fold_n<P2>(org[1] + tw.o[1] + b, n)) * n +
-                            fold_n<P2>(org[2] + tw.o[2] + cz, n);
+        const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + tw.o[0] + a, n), fold_n<P2>(org[1] + tw.o[1] + b, n),
+                                            fold_n<P2>(org[2] + tw.o[2] + cz, n), n);
         atomic_add(gd + idx, (float)((double)q * inv));
       }
     }
@@ -363,7 +363,7 @@ int launch_adj_gather_kdk(const pm_plan* p, const void* force, const void* pos, 
                           void* lam_pos, void* lam_mom, void* g, hipStream_t s) {
   if (np <= 0) return PM_OK;
   const int n = p->n;
-  if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % AZ == 0) {
+  if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n <= 1024 && n % AZ == 0) {
     {
       ProfScope ps(p, PK_ADJ_GATHER, s);
       const unsigned tiles = (unsigned)((n / AX) * (n / AY) * (n / AZ));

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
   for (int p = 0; p < TPP; ++p) {
     const int loc = t + kBlock * p;
     const int li = loc / (TY * TZ), lk = (loc / TZ) % TY, ll = loc % TZ;
-    const int64_t j = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
+    const int64_t j = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
     x[p] = pos[j];
     y[p] = pos[np + j];
     z[p] = pos[2 * np + j];
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
     const float wxy00 = ax.w0 * ay.w0, wxy01 = ax.w0 * ay.w1;
     const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
     if (rx >= 0 && rx <= W[0] - 2 && ry >= 0 && ry <= W[1] - 2 && rz >= 0 && rz <= W[2] - 2) {
-      unsigned long long* w = win + rx * sx + ry * sy + rz;
+      unsigned long long* w = win + win_index(rx, ry, rz, sx, sy);
       atomicAdd(w, to_fix(wxy00 * az.w0));
       atomicAdd(w + 1, to_fix(wxy00 * az.w1));
       atomicAdd(w + sy, to_fix(wxy01 * az.w0));
@@ -210,8 +210,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
     if (v == 0ull) continue;
     int a, b, cz;
     win_cell(c, qsx, qsy, a, b, cz);
-    const int64_t idx = ((int64_t)fold_n<P2>(org[0] + o[0] + a, n) * n + fold_n<P2>(org[1] + o[1] + b, n)) * n +
-                        fold_n<P2>(org[2] + o[2] + cz, n);
+    const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + o[0] + a, n), fold_n<P2>(org[1] + o[1] + b, n),
+                                        fold_n<P2>(org[2] + o[2] + cz, n), n);
     atomic_add(mesh + idx, (float)((double)v * scale));
   }
 }
@@ -226,7 +226,7 @@ int launch_deposit(const pm_plan* p, const void* pos, int64_t np, void* mesh, hi
   const int n = p->n;
   const double n3 = (double)n * n * n;
   const double w = n3 / (double)np;  // 1 / nbar
-  if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % TZ == 0 && n % TX == 0) {
+  if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n <= 1024 && n % TZ == 0 && n % TX == 0) {
     const unsigned tiles = (unsigned)((n / TX) * (n / TY) * (n / TZ));
     // a power-of-two N wraps without a division (same results)
     auto kern = (n & (n - 1)) == 0 ? k_deposit_tiled<true> : k_deposit_tiled<false>;

@@ -123,7 +123,7 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
   for (int p = 0; p < GPP; ++p) {
     const int loc = t + kBlock * p;
     const int li = loc / (GTY * GTZ), lk = (loc / GTZ) % GTY, ll = loc % GTZ;
-    jj[p] = ((int64_t)(org[0] + li) * n + (org[1] + lk)) * n + (org[2] + ll);
+    jj[p] = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
     x[p] = wrap_n<P2>(pos[jj[p]], n);
     y[p] = wrap_n<P2>(pos[np + jj[p]], n);
     z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
@@ -200,8 +200,8 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
     if (c < wtot) {
       int a, b, cz;
       win_cell(c, qsx, qsy, a, b, cz);
-      const int64_t idx = ((int64_t)fold_n<P2>(org[0] + o[0] + a, n) * n + fold_n<P2>(org[1] + o[1] + b, n)) * n +
-                          fold_n<P2>(org[2] + o[2] + cz, n);
+      const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + o[0] + a, n), fold_n<P2>(org[1] + o[1] + b, n),
+                                          fold_n<P2>(org[2] + o[2] + cz, n), n);
       fa[k] = force[idx];
       fb[k] = force[fstride + idx];
       fc[k] = force[2 * fstride + idx];
@@ -225,7 +225,7 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
     const float w[4] = {ax.w0 * ay.w0, ax.w0 * ay.w1, ax.w1 * ay.w0, ax.w1 * ay.w1};
     float fx = 0.f, fy = 0.f, fz = 0.f;
     if (rx >= 0 && rx <= W[0] - 2 && ry >= 0 && ry <= W[1] - 2 && rz >= 0 && rz <= W[2] - 2) {
-      const int base = rx * sx + ry * sy + rz;
+      const int base = win_index(rx, ry, rz, sx, sy);
       const int r[4] = {base, base + sy, base + sx, base + sx + sy};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
     const float wxy00 = ax.w0 * ay.w0, wxy01 = ax.w0 * ay.w1;
     const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
     if (rx >= 0 && rx <= D0 - 2 && ry >= 0 && ry <= D1 - 2 && rz >= 0 && rz <= D2 - 2) {
-      unsigned long long* w = dwin + rx * dsx + ry * dsy + rz;
+      unsigned long long* w = dwin + win_index(rx, ry, rz, dsx, dsy);
       atomicAdd(w, to_fix(wxy00 * az.w0));
       atomicAdd(w + 1, to_fix(wxy00 * az.w1));
       atomicAdd(w + dsy, to_fix(wxy01 * az.w0));
@@ -345,8 +345,8 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
     if (v == 0ull) continue;
     int a, b, cz;
     win_cell(c, qsx, qsy, a, b, cz);
-    const int64_t idx = ((int64_t)fold_n<P2>(org[0] + dw.o[0] + a, n) * n + fold_n<P2>(org[1] + dw.o[1] + b, n)) * n +
-                        fold_n<P2>(org[2] + dw.o[2] + cz, n);
+    const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + dw.o[0] + a, n), fold_n<P2>(org[1] + dw.o[1] + b, n),
+                                        fold_n<P2>(org[2] + dw.o[2] + cz, n), n);
     atomic_add(dens + idx, (float)((double)v * scale));
   }
 }
@@ -483,7 +483,7 @@ int launch_gather(const pm_plan* p, const void* force, const void* pos, int64_t 
 
 bool gather_kdk_can_deposit(const pm_plan* p, int64_t np) {
   const int n = p->n;
-  return p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % GTZ == 0;
+  return p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n <= 1024 && n % GTZ == 0;
 }
 
 int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom, int64_t np, double kick,
@@ -493,7 +493,7 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
   const int n = p->n;
   const int64_t fstride = (int64_t)p->nb * n * n * n;  // force meshes are [3][nb][N^3]
   if (dens && !gather_kdk_can_deposit(p, np)) return set_error(PM_ERR_ARG, "fused deposit needs a full FP32 lattice");
-  if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n % GTZ == 0) {
+  if (gather_kdk_can_deposit(p, np)) {  // a full FP32 lattice, 64 <= N <= 1024
     const unsigned tiles = (unsigned)((n / GTX) * (n / GTY) * (n / GTZ));
     const float w = (float)((double)n * n * n / (double)np);  // 1 / nbar
     // a power-of-two N wraps without a division (same results)

@@ -87,6 +87,24 @@ __device__ __forceinline__ unsigned long long to_fix(float w) {
   return r > 25 ? 0ull : (m + (1ull << (r - 1))) >> r;
 }
 
+// Flat index (i N + j) N + l of a mesh node (i, j, l in [0, N)) as a 32-bit value
+// (N <= 1024, so below 2^30): shifts for a power-of-two N, else 24-bit multiplies
+// (full rate, where a 32-bit multiply is quarter rate).
+template <bool P2>
+__device__ __forceinline__ unsigned node_index(int i, int j, int l, int n) {
+  if constexpr (P2) {
+    const int k = __builtin_ctz((unsigned)n);
+    return ((((unsigned)i << k) | (unsigned)j) << k) | (unsigned)l;
+  } else {
+    return (unsigned)__umul24((unsigned)__umul24((unsigned)i, (unsigned)n) + (unsigned)j, (unsigned)n) + (unsigned)l;
+  }
+}
+
+// Window cell number a sx + b sy + c of in-window offsets (all products below 2^24)
+__device__ __forceinline__ int win_index(int a, int b, int c, int sx, int sy) {
+  return __umul24((unsigned)a, (unsigned)sx) + __umul24((unsigned)b, (unsigned)sy) + c;
+}
+
 // Window cells are numbered c = (a W1 + b) W2 + cz.  Their decomposition divides by
 // runtime extents, which a high multiply does exactly in the range windows use
 // (2 <= d < 2^13, 0 <= c < 2^13): with m = floor((2^32 - 1) / d) + 1 the product
@@ -100,11 +118,11 @@ struct WinDiv {
 // c -> (a, b, cz) for the strides sx = W1 W2 (in qx) and sy = W2 (in qy)
 __device__ __forceinline__ void win_cell(int c, const WinDiv& qx, const WinDiv& qy, int& a, int& b, int& cz) {
   const unsigned ua = qx.quot((unsigned)c);
-  const unsigned r = (unsigned)c - ua * qx.d;
+  const unsigned r = (unsigned)c - (unsigned)__umul24(ua, qx.d);
   const unsigned ub = qy.quot(r);
   a = (int)ua;
   b = (int)ub;
-  cz = (int)(r - ub * qy.d);
+  cz = (int)(r - (unsigned)__umul24(ub, qy.d));
 }
 
 // v in (-N, 2N) -> [0, N)
