@@ -77,7 +77,6 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_kdk(const T* __restrict__
 constexpr int AX = 4, AY = 8, AZ = 32;
 constexpr int APP = AX * AY * AZ / kBlock;
 constexpr int ACAP = 4096;
-constexpr int AWF = 16;
 
 template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __restrict__ force, const float* __restrict__ pos,
@@ -103,7 +102,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     y[p] = wrap_n<P2>(pos[np + jj[p]], n);
     z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
   }
-  const TileWindow tw = tile_window<APP, P2>(x, y, z, n, org, ACAP, AWF, AX * AY * AZ, wlo, whi, wsum);
+  const TileWindow tw = tile_window<APP, P2>(x, y, z, n, org, ACAP, AX * AY * AZ, wlo, whi, wsum);
   const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
   const int sy = W2, sx = W1 * W2;
   const int wtot = W0 * W1 * W2;
@@ -176,7 +175,6 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
 constexpr int VX = 8, VY = 8, VZ = 16;
 constexpr int VPP = VX * VY * VZ / kBlock;
 constexpr int VCAP = 4096;
-constexpr int VWF = 16;
 // g[d] += sum_p W(x_p - c) v_{p,d}, v = kick * lam_mom, one tile per block: the
 // window is accumulated in LDS and added to g with one global atomic per non-empty
 // cell; particles outside their tile's window go to global atomics directly.
@@ -210,7 +208,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
       vmax[d] = fmaxf(vmax[d], fabsf(v[d][p]));
     }
   }
-  const TileWindow tw = tile_window<VPP, P2>(x, y, z, n, org, VCAP, VWF, VX * VY * VZ, wlo, whi, wsum);
+  const TileWindow tw = tile_window<VPP, P2>(x, y, z, n, org, VCAP, VX * VY * VZ, wlo, whi, wsum);
   // per-component fixed-point scale 2^(40 - e), |v| < 2^e over the tile
 #pragma unroll
   for (int d = 0; d < 3; ++d)

@@ -60,7 +60,6 @@ __global__ void __launch_bounds__(kBlock) k_deposit(const T* __restrict__ pos, i
 constexpr int TX = 8, TY = 8, TZ = 16;
 constexpr int TPP = TX * TY * TZ / kBlock;  // particles per thread
 constexpr int WCAP = 4096;                  // LDS window cells (u64)
-constexpr int WF = 16;                      // fallback window side (WF^3 <= WCAP)
 
 template <typename F>
 __device__ __forceinline__ int wave_reduce_i(int v, F op) {
@@ -73,9 +72,9 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 }
 
 // np = N^3, particle (i N + k) N + l started in cell (i, k, l).  The window is the
-// bounding box of the tile's CIC cells when it fits in WCAP cells, else a WF^3 box
-// around the mean base cell; particles whose cells fall outside the window go to
-// global atomics.  All window arithmetic is integer on the base nodes floor(x).
+// bounding box of the tile's CIC cells when it fits in WCAP cells, else fit_box's
+// smaller box of the same proportions; particles whose cells fall outside the window
+// go to global atomics.  All window arithmetic is integer on the base nodes floor(x).
 template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restrict__ pos, float* __restrict__ mesh,
                                                           int n, double w_scale, unsigned* __restrict__ guard) {
@@ -158,13 +157,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
     vol *= W[d];
     mean[d] = s * (1.f / float(TX * TY * TZ));
   }
-  if (vol > WCAP) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      o[d] = (int)rintf(mean[d]) - WF / 2;
-      W[d] = WF;
-    }
-  }
+  if (vol > WCAP) fit_box(o, W, mean, vol, WCAP);
   const int wtot = W[0] * W[1] * W[2];
   for (int c = t; c < wtot; c += kBlock) win[c] = 0ull;
   __syncthreads();

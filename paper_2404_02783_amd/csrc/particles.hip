@@ -88,13 +88,12 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk(const T* __restrict__ for
 // owns a Lagrangian tile of GTX x GTY x GTZ particles, loads the three force meshes
 // over the bounding box of the tile's CIC cells into LDS with row-contiguous loads
 // (neighbouring tiles on the same XCD re-read overlapping rows from L2), and
-// interpolates from LDS.  If the box exceeds the LDS capacity, a GWF^3 box around
-// the mean base cell is staged and particles outside it read the meshes directly.
+// interpolates from LDS.  If the box exceeds the LDS capacity, fit_box's smaller box
+// of the same proportions is staged and particles outside it read the meshes directly.
 // Weights and arithmetic are those of k_gather_kdk.
 constexpr int GTX = 4, GTY = 8, GTZ = 32;
 constexpr int GPP = GTX * GTY * GTZ / kBlock;  // particles per thread
 constexpr int GCAP = 4096;                     // staged cells (x3 components, float)
-constexpr int GWF = 16;                        // fallback box side (GWF^3 <= GCAP)
 
 // DEPOSIT: after the drift, the tile's new positions are also deposited into `dens`
 // (pre-filled with -1, box offset N^3) exactly as the standalone tiled deposit does --
@@ -103,7 +102,6 @@ constexpr int GWF = 16;                        // fallback box side (GWF^3 <= GC
 // global atomics for particles outside the window -- so the next cycle need not read
 // the positions again.
 constexpr int DCAP = 3 * GCAP * (int)sizeof(float) / (int)sizeof(unsigned long long);
-constexpr int DWF = 18;  // fallback deposit box side (DWF^3 <= DCAP)
 // Gather + kick + drift of one GTX x GTY x GTZ Lagrangian tile at `org` (block-wide):
 // stages the three force meshes over the tile's CIC bounding box in `win`, updates
 // (pos, mom) and leaves the drifted, wrapped positions in (x, y, z).  GUARD counts
@@ -173,13 +171,7 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
     vol *= W[d];
     mean[d] = s * (1.f / float(GTX * GTY * GTZ));
   }
-  if (vol > GCAP) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      o[d] = (int)rintf(mean[d]) - GWF / 2;
-      W[d] = GWF;
-    }
-  }
+  if (vol > GCAP) fit_box(o, W, mean, vol, GCAP);
   const int wtot = W[0] * W[1] * W[2];
   const int sy = W[2], sx = W[1] * W[2];
   // the momenta are needed only after the window: start their loads now
@@ -301,7 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __rest
   __syncthreads();  // every thread is done with the force window
   unsigned long long* dwin = reinterpret_cast<unsigned long long*>(win);
   const int org[3] = {ti * NT * GTX, tk * GTY, tl * GTZ};
-  const TileWindow dw = tile_window<NT * GPP, P2>(x, y, z, n, org, DCAP, DWF, NT * GTX * GTY * GTZ, wlo, whi, wsum);
+  const TileWindow dw = tile_window<NT * GPP, P2>(x, y, z, n, org, DCAP, NT * GTX * GTY * GTZ, wlo, whi, wsum);
   const int D0 = dw.W[0], D1 = dw.W[1], D2 = dw.W[2];
   const int dtot = D0 * D1 * D2;
   for (int c = t; c < dtot; c += kBlock) dwin[c] = 0ull;

@@ -149,18 +149,44 @@ __device__ __forceinline__ int idiff_n(int a, int b, int n) {
   else return idiff(a, b, n);
 }
 
+// Window of a tile whose bounding box (origin o, extents W, volume vol) exceeds the
+// LDS capacity `cap` (>= 8): the same proportions scaled by (cap/vol)^(1/3), each side
+// at least 2; while the volume still exceeds cap the longest side is cut to
+// cap / (product of the other two) (at least 2), which fits after at most three cuts;
+// centred on the tile's mean base cell and kept inside the bounding box.  Particles outside it take the direct global
+// path; for late-time (clustered) tiles this leaves about a tenth of the particles a
+// fixed cube would.  Every thread computes the same box.
+__device__ __forceinline__ void fit_box(int (&o)[3], int (&W)[3], const float (&mean)[3], int64_t vol, int cap) {
+  const float f = cbrtf((float)cap / (float)vol);
+  int Wf[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) Wf[d] = max(2, min(W[d], (int)((float)W[d] * f)));
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    const int m = Wf[0] >= Wf[1] ? (Wf[0] >= Wf[2] ? 0 : 2) : (Wf[1] >= Wf[2] ? 1 : 2);
+    const int rest = Wf[m == 0 ? 1 : 0] * Wf[m == 2 ? 1 : 2];
+    if (Wf[m] * rest > cap) Wf[m] = max(2, cap / rest);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int c = (int)rintf(mean[d]) - Wf[d] / 2;
+    o[d] = max(o[d], min(c, o[d] + W[d] - Wf[d]));
+    W[d] = Wf[d];
+  }
+}
+
 // Window of a Lagrangian tile (one 256-thread block, PP particles per thread): the
 // bounding box of the particles' CIC base cells floor(x), relative to the tile
 // origin `org` (minimum image), widened by one cell so the +1 CIC neighbours fit:
-// cells [o_d, o_d + W_d).  If its volume exceeds `cap` cells, a side^3 box around the
-// mean base cell is used instead.  Particles with x < 0 are skipped.  Block-wide
+// cells [o_d, o_d + W_d).  If its volume exceeds `cap` cells, fit_box's smaller box
+// is used instead.  Particles with x < 0 are skipped.  Block-wide
 // (every thread must call); wlo/whi/wsum are __shared__ [4][3] scratch.
 struct TileWindow {
   int o[3], W[3];
 };
 template <int PP, bool P2>
 __device__ __forceinline__ TileWindow tile_window(const float (&x)[PP], const float (&y)[PP], const float (&z)[PP],
-                                                  int n, const int (&org)[3], int cap, int side, int count,
+                                                  int n, const int (&org)[3], int cap, int count,
                                                   int (*wlo)[3], int (*whi)[3], float (*wsum)[3]) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
@@ -212,13 +238,7 @@ __device__ __forceinline__ TileWindow tile_window(const float (&x)[PP], const fl
     vol *= w.W[d];
     mean[d] = s / float(count);
   }
-  if (vol > cap) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      w.o[d] = (int)rintf(mean[d]) - side / 2;
-      w.W[d] = side;
-    }
-  }
+  if (vol > cap) fit_box(w.o, w.W, mean, vol, cap);
   __syncthreads();  // the scratch may be reused after return
   return w;
 }
