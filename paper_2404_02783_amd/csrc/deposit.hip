@@ -61,16 +61,6 @@ constexpr int TX = 8, TY = 8, TZ = 16;
 constexpr int TPP = TX * TY * TZ / kBlock;  // particles per thread
 constexpr int WCAP = 4096;                  // LDS window cells (u64)
 
-template <typename F>
-__device__ __forceinline__ int wave_reduce_i(int v, F op) {
-  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ __forceinline__ float wave_sum_f(float v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // np = N^3, particle (i N + k) N + l started in cell (i, k, l).  The window is the
 // bounding box of the tile's CIC cells when it fits in WCAP cells, else fit_box's
 // smaller box of the same proportions; particles whose cells fall outside the window
@@ -89,7 +79,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
   const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
   (void)tpx;
   const int org[3] = {ti * TX, tk * TY, tl * TZ};
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int t = threadIdx.x;
   const float fn = float(n);
   float x[TPP], y[TPP], z[TPP];
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
@@ -125,39 +115,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
       sum[d] += float(r[d]);
     }
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    lo[d] = wave_reduce_i(lo[d], [](int a, int b) { return min(a, b); });
-    hi[d] = wave_reduce_i(hi[d], [](int a, int b) { return max(a, b); });
-    sum[d] = wave_sum_f(sum[d]);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      wlo[wave][d] = lo[d];
-      whi[wave][d] = hi[d];
-      wsum[wave][d] = sum[d];
-    }
-  }
-  __syncthreads();
   int o[3], W[3];
-  int64_t vol = 1;
-  float mean[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int a = wlo[0][d], b = whi[0][d];
-    float s = wsum[0][d];
-    for (int w = 1; w < kBlock / 64; ++w) {
-      a = min(a, wlo[w][d]);
-      b = max(b, whi[w][d]);
-      s += wsum[w][d];
-    }
-    o[d] = a;
-    W[d] = b >= a ? b - a + 2 : 2;
-    vol *= W[d];
-    mean[d] = s * (1.f / float(TX * TY * TZ));
-  }
-  if (vol > WCAP) fit_box(o, W, mean, vol, WCAP);
+  block_window(lo, hi, sum, TX * TY * TZ, WCAP, wlo, whi, wsum, o, W);
   const int wtot = W[0] * W[1] * W[2];
   for (int c = t; c < wtot; c += kBlock) win[c] = 0ull;
   __syncthreads();

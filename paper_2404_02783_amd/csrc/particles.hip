@@ -113,7 +113,7 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
                                             float (*wsum)[3], float (&x)[GPP], float (&y)[GPP], float (&z)[GPP],
                                             unsigned* __restrict__ guard) {
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int t = threadIdx.x;
   int64_t jj[GPP];
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
   float sum[3] = {0.f, 0.f, 0.f};
@@ -137,41 +137,8 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
       sum[d] += float(r[d]);
     }
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    for (int off = 32; off > 0; off >>= 1) {
-      lo[d] = min(lo[d], __shfl_xor(lo[d], off, 64));
-      hi[d] = max(hi[d], __shfl_xor(hi[d], off, 64));
-      sum[d] += __shfl_xor(sum[d], off, 64);
-    }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      wlo[wave][d] = lo[d];
-      whi[wave][d] = hi[d];
-      wsum[wave][d] = sum[d];
-    }
-  }
-  __syncthreads();
   int o[3], W[3];
-  int64_t vol = 1;
-  float mean[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int a = wlo[0][d], b = whi[0][d];
-    float s = wsum[0][d];
-    for (int w = 1; w < kBlock / 64; ++w) {
-      a = min(a, wlo[w][d]);
-      b = max(b, whi[w][d]);
-      s += wsum[w][d];
-    }
-    o[d] = a;
-    W[d] = b - a + 2;
-    vol *= W[d];
-    mean[d] = s * (1.f / float(GTX * GTY * GTZ));
-  }
-  if (vol > GCAP) fit_box(o, W, mean, vol, GCAP);
+  block_window(lo, hi, sum, GTX * GTY * GTZ, GCAP, wlo, whi, wsum, o, W);
   const int wtot = W[0] * W[1] * W[2];
   const int sy = W[2], sx = W[1] * W[2];
   // the momenta are needed only after the window: start their loads now
@@ -258,7 +225,7 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
 // One workgroup per NT tiles adjacent along x (NT = 2 with DEPOSIT: their deposit
 // windows are merged, so the halo they share is flushed once).
 template <bool DEPOSIT, bool P2>
-__global__ void __launch_bounds__(kBlock) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
+__global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
                                                              float* __restrict__ mom, int n, int64_t fstride,
                                                              float kick, float drift, float* __restrict__ dens,
                                                              float w_scale, unsigned* __restrict__ guard) {

@@ -175,6 +175,70 @@ __device__ __forceinline__ void fit_box(int (&o)[3], int (&W)[3], const float (&
   }
 }
 
+// Block-wide (256 threads) window from per-thread ranges [lo_d, hi_d] of tile-relative
+// base cells and per-thread sums of them over `count` particles: o = the block's
+// minimum, W = max - min + 2 (a 2-cell box at 0 when no thread saw a particle); if the
+// volume exceeds `cap`, the sums are reduced too and fit_box shrinks the window.
+// Within a wave lo and -hi travel together as two 16-bit halves (|values| < 2^15):
+// one shuffle and one packed minimum per step.  wlo/whi/wsum: __shared__ [4][3]
+// scratch, free again on return; every thread must call.
+__device__ __forceinline__ int pack_lo_nhi(int lo, int hi) {
+  const int a = max(-32767, min(32767, lo)), b = max(-32767, min(32767, -hi));
+  return (int)((unsigned)(unsigned short)a | ((unsigned)(unsigned short)b << 16));
+}
+__device__ __forceinline__ int min_lo_nhi(int u, int v) {
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(int, __builtin_elementwise_min(__builtin_bit_cast(s16x2, u), __builtin_bit_cast(s16x2, v)));
+}
+__device__ __forceinline__ void block_window(const int (&lo)[3], const int (&hi)[3], const float (&sum)[3], int count,
+                                             int cap, int (*wlo)[3], int (*whi)[3], float (*wsum)[3], int (&o)[3],
+                                             int (&W)[3]) {
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  int pk[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    pk[d] = pack_lo_nhi(lo[d], hi[d]);
+    for (int off = 32; off > 0; off >>= 1) pk[d] = min_lo_nhi(pk[d], __shfl_xor(pk[d], off, 64));
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      wlo[wave][d] = (int)(short)(pk[d] & 0xFFFF);
+      whi[wave][d] = -(int)(short)((unsigned)pk[d] >> 16);
+    }
+  }
+  __syncthreads();
+  int64_t vol = 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int a = wlo[0][d], b = whi[0][d];
+    for (int k = 1; k < 4; ++k) {
+      a = min(a, wlo[k][d]);
+      b = max(b, whi[k][d]);
+    }
+    if (b < a) a = b = 0;  // no particle: an empty 2-cell box at the origin
+    o[d] = a;
+    W[d] = b - a + 2;
+    vol *= W[d];
+  }
+  if (vol > cap) {  // the same decision in every thread
+    float sm[3] = {sum[0], sum[1], sum[2]};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      for (int off = 32; off > 0; off >>= 1) sm[d] += __shfl_xor(sm[d], off, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) wsum[wave][d] = sm[d];
+    }
+    __syncthreads();
+    float mean[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) mean[d] = (wsum[0][d] + wsum[1][d] + wsum[2][d] + wsum[3][d]) / float(count);
+    fit_box(o, W, mean, vol, cap);
+  }
+  __syncthreads();  // the scratch may be reused after return
+}
+
 // Window of a Lagrangian tile (one 256-thread block, PP particles per thread): the
 // bounding box of the particles' CIC base cells floor(x), relative to the tile
 // origin `org` (minimum image), widened by one cell so the +1 CIC neighbours fit:
@@ -188,7 +252,6 @@ template <int PP, bool P2>
 __device__ __forceinline__ TileWindow tile_window(const float (&x)[PP], const float (&y)[PP], const float (&z)[PP],
                                                   int n, const int (&org)[3], int cap, int count,
                                                   int (*wlo)[3], int (*whi)[3], float (*wsum)[3]) {
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
   float sum[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -203,43 +266,8 @@ __device__ __forceinline__ TileWindow tile_window(const float (&x)[PP], const fl
       sum[d] += float(r[d]);
     }
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    for (int off = 32; off > 0; off >>= 1) {
-      lo[d] = min(lo[d], __shfl_xor(lo[d], off, 64));
-      hi[d] = max(hi[d], __shfl_xor(hi[d], off, 64));
-      sum[d] += __shfl_xor(sum[d], off, 64);
-    }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      wlo[wave][d] = lo[d];
-      whi[wave][d] = hi[d];
-      wsum[wave][d] = sum[d];
-    }
-  }
-  __syncthreads();
   TileWindow w;
-  int64_t vol = 1;
-  float mean[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int a = wlo[0][d], b = whi[0][d];
-    float s = wsum[0][d];
-    for (int k = 1; k < 4; ++k) {
-      a = min(a, wlo[k][d]);
-      b = max(b, whi[k][d]);
-      s += wsum[k][d];
-    }
-    if (b < a) a = b = 0;  // no particle: an empty 2-cell box at the origin
-    w.o[d] = a;
-    w.W[d] = b - a + 2;
-    vol *= w.W[d];
-    mean[d] = s / float(count);
-  }
-  if (vol > cap) fit_box(w.o, w.W, mean, vol, cap);
-  __syncthreads();  // the scratch may be reused after return
+  block_window(lo, hi, sum, count, cap, wlo, whi, wsum, w.o, w.W);
   return w;
 }
 
