@@ -78,8 +78,8 @@ constexpr double kFix = 4294967296.0;
 // exact, a right shift by -s adds half of the last kept unit first, and below
 // 2^-26 (s < -25) the value is under one half.  Zero and subnormal w give 0.  Equal
 // to floor(w 2^32 + 1/2) for every float in [0, 1].
-__device__ __forceinline__ unsigned long long to_fix(float w) {
-  const unsigned b = __float_as_uint(w);
+__host__ __device__ __forceinline__ unsigned long long to_fix(float w) {
+  const unsigned b = __builtin_bit_cast(unsigned, w);
   const int s = (int)(b >> 23) - 118;
   const unsigned long long m = (unsigned long long)((b & 0x7FFFFFu) | 0x800000u);
   if (s >= 0) return m << s;
@@ -90,19 +90,22 @@ __device__ __forceinline__ unsigned long long to_fix(float w) {
 // Flat index (i N + j) N + l of a mesh node (i, j, l in [0, N)) as a 32-bit value
 // (N <= 1024, so below 2^30): shifts for a power-of-two N, else 24-bit multiplies
 // (full rate, where a 32-bit multiply is quarter rate).
+// (a product of factors below 2^24 is what the 24-bit multiplier takes; the compiler
+// selects it from the masks)
+__host__ __device__ __forceinline__ unsigned mul24(unsigned a, unsigned b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
 template <bool P2>
-__device__ __forceinline__ unsigned node_index(int i, int j, int l, int n) {
+__host__ __device__ __forceinline__ unsigned node_index(int i, int j, int l, int n) {
   if constexpr (P2) {
     const int k = __builtin_ctz((unsigned)n);
     return ((((unsigned)i << k) | (unsigned)j) << k) | (unsigned)l;
   } else {
-    return (unsigned)__umul24((unsigned)__umul24((unsigned)i, (unsigned)n) + (unsigned)j, (unsigned)n) + (unsigned)l;
+    return mul24(mul24((unsigned)i, (unsigned)n) + (unsigned)j, (unsigned)n) + (unsigned)l;
   }
 }
 
 // Window cell number a sx + b sy + c of in-window offsets (all products below 2^24)
-__device__ __forceinline__ int win_index(int a, int b, int c, int sx, int sy) {
-  return __umul24((unsigned)a, (unsigned)sx) + __umul24((unsigned)b, (unsigned)sy) + c;
+__host__ __device__ __forceinline__ int win_index(int a, int b, int c, int sx, int sy) {
+  return (int)(mul24((unsigned)a, (unsigned)sx) + mul24((unsigned)b, (unsigned)sy)) + c;
 }
 
 // Window cells are numbered c = (a W1 + b) W2 + cz.  Their decomposition divides by
@@ -112,17 +115,20 @@ __device__ __forceinline__ int win_index(int a, int b, int c, int sx, int sy) {
 // 1/d >= 2^-13 below the next integer, so floor(c m / 2^32) = floor(c / d).
 struct WinDiv {
   unsigned d, m;
-  __device__ __forceinline__ explicit WinDiv(int dd) : d((unsigned)dd), m(0xFFFFFFFFu / (unsigned)dd + 1u) {}
-  __device__ __forceinline__ unsigned quot(unsigned c) const { return __umulhi(c, m); }
+  __host__ __device__ __forceinline__ explicit WinDiv(int dd) : d((unsigned)dd), m(0xFFFFFFFFu / (unsigned)dd + 1u) {}
+  __host__ __device__ __forceinline__ unsigned quot(unsigned c) const {
+    return (unsigned)(((unsigned long long)c * m) >> 32);
+  }
 };
 // c -> (a, b, cz) for the strides sx = W1 W2 (in qx) and sy = W2 (in qy)
-__device__ __forceinline__ void win_cell(int c, const WinDiv& qx, const WinDiv& qy, int& a, int& b, int& cz) {
+__host__ __device__ __forceinline__ void win_cell(int c, const WinDiv& qx, const WinDiv& qy, int& a, int& b,
+                                                  int& cz) {
   const unsigned ua = qx.quot((unsigned)c);
-  const unsigned r = (unsigned)c - (unsigned)__umul24(ua, qx.d);
+  const unsigned r = (unsigned)c - mul24(ua, qx.d);
   const unsigned ub = qy.quot(r);
   a = (int)ua;
   b = (int)ub;
-  cz = (int)(r - (unsigned)__umul24(ub, qy.d));
+  cz = (int)(r - mul24(ub, qy.d));
 }
 
 // v in (-N, 2N) -> [0, N)
@@ -156,21 +162,25 @@ __device__ __forceinline__ int idiff_n(int a, int b, int n) {
 // centred on the tile's mean base cell and kept inside the bounding box.  Particles outside it take the direct global
 // path; for late-time (clustered) tiles this leaves about a tenth of the particles a
 // fixed cube would.  Every thread computes the same box.
-__device__ __forceinline__ void fit_box(int (&o)[3], int (&W)[3], const float (&mean)[3], int64_t vol, int cap) {
+__host__ __device__ __forceinline__ void fit_box(int (&o)[3], int (&W)[3], const float (&mean)[3], int64_t vol,
+                                                 int cap) {
   const float f = cbrtf((float)cap / (float)vol);
   int Wf[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) Wf[d] = max(2, min(W[d], (int)((float)W[d] * f)));
+  for (int d = 0; d < 3; ++d) {
+    const int w = (int)((float)W[d] * f);
+    Wf[d] = w < 2 ? 2 : (w > W[d] ? W[d] : w);
+  }
 #pragma unroll
   for (int it = 0; it < 3; ++it) {
     const int m = Wf[0] >= Wf[1] ? (Wf[0] >= Wf[2] ? 0 : 2) : (Wf[1] >= Wf[2] ? 1 : 2);
     const int rest = Wf[m == 0 ? 1 : 0] * Wf[m == 2 ? 1 : 2];
-    if (Wf[m] * rest > cap) Wf[m] = max(2, cap / rest);
+    if (Wf[m] * rest > cap) Wf[m] = cap / rest < 2 ? 2 : cap / rest;
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int c = (int)rintf(mean[d]) - Wf[d] / 2;
-    o[d] = max(o[d], min(c, o[d] + W[d] - Wf[d]));
+    const int c = (int)rintf(mean[d]) - Wf[d] / 2, hi = o[d] + W[d] - Wf[d];
+    o[d] = c < o[d] ? o[d] : (c > hi ? hi : c);
     W[d] = Wf[d];
   }
 }
@@ -182,11 +192,12 @@ __device__ __forceinline__ void fit_box(int (&o)[3], int (&W)[3], const float (&
 // Within a wave lo and -hi travel together as two 16-bit halves (|values| < 2^15):
 // one shuffle and one packed minimum per step.  wlo/whi/wsum: __shared__ [4][3]
 // scratch, free again on return; every thread must call.
-__device__ __forceinline__ int pack_lo_nhi(int lo, int hi) {
-  const int a = max(-32767, min(32767, lo)), b = max(-32767, min(32767, -hi));
+__host__ __device__ __forceinline__ int pack_lo_nhi(int lo, int hi) {
+  const int a = lo < -32767 ? -32767 : (lo > 32767 ? 32767 : lo);
+  const int b = -hi < -32767 ? -32767 : (-hi > 32767 ? 32767 : -hi);
   return (int)((unsigned)(unsigned short)a | ((unsigned)(unsigned short)b << 16));
 }
-__device__ __forceinline__ int min_lo_nhi(int u, int v) {
+__host__ __device__ __forceinline__ int min_lo_nhi(int u, int v) {
   typedef short s16x2 __attribute__((ext_vector_type(2)));
   return __builtin_bit_cast(int, __builtin_elementwise_min(__builtin_bit_cast(s16x2, u), __builtin_bit_cast(s16x2, v)));
 }

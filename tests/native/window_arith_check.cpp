@@ -1,0 +1,97 @@
+// Host-side check of the exact integer arithmetic the tiled particle kernels use
+// (pm_particles.h): the window-cell division by a high multiply, the cell
+// decomposition and numbering, the fixed-point weights, the node index, the packed
+// window reduction and the over-capacity window.  Prints "ok" and exits 0 on success.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+
+#include "pm_particles.h"
+
+using namespace pm;
+
+static int fails = 0;
+#define EXPECT(cond, ...)                 \
+  do {                                    \
+    if (!(cond)) {                        \
+      if (fails < 10) printf(__VA_ARGS__); \
+      ++fails;                            \
+    }                                     \
+  } while (0)
+
+int main() {
+  // WinDiv: floor(c / d) for every c, d in the window range (c < 2^13, 2 <= d < 2^13)
+  for (unsigned d = 2; d < 8192; ++d) {
+    const WinDiv q((int)d);
+    for (unsigned c = 0; c < 8192; ++c) EXPECT(q.quot(c) == c / d, "quot %u / %u\n", c, d);
+  }
+  // win_cell / win_index: c = a sx + b sy + cz round trip over whole windows
+  std::mt19937 rng(7);
+  for (int it = 0; it < 2000; ++it) {
+    const int W0 = 2 + (int)(rng() % 30), W1 = 2 + (int)(rng() % 30), W2 = 2 + (int)(rng() % 60);
+    if (W0 * W1 * W2 > 6144) continue;
+    const int sy = W2, sx = W1 * W2;
+    const WinDiv qx(sx), qy(sy);
+    for (int c = 0; c < W0 * W1 * W2; ++c) {
+      int a, b, cz;
+      win_cell(c, qx, qy, a, b, cz);
+      EXPECT(a >= 0 && a < W0 && b >= 0 && b < W1 && cz >= 0 && cz < W2 && win_index(a, b, cz, sx, sy) == c,
+             "win_cell %d in %dx%dx%d\n", c, W0, W1, W2);
+    }
+  }
+  // to_fix: round-half-up of w 2^32 for every float in [0, 1]
+  for (unsigned bits = 0; bits <= 0x3F800000u; ++bits) {
+    const float w = __builtin_bit_cast(float, bits);
+    const unsigned long long want = (unsigned long long)std::floor((double)w * 4294967296.0 + 0.5);
+    EXPECT(to_fix(w) == want, "to_fix %a\n", (double)w);
+  }
+  // node_index: both forms against the 64-bit flat index
+  for (int n : {64, 128, 192, 256, 1024}) {
+    for (int it = 0; it < 100000; ++it) {
+      const int i = (int)(rng() % n), j = (int)(rng() % n), l = (int)(rng() % n);
+      const unsigned long long want = ((unsigned long long)i * n + j) * n + l;
+      EXPECT(node_index<false>(i, j, l, n) == want, "node_index %d %d %d / %d\n", i, j, l, n);
+      if ((n & (n - 1)) == 0) EXPECT(node_index<true>(i, j, l, n) == want, "node_index p2 %d %d %d / %d\n", i, j, l, n);
+    }
+  }
+  // packed reduction of (lo, -hi): the minimum of packs is the pack of (min lo, max hi)
+  for (int it = 0; it < 200000; ++it) {
+    int lo = 1 << 30, hi = -(1 << 30), pk = pack_lo_nhi(1 << 30, -(1 << 30));
+    const int k = (int)(rng() % 64);
+    for (int s = 0; s < k; ++s) {
+      const int a = (int)(rng() % 1025) - 512, b = a + (int)(rng() % 40);
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+      pk = min_lo_nhi(pk, pack_lo_nhi(a, b));
+    }
+    const int glo = (int)(short)(pk & 0xFFFF), ghi = -(int)(short)((unsigned)pk >> 16);
+    if (k == 0) EXPECT(glo == 32767 && ghi == -32767, "empty pack\n");
+    else EXPECT(glo == lo && ghi == hi, "pack %d %d vs %d %d\n", glo, ghi, lo, hi);
+  }
+  // fit_box: the window fits the capacity, keeps every side in [2, W] and stays inside the box
+  for (int cap : {4096, 6144}) {
+    for (int it = 0; it < 300000; ++it) {
+      int W[3], o[3];
+      float mean[3];
+      for (int d = 0; d < 3; ++d) {
+        W[d] = 2 + (int)(rng() % ((rng() & 1) ? 40 : 1100));
+        o[d] = -(int)(rng() % 600);
+        mean[d] = (float)o[d] + (float)(rng() % (unsigned)W[d]) + 0.37f;
+      }
+      const long long vol = (long long)W[0] * W[1] * W[2];
+      if (vol <= cap) continue;
+      int Wf[3] = {W[0], W[1], W[2]}, of[3] = {o[0], o[1], o[2]};
+      fit_box(of, Wf, mean, vol, cap);
+      EXPECT((long long)Wf[0] * Wf[1] * Wf[2] <= cap, "fit_box volume %d %d %d\n", Wf[0], Wf[1], Wf[2]);
+      for (int d = 0; d < 3; ++d)
+        EXPECT(Wf[d] >= 2 && Wf[d] <= W[d] && of[d] >= o[d] && of[d] + Wf[d] <= o[d] + W[d], "fit_box side %d\n", d);
+    }
+  }
+  if (fails) {
+    printf("%d failures\n", fails);
+    return 1;
+  }
+  printf("ok\n");
+  return 0;
+}
