@@ -146,14 +146,7 @@ def power_spectrum_sparse(modes: torch.Tensor, values: torch.Tensor, n: int, box
     sk = torch.zeros(n_bins, dtype=torch.float64)
 
     def bin_of(s):
-        # the b with N^2 (2b+1)^2 <= 16 n_bins^2 |n|^2 < N^2 (2b+3)^2: a float guess of
-        # b = floor((4 n_bins |n| / N - 1) / 2), then the integer inequalities settle it
-        q = 16 * n_bins * n_bins * s
-        b = torch.floor((4.0 * n_bins * torch.sqrt(s.double()) / n - 1.0) / 2.0).long()
-        for _ in range(2):
-            b = torch.where(n * n * (2 * b + 1) ** 2 > q, b - 1, b)
-            b = torch.where(n * n * (2 * b + 3) ** 2 <= q, b + 1, b)
-        return torch.where((b >= 0) & (b < n_bins), b, torch.full_like(b, -1))
+        return bin_of_norm2(s, n, n_bins)
 
     yz = full.view(n, 1) ** 2 + nz.view(1, n // 2 + 1) ** 2
     w_plane = wz.view(1, -1).expand(n, n // 2 + 1).reshape(-1)
@@ -223,3 +216,16 @@ def bispectrum_numerator_sparse(modes: torch.Tensor, values: torch.Tensor, n: in
     mask = closed & ia.view(-1, 1, 1) & ib.view(1, -1, 1) & ic.view(1, 1, -1)
     prod = values.view(-1, 1, 1) * values.view(1, -1, 1) * values.view(1, 1, -1)
     return complex(prod[mask].sum()) if bool(mask.any()) else 0j
+
+
+def bin_of_norm2(s: torch.Tensor, n: int, n_bins: int) -> torch.Tensor:
+    """Bin of integer |n|^2 values under the rule of ``pk_bin_index`` (-1 outside every
+    bin), without forming the N^3 grid: the b with N^2 (2b+1)^2 <= 16 n_bins^2 |n|^2 <
+    N^2 (2b+3)^2 from a float guess floor((4 n_bins |n| / N - 1) / 2) settled by the
+    integer inequalities."""
+    q = 16 * n_bins * n_bins * s
+    b = torch.floor((4.0 * n_bins * torch.sqrt(s.double()) / n - 1.0) / 2.0).long()
+    for _ in range(2):
+        b = torch.where(n * n * (2 * b + 1) ** 2 > q, b - 1, b)
+        b = torch.where(n * n * (2 * b + 3) ** 2 <= q, b + 1, b)
+    return torch.where((b >= 0) & (b < n_bins), b, torch.full_like(b, -1))

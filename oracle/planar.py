@@ -27,7 +27,7 @@ import math
 
 import torch
 
-from . import cic
+from . import cic, estimators
 
 
 def deposit_delta_line(x: torch.Tensor, n: int) -> torch.Tensor:
@@ -113,3 +113,35 @@ def cycle_line_vjp(coord: torch.Tensor, mom: torch.Tensor, axis: int, kick: floa
     c1, m1, _ = cycle_line(c, m, axis, kick, drift, n, omega_m, grad)
     gc, gm = torch.autograd.grad((c1, m1), (c, m), grad_outputs=(lam_coord, lam_mom), allow_unused=True)
     return (torch.zeros_like(c) if gc is None else gc), (torch.zeros_like(m) if gm is None else gm)
+
+
+def power_spectrum_line(x: torch.Tensor, n: int, box: float, n_bins: int, counts: torch.Tensor) -> torch.Tensor:
+    """The P(k) estimator (eq. powerspectrum, bins of ``estimators.pk_bin_index``) of
+    the counting density of a plane-parallel lattice with plane coordinates x: only
+    the wavevectors on the axis line carry power, with 3-D amplitude N^2 times the
+    one-dimensional DFT.  ``counts`` are the estimator's mode counts per bin (all 3-D
+    modes, e.g. from ``estimators.power_spectrum_sparse``).  Differentiable in x."""
+    d = deposit_delta_line(x, n)
+    dh = torch.fft.fft(d.to(torch.complex128))
+    m = torch.fft.fftfreq(n, d=1.0 / n).round().long()
+    b = estimators.bin_of_norm2(m * m, n, n_bins)
+    p2 = (dh.real ** 2 + dh.imag ** 2) * float(n) ** 4
+    sel = b >= 0
+    sp = torch.zeros(n_bins, dtype=torch.float64).index_add(0, b[sel], p2[sel])
+    cnt = counts.to(torch.float64)
+    return torch.where(cnt > 0, box ** 3 / float(n) ** 6 * sp / torch.where(cnt > 0, cnt, torch.ones_like(cnt)),
+                       torch.zeros_like(sp))
+
+
+def power_spectrum_line_vjp(x: torch.Tensor, n: int, box: float, n_bins: int, counts: torch.Tensor,
+                            dpk: torch.Tensor) -> torch.Tensor:
+    """Cotangent of every particle's coordinate along the axis for the loss
+    sum_b dpk_b P_b: the derivative with respect to a plane coordinate (which moves
+    the plane's N^2 particles) divided by N^2, since moving one particle changes the
+    transverse mean of the density by 1/N^2 of that and off-axis modes, zero at the
+    plane-parallel lattice, only to second order.  The transverse cotangents are 0.
+    Returns [N] (one value per lattice plane)."""
+    xr = x.detach().clone().requires_grad_(True)
+    pk = power_spectrum_line(xr, n, box, n_bins, counts)
+    (g,) = torch.autograd.grad(pk, xr, grad_outputs=dpk.to(torch.float64))
+    return g / float(n) ** 2

@@ -229,3 +229,24 @@ def test_truncate_noise_sparse_equals_dense():
     got = fourier.idft_at(cm_, cv, nc, pts).real
     assert torch.allclose(got, want.reshape(-1), atol=1e-12)
     assert float(want.abs().max()) > 0.1
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_planar_power_spectrum_and_vjp_equal_3d_oracle(axis):
+    from oracle import adjoint as oadj, estimators
+    n, box, nb = 16, 300.0, 8
+    c, m, pos, _ = _planar_case(n, axis, 60 + axis, 0)
+    _, pk3, cnt = estimators.power_spectrum(cic.deposit_delta(pos, n), box, nb)
+    _, _, cnt_sparse = estimators.power_spectrum_sparse(torch.zeros((0, 3), dtype=torch.long),
+                                                        torch.zeros(0, dtype=torch.complex128), n, box, nb)
+    assert torch.equal(cnt, cnt_sparse)
+    pk1 = planar.power_spectrum_line(c[axis], n, box, nb, cnt)
+    assert torch.allclose(pk1, pk3, rtol=1e-10, atol=1e-10 * float(pk3.abs().max()))
+    dpk = torch.randn(nb, generator=torch.Generator().manual_seed(3), dtype=torch.float64)
+    (want,) = oadj.vjp(lambda x: estimators.power_spectrum(cic.deposit_delta(x, n), box, nb)[1], (pos,), dpk)
+    g = planar.power_spectrum_line_vjp(c[axis], n, box, nb, cnt, dpk)
+    full = torch.zeros((3, n), dtype=torch.float64)
+    full[axis] = g
+    got = si.broadcast_planes(full, n, axis, dtype=torch.float64)
+    assert torch.allclose(got, want, atol=1e-10 * float(want.abs().max()))
+    assert float(g.abs().max()) > 0
