@@ -224,3 +224,38 @@ def truncate_noise_sparse(modes: torch.Tensor, w_hat: torch.Tensor, n_fine: int,
     h = n_coarse // 2
     keep = (modes.abs() < h).all(dim=1)
     return modes[keep].clone(), w_hat[keep] * (n_coarse / n_fine) ** 1.5
+
+
+def zeldovich_adjoint_sparse(lam_pos_spectra, lam_mom_spectra, p: ICParams, cells: torch.Tensor) -> torch.Tensor:
+    """Cotangent of the white noise at ``cells`` ([3, M] integer) for cotangents
+    (lam_pos, lam_mom) of the Newtonian set of ``zeldovich``, given as sparse
+    full-cube DFTs of their three components on the particle lattice (lists of
+    (modes [K, 3], values [K]), components in [-N/2, N/2)).  The set is linear in the
+    noise, Psi_d = IDFT(A_d DFT(w)) with A_d = i k_d T(k) e^{i k . (1/2, 1/2, 1/2)} / k^2
+    (T the factor of ``linear_delta_k``, zero at k = 0 and on the Nyquist planes), pos
+    = q + Psi (the wrap has unit derivative) and mom = c_m Psi; so the cotangent of the
+    noise is IDFT(sum_d conj(A_d) DFT(lam_pos_d + c_m lam_mom_d)).  Returns [M]."""
+    n = p.n
+    a = p.a_init
+    c_m = a * a * cm.hubble_e(p.cosmo, a) * cm.growth_f(p.cosmo, a)
+    growth = cm.growth_d(p.cosmo, p.a_init) / cm.growth_d(p.cosmo, p.a_norm)
+    kf = 2.0 * math.pi / p.box
+    acc = {}
+    for d in range(3):
+        for (modes, vals), f in ((lam_pos_spectra[d], 1.0), (lam_mom_spectra[d], c_m)):
+            for m, v in zip(modes.tolist(), vals.tolist()):
+                if all(c == 0 for c in m) or any(c == -(n // 2) for c in m):
+                    continue
+                kg = [2.0 * math.pi * c / n for c in m]
+                k2 = sum(x * x for x in kg)
+                t = math.sqrt(p.power(kf * math.sqrt(sum(c * c for c in m))) / p.dx ** 3) * growth
+                ph = 0.5 * sum(kg)
+                amp = 1j * kg[d] * t / k2 * complex(math.cos(ph), math.sin(ph))
+                key = tuple(m)
+                acc[key] = acc.get(key, 0j) + amp.conjugate() * f * v
+    if not acc:
+        return torch.zeros(cells.shape[1], dtype=torch.float64)
+    keys = sorted(acc)
+    modes = torch.tensor(keys, dtype=torch.long).view(-1, 3)
+    vals = torch.tensor([acc[k] for k in keys], dtype=torch.complex128)
+    return fourier.idft_at(modes, vals, n, cells).real

@@ -250,3 +250,28 @@ def test_planar_power_spectrum_and_vjp_equal_3d_oracle(axis):
     got = si.broadcast_planes(full, n, axis, dtype=torch.float64)
     assert torch.allclose(got, want, atol=1e-10 * float(want.abs().max()))
     assert float(g.abs().max()) > 0
+
+
+def test_zeldovich_adjoint_sparse_equals_autograd():
+    from oracle import adjoint as oadj, fourier, ics as oics
+    n, box = 16, 500.0
+    c = ocm.Cosmo(n_s=0.965)
+    p = oics.ICParams(n=n, box=box, a_init=0.05, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    pos_waves = [[(0.7, (1, 2, -3), 0.2), (0.2, (8, 1, 0), 0.5)], [(0.5, (0, 3, 1), 1.0)],
+                 [(0.3, (-5, 2, 7), 2.0), (0.4, (2, 2, 2), 0.1)]]
+    mom_waves = [[(1.1, (3, -1, 0), 0.4)], [(0.9, (1, 2, -3), 2.5), (0.2, (0, 0, 8), 0.0)], [(0.6, (4, 0, 1), 1.4)]]
+    lx = torch.stack([_cosine_mesh(w, n).reshape(-1) for w in pos_waves])
+    lp = torch.stack([_cosine_mesh(w, n).reshape(-1) for w in mom_waves])
+    noise = _cosine_mesh(NOISE_WAVES, n)
+
+    def fwd(w):
+        x, m = oics.zeldovich(w, p)
+        return torch.cat([x.reshape(-1), m.reshape(-1)])
+
+    (want,) = oadj.vjp(fwd, (noise,), torch.cat([lx.reshape(-1), lp.reshape(-1)]))
+    g = torch.arange(n)
+    cells = torch.stack(torch.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    got = oics.zeldovich_adjoint_sparse([fourier.plane_wave_modes_full(w, n) for w in pos_waves],
+                                        [fourier.plane_wave_modes_full(w, n) for w in mom_waves], p, cells)
+    assert torch.allclose(got, want.reshape(-1), atol=1e-10 * float(want.abs().max()))
+    assert float(want.abs().max()) > 1e-3
