@@ -24,6 +24,8 @@ at a time, or a property that holds at any size:
   * the adjoint cycle on a plane-parallel lattice with cotangents constant on
     lattice planes: sampled particles against the reverse-mode derivative of the
     plane-parallel reduction; the P(k) adjoint (256 bins) on such a lattice likewise;
+    the adjoint of the Zel'dovich ICs for cotangents made of plane waves, at sampled
+    noise cells, against the oracle's adjoint of the sparse spectra;
   * Zel'dovich and Poisson-gauge ICs at 1024^3 (EH98, a = 0.02) from a white-noise
     field made of plane waves (one on a Nyquist plane, which the ICs drop):
     sampled particles against the oracle's ICs of the sparse noise spectrum; the
@@ -493,3 +495,25 @@ def test_pk_adjoint_full_size_plane_parallel_lattice(plan):
     for b in range(3):
         if b != axis:
             assert float(got[b].abs().max()) < 1e-4 * scale
+
+
+def test_ic_adjoint_full_size_plane_wave_cotangents(plan):
+    dev = plan.device
+    icp, c = _eh98_ics()
+    pos_waves = [[(0.7, (1, 2, -3), 0.2), (0.2, (512, 1, 0), 0.5)], [(0.5, (0, 300, 1), 1.0)],
+                 [(0.3, (-5, 2, 7), 2.0), (0.4, (200, -200, 64), 0.1)]]
+    mom_waves = [[(1.1, (30, -1, 0), 0.4)], [(0.9, (1, 2, -3), 2.5), (0.2, (0, 0, 511), 0.0)],
+                 [(0.6, (4, 0, 1), 1.4)]]
+    lx = torch.stack([si.plane_wave_mesh(N, w, device=dev, dtype=torch.float32).reshape(-1) for w in pos_waves])
+    lp = torch.stack([si.plane_wave_mesh(N, w, device=dev, dtype=torch.float32).reshape(-1) for w in mom_waves])
+    lam = pm.pm_ic_zeldovich_adjoint(plan, icp, lx, lp)
+    torch.cuda.synchronize()
+    del lx, lp
+    cells = _sample_nodes(4096, 77)
+    got = lam[cells[0].to(dev), cells[1].to(dev), cells[2].to(dev)].double().cpu()
+    del lam
+    p = oics.ICParams(n=N, box=BOX, a_init=0.02, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    want = oics.zeldovich_adjoint_sparse([fourier.plane_wave_modes_full(w, N) for w in pos_waves],
+                                         [fourier.plane_wave_modes_full(w, N) for w in mom_waves], p, cells)
+    assert float(want.abs().max()) > 0
+    assert rel_l2(got, want) < F32_TOL
