@@ -87,12 +87,12 @@ __host__ __device__ __forceinline__ unsigned long long to_fix(float w) {
   return r > 25 ? 0ull : (m + (1ull << (r - 1))) >> r;
 }
 
-// Flat index (i N + j) N + l of a mesh node (i, j, l in [0, N)) as a 32-bit value
-// (N <= 1024, so below 2^30): shifts for a power-of-two N, else 24-bit multiplies
-// (full rate, where a 32-bit multiply is quarter rate).
-// (a product of factors below 2^24 is what the 24-bit multiplier takes; the compiler
-// selects it from the masks)
+// Product of two factors below 2^24 (the masks let the compiler use the full-rate
+// 24-bit multiplier, where a 32-bit multiply is quarter rate)
 __host__ __device__ __forceinline__ unsigned mul24(unsigned a, unsigned b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
+
+// Flat index (i N + j) N + l of a mesh node (i, j, l in [0, N)) as a 32-bit value
+// (N <= 1024, so below 2^30): shifts for a power-of-two N, else 24-bit multiplies.
 template <bool P2>
 __host__ __device__ __forceinline__ unsigned node_index(int i, int j, int l, int n) {
   if constexpr (P2) {
@@ -159,9 +159,10 @@ __device__ __forceinline__ int idiff_n(int a, int b, int n) {
 // LDS capacity `cap` (>= 8): the same proportions scaled by (cap/vol)^(1/3), each side
 // at least 2; while the volume still exceeds cap the longest side is cut to
 // cap / (product of the other two) (at least 2), which fits after at most three cuts;
-// centred on the tile's mean base cell and kept inside the bounding box.  Particles outside it take the direct global
-// path; for late-time (clustered) tiles this leaves about a tenth of the particles a
-// fixed cube would.  Every thread computes the same box.
+// centred on the tile's mean base cell and kept inside the bounding box.  Particles
+// outside it take the direct global path; for late-time (clustered) tiles this leaves
+// about a tenth of the particles a fixed cube would.  Every thread computes the same
+// box.
 __host__ __device__ __forceinline__ void fit_box(int (&o)[3], int (&W)[3], const float (&mean)[3], int64_t vol,
                                                  int cap) {
   const float f = cbrtf((float)cap / (float)vol);
