@@ -80,3 +80,27 @@ def combine_at(x_gr: torch.Tensor, x_n: torch.Tensor, n_c: int, x_fine: torch.Te
         w = (t[0] if dx else 1.0 - t[0]) * (t[1] if dy else 1.0 - t[1]) * (t[2] if dz else 1.0 - t[2])
         xi_f = xi_f + xi_min_image(x_gr[:, idx], x_n[:, idx], n_c) * w
     return cic.wrap(x_fine + (n_f / n_c) * xi_f, n_f)
+
+
+def add_displacement(xi: torch.Tensor, n_c: int, x_fine: torch.Tensor, n_f: int) -> torch.Tensor:
+    """eq. combined with a displacement field given directly (e.g. the linear
+    Poisson-gauge shift xi_lin(a) in place of the GR-minus-Newton difference of two
+    runs): x = wrap(x_fine + (N_f/N_c) * CIC_q[xi](q_fine)), xi [3, Nc^3] in coarse
+    cells on the coarse lattice."""
+    xi_f = xi if n_f == n_c else interpolate_lagrangian(xi, n_c, n_f)
+    return cic.wrap(x_fine + (n_f / n_c) * xi_f, n_f)
+
+
+def add_displacement_at(xi: torch.Tensor, n_c: int, x_fine: torch.Tensor, j_fine: torch.Tensor,
+                        n_f: int) -> torch.Tensor:
+    """``add_displacement`` for a sample of fine particles (lattice indices j_fine
+    [3, M], positions x_fine [3, M])."""
+    i0_ax, t_ax = fine_to_coarse_axis(n_c, n_f)
+    i0 = torch.stack([i0_ax[j_fine[d]] for d in range(3)])
+    t = torch.stack([t_ax[j_fine[d]] for d in range(3)])
+    xi_f = torch.zeros(x_fine.shape, dtype=torch.float64)
+    for dx, dy, dz in itertools.product((0, 1), repeat=3):
+        idx = (((i0[0] + dx) % n_c) * n_c + (i0[1] + dy) % n_c) * n_c + (i0[2] + dz) % n_c
+        w = (t[0] if dx else 1.0 - t[0]) * (t[1] if dy else 1.0 - t[1]) * (t[2] if dz else 1.0 - t[2])
+        xi_f = xi_f + xi[:, idx] * w
+    return cic.wrap(x_fine + (n_f / n_c) * xi_f, n_f)

@@ -217,6 +217,20 @@ def zeldovich_pair_sparse(modes: torch.Tensor, w_hat: torch.Tensor, p: ICParams,
     return pos_n, mom_n, pos_gr, mom_gr
 
 
+def xi_linear_sparse(modes: torch.Tensor, w_hat: torch.Tensor, p: ICParams, a: float, q_index: torch.Tensor):
+    """``xi_linear(noise, p, a)[0]`` for white noise whose full-cube spectrum vanishes
+    except at ``modes`` with amplitudes ``w_hat``, at the particles with lattice
+    indices q_index ([3, P]) only.  Returns [3, P] in cells."""
+    n = p.n
+    dl = _linear_delta_sparse(modes, w_hat, p)
+    kg = (2.0 * math.pi / n) * modes.to(torch.float64)
+    k2 = (kg * kg).sum(dim=1)
+    inv = torch.where(k2 > 0, 1.0 / torch.where(k2 > 0, k2, torch.ones_like(k2)), torch.zeros_like(k2))
+    q = q_index.to(torch.float64) + 0.5
+    g, _ = gr_shift_coefficients(p, a)
+    return torch.stack([g * fourier.idft_at(modes, 1j * kg[:, d] * dl * inv * inv, n, q).real for d in range(3)])
+
+
 def truncate_noise_sparse(modes: torch.Tensor, w_hat: torch.Tensor, n_fine: int, n_coarse: int):
     """``truncate_noise`` of a fine noise spectrum that vanishes except at ``modes``:
     the coarse spectrum's non-zero modes (|n_i| < N_c/2 kept, scaled by

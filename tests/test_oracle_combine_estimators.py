@@ -65,6 +65,49 @@ def test_constant_shift_and_linear_field_interpolation():
     assert torch.allclose(fine[2], torch.full_like(fine[2], 0.1), atol=1e-14)
 
 
+def test_add_displacement_brute_force_periodic_cic():
+    # Fine particle j sits at coarse coordinate u_j = (j + 1/2) N_c/N_f - 1/2; its value
+    # is sum_i xi_i prod_axes max(0, 1 - |u - i|) over the periodic coarse lattice.
+    for nc, nf in ((4, 12), (3, 6), (5, 5)):
+        g = si.rng(7)
+        xi = torch.from_numpy(g.standard_normal((3, nc ** 3)))
+        xf = torch.from_numpy(g.uniform(0, nf, (3, nf ** 3)))
+        got = combine.add_displacement(xi, nc, xf, nf)
+        want = torch.empty_like(xf)
+        for jx, jy, jz in itertools.product(range(nf), repeat=3):
+            u = [(j + 0.5) * nc / nf - 0.5 for j in (jx, jy, jz)]
+            acc = [0.0, 0.0, 0.0]
+            for ix, iy, iz in itertools.product(range(nc), repeat=3):
+                w = 1.0
+                for uu, ii in zip(u, (ix, iy, iz)):
+                    d = abs(uu - ii)
+                    d = min(d, nc - d)
+                    w *= max(0.0, 1.0 - d)
+                if w:
+                    for c in range(3):
+                        acc[c] += w * float(xi[c, (ix * nc + iy) * nc + iz])
+            jj = (jx * nf + jy) * nf + jz
+            for c in range(3):
+                v = float(xf[c, jj]) + nf / nc * acc[c]
+                want[c, jj] = v - nf * math.floor(v / nf)
+        d = (got - want + nf / 2) % nf - nf / 2
+        assert float(d.abs().max()) < 1e-12
+
+
+def test_add_displacement_of_the_run_difference_is_the_combination():
+    nc, nf = 8, 16
+    xn = torch.from_numpy(si.lattice_jitter_particles(nc, 11, 1.3))
+    xg = torch.from_numpy(si.lattice_jitter_particles(nc, 12, 1.3))
+    xf = torch.from_numpy(si.lattice_jitter_particles(nf, 13, 0.8))
+    got = combine.add_displacement(combine.xi_min_image(xg, xn, nc), nc, xf, nf)
+    want = combine.combine(xg, xn, nc, xf, nf)
+    assert float(((got - want + nf / 2) % nf - nf / 2).abs().max()) < 1e-12
+    idx = torch.arange(0, nf ** 3, 5)
+    j = torch.stack([idx // (nf * nf), (idx // nf) % nf, idx % nf])
+    at = combine.add_displacement_at(combine.xi_min_image(xg, xn, nc), nc, xf[:, idx], j, nf)
+    assert float(((at - want[:, idx] + nf / 2) % nf - nf / 2).abs().max()) < 1e-12
+
+
 # ---------------------------------------------------------------------------
 # eq. powerspectrum
 # ---------------------------------------------------------------------------

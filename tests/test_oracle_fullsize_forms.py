@@ -217,6 +217,22 @@ def test_zeldovich_pair_sparse_equals_dense(kind):
     assert float(disp.abs().max()) > 1e-3   # a displacement that is not trivially zero
 
 
+@pytest.mark.parametrize("a", [0.05, 0.5, 1.0])
+def test_xi_linear_sparse_equals_dense(a):
+    from oracle import fourier, ics as oics
+    n, box = 16, 500.0
+    c = ocm.Cosmo(n_s=0.965)
+    p = oics.ICParams(n=n, box=box, a_init=0.05, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    want, _ = oics.xi_linear(_cosine_mesh(NOISE_WAVES, n), p, a)
+    modes, vals = fourier.plane_wave_modes_full(NOISE_WAVES, n)
+    g = torch.arange(n)
+    q = torch.stack(torch.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    got = oics.xi_linear_sparse(modes, vals, p, a, q)
+    scale = float(want.abs().max())
+    assert scale > 1e-5   # about 1e-4 cells on this coarse 31 Mpc/h mesh
+    assert float((got - want).abs().max()) < 1e-12 * scale
+
+
 def test_truncate_noise_sparse_equals_dense():
     from oracle import fourier, ics as oics
     nf, nc = 16, 8
