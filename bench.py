@@ -142,7 +142,8 @@ def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
     """Timings of the estimator and combination calls of the displacement-combination
     configuration on the final 1024^3 positions: deposit + P(k) in 256 bins, B(k)
     on 64 triangles (32 equilateral k = m*16 k_f, 32 squeezed with k3 = 4 k_f; shell
-    width 2 k_f), and the combination of a 256^3 pair into the 1024^3 run."""
+    width 2 k_f), the combination of a 256^3 pair into the 1024^3 run, and the
+    combination with the linear shift at 256^3 in place of the pair."""
     import torch
     import synth_inputs as si
     out = {}
@@ -194,6 +195,21 @@ def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
     dt = time.perf_counter() - t0
     out["combine_ms"] = round(dt * 1e3, 2)
     out["combine_GBps_alg"] = round(24 * n ** 3 / dt / 1e9, 1)  # read x_fine, write x_out
+    # combination with linear theory: the linear Poisson-gauge shift at a = 1 from the
+    # coarse noise (one k-space pass and its inverse transform), added to the fine run
+    xi = cplan.mesh(3)
+    pm.pm_xi_linear(cplan, noise, icp, 1.0, xi)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm.pm_xi_linear(cplan, noise, icp, 1.0, xi)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pm.displacement_add(xi, nc, pos, n, x_out)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["xi_linear_256_ms"] = round((t1 - t0) * 1e3, 2)
+    out["add_linear_shift_ms"] = round((t2 - t1) * 1e3, 2)
+    del xi
     out["note"] = ("coarse noise is the Fourier truncation of the fine noise (shared phases); B(k) keeps 8 shell "
                    "fields resident and recomputes evicted shells")
     del x_out, xn, pn, xg, pg, disp, cplan, delta

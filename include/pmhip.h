@@ -238,6 +238,13 @@ int pm_step_adjoint(pm_plan* plan, const void* pos, int64_t np, const pm_step_pa
 int displacement_combine(const void* x_gr, const void* x_newton, int n_coarse, const void* x_fine, int n_fine,
                          int dtype, void* x_out, void* stream);
 
+/* eq. combined with a given displacement field: x_out = wrap(x_fine + (n_f/n_c) xi_f),
+ * xi ([3][n_coarse^3], coarse cells, on the coarse lattice) interpolated to the fine
+ * lattice exactly as in displacement_combine (e.g. xi = pm_xi_linear's output).  x_out
+ * may alias x_fine. */
+int displacement_add(const void* xi, int n_coarse, const void* x_fine, int n_fine, int dtype, void* x_out,
+                     void* stream);
+
 /* Power spectrum (eq. powerspectrum), raw estimator without shot-noise subtraction or
  * deconvolution.  Bin width w = (N/2)/n_bins (units of k_f = 2 pi/L); bin b holds
  * modes with N^2 (2b+1)^2 <= 16 n_bins^2 |n|^2 < N^2 (2b+3)^2 (integer decision).
@@ -304,6 +311,16 @@ int pm_noise_truncate(pm_plan* fine, const void* noise_fine, pm_plan* coarse, vo
  * mom_gr = mom_n + a^2 E (dg/dlna / g) xi.  disp_scratch as above. */
 int pm_ic_gauge(pm_plan* plan, const void* noise, const pm_ic_params* ic, void* disp_scratch,
                 const void* pos_n, const void* mom_n, void* pos_gr, void* mom_gr, void* stream);
+
+/* The linear Poisson-gauge displacement at scale factor a (the same reading of eqs.
+ * physical_density, b1 and bgr as pm_ic_gauge): xi_lin(a) = g(a) IDFT(i k delta_L_hat /
+ * k^4) on the half-cell lattice, g(a) = (3f + (9/2) Omega_m(a)) calh(a)^2 D(a)/D(a_init),
+ * with delta_L at a_init from `noise` and `ic` as in pm_ic_zeldovich.  Added to a
+ * Newtonian run with displacement_add it gives the combination with linear theory in
+ * place of the GR-minus-Newton displacement of eq. xiGR.  xi: [3][N^3] of the plan's
+ * dtype, in cells (written; also serves as the transform's output scratch).
+ * Single-box plans only. */
+int pm_xi_linear(pm_plan* plan, const void* noise, const pm_ic_params* ic, double a, void* xi, void* stream);
 
 /* --------------------------------------------------- host cosmology --------- */
 /* Host-side double-precision scalars that parameterise the kernels.  Growth D(a) is

@@ -16,7 +16,8 @@ import torch
 
 __all__ = [
     "PMError", "lib", "SolveParams", "StepParams", "Cosmology", "ICParams", "Plan",
-    "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "pk_estimate", "bk_estimate",
+    "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "displacement_add", "pm_xi_linear",
+    "pk_estimate", "bk_estimate",
     "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
     "pm_ic_zeldovich", "pm_ic_gauge", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
@@ -89,6 +90,7 @@ def _declare(l):
                              _c_void_p]),
         "displacement_combine": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_int, _c_int, _c_void_p,
                                           _c_void_p]),
+        "displacement_add": (_c_int, [_c_void_p, _c_int, _c_void_p, _c_int, _c_int, _c_void_p, _c_void_p]),
         "pk_estimate": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "bk_estimate": (_c_int, [_c_void_p, _c_void_p, _c_int, P(_c_double), _c_double, P(ctypes.c_int32), _c_int,
                                  _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_size_t, _c_void_p]),
@@ -101,6 +103,7 @@ def _declare(l):
         "pm_noise_truncate": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_gauge": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                                  _c_void_p, _c_void_p]),
+        "pm_xi_linear": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_double, _c_void_p, _c_void_p]),
         "pm_cosmo_hubble_e": (_c_double, [P(Cosmology), _c_double]),
         "pm_cosmo_omega_m_a": (_c_double, [P(Cosmology), _c_double]),
         "pm_cosmo_growth": (_c_double, [P(Cosmology), _c_double]),
@@ -308,6 +311,18 @@ def displacement_combine(x_gr, x_newton, n_coarse: int, x_fine, n_fine: int, x_o
     return x_out
 
 
+def displacement_add(xi, n_coarse: int, x_fine, n_fine: int, x_out=None):
+    """x_fine + (n_fine/n_coarse) xi interpolated to the fine lattice (wrapped)."""
+    x_out = torch.empty_like(x_fine) if x_out is None else x_out
+    dt = PM_F32 if x_fine.dtype == torch.float32 else PM_F64
+    _need(xi, 3 * n_coarse ** 3, "xi")
+    _need(x_fine, 3 * n_fine ** 3, "x_fine")
+    _need(x_out, 3 * n_fine ** 3, "x_out")
+    _check(lib().displacement_add(_ptr(xi, x_fine.dtype, "xi"), int(n_coarse), _ptr(x_fine, x_fine.dtype, "x_fine"),
+                                  int(n_fine), dt, _ptr(x_out, x_fine.dtype, "x_out"), _stream()))
+    return x_out
+
+
 def pk_estimate(plan: Plan, delta, n_bins: int):
     """(k_mean, P, n_modes), each [n_bins] ([batch, n_bins] for a batch)."""
     shape = (n_bins,) if plan.batch == 1 else (plan.batch, n_bins)
@@ -379,6 +394,17 @@ def pm_ic_gauge(plan: Plan, noise, ic: ICParams, disp_scratch, pos_n, mom_n, pos
                              _ptr(disp_scratch, plan.dtype, "disp_scratch"), _ptr(pos_n, plan.dtype, "pos_n"),
                              _ptr(mom_n, plan.dtype, "mom_n"), _ptr(pos_gr, plan.dtype, "pos_gr"),
                              _ptr(mom_gr, plan.dtype, "mom_gr"), _stream()))
+
+
+def pm_xi_linear(plan: Plan, noise, ic: ICParams, a: float, xi=None):
+    """Linear Poisson-gauge displacement xi_lin(a) [3, N^3] (cells) from the noise."""
+    n3 = plan.n ** 3
+    xi = plan.mesh(3) if xi is None else xi
+    _need(noise, n3, "noise")
+    _need(xi, 3 * n3, "xi")
+    _check(lib().pm_xi_linear(plan.handle, _ptr(noise, plan.dtype, "noise"), ctypes.byref(ic), float(a),
+                              _ptr(xi, plan.dtype, "xi"), _stream()))
+    return xi
 
 
 # ------------------------------------------------------------ host cosmology --

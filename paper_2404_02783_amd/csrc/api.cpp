@@ -446,6 +446,18 @@ int displacement_combine(const void* x_gr, const void* x_newton, int n_coarse, c
   return launch_combine(x_gr, x_newton, n_coarse, x_fine, n_fine, dtype, x_out, static_cast<hipStream_t>(stream));
 }
 
+int displacement_add(const void* xi, int n_coarse, const void* x_fine, int n_fine, int dtype, void* x_out,
+                     void* stream) {
+  g_err[0] = 0;
+  if (!xi || !x_fine || !x_out) return set_error(PM_ERR_ARG, "displacement_add: null pointer");
+  if (n_coarse <= 0 || n_fine <= 0 || n_fine % n_coarse != 0)
+    return set_error(PM_ERR_ARG, "displacement_add: n_fine (%d) must be a positive multiple of n_coarse (%d)", n_fine,
+                     n_coarse);
+  if (n_fine > 4096) return set_error(PM_ERR_SIZE, "displacement_add: n_fine too large");
+  if (dtype != PM_F32 && dtype != PM_F64) return set_error(PM_ERR_ARG, "displacement_add: bad dtype");
+  return launch_combine(xi, nullptr, n_coarse, x_fine, n_fine, dtype, x_out, static_cast<hipStream_t>(stream));
+}
+
 int pk_estimate(pm_plan* p, const void* delta, int n_bins, double* k_mean, double* pk, int64_t* n_modes,
                 void* stream) {
   PM_TRY(check_plan(p));

@@ -277,6 +277,23 @@ int pm_noise_truncate(pm_plan* fine, const void* noise_fine, pm_plan* coarse, vo
   return fft3_c2r(coarse, 1, cbuf(coarse, 0), 0, noise_coarse, s);
 }
 
+// Coefficient g(a) of the linear Poisson-gauge displacement xi_lin(a) = g(a) IDFT(i k
+// delta_L_hat / k^4) (delta_L at a_init) and its derivative g'(a) = dg/dlna:
+// g = (3f + (9/2) Omega_m(a)) calh(a)^2 D(a)/D(a_init), calh in inverse cells.
+static void gr_shift_coefficients(const pm_cosmology* c, double a, double a_init, double dx, double* g, double* gp) {
+  const double cg = kC_over_H0 / dx;
+  const double e = pm_cosmo_hubble_e(c, a);
+  const double h2 = (a * e / cg) * (a * e / cg);
+  const double om = pm_cosmo_omega_m_a(c, a);
+  const double f = pm_cosmo_growth_rate(c, a);
+  const double dratio = pm_cosmo_growth(c, a) / pm_cosmo_growth(c, a_init);
+  // df/dlna from the growth equation; dOm/dlna = -3 Om (1 - Om); dcalH^2/dlna = calH^2 (2 - 3 Om); dD/dlna = f D
+  const double fp = 1.5 * om - f * f - (2.0 - 1.5 * om) * f;
+  const double sfac = 3.0 * f + 4.5 * om;
+  *g = sfac * h2 * dratio;
+  *gp = h2 * dratio * (3.0 * fp - 13.5 * om * (1.0 - om) + sfac * (2.0 - 3.0 * om + f));
+}
+
 int pm_ic_gauge(pm_plan* p, const void* noise, const pm_ic_params* ic, void* disp, const void* pos_n,
                 const void* mom_n, void* pos_gr, void* mom_gr, void* stream) {
   using namespace pm;
@@ -287,22 +304,25 @@ int pm_ic_gauge(pm_plan* p, const void* noise, const pm_ic_params* ic, void* dis
   if (!pos_n || !mom_n || !pos_gr || !mom_gr) return set_error(PM_ERR_ARG, "pm_ic_gauge: null pointer");
   const pm_cosmology* c = &ic->cosmo;
   const double a = ic->a_init;
-  const double dx = p->box / p->n;
-  const double cg = kC_over_H0 / dx;
-  const double e = pm_cosmo_hubble_e(c, a);
-  const double h2 = (a * e / cg) * (a * e / cg);
-  const double om = pm_cosmo_omega_m_a(c, a);
-  const double f = pm_cosmo_growth_rate(c, a);
-  // df/dlna from the growth equation; dOm/dlna = -3 Om (1 - Om); dcalH^2/dlna = calH^2 (2 - 3 Om)
-  const double fp = 1.5 * om - f * f - (2.0 - 1.5 * om) * f;
-  const double sfac = 3.0 * f + 4.5 * om;
-  const double g = sfac * h2;
-  const double gp = h2 * (3.0 * fp - 13.5 * om * (1.0 - om) + sfac * (2.0 - 3.0 * om + f));
+  double g, gp;
+  gr_shift_coefficients(c, a, a, p->box / p->n, &g, &gp);
   hipStream_t s = static_cast<hipStream_t>(stream);
   rc = ic_common(p, noise, ic, disp, 2, g, s);
   if (rc) return rc;
-  const double fac = a * a * e * (gp / g);
+  const double fac = a * a * pm_cosmo_hubble_e(c, a) * (gp / g);
   return launch_ic_gauge_lattice(p, disp, pos_n, mom_n, pos_gr, mom_gr, fac, s);
+}
+
+int pm_xi_linear(pm_plan* p, const void* noise, const pm_ic_params* ic, double a, void* xi, void* stream) {
+  using namespace pm;
+  int rc = check_ic(p, noise, ic, xi, "pm_xi_linear");
+  if (rc) return rc;
+  p->dens_valid = false;
+  if (p->nb != 1) return set_error(PM_ERR_ARG, "pm_xi_linear: needs a single-box plan");
+  if (!(a > 0.0)) return set_error(PM_ERR_ARG, "pm_xi_linear: bad scale factor");
+  double g, gp;
+  gr_shift_coefficients(&ic->cosmo, a, ic->a_init, p->box / p->n, &g, &gp);
+  return ic_common(p, noise, ic, xi, 2, g, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -337,7 +337,8 @@ __device__ __forceinline__ int lagr_base(int j, int nc, int nf, T& t) {
 // particles touch, zc cells per row) in LDS, then interpolates; the weights and the
 // summation order are those of a direct per-particle evaluation.
 constexpr int kCombineZ = kBlock + 4;  // staged coarse cells per row (nc <= nf)
-template <typename T>
+// XI: xg already holds xi (coarse cells) and xn is unused.
+template <typename T, bool XI>
 __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, const T* __restrict__ xn, int nc,
                                                     const T* __restrict__ xf, int nf, T* __restrict__ out) {
   __shared__ T xs[3][4][kCombineZ];
@@ -358,7 +359,8 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, co
     zi = zi < 0 ? zi + nc : (zi >= nc ? zi - nc : zi);
     const int64_t id = ((int64_t)ix[r >> 1] * nc + iy[r & 1]) * nc + zi;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xs[d][r][k] = min_image(xg[d * npc + id] - xn[d * npc + id], nc);
+    for (int d = 0; d < 3; ++d)
+      xs[d][r][k] = XI ? xg[d * npc + id] : min_image(xg[d * npc + id] - xn[d * npc + id], nc);
   }
   __syncthreads();
   if (jz >= nf) return;
@@ -476,15 +478,18 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
 
 int launch_combine(const void* x_gr, const void* x_n, int nc, const void* x_f, int nf, int dtype, void* x_out,
                    hipStream_t s) {
+  // x_n == nullptr: x_gr holds xi itself
   const dim3 grid((unsigned)((nf + kBlock - 1) / kBlock), (unsigned)nf, (unsigned)nf);
-  if (dtype == PM_F32)
-    hipLaunchKernelGGL(k_combine<float>, grid, dim3(kBlock), 0, s, static_cast<const float*>(x_gr),
-                       static_cast<const float*>(x_n), nc, static_cast<const float*>(x_f), nf,
-                       static_cast<float*>(x_out));
-  else
-    hipLaunchKernelGGL(k_combine<double>, grid, dim3(kBlock), 0, s, static_cast<const double*>(x_gr),
+  if (dtype == PM_F32) {
+    auto kern = x_n ? k_combine<float, false> : k_combine<float, true>;
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, static_cast<const float*>(x_gr), static_cast<const float*>(x_n),
+                       nc, static_cast<const float*>(x_f), nf, static_cast<float*>(x_out));
+  } else {
+    auto kern = x_n ? k_combine<double, false> : k_combine<double, true>;
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, static_cast<const double*>(x_gr),
                        static_cast<const double*>(x_n), nc, static_cast<const double*>(x_f), nf,
                        static_cast<double*>(x_out));
+  }
   return hip_check(hipGetLastError(), "displacement combine");
 }
 

@@ -449,6 +449,65 @@ def test_ics_full_size_sampled_particles(plan):
     assert float(min_image(wpg - wpn, N).abs().max()) > 1.0
 
 
+def test_xi_linear_full_size_sampled_particles(plan):
+    dev = plan.device
+    icp, c = _eh98_ics()
+    noise = si.plane_wave_mesh(N, NWAVES, device=dev, dtype=torch.float32)
+    xi = pm.pm_xi_linear(plan, noise, icp, 1.0)
+    torch.cuda.synchronize()
+    del noise
+    idx = _sample_particles(4096, 83)
+    got = xi.reshape(3, -1)[:, idx.to(dev)].double().cpu()
+    del xi
+    p = oics.ICParams(n=N, box=BOX, a_init=0.02, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    modes, vals = fourier.plane_wave_modes_full(NWAVES, N)
+    want = oics.xi_linear_sparse(modes, vals, p, 1.0, _lattice_index(idx))
+    assert float(want.abs().max()) > 1.0
+    assert rel_l2(got, want) < F32_TOL
+
+
+def test_combined_linear_shift_full_size(plan):
+    """Combination with linear theory at the combination configuration's sizes: the
+    Zel'dovich set at 1024^3 plus the linear Poisson-gauge shift at a = 1 of the noise
+    truncated to 256^3, interpolated to the fine lattice; sampled fine particles."""
+    dev = plan.device
+    nc = 256
+    icp, c = _eh98_ics()
+    noise = si.plane_wave_mesh(N, NWAVES, device=dev, dtype=torch.float32)
+    cplan = pm.Plan(nc, BOX, torch.float32)
+    xi = pm.pm_xi_linear(cplan, pm.pm_noise_truncate(plan, noise, cplan), icp, 1.0)
+    pos, mom = plan.particles(), plan.particles()
+    pm.pm_ic_zeldovich(plan, noise, icp, plan.mesh(3), pos, mom)
+    del noise, mom
+    pm.displacement_add(xi, nc, pos, N, x_out=pos)
+    torch.cuda.synchronize()
+    idx = _sample_particles(4096, 85)
+    got = pos[:, idx.to(dev)].double().cpu()
+    del pos, xi
+    power = ocm.eh98_normalised(c, 0.965, 0.81)
+    pf = oics.ICParams(n=N, box=BOX, a_init=0.02, power=power, a_norm=1.0, cosmo=c)
+    pc = oics.ICParams(n=nc, box=BOX, a_init=0.02, power=power, a_norm=1.0, cosmo=c)
+    modes, vals = fourier.plane_wave_modes_full(NWAVES, N)
+    j = _lattice_index(idx)
+    x_fine = oics.zeldovich_pair_sparse(modes, vals, pf, j)[0]
+    # the linear shift on the coarse lattice, at the eight coarse particles around each
+    # sampled fine lattice point (zero elsewhere, where it is not read)
+    cmodes, cvals = oics.truncate_noise_sparse(modes, vals, N, nc)
+    i0_ax, _ = ocomb.fine_to_coarse_axis(nc, N)
+    cells = set()
+    for d in range(j.shape[1]):
+        b = [int(i0_ax[j[ax, d]]) for ax in range(3)]
+        for o in range(8):
+            cells.add(tuple((b[ax] + ((o >> (2 - ax)) & 1)) % nc for ax in range(3)))
+    cq = torch.tensor(sorted(cells), dtype=torch.long).T
+    xi_c = torch.zeros((3, nc ** 3), dtype=torch.float64)
+    xi_c[:, (cq[0] * nc + cq[1]) * nc + cq[2]] = oics.xi_linear_sparse(cmodes, cvals, pc, 1.0, cq)
+    want = ocomb.add_displacement_at(xi_c, nc, x_fine, j, N)
+    ulp = float(torch.finfo(torch.float32).eps) * N
+    assert float(min_image(got - want, N).abs().max()) < 8 * ulp
+    assert float(min_image(want - x_fine, N).abs().max()) > 1.0   # a shift of cells
+
+
 def test_noise_truncate_full_size(plan):
     dev = plan.device
     nc = 256
