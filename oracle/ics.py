@@ -163,6 +163,73 @@ def zeldovich_pair(noise: torch.Tensor, p: ICParams):
     return pos_n, mom_n, pos_gr, mom_gr
 
 
+# ------------------------------------------------------------ second order --
+#
+# Sec. 3 starts the runs from second-order Lagrangian initial conditions.  The
+# paper's discrete relativistic derivation is not reproducible from its text; the
+# Newtonian set here is the standard continuous 2LPT (reading): with Psi1 = grad chi,
+# lap chi = -delta_L (chi_hat = delta_L_hat / k^2),
+#     S(q) = sum_{i<j} (chi_ii chi_jj - chi_ij^2),
+#     Psi2 = c2 grad(-lap^-1 S),   Psi2_hat = c2 i k S_hat / k^2,
+# c2 = -D2 / D1^2 = (3/7) Omega_m(a)^(-1/143) (the second-order growth factor
+# D2 = -(3/7) D1^2 Omega_m^(-1/143)), and momenta a^2 E (f1 Psi1 + f2 Psi2) with
+# f2 = dln D2 / dln a = 2 f1 + (3/143)(1 - Omega_m(a)).  S is formed from the Hessian
+# sampled on the particle lattice and differentiated spectrally on the same samples
+# (no de-aliasing of the product); k = 0 and the Nyquist planes of S_hat are dropped.
+
+def lpt2_coefficients(p: ICParams):
+    """(c2, f2) at a_init."""
+    om = cm.omega_m_of_a(p.cosmo, p.a_init)
+    c2 = (3.0 / 7.0) * om ** (-1.0 / 143.0)
+    f2 = 2.0 * cm.growth_f(p.cosmo, p.a_init) + (3.0 / 143.0) * (1.0 - om)
+    return c2, f2
+
+
+def second_order_source(dl_hat: torch.Tensor, n: int) -> torch.Tensor:
+    """S on the particle lattice, [N^3], from delta_L_hat on the r2c grid."""
+    kx, ky, kz = fourier.kgrid(n)
+    k2 = kx * kx + ky * ky + kz * kz
+    inv = torch.where(k2 > 0, 1.0 / torch.where(k2 > 0, k2, torch.ones_like(k2)), torch.zeros_like(k2))
+    chi_hat = dl_hat * inv * _lattice_phase(n)
+    k = (kx, ky, kz)
+    h = {(i, j): fourier.irfft3(-k[i] * k[j] * chi_hat, n) for i in range(3) for j in range(i, 3)}
+    s = (h[0, 0] * h[1, 1] + h[0, 0] * h[2, 2] + h[1, 1] * h[2, 2]
+         - h[0, 1] ** 2 - h[0, 2] ** 2 - h[1, 2] ** 2)
+    return s.reshape(-1)
+
+
+def second_order_displacement(s: torch.Tensor, n: int, c2: float) -> torch.Tensor:
+    """Psi2 = c2 IDFT(i k DFT(S) / k^2) on the same samples as S, [3, N^3]."""
+    s_hat = fourier.rfft3(s.view(n, n, n))
+    kx, ky, kz = fourier.kgrid(n)
+    k2 = kx * kx + ky * ky + kz * kz
+    mx, my, mz = fourier.nyquist_masks(n)
+    keep = ~(mx | my | mz) & (k2 > 0)
+    inv = torch.where(keep, 1.0 / torch.where(k2 > 0, k2, torch.ones_like(k2)), torch.zeros_like(k2))
+    base = c2 * s_hat * inv
+    return torch.stack([fourier.irfft3(torch.complex(torch.zeros_like(k), k) * base, n).reshape(-1)
+                        for k in (kx, ky, kz)])
+
+
+def lpt2_displacement(noise: torch.Tensor, p: ICParams):
+    """(Psi1, Psi2) at a_init, each [3, N^3] in cells."""
+    dl = linear_delta_k(noise, p)
+    c2, _ = lpt2_coefficients(p)
+    return (_vector_field_on_lattice(dl, p.n, 1),
+            second_order_displacement(second_order_source(dl, p.n), p.n, c2))
+
+
+def lpt2(noise: torch.Tensor, p: ICParams):
+    """Newtonian second-order set: (pos, mom), each [3, N^3] float64."""
+    psi1, psi2 = lpt2_displacement(noise, p)
+    _, f2 = lpt2_coefficients(p)
+    a = p.a_init
+    ae = a * a * cm.hubble_e(p.cosmo, a)
+    pos = cic.wrap(lagrangian_lattice(p.n) + psi1 + psi2, p.n)
+    mom = ae * (cm.growth_f(p.cosmo, a) * psi1 + f2 * psi2)
+    return pos, mom
+
+
 def powerlaw_for_rms_displacement(n: int, box: float, rms_cells: float, index: float = -2.0) -> cm.PowerSpec:
     """P(k) = A k^index with A chosen so that the expected 3-D rms Zel'dovich
     displacement over the discrete (non-Nyquist, n != 0) mode set is ``rms_cells``.
@@ -229,6 +296,51 @@ def xi_linear_sparse(modes: torch.Tensor, w_hat: torch.Tensor, p: ICParams, a: f
     q = q_index.to(torch.float64) + 0.5
     g, _ = gr_shift_coefficients(p, a)
     return torch.stack([g * fourier.idft_at(modes, 1j * kg[:, d] * dl * inv * inv, n, q).real for d in range(3)])
+
+
+def lpt2_sparse(modes: torch.Tensor, w_hat: torch.Tensor, p: ICParams, q_index: torch.Tensor):
+    """``lpt2`` for white noise whose full-cube spectrum vanishes except at ``modes``
+    (values ``w_hat``), at the particles with lattice indices q_index ([3, P]) only:
+    (pos, mom), each [3, P].  The Hessian of chi is a sum over the modes, so S on the
+    lattice is a sum over ordered mode pairs (m1, m2): its sample spectrum sits at
+    m1 + m2 reduced to [-N/2, N/2) with the half-cell phase of the unreduced sum (the
+    product aliases exactly as on the mesh)."""
+    n = p.n
+    dl = _linear_delta_sparse(modes, w_hat, p)
+    kg = (2.0 * math.pi / n) * modes.to(torch.float64)
+    k2 = (kg * kg).sum(dim=1)
+    inv = torch.where(k2 > 0, 1.0 / torch.where(k2 > 0, k2, torch.ones_like(k2)), torch.zeros_like(k2))
+    chi = dl * inv
+    live = [i for i in range(modes.shape[0]) if chi[i] != 0]
+    pairs = [(0, 1), (0, 2), (1, 2)]
+    acc = {}
+    for i1 in live:
+        for i2 in live:
+            k1, k2v = kg[i1], kg[i2]
+            h1 = lambda a, b: -float(k1[a] * k1[b])
+            h2 = lambda a, b: -float(k2v[a] * k2v[b])
+            w = sum(h1(a, a) * h2(b, b) - h1(a, b) * h2(a, b) for a, b in pairs)
+            if w == 0.0:
+                continue
+            msum = modes[i1] + modes[i2]
+            ph = math.pi * float(msum.sum()) / n
+            v = complex(chi[i1] * chi[i2]) * w * complex(math.cos(ph), math.sin(ph)) / n ** 3
+            key = tuple(((int(c) + n // 2) % n) - n // 2 for c in msum)
+            acc[key] = acc.get(key, 0j) + v
+    c2, f2 = lpt2_coefficients(p)
+    keys = [k for k in acc if any(c != 0 for c in k) and all(c != -(n // 2) for c in k)]
+    psi2 = torch.zeros((3, q_index.shape[1]), dtype=torch.float64)
+    if keys:
+        sm = torch.tensor(keys, dtype=torch.long).view(-1, 3)
+        sv = torch.tensor([acc[k] for k in keys], dtype=torch.complex128)
+        sk = (2.0 * math.pi / n) * sm.to(torch.float64)
+        sk2 = (sk * sk).sum(dim=1)
+        psi2 = torch.stack([fourier.idft_at(sm, c2 * 1j * sk[:, d] * sv / sk2, n, q_index).real for d in range(3)])
+    q = q_index.to(torch.float64) + 0.5
+    psi1 = torch.stack([fourier.idft_at(modes, 1j * kg[:, d] * dl * inv, n, q).real for d in range(3)])
+    a = p.a_init
+    ae = a * a * cm.hubble_e(p.cosmo, a)
+    return cic.wrap(q + psi1 + psi2, n), ae * (cm.growth_f(p.cosmo, a) * psi1 + f2 * psi2)
 
 
 def truncate_noise_sparse(modes: torch.Tensor, w_hat: torch.Tensor, n_fine: int, n_coarse: int):

@@ -233,6 +233,27 @@ def test_xi_linear_sparse_equals_dense(a):
     assert float((got - want).abs().max()) < 1e-12 * scale
 
 
+@pytest.mark.parametrize("n", [16, 12])
+def test_lpt2_sparse_equals_dense(n):
+    # includes mode pairs whose sum wraps past the Nyquist frequency (aliasing, with
+    # the sign the half-cell lattice phase gives it)
+    from oracle import fourier, ics as oics
+    box = 500.0
+    c = ocm.Cosmo(n_s=0.965)
+    p = oics.ICParams(n=n, box=box, a_init=0.05, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    waves = [(0.5, (1, 0, 2), 0.3), (1.0, (3, -2, 5), 1.2), (0.8, (-4, 5, 1), 2.2), (0.3, (2, 2, -5), 0.9)]
+    noise = _cosine_mesh(waves, n)
+    want = oics.lpt2(noise, p)
+    psi2 = oics.lpt2_displacement(noise, p)[1]
+    modes, vals = fourier.plane_wave_modes_full(waves, n)
+    g = torch.arange(n)
+    q = torch.stack(torch.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    got = oics.lpt2_sparse(modes, vals, p, q)
+    assert float(psi2.abs().max()) > 1e-3 * float((want[0] - q - 0.5).abs().max())
+    assert float(torch.remainder(got[0] - want[0] + n / 2, n).sub(n / 2).abs().max()) < 1e-11
+    assert float((got[1] - want[1]).abs().max()) < 1e-11 * float(want[1].abs().max())
+
+
 def test_truncate_noise_sparse_equals_dense():
     from oracle import fourier, ics as oics
     nf, nc = 16, 8

@@ -313,3 +313,89 @@ def test_truncated_noise_identity_and_variance():
     mean = sum(v) / len(v)
     sd = (sum((x - mean) ** 2 for x in v) / (len(v) - 1)) ** 0.5 / len(v) ** 0.5
     assert abs(mean - want) < 4 * sd + 1e-3
+
+
+# ---------------------------------------------------------------------------
+# second-order Lagrangian ICs (Sec. 3)
+# ---------------------------------------------------------------------------
+
+def _f2_kernel(k, l):
+    """Second-order Eulerian density kernel of standard perturbation theory (EdS)."""
+    kl = float(k @ l)
+    k2, l2 = float(k @ k), float(l @ l)
+    return 5.0 / 7.0 + 0.5 * kl * (1.0 / k2 + 1.0 / l2) + 2.0 / 7.0 * kl * kl / (k2 * l2)
+
+
+@pytest.mark.parametrize("m1,m2", [((1, 2, 0), (2, -1, 1)), ((3, 0, 0), (0, 2, 0)), ((1, 1, 1), (2, -1, 0))])
+def test_lpt2_reproduces_the_second_order_density_kernel(m1, m2):
+    # The particle distribution's density contrast, delta_E(K) = N^-3 sum_q exp(-i K.x_q)
+    # (exact for point particles), has at second order in the amplitude the component
+    # F2(k, l) A B / 2 at K = k + l and F2(k, -l) A B / 2 at K = k - l for
+    # delta_L = A cos(k.x) + B cos(l.x).  Zel'dovich alone gives another kernel; the
+    # second-order displacement (c2 = 3/7 in EdS) supplies the difference.
+    n = 16
+    a_amp, b_amp = 1.0, 0.7
+    s = 2.0 * math.pi / n
+    k = torch.tensor(m1, dtype=torch.float64) * s
+    l = torch.tensor(m2, dtype=torch.float64) * s
+    g = torch.arange(n, dtype=torch.float64)
+    x = torch.stack(torch.meshgrid(g, g, g, indexing="ij"))
+    delta = a_amp * torch.cos(torch.einsum("d,dxyz->xyz", k, x)) + b_amp * torch.cos(torch.einsum("d,dxyz->xyz", l, x))
+    q = ics.lagrangian_lattice(n)
+
+    def density_at(kvec, eps, c2):
+        dl = fourier.rfft3(eps * delta)
+        psi1 = ics._vector_field_on_lattice(dl, n, 1)
+        psi2 = ics.second_order_displacement(ics.second_order_source(dl, n), n, c2)
+        arg = -(kvec.view(3, 1) * (q + psi1 + psi2)).sum(0)
+        return torch.complex(torch.cos(arg), torch.sin(arg)).mean()
+
+    eps = 1e-3
+    for kk, lv in ((k, l), (k, -l)):
+        big_k = kk + lv
+        even = (density_at(big_k, eps, 3.0 / 7.0) + density_at(big_k, -eps, 3.0 / 7.0)) / (2 * eps * eps)
+        want = _f2_kernel(kk, lv) * a_amp * b_amp / 2.0
+        assert abs(complex(even) - want) < 1e-5 * abs(want)
+        za = (density_at(big_k, eps, 0.0) + density_at(big_k, -eps, 0.0)) / (2 * eps * eps)
+        assert abs(complex(za) - want) > 1e-2 * abs(want)     # Zel'dovich alone misses it
+
+
+def test_lpt2_plane_wave_has_no_second_order_displacement():
+    n = 16
+    g = torch.arange(n, dtype=torch.float64)
+    x = torch.stack(torch.meshgrid(g, g, g, indexing="ij"))
+    delta = 0.3 * torch.cos(2.0 * math.pi * (2 * x[0] - x[1] + 3 * x[2]) / n + 0.4)
+    dl = fourier.rfft3(delta)
+    s = ics.second_order_source(dl, n)
+    assert float(s.abs().max()) < 1e-15
+    assert float(ics.second_order_displacement(s, n, 3.0 / 7.0).abs().max()) < 1e-15
+
+
+def test_lpt2_growth_coefficients():
+    c = cm.FIDUCIAL
+    for a in (0.02, 0.3, 1.0):
+        p = ics.ICParams(n=8, box=100.0, a_init=a, power=cm.PowerSpec("powerlaw", 1.0, -2.0), cosmo=c)
+        c2, f2 = ics.lpt2_coefficients(p)
+        # c2 = -D2/D1^2 and f2 = dln|D2|/dln a, |D2| = (3/7) D1^2 Omega_m(a)^(-1/143)
+        h = 1e-4
+        lnd2 = lambda aa: 2.0 * math.log(cm.growth_d(c, aa)) - math.log(cm.omega_m_of_a(c, aa)) / 143.0
+        num = (lnd2(a * math.exp(h)) - lnd2(a * math.exp(-h))) / (2 * h)
+        assert f2 == pytest.approx(num, rel=1e-6)
+        assert c2 == pytest.approx(3.0 / 7.0, rel=1e-2)       # Omega_m^(-1/143) within 1 %
+    # matter domination: f2 -> 2
+    _, f2 = ics.lpt2_coefficients(ics.ICParams(n=8, box=100.0, a_init=1e-3, power=cm.PowerSpec("powerlaw", 1.0, -2.0)))
+    assert f2 == pytest.approx(2.0, abs=1e-6)
+
+
+def test_lpt2_set_is_zeldovich_plus_second_order():
+    n, box = 16, 500.0
+    c = cm.Cosmo(n_s=0.965)
+    p = ics.ICParams(n=n, box=box, a_init=0.05, power=cm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    noise = torch.from_numpy(si.white_noise(n, 41))
+    pos, mom = ics.lpt2(noise, p)
+    pz, mz = ics.zeldovich(noise, p)
+    psi1, psi2 = ics.lpt2_displacement(noise, p)
+    assert torch.allclose(psi1, ics.za_displacement(noise, p), atol=0)
+    d = (pos - pz - psi2 + n / 2) % n - n / 2
+    assert float(d.abs().max()) < 1e-12
+    assert 1e-4 < float(psi2.abs().max()) < 0.1 * float(psi1.abs().max())
