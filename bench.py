@@ -216,6 +216,24 @@ def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
     return out
 
 
+def ic_leg(pm, plan, noise, icp):
+    """Wall time of the Zel'dovich and second-order (2LPT) initial conditions at the
+    plan's size (one call each after a warm call; not part of the timed step)."""
+    import torch
+    out = {}
+    disp = plan.mesh(3)
+    pos, mom = plan.particles(), plan.particles()
+    for name, fn in (("zeldovich", pm.pm_ic_zeldovich), ("2lpt", pm.pm_ic_2lpt)):
+        fn(plan, noise, icp, disp, pos, mom)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(plan, noise, icp, disp, pos, mom)
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    del disp, pos, mom
+    return out
+
+
 def adjoint_small(pm, n=128, box=1000.0, n_steps=20, ckpt=5, n_bins=64):
     """Adjoint/forward time of the differentiable configuration: 128^3, L = 1000 Mpc/h,
     20 log steps a = 0.05 -> 1, P(k) in 64 bins, checkpoints every 5 cycles."""
@@ -442,6 +460,8 @@ def main():
     if not args.no_extras:
         print("[bench] estimators and combination at 1024^3", file=sys.stderr, flush=True)
         out["estimators_combination_1024"] = estimators_and_combination(pm, plan, pos, noise)
+        print("[bench] initial conditions at 1024^3", file=sys.stderr, flush=True)
+        out["initial_conditions_1024"] = ic_leg(pm, plan, noise, icp)
     if args.adjoint_cycles > 0:
         del run, pos, mom
         torch.cuda.synchronize()

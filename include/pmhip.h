@@ -286,6 +286,20 @@ int bk_estimate(pm_plan* plan, const void* delta, int n_shells, const double* sh
 int pm_ic_zeldovich(pm_plan* plan, const void* noise, const pm_ic_params* ic, void* disp_scratch, void* pos,
                     void* mom, void* stream);
 
+/* Second-order Lagrangian (2LPT) Newtonian set (Sec. 3 starts the runs from
+ * second-order ICs; continuous-2LPT reading of that start).  With chi_hat =
+ * delta_L_hat / k^2 (delta_L as in pm_ic_zeldovich, so Psi1 = grad chi is the
+ * Zel'dovich displacement): S = sum_{i<j} (chi_ii chi_jj - chi_ij^2) sampled on the
+ * lattice, Psi2_hat = c2 i k DFT(S) / k^2 (k = 0 and Nyquist planes dropped, no
+ * de-aliasing), c2 = (3/7) Omega_m(a_init)^(-1/143); pos = wrap(q + Psi1 + Psi2),
+ * mom = a^2 E (f Psi1 + f2 Psi2), f2 = 2f + (3/143)(1 - Omega_m).  noise [N][N][N]
+ * (read only); disp_scratch [3][N][N][N] (overwritten with Psi1); pos and mom
+ * [3][N^3] (written; mom also holds intermediate Hessian fields).  The four buffers
+ * must be distinct (PM_ERR_ARG).  Single-box plans only.  Four forward and twelve
+ * inverse transforms of N^3. */
+int pm_ic_2lpt(pm_plan* plan, const void* noise, const pm_ic_params* ic, void* disp_scratch, void* pos, void* mom,
+               void* stream);
+
 /* Adjoint of pm_ic_zeldovich with respect to the noise; not in the paper.  The
  * forward map noise -> (pos, mom) is affine: pos = wrap(q + Psi), mom = m Psi with
  * Psi_d = IDFT(S_d DFT(noise)).  Given the cotangents lam_pos, lam_mom [3][N^3]
@@ -305,7 +319,7 @@ int pm_ic_zeldovich_adjoint(pm_plan* plan, const pm_ic_params* ic, const void* l
  * workspaces. */
 int pm_noise_truncate(pm_plan* fine, const void* noise_fine, pm_plan* coarse, void* noise_coarse, void* stream);
 
-/* Poisson-gauge partner set of pm_ic_zeldovich's output (linear reading of eqs.
+/* Poisson-gauge partner set of pm_ic_zeldovich's (or pm_ic_2lpt's) output (linear reading of eqs.
  * physical_density, b1, bgr): xi_hat = i k g(a_init) delta_L_hat / k^4 on the same
  * lattice with g = (3f + (9/2) Omega_m(a)) calh^2; pos_gr = wrap(pos_n + xi),
  * mom_gr = mom_n + a^2 E (dg/dlna / g) xi.  disp_scratch as above. */

@@ -199,6 +199,7 @@ static pm::IcSymbol ic_symbol_of(const pm_plan* p, const pm_ic_params* ic, int k
   sy.growth = pm_cosmo_growth(&ic->cosmo, ic->a_init) / pm_cosmo_growth(&ic->cosmo, ic->a_norm);
   sy.coef = coef / ((double)p->n * p->n * p->n);
   sy.kpow = kpow;
+  sy.mode = 0;
   return sy;
 }
 
@@ -234,6 +235,55 @@ int pm_ic_zeldovich(pm_plan* p, const void* noise, const pm_ic_params* ic, void*
   const double a = ic->a_init;
   const double fac = a * a * pm_cosmo_hubble_e(&ic->cosmo, a) * pm_cosmo_growth_rate(&ic->cosmo, a);
   return launch_ic_lattice(p, disp, pos, mom, fac, s);
+}
+
+int pm_ic_2lpt(pm_plan* p, const void* noise, const pm_ic_params* ic, void* disp, void* pos, void* mom,
+               void* stream) {
+  using namespace pm;
+  int rc = check_ic(p, noise, ic, disp, "pm_ic_2lpt");
+  if (rc) return rc;
+  p->dens_valid = false;
+  if (!pos || !mom) return set_error(PM_ERR_ARG, "pm_ic_2lpt: null pointer");
+  if (p->nb != 1) return set_error(PM_ERR_ARG, "pm_ic_2lpt: needs a single-box plan");
+  if (noise == disp || noise == pos || noise == mom || disp == pos || disp == mom || pos == mom)
+    return set_error(PM_ERR_ARG, "pm_ic_2lpt: noise, disp, pos and mom must be distinct buffers");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t cs = cstride(p);
+  IcSymbol sy = ic_symbol_of(p, ic, 1, 1.0);
+  // S = sum_{i<j} (chi_ii chi_jj - chi_ij^2) on the lattice, into disp[0]; the three
+  // Hessian components of each half pass through mom
+  for (int pass = 0; pass < 2; ++pass) {
+    rc = fft3_r2c(p, noise, cbuf(p, 0), s);
+    if (rc) return rc;
+    sy.mode = 1 + pass;
+    rc = launch_ic_symbol(p, sy, false, s);
+    if (rc) return rc;
+    rc = fft3_c2r(p, 3, cbuf(p, 0), cs, mom, s);
+    if (rc) return rc;
+    rc = launch_lpt2_source(p, mom, disp, pass, s);
+    if (rc) return rc;
+  }
+  // Psi2 = c2 IDFT(i k DFT(S) / k^2) into mom
+  const pm_cosmology* c = &ic->cosmo;
+  const double a = ic->a_init;
+  const double om = pm_cosmo_omega_m_a(c, a);
+  const double c2 = (3.0 / 7.0) * std::pow(om, -1.0 / 143.0);
+  rc = fft3_r2c(p, disp, cbuf(p, 0), s);
+  if (rc) return rc;
+  IcSymbol s3 = sy;
+  s3.mode = 3;
+  s3.coef = c2 / ((double)p->n * p->n * p->n);
+  rc = launch_ic_symbol(p, s3, false, s);
+  if (rc) return rc;
+  rc = fft3_c2r(p, 3, cbuf(p, 0), cs, mom, s);
+  if (rc) return rc;
+  // Psi1 into disp
+  rc = ic_common(p, noise, ic, disp, 1, 1.0, s);
+  if (rc) return rc;
+  const double ae = a * a * pm_cosmo_hubble_e(c, a);
+  const double f1 = pm_cosmo_growth_rate(c, a);
+  const double f2 = 2.0 * f1 + (3.0 / 143.0) * (1.0 - om);
+  return launch_ic_lattice2(p, disp, mom, pos, mom, ae * f1, ae * f2, s);
 }
 
 int pm_ic_zeldovich_adjoint(pm_plan* p, const pm_ic_params* ic, const void* lam_pos, const void* lam_mom,

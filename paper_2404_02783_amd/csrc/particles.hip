@@ -403,6 +403,34 @@ __global__ void __launch_bounds__(kBlock) k_ic_lattice(const T* __restrict__ dis
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kBlock) k_lpt2_source(const T* __restrict__ h, T* __restrict__ s, int64_t n3,
+                                                        int pass) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n3) return;
+  const double a = (double)h[j], b = (double)h[n3 + j], c = (double)h[2 * n3 + j];
+  // FP64 products: S is a small difference of such products where the field is nearly planar
+  if (pass == 0)
+    s[j] = T(a * b + a * c + b * c);
+  else
+    s[j] = T((double)s[j] - (a * a + b * b + c * c));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ic_lattice2(const T* __restrict__ psi1, const T* psi2, T* __restrict__ pos,
+                                                        T* mom, int n, T f1, T f2) {
+  const int64_t np = (int64_t)n * n * n;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= np) return;
+  const int q[3] = {(int)(j / ((int64_t)n * n)), (int)((j / n) % n), (int)(j % n)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const T s1 = psi1[d * np + j], s2 = psi2[d * np + j];   // psi2 may alias mom: read before the write
+    pos[d * np + j] = wrap(T(q[d]) + T(0.5) + (s1 + s2), n);
+    mom[d * np + j] = f1 * s1 + f2 * s2;
+  }
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ic_gauge_lattice(const T* __restrict__ xi, const T* __restrict__ pn,
                                                              const T* __restrict__ mn, T* __restrict__ pg,
                                                              T* __restrict__ mg, int n, T mom_factor) {
@@ -504,6 +532,33 @@ int launch_ic_lattice(const pm_plan* p, const void* disp, void* pos, void* mom, 
     hipLaunchKernelGGL(k_ic_lattice<double>, grid, dim3(kBlock), 0, s, static_cast<const double*>(disp),
                        static_cast<double*>(pos), static_cast<double*>(mom), p->n, mom_factor);
   return hip_check(hipGetLastError(), "ic lattice");
+}
+
+int launch_lpt2_source(const pm_plan* p, const void* h, void* s_out, int pass, hipStream_t s) {
+  ProfScope ps(p, PK_IC, s);
+  const int64_t n3 = (int64_t)p->n * p->n * p->n;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_lpt2_source<float>, dim3(nblocks(n3)), dim3(kBlock), 0, s, static_cast<const float*>(h),
+                       static_cast<float*>(s_out), n3, pass);
+  else
+    hipLaunchKernelGGL(k_lpt2_source<double>, dim3(nblocks(n3)), dim3(kBlock), 0, s, static_cast<const double*>(h),
+                       static_cast<double*>(s_out), n3, pass);
+  return hip_check(hipGetLastError(), "lpt2 source");
+}
+
+int launch_ic_lattice2(const pm_plan* p, const void* psi1, const void* psi2, void* pos, void* mom, double f1,
+                       double f2, hipStream_t s) {
+  ProfScope ps(p, PK_IC, s);
+  const int64_t np = (int64_t)p->n * p->n * p->n;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_ic_lattice2<float>, dim3(nblocks(np)), dim3(kBlock), 0, s, static_cast<const float*>(psi1),
+                       static_cast<const float*>(psi2), static_cast<float*>(pos), static_cast<float*>(mom), p->n,
+                       (float)f1, (float)f2);
+  else
+    hipLaunchKernelGGL(k_ic_lattice2<double>, dim3(nblocks(np)), dim3(kBlock), 0, s,
+                       static_cast<const double*>(psi1), static_cast<const double*>(psi2), static_cast<double*>(pos),
+                       static_cast<double*>(mom), p->n, f1, f2);
+  return hip_check(hipGetLastError(), "ic lattice 2lpt");
 }
 
 int launch_ic_gauge_lattice(const pm_plan* p, const void* xi, const void* pos_n, const void* mom_n, void* pos_gr,

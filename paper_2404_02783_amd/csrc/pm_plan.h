@@ -121,6 +121,12 @@ int launch_combine(const void* x_gr, const void* x_n, int nc, const void* x_f, i
 int launch_ic_lattice(const pm_plan* p, const void* disp, void* pos, void* mom, double mom_factor, hipStream_t s);
 int launch_ic_gauge_lattice(const pm_plan* p, const void* xi, const void* pos_n, const void* mom_n, void* pos_gr,
                             void* mom_gr, double mom_factor, hipStream_t s);
+// Second-order source from three Hessian components h ([3][N^3]):
+// pass 0: s = h0 h1 + h0 h2 + h1 h2; pass 1: s -= h0^2 + h1^2 + h2^2.
+int launch_lpt2_source(const pm_plan* p, const void* h, void* s_out, int pass, hipStream_t s);
+// pos = wrap(q + 1/2 + psi1 + psi2), mom = f1 psi1 + f2 psi2 (psi2 may alias mom).
+int launch_ic_lattice2(const pm_plan* p, const void* psi1, const void* psi2, void* pos, void* mom, double f1,
+                       double f2, hipStream_t s);
 
 // ------------------------------------------------------------ spectra.hip --
 struct IcSymbol {
@@ -132,6 +138,11 @@ struct IcSymbol {
   double growth;             // D(a_init)/D(a_norm)
   double coef;               // multiplies the displacement symbol (includes 1/N^3)
   int kpow;                  // 1: i k / k^2 (Zel'dovich), 2: i k / k^4 (gauge shift)
+  // 0: the displacement i k_d A w_hat / k^(2 kpow) on the lattice (A: sqrt(P/dx^3) D);
+  // 1: Hessian diagonal -k_d^2 A w_hat / k^2 on the lattice (d = x, y, z);
+  // 2: Hessian off-diagonal -k_a k_b A w_hat / k^2 on the lattice ((a, b) = xy, xz, yz);
+  // 3: i k_d w_hat / k^2 of a field already sampled on the lattice (no A, no phase).
+  int mode;
 };
 // Forward: cbuf(0) holds DFT(noise); writes the three displacement spectra S_d w_hat
 // to cbuf 0, 1, 2.  Adjoint: cbuf(0) <- sum_d conj(S_d) cbuf(d).

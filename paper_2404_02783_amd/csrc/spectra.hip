@@ -51,7 +51,15 @@ __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx
   const bool nyq = (nx == -n / 2) || (ny == -n / 2) || (nz == n / 2);
   const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
   cx<T> out[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
-  if (!nyq && n2 > 0) {
+  if (!ADJ && sy.mode == 3 && !nyq && n2 > 0) {
+    // gradient of a field sampled on the lattice: i k_d coef w_hat / k^2
+    const double s = 2.0 * kPi / n;
+    const double kd[3] = {s * nx, s * ny, s * nz};
+    const double f = sy.coef / (kd[0] * kd[0] + kd[1] * kd[1] + kd[2] * kd[2]);
+    const cx<T> w = ldc(c0 + idx);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[d] = mk(T(-kd[d] * f * (double)w.y), T(kd[d] * f * (double)w.x));
+  } else if (!nyq && n2 > 0) {
     const double kmag = sy.kf * sqrt((double)n2);
     double pk = sy.amp * pow(kmag, sy.index);
     if (sy.pk_kind == PM_PK_EH98) {
@@ -80,11 +88,21 @@ __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx
       out[0] = mk(T(f * (rr * cs + ri * sn)), T(f * (ri * cs - rr * sn)));
     } else {
       const cx<T> w = ldc(c0 + idx);
-      // base = w * amp * inv * coef * e^{i phase}; component d = i k_d base
+      // base = w * amp * inv * coef * e^{i phase}; component d = i k_d base, or a
+      // Hessian component -k_a k_b base
       const double br = f * ((double)w.x * cs - (double)w.y * sn);
       const double bi = f * ((double)w.x * sn + (double)w.y * cs);
+      if (sy.mode == 0) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) out[d] = mk(T(-kd[d] * bi), T(kd[d] * br));
+        for (int d = 0; d < 3; ++d) out[d] = mk(T(-kd[d] * bi), T(kd[d] * br));
+      } else {
+        const int ia[3] = {0, 0, 1}, ib[3] = {1, 2, 2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double h = sy.mode == 1 ? -kd[d] * kd[d] : -kd[ia[d]] * kd[ib[d]];
+          out[d] = mk(T(h * br), T(h * bi));
+        }
+      }
     }
   }
   stc(c0 + idx, out[0]);

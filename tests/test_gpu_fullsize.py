@@ -26,10 +26,13 @@ at a time, or a property that holds at any size:
     plane-parallel reduction; the P(k) adjoint (256 bins) on such a lattice likewise;
     the adjoint of the Zel'dovich ICs for cotangents made of plane waves, at sampled
     noise cells, against the oracle's adjoint of the sparse spectra;
-  * Zel'dovich and Poisson-gauge ICs at 1024^3 (EH98, a = 0.02) from a white-noise
-    field made of plane waves (one on a Nyquist plane, which the ICs drop):
-    sampled particles against the oracle's ICs of the sparse noise spectrum; the
+  * Zel'dovich, second-order (2LPT) and Poisson-gauge ICs at 1024^3 (EH98, a = 0.02)
+    from a white-noise field made of plane waves (one on a Nyquist plane, which the
+    ICs drop): sampled particles against the oracle's ICs of the sparse noise
+    spectrum (for 2LPT, the second-order source as a sum over mode pairs); the
     truncation of that noise to 256^3, whole, against the sparse truncation;
+  * the linear Poisson-gauge shift at a = 1 at 1024^3, and the combination with it
+    of the 256^3 truncation into the 1024^3 Zel'dovich set, at sampled particles;
   * the coarse 256^3 pair of the combination configuration (Zel'dovich and
     Poisson-gauge sets from EH98 ICs at a = 0.02, L = 4000 Mpc/h), whole, through
     the leapfrog host loop, against the dense oracle.
@@ -506,6 +509,31 @@ def test_combined_linear_shift_full_size(plan):
     ulp = float(torch.finfo(torch.float32).eps) * N
     assert float(min_image(got - want, N).abs().max()) < 8 * ulp
     assert float(min_image(want - x_fine, N).abs().max()) > 1.0   # a shift of cells
+
+
+def test_ics_2lpt_full_size_sampled_particles(plan):
+    dev = plan.device
+    icp, c = _eh98_ics()
+    noise = si.plane_wave_mesh(N, NWAVES, device=dev, dtype=torch.float32)
+    disp = plan.mesh(3)
+    pos, mom = plan.particles(), plan.particles()
+    pm.pm_ic_2lpt(plan, noise, icp, disp, pos, mom)
+    torch.cuda.synchronize()
+    del noise, disp
+    idx = _sample_particles(4096, 87)
+    idx_d = idx.to(dev)
+    got = [t[:, idx_d].double().cpu() for t in (pos, mom)]
+    del pos, mom
+    p = oics.ICParams(n=N, box=BOX, a_init=0.02, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    modes, vals = fourier.plane_wave_modes_full(NWAVES, N)
+    j = _lattice_index(idx)
+    wpos, wmom = oics.lpt2_sparse(modes, vals, p, j)
+    ulp = float(torch.finfo(torch.float32).eps) * N
+    assert float(min_image(got[0] - wpos, N).abs().max()) < 8 * ulp
+    assert rel_l2(got[1], wmom) < F32_TOL
+    # the second-order displacement is a sizeable part of the answer (0.65 cell here)
+    wza = oics.zeldovich_pair_sparse(modes, vals, p, j)[0]
+    assert float(min_image(wpos - wza, N).abs().max()) > 0.1
 
 
 def test_noise_truncate_full_size(plan):

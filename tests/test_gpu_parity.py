@@ -409,6 +409,70 @@ def test_combined_linear_shift(dt, nf, nc):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n,kind", [(32, "eh98"), (64, "powerlaw"), (192, "eh98")])
+def test_initial_conditions_2lpt(dt, n, kind):
+    """Second-order Newtonian set, and the Poisson-gauge partner built on it."""
+    dev = _dev()
+    box, a_i = 1000.0, 0.02
+    c = ocm.Cosmo(n_s=0.965)
+    if kind == "powerlaw":
+        power, a_norm = oics.powerlaw_for_rms_displacement(n, box, 0.4), a_i
+        icp = pm.ICParams(pk_kind=pm.PM_PK_POWERLAW, amp=pm.power_law_amplitude(n, box, 0.4), index=-2.0,
+                          a_init=a_i, a_norm=a_norm, cosmo=pm.FIDUCIAL)
+    else:
+        power, a_norm = ocm.eh98_normalised(c, 0.965, 0.81), 1.0
+        icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965,
+                          a_init=a_i, a_norm=a_norm, cosmo=pm.FIDUCIAL)
+    p = oics.ICParams(n=n, box=box, a_init=a_i, power=power, a_norm=a_norm, cosmo=c)
+    noise = torch.from_numpy(si.white_noise(n, 91)).to(dt)
+    plan = pm.Plan(n, box, dt)
+    disp = plan.mesh(3)
+    pos, mom, pg, mg = (plan.particles() for _ in range(4))
+    pm.pm_ic_2lpt(plan, noise.to(dev), icp, disp, pos, mom)
+    torch.cuda.synchronize()
+    psi1 = disp.reshape(3, -1).double().cpu().clone()
+    pm.pm_ic_gauge(plan, noise.to(dev), icp, disp, pos, mom, pg, mg)
+    torch.cuda.synchronize()
+    nd = noise.double()
+    wpos, wmom = oics.lpt2(nd, p)
+    w1, w2 = oics.lpt2_displacement(nd, p)
+    tol = _tol(dt)
+    assert rel_l2(psi1, w1) < tol
+    ulp = float(torch.finfo(dt).eps) * n
+    assert float(min_image(pos.double().cpu() - wpos, n).abs().max()) < 8 * ulp
+    assert rel_l2(mom, wmom) < tol
+    # the second-order part itself: from the positions where it is well above their
+    # rounding (the power-law case: 0.03 cell; EH98 at a = 0.02 on 31 Mpc/h cells gives
+    # 5e-5 cell), and from the FP64 momenta, mom = a^2 E (f Psi1 + f2 Psi2)
+    if kind == "powerlaw":
+        got2 = min_image(pos.double().cpu() - (oics.lagrangian_lattice(n) + w1), n)
+        assert float(w2.abs().max()) > 100 * ulp
+        assert float((got2 - w2).abs().max()) < 8 * ulp + tol * float(w2.abs().max())
+    ae = a_i * a_i * ocm.hubble_e(c, a_i)
+    if dt == torch.float64:
+        _, f2 = oics.lpt2_coefficients(p)
+        psi2 = (mom.cpu() - ae * ocm.growth_f(c, a_i) * psi1) / (ae * f2)
+        assert rel_l2(psi2, w2) < 1e-6
+    xi, dxi = oics.xi_linear(nd, p, a_i)
+    assert float(min_image(pg.double().cpu() - cic.wrap(wpos + xi, n), n).abs().max()) < 8 * ulp
+    assert rel_l2(mg, wmom + ae * dxi) < 10 * tol
+
+
+def test_2lpt_rejects_shared_buffers_and_batches():
+    dev = _dev()
+    n = 16
+    plan = pm.Plan(n, 100.0, torch.float32)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_POWERLAW, amp=1.0, index=-2.0, a_init=0.02, a_norm=0.02, cosmo=pm.FIDUCIAL)
+    noise = plan.mesh().normal_()
+    disp, pos = plan.mesh(3), plan.particles()
+    with pytest.raises(pm.PMError, match="distinct"):
+        pm.pm_ic_2lpt(plan, noise, icp, disp, pos, pos)
+    bplan = pm.Plan(n, 100.0, torch.float32, batch=2)
+    with pytest.raises(pm.PMError, match="single-box"):
+        pm.pm_ic_2lpt(bplan, bplan.mesh(), icp, bplan.mesh(3), bplan.particles(), bplan.particles())
+
+
+@pytest.mark.parametrize("dt", DTYPES)
 @pytest.mark.parametrize("nf,nc", [(64, 16), (32, 32), (128, 32)])
 def test_noise_truncate(dt, nf, nc):
     dev = _dev()
