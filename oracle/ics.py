@@ -89,6 +89,23 @@ def truncate_noise(noise: torch.Tensor, n_coarse: int) -> torch.Tensor:
     return fourier.irfft3(out, n_coarse)
 
 
+def fix_spectrum(w_hat: torch.Tensor, n: int) -> torch.Tensor:
+    """Every mode keeps its phase and takes the expected modulus of unit white noise,
+    |w_hat| = N^(3/2); modes with w_hat = 0 stay zero (no phase; reading)."""
+    mag = w_hat.abs()
+    return torch.where(mag > 0, w_hat / torch.where(mag > 0, mag, torch.ones_like(mag)) * n ** 1.5,
+                       torch.zeros_like(w_hat))
+
+
+def fixed_noise(noise: torch.Tensor, negate: bool = False) -> torch.Tensor:
+    """Paired-and-fixed white noise (the pairing method cited in Sec. 4 for the
+    bispectrum): the fixed spectrum of the noise, transformed back; the partner
+    realisation is its negative (all phases shifted by pi)."""
+    n = noise.shape[-1]
+    out = fourier.irfft3(fix_spectrum(fourier.rfft3(noise.to(torch.float64)), n), n)
+    return -out if negate else out
+
+
 def _lattice_phase(n: int) -> torch.Tensor:
     kx, ky, kz = fourier.kgrid(n)
     ph = 0.5 * (kx + ky + kz)

@@ -399,3 +399,43 @@ def test_lpt2_set_is_zeldovich_plus_second_order():
     d = (pos - pz - psi2 + n / 2) % n - n / 2
     assert float(d.abs().max()) < 1e-12
     assert 1e-4 < float(psi2.abs().max()) < 0.1 * float(psi1.abs().max())
+
+
+# ---------------------------------------------------------------------------
+# paired-and-fixed noise (pairing method, Sec. 4)
+# ---------------------------------------------------------------------------
+
+def test_fixed_spectrum_of_a_plane_wave_is_a_plane_wave_of_fixed_amplitude():
+    # A cos(2 pi m.x/N + ph) has w_hat = (A N^3 / 2) e^{i ph} at m (and its conjugate at
+    # -m); fixing sets the modulus to N^(3/2): the field 2 N^(-3/2) cos(2 pi m.x/N + ph)
+    # whatever A.  (Built in Fourier space: a transform would leave rounding-level
+    # modes elsewhere, which fixing would raise to full amplitude.)
+    n = 16
+    g = torch.arange(n, dtype=torch.float64)
+    x = torch.stack(torch.meshgrid(g, g, g, indexing="ij"))
+    for m, ph, amp in (((1, 2, 3), 0.7, 5.0), ((0, 0, 4), -1.1, 0.01), ((3, -5, 1), 2.0, 1.0)):
+        w = torch.zeros((n, n, n // 2 + 1), dtype=torch.complex128)
+        w[m[0] % n, m[1] % n, m[2]] = amp * n ** 3 / 2 * complex(math.cos(ph), math.sin(ph))
+        got = fourier.irfft3(ics.fix_spectrum(w, n), n)
+        arg = 2 * math.pi * (m[0] * x[0] + m[1] * x[1] + m[2] * x[2]) / n + ph
+        assert torch.allclose(got, 2 * n ** -1.5 * torch.cos(arg), atol=1e-14)
+    noise = torch.from_numpy(si.white_noise(n, 6))
+    assert torch.equal(ics.fixed_noise(noise, negate=True), -ics.fixed_noise(noise))
+
+
+def test_fixed_noise_keeps_phases_and_removes_amplitude_scatter():
+    n = 16
+    noise = torch.from_numpy(si.white_noise(n, 5))
+    w = fourier.rfft3(noise)
+    f = fourier.rfft3(ics.fixed_noise(noise))
+    assert torch.allclose(f.abs(), torch.full_like(f.abs(), n ** 1.5), rtol=1e-12)
+    assert float((torch.angle(f / w)).abs().max()) < 1e-10
+    # per-mode power of the Zel'dovich linear density from fixed noise is the input P(k) exactly
+    p = ics.ICParams(n=n, box=200.0, a_init=0.1, power=cm.PowerSpec("powerlaw", 50.0, -1.0), a_norm=0.1)
+    dl = ics.linear_delta_k(ics.fixed_noise(noise), p)
+    kx, ky, kz = fourier.kgrid(n)
+    kf = 2 * math.pi / p.box
+    kmag = torch.sqrt(kx * kx + ky * ky + kz * kz) / (2 * math.pi / n) * kf
+    keep = dl.abs() > 0
+    want = p.power.amp * kmag[keep] ** -1.0 / p.dx ** 3 * n ** 3
+    assert torch.allclose(dl.abs()[keep] ** 2, want, rtol=1e-10)
