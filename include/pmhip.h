@@ -300,6 +300,16 @@ int pm_ic_zeldovich(pm_plan* plan, const void* noise, const pm_ic_params* ic, vo
 int pm_ic_2lpt(pm_plan* plan, const void* noise, const pm_ic_params* ic, void* disp_scratch, void* pos, void* mom,
                void* stream);
 
+/* Paired-and-fixed white noise (the pairing method cited in Sec. 4 for the
+ * bispectrum).  Every Fourier mode of every box keeps its phase and takes the
+ * expected modulus of unit white noise, |DFT(noise)| = N^(3/2) (exact zeros stay
+ * zero).  pair_mode 0: fixed only; 1: fixed and negated (the partner realisation);
+ * 2: fixed, and every odd box of the batch negated, so that boxes (2j, 2j+1) given the
+ * same noise become a pair (needs an even number of boxes).  noise: [boxes][N^3]
+ * (read only); noise_out: same shape (written; may alias noise).  Uses the plan's
+ * spectrum workspace. */
+int pm_noise_fix(pm_plan* plan, const void* noise, int pair_mode, void* noise_out, void* stream);
+
 /* Adjoint of pm_ic_zeldovich with respect to the noise; not in the paper.  The
  * forward map noise -> (pos, mom) is affine: pos = wrap(q + Psi), mom = m Psi with
  * Psi_d = IDFT(S_d DFT(noise)).  Given the cotangents lam_pos, lam_mom [3][N^3]

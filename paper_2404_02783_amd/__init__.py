@@ -19,7 +19,7 @@ __all__ = [
     "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "displacement_add", "pm_xi_linear",
     "pk_estimate", "bk_estimate",
     "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
-    "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_gauge", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
+    "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_gauge", "pm_noise_fix", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
     "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH",
     "PM_F32", "PM_F64", "PM_NEWTON", "PM_POISSON_GAUGE", "PM_GRAD_SPECTRAL", "PM_GRAD_FD2", "PM_GRAD_FD1",
@@ -99,6 +99,7 @@ def _declare(l):
         "pk_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int64, _c_int, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_zeldovich": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_2lpt": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+        "pm_noise_fix": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_void_p]),
         "pm_ic_zeldovich_adjoint": (_c_int, [_c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                                              _c_void_p]),
         "pm_noise_truncate": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
@@ -374,6 +375,18 @@ def pm_ic_2lpt(plan: Plan, noise, ic: ICParams, disp_scratch, pos, mom):
     _check(lib().pm_ic_2lpt(plan.handle, _ptr(noise, plan.dtype, "noise"), ctypes.byref(ic),
                             _ptr(disp_scratch, plan.dtype, "disp_scratch"), _ptr(pos, plan.dtype, "pos"),
                             _ptr(mom, plan.dtype, "mom"), _stream()))
+
+
+def pm_noise_fix(plan: Plan, noise, pair_mode: int = 0, out=None):
+    """Paired-and-fixed noise: 0 fixed, 1 fixed and negated, 2 odd boxes of a batch
+    negated (pairs of boxes)."""
+    out = torch.empty_like(noise) if out is None else out
+    n3 = plan.batch * plan.n ** 3
+    _need(noise, n3, "noise")
+    _need(out, n3, "out")
+    _check(lib().pm_noise_fix(plan.handle, _ptr(noise, plan.dtype, "noise"), int(pair_mode),
+                              _ptr(out, plan.dtype, "out"), _stream()))
+    return out
 
 
 def pm_ic_zeldovich_adjoint(plan: Plan, ic: ICParams, lam_pos, lam_mom, disp_scratch=None, lam_noise=None):

@@ -286,6 +286,24 @@ int pm_ic_2lpt(pm_plan* p, const void* noise, const pm_ic_params* ic, void* disp
   return launch_ic_lattice2(p, disp, mom, pos, mom, ae * f1, ae * f2, s);
 }
 
+int pm_noise_fix(pm_plan* p, const void* noise, int pair_mode, void* noise_out, void* stream) {
+  using namespace pm;
+  if (!p) return set_error(PM_ERR_ARG, "pm_noise_fix: null plan");
+  if (!noise || !noise_out) return set_error(PM_ERR_ARG, "pm_noise_fix: null pointer");
+  if (pair_mode < 0 || pair_mode > 2) return set_error(PM_ERR_ARG, "pm_noise_fix: bad pair_mode %d", pair_mode);
+  if (pair_mode == 2 && p->nb % 2 != 0)
+    return set_error(PM_ERR_ARG, "pm_noise_fix: pair_mode 2 needs an even number of boxes (%d)", p->nb);
+  p->dens_valid = false;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = fft3_r2c(p, noise, cbuf(p, 0), s);
+  if (rc) return rc;
+  const double n = (double)p->n;
+  const int mask = pair_mode == 0 ? 0 : (pair_mode == 1 ? 3 : 2);
+  rc = launch_fix_spectrum(p, std::pow(n, 1.5) / (n * n * n), mask, s);
+  if (rc) return rc;
+  return fft3_c2r(p, p->nb, cbuf(p, 0), cstride(p), noise_out, s);
+}
+
 int pm_ic_zeldovich_adjoint(pm_plan* p, const pm_ic_params* ic, const void* lam_pos, const void* lam_mom,
                             void* disp_scratch, void* lam_noise, void* stream) {
   using namespace pm;

@@ -156,6 +156,9 @@ int launch_triple_sum(const pm_plan* p, const void* a, const void* b, const void
 int launch_bk_finalize(const pm_plan* p, int n_tri, const double* sums, double* bk, double* ntri_out,
                        const double* ntri_known, hipStream_t s);
 int launch_zero_doubles(double* d, int64_t n, hipStream_t s);
+// cbuf(0) of every box: modulus set to target, phase kept; box b negated when bit
+// (b & 1) of negate_mask is set.
+int launch_fix_spectrum(const pm_plan* p, double target, int negate_mask, hipStream_t s);
 // cbuf(coarse, 0) <- the shared modes of cbuf(fine, 0) scaled by (Nc/Nf)^(3/2) / Nc^3.
 int launch_truncate_spectrum(const pm_plan* fine, const pm_plan* coarse, hipStream_t s);
 // dhat <- beta_b dhat with beta from dP (device [n_bins]) and the counts of the last reduction.

@@ -268,6 +268,26 @@ __global__ void __launch_bounds__(kBlock) k_truncate_spectrum(const cx<T>* __res
   stc(coarse + idx, v);
 }
 
+// Paired-and-fixed noise: every stored mode keeps its phase and takes the modulus
+// `target` (N^(3/2) times the inverse transform's 1/N^3); exact zeros stay zero.
+// Box b of the batch is negated when `negate_mask` has its bit (b & 1) set
+// (bit 0: even boxes, bit 1: odd boxes).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fix_spectrum(cx<T>* __restrict__ c, int n, int hp, int64_t cs,
+                                                         double target, int negate_mask) {
+  const int64_t total = (int64_t)n * n * hp;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= total) return;
+  if ((int)(idx % hp) > n / 2) return;
+  c += (int64_t)blockIdx.y * cs;
+  const cx<T> v = ldc(c + idx);
+  const double re = (double)v.x, im = (double)v.y;
+  const double m = sqrt(re * re + im * im);
+  double f = m > 0.0 ? target / m : 0.0;
+  if ((negate_mask >> (blockIdx.y & 1)) & 1) f = -f;
+  stc(c + idx, mk(T(re * f), T(im * f)));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_shell_mask(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n,
                                                        int hp, double lo4, double hi4) {
@@ -347,6 +367,20 @@ int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, bool adjoint, hipStr
   else
     hipLaunchKernelGGL((k_ic_symbol<double, false>), g, dim3(kBlock), 0, s, d[0], d[1], d[2], n, p->hp, cs, sym);
   return hip_check(hipGetLastError(), "ic symbol");
+}
+
+int launch_fix_spectrum(const pm_plan* p, double target, int negate_mask, hipStream_t s) {
+  ProfScope ps(p, PK_IC, s);
+  const int n = p->n;
+  const int64_t total = (int64_t)n * n * p->hp;
+  const dim3 g((unsigned)((total + kBlock - 1) / kBlock), (unsigned)p->nb);
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_fix_spectrum<float>, g, dim3(kBlock), 0, s, static_cast<cx<float>*>(cbuf(p, 0)), n, p->hp,
+                       cstride(p), target, negate_mask);
+  else
+    hipLaunchKernelGGL(k_fix_spectrum<double>, g, dim3(kBlock), 0, s, static_cast<cx<double>*>(cbuf(p, 0)), n,
+                       p->hp, cstride(p), target, negate_mask);
+  return hip_check(hipGetLastError(), "fix spectrum");
 }
 
 int launch_zero_doubles(double* d, int64_t n, hipStream_t s) {

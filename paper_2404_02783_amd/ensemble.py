@@ -18,7 +18,8 @@ from dataclasses import dataclass, field
 import torch
 
 from . import (FIDUCIAL, ICParams, PM_PK_EH98, PM_STEP_DENSITY_READY, PM_STEP_DEPOSIT_NEXT, Plan, StepParams,
-               kdk_factors, newton_params, pk_estimate, pm_deposit, pm_ic_zeldovich, pm_step, power_eh98_amplitude)
+               kdk_factors, newton_params, pk_estimate, pm_deposit, pm_ic_zeldovich, pm_noise_fix, pm_step,
+               power_eh98_amplitude)
 from .sim import log_steps
 
 __all__ = ["Group", "Ensemble", "default_groups", "schedule", "run_sequential"]
@@ -76,18 +77,27 @@ def schedule(a_start=0.02, a_end=1.0, n_steps=30, n_s=0.965, sigma8=0.81, cosmo=
 
 class Ensemble:
     """All groups of an ensemble with their device buffers.  ``noise_fn(n, seed)``
-    returns the host white-noise field of one box (float64 numpy [n, n, n])."""
+    returns the host white-noise field of one box (float64 numpy [n, n, n]).
+
+    ``paired_fixed``: every seed gives two boxes, 2j and 2j + 1, run from the
+    paired-and-fixed noise of that seed (fixed mode amplitudes; the partner's field
+    negated); ``paired_power_spectra`` averages each pair."""
 
     def __init__(self, groups, noise_fn, a_start=0.02, a_end=1.0, n_steps=30, dtype=torch.float32, device=None,
-                 n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL):
+                 n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL, paired_fixed: bool = False):
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.dtype = dtype
+        self.paired_fixed = paired_fixed
         self.a_steps, self.ic, self.cycles = schedule(a_start, a_end, n_steps, n_s, sigma8, cosmo)
         self.states = []
         for g in groups:
-            plan = Plan(g.n, g.box, dtype, self.device, batch=len(g.seeds))
-            noise = torch.stack([torch.from_numpy(noise_fn(g.n, s)) for s in g.seeds]).to(dtype).to(self.device)
-            self.states.append(_State(g, plan, noise.contiguous(), plan.particles(), plan.particles(), plan.mesh(3),
+            reps = 2 if paired_fixed else 1
+            plan = Plan(g.n, g.box, dtype, self.device, batch=reps * len(g.seeds))
+            noise = torch.stack([torch.from_numpy(noise_fn(g.n, s)) for s in g.seeds for _ in range(reps)])
+            noise = noise.to(dtype).to(self.device).contiguous()
+            if paired_fixed:
+                pm_noise_fix(plan, noise, 2, out=noise)
+            self.states.append(_State(g, plan, noise, plan.particles(), plan.particles(), plan.mesh(3),
                                       plan.mesh(3), plan.mesh()))
         self.graph = None
 
@@ -124,6 +134,13 @@ class Ensemble:
     def power_spectra(self):
         """[(k_mean, P, n_modes) per group], each [boxes, bins] on the device."""
         return [st.out for st in self.states]
+
+    def paired_power_spectra(self):
+        """For a paired-and-fixed ensemble: [(k_mean, P averaged over each pair,
+        n_modes) per group], each [seeds, bins]."""
+        if not self.paired_fixed:
+            raise ValueError("not a paired-and-fixed ensemble")
+        return [(k[0::2], 0.5 * (p[0::2] + p[1::2]), c[0::2]) for k, p, c in self.power_spectra()]
 
 
 def run_sequential(groups, noise_fn, a_start=0.02, a_end=1.0, n_steps=30, dtype=torch.float32, device=None,

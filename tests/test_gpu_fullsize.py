@@ -31,6 +31,8 @@ at a time, or a property that holds at any size:
     ICs drop): sampled particles against the oracle's ICs of the sparse noise
     spectrum (for 2LPT, the second-order source as a sum over mode pairs); the
     truncation of that noise to 256^3, whole, against the sparse truncation;
+  * paired-and-fixed noise at 1024^3: moduli and phases of every mode against an
+    independent FFT, the partner exactly negated;
   * the linear Poisson-gauge shift at a = 1 at 1024^3, and the combination with it
     of the 256^3 truncation into the 1024^3 Zel'dovich set, at sampled particles;
   * the coarse 256^3 pair of the combination configuration (Zel'dovich and
@@ -534,6 +536,31 @@ def test_ics_2lpt_full_size_sampled_particles(plan):
     # the second-order displacement is a sizeable part of the answer (0.65 cell here)
     wza = oics.zeldovich_pair_sparse(modes, vals, p, j)[0]
     assert float(min_image(wpos - wza, N).abs().max()) > 0.1
+
+
+def test_noise_fix_full_size_properties(plan):
+    """Paired-and-fixed noise at 1024^3: every mode's modulus is N^(3/2) and its phase
+    is the input's (checked with an independent FFT), and the partner is the exact
+    negative."""
+    dev = plan.device
+    g = torch.Generator(device=dev).manual_seed(97)
+    noise = torch.randn((N, N, N), generator=g, device=dev, dtype=torch.float32)
+    fixed = pm.pm_noise_fix(plan, noise, 0)
+    partner = pm.pm_noise_fix(plan, noise, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(partner, -fixed)
+    del partner
+    w = torch.fft.rfftn(noise)
+    del noise
+    f = torch.fft.rfftn(fixed)
+    del fixed
+    mag = f.abs()
+    assert float((mag / N ** 1.5 - 1.0).abs().max()) < 1e-3
+    assert float((mag / N ** 1.5 - 1.0).pow(2).mean().sqrt()) < 1e-5
+    big = w.abs() > 0.1 * N ** 1.5          # phases well defined in FP32
+    ph = torch.angle(f[big] * torch.conj(w[big]))
+    assert float(ph.abs().max()) < 1e-3
+    assert float(ph.pow(2).mean().sqrt()) < 1e-5
 
 
 def test_noise_truncate_full_size(plan):

@@ -473,6 +473,37 @@ def test_2lpt_rejects_shared_buffers_and_batches():
 
 
 @pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n", [32, 192])
+def test_noise_fix(dt, n):
+    dev = _dev()
+    plan = pm.Plan(n, 1000.0, dt)
+    noise = torch.from_numpy(si.white_noise(n, 93)).to(dt)
+    want = oics.fixed_noise(noise.double())
+    for mode, sign in ((0, 1.0), (1, -1.0)):
+        got = pm.pm_noise_fix(plan, noise.to(dev), mode)
+        torch.cuda.synchronize()
+        assert rel_l2(got, sign * want) < _tol(dt)
+    inplace = noise.to(dev)
+    pm.pm_noise_fix(plan, inplace, 0, out=inplace)
+    torch.cuda.synchronize()
+    assert rel_l2(inplace, want) < _tol(dt)
+
+
+def test_noise_fix_pairs_in_a_batch():
+    dev = _dev()
+    n = 32
+    plan = pm.Plan(n, 1000.0, torch.float64, batch=4)
+    a, b = (torch.from_numpy(si.white_noise(n, s)) for s in (94, 95))
+    got = pm.pm_noise_fix(plan, torch.stack([a, a, b, b]).to(dev), 2)
+    torch.cuda.synchronize()
+    for i, want in enumerate((oics.fixed_noise(a), -oics.fixed_noise(a), oics.fixed_noise(b), -oics.fixed_noise(b))):
+        assert rel_l2(got[i], want) < F64_TOL
+    with pytest.raises(pm.PMError, match="even"):
+        pm.pm_noise_fix(pm.Plan(n, 1000.0, torch.float64, batch=3), torch.zeros((3, n, n, n), device=dev,
+                                                                                dtype=torch.float64), 2)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
 @pytest.mark.parametrize("nf,nc", [(64, 16), (32, 32), (128, 32)])
 def test_noise_truncate(dt, nf, nc):
     dev = _dev()
