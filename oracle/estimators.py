@@ -229,3 +229,41 @@ def bin_of_norm2(s: torch.Tensor, n: int, n_bins: int) -> torch.Tensor:
         b = torch.where(n * n * (2 * b + 1) ** 2 > q, b - 1, b)
         b = torch.where(n * n * (2 * b + 3) ** 2 <= q, b + 1, b)
     return torch.where((b >= 0) & (b < n_bins), b, torch.full_like(b, -1))
+
+
+def cross_power_spectrum(delta_a: torch.Tensor, delta_b: torch.Tensor, box: float, n_bins: int):
+    """(k_mean, P_ab, n_modes): the cross spectrum of two meshes of one box,
+    <delta_a(k) delta_b(k)*> = (2 pi)^3 delta_D(0) P_ab, i.e. (V/N^6) <Re(a_hat conj(b_hat))>
+    over the P(k) bins (cross power of the combined and Newtonian fields; the halo-
+    matter cross power of the bias fits, Sec. 5, with matter fields as proxies)."""
+    n = delta_a.shape[0]
+    ah, bh = fourier.rfft3(delta_a.to(torch.float64)), fourier.rfft3(delta_b.to(torch.float64))
+    b = pk_bin_index(n, n_bins).reshape(-1)
+    wt = fourier.r2c_weights(n).expand(n, n, n // 2 + 1).reshape(-1)
+    cross = (ah.real * bh.real + ah.imag * bh.imag).reshape(-1)
+    kmag = torch.sqrt(mode_norm_sq(n).double()).reshape(-1)
+    sel = b >= 0
+    cnt = torch.zeros(n_bins, dtype=torch.float64).index_add(0, b[sel], wt[sel])
+    sp = torch.zeros(n_bins, dtype=torch.float64).index_add(0, b[sel], (wt * cross)[sel])
+    sk = torch.zeros(n_bins, dtype=torch.float64).index_add(0, b[sel], (wt * kmag)[sel])
+    safe = torch.where(cnt > 0, cnt, torch.ones_like(cnt))
+    pk = torch.where(cnt > 0, box ** 3 / n ** 6 * sp / safe, torch.zeros_like(cnt))
+    km = torch.where(cnt > 0, 2.0 * math.pi / box * sk / safe, torch.zeros_like(cnt))
+    return km, pk, cnt.round().long()
+
+
+def bias_fit(k: torch.Tensor, ratio: torch.Tensor, n_modes: torch.Tensor, k_cut: float, calh: float,
+             skip: int = 2, with_k2: bool = True):
+    """Scale-dependent linear bias (eq. b1 with the scale dependence of Sec. 5):
+    ratio(k) = b1 + b1_GR calH^2 / k^2 [+ c2 k^2], fitted by weighted least squares
+    (weights: mode counts, reading) over the bins with 0 < k < k_cut after dropping
+    the first ``skip`` of them (the paper drops the first two points).  calH in h/Mpc.
+    Returns (b1, b1_GR, c2) (c2 = 0 without the k^2 term)."""
+    sel = [i for i in range(k.shape[0]) if n_modes[i] > 0 and 0.0 < float(k[i]) < k_cut]
+    sel = sel[skip:]
+    kk = k[sel].to(torch.float64)
+    cols = [torch.ones_like(kk), calh * calh / (kk * kk)] + ([kk * kk] if with_k2 else [])
+    a = torch.stack(cols, dim=1)
+    w = torch.sqrt(n_modes[sel].to(torch.float64)).view(-1, 1)
+    sol = torch.linalg.lstsq(a * w, ratio[sel].to(torch.float64).view(-1, 1) * w).solution.view(-1)
+    return float(sol[0]), float(sol[1]), float(sol[2]) if with_k2 else 0.0

@@ -217,3 +217,61 @@ def test_triangle_count_brute_force():
                     cnt += 1
         want.append(cnt)
     assert n_fft.round().long().tolist() == want
+
+
+# ---------------------------------------------------------------------------
+# cross spectrum and scale-dependent bias fit (Sec. 5, eq. b1)
+# ---------------------------------------------------------------------------
+
+def test_cross_spectrum_special_cases():
+    n, box, nb = 16, 300.0, 8
+    g = si.rng(3)
+    a = torch.from_numpy(g.standard_normal((n, n, n)))
+    e = torch.from_numpy(g.standard_normal((n, n, n)))
+    k0, p0, c0 = estimators.power_spectrum(a, box, nb)
+    k1, p1, c1 = estimators.cross_power_spectrum(a, a, box, nb)
+    assert torch.equal(c0, c1) and torch.allclose(k0, k1, rtol=1e-15)
+    assert torch.allclose(p1, p0, rtol=1e-13)
+    # bilinear: P(a, 2a + e) = 2 P(a, a) + P(a, e); symmetric; Cauchy-Schwarz per bin
+    _, pab, _ = estimators.cross_power_spectrum(a, 2 * a + e, box, nb)
+    _, pae, _ = estimators.cross_power_spectrum(a, e, box, nb)
+    _, pea, _ = estimators.cross_power_spectrum(e, a, box, nb)
+    _, pee, _ = estimators.power_spectrum(e, box, nb)
+    assert torch.allclose(pab, 2 * p0 + pae, rtol=1e-12, atol=1e-12 * float(p0.abs().max()))
+    assert torch.allclose(pae, pea, rtol=1e-14)
+    assert bool((pae.abs() <= torch.sqrt(p0 * pee) * (1 + 1e-12)).all())
+    # one plane wave in each field, same mode, phase lag phi: P_ab = (V/N^6) w |a||b| cos(phi) / count
+    x = torch.arange(n, dtype=torch.float64)
+    gx, gy, gz = torch.meshgrid(x, x, x, indexing="ij")
+    arg = 2 * math.pi * (3 * gx + gy - 2 * gz) / n
+    _, pc, cnt = estimators.cross_power_spectrum(torch.cos(arg), 2 * torch.cos(arg + 0.6), box, nb)
+    b = int(estimators.pk_bin_index(n, nb)[3, 1, 2])
+    want = box ** 3 / n ** 6 * 2 * (n ** 3 / 2) * (n ** 3) * math.cos(0.6) / float(cnt[b])
+    assert float(pc[b]) == pytest.approx(want, rel=1e-12)
+
+
+def test_bias_fit_recovers_exact_coefficients_and_reduces_to_the_mean():
+    k = torch.linspace(0.002, 0.12, 40, dtype=torch.float64)
+    cnt = torch.arange(1, 41) * 6
+    calh = 3.3e-4
+    ratio = 1.7 + 2.9 * calh ** 2 / k ** 2 - 15.0 * k ** 2
+    b1, bgr, c2 = estimators.bias_fit(k, ratio, cnt, 0.08, calh)
+    assert (b1, bgr, c2) == (pytest.approx(1.7, rel=1e-10), pytest.approx(2.9, rel=1e-8), pytest.approx(-15.0, rel=1e-8))
+    # the first two bins below the cut are dropped: corrupting them changes nothing
+    bad = ratio.clone()
+    bad[:2] += 100.0
+    assert estimators.bias_fit(k, bad, cnt, 0.08, calh) == pytest.approx((b1, bgr, c2), rel=1e-9)
+    # bins at and above the cut are ignored
+    bad = ratio.clone()
+    bad[k >= 0.08] = -50.0
+    assert estimators.bias_fit(k, bad, cnt, 0.08, calh) == pytest.approx((b1, bgr, c2), rel=1e-9)
+    # a constant ratio without scale dependence: b1 is the (weighted) mean, b1_GR = 0
+    noise = torch.from_numpy(si.rng(4).standard_normal(40)) * 0.01
+    sel = slice(2, int((k < 0.08).sum()))
+    r = 1.3 + noise
+    b1, bgr, _ = estimators.bias_fit(k, r, cnt, 0.08, calh, with_k2=False)
+    # normal equations: the weighted residual is orthogonal to both columns
+    kk, rr, ww = k[sel], r[sel], cnt[sel].double()
+    res = rr - b1 - bgr * calh ** 2 / kk ** 2
+    assert abs(float((ww * res).sum())) < 1e-12
+    assert abs(float((ww * res / kk ** 2).sum())) < 1e-12 * float((ww / kk ** 2).sum())
