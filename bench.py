@@ -210,6 +210,14 @@ def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
     out["xi_linear_256_ms"] = round((t1 - t0) * 1e3, 2)
     out["add_linear_shift_ms"] = round((t2 - t1) * 1e3, 2)
     del xi
+    # cross spectrum of the combined field with the fine run's (256 bins)
+    delta_c = pm.pm_deposit(plan, x_out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm.pk_cross_estimate(plan, delta_c, delta, n_bins)
+    torch.cuda.synchronize()
+    out["pk_cross_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    del delta_c
     out["note"] = ("coarse noise is the Fourier truncation of the fine noise (shared phases); B(k) keeps 8 shell "
                    "fields resident and recomputes evicted shells")
     del x_out, xn, pn, xg, pg, disp, cplan, delta

@@ -253,6 +253,24 @@ int displacement_add(const void* xi, int n_coarse, const void* x_fine, int n_fin
 int pk_estimate(pm_plan* plan, const void* delta, int n_bins, double* k_mean, double* pk, int64_t* n_modes,
                 void* stream);
 
+/* Cross power spectrum of two meshes of the same box(es): P_ab = (V/N^6)
+ * <Re(a_hat conj(b_hat))> over the bins of pk_estimate (the halo-matter cross power of
+ * the bias fits, Sec. 5, here of any two fields, e.g. combined and Newtonian).
+ * delta_a, delta_b: [boxes][N][N][N] real (read only); outputs as pk_estimate.  Uses
+ * two spectra of the plan's workspace. */
+int pk_cross_estimate(pm_plan* plan, const void* delta_a, const void* delta_b, int n_bins, double* k_mean,
+                      double* pk, int64_t* n_modes, void* stream);
+
+/* Scale-dependent linear bias (eq. b1 and the scale dependence of Sec. 5): fits
+ * ratio(k) = b1 + b1_GR calh^2/k^2 (+ c2 k^2 when with_k2) by least squares weighted
+ * with the mode counts, over the bins with n_modes > 0 and 0 < k < k_cut after
+ * dropping the first `skip` of them (the paper drops two).  Host arrays of n_bins: k
+ * [h/Mpc], ratio (e.g. P_cross / P_auto), n_modes; calh = aH/c in h/Mpc.  Writes coef[3]
+ * = (b1, b1_GR, c2) (c2 = 0 without the k^2 term).  PM_ERR_ARG when fewer bins than
+ * parameters remain or the system is singular.  Host computation only. */
+int bias_fit(const double* k, const double* ratio, const int64_t* n_modes, int n_bins, double k_cut, double calh,
+             int skip, int with_k2, double* coef);
+
 /* Adjoint of positions -> CIC counting density -> pk_estimate (eq. powerspectrum);
  * not in the paper.  dpk: device double [n_bins], the cotangent dL/dP_b.  Writes
  * lam_pos[d][p] = dL/dx_{p,d} (overwritten): the spectrum of the particles' density

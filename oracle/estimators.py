@@ -132,11 +132,14 @@ def brute_bispectrum(delta: torch.Tensor, box: float, centres, width: float, tri
     return torch.tensor(out_b, dtype=torch.float64), torch.tensor(out_n, dtype=torch.float64)
 
 
-def power_spectrum_sparse(modes: torch.Tensor, values: torch.Tensor, n: int, box: float, n_bins: int):
+def power_spectrum_sparse(modes: torch.Tensor, values: torch.Tensor, n: int, box: float, n_bins: int,
+                          values_b: torch.Tensor | None = None):
     """``power_spectrum_from_k`` of an r2c spectrum that vanishes except at the stored
     modes ``modes`` ([M, 3]: n_x, n_y in [-N/2, N/2), n_z in [0, N/2]) with amplitudes
-    ``values``.  Mode counts and mean |k| run over every mode, one n_x plane at a time,
-    so no N^3 array is formed."""
+    ``values``; with ``values_b`` (a second spectrum on the same modes) the cross
+    spectrum, Re(values conj(values_b)), as ``cross_power_spectrum`` bins it.  Mode
+    counts and mean |k| run over every mode, one n_x plane at a time, so no N^3 array
+    is formed."""
     full = torch.fft.fftfreq(n, d=1.0 / n).round().long()
     nz = torch.arange(n // 2 + 1, dtype=torch.long)
     wz = torch.full((n // 2 + 1,), 2.0, dtype=torch.float64)
@@ -162,7 +165,8 @@ def power_spectrum_sparse(modes: torch.Tensor, values: torch.Tensor, n: int, box
     s = (m * m).sum(dim=1)
     b = bin_of(s)
     wt = wz[m[:, 2]]
-    p2 = values.real ** 2 + values.imag ** 2
+    vb = values if values_b is None else values_b
+    p2 = values.real * vb.real + values.imag * vb.imag
     sp = torch.zeros(n_bins, dtype=torch.float64)
     sel = b >= 0
     sp.index_add_(0, b[sel], (wt * p2)[sel])

@@ -17,7 +17,7 @@ import torch
 __all__ = [
     "PMError", "lib", "SolveParams", "StepParams", "Cosmology", "ICParams", "Plan",
     "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "displacement_add", "pm_xi_linear",
-    "pk_estimate", "bk_estimate",
+    "pk_estimate", "pk_cross_estimate", "bias_fit", "bk_estimate",
     "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
     "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_gauge", "pm_noise_fix", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
@@ -92,6 +92,10 @@ def _declare(l):
                                           _c_void_p]),
         "displacement_add": (_c_int, [_c_void_p, _c_int, _c_void_p, _c_int, _c_int, _c_void_p, _c_void_p]),
         "pk_estimate": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+        "pk_cross_estimate": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_void_p, _c_void_p, _c_void_p,
+                                       _c_void_p]),
+        "bias_fit": (_c_int, [P(_c_double), P(_c_double), P(ctypes.c_int64), _c_int, _c_double, _c_double, _c_int,
+                              _c_int, P(_c_double)]),
         "bk_estimate": (_c_int, [_c_void_p, _c_void_p, _c_int, P(_c_double), _c_double, P(ctypes.c_int32), _c_int,
                                  _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_size_t, _c_void_p]),
         "pm_step_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int64, P(StepParams), _c_void_p, _c_void_p, _c_void_p,
@@ -335,6 +339,35 @@ def pk_estimate(plan: Plan, delta, n_bins: int):
     _check(lib().pk_estimate(plan.handle, _ptr(delta, plan.dtype, "delta"), int(n_bins), _ptr(k), _ptr(p), _ptr(c),
                              _stream()))
     return k, p, c
+
+
+def pk_cross_estimate(plan: Plan, delta_a, delta_b, n_bins: int):
+    """(k_mean, P_ab, n_modes), each [n_bins] ([batch, n_bins] for a batch)."""
+    shape = (n_bins,) if plan.batch == 1 else (plan.batch, n_bins)
+    _need(delta_a, plan.batch * plan.n ** 3, "delta_a")
+    _need(delta_b, plan.batch * plan.n ** 3, "delta_b")
+    k = torch.empty(shape, dtype=torch.float64, device=plan.device)
+    p = torch.empty(shape, dtype=torch.float64, device=plan.device)
+    c = torch.empty(shape, dtype=torch.int64, device=plan.device)
+    _check(lib().pk_cross_estimate(plan.handle, _ptr(delta_a, plan.dtype, "delta_a"),
+                                   _ptr(delta_b, plan.dtype, "delta_b"), int(n_bins), _ptr(k), _ptr(p), _ptr(c),
+                                   _stream()))
+    return k, p, c
+
+
+def bias_fit(k, ratio, n_modes, k_cut: float, calh: float, skip: int = 2, with_k2: bool = True):
+    """(b1, b1_GR, c2) of ratio(k) = b1 + b1_GR calh^2/k^2 (+ c2 k^2); host sequences."""
+    k = [float(v) for v in k]
+    ratio = [float(v) for v in ratio]
+    n_modes = [int(v) for v in n_modes]
+    nb = len(k)
+    if len(ratio) != nb or len(n_modes) != nb:
+        raise PMError(PM_ERR_ARG, "bias_fit: k, ratio and n_modes differ in length")
+    coef = (ctypes.c_double * 3)()
+    _check(lib().bias_fit((ctypes.c_double * nb)(*k), (ctypes.c_double * nb)(*ratio),
+                          (ctypes.c_int64 * nb)(*n_modes), nb, float(k_cut), float(calh), int(skip),
+                          int(bool(with_k2)), coef))
+    return coef[0], coef[1], coef[2]
 
 
 def bk_estimate(plan: Plan, delta, centres, width: float, triangles, shell_ws=None, ntri_known=None):

@@ -472,6 +472,68 @@ int pk_estimate(pm_plan* p, const void* delta, int n_bins, double* k_mean, doubl
   return launch_pk_finalize(p, n_bins, k_mean, pk, n_modes, s);
 }
 
+int pk_cross_estimate(pm_plan* p, const void* delta_a, const void* delta_b, int n_bins, double* k_mean, double* pk,
+                      int64_t* n_modes, void* stream) {
+  PM_TRY(check_plan(p));
+  drop_density(p);
+  if (!delta_a || !delta_b || !k_mean || !pk || !n_modes) return set_error(PM_ERR_ARG, "pk_cross_estimate: null pointer");
+  if (n_bins <= 0 || 3 * (size_t)n_bins * p->nb > p->sums_cap || n_bins > 4 * p->n)
+    return set_error(PM_ERR_ARG, "pk_cross_estimate: n_bins %d out of range", n_bins);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PM_TRY(fft3_r2c(p, delta_a, cbuf(p, 0), s));
+  PM_TRY(fft3_r2c(p, delta_b, cbuf(p, 1), s));
+  PM_TRY(launch_zero_doubles(p->sums, 3 * (int64_t)n_bins * p->nb, s));
+  PM_TRY(launch_pk_reduce(p, cbuf(p, 0), n_bins, s, cbuf(p, 1)));
+  return launch_pk_finalize(p, n_bins, k_mean, pk, n_modes, s);
+}
+
+int bias_fit(const double* k, const double* ratio, const int64_t* n_modes, int n_bins, double k_cut, double calh,
+             int skip, int with_k2, double* coef) {
+  g_err[0] = 0;
+  if (!k || !ratio || !n_modes || !coef) return set_error(PM_ERR_ARG, "bias_fit: null pointer");
+  if (n_bins <= 0 || skip < 0 || !(k_cut > 0.0)) return set_error(PM_ERR_ARG, "bias_fit: bad arguments");
+  const int m = with_k2 ? 3 : 2;
+  // weighted normal equations (weights: mode counts) over 0 < k < k_cut, after `skip` bins
+  double a[3][3] = {{0}}, r[3] = {0};
+  int used = 0, seen = 0;
+  for (int b = 0; b < n_bins; ++b) {
+    if (n_modes[b] <= 0 || !(k[b] > 0.0 && k[b] < k_cut)) continue;
+    if (seen++ < skip) continue;
+    const double x[3] = {1.0, calh * calh / (k[b] * k[b]), k[b] * k[b]};
+    const double w = (double)n_modes[b];
+    for (int i = 0; i < m; ++i) {
+      r[i] += w * x[i] * ratio[b];
+      for (int j = 0; j < m; ++j) a[i][j] += w * x[i] * x[j];
+    }
+    ++used;
+  }
+  if (used < m) return set_error(PM_ERR_ARG, "bias_fit: %d bins below k_cut after the skip, %d needed", used, m);
+  // Gaussian elimination with partial pivoting
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < m; ++i)
+      if (std::fabs(a[i][c]) > std::fabs(a[piv][c])) piv = i;
+    if (!(std::fabs(a[piv][c]) > 0.0)) return set_error(PM_ERR_ARG, "bias_fit: singular system");
+    if (piv != c) {
+      for (int j = 0; j < m; ++j) std::swap(a[c][j], a[piv][j]);
+      std::swap(r[c], r[piv]);
+    }
+    for (int i = c + 1; i < m; ++i) {
+      const double f = a[i][c] / a[c][c];
+      for (int j = c; j < m; ++j) a[i][j] -= f * a[c][j];
+      r[i] -= f * r[c];
+    }
+  }
+  double x[3] = {0.0, 0.0, 0.0};
+  for (int i = m - 1; i >= 0; --i) {
+    double v = r[i];
+    for (int j = i + 1; j < m; ++j) v -= a[i][j] * x[j];
+    x[i] = v / a[i][i];
+  }
+  for (int i = 0; i < 3; ++i) coef[i] = x[i];
+  return PM_OK;
+}
+
 int bk_estimate(pm_plan* p, const void* delta, int n_shells, const double* centre, double width, const int32_t* tri,
                 int n_tri, double* bk, double* ntri_out, const double* ntri_known, void* shell_ws,
                 size_t shell_ws_bytes, void* stream) {

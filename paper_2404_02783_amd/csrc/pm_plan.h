@@ -147,7 +147,8 @@ struct IcSymbol {
 // Forward: cbuf(0) holds DFT(noise); writes the three displacement spectra S_d w_hat
 // to cbuf 0, 1, 2.  Adjoint: cbuf(0) <- sum_d conj(S_d) cbuf(d).
 int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, bool adjoint, hipStream_t s);
-int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s);
+// bhat non-NULL: cross power Re(dhat conj(bhat)) of the pair.
+int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s, const void* bhat = nullptr);
 int launch_pk_finalize(const pm_plan* p, int n_bins, double* k_mean, double* pk, int64_t* n_modes, hipStream_t s);
 // dst = src * 1_S (src may be NULL: indicator); shell membership (2c-w)^2 <= 4|n|^2 < (2c+w)^2.
 int launch_shell_mask(const pm_plan* p, const void* src, void* dst, double lo4, double hi4, hipStream_t s);

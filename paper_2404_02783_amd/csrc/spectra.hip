@@ -138,11 +138,13 @@ __device__ __forceinline__ int pk_bin(int64_t n2, int n, int nb) {
   return -1;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ dhat, int n, int hp, int64_t cs,
-                                                      int nb, double* __restrict__ sums) {
+// CROSS: the power of the pair (dhat, bhat), Re(dhat conj(bhat)), in place of |dhat|^2.
+template <typename T, bool CROSS>
+__global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ dhat, const cx<T>* __restrict__ bhat,
+                                                      int n, int hp, int64_t cs, int nb, double* __restrict__ sums) {
   extern __shared__ double sh[];
   dhat += (int64_t)blockIdx.y * cs;  // box of the batch
+  if (CROSS) bhat += (int64_t)blockIdx.y * cs;
   sums += (int64_t)blockIdx.y * 3 * nb;
   double* sp = sh;
   double* sk = sh + nb;
@@ -171,7 +173,13 @@ __global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ 
     if (b < 0) continue;
     const int wgt = (iz == 0 || iz == n / 2) ? 1 : 2;
     const cx<T> v = ldc(dhat + idx);
-    const double p2 = (double)v.x * v.x + (double)v.y * v.y;
+    double p2;
+    if (CROSS) {
+      const cx<T> u = ldc(bhat + idx);
+      p2 = (double)v.x * u.x + (double)v.y * u.y;
+    } else {
+      p2 = (double)v.x * v.x + (double)v.y * v.y;
+    }
     if (b != cur) {
       if (cur >= 0) {
         atomicAdd(&sp[cur], ap);
@@ -389,7 +397,7 @@ int launch_zero_doubles(double* d, int64_t n, hipStream_t s) {
   return hip_check(hipGetLastError(), "zero");
 }
 
-int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s) {
+int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s, const void* bhat) {
   ProfScope ps(p, PK_PK, s);
   const int n = p->n;
   const int64_t total = (int64_t)n * n * p->hp;
@@ -398,12 +406,15 @@ int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t
   if (g > 65535) g = 65535;
   const size_t shm = (size_t)n_bins * 3 * sizeof(double);
   const dim3 grid((unsigned)g, (unsigned)p->nb);
-  if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_pk_reduce<float>, grid, dim3(kBlock), shm, s, static_cast<const cx<float>*>(dhat), n, p->hp,
-                       cstride(p), n_bins, p->sums);
-  else
-    hipLaunchKernelGGL(k_pk_reduce<double>, grid, dim3(kBlock), shm, s, static_cast<const cx<double>*>(dhat), n,
-                       p->hp, cstride(p), n_bins, p->sums);
+  if (p->dtype == PM_F32) {
+    auto kern = bhat ? k_pk_reduce<float, true> : k_pk_reduce<float, false>;
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), shm, s, static_cast<const cx<float>*>(dhat),
+                       static_cast<const cx<float>*>(bhat), n, p->hp, cstride(p), n_bins, p->sums);
+  } else {
+    auto kern = bhat ? k_pk_reduce<double, true> : k_pk_reduce<double, false>;
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), shm, s, static_cast<const cx<double>*>(dhat),
+                       static_cast<const cx<double>*>(bhat), n, p->hp, cstride(p), n_bins, p->sums);
+  }
   return hip_check(hipGetLastError(), "pk reduce");
 }
 

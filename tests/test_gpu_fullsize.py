@@ -14,7 +14,8 @@ at a time, or a property that holds at any size:
     their weights and the gradient symbol is odd), and the density handed between
     cycles reproduces the density of a fresh deposit;
   * P(k) in 256 bins of a plane-wave field: bit-exact mode counts, mean |k| and
-    powers against the oracle's estimator of the sparse spectrum;
+    powers against the oracle's estimator of the sparse spectrum; the cross spectrum
+    of two such fields likewise;
   * B(k) on the benchmark's 64 triangle configurations of a field of plane waves
     that close triangles in several of them: the triple sums against the oracle's
     sum over the sparse modes, and the triangle counts of the smaller shells against
@@ -273,6 +274,25 @@ def test_pk_full_size_plane_waves(plan):
     del delta
     modes, vals = fourier.plane_wave_modes(WAVES, N)
     wk, wp, wc = estimators.power_spectrum_sparse(modes, vals, N, BOX, 256)
+    assert torch.equal(c.cpu(), wc)
+    assert rel_l2(k, wk) < 1e-12
+    assert rel_l2(p, wp) < F32_TOL
+
+
+def test_pk_cross_full_size_plane_waves(plan):
+    """Cross spectrum in 256 bins of two plane-wave fields on the same modes with other
+    amplitudes and phases (a phase lag of pi/2 on one of them: no cross power there)."""
+    dev = plan.device
+    wb = [(0.6 * a + 0.01, m, ph + (math.pi / 2 if i == 2 else 0.4 * i)) for i, (a, m, ph) in enumerate(WAVES)]
+    da = si.plane_wave_mesh(N, WAVES, device=dev, dtype=torch.float32)
+    db = si.plane_wave_mesh(N, wb, device=dev, dtype=torch.float32)
+    k, p, c = pm.pk_cross_estimate(plan, da, db, 256)
+    torch.cuda.synchronize()
+    del da, db
+    ma, va = fourier.plane_wave_modes(WAVES, N)
+    mb, vb = fourier.plane_wave_modes(wb, N)
+    assert torch.equal(ma, mb)
+    wk, wp, wc = estimators.power_spectrum_sparse(ma, va, N, BOX, 256, values_b=vb)
     assert torch.equal(c.cpu(), wc)
     assert rel_l2(k, wk) < 1e-12
     assert rel_l2(p, wp) < F32_TOL

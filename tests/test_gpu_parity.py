@@ -286,6 +286,93 @@ def test_pk_estimate(dt, n, nb):
 # ------------------------------------------------------------------- B(k) --
 
 @pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n,nb,batch", [(32, 16, 1), (64, 13, 1), (192, 96, 1), (32, 16, 2)])
+def test_pk_cross_estimate(dt, n, nb, batch):
+    dev = _dev()
+    box = 800.0
+    g = si.rng(40 + n)
+    a = torch.from_numpy(g.standard_normal((batch, n, n, n)))
+    b = 0.5 * a + torch.from_numpy(g.standard_normal((batch, n, n, n)))
+    plan = pm.Plan(n, box, dt, batch=batch)
+    ad, bd = a.to(dt).to(dev).squeeze(0).contiguous(), b.to(dt).to(dev).squeeze(0).contiguous()
+    k, p, c = pm.pk_cross_estimate(plan, ad, bd, nb)
+    torch.cuda.synchronize()
+    k, p, c = (t.reshape(batch, nb).cpu() for t in (k, p, c))
+    for i in range(batch):
+        wk, wp, wc = estimators.cross_power_spectrum(a[i].to(dt).double(), b[i].to(dt).double(), box, nb)
+        assert torch.equal(c[i], wc)
+        assert rel_l2(k[i], wk) < 1e-12
+        assert rel_l2(p[i], wp) < _tol(dt)
+    # the auto case equals pk_estimate
+    _, pa, _ = pm.pk_cross_estimate(plan, ad, ad, nb)
+    _, pp, _ = pm.pk_estimate(plan, ad, nb)
+    torch.cuda.synchronize()
+    assert rel_l2(pa, pp) < 1e-12
+
+
+def test_bias_fit_matches_oracle_and_rejects_short_input():
+    _dev()
+    g = si.rng(44)
+    k = torch.linspace(0.003, 0.15, 50, dtype=torch.float64)
+    cnt = torch.from_numpy(g.integers(1, 500, 50))
+    ratio = 1.2 + 3.0 * (4e-4 / k) ** 2 + 5.0 * k * k + torch.from_numpy(g.standard_normal(50)) * 0.02
+    for with_k2 in (True, False):
+        got = pm.bias_fit(k.tolist(), ratio.tolist(), cnt.tolist(), 0.08, 4e-4, 2, with_k2)
+        want = estimators.bias_fit(k, ratio, cnt, 0.08, 4e-4, 2, with_k2)
+        assert got == pytest.approx(want, rel=1e-9, abs=1e-12)
+    with pytest.raises(pm.PMError, match="bins"):
+        pm.bias_fit([0.01, 0.02, 0.03, 0.04], [1.0] * 4, [1] * 4, 0.08, 4e-4, 2, True)
+
+
+def test_bias_of_the_poisson_gauge_counting_density():
+    """Matter proxy of the scale-dependent bias fit: the Poisson-gauge counting density
+    of the partner set, against the Newtonian set, is biased by b1 = 1 and b1_GR =
+    3f + (9/2) Omega_m at linear order (eqs. physical_density and b1).  Noise made of
+    plane waves with one |n| per P(k) bin makes each bin's ratio exactly
+    1 + b1_GR calH^2/k^2 at that |n| (the bin's mean k averages over all its modes,
+    so the fit is given the waves' k), and the fit must return these values."""
+    dev = _dev()
+    n, box, a_i = 64, 30000.0, 0.1
+    nb = n // 2
+    waves = [(1.0, (1, 0, 0), 0.2), (1.0, (0, 2, 0), 0.4), (1.0, (3, 0, 0), 1.0), (1.0, (0, 4, 0), 2.0),
+             (1.0, (0, 0, 5), 0.3), (1.0, (3, 4, 0), 1.3), (1.0, (6, 0, 0), 0.8), (1.0, (2, 3, 6), 2.5),
+             (1.0, (0, 8, 0), 0.1), (1.0, (0, 0, 10), 1.7), (1.0, (6, 8, 0), 0.6), (1.0, (12, 0, 0), 2.9),
+             (1.0, (0, 0, 16), 1.4), (1.0, (20, 0, 0), 0.5)]
+    noise = si.plane_wave_mesh(n, waves, device=dev, dtype=torch.float64)
+    plan = pm.Plan(n, box, torch.float64)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_POWERLAW, amp=pm.power_law_amplitude(n, box, 1e-7), index=-2.0,
+                      a_init=a_i, a_norm=a_i, cosmo=pm.FIDUCIAL)
+    disp = plan.mesh(3)
+    pos, mom, pg, mg = (plan.particles() for _ in range(4))
+    pm.pm_ic_zeldovich(plan, noise, icp, disp, pos, mom)
+    pm.pm_ic_gauge(plan, noise, icp, disp, pos, mom, pg, mg)
+    dn, dg = pm.pm_deposit(plan, pos), pm.pm_deposit(plan, pg)
+    k, pnn, cnt = pm.pk_estimate(plan, dn, nb)
+    _, pgn, _ = pm.pk_cross_estimate(plan, dg, dn, nb)
+    torch.cuda.synchronize()
+    k, pnn, pgn, cnt = (t.cpu() for t in (k, pnn, pgn, cnt))
+    sel = pnn > 1e-6 * float(pnn.max())
+    # bin of each wave: (2b+1)^2 <= 4|n|^2 < (2b+3)^2 for n_bins = N/2
+    k_wave = {}
+    for _, m, _ in waves:
+        n2 = sum(v * v for v in m)
+        b = next(b for b in range(nb) if (2 * b + 1) ** 2 <= 4 * n2 < (2 * b + 3) ** 2)
+        k_wave[b] = math.sqrt(n2) * 2.0 * math.pi / box
+    bins = [b for b in range(nb) if bool(sel[b])]
+    assert bins == sorted(k_wave)
+    calh = a_i * pm.cosmo_hubble_e(a_i) / 2997.92458
+    ratio = pgn[sel] / pnn[sel]
+    kk = [k_wave[b] for b in bins]
+    b1, bgr, c2 = pm.bias_fit(kk, ratio.tolist(), cnt[sel].tolist(), 0.08, calh, 2, True)
+    c = ocm.Cosmo(n_s=0.965)
+    want = 3.0 * ocm.growth_f(c, a_i) + 4.5 * ocm.omega_m_of_a(c, a_i)
+    assert b1 == pytest.approx(1.0, abs=1e-4)
+    assert bgr == pytest.approx(want, rel=1e-4)
+    assert abs(c2) * max(kk) ** 2 < 1e-4
+    assert float(ratio[0]) > 10.0     # a strong large-scale effect in this horizon-size box
+
+
+@pytest.mark.parametrize("dt", DTYPES)
 def test_bk_estimate(dt):
     dev = _dev()
     n = 32

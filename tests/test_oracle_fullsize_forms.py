@@ -129,6 +129,22 @@ def test_power_spectrum_sparse_equals_dense(n, nb):
     assert torch.allclose(pk, wpk, rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("n,nb", [(16, 8), (32, 5)])
+def test_cross_spectrum_sparse_equals_dense(n, nb):
+    from oracle import estimators, fourier
+    wa = [(0.3, (1, 0, 0), 0.1), (0.2, (0, 5, 0), 1.0), (0.15, (3, -7, 2), 2.0), (0.1, (n // 2 - 1, 1, 3), 0.5)]
+    wb = [(0.7 * a, m, ph + 0.3 * i) for i, (a, m, ph) in enumerate(wa)]
+    ma, va = fourier.plane_wave_modes(wa, n)
+    mb, vb = fourier.plane_wave_modes(wb, n)
+    assert torch.equal(ma, mb)
+    km, pk, cnt = estimators.power_spectrum_sparse(ma, va, n, 700.0, nb, values_b=vb)
+    wkm, wpk, wcnt = estimators.cross_power_spectrum(_cosine_mesh(wa, n), _cosine_mesh(wb, n), 700.0, nb)
+    assert torch.equal(cnt, wcnt)
+    assert torch.allclose(km, wkm, rtol=1e-12)
+    assert torch.allclose(pk, wpk, rtol=1e-10, atol=1e-12 * float(wpk.abs().max()))
+    assert float(wpk.abs().max()) > 0
+
+
 def test_sparse_bispectrum_pieces_equal_dense_estimator():
     from oracle import estimators, fourier
     n, box = 16, 300.0
