@@ -242,6 +242,48 @@ def ic_leg(pm, plan, noise, icp):
     return out
 
 
+def gradient_study(pm, n=256, box=2000.0, steps=50, n_bins=128):
+    """Gradient-order study on the 256^3 configuration (EH98 ICs at a = 0.02, 50 log
+    steps to a = 1): P(k) of the Newtonian and Poisson-gauge runs with the first- and
+    second-order finite-difference gradients relative to the spectral runs, and of the
+    spectral Newtonian run combined with each variant's xi relative to the spectral
+    Poisson-gauge run, at selected bins."""
+    import torch
+    import synth_inputs as si
+    plan = pm.Plan(n, box, torch.float32)
+    noise = torch.from_numpy(si.white_noise(n, 11, dtype=np.float32)).to(plan.device)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=0.02,
+                      a_norm=1.0, cosmo=pm.FIDUCIAL)
+    disp = plan.mesh(3)
+    a_s = pm.sim.log_steps(0.02, 1.0, steps)
+    pk, runs = {}, {}
+    for name, g in (("spectral", pm.PM_GRAD_SPECTRAL), ("fd2", pm.PM_GRAD_FD2), ("fd1", pm.PM_GRAD_FD1)):
+        pos, mom, pg, mg = (plan.particles() for _ in range(4))
+        pm.pm_ic_zeldovich(plan, noise, icp, disp, pos, mom)
+        pm.pm_ic_gauge(plan, noise, icp, disp, pos, mom, pg, mg)
+        pm.sim.Run(plan, pos, mom, grad=g).leapfrog(a_s)
+        pm.sim.Run(plan, pg, mg, gauge=True, grad=g).leapfrog(a_s)
+        runs[name] = (pos, pg)
+        for tag, x in (("N", pos), ("GR", pg)):
+            k, p, _ = pm.pk_estimate(plan, pm.pm_deposit(plan, x), n_bins)
+            pk[name, tag] = p.cpu()
+    for name in ("fd2", "fd1"):
+        comb = pm.displacement_combine(runs[name][1], runs[name][0], n, runs["spectral"][0], n)
+        _, p, _ = pm.pk_estimate(plan, pm.pm_deposit(plan, comb), n_bins)
+        pk[name, "comb"] = p.cpu()
+    torch.cuda.synchronize()
+    sel = [0, 2, 5, 12, 20, 40, 60, n_bins - 1]
+    kk = k.cpu()
+    out = {"workload": f"{n}^3, L={box:g} Mpc/h, EH98 ICs a=0.02, {steps} log steps to a=1, P(k) in {n_bins} bins",
+           "k_h_per_Mpc": [round(float(kk[i]), 4) for i in sel]}
+    for name in ("fd1", "fd2"):
+        for tag, ref in (("N", ("spectral", "N")), ("GR", ("spectral", "GR")), ("comb", ("spectral", "GR"))):
+            r = pk[name, tag] / pk[ref] - 1.0
+            out[f"{name}_{tag}_rel"] = [round(float(r[i]), 4) for i in sel]
+    del runs, plan
+    return out
+
+
 def adjoint_small(pm, n=128, box=1000.0, n_steps=20, ckpt=5, n_bins=64):
     """Adjoint/forward time of the differentiable configuration: 128^3, L = 1000 Mpc/h,
     20 log steps a = 0.05 -> 1, P(k) in 64 bins, checkpoints every 5 cycles."""
@@ -486,6 +528,8 @@ def main():
     del noise, plan
     if not args.no_extras:
         torch.cuda.empty_cache()
+        print("[bench] gradient-order study at 256^3", file=sys.stderr, flush=True)
+        out["gradient_order_study"] = gradient_study(pm)
         print("[bench] 128^3 adjoint configuration", file=sys.stderr, flush=True)
         out["adjoint_128"] = adjoint_small(pm)
         print("[bench] 64-box ensemble", file=sys.stderr, flush=True)

@@ -674,6 +674,57 @@ def test_combined_pm_and_combined_linear_shift_agree_in_the_linear_regime():
     assert float(pks[2][0]) < 0.05 * float(pks[0][0])
 
 
+def _gradient_variant_runs(n, box, steps, nb):
+    """P(k) of the Newtonian and Poisson-gauge runs with each gradient symbol, and of
+    the spectral Newtonian run combined with each variant's xi (eq. combined)."""
+    dev = _dev()
+    plan = pm.Plan(n, box, torch.float32)
+    noise = torch.from_numpy(si.white_noise(n, 11, dtype=np.float32)).to(dev)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=0.02,
+                      a_norm=1.0, cosmo=pm.FIDUCIAL)
+    disp = plan.mesh(3)
+    a_s = pm.sim.log_steps(0.02, 1.0, steps)
+    pk, runs = {}, {}
+    for name, g in (("spectral", pm.PM_GRAD_SPECTRAL), ("fd2", pm.PM_GRAD_FD2), ("fd1", pm.PM_GRAD_FD1)):
+        pos, mom, pg, mg = (plan.particles() for _ in range(4))
+        pm.pm_ic_zeldovich(plan, noise, icp, disp, pos, mom)
+        pm.pm_ic_gauge(plan, noise, icp, disp, pos, mom, pg, mg)
+        pm.sim.Run(plan, pos, mom, grad=g).leapfrog(a_s)
+        pm.sim.Run(plan, pg, mg, gauge=True, grad=g).leapfrog(a_s)
+        runs[name] = (pos, pg)
+        for tag, x in (("N", pos), ("GR", pg)):
+            k, p, _ = pm.pk_estimate(plan, pm.pm_deposit(plan, x), nb)
+            pk[name, tag] = p.cpu()
+    for name in ("fd2", "fd1"):
+        xn, xg = runs[name]
+        _, p, _ = pm.pk_estimate(plan, pm.pm_deposit(plan, pm.displacement_combine(xg, xn, n, runs["spectral"][0], n)), nb)
+        pk[name, "comb"] = p.cpu()
+    torch.cuda.synchronize()
+    return k.cpu(), pk
+
+
+def test_gradient_order_study():
+    """Finite-difference gradients (first-order one-sided, second-order central) lose
+    power against the spectral gradient, little on the largest scales and more towards
+    the mesh scale (Sec. 4.1 discusses the loss with gevolution's gradients).  The same
+    loss hits the relativistic and the Newtonian run, so it cancels in xi: the spectral
+    Newtonian run plus xi from either finite-difference pair reproduces the spectral
+    relativistic run far better than that pair's relativistic run does."""
+    k, pk = _gradient_variant_runs(128, 8000.0, 50, 64)
+    ref_n, ref_gr = pk["spectral", "N"], pk["spectral", "GR"]
+    for name in ("fd1", "fd2"):
+        d_n = pk[name, "N"] / ref_n - 1.0
+        d_gr = pk[name, "GR"] / ref_gr - 1.0
+        d_comb = pk[name, "comb"] / ref_gr - 1.0
+        assert float(d_n[:3].abs().max()) < 0.02          # largest scales barely affected
+        assert float(d_n[16:48].max()) < -0.1               # towards the mesh scale: a clear deficit
+        assert float(d_gr.abs().max()) > 0.2
+        assert float(d_comb.abs().max()) < 0.01             # the loss cancels in xi
+        assert float(d_comb.abs().max()) < 0.05 * float(d_gr.abs().max())
+    # the gauge itself is a large-scale effect here (L = 8000 Mpc/h): tens of per cent in the first bin
+    assert float(ref_gr[0] / ref_n[0]) > 1.3
+
+
 # ------------------------------------------- density handed to the next cycle --
 
 @pytest.mark.parametrize("dt,n,amp", [(torch.float32, 128, 0.8), (torch.float32, 64, 6.0), (torch.float64, 32, 0.8)])
