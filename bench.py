@@ -332,15 +332,28 @@ def adjoint_small(pm, n=128, box=1000.0, n_steps=20, ckpt=5, n_bins=64):
 
 def ensemble_leg(pm):
     """64-box ensemble (16 x 64^3, 24 x 128^3, 16 x 192^3, 8 x 256^3; 30 log steps
-    a = 0.02 -> 1; per-box P(k)): one captured graph over the batched groups vs
-    the same boxes run one by one on single-box plans with eager launches."""
+    a = 0.02 -> 1; per-box P(k)): one captured graph over the batched groups (FFT
+    launch shapes autotuned per group; also timed with the built-in shapes) vs the
+    same boxes run one by one on single-box plans (also autotuned) with eager
+    launches."""
     import torch
     import synth_inputs as si
     from paper_2404_02783_amd import ensemble
     dev = torch.device("cuda:0")
     groups = ensemble.default_groups()
     noise_fn = lambda n, s: si.white_noise(n, s)  # noqa: E731
+    from paper_2404_02783_amd import tuning
+    # the graph with the built-in FFT launch shapes, then with autotuned ones
     ens = ensemble.Ensemble(groups, noise_fn, 0.02, 1.0, 30, torch.float32, dev)
+    ens.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.replay()
+    torch.cuda.synchronize()
+    t_graph_builtin = time.perf_counter() - t0
+    del ens
+    ens = ensemble.Ensemble(groups, noise_fn, 0.02, 1.0, 30, torch.float32, dev, autotune=True)
+    shapes = {f"{st.group.n}^3 x {st.plan.batch}": st.tuning[0] for st in ens.states}
     ens.capture()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -353,6 +366,8 @@ def ensemble_leg(pm):
     t_eager = time.perf_counter() - t0
     pk_batched = [o[1].clone() for o in ens.power_spectra()]
     plans = {(g.n, g.box): pm.Plan(g.n, g.box, torch.float32, dev) for g in groups}
+    for pl in plans.values():
+        tuning.tune(pl)
     noises = {s: st.noise[i] for st in ens.states for i, s in enumerate(st.group.seeds)}
     one = [ensemble.Group(g.n, g.box, g.seeds[:1]) for g in groups]
     ensemble.run_sequential(one, noise_fn, 0.02, 1.0, 30, torch.float32, dev, plans, noises)  # warm
@@ -363,13 +378,14 @@ def ensemble_leg(pm):
     t_seq = time.perf_counter() - t0
     worst = max(float(((a - b).abs() / b.abs().clamp_min(1e-30)).max()) for a, b in zip(pk_batched, pk_seq))
     out = {"boxes": sum(len(g.seeds) for g in groups), "graph_s": round(t_graph, 4),
+           "graph_builtin_fft_shapes_s": round(t_graph_builtin, 4), "fft_shapes_autotuned": shapes,
            "batched_eager_s": round(t_eager, 4), "sequential_s": round(t_seq, 4),
            "speedup_graph_vs_sequential": round(t_seq / t_graph, 2),
            "max_rel_pk_diff_batched_vs_sequential": worst}
     del ens, plans, noises
     # the same comparison for 64 small boxes only (64^3, L = 500 Mpc/h), where launches dominate
     small = [ensemble.Group(64, 500.0, list(range(200, 264)))]
-    ens = ensemble.Ensemble(small, noise_fn, 0.02, 1.0, 30, torch.float32, dev)
+    ens = ensemble.Ensemble(small, noise_fn, 0.02, 1.0, 30, torch.float32, dev, autotune=True)
     ens.capture()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -377,6 +393,7 @@ def ensemble_leg(pm):
     torch.cuda.synchronize()
     ts_graph = time.perf_counter() - t0
     plans = {(64, 500.0): pm.Plan(64, 500.0, torch.float32, dev)}
+    tuning.tune(plans[(64, 500.0)])
     noises = {s: ens.states[0].noise[i] for i, s in enumerate(small[0].seeds)}
     ensemble.run_sequential([ensemble.Group(64, 500.0, [200])], noise_fn, 0.02, 1.0, 30, torch.float32, dev, plans,
                             noises)
@@ -440,6 +457,12 @@ def main():
     del disp
     torch.cuda.synchronize()
     print(f"[bench] initial conditions ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    # FFT launch shapes of the 1024^3 plan, measured once before the run (setup, untimed)
+    scratch = plan.mesh()
+    tuned, tuned_ms = pm.pm_plan_autotune(plan, reps=3, use_cache=False, mesh_scratch=scratch)
+    del scratch
+    print(f"[bench] FFT launch shapes {tuned} ({[round(m, 3) for m in tuned_ms]} ms)", file=sys.stderr, flush=True)
 
     total = max(50, args.warmup + args.steps)
     a_s = pm.sim.log_steps(0.02, 1.0, total)
@@ -505,6 +528,7 @@ def main():
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBps": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "kernels": kernels,
+        "fft_tuning": {"slots": list(pm.TUNING_SLOTS), "shapes": tuned, "best_ms": [round(m, 4) for m in tuned_ms]},
         "adjoint_forward_ratio": None,
     }
     if not args.no_extras:

@@ -179,6 +179,31 @@ int pm_profile_enable(pm_plan* plan, int on);
  * written, or a negative error code (PM_ERR_ARG if profiling is off). */
 int pm_profile_read(pm_plan* plan, int n_max, char* names, double* ms, int64_t* count);
 
+/* ------------------------------------------------- FFT launch-shape tuning --- */
+/* Not in the paper (the transforms are this library's).  Four tuning slots pick the
+ * launch shape of the FFT passes of a plan: 0 columns per workgroup of the plain
+ * column passes, 1 of the fused solve pass, 2 rows per workgroup of the r2c rows pass,
+ * 3 of the c2r rows pass.  Every shape computes the same numbers (each column or row
+ * is transformed by the same arithmetic), only the speed differs. */
+
+/* Writes up to `cap` allowed shapes of slot `kind` (powers of two within 256 threads
+ * and 64 KiB of LDS per workgroup, the built-in choice always included), ascending, to
+ * host `out`; returns how many there are (may exceed cap), or a negative error. */
+int pm_plan_tuning_candidates(const pm_plan* plan, int kind, int* out, int cap);
+/* Host int[4]: the shapes the plan uses now (the built-in choice where none is set). */
+int pm_plan_get_tuning(const pm_plan* plan, int* shapes);
+/* Host int[4]: sets the shapes (0 = built-in choice); PM_ERR_ARG, and nothing changed,
+ * if any is not an allowed shape of its slot. */
+int pm_plan_set_tuning(pm_plan* plan, const int* shapes);
+/* Measures every allowed shape of every slot on this device (reps timed launches of
+ * the pass after one warm launch, HIP events on `stream`; waits for them) and keeps the
+ * fastest.  mesh_scratch: [boxes][N^3] real of the plan's dtype (overwritten); the
+ * plan's workspace is overwritten.  The choice is cached per (device, N, dtype, boxes)
+ * for the process; with use_cache non-zero a cached choice is applied without
+ * measuring.  best_ms: optional host double[4], the fastest time per launch of each
+ * slot (-1 when taken from the cache).  A setup call: it synchronises the stream. */
+int pm_plan_autotune(pm_plan* plan, void* mesh_scratch, int reps, int use_cache, double* best_ms, void* stream);
+
 /* ----------------------------------------------------------- hot path ------- */
 
 /* CIC counting density (Sec. 4: counting density of a cloud-in-cell assignment):

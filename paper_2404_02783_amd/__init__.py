@@ -19,7 +19,8 @@ __all__ = [
     "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "displacement_add", "pm_xi_linear",
     "pk_estimate", "pk_cross_estimate", "bias_fit", "bk_estimate",
     "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
-    "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_gauge", "pm_noise_fix", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
+    "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_gauge", "pm_noise_fix",
+    "pm_plan_tuning_candidates", "pm_plan_get_tuning", "pm_plan_set_tuning", "pm_plan_autotune", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
     "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH",
     "PM_F32", "PM_F64", "PM_NEWTON", "PM_POISSON_GAUGE", "PM_GRAD_SPECTRAL", "PM_GRAD_FD2", "PM_GRAD_FD1",
@@ -104,6 +105,10 @@ def _declare(l):
         "pm_ic_zeldovich": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_2lpt": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "pm_noise_fix": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_void_p]),
+        "pm_plan_tuning_candidates": (_c_int, [_c_void_p, _c_int, P(_c_int), _c_int]),
+        "pm_plan_get_tuning": (_c_int, [_c_void_p, P(_c_int)]),
+        "pm_plan_set_tuning": (_c_int, [_c_void_p, P(_c_int)]),
+        "pm_plan_autotune": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_int, P(_c_double), _c_void_p]),
         "pm_ic_zeldovich_adjoint": (_c_int, [_c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                                              _c_void_p]),
         "pm_noise_truncate": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
@@ -408,6 +413,41 @@ def pm_ic_2lpt(plan: Plan, noise, ic: ICParams, disp_scratch, pos, mom):
     _check(lib().pm_ic_2lpt(plan.handle, _ptr(noise, plan.dtype, "noise"), ctypes.byref(ic),
                             _ptr(disp_scratch, plan.dtype, "disp_scratch"), _ptr(pos, plan.dtype, "pos"),
                             _ptr(mom, plan.dtype, "mom"), _stream()))
+
+
+TUNING_SLOTS = ("cols", "solve", "r2c_rows", "c2r_rows")
+
+
+def pm_plan_tuning_candidates(plan: Plan, kind: int):
+    buf = (_c_int * 16)()
+    n = lib().pm_plan_tuning_candidates(plan.handle, int(kind), buf, 16)
+    if n < 0:
+        _check(n)
+    return [buf[i] for i in range(min(n, 16))]
+
+
+def pm_plan_get_tuning(plan: Plan):
+    buf = (_c_int * 4)()
+    _check(lib().pm_plan_get_tuning(plan.handle, buf))
+    return [buf[i] for i in range(4)]
+
+
+def pm_plan_set_tuning(plan: Plan, shapes):
+    vals = [int(v) for v in shapes]
+    if len(vals) != 4:
+        raise PMError(PM_ERR_ARG, "four tuning shapes expected")
+    _check(lib().pm_plan_set_tuning(plan.handle, (_c_int * 4)(*vals)))
+
+
+def pm_plan_autotune(plan: Plan, reps: int = 3, use_cache: bool = True, mesh_scratch=None):
+    """Times every allowed launch shape of the plan's FFT passes and keeps the fastest;
+    returns (shapes, best ms per launch or -1 where taken from the process cache)."""
+    mesh_scratch = plan.mesh() if mesh_scratch is None else mesh_scratch
+    _need(mesh_scratch, plan.batch * plan.n ** 3, "mesh_scratch")
+    ms = (_c_double * 4)()
+    _check(lib().pm_plan_autotune(plan.handle, _ptr(mesh_scratch, plan.dtype, "mesh_scratch"), int(reps),
+                                  int(bool(use_cache)), ms, _stream()))
+    return pm_plan_get_tuning(plan), [ms[i] for i in range(4)]
 
 
 def pm_noise_fix(plan: Plan, noise, pair_mode: int = 0, out=None):

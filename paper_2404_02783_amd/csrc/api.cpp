@@ -7,7 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "pm_common.h"
@@ -215,6 +218,131 @@ int pm_plan_create_batch(pm_plan** out, int n_mesh, double box_mpch, int dtype, 
     return rc;
   }
   *out = p;
+  return PM_OK;
+}
+
+// ------------------------------------------------------------------ tuning --
+
+namespace {
+std::mutex g_tune_mu;
+// (device, N, dtype, boxes) -> launch shapes picked by a measurement in this process
+std::map<std::tuple<int, int, int, int>, std::vector<int>> g_tune_cache;
+
+bool tune_value_ok(const pm_plan* p, int kind, int v) {
+  if (v == 0) return true;
+  int c[16];
+  const int nc = std::min(fft_tune_candidates(p, kind, c, 16), 16);
+  for (int i = 0; i < nc; ++i)
+    if (c[i] == v) return true;
+  return false;
+}
+
+// One timed instance of the pass of tuning slot `kind` on the plan's workspace.
+int tune_run(pm_plan* p, int kind, void* mesh, hipStream_t s) {
+  switch (kind) {
+    case 0:
+      PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, -1, p->nb, cstride(p), s));
+      return fft_pass_cols(p, cbuf(p, 0), 0, 1, p->nb, cstride(p), s);
+    case 1: {
+      pm_solve_params sp{};
+      sp.kind = PM_NEWTON;
+      sp.grad = PM_GRAD_SPECTRAL;
+      sp.omega_m = 0.3;
+      return fft_pass_solve(p, &sp, nullptr, s);
+    }
+    case 2:
+      return fft_pass_rows_r2c(p, p->nb, mesh, cbuf(p, 0), s);
+    default:
+      return fft_pass_rows_c2r(p, p->nb, cbuf(p, 0), cstride(p), mesh, s);
+  }
+}
+}  // namespace
+
+int pm_plan_tuning_candidates(const pm_plan* p, int kind, int* out, int cap) {
+  PM_TRY(check_plan(p));
+  if (kind < 0 || kind > 3 || cap < 0 || (cap > 0 && !out)) return set_error(PM_ERR_ARG, "bad tuning slot or buffer");
+  return fft_tune_candidates(p, kind, out, cap);
+}
+
+int pm_plan_get_tuning(const pm_plan* p, int* shapes) {
+  PM_TRY(check_plan(p));
+  if (!shapes) return set_error(PM_ERR_ARG, "pm_plan_get_tuning: null pointer");
+  for (int k = 0; k < 4; ++k) shapes[k] = p->tune[k] > 0 ? p->tune[k] : fft_tune_default(p, k);
+  return PM_OK;
+}
+
+int pm_plan_set_tuning(pm_plan* p, const int* shapes) {
+  PM_TRY(check_plan(p));
+  if (!shapes) return set_error(PM_ERR_ARG, "pm_plan_set_tuning: null pointer");
+  for (int k = 0; k < 4; ++k)
+    if (!tune_value_ok(p, k, shapes[k]))
+      return set_error(PM_ERR_ARG, "pm_plan_set_tuning: %d is not a launch shape of slot %d", shapes[k], k);
+  for (int k = 0; k < 4; ++k) p->tune[k] = shapes[k];
+  return PM_OK;
+}
+
+int pm_plan_autotune(pm_plan* p, void* mesh_scratch, int reps, int use_cache, double* best_ms, void* stream) {
+  PM_TRY(check_plan(p));
+  if (!mesh_scratch) return set_error(PM_ERR_ARG, "pm_plan_autotune: null scratch mesh");
+  if (reps < 1 || reps > 1000) return set_error(PM_ERR_ARG, "pm_plan_autotune: reps %d out of range", reps);
+  drop_density(p);
+  const auto key = std::make_tuple(p->device, p->n, p->dtype, p->nb);
+  if (use_cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      for (int k = 0; k < 4; ++k) p->tune[k] = it->second[k];
+      if (best_ms)
+        for (int k = 0; k < 4; ++k) best_ms[k] = -1.0;
+      return PM_OK;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // defined contents: a zero mesh and its (zero) spectrum
+  PM_TRY(launch_fill(p, mesh_scratch, (int64_t)p->nb * p->n * p->n * p->n, 0.0, s));
+  PM_TRY(fft_pass_rows_r2c(p, p->nb, mesh_scratch, cbuf(p, 0), s));
+  hipEvent_t e0, e1;
+  PM_TRY(hip_check(hipEventCreate(&e0), "autotune event"));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_error(PM_ERR_HIP, "autotune event");
+  }
+  int rc = PM_OK;
+  for (int k = 0; k < 4 && rc == PM_OK; ++k) {
+    int c[16];
+    const int nc = std::min(fft_tune_candidates(p, k, c, 16), 16);
+    int best = 0;
+    float best_t = 0.0f;
+    for (int i = 0; i < nc && rc == PM_OK; ++i) {
+      p->tune[k] = c[i];
+      rc = tune_run(p, k, mesh_scratch, s);  // warm
+      if (rc) break;
+      rc = hip_check(hipEventRecord(e0, s), "autotune record");
+      for (int r = 0; r < reps && rc == PM_OK; ++r) rc = tune_run(p, k, mesh_scratch, s);
+      if (rc) break;
+      rc = hip_check(hipEventRecord(e1, s), "autotune record");
+      if (rc) break;
+      rc = hip_check(hipEventSynchronize(e1), "autotune sync");
+      if (rc) break;
+      float ms = 0.0f;
+      rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune elapsed");
+      if (rc) break;
+      if (best == 0 || ms < best_t) {
+        best = c[i];
+        best_t = ms;
+      }
+    }
+    p->tune[k] = best;
+    if (best_ms) best_ms[k] = best_t / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    for (int k = 0; k < 4; ++k) p->tune[k] = 0;
+    return rc;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = std::vector<int>(p->tune, p->tune + 4);
   return PM_OK;
 }
 

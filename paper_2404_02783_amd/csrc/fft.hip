@@ -37,24 +37,24 @@ void launch_cols_t(cx<T>* data, const ColArgs& g, int dir, int ncomp, int outer,
 }
 
 template <typename T, int L1, int L2>
-void launch_r2c_t(const T* in, cx<T>* out, const RowArgs& g, int ncomp, const cx<T>* tw, hipStream_t s) {
+void launch_r2c_t(const T* in, cx<T>* out, const RowArgs& g, int ncomp, const cx<T>* tw, int rows, hipStream_t s) {
   constexpr int M = L1 * L2;
   constexpr int TPC = L1 > L2 ? L1 : L2;
   constexpr int XS = L1 * (L2 + 1);
   constexpr int RS = XS > M ? XS : M;
-  const int R = 256 / TPC;
+  const int R = rows > 0 ? rows : 256 / TPC;
   dim3 grid((unsigned)((g.nrows + R - 1) / R), (unsigned)ncomp);
   dim3 block((unsigned)(R * TPC));
   hipLaunchKernelGGL((k_fft_rows_r2c<T, L1, L2>), grid, block, (size_t)R * RS * sizeof(cx<T>), s, in, out, g, tw);
 }
 
 template <typename T, int L1, int L2>
-void launch_c2r_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx<T>* tw, hipStream_t s) {
+void launch_c2r_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx<T>* tw, int rows, hipStream_t s) {
   constexpr int M = L1 * L2;
   constexpr int TPC = L1 > L2 ? L1 : L2;
   constexpr int XS = L1 * (L2 + 1);
   (void)M;
-  const int R = 256 / TPC;
+  const int R = rows > 0 ? rows : 256 / TPC;
   dim3 grid((unsigned)((g.nrows + R - 1) / R), (unsigned)ncomp);
   dim3 block((unsigned)(R * TPC));
   hipLaunchKernelGGL((k_fft_rows_c2r<T, L1, L2>), grid, block, (size_t)R * XS * sizeof(cx<T>), s, in, out, g, tw);
@@ -110,7 +110,7 @@ ColArgs col_args(int n, int hp, int axis, int bcols) {
 template <typename T>
 int cols_t(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s) {
   const int n = p->n;
-  ColArgs g = col_args(n, p->hp, axis, cols_per_block<T>(n));
+  ColArgs g = col_args(n, p->hp, axis, p->tune[0] > 0 ? p->tune[0] : cols_per_block<T>(n));
   g.comp_stride = comp_stride;
   cx<T>* d = static_cast<cx<T>*>(data);
   const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
@@ -128,7 +128,8 @@ int r2c_t(const pm_plan* p, int count, const void* in, void* out, hipStream_t s)
   g.n = n;
   g.hs = p->hp;
   const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
-  PM_DISPATCH_LEN(n / 2, launch_r2c_t, static_cast<const T*>(in), static_cast<cx<T>*>(out), g, count, tw, s)
+  PM_DISPATCH_LEN(n / 2, launch_r2c_t, static_cast<const T*>(in), static_cast<cx<T>*>(out), g, count, tw, p->tune[2],
+                  s)
   return hip_check(hipGetLastError(), "fft r2c rows");
 }
 
@@ -142,14 +143,15 @@ int c2r_t(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* ou
   g.n = n;
   g.hs = p->hp;
   const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
-  PM_DISPATCH_LEN(n / 2, launch_c2r_t, static_cast<const cx<T>*>(in), static_cast<T*>(out), g, ncomp, tw, s)
+  PM_DISPATCH_LEN(n / 2, launch_c2r_t, static_cast<const cx<T>*>(in), static_cast<T*>(out), g, ncomp, tw, p->tune[3],
+                  s)
   return hip_check(hipGetLastError(), "fft c2r rows");
 }
 
 template <typename T>
 int solve_t(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t s) {
   const int n = p->n;
-  ColArgs g = col_args(n, p->hp, 0, cols_per_block<T>(n));
+  ColArgs g = col_args(n, p->hp, 0, p->tune[1] > 0 ? p->tune[1] : cols_per_block<T>(n));
   SolveArgs a;
   const double n3 = (double)n * n * n;
   a.n = n;
@@ -172,7 +174,58 @@ int solve_t(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t 
   return hip_check(hipGetLastError(), "fft solve pass");
 }
 
+// Launch shapes of tuning slot `kind` that stay within the kernels' limits: at most
+// 256 threads per workgroup (their launch bounds) and 64 KiB of LDS, columns per
+// workgroup no more than the next power of two above the N/2+1 columns.
+template <typename T>
+int tune_candidates_t(const pm_plan* p, int kind, int* out, int cap) {
+  const int n = p->n;
+  const size_t cxs = sizeof(cx<T>);
+  int cnt = 0;
+  auto push = [&](int v) {
+    if (cnt < cap) out[cnt] = v;
+    ++cnt;
+  };
+  if (kind == 0 || kind == 1) {
+    const Shape sh = shape_for(n);
+    const int tpc = std::max(sh.L1, sh.L2);
+    const int h = n / 2 + 1;
+    int colcap = 1;
+    while (colcap < h) colcap <<= 1;
+    for (int b = 1; b * tpc <= 256 && b <= colcap; b <<= 1)
+      if ((size_t)sh.L1 * sh.L2 * b * cxs <= 65536) push(b);
+  } else {
+    const Shape sh = shape_for(n / 2);
+    const int tpc = std::max(sh.L1, sh.L2);
+    const int xs = sh.L1 * (sh.L2 + 1);
+    const int rs = kind == 2 ? std::max(xs, sh.L) : xs;
+    const int def = 256 / tpc;  // the built-in choice (not always a power of two)
+    bool def_done = false;
+    for (int r = 1; r * tpc <= 256; r <<= 1) {
+      if (!def_done && def < r) {
+        push(def);
+        def_done = true;
+      }
+      if (r == def) def_done = true;
+      if ((size_t)r * rs * cxs <= 65536 || r == def) push(r);
+    }
+    if (!def_done) push(def);
+  }
+  return cnt;
+}
+
 }  // namespace
+
+int fft_tune_default(const pm_plan* p, int kind) {
+  if (kind == 0 || kind == 1) return p->dtype == PM_F32 ? cols_per_block<float>(p->n) : cols_per_block<double>(p->n);
+  const Shape sh = shape_for(p->n / 2);
+  return 256 / std::max(sh.L1, sh.L2);
+}
+
+int fft_tune_candidates(const pm_plan* p, int kind, int* out, int cap) {
+  if (kind < 0 || kind > 3) return 0;
+  return p->dtype == PM_F32 ? tune_candidates_t<float>(p, kind, out, cap) : tune_candidates_t<double>(p, kind, out, cap);
+}
 
 int fft_pass_cols(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s) {
   const int kind = axis == 1 ? (dir < 0 ? PK_COLS_FWD_AXIS1 : PK_COLS_INV_AXIS1)

@@ -59,6 +59,10 @@ struct pm_plan {
   const void* dens_pos;
   int64_t dens_np;
   bool dens_valid;
+  // launch shapes of the FFT passes picked by pm_plan_autotune (0: built-in choice):
+  // [0] columns per workgroup of the plain column passes, [1] of the fused solve pass,
+  // [2] rows per workgroup of the r2c rows pass, [3] of the c2r rows pass
+  int tune[4];
 };
 
 namespace pm {
@@ -127,6 +131,12 @@ int launch_lpt2_source(const pm_plan* p, const void* h, void* s_out, int pass, h
 // pos = wrap(q + 1/2 + psi1 + psi2), mom = f1 psi1 + f2 psi2 (psi2 may alias mom).
 int launch_ic_lattice2(const pm_plan* p, const void* psi1, const void* psi2, void* pos, void* mom, double f1,
                        double f2, hipStream_t s);
+
+// Launch shapes the FFT passes accept for tuning slot `kind` (see pm_plan::tune),
+// ascending; returns their number (at most `cap` written).  The built-in choice is
+// always among them.
+int fft_tune_candidates(const pm_plan* p, int kind, int* out, int cap);
+int fft_tune_default(const pm_plan* p, int kind);
 
 // ------------------------------------------------------------ spectra.hip --
 struct IcSymbol {

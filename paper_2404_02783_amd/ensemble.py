@@ -21,6 +21,7 @@ from . import (FIDUCIAL, ICParams, PM_PK_EH98, PM_STEP_DENSITY_READY, PM_STEP_DE
                kdk_factors, newton_params, pk_estimate, pm_deposit, pm_ic_zeldovich, pm_noise_fix, pm_step,
                power_eh98_amplitude)
 from .sim import log_steps
+from .tuning import tune
 
 __all__ = ["Group", "Ensemble", "default_groups", "schedule", "run_sequential"]
 
@@ -58,6 +59,7 @@ class _State:
     disp: torch.Tensor
     delta: torch.Tensor
     out: tuple = field(default=None)
+    tuning: tuple = field(default=None)
 
 
 def schedule(a_start=0.02, a_end=1.0, n_steps=30, n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL):
@@ -81,10 +83,13 @@ class Ensemble:
 
     ``paired_fixed``: every seed gives two boxes, 2j and 2j + 1, run from the
     paired-and-fixed noise of that seed (fixed mode amplitudes; the partner's field
-    negated); ``paired_power_spectra`` averages each pair."""
+    negated); ``paired_power_spectra`` averages each pair.  ``autotune``: each size
+    group's FFT launch shapes are measured for its batch (or read from
+    ``tuning_cache``, a JSON file) before the run."""
 
     def __init__(self, groups, noise_fn, a_start=0.02, a_end=1.0, n_steps=30, dtype=torch.float32, device=None,
-                 n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL, paired_fixed: bool = False):
+                 n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL, paired_fixed: bool = False, autotune: bool = False,
+                 tuning_cache: str | None = None):
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.dtype = dtype
         self.paired_fixed = paired_fixed
@@ -97,8 +102,10 @@ class Ensemble:
             noise = noise.to(dtype).to(self.device).contiguous()
             if paired_fixed:
                 pm_noise_fix(plan, noise, 2, out=noise)
-            self.states.append(_State(g, plan, noise, plan.particles(), plan.particles(), plan.mesh(3),
-                                      plan.mesh(3), plan.mesh()))
+            st = _State(g, plan, noise, plan.particles(), plan.particles(), plan.mesh(3), plan.mesh(3), plan.mesh())
+            if autotune:   # FFT launch shapes measured for this group's batch (delta as scratch)
+                st.tuning = tune(plan, tuning_cache, mesh_scratch=st.delta)
+            self.states.append(st)
         self.graph = None
 
     def run(self):
