@@ -138,12 +138,14 @@ def adjoint_ratio(pm, plan, noise, icp, n_cycles: int, ckpt: int, n_bins: int):
     return t1 - t0, t2 - t1, prof
 
 
-def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
+def estimators_and_combination(pm, plan, pos, fine_noise, a_end, n_bins=256):
     """Timings of the estimator and combination calls of the displacement-combination
     configuration on the final 1024^3 positions: deposit + P(k) in 256 bins, B(k)
     on 64 triangles (32 equilateral k = m*16 k_f, 32 squeezed with k3 = 4 k_f; shell
     width 2 k_f), the combination of a 256^3 pair into the 1024^3 run, and the
-    combination with the linear shift at 256^3 in place of the pair."""
+    combination with the linear shift at 256^3 in place of the pair; then P(k) and
+    B(k) of the two combinations against each other and against the Newtonian run
+    (the comparison of the paper's power-spectrum and bispectrum figures)."""
     import torch
     import synth_inputs as si
     out = {}
@@ -168,7 +170,7 @@ def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
     t2 = time.perf_counter()
     out["bk_first_call_ms"] = round((t1 - t0) * 1e3, 1)
     out["bk_cached_counts_ms"] = round((t2 - t1) * 1e3, 1)
-    del shell_ws, bk, bk2, ntri
+    del bk
     # combination: a coarse 256^3 Newtonian/Poisson-gauge pair (L = 4000 Mpc/h, 50 log steps)
     nc = 256
     cplan = pm.Plan(nc, plan.box, plan.dtype, plan.device)
@@ -195,6 +197,14 @@ def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
     dt = time.perf_counter() - t0
     out["combine_ms"] = round(dt * 1e3, 2)
     out["combine_GBps_alg"] = round(24 * n ** 3 / dt / 1e9, 1)  # read x_fine, write x_out
+    stats = {"newton": (pk, bk2)}
+
+    def statistics(x):
+        d = pm.pm_deposit(plan, x)
+        p = pm.pk_estimate(plan, d, n_bins)[1]
+        b, _ = pm.bk_estimate(plan, d, centres, 2.0, tris, shell_ws=shell_ws, ntri_known=ntri)
+        return p, b
+    stats["combined"] = statistics(x_out)
     # combination with linear theory: the linear Poisson-gauge shift at a = 1 from the
     # coarse noise (one k-space pass and its inverse transform), added to the fine run
     xi = cplan.mesh(3)
@@ -210,6 +220,22 @@ def estimators_and_combination(pm, plan, pos, fine_noise, n_bins=256):
     out["xi_linear_256_ms"] = round((t1 - t0) * 1e3, 2)
     out["add_linear_shift_ms"] = round((t2 - t1) * 1e3, 2)
     del xi
+    stats["combined_1lpt"] = statistics(x_out)
+    pb = [0, 1, 2, 3, 5, 8, 16, 64]
+    tb = [0, 1, 3, 7, 32, 33, 35, 39]   # equilateral m = 1, 2, 4, 8 and squeezed m = 1, 2, 4, 8
+
+    def rel(a, b, idx):
+        return [round(float(a[i] / b[i] - 1.0), 5) for i in idx]
+    (p_n, b_n), (p_c, b_c), (p_l, b_l) = stats["newton"], stats["combined"], stats["combined_1lpt"]
+    out["combined_vs_linear"] = {
+        "a_end": round(a_end, 4),
+        "k_h_per_Mpc": [round(float(k[i]), 5) for i in pb],
+        "pk_combined_over_newton_minus_1": rel(p_c, p_n, pb),
+        "pk_combined_1lpt_over_combined_minus_1": rel(p_l, p_c, pb),
+        "bk_triangles": ["equilateral 16,32,64,128 k_f", "squeezed k1=k2=16,32,64,128 k_f, k3=4 k_f"],
+        "bk_combined_over_newton_minus_1": rel(b_c, b_n, tb),
+        "bk_combined_1lpt_over_combined_minus_1": rel(b_l, b_c, tb)}
+    del stats, shell_ws, bk2, ntri
     # cross spectrum of the combined field with the fine run's (256 bins)
     delta_c = pm.pm_deposit(plan, x_out)
     torch.cuda.synchronize()
@@ -533,7 +559,8 @@ def main():
     }
     if not args.no_extras:
         print("[bench] estimators and combination at 1024^3", file=sys.stderr, flush=True)
-        out["estimators_combination_1024"] = estimators_and_combination(pm, plan, pos, noise)
+        a_end = float(a_s[args.warmup + args.steps])
+        out["estimators_combination_1024"] = estimators_and_combination(pm, plan, pos, noise, a_end)
         print("[bench] initial conditions at 1024^3", file=sys.stderr, flush=True)
         out["initial_conditions_1024"] = ic_leg(pm, plan, noise, icp)
     if args.adjoint_cycles > 0:
