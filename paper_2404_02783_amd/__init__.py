@@ -20,7 +20,8 @@ __all__ = [
     "pk_estimate", "pk_cross_estimate", "bias_fit", "bk_estimate",
     "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
     "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_gauge", "pm_noise_fix",
-    "pm_plan_tuning_candidates", "pm_plan_get_tuning", "pm_plan_set_tuning", "pm_plan_autotune", "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
+    "pm_plan_tuning_candidates", "pm_plan_get_tuning", "pm_plan_set_tuning", "pm_plan_autotune", "TUNING_SLOTS",
+    "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
     "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH",
     "PM_F32", "PM_F64", "PM_NEWTON", "PM_POISSON_GAUGE", "PM_GRAD_SPECTRAL", "PM_GRAD_FD2", "PM_GRAD_FD1",
