@@ -636,12 +636,23 @@ int bias_fit(const double* k, const double* ratio, const int64_t* n_modes, int n
     ++used;
   }
   if (used < m) return set_error(PM_ERR_ARG, "bias_fit: %d bins below k_cut after the skip, %d needed", used, m);
+  // equilibrate to a unit diagonal (the columns differ by orders of magnitude), so that
+  // a pivot below 1e-10 means linearly dependent columns
+  double dsc[3];
+  for (int i = 0; i < m; ++i) {
+    if (!(a[i][i] > 0.0)) return set_error(PM_ERR_ARG, "bias_fit: singular system");
+    dsc[i] = 1.0 / std::sqrt(a[i][i]);
+  }
+  for (int i = 0; i < m; ++i) {
+    r[i] *= dsc[i];
+    for (int j = 0; j < m; ++j) a[i][j] *= dsc[i] * dsc[j];
+  }
   // Gaussian elimination with partial pivoting
   for (int c = 0; c < m; ++c) {
     int piv = c;
     for (int i = c + 1; i < m; ++i)
       if (std::fabs(a[i][c]) > std::fabs(a[piv][c])) piv = i;
-    if (!(std::fabs(a[piv][c]) > 0.0)) return set_error(PM_ERR_ARG, "bias_fit: singular system");
+    if (!(std::fabs(a[piv][c]) > 1e-10)) return set_error(PM_ERR_ARG, "bias_fit: singular system");
     if (piv != c) {
       for (int j = 0; j < m; ++j) std::swap(a[c][j], a[piv][j]);
       std::swap(r[c], r[piv]);
@@ -658,7 +669,7 @@ int bias_fit(const double* k, const double* ratio, const int64_t* n_modes, int n
     for (int j = i + 1; j < m; ++j) v -= a[i][j] * x[j];
     x[i] = v / a[i][i];
   }
-  for (int i = 0; i < 3; ++i) coef[i] = x[i];
+  for (int i = 0; i < 3; ++i) coef[i] = i < m ? x[i] * dsc[i] : 0.0;
   return PM_OK;
 }
 

@@ -817,3 +817,33 @@ def test_poisson_gauge_run_with_density_handoff_matches_plain_cycles():
     torch.cuda.synchronize()
     assert float(min_image(x.double().cpu() - xr.double().cpu(), n).abs().max()) < 1e-12 * n
     assert rel_l2(p, pr) < 1e-12
+
+
+def test_entry_points_of_the_extensions_reject_bad_arguments():
+    """Argument errors of the combined-1LPT, 2LPT, pairing, cross-spectrum, bias-fit
+    and tuning entry points are reported synchronously, before any launch."""
+    dev = _dev()
+    n = 16
+    plan = pm.Plan(n, 100.0, torch.float32)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_POWERLAW, amp=1.0, index=-2.0, a_init=0.02, a_norm=0.02, cosmo=pm.FIDUCIAL)
+    noise = plan.mesh().normal_()
+    with pytest.raises(pm.PMError, match="scale factor"):
+        pm.pm_xi_linear(plan, noise, icp, 0.0)
+    bplan = pm.Plan(n, 100.0, torch.float32, batch=2)
+    with pytest.raises(pm.PMError, match="single-box"):
+        pm.pm_xi_linear(bplan, bplan.mesh(), icp, 1.0)
+    with pytest.raises(pm.PMError, match="pair_mode"):
+        pm.pm_noise_fix(plan, noise, 3)
+    with pytest.raises(pm.PMError, match="n_bins|null"):   # zero bins: empty output buffers
+        pm.pk_cross_estimate(plan, noise, noise, 0)
+    with pytest.raises(pm.PMError, match="n_bins"):
+        pm.pk_cross_estimate(plan, noise, noise, 4 * n + 1)
+    with pytest.raises(pm.PMError, match="singular"):
+        pm.bias_fit([0.01] * 6, [1.0] * 6, [5] * 6, 0.08, 1e-3, 0, True)   # one k: columns collinear
+    with pytest.raises(pm.PMError, match="reps"):
+        pm.pm_plan_autotune(plan, reps=0)
+    with pytest.raises(pm.PMError):
+        pm.pm_plan_tuning_candidates(plan, 4)
+    x = torch.zeros((3, 8 ** 3), device=dev)
+    with pytest.raises(pm.PMError, match="multiple"):
+        pm.displacement_add(torch.zeros((3, 16 ** 3), device=dev), 16, x, 8)
