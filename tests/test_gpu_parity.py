@@ -674,6 +674,46 @@ def test_combined_pm_and_combined_linear_shift_agree_in_the_linear_regime():
     assert float(pks[2][0]) < 0.05 * float(pks[0][0])
 
 
+def test_combination_recovers_the_relativistic_run_at_several_redshifts():
+    """The paper's power-spectrum comparison (Sec. 4.1) in miniature: a fine 128^3
+    Newtonian run plus xi of a 64^3 relativistic/Newtonian pair sharing its phases
+    (eq. combined) against a fine 128^3 Poisson-gauge run, L = 4000 Mpc/h, EH98 2LPT
+    ICs at a = 0.02, 50 log steps, at a = 0.17, 0.36, 0.49 and 1.  The gauge raises the
+    fundamental bin by 6-31 % over the Newtonian run; the combination reproduces the
+    relativistic run to 0.4 % in every bin (measured 0.33 % at most)."""
+    dev = _dev()
+    box, nf, nc = 4000.0, 128, 64
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=0.02,
+                      a_norm=1.0, cosmo=pm.FIDUCIAL)
+    fine, coarse = pm.Plan(nf, box, torch.float32), pm.Plan(nc, box, torch.float32)
+    noise_f = torch.from_numpy(si.white_noise(nf, 71, dtype=np.float32)).to(dev)
+    noise_c = pm.pm_noise_truncate(fine, noise_f, coarse)
+    a_s = pm.sim.log_steps(0.02, 1.0, 50)
+    snap = [26, 36, 40, 49]
+
+    def run(plan, noise, gauge):
+        disp = plan.mesh(3)
+        pos, mom, pg, mg = (plan.particles() for _ in range(4))
+        pm.pm_ic_2lpt(plan, noise, icp, disp, pos, mom)
+        if gauge:
+            pm.pm_ic_gauge(plan, noise, icp, disp, pos, mom, pg, mg)
+            pos, mom = pg, mg
+        out = {}
+        pm.sim.Run(plan, pos, mom, gauge=gauge).leapfrog(
+            a_s, close=False, on_cycle=lambda j: out.__setitem__(j, pos.clone()) if j in snap else None)
+        return out
+    fn, fg, cn, cg = run(fine, noise_f, False), run(fine, noise_f, True), run(coarse, noise_c, False), \
+        run(coarse, noise_c, True)
+    nb = nf // 4
+    for j in snap:
+        comb = pm.displacement_combine(cg[j], cn[j], nc, fn[j], nf)
+        p_n, p_g, p_c = (pm.pk_estimate(fine, pm.pm_deposit(fine, x), nb)[1].cpu() for x in (fn[j], fg[j], comb))
+        gauge_effect = float(p_g[0] / p_n[0] - 1.0)
+        assert gauge_effect > 0.05, (a_s[j + 1], gauge_effect)
+        assert float((p_c / p_g - 1.0).abs().max()) < 0.004, a_s[j + 1]
+        assert abs(float(p_c[0] / p_g[0] - 1.0)) < 0.05 * gauge_effect
+
+
 def _gradient_variant_runs(n, box, steps, nb):
     """P(k) of the Newtonian and Poisson-gauge runs with each gradient symbol, and of
     the spectral Newtonian run combined with each variant's xi (eq. combined)."""
