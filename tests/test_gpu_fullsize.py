@@ -32,6 +32,8 @@ at a time, or a property that holds at any size:
     ICs drop): sampled particles against the oracle's ICs of the sparse noise
     spectrum (for 2LPT, the second-order source as a sum over mode pairs); the
     truncation of that noise to 256^3, whole, against the sparse truncation;
+  * every FFT launch shape the autotuner may pick at 1024^3 gives the same force, bit
+    for bit;
   * paired-and-fixed noise at 1024^3: moduli and phases of every mode against an
     independent FFT, the partner exactly negated;
   * the linear Poisson-gauge shift at a = 1 at 1024^3, and the combination with it
@@ -581,6 +583,32 @@ def test_noise_fix_full_size_properties(plan):
     ph = torch.angle(f[big] * torch.conj(w[big]))
     assert float(ph.abs().max()) < 1e-3
     assert float(ph.pow(2).mean().sqrt()) < 1e-5
+
+
+def test_fft_launch_shapes_full_size(plan):
+    """Every allowed FFT launch shape of the 1024^3 plan computes the same force of a
+    plane-wave field, bit for bit (the autotuner may pick any of them; the built-in
+    shapes are checked against the closed form by the solve test)."""
+    dev = plan.device
+    delta = si.plane_wave_mesh(N, WAVES, device=dev, dtype=torch.float32)
+    pm.pm_plan_set_tuning(plan, [0, 0, 0, 0])
+    ref = pm.pm_solve(plan, delta, pm.newton_params()).clone()
+    force = plan.mesh(3)
+    tried = 0
+    try:
+        for slot in range(4):
+            for c in pm.pm_plan_tuning_candidates(plan, slot):
+                shapes = [0, 0, 0, 0]
+                shapes[slot] = c
+                pm.pm_plan_set_tuning(plan, shapes)
+                pm.pm_solve(plan, delta, pm.newton_params(), force=force)
+                torch.cuda.synchronize()
+                assert torch.equal(force, ref), (slot, c)
+                tried += 1
+    finally:
+        pm.pm_plan_set_tuning(plan, [0, 0, 0, 0])
+    assert tried >= 12
+    del delta, force, ref
 
 
 def test_noise_truncate_full_size(plan):
