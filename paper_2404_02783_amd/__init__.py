@@ -335,13 +335,20 @@ def displacement_add(xi, n_coarse: int, x_fine, n_fine: int, x_out=None):
     return x_out
 
 
-def pk_estimate(plan: Plan, delta, n_bins: int):
-    """(k_mean, P, n_modes), each [n_bins] ([batch, n_bins] for a batch)."""
+def pk_estimate(plan: Plan, delta, n_bins: int, out=None):
+    """(k_mean, P, n_modes), each [n_bins] ([batch, n_bins] for a batch); ``out``:
+    optional preallocated (k_mean, P, n_modes) device tensors to write."""
     shape = (n_bins,) if plan.batch == 1 else (plan.batch, n_bins)
     _need(delta, plan.batch * plan.n ** 3, "delta")
-    k = torch.empty(shape, dtype=torch.float64, device=plan.device)
-    p = torch.empty(shape, dtype=torch.float64, device=plan.device)
-    c = torch.empty(shape, dtype=torch.int64, device=plan.device)
+    if out is None:
+        k = torch.empty(shape, dtype=torch.float64, device=plan.device)
+        p = torch.empty(shape, dtype=torch.float64, device=plan.device)
+        c = torch.empty(shape, dtype=torch.int64, device=plan.device)
+    else:
+        k, p, c = out
+        for t, dt, nm in ((k, torch.float64, "k_mean"), (p, torch.float64, "pk"), (c, torch.int64, "n_modes")):
+            if t.dtype != dt or t.numel() < plan.batch * n_bins or not t.is_contiguous():
+                raise PMError(PM_ERR_ARG, f"pk_estimate: out {nm} must be a contiguous {dt} of {plan.batch * n_bins}")
     _check(lib().pk_estimate(plan.handle, _ptr(delta, plan.dtype, "delta"), int(n_bins), _ptr(k), _ptr(p), _ptr(c),
                              _stream()))
     return k, p, c

@@ -60,6 +60,8 @@ class _State:
     delta: torch.Tensor
     out: tuple = field(default=None)
     tuning: tuple = field(default=None)
+    pk_out: tuple = field(default=None)
+    stream: object = field(default=None)
 
 
 def schedule(a_start=0.02, a_end=1.0, n_steps=30, n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL):
@@ -89,7 +91,7 @@ class Ensemble:
 
     def __init__(self, groups, noise_fn, a_start=0.02, a_end=1.0, n_steps=30, dtype=torch.float32, device=None,
                  n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL, paired_fixed: bool = False, autotune: bool = False,
-                 tuning_cache: str | None = None):
+                 tuning_cache: str | None = None, concurrent: bool = False):
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.dtype = dtype
         self.paired_fixed = paired_fixed
@@ -105,12 +107,41 @@ class Ensemble:
             st = _State(g, plan, noise, plan.particles(), plan.particles(), plan.mesh(3), plan.mesh(3), plan.mesh())
             if autotune:   # FFT launch shapes measured for this group's batch (delta as scratch)
                 st.tuning = tune(plan, tuning_cache, mesh_scratch=st.delta)
+            shape = (plan.batch, g.bins())
+            st.pk_out = (torch.empty(shape, dtype=torch.float64, device=self.device),
+                         torch.empty(shape, dtype=torch.float64, device=self.device),
+                         torch.empty(shape, dtype=torch.int64, device=self.device))
+            st.stream = torch.cuda.Stream(device=self.device) if concurrent else None
             self.states.append(st)
+        self.concurrent = concurrent
         self.graph = None
 
+    def _run_group(self, st):
+        """The whole run of one group, in order, on the current stream."""
+        pm_ic_zeldovich(st.plan, st.noise, self.ic, st.disp, st.pos, st.mom)
+        for j, cyc in enumerate(self.cycles):
+            fl = (PM_STEP_DENSITY_READY if j > 0 else 0) | (PM_STEP_DEPOSIT_NEXT if j + 1 < len(self.cycles) else 0)
+            pm_step(st.plan, st.pos, st.mom, StepParams(kick=cyc.kick, drift=cyc.drift, solve=cyc.solve, flags=fl),
+                    st.force)
+        pm_deposit(st.plan, st.pos, st.delta)
+        pk_estimate(st.plan, st.delta, st.group.bins(), out=st.pk_out)
+        st.out = st.pk_out
+
     def run(self):
-        """Issue the whole run of every group on the current stream: ICs, the
-        leapfrog cycles (without the final half kick) and P(k) at a_end."""
+        """Issue the whole run of every group: ICs, the leapfrog cycles (without the
+        final half kick) and P(k) at a_end.  On the current stream, cycle by cycle
+        over the groups; with ``concurrent`` each group runs on a stream of its own
+        (forked from and joined back into the current stream), so that the groups'
+        kernels may overlap on the GPU."""
+        if self.concurrent:
+            cur = torch.cuda.current_stream()
+            for st in self.states:
+                st.stream.wait_stream(cur)
+                with torch.cuda.stream(st.stream):
+                    self._run_group(st)
+            for st in self.states:
+                cur.wait_stream(st.stream)
+            return
         for st in self.states:
             pm_ic_zeldovich(st.plan, st.noise, self.ic, st.disp, st.pos, st.mom)
         for j, cyc in enumerate(self.cycles):
@@ -121,9 +152,8 @@ class Ensemble:
                 pm_step(st.plan, st.pos, st.mom, c, st.force)
         for st in self.states:
             pm_deposit(st.plan, st.pos, st.delta)
-            out = pk_estimate(st.plan, st.delta, st.group.bins())
-            # a one-box group has an unbatched plan: keep the [boxes, bins] shape
-            st.out = out if st.plan.batch > 1 else tuple(t.unsqueeze(0) for t in out)
+            pk_estimate(st.plan, st.delta, st.group.bins(), out=st.pk_out)
+            st.out = st.pk_out   # [boxes, bins], also for a one-box group
 
     def capture(self):
         """Capture run() into one HIP graph (after one eager warm-up run)."""

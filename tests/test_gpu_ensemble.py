@@ -127,6 +127,38 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
 
 
+def test_concurrent_groups_match_the_serial_run_eager_and_graphed():
+    """Each size group on a stream of its own (forked from and joined into the
+    current stream, also inside a captured graph) reproduces the serial run."""
+    dev = _dev()
+    groups = [ensemble.Group(32, 250.0, [41, 42, 43]), ensemble.Group(64, 500.0, [44, 45]),
+              ensemble.Group(128, 1000.0, [46])]
+    serial = ensemble.Ensemble(groups, _noise, 0.02, 0.06, 3, torch.float64, dev)
+    serial.run()
+    torch.cuda.synchronize()
+    want = [o[1].clone() for o in serial.power_spectra()]
+    del serial
+    ens = ensemble.Ensemble(groups, _noise, 0.02, 0.06, 3, torch.float64, dev, concurrent=True)
+    assert len({id(st.stream) for st in ens.states}) == 3
+    ens.run()
+    torch.cuda.synchronize()
+    for o, w in zip(ens.power_spectra(), want):
+        assert o[1].shape == w.shape
+        assert rel(o[1], w) < 1e-12
+    ens.capture()
+    for _ in range(3):
+        for o in ens.power_spectra():
+            o[1].zero_()
+        torch.cuda.synchronize()
+        ens.replay()
+        torch.cuda.synchronize()
+        for o, w in zip(ens.power_spectra(), want):
+            assert rel(o[1], w) < 1e-12
+        x = torch.randn(1 << 20, device=dev)   # eager work between replays
+        float(x.sum())
+        torch.cuda.synchronize()
+
+
 def test_single_box_entry_points_reject_batches():
     dev = _dev()
     plan = pm.Plan(64, 500.0, torch.float32, dev, batch=2)
