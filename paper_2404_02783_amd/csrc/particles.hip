@@ -96,12 +96,13 @@ constexpr int GPP = GTX * GTY * GTZ / kBlock;  // particles per thread
 constexpr int GCAP = 4096;                     // staged cells (x3 components, float)
 
 // DEPOSIT: after the drift, the tile's new positions are also deposited into `dens`
-// (pre-filled with -1, box offset N^3) exactly as the standalone tiled deposit does --
-// an LDS window over the bounding box of their CIC cells in 64-bit fixed point (the
-// force window's LDS is reused: DCAP cells), one global atomic per non-empty cell,
-// global atomics for particles outside the window -- so the next cycle need not read
-// the positions again.
-constexpr int DCAP = 3 * GCAP * (int)sizeof(float) / (int)sizeof(unsigned long long);
+// (pre-filled with -1, box offset N^3) like the standalone tiled deposit -- an LDS
+// window over the bounding box of their CIC cells, one global atomic per non-empty
+// cell, global atomics for particles outside the window -- so the next cycle need not
+// read the positions again.  The window reuses the force window's LDS as DCAP cells of
+// 32-bit fixed point (to_fix_w): half the LDS traffic of 64-bit cells and twice the
+// cells; the window holds at most 2048 particles, so a cell cannot wrap.
+constexpr int DCAP = 3 * GCAP * (int)sizeof(float) / (int)sizeof(unsigned);
 // Gather + kick + drift of one GTX x GTY x GTZ Lagrangian tile at `org` (block-wide):
 // stages the three force meshes over the tile's CIC bounding box in `win`, updates
 // (pos, mom) and leaves the drifted, wrapped positions in (x, y, z).  GUARD counts
@@ -258,12 +259,13 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
   }
   if (!DEPOSIT) return;
   __syncthreads();  // every thread is done with the force window
-  unsigned long long* dwin = reinterpret_cast<unsigned long long*>(win);
+  static_assert((double)NT * GTX * GTY * GTZ * kFixW < 4294967296.0, "a window cell could wrap");
+  unsigned* dwin = reinterpret_cast<unsigned*>(win);
   const int org[3] = {ti * NT * GTX, tk * GTY, tl * GTZ};
   const TileWindow dw = tile_window<NT * GPP, P2>(x, y, z, n, org, DCAP, NT * GTX * GTY * GTZ, wlo, whi, wsum);
   const int D0 = dw.W[0], D1 = dw.W[1], D2 = dw.W[2];
   const int dtot = D0 * D1 * D2;
-  for (int c = t; c < dtot; c += kBlock) dwin[c] = 0ull;
+  for (int c = t; c < dtot; c += kBlock) dwin[c] = 0u;
   __syncthreads();
   const int dsy = D2, dsx = D1 * D2;
 #pragma unroll
@@ -274,15 +276,15 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
     const float wxy00 = ax.w0 * ay.w0, wxy01 = ax.w0 * ay.w1;
     const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
     if (rx >= 0 && rx <= D0 - 2 && ry >= 0 && ry <= D1 - 2 && rz >= 0 && rz <= D2 - 2) {
-      unsigned long long* w = dwin + win_index(rx, ry, rz, dsx, dsy);
-      atomicAdd(w, to_fix(wxy00 * az.w0));
-      atomicAdd(w + 1, to_fix(wxy00 * az.w1));
-      atomicAdd(w + dsy, to_fix(wxy01 * az.w0));
-      atomicAdd(w + dsy + 1, to_fix(wxy01 * az.w1));
-      atomicAdd(w + dsx, to_fix(wxy10 * az.w0));
-      atomicAdd(w + dsx + 1, to_fix(wxy10 * az.w1));
-      atomicAdd(w + dsx + dsy, to_fix(wxy11 * az.w0));
-      atomicAdd(w + dsx + dsy + 1, to_fix(wxy11 * az.w1));
+      unsigned* w = dwin + win_index(rx, ry, rz, dsx, dsy);
+      atomicAdd(w, to_fix_w(wxy00 * az.w0));
+      atomicAdd(w + 1, to_fix_w(wxy00 * az.w1));
+      atomicAdd(w + dsy, to_fix_w(wxy01 * az.w0));
+      atomicAdd(w + dsy + 1, to_fix_w(wxy01 * az.w1));
+      atomicAdd(w + dsx, to_fix_w(wxy10 * az.w0));
+      atomicAdd(w + dsx + 1, to_fix_w(wxy10 * az.w1));
+      atomicAdd(w + dsx + dsy, to_fix_w(wxy11 * az.w0));
+      atomicAdd(w + dsx + dsy + 1, to_fix_w(wxy11 * az.w1));
     } else {
       const int64_t r00 = ax.i0 * n2 + (int64_t)ay.i0 * n, r01 = ax.i0 * n2 + (int64_t)ay.i1 * n;
       const int64_t r10 = ax.i1 * n2 + (int64_t)ay.i0 * n, r11 = ax.i1 * n2 + (int64_t)ay.i1 * n;
@@ -297,16 +299,16 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
     }
   }
   __syncthreads();
-  const double scale = (double)w_scale / kFix;
+  const float scale = w_scale / kFixW;
   const WinDiv qsx(dsx), qsy(dsy);
   for (int c = t; c < dtot; c += kBlock) {
-    const unsigned long long v = dwin[c];
-    if (v == 0ull) continue;
+    const unsigned v = dwin[c];
+    if (v == 0u) continue;
     int a, b, cz;
     win_cell(c, qsx, qsy, a, b, cz);
     const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + dw.o[0] + a, n), fold_n<P2>(org[1] + dw.o[1] + b, n),
                                         fold_n<P2>(org[2] + dw.o[2] + cz, n), n);
-    atomic_add(dens + idx, (float)((double)v * scale));
+    atomic_add(dens + idx, (float)v * scale);
   }
 }
 

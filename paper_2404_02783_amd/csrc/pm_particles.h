@@ -87,6 +87,13 @@ __host__ __device__ __forceinline__ unsigned long long to_fix(float w) {
   return r > 25 ? 0ull : (m + (1ull << (r - 1))) >> r;
 }
 
+// The fused gather-deposit kernel's LDS window holds 32-bit fixed point with scale
+// S = 2^21 - 1: to_fix_w(w) = floor(w S + 1/2) (float arithmetic) is at most S for w in
+// [0, 1], so the sum of up to 2048 terms stays below 2^32; the quantum 1/S ~ 4.8e-7 of
+// a particle is far below the FP32 rounding of the density it is flushed into.
+constexpr float kFixW = 2097151.0f;
+__host__ __device__ __forceinline__ unsigned to_fix_w(float w) { return (unsigned)(w * kFixW + 0.5f); }
+
 // Product of two factors below 2^24 (the masks let the compiler use the full-rate
 // 24-bit multiplier, where a 32-bit multiply is quarter rate)
 __host__ __device__ __forceinline__ unsigned mul24(unsigned a, unsigned b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
@@ -110,9 +117,10 @@ __host__ __device__ __forceinline__ int win_index(int a, int b, int c, int sx, i
 
 // Window cells are numbered c = (a W1 + b) W2 + cz.  Their decomposition divides by
 // runtime extents, which a high multiply does exactly in the range windows use
-// (2 <= d < 2^13, 0 <= c < 2^13): with m = floor((2^32 - 1) / d) + 1 the product
-// c m / 2^32 exceeds c / d by less than c / 2^32 < 2^-19, while c / d stays at least
-// 1/d >= 2^-13 below the next integer, so floor(c m / 2^32) = floor(c / d).
+// (2 <= d < 2^14, 0 <= c < 2^14; the largest window has 12288 cells): with
+// m = floor((2^32 - 1) / d) + 1 the product c m / 2^32 exceeds c / d by less than
+// c / 2^32 < 2^-18, while c / d stays at least 1/d > 2^-14 below the next integer,
+// so floor(c m / 2^32) = floor(c / d).
 struct WinDiv {
   unsigned d, m;
   __host__ __device__ __forceinline__ explicit WinDiv(int dd) : d((unsigned)dd), m(0xFFFFFFFFu / (unsigned)dd + 1u) {}

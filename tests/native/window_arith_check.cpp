@@ -21,10 +21,10 @@ static int fails = 0;
   } while (0)
 
 int main() {
-  // WinDiv: floor(c / d) for every c, d in the window range (c < 2^13, 2 <= d < 2^13)
-  for (unsigned d = 2; d < 8192; ++d) {
+  // WinDiv: floor(c / d) for every c, d in the window range (c < 2^14, 2 <= d < 2^14)
+  for (unsigned d = 2; d < 16384; ++d) {
     const WinDiv q((int)d);
-    for (unsigned c = 0; c < 8192; ++c) EXPECT(q.quot(c) == c / d, "quot %u / %u\n", c, d);
+    for (unsigned c = 0; c < 16384; ++c) EXPECT(q.quot(c) == c / d, "quot %u / %u\n", c, d);
   }
   // win_cell / win_index: c = a sx + b sy + cz round trip over whole windows
   std::mt19937 rng(7);
@@ -46,6 +46,15 @@ int main() {
     const unsigned long long want = (unsigned long long)std::floor((double)w * 4294967296.0 + 0.5);
     EXPECT(to_fix(w) == want, "to_fix %a\n", (double)w);
   }
+  // to_fix_w: within half a unit (plus the float product's rounding) of w S, never
+  // above S, for every float in [0, 1]; 2048 of them cannot wrap 32 bits
+  for (unsigned bits = 0; bits <= 0x3F800000u; ++bits) {
+    const float w = __builtin_bit_cast(float, bits);
+    const unsigned got = to_fix_w(w);
+    const double exact = (double)w * (double)kFixW;
+    EXPECT(got <= 2097151u && std::fabs((double)got - exact) <= 0.5 + 0.125, "to_fix_w %a -> %u\n", (double)w, got);
+  }
+  EXPECT(2048.0 * (double)kFixW < 4294967296.0, "window sum bound\n");
   // node_index: both forms against the 64-bit flat index
   for (int n : {64, 128, 192, 256, 1024}) {
     for (int it = 0; it < 100000; ++it) {
