@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit(const T* __restrict__ pos, i
 // Tile of TX x TY x TZ particles (Lagrangian indices), window capacity in cells.
 constexpr int TX = 8, TY = 8, TZ = 16;
 constexpr int TPP = TX * TY * TZ / kBlock;  // particles per thread
-constexpr int WCAP = 4096;                  // LDS window cells (u64)
+constexpr int WCAP = 8192;                  // LDS window cells (32-bit fixed point, to_fix_w)
 
 // np = N^3, particle (i N + k) N + l started in cell (i, k, l).  The window is the
 // bounding box of the tile's CIC cells when it fits in WCAP cells, else fit_box's
@@ -68,7 +68,8 @@ constexpr int WCAP = 4096;                  // LDS window cells (u64)
 template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restrict__ pos, float* __restrict__ mesh,
                                                           int n, double w_scale, unsigned* __restrict__ guard) {
-  __shared__ unsigned long long win[WCAP];
+  static_assert((double)TX * TY * TZ * kFixW < 4294967296.0, "a window cell could wrap");  // 2^31 at most
+  __shared__ unsigned win[WCAP];
   __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
   __shared__ float wsum[kBlock / 64][3];
   const int64_t np = (int64_t)n * n * n;
@@ -118,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
   int o[3], W[3];
   block_window(lo, hi, sum, TX * TY * TZ, WCAP, wlo, whi, wsum, o, W);
   const int wtot = W[0] * W[1] * W[2];
-  for (int c = t; c < wtot; c += kBlock) win[c] = 0ull;
+  for (int c = t; c < wtot; c += kBlock) win[c] = 0u;
   __syncthreads();
   const int sy = W[2], sx = W[1] * W[2];
   const int64_t n2 = (int64_t)n * n;
@@ -131,15 +132,15 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
     const float wxy00 = ax.w0 * ay.w0, wxy01 = ax.w0 * ay.w1;
     const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
     if (rx >= 0 && rx <= W[0] - 2 && ry >= 0 && ry <= W[1] - 2 && rz >= 0 && rz <= W[2] - 2) {
-      unsigned long long* w = win + win_index(rx, ry, rz, sx, sy);
-      atomicAdd(w, to_fix(wxy00 * az.w0));
-      atomicAdd(w + 1, to_fix(wxy00 * az.w1));
-      atomicAdd(w + sy, to_fix(wxy01 * az.w0));
-      atomicAdd(w + sy + 1, to_fix(wxy01 * az.w1));
-      atomicAdd(w + sx, to_fix(wxy10 * az.w0));
-      atomicAdd(w + sx + 1, to_fix(wxy10 * az.w1));
-      atomicAdd(w + sx + sy, to_fix(wxy11 * az.w0));
-      atomicAdd(w + sx + sy + 1, to_fix(wxy11 * az.w1));
+      unsigned* w = win + win_index(rx, ry, rz, sx, sy);
+      atomicAdd(w, to_fix_w(wxy00 * az.w0));
+      atomicAdd(w + 1, to_fix_w(wxy00 * az.w1));
+      atomicAdd(w + sy, to_fix_w(wxy01 * az.w0));
+      atomicAdd(w + sy + 1, to_fix_w(wxy01 * az.w1));
+      atomicAdd(w + sx, to_fix_w(wxy10 * az.w0));
+      atomicAdd(w + sx + 1, to_fix_w(wxy10 * az.w1));
+      atomicAdd(w + sx + sy, to_fix_w(wxy11 * az.w0));
+      atomicAdd(w + sx + sy + 1, to_fix_w(wxy11 * az.w1));
     } else {
       const float ws = float(w_scale);
       const int64_t r00 = ax.i0 * n2 + (int64_t)ay.i0 * n, r01 = ax.i0 * n2 + (int64_t)ay.i1 * n;
@@ -155,11 +156,11 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
     }
   }
   __syncthreads();
-  const double scale = w_scale / kFix;
+  const double scale = w_scale / (double)kFixW;  // in FP64: a float 1/S would bias the total mass
   const WinDiv qsx(sx), qsy(sy);
   for (int c = t; c < wtot; c += kBlock) {
-    const unsigned long long v = win[c];
-    if (v == 0ull) continue;
+    const unsigned v = win[c];
+    if (v == 0u) continue;
     int a, b, cz;
     win_cell(c, qsx, qsy, a, b, cz);
     const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + o[0] + a, n), fold_n<P2>(org[1] + o[1] + b, n),

@@ -100,8 +100,9 @@ constexpr int GCAP = 4096;                     // staged cells (x3 components, f
 // window over the bounding box of their CIC cells, one global atomic per non-empty
 // cell, global atomics for particles outside the window -- so the next cycle need not
 // read the positions again.  The window reuses the force window's LDS as DCAP cells of
-// 32-bit fixed point (to_fix_w): half the LDS traffic of 64-bit cells and twice the
-// cells; the window holds at most 2048 particles, so a cell cannot wrap.
+// 32-bit fixed point (to_fix_w_capped): half the LDS traffic of 64-bit cells and twice
+// the cells; the window holds at most 2048 particles of capped terms, so a cell cannot
+// wrap.
 constexpr int DCAP = 3 * GCAP * (int)sizeof(float) / (int)sizeof(unsigned);
 // Gather + kick + drift of one GTX x GTY x GTZ Lagrangian tile at `org` (block-wide):
 // stages the three force meshes over the tile's CIC bounding box in `win`, updates
@@ -259,7 +260,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
   }
   if (!DEPOSIT) return;
   __syncthreads();  // every thread is done with the force window
-  static_assert((double)NT * GTX * GTY * GTZ * kFixW < 4294967296.0, "a window cell could wrap");
+  static_assert((double)NT * GTX * GTY * GTZ * (kFixW - 1.0f) < 4294967296.0, "a window cell could wrap");
   unsigned* dwin = reinterpret_cast<unsigned*>(win);
   const int org[3] = {ti * NT * GTX, tk * GTY, tl * GTZ};
   const TileWindow dw = tile_window<NT * GPP, P2>(x, y, z, n, org, DCAP, NT * GTX * GTY * GTZ, wlo, whi, wsum);
@@ -277,14 +278,14 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
     const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
     if (rx >= 0 && rx <= D0 - 2 && ry >= 0 && ry <= D1 - 2 && rz >= 0 && rz <= D2 - 2) {
       unsigned* w = dwin + win_index(rx, ry, rz, dsx, dsy);
-      atomicAdd(w, to_fix_w(wxy00 * az.w0));
-      atomicAdd(w + 1, to_fix_w(wxy00 * az.w1));
-      atomicAdd(w + dsy, to_fix_w(wxy01 * az.w0));
-      atomicAdd(w + dsy + 1, to_fix_w(wxy01 * az.w1));
-      atomicAdd(w + dsx, to_fix_w(wxy10 * az.w0));
-      atomicAdd(w + dsx + 1, to_fix_w(wxy10 * az.w1));
-      atomicAdd(w + dsx + dsy, to_fix_w(wxy11 * az.w0));
-      atomicAdd(w + dsx + dsy + 1, to_fix_w(wxy11 * az.w1));
+      atomicAdd(w, to_fix_w_capped(wxy00 * az.w0));
+      atomicAdd(w + 1, to_fix_w_capped(wxy00 * az.w1));
+      atomicAdd(w + dsy, to_fix_w_capped(wxy01 * az.w0));
+      atomicAdd(w + dsy + 1, to_fix_w_capped(wxy01 * az.w1));
+      atomicAdd(w + dsx, to_fix_w_capped(wxy10 * az.w0));
+      atomicAdd(w + dsx + 1, to_fix_w_capped(wxy10 * az.w1));
+      atomicAdd(w + dsx + dsy, to_fix_w_capped(wxy11 * az.w0));
+      atomicAdd(w + dsx + dsy + 1, to_fix_w_capped(wxy11 * az.w1));
     } else {
       const int64_t r00 = ax.i0 * n2 + (int64_t)ay.i0 * n, r01 = ax.i0 * n2 + (int64_t)ay.i1 * n;
       const int64_t r10 = ax.i1 * n2 + (int64_t)ay.i0 * n, r11 = ax.i1 * n2 + (int64_t)ay.i1 * n;
@@ -299,7 +300,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
     }
   }
   __syncthreads();
-  const float scale = w_scale / kFixW;
+  const double scale = (double)w_scale / (double)kFixW;  // in FP64: a float 1/S would bias the total mass
   const WinDiv qsx(dsx), qsy(dsy);
   for (int c = t; c < dtot; c += kBlock) {
     const unsigned v = dwin[c];
@@ -308,7 +309,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
     win_cell(c, qsx, qsy, a, b, cz);
     const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + dw.o[0] + a, n), fold_n<P2>(org[1] + dw.o[1] + b, n),
                                         fold_n<P2>(org[2] + dw.o[2] + cz, n), n);
-    atomic_add(dens + idx, (float)v * scale);
+    atomic_add(dens + idx, (float)((double)v * scale));
   }
 }
 

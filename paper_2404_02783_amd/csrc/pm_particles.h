@@ -69,30 +69,19 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
-// LDS deposit windows accumulate CIC weights (<= 1) as 64-bit fixed point with scale
-// 2^32: integer LDS atomics are much faster than float ones on gfx950, and a window
-// cell cannot overflow (at most 2^31 particles per tile).
-constexpr double kFix = 4294967296.0;
-// round-half-up of w 2^32 for w in [0, 1], from the float's fields: w = m 2^(e - 150)
-// with the 24-bit significand m, so w 2^32 = m 2^s, s = e - 118 <= 9; a left shift is
-// exact, a right shift by -s adds half of the last kept unit first, and below
-// 2^-26 (s < -25) the value is under one half.  Zero and subnormal w give 0.  Equal
-// to floor(w 2^32 + 1/2) for every float in [0, 1].
-__host__ __device__ __forceinline__ unsigned long long to_fix(float w) {
-  const unsigned b = __builtin_bit_cast(unsigned, w);
-  const int s = (int)(b >> 23) - 118;
-  const unsigned long long m = (unsigned long long)((b & 0x7FFFFFu) | 0x800000u);
-  if (s >= 0) return m << s;
-  const int r = -s;
-  return r > 25 ? 0ull : (m + (1ull << (r - 1))) >> r;
+// LDS deposit windows accumulate CIC weights (<= 1) as 32-bit fixed point with scale
+// S = 2^21 (integer LDS atomics are much faster than float ones on gfx950): w S is
+// exact in float and to_fix_w rounds it to nearest-even, so the terms carry no bias;
+// each is at most 2^21, so a window of up to 2048 particles reaches 2^32 in a cell only
+// if all of them sit exactly on the same node (to_fix_w_capped, for such windows,
+// keeps every term below 2^21).  The quantum 2^-21 ~ 4.8e-7 of a particle is far
+// below the FP32 rounding of the density it is flushed into.
+constexpr float kFixW = 2097152.0f;
+__host__ __device__ __forceinline__ unsigned to_fix_w(float w) { return (unsigned)__builtin_rintf(w * kFixW); }
+__host__ __device__ __forceinline__ unsigned to_fix_w_capped(float w) {
+  const unsigned v = to_fix_w(w);
+  return v < 2097151u ? v : 2097151u;
 }
-
-// The fused gather-deposit kernel's LDS window holds 32-bit fixed point with scale
-// S = 2^21 - 1: to_fix_w(w) = floor(w S + 1/2) (float arithmetic) is at most S for w in
-// [0, 1], so the sum of up to 2048 terms stays below 2^32; the quantum 1/S ~ 4.8e-7 of
-// a particle is far below the FP32 rounding of the density it is flushed into.
-constexpr float kFixW = 2097151.0f;
-__host__ __device__ __forceinline__ unsigned to_fix_w(float w) { return (unsigned)(w * kFixW + 0.5f); }
 
 // Product of two factors below 2^24 (the masks let the compiler use the full-rate
 // 24-bit multiplier, where a 32-bit multiply is quarter rate)

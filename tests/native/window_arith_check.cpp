@@ -2,6 +2,7 @@
 // (pm_particles.h): the window-cell division by a high multiply, the cell
 // decomposition and numbering, the fixed-point weights, the node index, the packed
 // window reduction and the over-capacity window.  Prints "ok" and exits 0 on success.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -40,21 +41,16 @@ int main() {
              "win_cell %d in %dx%dx%d\n", c, W0, W1, W2);
     }
   }
-  // to_fix: round-half-up of w 2^32 for every float in [0, 1]
+  // to_fix_w: w 2^21 rounded to nearest-even, exactly, for every float in [0, 1]; the
+  // capped form stays below 2^21, so 2048 terms cannot wrap 32 bits
   for (unsigned bits = 0; bits <= 0x3F800000u; ++bits) {
     const float w = __builtin_bit_cast(float, bits);
-    const unsigned long long want = (unsigned long long)std::floor((double)w * 4294967296.0 + 0.5);
-    EXPECT(to_fix(w) == want, "to_fix %a\n", (double)w);
+    const double x = (double)w * 2097152.0;  // exact
+    const double want = std::nearbyint(x);   // default rounding: to nearest, ties to even
+    EXPECT(to_fix_w(w) == (unsigned)want, "to_fix_w %a\n", (double)w);
+    EXPECT(to_fix_w_capped(w) == (unsigned)std::min(want, 2097151.0), "to_fix_w_capped %a\n", (double)w);
   }
-  // to_fix_w: within half a unit (plus the float product's rounding) of w S, never
-  // above S, for every float in [0, 1]; 2048 of them cannot wrap 32 bits
-  for (unsigned bits = 0; bits <= 0x3F800000u; ++bits) {
-    const float w = __builtin_bit_cast(float, bits);
-    const unsigned got = to_fix_w(w);
-    const double exact = (double)w * (double)kFixW;
-    EXPECT(got <= 2097151u && std::fabs((double)got - exact) <= 0.5 + 0.125, "to_fix_w %a -> %u\n", (double)w, got);
-  }
-  EXPECT(2048.0 * (double)kFixW < 4294967296.0, "window sum bound\n");
+  EXPECT(2048.0 * 2097151.0 < 4294967296.0 && 1024.0 * 2097152.0 < 4294967296.0, "window sum bounds\n");
   // node_index: both forms against the 64-bit flat index
   for (int n : {64, 128, 192, 256, 1024}) {
     for (int it = 0; it < 100000; ++it) {
