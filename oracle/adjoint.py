@@ -65,3 +65,10 @@ def step_vjp(pos, mom, kick: float, drift: float, n: int, cosmo: cm.Cosmo, lam_p
 
     ct = torch.cat([lam_pos.reshape(-1), lam_mom.reshape(-1)])
     return vjp(cycle, (pos, mom), ct)
+
+
+def lpt2_vjp(noise: torch.Tensor, p: ics.ICParams, lam_pos: torch.Tensor, lam_mom: torch.Tensor) -> torch.Tensor:
+    """Cotangent of the white noise for cotangents (lam_pos, lam_mom) of the second-
+    order Newtonian set ``ics.lpt2`` (the wrap has unit derivative)."""
+    (g,) = vjp(lambda w: ics.lpt2(w, p), (noise.to(torch.float64),), (lam_pos, lam_mom))
+    return g

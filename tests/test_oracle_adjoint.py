@@ -1,4 +1,5 @@
 """Pins of the oracle's reference gradient (central finite differences)."""
+import pytest
 import torch
 
 import synth_inputs as si
@@ -41,3 +42,30 @@ def test_deposit_gather_dot_product():
     # <deposit(m), A> = <m, gather(A)>: the mesh cotangent of a deposit is a gather.
     (gm,) = adjoint.vjp(lambda m: cic.deposit_rho(pos, n, m), (mass,), mesh)
     assert torch.allclose(gm, cic.gather(mesh, pos), atol=1e-13)
+
+
+def test_lpt2_vjp_equals_central_differences():
+    # The 2LPT set is quadratic in the noise, so a central difference along v is exact
+    # up to rounding: <lam, (F(w + e v) - F(w - e v)) / 2e> = <VJP(lam), v>.
+    import math
+    from oracle import adjoint as oadj, cosmology as cm, ics
+    n, box = 16, 500.0
+    c = cm.Cosmo(n_s=0.965)
+    p = ics.ICParams(n=n, box=box, a_init=0.05, power=ics.powerlaw_for_rms_displacement(n, box, 0.8), a_norm=0.05,
+                     cosmo=c)
+    g = si.rng(9)
+    w = torch.from_numpy(g.standard_normal((n, n, n)))
+    v = torch.from_numpy(g.standard_normal((n, n, n)))
+    lp = torch.from_numpy(g.standard_normal((3, n ** 3)))
+    lm = torch.from_numpy(g.standard_normal((3, n ** 3)))
+    got = float((oadj.lpt2_vjp(w, p, lp, lm) * v).sum())
+    e = 1e-3
+    (pp, mp), (pm_, mm) = ics.lpt2(w + e * v, p), ics.lpt2(w - e * v, p)
+    dpos = torch.remainder(pp - pm_ + n / 2, n) - n / 2
+    want = float(((lp * dpos).sum() + (lm * (mp - mm)).sum()) / (2 * e))
+    assert got == pytest.approx(want, rel=1e-8)
+    # the second-order part matters: the Zel'dovich VJP alone differs
+    (pz, mz), (pz2, mz2) = ics.zeldovich(w + e * v, p), ics.zeldovich(w - e * v, p)
+    wz = float(((lp * (torch.remainder(pz - pz2 + n / 2, n) - n / 2)).sum() + (lm * (mz - mz2)).sum()) / (2 * e))
+    assert abs(wz - want) > 1e-4 * abs(want)
+    assert math.isfinite(got)
