@@ -353,6 +353,17 @@ int pm_ic_2lpt(pm_plan* plan, const void* noise, const pm_ic_params* ic, void* d
  * spectrum workspace. */
 int pm_noise_fix(pm_plan* plan, const void* noise, int pair_mode, void* noise_out, void* stream);
 
+/* Adjoint of pm_ic_2lpt with respect to the noise; not in the paper (the
+ * differentiable model with the second-order start).  The set is quadratic in the
+ * noise, so the noise itself is an input: with Psi1 = A w, chi_ab = H_ab w and
+ * Psi2 = c2 G S(chi), lam_noise = A^T(lam_pos + m1 lam_mom) + sum_ab H_ab^T(g_ab),
+ * g_ab = (c2 G^T(lam_pos + m2 lam_mom)) dS/dchi_ab (m1, m2 = a^2 E f, a^2 E f2;
+ * transposes are the conjugate symbols).  noise [N^3], lam_pos, lam_mom [3][N^3]
+ * (read only); scratch [9][N^3] of the plan's dtype (overwritten); lam_noise [N^3]
+ * (written; must not alias noise or scratch).  Single-box plans only. */
+int pm_ic_2lpt_adjoint(pm_plan* plan, const void* noise, const pm_ic_params* ic, const void* lam_pos,
+                       const void* lam_mom, void* scratch, void* lam_noise, void* stream);
+
 /* Adjoint of pm_ic_zeldovich with respect to the noise; not in the paper.  The
  * forward map noise -> (pos, mom) is affine: pos = wrap(q + Psi), mom = m Psi with
  * Psi_d = IDFT(S_d DFT(noise)).  Given the cotangents lam_pos, lam_mom [3][N^3]

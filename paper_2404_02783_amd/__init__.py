@@ -19,7 +19,7 @@ __all__ = [
     "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "displacement_add", "pm_xi_linear",
     "pk_estimate", "pk_cross_estimate", "bias_fit", "bk_estimate",
     "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
-    "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_gauge", "pm_noise_fix",
+    "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_2lpt_adjoint", "pm_ic_gauge", "pm_noise_fix",
     "pm_plan_tuning_candidates", "pm_plan_get_tuning", "pm_plan_set_tuning", "pm_plan_autotune", "TUNING_SLOTS",
     "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
@@ -105,6 +105,8 @@ def _declare(l):
         "pk_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int64, _c_int, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_zeldovich": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_2lpt": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+        "pm_ic_2lpt_adjoint": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p,
+                                        _c_void_p, _c_void_p]),
         "pm_noise_fix": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_void_p]),
         "pm_plan_tuning_candidates": (_c_int, [_c_void_p, _c_int, P(_c_int), _c_int]),
         "pm_plan_get_tuning": (_c_int, [_c_void_p, P(_c_int)]),
@@ -456,6 +458,23 @@ def pm_plan_autotune(plan: Plan, reps: int = 3, use_cache: bool = True, mesh_scr
     _check(lib().pm_plan_autotune(plan.handle, _ptr(mesh_scratch, plan.dtype, "mesh_scratch"), int(reps),
                                   int(bool(use_cache)), ms, _stream()))
     return pm_plan_get_tuning(plan), [ms[i] for i in range(4)]
+
+
+def pm_ic_2lpt_adjoint(plan: Plan, noise, ic: ICParams, lam_pos, lam_mom, scratch=None, lam_noise=None):
+    """dL/dnoise from the cotangents of the second-order (pos, mom)."""
+    n3 = plan.n ** 3
+    scratch = plan.mesh(9) if scratch is None else scratch
+    lam_noise = plan.mesh() if lam_noise is None else lam_noise
+    _need(noise, n3, "noise")
+    _need(scratch, 9 * n3, "scratch")
+    _need(lam_noise, n3, "lam_noise")
+    _need(lam_pos, 3 * n3, "lam_pos")
+    _need(lam_mom, 3 * n3, "lam_mom")
+    _check(lib().pm_ic_2lpt_adjoint(plan.handle, _ptr(noise, plan.dtype, "noise"), ctypes.byref(ic),
+                                    _ptr(lam_pos, plan.dtype, "lam_pos"), _ptr(lam_mom, plan.dtype, "lam_mom"),
+                                    _ptr(scratch, plan.dtype, "scratch"), _ptr(lam_noise, plan.dtype, "lam_noise"),
+                                    _stream()))
+    return lam_noise
 
 
 def pm_noise_fix(plan: Plan, noise, pair_mode: int = 0, out=None):

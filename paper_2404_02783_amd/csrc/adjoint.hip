@@ -355,7 +355,52 @@ __global__ void __launch_bounds__(kBlock) k_ic_lattice_adj(const T* __restrict__
   lam_psi[j] = lam_pos[j] + mom_factor * lam_mom[j];
 }
 
+// Adjoint of the second-order source S = sum_{i<j} (h_ii h_jj - h_ij^2) for a
+// cotangent g of S: dS/dh_aa = sum_{b != a} h_bb, dS/dh_ab = -2 h_ab (a < b).  h holds
+// [xx, yy, zz, xy, xz, yz] and is overwritten with the six cotangents g dS/dh.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_lpt2_source_adj(T* __restrict__ h, const T* __restrict__ g,
+                                                            int64_t n3) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n3) return;
+  const double gj = (double)g[j];
+  const double xx = (double)h[j], yy = (double)h[n3 + j], zz = (double)h[2 * n3 + j];
+  h[j] = T(gj * (yy + zz));
+  h[n3 + j] = T(gj * (xx + zz));
+  h[2 * n3 + j] = T(gj * (xx + yy));
+#pragma unroll
+  for (int d = 3; d < 6; ++d) h[d * n3 + j] = T(-2.0 * gj * (double)h[d * n3 + j]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_accumulate(T* __restrict__ y, const T* __restrict__ x, int64_t count) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j < count) y[j] += x[j];
+}
+
 }  // namespace
+
+int launch_lpt2_source_adj(const pm_plan* p, void* h, const void* g, hipStream_t s) {
+  ProfScope ps(p, PK_ADJ_SYMBOL, s);
+  const int64_t n3 = (int64_t)p->n * p->n * p->n;
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_lpt2_source_adj<float>, dim3(nblocks(n3)), dim3(kBlock), 0, s, static_cast<float*>(h),
+                       static_cast<const float*>(g), n3);
+  else
+    hipLaunchKernelGGL(k_lpt2_source_adj<double>, dim3(nblocks(n3)), dim3(kBlock), 0, s, static_cast<double*>(h),
+                       static_cast<const double*>(g), n3);
+  return hip_check(hipGetLastError(), "lpt2 source adjoint");
+}
+
+int launch_accumulate(const pm_plan* p, void* y, const void* x, int64_t count, hipStream_t s) {
+  if (p->dtype == PM_F32)
+    hipLaunchKernelGGL(k_accumulate<float>, dim3(nblocks(count)), dim3(kBlock), 0, s, static_cast<float*>(y),
+                       static_cast<const float*>(x), count);
+  else
+    hipLaunchKernelGGL(k_accumulate<double>, dim3(nblocks(count)), dim3(kBlock), 0, s, static_cast<double*>(y),
+                       static_cast<const double*>(x), count);
+  return hip_check(hipGetLastError(), "accumulate");
+}
 
 int launch_adj_gather_kdk(const pm_plan* p, const void* force, const void* pos, int64_t np, double kick, double drift,
                           void* lam_pos, void* lam_mom, void* g, hipStream_t s) {

@@ -328,6 +328,79 @@ int pm_ic_zeldovich_adjoint(pm_plan* p, const pm_ic_params* ic, const void* lam_
   return fft3_c2r(p, 1, cbuf(p, 0), 0, lam_noise, s);
 }
 
+int pm_ic_2lpt_adjoint(pm_plan* p, const void* noise, const pm_ic_params* ic, const void* lam_pos,
+                       const void* lam_mom, void* scratch, void* lam_noise, void* stream) {
+  using namespace pm;
+  int rc = check_ic(p, noise, ic, scratch, "pm_ic_2lpt_adjoint");
+  if (rc) return rc;
+  p->dens_valid = false;
+  if (p->nb != 1) return set_error(PM_ERR_ARG, "pm_ic_2lpt_adjoint: needs a single-box plan");
+  if (!lam_pos || !lam_mom || !lam_noise) return set_error(PM_ERR_ARG, "pm_ic_2lpt_adjoint: null pointer");
+  if (lam_noise == noise || lam_noise == scratch)
+    return set_error(PM_ERR_ARG, "pm_ic_2lpt_adjoint: lam_noise must not alias noise or scratch");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n3 = (int64_t)p->n * p->n * p->n;
+  const int64_t cs = cstride(p);
+  char* h = static_cast<char*>(scratch);               // [6][N^3]: the Hessian of chi, then its cotangents
+  char* t = h + 6 * n3 * (int64_t)p->esize;            // [3][N^3]
+  char* t1 = t + n3 * (int64_t)p->esize;
+  const pm_cosmology* c = &ic->cosmo;
+  const double a = ic->a_init;
+  const double ae = a * a * pm_cosmo_hubble_e(c, a);
+  const double om = pm_cosmo_omega_m_a(c, a);
+  const double f1 = pm_cosmo_growth_rate(c, a);
+  const double f2 = 2.0 * f1 + (3.0 / 143.0) * (1.0 - om);
+  const double c2 = (3.0 / 7.0) * std::pow(om, -1.0 / 143.0);
+  IcSymbol sy = ic_symbol_of(p, ic, 1, 1.0);
+  // first order: the Zel'dovich map's transpose applied to lam_pos + ae f1 lam_mom
+  rc = launch_ic_lattice_adj(p, lam_pos, lam_mom, t, ae * f1, s);
+  if (rc) return rc;
+  rc = fft3_r2c_n(p, 3, t, cbuf(p, 0), s);
+  if (rc) return rc;
+  rc = launch_ic_symbol(p, sy, true, s);
+  if (rc) return rc;
+  rc = fft3_c2r(p, 1, cbuf(p, 0), 0, lam_noise, s);
+  if (rc) return rc;
+  // the six Hessian components of chi (as the forward pass computes them)
+  for (int pass = 0; pass < 2; ++pass) {
+    rc = fft3_r2c(p, noise, cbuf(p, 0), s);
+    if (rc) return rc;
+    sy.mode = 1 + pass;
+    rc = launch_ic_symbol(p, sy, false, s);
+    if (rc) return rc;
+    rc = fft3_c2r(p, 3, cbuf(p, 0), cs, h + pass * 3 * n3 * (int64_t)p->esize, s);
+    if (rc) return rc;
+  }
+  // cotangent of S: the transpose of Psi2 = c2 IDFT(i k DFT(S) / k^2) applied to
+  // lam_pos + ae f2 lam_mom
+  rc = launch_ic_lattice_adj(p, lam_pos, lam_mom, t, ae * f2, s);
+  if (rc) return rc;
+  rc = fft3_r2c_n(p, 3, t, cbuf(p, 0), s);
+  if (rc) return rc;
+  IcSymbol s3 = sy;
+  s3.mode = 3;
+  s3.coef = c2 / ((double)n3);
+  rc = launch_ic_symbol(p, s3, true, s);
+  if (rc) return rc;
+  rc = fft3_c2r(p, 1, cbuf(p, 0), 0, t, s);
+  if (rc) return rc;
+  // cotangents of the Hessian components, then the transposes of their symbols
+  rc = launch_lpt2_source_adj(p, h, t, s);
+  if (rc) return rc;
+  for (int pass = 0; pass < 2; ++pass) {
+    rc = fft3_r2c_n(p, 3, h + pass * 3 * n3 * (int64_t)p->esize, cbuf(p, 0), s);
+    if (rc) return rc;
+    sy.mode = 1 + pass;
+    rc = launch_ic_symbol(p, sy, true, s);
+    if (rc) return rc;
+    rc = fft3_c2r(p, 1, cbuf(p, 0), 0, t1, s);
+    if (rc) return rc;
+    rc = launch_accumulate(p, lam_noise, t1, n3, s);
+    if (rc) return rc;
+  }
+  return PM_OK;
+}
+
 int pm_noise_truncate(pm_plan* fine, const void* noise_fine, pm_plan* coarse, void* noise_coarse, void* stream) {
   using namespace pm;
   if (!fine || !coarse) return set_error(PM_ERR_ARG, "pm_noise_truncate: null plan");

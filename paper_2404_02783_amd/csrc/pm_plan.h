@@ -186,5 +186,9 @@ int launch_grad_gather(const pm_plan* p, const void* h, const void* pos, int64_t
 int launch_div_newton(const pm_plan* p, int grad, double coef, hipStream_t s);
 int launch_ic_lattice_adj(const pm_plan* p, const void* lam_pos, const void* lam_mom, void* lam_psi,
                           double mom_factor, hipStream_t s);
+// h [6][N^3] (xx, yy, zz, xy, xz, yz) <- g dS/dh for the second-order source S.
+int launch_lpt2_source_adj(const pm_plan* p, void* h, const void* g, hipStream_t s);
+// y[0, count) += x[0, count) (the plan's dtype).
+int launch_accumulate(const pm_plan* p, void* y, const void* x, int64_t count, hipStream_t s);
 
 }  // namespace pm

@@ -51,15 +51,27 @@ __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx
   const bool nyq = (nx == -n / 2) || (ny == -n / 2) || (nz == n / 2);
   const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
   cx<T> out[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
-  if (!ADJ && sy.mode == 3 && !nyq && n2 > 0) {
-    // gradient of a field sampled on the lattice: i k_d coef w_hat / k^2
+  if (sy.mode == 3 && !nyq && n2 > 0) {
+    // gradient of a field sampled on the lattice: i k_d coef w_hat / k^2; adjoint:
+    // sum_d conj(i k_d) coef c_d / k^2
     const double s = 2.0 * kPi / n;
     const double kd[3] = {s * nx, s * ny, s * nz};
     const double f = sy.coef / (kd[0] * kd[0] + kd[1] * kd[1] + kd[2] * kd[2]);
-    const cx<T> w = ldc(c0 + idx);
+    if (ADJ) {
+      double qr = 0.0, qi = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) out[d] = mk(T(-kd[d] * f * (double)w.y), T(kd[d] * f * (double)w.x));
-  } else if (!nyq && n2 > 0) {
+      for (int d = 0; d < 3; ++d) {
+        const cx<T> cdd = ldc((d == 0 ? c0 : d == 1 ? c1 : c2) + idx);
+        qr += kd[d] * (double)cdd.x;
+        qi += kd[d] * (double)cdd.y;
+      }
+      out[0] = mk(T(f * qi), T(-f * qr));  // -i q
+    } else {
+      const cx<T> w = ldc(c0 + idx);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) out[d] = mk(T(-kd[d] * f * (double)w.y), T(kd[d] * f * (double)w.x));
+    }
+  } else if (sy.mode != 3 && !nyq && n2 > 0) {
     const double kmag = sy.kf * sqrt((double)n2);
     double pk = sy.amp * pow(kmag, sy.index);
     if (sy.pk_kind == PM_PK_EH98) {
@@ -75,7 +87,20 @@ __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx
     sincos(0.5 * (kx + ky + kz), &sn, &cs);
     const double f = amp * inv * sy.coef;
     const double kd[3] = {kx, ky, kz};
-    if (ADJ) {
+    if (ADJ && sy.mode != 0) {
+      // sum_d conj(h_d f e^{i phase}) c_d = f e^{-i phase} sum_d h_d c_d (h_d real:
+      // -k_d^2, or -k_a k_b for the pairs xy, xz, yz)
+      const cx<T> cd[3] = {ldc(c0 + idx), ldc(c1 + idx), ldc(c2 + idx)};
+      const int ia[3] = {0, 0, 1}, ib[3] = {1, 2, 2};
+      double qr = 0.0, qi = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double h = sy.mode == 1 ? -kd[d] * kd[d] : -kd[ia[d]] * kd[ib[d]];
+        qr += h * (double)cd[d].x;
+        qi += h * (double)cd[d].y;
+      }
+      out[0] = mk(T(f * (qr * cs + qi * sn)), T(f * (qi * cs - qr * sn)));
+    } else if (ADJ) {
       // sum_d conj(i k_d f e^{i phase}) c_d = f e^{-i phase} (-i) sum_d k_d c_d
       const cx<T> cd[3] = {ldc(c0 + idx), ldc(c1 + idx), ldc(c2 + idx)};
       double qr = 0.0, qi = 0.0;

@@ -34,6 +34,8 @@ at a time, or a property that holds at any size:
     truncation of that noise to 256^3, whole, against the sparse truncation;
   * every FFT launch shape the autotuner may pick at 1024^3 gives the same force, bit
     for bit;
+  * the adjoint of the 2LPT ICs at 1024^3 against an exact central difference (the
+    set is quadratic in the noise);
   * paired-and-fixed noise at 1024^3: moduli and phases of every mode against an
     independent FFT, the partner exactly negated;
   * the linear Poisson-gauge shift at a = 1 at 1024^3, and the combination with it
@@ -609,6 +611,41 @@ def test_fft_launch_shapes_full_size(plan):
         pm.pm_plan_set_tuning(plan, [0, 0, 0, 0])
     assert tried >= 12
     del delta, force, ref
+
+
+def test_ic_2lpt_adjoint_full_size_exact_central_difference(plan):
+    """The second-order set is quadratic in the noise, so for any step e the central
+    difference (F(w + e v) - F(w - e v)) / 2e is the exact directional derivative:
+    <lam, that> must equal <adjoint(lam), v> at 1024^3 (e = 1 keeps FP32 differences
+    well resolved; positions are differenced with the minimum image).  The position
+    cotangent sits on 4106 sampled particles only and equals their position
+    difference there (a coordinate near 1000 carries an FP32 rounding of ~3e-5 cell,
+    which a dense random cotangent would sum over 3 x 2^30 terms into an answer that
+    itself cancels); the momentum cotangent is dense and random."""
+    dev = plan.device
+    icp, c = _eh98_ics()
+    gen = torch.Generator(device=dev).manual_seed(99)
+    w = torch.randn((N, N, N), generator=gen, device=dev)
+    v = torch.randn((N, N, N), generator=gen, device=dev)
+    idx = _sample_particles(4096, 89).to(dev)
+    lam_mom = torch.randn((3, N ** 3), generator=gen, device=dev)
+    disp = plan.mesh(3)
+    pos1, mom1, pos2, mom2 = (plan.particles() for _ in range(4))
+    pm.pm_ic_2lpt(plan, w + v, icp, disp, pos1, mom1)
+    pm.pm_ic_2lpt(plan, w - v, icp, disp, pos2, mom2)
+    dpos = pos1.sub_(pos2).add_(N / 2).remainder_(N).sub_(N / 2)
+    dmom = mom1.sub_(mom2)
+    lam_pos = torch.zeros((3, N ** 3), device=dev)
+    lam_pos[:, idx] = dpos[:, idx]
+    want_p = float(torch.sum(lam_pos[:, idx].double() * dpos[:, idx].double())) / 2.0
+    want_m = float(torch.sum(lam_mom.double() * dmom.double())) / 2.0
+    del pos1, mom1, pos2, mom2, disp, dpos, dmom
+    zero = torch.zeros_like(lam_mom)
+    got_p = float(torch.sum(pm.pm_ic_2lpt_adjoint(plan, w, icp, lam_pos, zero).double() * v.double()))
+    got_m = float(torch.sum(pm.pm_ic_2lpt_adjoint(plan, w, icp, zero, lam_mom).double() * v.double()))
+    torch.cuda.synchronize()
+    assert abs(got_p - want_p) < 1e-4 * abs(want_p)
+    assert abs(got_m - want_m) < 1e-4 * abs(want_m)
 
 
 def test_noise_truncate_full_size(plan):
