@@ -23,9 +23,11 @@ def pk_loss(pk: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
     return (((pk[sel] - target[sel]) / target[sel]) ** 2).sum()
 
 
-def forward_pk(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, grad: str = "spectral"):
-    """Final-time P(k) of a Newtonian run started from ``noise``."""
-    pos, mom = ics.zeldovich(noise, p)
+def forward_pk(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, grad: str = "spectral",
+               lpt_order: int = 1):
+    """Final-time P(k) of a Newtonian run started from ``noise`` (Zel'dovich ICs, or
+    the second-order set for lpt_order = 2)."""
+    pos, mom = ics.zeldovich(noise, p) if lpt_order == 1 else ics.lpt2(noise, p)
     force = integrate.NewtonForce(p.n, p.cosmo, grad)
     pos, mom = integrate.run_kdk(pos, mom, a_steps, force, p.n, p.cosmo)
     delta = cic.deposit_delta(pos, p.n)
@@ -33,16 +35,16 @@ def forward_pk(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, grad:
 
 
 def loss(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, target: torch.Tensor,
-         grad: str = "spectral") -> torch.Tensor:
-    _, pk, _ = forward_pk(noise, p, a_steps, n_bins, grad)
+         grad: str = "spectral", lpt_order: int = 1) -> torch.Tensor:
+    _, pk, _ = forward_pk(noise, p, a_steps, n_bins, grad, lpt_order)
     return pk_loss(pk, target)
 
 
 def loss_and_grad(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, target: torch.Tensor,
-                  grad: str = "spectral"):
+                  grad: str = "spectral", lpt_order: int = 1):
     """(L, dL/dnoise) by reverse-mode differentiation of the FP64 forward model."""
     w = noise.detach().to(torch.float64).clone().requires_grad_(True)
-    val = loss(w, p, a_steps, n_bins, target, grad)
+    val = loss(w, p, a_steps, n_bins, target, grad, lpt_order)
     (g,) = torch.autograd.grad(val, w)
     return float(val.detach()), g
 

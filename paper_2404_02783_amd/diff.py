@@ -10,8 +10,9 @@ Reverse pass: ``pk_adjoint`` gives dL/dx_n from dL/dP; then, segment by segment
 from the end, the forward cycles of the segment are recomputed from a checkpoint
 of (pos, mom) taken every ``ckpt_every`` cycles, keeping each cycle's input
 positions and force meshes, and ``pm_step_adjoint`` pulls the cotangents back
-through the cycles in reverse order; ``pm_ic_zeldovich_adjoint`` finally maps
-them onto the noise.  Memory: n/ckpt_every checkpoints of (pos, mom) plus one
+through the cycles in reverse order; ``pm_ic_zeldovich_adjoint`` (or
+``pm_ic_2lpt_adjoint`` for the second-order start, ``Schedule.lpt_order = 2``)
+finally maps them onto the noise.  Memory: n/ckpt_every checkpoints of (pos, mom) plus one
 segment's positions and force meshes.
 """
 from __future__ import annotations
@@ -21,7 +22,8 @@ from dataclasses import dataclass
 import torch
 
 from . import (FIDUCIAL, ICParams, PM_GRAD_SPECTRAL, Plan, StepParams, kdk_factors, newton_params, pk_adjoint,
-               pk_estimate, pm_deposit, pm_ic_zeldovich, pm_ic_zeldovich_adjoint, pm_step, pm_step_adjoint)
+               pk_estimate, pm_deposit, pm_ic_2lpt, pm_ic_2lpt_adjoint, pm_ic_zeldovich, pm_ic_zeldovich_adjoint,
+               pm_step, pm_step_adjoint)
 
 __all__ = ["Schedule", "ForwardTape", "forward", "backward", "GraphedModel", "PowerSpectrumModel",
            "power_spectrum_model"]
@@ -34,6 +36,7 @@ class Schedule:
     a_steps: list
     cosmo: object = FIDUCIAL
     grad: int = PM_GRAD_SPECTRAL
+    lpt_order: int = 1   # 1: Zel'dovich ICs, 2: second-order (2LPT) ICs
 
     def cycles(self):
         out = []
@@ -54,17 +57,21 @@ class ForwardTape:
     ckpt_every: int
     checkpoints: dict    # cycle index -> (pos, mom) before that cycle
     pos_final: torch.Tensor
+    noise: torch.Tensor = None   # kept for the 2LPT adjoint (the set is quadratic in it)
+    lpt_order: int = 1
 
 
 def forward(plan: Plan, noise: torch.Tensor, ic: ICParams, schedule: Schedule, n_bins: int, ckpt_every: int = 5):
     """Run the forward model; returns ((k_mean, pk, n_modes), tape)."""
     if ckpt_every < 1:
         raise ValueError("ckpt_every must be >= 1")
+    if schedule.lpt_order not in (1, 2):
+        raise ValueError("lpt_order must be 1 or 2")
     n = plan.n
     pos = torch.empty((3, n ** 3), dtype=plan.dtype, device=plan.device)
     mom = torch.empty_like(pos)
     disp = plan.mesh(3)
-    pm_ic_zeldovich(plan, noise, ic, disp, pos, mom)
+    (pm_ic_zeldovich if schedule.lpt_order == 1 else pm_ic_2lpt)(plan, noise, ic, disp, pos, mom)
     del disp
     steps = schedule.cycles()
     force = plan.mesh(3)
@@ -75,7 +82,8 @@ def forward(plan: Plan, noise: torch.Tensor, ic: ICParams, schedule: Schedule, n
         pm_step(plan, pos, mom, st, force)
     delta = pm_deposit(plan, pos)
     k, pk, cnt = pk_estimate(plan, delta, n_bins)
-    return (k, pk, cnt), ForwardTape(plan, ic, steps, n_bins, ckpt_every, ckpts, pos)
+    return (k, pk, cnt), ForwardTape(plan, ic, steps, n_bins, ckpt_every, ckpts, pos,
+                                     noise if schedule.lpt_order == 2 else None, schedule.lpt_order)
 
 
 def backward(tape: ForwardTape, dpk: torch.Tensor) -> torch.Tensor:
@@ -102,6 +110,8 @@ def backward(tape: ForwardTape, dpk: torch.Tensor) -> torch.Tensor:
             pm_step_adjoint(plan, xs[j - s0], tape.steps[j], lam_pos, lam_mom, force=fs[j - s0],
                             mesh_scratch=scratch)
             xs[j - s0] = fs[j - s0] = None
+    if tape.lpt_order == 2:
+        return pm_ic_2lpt_adjoint(plan, tape.noise, tape.ic, lam_pos, lam_mom)
     return pm_ic_zeldovich_adjoint(plan, tape.ic, lam_pos, lam_mom)
 
 
@@ -115,6 +125,7 @@ class GraphedModel:
     def __init__(self, plan: Plan, ic: ICParams, schedule: Schedule, n_bins: int, ckpt_every: int = 5):
         self.plan, self.ic, self.n_bins, self.ckpt = plan, ic, n_bins, ckpt_every
         self.steps = schedule.cycles()
+        self.lpt_order = schedule.lpt_order
         n3 = plan.n ** 3
         dev, dt = plan.device, plan.dtype
         part = lambda: torch.empty((3, n3), dtype=dt, device=dev)  # noqa: E731
@@ -130,11 +141,13 @@ class GraphedModel:
         self.scratch = torch.empty(3 * n3, dtype=dt, device=dev)
         self.dpk = torch.zeros(n_bins, dtype=torch.float64, device=dev)
         self.lam_noise = plan.mesh()
+        self.ic_scratch = plan.mesh(9) if self.lpt_order == 2 else None
         self.out = None
         self.g_fwd = self.g_bwd = None
 
     def _forward(self):
-        pm_ic_zeldovich(self.plan, self.noise, self.ic, self.disp, self.pos, self.mom)
+        (pm_ic_zeldovich if self.lpt_order == 1 else pm_ic_2lpt)(self.plan, self.noise, self.ic, self.disp, self.pos,
+                                                                  self.mom)
         for j, st in enumerate(self.steps):
             if j in self.ckpts:
                 self.ckpts[j][0].copy_(self.pos)
@@ -158,7 +171,10 @@ class GraphedModel:
             for j in reversed(range(s0, s1)):
                 pm_step_adjoint(plan, self.seg_x[j - s0], self.steps[j], self.lam_pos, self.lam_mom,
                                 force=self.seg_f[j - s0], mesh_scratch=self.scratch)
-        pm_ic_zeldovich_adjoint(plan, self.ic, self.lam_pos, self.lam_mom, self.disp, self.lam_noise)
+        if self.lpt_order == 2:
+            pm_ic_2lpt_adjoint(plan, self.noise, self.ic, self.lam_pos, self.lam_mom, self.ic_scratch, self.lam_noise)
+        else:
+            pm_ic_zeldovich_adjoint(plan, self.ic, self.lam_pos, self.lam_mom, self.disp, self.lam_noise)
 
     def capture(self):
         """Warm both passes eagerly, then capture each into its own graph."""

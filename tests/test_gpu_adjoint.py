@@ -195,6 +195,37 @@ def test_loss_gradient_matches_oracle(dt):
         assert rel_l2(w.grad, want) < 1e-3
 
 
+@pytest.mark.parametrize("graphed", [False, True])
+def test_loss_gradient_with_2lpt_start_matches_oracle(graphed):
+    """The same loss and gradient from second-order ICs (FP64), through the autograd
+    function and through the graph-captured model."""
+    dev = _dev()
+    n, box, nb = 32, 500.0, 16
+    p, icp, a_steps, noise = _model(n, box, 0.05, 0.5, 6, 43)
+    _, target, _ = oadj.forward_pk(torch.from_numpy(si.white_noise(n, 44)), p, a_steps, nb, lpt_order=2)
+    val, want = oadj.loss_and_grad(noise, p, a_steps, nb, target, lpt_order=2)
+    _, want_za = oadj.loss_and_grad(noise, p, a_steps, nb, target)
+    plan = pm.Plan(n, box, torch.float64)
+    sched = diff.Schedule(a_steps, lpt_order=2)
+    t = target.to(dev)
+    if graphed:
+        model = diff.GraphedModel(plan, icp, sched, nb, 4).capture()
+        pk = model.forward(noise.to(dev))
+        dpk = 2.0 * (pk - t) / t ** 2
+        got_val = float((((pk - t) / t) ** 2).sum())
+        got = model.backward(dpk).clone()
+    else:
+        w = noise.to(dev).requires_grad_(True)
+        pk = diff.power_spectrum_model(w, plan, icp, sched, nb, 4)
+        loss = (((pk - t) / t) ** 2).sum()
+        loss.backward()
+        got_val, got = float(loss), w.grad
+    torch.cuda.synchronize()
+    assert got_val == pytest.approx(val, rel=1e-9)
+    assert rel_l2(got, want) < 1e-8
+    assert rel_l2(want_za, want) > 1e-6   # the second-order start changes the gradient
+
+
 def test_checkpoint_interval_does_not_change_gradient():
     dev = _dev()
     n, box, nb = 16, 300.0, 8
