@@ -480,6 +480,9 @@ def main():
     ap.add_argument("--adjoint-ckpt", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the estimator/combination timings, the 128^3 adjoint and the ensemble legs")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the FFT launch shapes of the 1024^3 plan (per pass; measured slower for the "
+                         "whole step than the built-in shapes, so off by default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -516,10 +519,14 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] initial conditions ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
-    # FFT launch shapes of the 1024^3 plan, measured once before the run (setup, untimed)
-    scratch = plan.mesh()
-    tuned, tuned_ms = pm.pm_plan_autotune(plan, reps=3, use_cache=False, mesh_scratch=scratch)
-    del scratch
+    # FFT launch shapes of the 1024^3 plan: built-in, or measured once before the run
+    # (setup, untimed) with --autotune
+    if not args.autotune:
+        tuned, tuned_ms = pm.pm_plan_get_tuning(plan), [-1.0] * 4
+    else:
+        scratch = plan.mesh()
+        tuned, tuned_ms = pm.pm_plan_autotune(plan, reps=3, use_cache=False, mesh_scratch=scratch)
+        del scratch
     print(f"[bench] FFT launch shapes {tuned} ({[round(m, 3) for m in tuned_ms]} ms)", file=sys.stderr, flush=True)
 
     total = max(50, args.warmup + args.steps)
@@ -586,7 +593,8 @@ def main():
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBps": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "kernels": kernels,
-        "fft_tuning": {"slots": list(pm.TUNING_SLOTS), "shapes": tuned, "best_ms": [round(m, 4) for m in tuned_ms]},
+        "fft_tuning": {"slots": list(pm.TUNING_SLOTS), "shapes": tuned, "autotuned": bool(args.autotune),
+                       "best_ms": [round(m, 4) for m in tuned_ms]},
         "adjoint_forward_ratio": None,
     }
     if not args.no_extras:
