@@ -76,3 +76,18 @@ def test_host_power_amplitudes_match_oracle():
     assert amp == pytest.approx(ocm.eh98_normalised(c65, 0.965, 0.81).amp, rel=1e-8)
     a_pl = pm.power_law_amplitude(16, 1000.0, 0.2, -2.0)
     assert a_pl == pytest.approx(oics.powerlaw_for_rms_displacement(16, 1000.0, 0.2).amp, rel=1e-12)
+
+
+def test_every_entry_point_has_a_binding_of_the_same_name():
+    # plan lifetime and the error string are covered by Plan and PMError
+    by_class = {"pm_plan_create", "pm_plan_create_batch", "pm_plan_destroy", "pm_plan_workspace_bytes",
+                "pm_plan_workspace_bytes_batch", "pm_last_error"}
+    missing = []
+    for n in _declared():
+        if n in by_class:
+            continue
+        cands = (n, n.replace("pm_cosmo_", "cosmo_"), n.replace("pm_power_", "power_"), n.replace("pm_", "", 1))
+        if not any(callable(getattr(pm, c, None)) for c in cands):
+            missing.append(n)
+    assert missing == []
+    assert callable(pm.Plan) and issubclass(pm.PMError, RuntimeError)
