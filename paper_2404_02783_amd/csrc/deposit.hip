@@ -5,9 +5,11 @@
 //   k_deposit        one thread per particle, 8 global float atomics each (any np);
 //   k_deposit_tiled  for a full Lagrangian lattice run (np = N^3): a workgroup owns a
 //                    Lagrangian tile, accumulates its particles in an LDS window in
-//                    64-bit fixed point (LDS integer atomics run ~20x faster than LDS
-//                    float atomics on gfx950), then adds each non-empty window cell to
-//                    the mesh with one global float atomic.
+//                    32-bit fixed point at scale 2^21 (LDS integer atomics run ~20x
+//                    faster than LDS float atomics on gfx950), then adds each non-empty
+//                    window cell to the mesh with one global float atomic.  A window
+//                    that would exceed the LDS capacity shrinks to fit_box's box of
+//                    the same proportions; particles outside it use global atomics.
 // The mesh is pre-filled with -1, so it holds delta = rho/nbar - 1 afterwards.
 #include <math.h>
 

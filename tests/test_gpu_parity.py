@@ -52,10 +52,11 @@ DTYPES = [torch.float32, torch.float64]
                                          (128, 128 ** 3, "lattice"), (128, 128 ** 3, "lattice_far"),
                                          (128, 128 ** 3, "lattice_vfar"), (256, 256 ** 3, "lattice")])
 def test_deposit(dt, n, np_, kind):
-    # N^3 lattice runs at N >= 128 take the LDS-window path in FP32 (tiles in 64 colour
-    # classes, windows added without atomics); "lattice_far" moves particles up to 5
-    # cells, so tile windows exceed the LDS capacity and the overflow list runs too;
-    # "lattice_vfar" moves them up to 20 cells, beyond the colour confinement box.
+    # FP32 N^3 lattice runs at N >= 64 take the tiled path: each Lagrangian tile sums its
+    # particles in an LDS window (32-bit fixed point, scale 2^21) that is flushed with one
+    # global float atomic per non-empty cell.  "lattice_far" moves particles up to 5
+    # cells, so windows outgrow the LDS capacity and shrink to fit_box's box, and the
+    # particles outside it take global atomics; "lattice_vfar" moves them up to 20 cells.
     dev = _dev()
     if kind == "lattice":
         x = si.lattice_jitter_particles(n, 3, 0.7, dtype=np.float64)
@@ -79,7 +80,8 @@ def test_deposit(dt, n, np_, kind):
 
 
 def test_deposit_batched_boxes():
-    """A batch of three 128^3 lattice boxes (coloured path) against the oracle per box."""
+    """A batch of three 128^3 lattice boxes (tiled LDS-window path, box index in the grid)
+    against the oracle per box."""
     dev = _dev()
     n = 128
     xs = [si.lattice_jitter_particles(n, 40 + b, 0.7 + 3 * b, dtype=np.float64) for b in range(3)]
