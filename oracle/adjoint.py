@@ -49,6 +49,43 @@ def loss_and_grad(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, ta
     return float(val.detach()), g
 
 
+def loss_and_grad_by_cycles(noise: torch.Tensor, p: ics.ICParams, a_steps, n_bins: int, target: torch.Tensor,
+                            grad: str = "spectral", lpt_order: int = 1):
+    """(L, dL/dnoise) as ``loss_and_grad``, with memory bounded by one cycle.
+
+    The leapfrog is written as its chain of force-kick-drift cycles (cycle j: force
+    at x_j, kick K2(j-1) + K1(j), drift Dr(a_j, a_j+1); the closing half-kick does not
+    move the particles, so P(k) does not see it).  The forward keeps every cycle's
+    input (x, p); the reverse pass takes the cotangent of the final positions from
+    the P(k) loss, pulls it back through the cycles from the last to the first with
+    ``step_vjp`` (autograd of one cycle), and through the ICs.  Mathematically the
+    same derivative as reverse mode over the whole run; for meshes whose whole-run
+    graph does not fit in host memory."""
+    w = noise.detach().to(torch.float64)
+    ic = (lambda w_: ics.zeldovich(w_, p)) if lpt_order == 1 else (lambda w_: ics.lpt2(w_, p))
+    pos, mom = ic(w)
+    force = integrate.NewtonForce(p.n, p.cosmo, grad)
+    cycles = []
+    k2_prev = 0.0
+    for a0, a1 in zip(a_steps[:-1], a_steps[1:]):
+        k1, dr, k2 = integrate.kdk_factors(p.cosmo, a0, a1)
+        cycles.append((k2_prev + k1, dr))
+        k2_prev = k2
+    states = []
+    for kick, drift in cycles:
+        states.append((pos, mom))
+        pos, mom = integrate.force_then_kick_drift(pos, mom, kick, drift, force, 0.0, p.n)
+    xf = pos.clone().requires_grad_(True)
+    _, pk, _ = estimators.power_spectrum(cic.deposit_delta(xf, p.n), p.box, n_bins)
+    val = pk_loss(pk, target)
+    (lam_x,) = torch.autograd.grad(val, xf)
+    lam_p = torch.zeros_like(lam_x)
+    for (x, v), (kick, drift) in zip(reversed(states), reversed(cycles)):
+        lam_x, lam_p = step_vjp(x, v, kick, drift, p.n, p.cosmo, lam_x, lam_p, grad)
+    (g,) = vjp(ic, (w,), (lam_x, lam_p))
+    return float(val.detach()), g
+
+
 def vjp(fn, primals, cotangent):
     """Vector-Jacobian product of ``fn`` at ``primals`` (a tuple of tensors)."""
     xs = tuple(t.detach().clone().requires_grad_(True) for t in primals)

@@ -326,3 +326,73 @@ def test_2lpt_ic_adjoint_matches_oracle(dt, tol, n, kind):
     za = pm.pm_ic_zeldovich_adjoint(plan, icp, lp.to(dev), lm.to(dev))
     torch.cuda.synchronize()
     assert rel_l2(za.reshape(-1), want.reshape(-1)) > 100 * tol
+
+
+# ------------------------------------------ the differentiable configuration --
+
+def _config5():
+    """128^3 particles on a 128^3 mesh, L = 1000 Mpc/h, EH98 no-wiggle LCDM ICs
+    (n_s = 0.965, sigma8 = 0.81), 20 log steps a = 0.05 -> 1, P(k) in 64 bins, target
+    spectrum from seed 6, noise from seed 5."""
+    n, box, nb = 128, 1000.0, 64
+    c = ocm.Cosmo(n_s=0.965)
+    p = oics.ICParams(n=n, box=box, a_init=0.05, power=ocm.eh98_normalised(c, 0.965, 0.81), a_norm=1.0, cosmo=c)
+    icp = pm.ICParams(pk_kind=pm.PM_PK_EH98, amp=pm.power_eh98_amplitude(0.965, 0.81), index=0.965, a_init=0.05,
+                      a_norm=1.0, cosmo=pm.FIDUCIAL)
+    a_steps = ocm.log_steps(0.05, 1.0, 20)
+    noise = torch.from_numpy(si.white_noise(n, 5)).float()
+    _, target, _ = oadj.forward_pk(torch.from_numpy(si.white_noise(n, 6)), p, a_steps, nb)
+    return n, box, nb, p, icp, a_steps, noise, target
+
+
+@pytest.mark.timeout(900)
+def test_differentiable_configuration_gradient_matches_oracle():
+    """The differentiable configuration at its own size, checkpoints every 5 cycles:
+    FP32 and FP64 gradients of L = sum_b ((P_b - T_b)/T_b)^2 with respect to the noise
+    against the oracle's FP64 reverse-mode gradient (taken cycle by cycle)."""
+    dev = _dev()
+    n, box, nb, p, icp, a_steps, noise, target = _config5()
+    val, want = oadj.loss_and_grad_by_cycles(noise.double(), p, a_steps, nb, target)
+    t = target.to(dev)
+    for dt, tol_val, tol in ((torch.float64, 1e-9, 1e-8), (torch.float32, 1e-3, 1e-3)):
+        plan = pm.Plan(n, box, dt)
+        w = noise.to(dt).to(dev).requires_grad_(True)
+        pk = diff.power_spectrum_model(w, plan, icp, diff.Schedule(a_steps), nb, 5)
+        loss = (((pk - t) / t) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        assert float(loss.detach()) == pytest.approx(val, rel=tol_val), dt
+        assert rel_l2(w.grad, want) < tol, dt
+        del plan, w, pk, loss
+
+
+def test_differentiable_configuration_central_differences_fp64():
+    """32 noise entries of the differentiable configuration: the FP64 gradient (reverse
+    pass with checkpoints every 5 cycles) against central differences of the FP64
+    forward model, h = 1e-4.  A perturbation moves every particle by ~1e-7 cells, so
+    the few particles it pushes across a cell edge (a kink of the CIC weights) change
+    the difference by far less than the bar."""
+    dev = _dev()
+    n, box, nb, p, icp, a_steps, noise, target = _config5()
+    plan = pm.Plan(n, box, torch.float64)
+    sched = diff.Schedule(a_steps)
+    t = target.to(dev)
+    w0 = noise.double().to(dev)
+
+    def loss_of(wv):
+        (_, pk, _), _ = diff.forward(plan, wv, icp, sched, nb, 5)
+        return float((((pk - t) / t) ** 2).sum())
+
+    w = w0.clone().requires_grad_(True)
+    pk = diff.power_spectrum_model(w, plan, icp, sched, nb, 5)
+    ((((pk - t) / t) ** 2).sum()).backward()
+    g = w.grad.detach().reshape(-1).cpu()
+    gmax = float(g.abs().max())
+    idx = si.rng(65).choice(n ** 3, size=32, replace=False)
+    h = 1e-4
+    for j in idx:
+        e = torch.zeros(n ** 3, dtype=torch.float64)
+        e[j] = h
+        e = e.reshape(w0.shape).to(dev)
+        fd = (loss_of(w0 + e) - loss_of(w0 - e)) / (2 * h)
+        assert abs(fd - float(g[j])) <= 1e-4 * max(abs(float(g[j])), 1e-2 * gmax), (int(j), fd, float(g[j]))
