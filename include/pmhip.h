@@ -254,6 +254,23 @@ int pm_step(pm_plan* plan, void* pos, void* mom, int64_t np, const pm_step_param
 int pm_step_adjoint(pm_plan* plan, const void* pos, int64_t np, const pm_step_params* st, const void* force,
                     void* mesh_scratch, void* lam_pos, void* lam_mom, void* stream);
 
+/* Allocation-free variant of pm_step_adjoint, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and results as pm_step_adjoint without mesh_scratch:
+ * the 3 N^3 reals of scratch (6 N^3 when force is NULL) come from a static device
+ * array of PM_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (its address is taken at plan creation).  The call makes no
+ * allocation (with the plan's profiler off, the default; pm_profile_enable creates
+ * HIP events).  Limit: PM_ERR_NOMEM when pm_step_adjoint_noalloc_bytes exceeds
+ * PM_STATIC_SCRATCH_BYTES (64 MiB: N <= 128 in FP32, and in FP64 with the force
+ * meshes given).  All calls on one GPU share the array, which keeps the last call's
+ * contents (each call clears what it needs): calls that overlap in time on one GPU,
+ * from any plan or stream, race and must be serialised by the caller. */
+#define PM_STATIC_SCRATCH_BYTES (64u << 20)
+size_t pm_step_adjoint_noalloc_bytes(int n_mesh, int dtype, int with_force);
+int pm_step_adjoint_noalloc(pm_plan* plan, const void* pos, int64_t np, const pm_step_params* st, const void* force,
+                            void* lam_pos, void* lam_mom, void* stream);
+
 /* eq. xiGR and eq. combined: xi = minimum-image (x_gr - x_newton) on the coarse
  * lattice (n_coarse^3 particles, coarse cells), interpolated with CIC weights in
  * Lagrangian coordinates to the fine lattice (n_fine^3 particles; fine particle j

@@ -18,7 +18,8 @@ __all__ = [
     "PMError", "lib", "SolveParams", "StepParams", "Cosmology", "ICParams", "Plan",
     "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "displacement_add", "pm_xi_linear",
     "pk_estimate", "pk_cross_estimate", "bias_fit", "bk_estimate",
-    "pm_step_adjoint", "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
+    "pm_step_adjoint", "pm_step_adjoint_noalloc", "pm_step_adjoint_noalloc_bytes", "PM_STATIC_SCRATCH_BYTES",
+    "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
     "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_2lpt_adjoint", "pm_ic_gauge", "pm_noise_fix",
     "pm_plan_tuning_candidates", "pm_plan_get_tuning", "pm_plan_set_tuning", "pm_plan_autotune", "TUNING_SLOTS",
     "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
@@ -35,6 +36,7 @@ PM_F32, PM_F64 = 0, 1
 PM_NEWTON, PM_POISSON_GAUGE = 0, 1
 PM_GRAD_SPECTRAL, PM_GRAD_FD2, PM_GRAD_FD1 = 0, 1, 2
 PM_PK_POWERLAW, PM_PK_EH98 = 0, 1
+PM_STATIC_SCRATCH_BYTES = 64 << 20
 
 _c_int, _c_double, _c_void_p, _c_int64, _c_size_t = (
     ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t)
@@ -102,6 +104,9 @@ def _declare(l):
                                  _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_size_t, _c_void_p]),
         "pm_step_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int64, P(StepParams), _c_void_p, _c_void_p, _c_void_p,
                                      _c_void_p, _c_void_p]),
+        "pm_step_adjoint_noalloc": (_c_int, [_c_void_p, _c_void_p, _c_int64, P(StepParams), _c_void_p, _c_void_p,
+                                             _c_void_p, _c_void_p]),
+        "pm_step_adjoint_noalloc_bytes": (_c_size_t, [_c_int, _c_int, _c_int]),
         "pk_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int64, _c_int, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_zeldovich": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
         "pm_ic_2lpt": (_c_int, [_c_void_p, _c_void_p, P(ICParams), _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
@@ -304,6 +309,27 @@ def pm_step_adjoint(plan: Plan, pos, st: StepParams, lam_pos, lam_mom, force=Non
                                  _ptr(force, plan.dtype, "force"), _ptr(mesh_scratch, plan.dtype, "mesh_scratch"),
                                  _ptr(lam_pos, plan.dtype, "lam_pos"), _ptr(lam_mom, plan.dtype, "lam_mom"),
                                  _stream()))
+
+
+def pm_step_adjoint_noalloc_bytes(n: int, dtype, with_force: bool) -> int:
+    """Scratch bytes pm_step_adjoint_noalloc takes from the library's static array."""
+    cd = PM_F32 if dtype == torch.float32 else PM_F64
+    return int(lib().pm_step_adjoint_noalloc_bytes(int(n), cd, 1 if with_force else 0))
+
+
+def pm_step_adjoint_noalloc(plan: Plan, pos, st: StepParams, lam_pos, lam_mom, force=None):
+    """pm_step_adjoint without a scratch argument: the library's static device scratch
+    stands in for it, and the call allocates nothing (for graph capture or loops that
+    must not allocate).  Calls that overlap in time on one GPU race."""
+    n3 = plan.n ** 3
+    if force is not None:
+        _need(force, 3 * n3, "force")
+    np_ = pos.shape[-1]
+    for t, nm in ((lam_pos, "lam_pos"), (lam_mom, "lam_mom")):
+        _need(t, 3 * np_, nm)
+    _check(lib().pm_step_adjoint_noalloc(plan.handle, _ptr(pos, plan.dtype, "pos"), np_, ctypes.byref(st),
+                                         _ptr(force, plan.dtype, "force"), _ptr(lam_pos, plan.dtype, "lam_pos"),
+                                         _ptr(lam_mom, plan.dtype, "lam_mom"), _stream()))
 
 
 def pk_adjoint(plan: Plan, pos, n_bins: int, dpk, lam_pos=None):

@@ -45,6 +45,36 @@ static int check_plan(const pm_plan* p) {
   return PM_OK;
 }
 
+// Scratch of pm_step_adjoint_noalloc: one file-scope device array, which every GPU the
+// library runs on holds (its own copy at its own address) until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device memory: the
+// device address of each GPU's copy is taken once per device with hipGetSymbolAddress
+// (static_scratch_init, called at plan creation with that device current) and only
+// that address is handed to kernels.
+constexpr size_t kStaticScratchBytes = size_t(PM_STATIC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return set_error(PM_ERR_ARG, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return PM_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_check(e, "static scratch address");
+  if (!ptr) return set_error(PM_ERR_HIP, "static scratch address: null");
+  g_scratch_dev[device] = ptr;
+  return PM_OK;
+}
+
+static void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
 // Every entry point other than pm_step may reuse the workspace: the density left for
 // the next cycle is discarded.
 static void drop_density(pm_plan* p) {
@@ -208,6 +238,7 @@ int pm_plan_create_batch(pm_plan** out, int n_mesh, double box_mpch, int dtype, 
     else
       rc = hip_check(hipMemset(p->guard, 0, 4 * sizeof(unsigned)), "pm_plan_create: guard init");
   }
+  if (rc == PM_OK) rc = static_scratch_init(p->device);
   if (rc == PM_OK) {
     p->sums_cap = (size_t)n_batch * 3 * (size_t)std::max(n_mesh, 512) + 2 * 4096;
     if (hipMalloc(&p->sums, p->sums_cap * sizeof(double)) != hipSuccess)
@@ -509,17 +540,20 @@ int pm_step(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* 
   return PM_OK;
 }
 
-int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, const void* force,
-                    void* mesh_scratch, void* lam_pos, void* lam_mom, void* stream) {
-  PM_TRY(check_single(p, "pm_step_adjoint"));
+// Argument checks shared by pm_step_adjoint and its allocation-free variant.
+static int check_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, void* lam_pos,
+                              void* lam_mom, const char* who) {
+  PM_TRY(check_single(p, who));
   drop_density(p);
-  if (np < 0) return set_error(PM_ERR_ARG, "pm_step_adjoint: negative particle count");
-  if (!st || !mesh_scratch || (np > 0 && (!pos || !lam_pos || !lam_mom)))
-    return set_error(PM_ERR_ARG, "pm_step_adjoint: null pointer");
-  if (st->solve.kind != PM_NEWTON)
-    return set_error(PM_ERR_ARG, "pm_step_adjoint: only the Newtonian step has an adjoint");
-  PM_TRY(check_solve_params(&st->solve, nullptr, "pm_step_adjoint"));
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (np < 0) return set_error(PM_ERR_ARG, "%s: negative particle count", who);
+  if (!st || (np > 0 && (!pos || !lam_pos || !lam_mom))) return set_error(PM_ERR_ARG, "%s: null pointer", who);
+  if (st->solve.kind != PM_NEWTON) return set_error(PM_ERR_ARG, "%s: only the Newtonian step has an adjoint", who);
+  return check_solve_params(&st->solve, nullptr, who);
+}
+
+// The adjoint cycle on `mesh_scratch` (3 N^3 reals, or 6 N^3 when force is null).
+static int step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, const void* force,
+                        void* mesh_scratch, void* lam_pos, void* lam_mom, hipStream_t s) {
   const int64_t n3 = (int64_t)p->n * p->n * p->n;
   const size_t mesh_bytes = (size_t)n3 * p->esize;
   char* g = static_cast<char*>(mesh_scratch);
@@ -539,6 +573,33 @@ int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_param
   PM_TRY(launch_div_newton(p, st->solve.grad, 1.5 * st->solve.omega_m / (double)n3, s));
   PM_TRY(fft3_c2r(p, 1, cbuf(p, 0), 0, g, s));
   return launch_grad_gather(p, g, pos, np, (double)n3 / (double)np, lam_pos, true, s);
+}
+
+int pm_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, const void* force,
+                    void* mesh_scratch, void* lam_pos, void* lam_mom, void* stream) {
+  PM_TRY(check_step_adjoint(p, pos, np, st, lam_pos, lam_mom, "pm_step_adjoint"));
+  if (!mesh_scratch) return set_error(PM_ERR_ARG, "pm_step_adjoint: null pointer");
+  return step_adjoint(p, pos, np, st, force, mesh_scratch, lam_pos, lam_mom, static_cast<hipStream_t>(stream));
+}
+
+size_t pm_step_adjoint_noalloc_bytes(int n_mesh, int dtype, int with_force) {
+  if (!mesh_supported(n_mesh) || (dtype != PM_F32 && dtype != PM_F64)) return 0;
+  return (with_force ? 3 : 6) * (size_t)n_mesh * n_mesh * n_mesh * (dtype == PM_F32 ? 4 : 8);
+}
+
+int pm_step_adjoint_noalloc(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, const void* force,
+                            void* lam_pos, void* lam_mom, void* stream) {
+  PM_TRY(check_step_adjoint(p, pos, np, st, lam_pos, lam_mom, "pm_step_adjoint_noalloc"));
+  const size_t need = pm_step_adjoint_noalloc_bytes(p->n, p->dtype, force != nullptr);
+  if (need > kStaticScratchBytes)
+    return set_error(PM_ERR_NOMEM,
+                     "pm_step_adjoint_noalloc: N = %d (%s, force %s) needs %zu bytes of scratch, more than the "
+                     "static %zu; use pm_step_adjoint with a caller workspace",
+                     p->n, p->dtype == PM_F32 ? "FP32" : "FP64", force ? "given" : "recomputed", need,
+                     kStaticScratchBytes);
+  void* g = static_scratch(p->device);
+  if (!g) return set_error(PM_ERR_STATE, "pm_step_adjoint_noalloc: no static scratch on device %d", p->device);
+  return step_adjoint(p, pos, np, st, force, g, lam_pos, lam_mom, static_cast<hipStream_t>(stream));
 }
 
 int pk_adjoint(pm_plan* p, const void* pos, int64_t np, int n_bins, const double* dpk, void* lam_pos, void* stream) {
