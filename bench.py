@@ -7,7 +7,9 @@ sigma_8 = 0.81) with second-order (2LPT) initial conditions at a = 0.02, 50 step
 in a to a = 1, FP32.  A "step" is one force-kick-drift cycle of the leapfrog: CIC
 deposit -> r2c FFT -> fused k-space Poisson solve and gradient -> three inverse
 FFTs -> CIC gather fused with kick and drift.  The W warmup steps are the first W
-steps of the schedule; the K timed steps follow them.
+steps of the schedule; the K timed steps follow them; the rest of the schedule then
+runs to a = 1 untimed, and its last ten cycles (the most clustered) are reported as a
+late-time sample beside the average over all cycles.
 
 Prints one JSON line with particle-updates/s, the roofline of the dominant kernel
 (per-kernel HIP event timing on the library's stream during the timed region) and
@@ -104,9 +106,29 @@ def cpu_baseline(n_sample: int, seed: int = 5, min_seconds: float = 10.0, max_cy
         cycles += 1
     dt = time.perf_counter() - t0
     return {"value": cycles * n_sample ** 3 / dt, "unit": "particle-updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "host": host_description(),
             "sample": f"{cycles} force-kick-drift cycles of the FP64 CPU oracle (plain PyTorch) on {n_sample}^3 "
                       f"particles and a {n_sample}^3 mesh ({dt:.1f} s), scaled per particle-update"}
+
+
+def host_description():
+    """CPU model, logical CPUs this process may use, and RAM of the host (Linux /proc)."""
+    model, mem_kib = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    mem_kib = int(line.split()[1])
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpus_available": len(os.sched_getaffinity(0)),
+            "ram_GiB": round(mem_kib / 2 ** 20, 1) if mem_kib else None}
 
 
 def adjoint_ratio(pm, plan, noise, icp, n_cycles: int, ckpt: int, n_bins: int):
@@ -468,8 +490,8 @@ def ensemble_leg(pm):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=48)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--box", type=float, default=4000.0)
     ap.add_argument("--seed", type=int, default=3)
@@ -540,20 +562,37 @@ def main():
         run.cycle(a_s[j], k2_prev + k1, dr)
         k2_prev = k2
 
+    # every cycle of the schedule is profiled (HIP events around each launch on the
+    # library's stream); windows: warm-up, timed, the rest, and the late-time sample
+    # of the last ten cycles (a -> 1, the most clustered and slowest)
+    pm.pm_profile_enable(plan, True)
     for j in range(args.warmup):
         cycle(j)
     torch.cuda.synchronize()
-    pm.pm_profile_enable(plan, True)
-    torch.cuda.synchronize()
+    prof_warm = pm.pm_profile_read(plan)
     t0 = time.perf_counter()
     for j in range(args.warmup, args.warmup + args.steps):
         cycle(j)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = pm.pm_profile_read(plan)
-    pm.pm_profile_enable(plan, False)
     pm.pm_check(plan)
     print(f"[bench] timed {args.steps} steps in {t1 - t0:.3f}s", file=sys.stderr, flush=True)
+    late0 = max(args.warmup + args.steps, total - 10)
+    for j in range(args.warmup + args.steps, late0):
+        cycle(j)
+    torch.cuda.synchronize()
+    prof_mid = pm.pm_profile_read(plan)
+    t2 = time.perf_counter()
+    for j in range(late0, total):
+        cycle(j)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    prof_late = pm.pm_profile_read(plan)
+    pm.pm_profile_enable(plan, False)
+    pm.pm_check(plan)
+    print(f"[bench] cycles {late0}..{total - 1} in {t3 - t2:.3f}s (schedule done, a = 1)", file=sys.stderr,
+          flush=True)
 
     ms_step = (t1 - t0) * 1000.0 / args.steps
     value = n ** 3 / (ms_step / 1000.0)
@@ -570,6 +609,19 @@ def main():
     # algorithmic bytes of the kernels the timed steps actually launched, per step
     step_bytes = sum(alg[k] * cnt for k, (_, cnt) in prof.items() if k in alg) // args.steps
     step_gbs = step_bytes / (ms_step / 1000.0) / 1e9
+
+    def window(pr, cycles, wall_s=None):
+        ms, cnt = pr.get(dom, (0.0, 0))
+        w = {"cycles": cycles, "dominant_avg_ms": round(ms / cnt, 4) if cnt else None,
+             "dominant_frac": round(alg[dom] / (ms / cnt / 1000.0) / 1e9 / HBM_PEAK_GBS, 4) if cnt else None}
+        if wall_s is not None and total > late0:
+            w["ms_per_step"] = round(wall_s * 1000.0 / (total - late0), 3)
+        return w
+    whole = {}
+    for pr in (prof_warm, prof, prof_mid, prof_late):
+        for k, (ms, cnt) in pr.items():
+            a, b = whole.get(k, (0.0, 0))
+            whole[k] = (a + ms, b + cnt)
     out = {
         "metric": METRIC,
         "value": value,
@@ -591,7 +643,9 @@ def main():
                      "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom, n), "alg_bytes_per_launch": alg[dom]},
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBps": round(step_gbs, 1),
-                          "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+                          "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                          "late_sample": window(prof_late, f"{late0}..{total - 1}", t3 - t2),
+                          "whole_run": window(whole, f"0..{total - 1}")},
         "kernels": kernels,
         "fft_tuning": {"slots": list(pm.TUNING_SLOTS), "shapes": tuned, "autotuned": bool(args.autotune),
                        "best_ms": [round(m, 4) for m in tuned_ms]},
@@ -599,7 +653,7 @@ def main():
     }
     if not args.no_extras:
         print("[bench] estimators and combination at 1024^3", file=sys.stderr, flush=True)
-        a_end = float(a_s[args.warmup + args.steps])
+        a_end = float(a_s[total])
         out["estimators_combination_1024"] = estimators_and_combination(pm, plan, pos, noise, a_end)
         print("[bench] initial conditions at 1024^3", file=sys.stderr, flush=True)
         out["initial_conditions_1024"] = ic_leg(pm, plan, noise, icp)
