@@ -511,13 +511,33 @@ int pm_step(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n3 = (int64_t)p->n * p->n * p->n;
   if (p->nb > 1 && np != n3) return set_error(PM_ERR_ARG, "pm_step: a batch needs N^3 particles per box");
-  void* delta = cbuf(p, 1);  // the density meshes live in the second spectrum region
   const bool ready = p->dens_valid && p->dens_pos == pos && p->dens_np == np;
   if ((st->flags & PM_STEP_DENSITY_READY) && !ready) {
     p->dens_valid = false;
     return set_error(PM_ERR_STATE, "pm_step: the plan holds no density of these positions from a previous step");
   }
   p->dens_valid = false;
+  PM_TRY(step_cycle(p, pos, mom, np, st, force_scratch, phi_state, s));
+  if (st->flags & PM_STEP_DEPOSIT_NEXT) {
+    p->dens_valid = true;
+    p->dens_pos = pos;
+    p->dens_np = np;
+  }
+  return PM_OK;
+}
+
+}  // extern "C"
+
+namespace pm {
+
+// The launches of one force-kick-drift cycle on all of the plan's boxes (arguments
+// already checked; the density bookkeeping is the caller's): with
+// PM_STEP_DENSITY_READY the second workspace region must hold the density of `pos`;
+// with PM_STEP_DEPOSIT_NEXT it holds that of the drifted positions on return.
+int step_cycle(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* st, void* force_scratch,
+               void* phi_state, hipStream_t s) {
+  const int64_t n3 = (int64_t)p->n * p->n * p->n;
+  void* delta = cbuf(p, 1);  // the density meshes live in the second spectrum region
   if (!(st->flags & PM_STEP_DENSITY_READY)) {
     PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
     PM_TRY(launch_deposit(p, pos, np, delta, s));
@@ -534,11 +554,12 @@ int pm_step(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* 
     PM_TRY(launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, nullptr, s));
     PM_TRY(launch_deposit(p, pos, np, delta, s));
   }
-  p->dens_valid = true;
-  p->dens_pos = pos;
-  p->dens_np = np;
   return PM_OK;
 }
+
+}  // namespace pm
+
+extern "C" {
 
 // Argument checks shared by pm_step_adjoint and its allocation-free variant.
 static int check_step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_params* st, void* lam_pos,
@@ -734,6 +755,50 @@ int bias_fit(const double* k, const double* ratio, const int64_t* n_modes, int n
   return PM_OK;
 }
 
+// Order in which the triangles of bk_estimate are evaluated: greedily, the next shell
+// field to compute is the one that completes the most pending triangles together with
+// the shells computed so far (ties: the shell used by more pending triangles, then the
+// lower id), and each triangle follows the computation of its last shell.  For the
+// usual sets (equilateral k, and squeezed k1 = k2 with a common k3) every shell is
+// transformed once and each triangle directly follows its shells.
+static std::vector<int> bk_triangle_order(int n_shells, const int32_t* tri, int n_tri) {
+  std::vector<char> done(n_tri, 0), have(n_shells, 0);
+  std::vector<int> order;
+  order.reserve(n_tri);
+  auto complete = [&](int t, int extra) {
+    for (int j = 0; j < 3; ++j) {
+      const int sh = tri[3 * t + j];
+      if (!have[sh] && sh != extra) return false;
+    }
+    return true;
+  };
+  while ((int)order.size() < n_tri) {
+    for (int t = 0; t < n_tri; ++t)
+      if (!done[t] && complete(t, -1)) {
+        done[t] = 1;
+        order.push_back(t);
+      }
+    if ((int)order.size() == n_tri) break;
+    std::vector<int> score(n_shells, 0), uses(n_shells, 0);
+    for (int t = 0; t < n_tri; ++t) {
+      if (done[t]) continue;
+      for (int j = 0; j < 3; ++j) {
+        const int sh = tri[3 * t + j];
+        if (j > 0 && (sh == tri[3 * t] || (j == 2 && sh == tri[3 * t + 1]))) continue;
+        uses[sh] += 1;
+        if (!have[sh] && complete(t, sh)) score[sh] += 1;
+      }
+    }
+    int best = -1;
+    for (int sh = 0; sh < n_shells; ++sh) {
+      if (have[sh] || uses[sh] == 0) continue;
+      if (best < 0 || score[sh] > score[best] || (score[sh] == score[best] && uses[sh] > uses[best])) best = sh;
+    }
+    have[best] = 1;
+  }
+  return order;
+}
+
 int bk_estimate(pm_plan* p, const void* delta, int n_shells, const double* centre, double width, const int32_t* tri,
                 int n_tri, double* bk, double* ntri_out, const double* ntri_known, void* shell_ws,
                 size_t shell_ws_bytes, void* stream) {
@@ -748,20 +813,55 @@ int bk_estimate(pm_plan* p, const void* delta, int n_shells, const double* centr
   const int slots = (int)std::min<size_t>(shell_ws_bytes / fbytes, 1 << 20);
   if (slots < 3) return set_error(PM_ERR_NOMEM, "bk_estimate: shell workspace holds %d fields, 3 needed", slots);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::vector<int> order = bk_triangle_order(n_shells, tri, n_tri);
   PM_TRY(fft3_r2c(p, delta, cbuf(p, 0), s));
   PM_TRY(launch_zero_doubles(p->sums, 2 * (int64_t)n_tri, s));
-  const int passes = ntri_known ? 1 : 2;
+  char* base = static_cast<char*>(shell_ws);
+  const int passes = ntri_known ? 1 : 2;  // 0: the density's shells; 1: the shells' indicators
   for (int pass = 0; pass < passes; ++pass) {
     std::vector<int> slot_shell(slots, -1);
-    for (int t = 0; t < n_tri; ++t) {
-      int sl[3];
+    TriPass tp{};  // triangles gathered for one pass over their fields
+    auto flush = [&]() -> int {
+      if (tp.nt == 0) return PM_OK;
+      const int rc = launch_triple_multi(p, tp, s);
+      tp = TriPass{};
+      return rc;
+    };
+    auto pass_field = [&](int slot) {
+      for (int f = 0; f < tp.nf; ++f)
+        if (tp.field[f] == base + (size_t)slot * fbytes) return f;
+      return -1;
+    };
+    for (int oi = 0; oi < n_tri; ++oi) {
+      const int t = order[oi];
+      // distinct shells of t: missing ones must be computed into slots that hold
+      // neither t's other shells nor the fields of the gathered triangles
+      int ts[3], nts = 0;
       for (int j = 0; j < 3; ++j) {
         const int sh = tri[3 * t + j];
-        int found = -1;
-        for (int k = 0; k < slots; ++k)
-          if (slot_shell[k] == sh) found = k;
-        if (found < 0) {
-          // evict the cached shell whose next use is farthest (never if used by this triangle)
+        if (std::find(ts, ts + nts, sh) == ts + nts) ts[nts++] = sh;
+      }
+      int missing = 0, new_fields = 0, resident_outside = 0;
+      for (int j = 0; j < nts; ++j) {
+        const int k = (int)(std::find(slot_shell.begin(), slot_shell.end(), ts[j]) - slot_shell.begin());
+        if (k == slots) {
+          ++missing;
+          ++new_fields;
+        } else if (pass_field(k) < 0) {
+          ++new_fields;
+          ++resident_outside;
+        }
+      }
+      if (tp.nt == kMaxTriPerPass || tp.nf + new_fields > kMaxFieldsPerPass ||
+          slots - (tp.nf + resident_outside) < missing)
+        PM_TRY(flush());
+      int fidx[3];
+      for (int j = 0; j < 3; ++j) {
+        const int sh = tri[3 * t + j];
+        int found = (int)(std::find(slot_shell.begin(), slot_shell.end(), sh) - slot_shell.begin());
+        if (found == slots) {
+          // evict the shell whose next use is farthest; never one of this triangle or of
+          // the gathered triangles
           int best = -1;
           long best_next = -1;
           for (int k = 0; k < slots; ++k) {
@@ -770,30 +870,38 @@ int bk_estimate(pm_plan* p, const void* delta, int n_shells, const double* centr
               best = k;
               break;
             }
-            if (cs == tri[3 * t] || cs == tri[3 * t + 1] || cs == tri[3 * t + 2]) continue;
-            long next = (long)n_tri * 3 + 1;
-            for (int u = t + 1; u < n_tri && next > (long)n_tri * 3; ++u)
-              if (tri[3 * u] == cs || tri[3 * u + 1] == cs || tri[3 * u + 2] == cs) next = u;
+            if (cs == tri[3 * t] || cs == tri[3 * t + 1] || cs == tri[3 * t + 2] || pass_field(k) >= 0) continue;
+            long next = (long)n_tri + 1;
+            for (int u = oi + 1; u < n_tri && next > (long)n_tri; ++u) {
+              const int tu = order[u];
+              if (tri[3 * tu] == cs || tri[3 * tu + 1] == cs || tri[3 * tu + 2] == cs) next = u;
+            }
             if (next > best_next) {
               best_next = next;
               best = k;
             }
           }
+          if (best < 0) return set_error(PM_ERR_STATE, "bk_estimate: no shell slot to evict");
           const double c = centre[sh];
           const double lo = (2.0 * c - width) * (2.0 * c - width);
           const double hi = (2.0 * c + width) * (2.0 * c + width);
-          PM_TRY(launch_shell_mask(p, pass == 0 ? cbuf(p, 0) : nullptr, cbuf(p, 1), lo, hi, s));
-          void* dst = static_cast<char*>(shell_ws) + (size_t)best * fbytes;
-          PM_TRY(fft3_c2r(p, 1, cbuf(p, 1), 0, dst, s));
+          PM_TRY(fft3_c2r_shell(p, pass == 0 ? cbuf(p, 0) : nullptr, cbuf(p, 1), base + (size_t)best * fbytes, lo, hi,
+                                s));
           slot_shell[best] = sh;
           found = best;
         }
-        sl[j] = found;
+        int f = pass_field(found);
+        if (f < 0) {
+          f = tp.nf++;
+          tp.field[f] = base + (size_t)found * fbytes;
+        }
+        fidx[j] = f;
       }
-      const char* base = static_cast<const char*>(shell_ws);
-      PM_TRY(launch_triple_sum(p, base + (size_t)sl[0] * fbytes, base + (size_t)sl[1] * fbytes,
-                               base + (size_t)sl[2] * fbytes, p->sums + (size_t)pass * n_tri + t, s));
+      for (int j = 0; j < 3; ++j) tp.idx[tp.nt][j] = fidx[j];
+      tp.slot[tp.nt] = p->sums + (size_t)pass * n_tri + t;
+      tp.nt += 1;
     }
+    PM_TRY(flush());
   }
   return launch_bk_finalize(p, n_tri, p->sums, bk, ntri_out, ntri_known, s);
 }

@@ -48,7 +48,7 @@ void launch_r2c_t(const T* in, cx<T>* out, const RowArgs& g, int ncomp, const cx
   hipLaunchKernelGGL((k_fft_rows_r2c<T, L1, L2>), grid, block, (size_t)R * RS * sizeof(cx<T>), s, in, out, g, tw);
 }
 
-template <typename T, int L1, int L2>
+template <typename T, int L1, int L2, bool ZMASK = false>
 void launch_c2r_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx<T>* tw, int rows, hipStream_t s) {
   constexpr int M = L1 * L2;
   constexpr int TPC = L1 > L2 ? L1 : L2;
@@ -57,7 +57,32 @@ void launch_c2r_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx
   const int R = rows > 0 ? rows : 256 / TPC;
   dim3 grid((unsigned)((g.nrows + R - 1) / R), (unsigned)ncomp);
   dim3 block((unsigned)(R * TPC));
-  hipLaunchKernelGGL((k_fft_rows_c2r<T, L1, L2>), grid, block, (size_t)R * XS * sizeof(cx<T>), s, in, out, g, tw);
+  hipLaunchKernelGGL((k_fft_rows_c2r<T, L1, L2, ZMASK>), grid, block, (size_t)R * XS * sizeof(cx<T>), s, in, out, g,
+                     tw);
+}
+
+template <typename T, int L1, int L2>
+void launch_c2r_zmask_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx<T>* tw, int rows,
+                        hipStream_t s) {
+  launch_c2r_t<T, L1, L2, true>(in, out, g, ncomp, tw, rows, s);
+}
+
+template <typename T, int L1, int L2>
+void launch_cols_shell0_t(const cx<T>* src, cx<T>* dst, const ColArgs& g, const ShellArgs& sh, int outer,
+                          const cx<T>* tw, hipStream_t s) {
+  const int tpc = std::max(L1, L2);
+  size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
+  hipLaunchKernelGGL((k_fft_cols_shell<T, L1, L2, 0>), dim3((unsigned)(outer * g.groups)),
+                     dim3((unsigned)(g.bcols * tpc)), shm, s, src, dst, g, sh, tw);
+}
+
+template <typename T, int L1, int L2>
+void launch_cols_shell1_t(cx<T>* data, const ColArgs& g, const ShellArgs& sh, int outer, const cx<T>* tw,
+                          hipStream_t s) {
+  const int tpc = std::max(L1, L2);
+  size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
+  hipLaunchKernelGGL((k_fft_cols_shell<T, L1, L2, 1>), dim3((unsigned)(outer * g.groups)),
+                     dim3((unsigned)(g.bcols * tpc)), shm, s, static_cast<const cx<T>*>(nullptr), data, g, sh, tw);
 }
 
 template <typename T, int L1, int L2>
@@ -74,6 +99,12 @@ void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* o2, cx<T>* phi, const ColArgs
     hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_POISSON_GAUGE, 2>), grid, block, shm, s, data, o1, o2, phi, g,
                        a, tw);
 }
+
+#define PM_TRY_HIP(expr, what)                  \
+  do {                                          \
+    const int rc_ = hip_check((expr), (what));  \
+    if (rc_ != PM_OK) return rc_;               \
+  } while (0)
 
 // Dispatch on a transform length L to the compile-time (L1, L2) instantiation.
 #define PM_DISPATCH_LEN(L, FN, ...)                  \
@@ -146,6 +177,36 @@ int c2r_t(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* ou
   PM_DISPATCH_LEN(n / 2, launch_c2r_t, static_cast<const cx<T>*>(in), static_cast<T*>(out), g, ncomp, tw, p->tune[3],
                   s)
   return hip_check(hipGetLastError(), "fft c2r rows");
+}
+
+// Inverse transform of one shell of the spectrum `src` (or of its indicator when src
+// is null) into the real mesh `out`, through the complex buffer `work`.
+template <typename T>
+int shell_c2r_t(const pm_plan* p, const void* src, void* work, void* out, double lo4, double hi4, hipStream_t s) {
+  const int n = p->n;
+  const int bc = p->tune[0] > 0 ? p->tune[0] : cols_per_block<T>(n);
+  const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
+  ShellArgs sh;
+  sh.lo4 = lo4;
+  sh.hi4 = hi4;
+  sh.n = n;
+  cx<T>* w = static_cast<cx<T>*>(work);
+  const ColArgs g0 = col_args(n, p->hp, 0, bc);
+  PM_DISPATCH_LEN(n, launch_cols_shell0_t, static_cast<const cx<T>*>(src), w, g0, sh, n, tw, s)
+  PM_TRY_HIP(hipGetLastError(), "shell column pass (axis 0)");
+  const ColArgs g1 = col_args(n, p->hp, 1, bc);
+  PM_DISPATCH_LEN(n, launch_cols_shell1_t, w, g1, sh, n, tw, s)
+  PM_TRY_HIP(hipGetLastError(), "shell column pass (axis 1)");
+  RowArgs g;
+  g.nrows = (int64_t)n * n;
+  g.in_comp = 0;
+  g.out_comp = (int64_t)n * n * n;
+  g.n = n;
+  g.hs = p->hp;
+  g.zmask4 = hi4;
+  PM_DISPATCH_LEN(n / 2, launch_c2r_zmask_t, static_cast<const cx<T>*>(w), static_cast<T*>(out), g, 1, tw,
+                  p->tune[3], s)
+  return hip_check(hipGetLastError(), "shell c2r rows");
 }
 
 template <typename T>
@@ -243,6 +304,12 @@ int fft_pass_rows_r2c(const pm_plan* p, int count, const void* in, void* out, hi
 int fft_pass_rows_c2r(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* out, hipStream_t s) {
   ProfScope ps(p, PK_C2R_ROWS, s);
   return p->dtype == PM_F32 ? c2r_t<float>(p, ncomp, in, in_comp, out, s) : c2r_t<double>(p, ncomp, in, in_comp, out, s);
+}
+
+int fft3_c2r_shell(const pm_plan* p, const void* src, void* work, void* out, double lo4, double hi4, hipStream_t s) {
+  ProfScope ps(p, PK_BK, s);
+  return p->dtype == PM_F32 ? shell_c2r_t<float>(p, src, work, out, lo4, hi4, s)
+                            : shell_c2r_t<double>(p, src, work, out, lo4, hi4, s);
 }
 
 int fft_pass_solve(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t s) {

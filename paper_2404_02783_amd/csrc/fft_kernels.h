@@ -82,6 +82,88 @@ __global__ void __launch_bounds__(256) k_fft_cols(cx<T>* __restrict__ data, ColA
   }
 }
 
+// Shell-filtered inverse column passes of the FFT bispectrum estimator (eq.
+// bispectre).  A shell S = {n : lo4 <= 4|n|^2 < hi4} fills a small part of the
+// spectrum, so these passes transform only what can be non-zero, and every load is
+// masked by the support the previous pass wrote (elements a skipped workgroup left
+// alone hold stale data and are never read):
+//   STAGE 0, along axis 0 (columns (iy, iz)), src -> dst: loads src where n is in S
+//     (1 where src is null: the shell's indicator), 0 elsewhere.  A workgroup whose
+//     columns all have 4(ny^2 + iz^2) >= hi4 contains no mode of S and returns.
+//   STAGE 1, along axis 1 (columns (ix, iz)), in place on dst: loads only where
+//     4(ny^2 + iz^2) < hi4 (the columns stage 0 transformed), 0 elsewhere.  A
+//     workgroup whose columns all have 4 iz^2 >= hi4 returns.
+// The rows pass that follows (k_fft_rows_c2r with ZMASK) loads only iz with
+// 4 iz^2 < hi4.  Same arithmetic as k_fft_cols on the values it keeps.
+struct ShellArgs {
+  double lo4, hi4;  // shell bounds on 4|n|^2 (exact integers in double)
+  int n;            // N
+};
+
+template <typename T, int L1, int L2, int STAGE>
+__global__ void __launch_bounds__(256) k_fft_cols_shell(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                                      ColArgs g, ShellArgs sh, const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int B = g.bcols;
+  const int t = threadIdx.x;
+  const int b = t % B, u = t / B;
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t outer = lb / g.groups;            // STAGE 0: iy; STAGE 1: ix
+  const int z0 = (int)(lb % g.groups) * B;        // first column (iz) of the workgroup
+  const int col = z0 + b;
+  const bool valid = col < g.ncols;
+  const int N = sh.n;
+  const double z4 = 4.0 * (double)z0 * (double)z0;
+  if (STAGE == 0) {
+    const int ny = outer < N / 2 ? (int)outer : (int)outer - N;
+    if (z4 + 4.0 * (double)ny * (double)ny >= sh.hi4) return;  // the same decision in every thread
+  } else {
+    if (z4 >= sh.hi4) return;
+  }
+  const int64_t off = outer * g.outer_stride + col;
+  const double c4 = 4.0 * (double)col * (double)col;
+  constexpr bool INV = true;
+
+  if (u < L2) {
+    cx<T> a[L1];
+#pragma unroll
+    for (int j1 = 0; j1 < L1; ++j1) {
+      const int i = u + L2 * j1;                 // index along the transform axis
+      const int ni = i < N / 2 ? i : i - N;
+      bool keep;
+      if (STAGE == 0) {
+        const int ny = outer < N / 2 ? (int)outer : (int)outer - N;
+        const double r4 = 4.0 * ((double)ni * ni + (double)ny * ny) + c4;
+        keep = valid && r4 >= sh.lo4 && r4 < sh.hi4;
+      } else {
+        keep = valid && 4.0 * (double)ni * ni + c4 < sh.hi4;
+      }
+      const cx<T>* from = STAGE == 0 ? src : dst;
+      cx<T> v = mk(T(0), T(0));
+      if (keep) v = (STAGE == 0 && !src) ? mk(T(1), T(0)) : ldc(from + off + (int64_t)i * g.stride);
+      a[j1] = v;
+    }
+    RegDFT<T, L1, 1>::run(a);
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) {
+      cx<T> v = k1 == 0 ? a[k1] : tw_mul<INV>(a[k1], tw, u * k1 * g.tw_step);
+      lds[col_lds_index<T, L1, L2>(k1, u, b, B)] = v;
+    }
+  }
+  __syncthreads();
+  if (u < L1) {
+    cx<T> c[L2];
+#pragma unroll
+    for (int j2 = 0; j2 < L2; ++j2) c[j2] = lds[col_lds_index<T, L1, L2>(u, j2, b, B)];
+    RegDFT<T, L2, 1>::run(c);
+    if (valid) {
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) stc(dst + off + (int64_t)(u + L1 * k2) * g.stride, c[k2]);
+    }
+  }
+}
+
 // Real-to-complex along the contiguous axis: rows of N reals -> rows of N/2+1
 // complex.  M = N/2 = L1*L2 complex points z[n] = x[2n] + i x[2n+1];
 // X[k] = E[k] + W_N^k O[k] with E = (Z[k] + conj Z[M-k])/2, O = -i (Z[k] - conj Z[M-k])/2.
@@ -92,6 +174,7 @@ struct RowArgs {
   int64_t in_comp, out_comp;  // component strides (elements of the in/out type)
   int n;                      // N (real row length)
   int hs;                     // spectrum row stride (complex elements, >= N/2+1)
+  double zmask4;              // c2r with ZMASK: only coefficients k with 4 k^2 < zmask4 are read
 };
 
 template <typename T, int L1, int L2>
@@ -152,7 +235,7 @@ __global__ void __launch_bounds__(256) k_fft_rows_r2c(const T* __restrict__ in, 
 // x[n] = sum_{k in full row} X[k] exp(+2 pi i n k / N)).
 // Z[k] = (X[k] + conj X[M-k]) + i conj(W_N^k) (X[k] - conj X[M-k]), z = IDFT_M(Z),
 // x[2n] = Re z[n], x[2n+1] = Im z[n].
-template <typename T, int L1, int L2>
+template <typename T, int L1, int L2, bool ZMASK = false>
 __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ in, T* __restrict__ out, RowArgs g,
                                                     const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
@@ -177,8 +260,13 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ 
 #pragma unroll
     for (int j1 = 0; j1 < L1; ++j1) {
       const int k = u + L2 * j1;
-      const cx<T> xk = valid ? ldc(src + k) : mk(T(0), T(0));
-      const cx<T> xm = valid ? conjg(ldc(src + (M - k))) : mk(T(0), T(0));
+      bool vk = valid, vm = valid;
+      if (ZMASK) {  // coefficients beyond the shell's reach hold stale data
+        vk = vk && 4.0 * (double)k * (double)k < g.zmask4;
+        vm = vm && 4.0 * (double)(M - k) * (double)(M - k) < g.zmask4;
+      }
+      const cx<T> xk = vk ? ldc(src + k) : mk(T(0), T(0));
+      const cx<T> xm = vm ? conjg(ldc(src + (M - k))) : mk(T(0), T(0));
       const cx<T> s = xk + xm;
       const cx<T> d = twiddle<true>(xk - xm, tw[k]);  // d * conj(W_N^k)
       a[j1] = mk(s.x - d.y, s.y + d.x);               // s + i d

@@ -35,6 +35,7 @@ enum ProfKind {
   PK_COUNT
 };
 struct ProfState;
+struct BoxEntry;
 }  // namespace pm
 
 struct pm_plan {
@@ -63,6 +64,9 @@ struct pm_plan {
   // [0] columns per workgroup of the plain column passes, [1] of the fused solve pass,
   // [2] rows per workgroup of the r2c rows pass, [3] of the c2r rows pass
   int tune[4];
+  // device table of the boxes' particle arrays (a pm_batch size group), or null: the
+  // particle kernels then take box b's arrays at b * 3 N^3 from the pointers passed
+  const pm::BoxEntry* box_tab;
 };
 
 namespace pm {
@@ -93,6 +97,12 @@ struct ProfScope {
   }
 };
 
+// ---------------------------------------------------------------- api.cpp --
+// The launches of one force-kick-drift cycle of pm_step on all of the plan's boxes
+// (arguments checked, density bookkeeping left to the caller).
+int step_cycle(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* st, void* force_scratch,
+               void* phi_state, hipStream_t s);
+
 // ---------------------------------------------------------------- fft.hip --
 // Forward 3-D r2c of the plan's nb boxes: real [nb][N][N][N] -> complex [nb][N][N][hp]
 // spaced cstride apart (unnormalised).
@@ -103,6 +113,11 @@ int fft3_r2c_n(const pm_plan* p, int count, const void* real_in, void* cplx_out,
 // (destroyed) -> ncomp real meshes spaced N^3 apart (unnormalised: N^3 times the
 // inverse DFT).
 int fft3_c2r(const pm_plan* p, int ncomp, void* cplx_in, int64_t comp_stride, void* real_out, hipStream_t s);
+// Inverse 3-D transform of the shell lo4 <= 4|n|^2 < hi4 of the spectrum `src`
+// ([N][N][hp], unchanged; null: the shell's indicator) into the real mesh `out`
+// (unnormalised), through the complex buffer `work` (overwritten); only the columns
+// and coefficients the shell can reach are transformed.
+int fft3_c2r_shell(const pm_plan* p, const void* src, void* work, void* out, double lo4, double hi4, hipStream_t s);
 // Forward column pass along axis 0 only (used after r2c rows + axis-1 pass).
 int fft_pass_cols(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s);
 int fft_pass_rows_r2c(const pm_plan* p, int count, const void* in, void* out, hipStream_t s);
@@ -160,10 +175,17 @@ int launch_ic_symbol(const pm_plan* p, const IcSymbol& sym, bool adjoint, hipStr
 // bhat non-NULL: cross power Re(dhat conj(bhat)) of the pair.
 int launch_pk_reduce(const pm_plan* p, const void* dhat, int n_bins, hipStream_t s, const void* bhat = nullptr);
 int launch_pk_finalize(const pm_plan* p, int n_bins, double* k_mean, double* pk, int64_t* n_modes, hipStream_t s);
-// dst = src * 1_S (src may be NULL: indicator); shell membership (2c-w)^2 <= 4|n|^2 < (2c+w)^2.
-int launch_shell_mask(const pm_plan* p, const void* src, void* dst, double lo4, double hi4, hipStream_t s);
-// sums[slot] += sum_x a*b*c (real meshes of N^3)
-int launch_triple_sum(const pm_plan* p, const void* a, const void* b, const void* c, double* slot, hipStream_t s);
+// Up to four triangle sums sum_x f_a f_b f_c over up to four distinct shell fields in
+// one pass: field[0..nf) are [N^3] reals of the plan's type; triangle t multiplies
+// fields idx[t][0..2] and adds its FP64 sum to *slot[t].
+constexpr int kMaxFieldsPerPass = 4, kMaxTriPerPass = 4;
+struct TriPass {
+  const void* field[kMaxFieldsPerPass];
+  double* slot[kMaxTriPerPass];
+  int idx[kMaxTriPerPass][3];
+  int nf, nt;
+};
+int launch_triple_multi(const pm_plan* p, const TriPass& tp, hipStream_t s);
 int launch_bk_finalize(const pm_plan* p, int n_tri, const double* sums, double* bk, double* ntri_out,
                        const double* ntri_known, hipStream_t s);
 int launch_zero_doubles(double* d, int64_t n, hipStream_t s);

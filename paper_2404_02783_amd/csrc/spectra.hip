@@ -2,6 +2,8 @@
 // the power-spectrum shell reduction and the bispectrum shell filter / triple sums.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pm_common.h"
 #include "pm_plan.h"
 
@@ -321,41 +323,49 @@ __global__ void __launch_bounds__(kBlock) k_fix_spectrum(cx<T>* __restrict__ c, 
   stc(c + idx, mk(T(re * f), T(im * f)));
 }
 
+// One pass over up to four shell fields accumulating up to four triangle sums
+// sum_x f_a f_b f_c (FP64 products and sums of the fields' values); each thread reads
+// 16-byte vectors of every field.  count is a multiple of the vector width.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_shell_mask(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n,
-                                                       int hp, double lo4, double hi4) {
-  const int h = hp;  // padded row stride; columns iz > N/2 are padding
-  const int64_t total = (int64_t)n * n * h;
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const int iz = (int)(idx % h);
-  if (iz > n / 2) return;
-  const int iy = (int)((idx / h) % n);
-  const int ix = (int)(idx / ((int64_t)h * n));
-  const int nx = signed_freq(ix, n), ny = signed_freq(iy, n);
-  const double r4 = 4.0 * (double)((int64_t)nx * nx + (int64_t)ny * ny + (int64_t)iz * iz);
-  const bool in = r4 >= lo4 && r4 < hi4;
-  cx<T> v = mk(T(0), T(0));
-  if (in) v = src ? ldc(src + idx) : mk(T(1), T(0));
-  stc(dst + idx, v);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_triple_sum(const T* __restrict__ a, const T* __restrict__ b,
-                                                       const T* __restrict__ c, int64_t count, double scale,
-                                                       double* __restrict__ slot) {
-  __shared__ double red[kBlock];
-  double acc = 0.0;
+__global__ void __launch_bounds__(kBlock) k_triple_multi(TriPass tp, int64_t count) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(VW)));
+  __shared__ double red[kMaxTriPerPass][kBlock / 64];
+  double acc[kMaxTriPerPass] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t nvec = count / VW;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
-    acc += (double)a[i] * (double)b[i] * (double)c[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+    vec_t v[kMaxFieldsPerPass];
+#pragma unroll
+    for (int f = 0; f < kMaxFieldsPerPass; ++f)
+      v[f] = f < tp.nf ? reinterpret_cast<const vec_t*>(tp.field[f])[i] : vec_t(T(0));
+#pragma unroll
+    for (int t = 0; t < kMaxTriPerPass; ++t) {
+      if (t >= tp.nt) break;
+      const int ia = tp.idx[t][0], ib = tp.idx[t][1], ic = tp.idx[t][2];
+      // the indices are uniform: selects, not dynamic register indexing
+      const vec_t a = ia == 0 ? v[0] : (ia == 1 ? v[1] : (ia == 2 ? v[2] : v[3]));
+      const vec_t b = ib == 0 ? v[0] : (ib == 1 ? v[1] : (ib == 2 ? v[2] : v[3]));
+      const vec_t c = ic == 0 ? v[0] : (ic == 1 ? v[1] : (ic == 2 ? v[2] : v[3]));
+#pragma unroll
+      for (int e = 0; e < VW; ++e) acc[t] += (double)a[e] * (double)b[e] * (double)c[e];
+    }
   }
-  if (threadIdx.x == 0) atomicAdd(slot, red[0] * scale);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < kMaxTriPerPass; ++t) {
+    double v = acc[t];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[t][wave] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < tp.nt) {
+    const int t = threadIdx.x;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) v += red[t][w];
+    atomicAdd(tp.slot[t], v);
+  }
 }
 
 __global__ void k_bk_finalize(const double* __restrict__ sums, int n_tri, int n, double box, double* __restrict__ bk,
@@ -485,33 +495,17 @@ int launch_truncate_spectrum(const pm_plan* fine, const pm_plan* coarse, hipStre
   return hip_check(hipGetLastError(), "truncate spectrum");
 }
 
-int launch_shell_mask(const pm_plan* p, const void* src, void* dst, double lo4, double hi4, hipStream_t s) {
-  ProfScope ps(p, PK_BK, s);
-  const int n = p->n;
-  const int64_t total = (int64_t)n * n * p->hp;
-  const unsigned g = (unsigned)((total + kBlock - 1) / kBlock);
-  if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_shell_mask<float>, dim3(g), dim3(kBlock), 0, s, static_cast<const cx<float>*>(src),
-                       static_cast<cx<float>*>(dst), n, p->hp, lo4, hi4);
-  else
-    hipLaunchKernelGGL(k_shell_mask<double>, dim3(g), dim3(kBlock), 0, s, static_cast<const cx<double>*>(src),
-                       static_cast<cx<double>*>(dst), n, p->hp, lo4, hi4);
-  return hip_check(hipGetLastError(), "shell mask");
-}
-
-int launch_triple_sum(const pm_plan* p, const void* a, const void* b, const void* c, double* slot, hipStream_t s) {
+int launch_triple_multi(const pm_plan* p, const TriPass& tp, hipStream_t s) {
   ProfScope ps(p, PK_BK, s);
   const int64_t count = (int64_t)p->n * p->n * p->n;
-  int64_t g = (count + kBlock * 8 - 1) / (kBlock * 8);
-  if (g < 1) g = 1;
-  if (g > 16384) g = 16384;
+  const int vw = p->dtype == PM_F32 ? 4 : 2;
+  int64_t g = (count / vw + kBlock * 16 - 1) / (kBlock * 16);
+  g = std::max<int64_t>(1, std::min<int64_t>(g, 8192));
   if (p->dtype == PM_F32)
-    hipLaunchKernelGGL(k_triple_sum<float>, dim3((unsigned)g), dim3(kBlock), 0, s, static_cast<const float*>(a),
-                       static_cast<const float*>(b), static_cast<const float*>(c), count, 1.0, slot);
+    hipLaunchKernelGGL(k_triple_multi<float>, dim3((unsigned)g), dim3(kBlock), 0, s, tp, count);
   else
-    hipLaunchKernelGGL(k_triple_sum<double>, dim3((unsigned)g), dim3(kBlock), 0, s, static_cast<const double*>(a),
-                       static_cast<const double*>(b), static_cast<const double*>(c), count, 1.0, slot);
-  return hip_check(hipGetLastError(), "triple sum");
+    hipLaunchKernelGGL(k_triple_multi<double>, dim3((unsigned)g), dim3(kBlock), 0, s, tp, count);
+  return hip_check(hipGetLastError(), "triple sums");
 }
 
 int launch_bk_finalize(const pm_plan* p, int n_tri, const double* sums, double* bk, double* ntri_out,

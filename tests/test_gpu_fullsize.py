@@ -330,13 +330,15 @@ def test_bk_full_size_benchmark_triangles(plan):
     scale = float(want_num.abs().max())
     closed = [tris.index(t) for t in ((0, 0, 0), (1, 1, 1), (31, 31, 31), (0, 0, 32), (1, 1, 32))]
     assert all(abs(float(want_num[i])) > 1e-3 * scale for i in closed)
-    assert float((got_num - want_num).abs().max()) < 1e-4 * scale
+    err = float((got_num - want_num).abs().max()) / scale
+    print(f"B(k) 1024^3: largest triple-sum error {err:.2e} of the largest triple sum")
+    assert err < F32_TOL
     for t in ((0, 0, 0), (0, 0, 32), (1, 1, 32), (2, 2, 32)):
         i = tris.index(t)
         cnt = estimators.triangle_count(N, centres, width, t)
         assert abs(float(ntri[i]) - cnt) <= F32_TOL * cnt
         want_b = vol2 / N ** 9 * float(want_num[i]) / cnt
-        assert abs(float(bk[i]) - want_b) <= 1e-4 * max(abs(want_b), 1e-3 * vol2 / N ** 9 * scale / cnt)
+        assert abs(float(bk[i]) - want_b) <= F32_TOL * max(abs(want_b), 1e-3 * vol2 / N ** 9 * scale / cnt)
 
 
 # ----------------------------------------------------------------- combine --
