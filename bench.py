@@ -43,8 +43,8 @@ def algorithmic_bytes(n: int, np_: int, es: int = 4):
         "deposit": 3 * es * np_ + es * n3,                  # read positions, write the mesh once
         "fft_r2c_rows": es * n3 + cs * c,
         "fft_cols_fwd_axis1": 2 * cs * c,
-        "fft_solve_axis0": cs * c + 3 * cs * c,             # read delta_hat, write 3 force spectra
-        "fft_cols_inv_axis1": 3 * 2 * cs * c,
+        "fft_solve_axis0": cs * c + 2 * cs * c,             # read delta_hat, write F_x and G spectra
+        "fft_cols_inv_axis1": 2 * cs * c + 3 * cs * c,      # read F_x, G; write F_x, D_y G, G (y-transformed)
         "fft_c2r_rows": 3 * cs * c + 3 * es * n3,
         "gather_kick_drift": 12 * es * np_ + 3 * es * n3,   # x, p read and written; force read once
         # the same plus the next cycle's density written once (positions still in registers)
@@ -398,10 +398,11 @@ def adjoint_small(pm, n=128, box=1000.0, n_steps=20, ckpt=5, n_bins=64):
 
 def ensemble_leg(pm):
     """64-box ensemble (16 x 64^3, 24 x 128^3, 16 x 192^3, 8 x 256^3; 30 log steps
-    a = 0.02 -> 1; per-box P(k)): one captured graph over the batched groups (FFT
-    launch shapes autotuned per group; also timed with the built-in shapes) vs the
-    same boxes run one by one on single-box plans (also autotuned) with eager
-    launches."""
+    a = 0.02 -> 1; per-box P(k)) as one pm_batch: one captured graph of the batch calls
+    (one launch per kernel and size group; FFT launch shapes autotuned per group; also
+    timed with the built-in shapes and with the groups on concurrent streams) vs the
+    same boxes run one by one on single-box plans (also autotuned) with eager launches;
+    plus the ensemble's HBM roofline fraction."""
     import torch
     import synth_inputs as si
     from paper_2404_02783_amd import ensemble
@@ -429,7 +430,7 @@ def ensemble_leg(pm):
     pk_conc = [o[1].clone() for o in ens.power_spectra()]
     del ens
     ens = ensemble.Ensemble(groups, noise_fn, 0.02, 1.0, 30, torch.float32, dev, autotune=True)
-    shapes = {f"{st.group.n}^3 x {st.plan.batch}": st.tuning[0] for st in ens.states}
+    shapes = {f"{n}^3 x {cnt}": t[0] for (n, _, cnt), t in ens.group_tuning}
     ens.capture()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -454,7 +455,21 @@ def ensemble_leg(pm):
     t_seq = time.perf_counter() - t0
     worst = max(float(((a - b).abs() / b.abs().clamp_min(1e-30)).max()) for a, b in zip(pk_batched, pk_seq))
     worst_conc = max(float(((a - b).abs() / b.abs().clamp_min(1e-30)).max()) for a, b in zip(pk_conc, pk_batched))
-    out = {"boxes": sum(len(g.seeds) for g in groups), "graph_s": round(t_graph, 4),
+    # HBM roofline of the ensemble: algorithmic bytes of the 30 cycles of every box (the
+    # kernels of one pm_step cycle with the handed-over density) over the graph replay,
+    # which also holds the ICs and the final P(k)
+    cyc_bytes = 0
+    for g in groups:
+        a = algorithmic_bytes(g.n, g.n ** 3)
+        per_cycle = sum(a[k] for k in ("fill", "fft_r2c_rows", "fft_cols_fwd_axis1", "fft_solve_axis0",
+                                       "fft_cols_inv_axis1", "fft_c2r_rows", "gather_kick_drift_deposit"))
+        cyc_bytes += 30 * per_cycle * len(g.seeds)
+    out = {"boxes": sum(len(g.seeds) for g in groups),
+           "particle_updates_per_s_graph": round(30 * sum(len(g.seeds) * g.n ** 3 for g in groups) / t_graph, 1),
+           "hbm_roofline_graph": {"alg_bytes_30_cycles": cyc_bytes, "achieved_GBps": round(cyc_bytes / t_graph / 1e9, 1),
+                                  "frac": round(cyc_bytes / t_graph / 1e9 / HBM_PEAK_GBS, 4),
+                                  "note": "graph time includes the ICs and the final P(k)"},
+           "graph_s": round(t_graph, 4),
            "graph_builtin_fft_shapes_s": round(t_graph_builtin, 4), "fft_shapes_autotuned": shapes,
            "graph_concurrent_groups_s": round(t_graph_conc, 4),
            "speedup_concurrent_graph_vs_sequential": round(t_seq / t_graph_conc, 2),

@@ -160,6 +160,54 @@ size_t pm_plan_workspace_bytes_batch(int n_mesh, int dtype, int n_batch);
 int pm_plan_create_batch(pm_plan** out, int n_mesh, double box_mpch, int dtype, int n_batch, void* workspace,
                          size_t ws_bytes);
 
+/* ------------------------------------------------------- uneven ensembles --- */
+/* An ensemble of independent periodic boxes of uneven mesh sizes advanced together
+ * (the ensembles of realisations behind the paper's error bars on the scale-dependent
+ * bias, Sec. 5.2; batching is not in the paper).  Boxes of equal mesh size and side
+ * form a size group with one internal batched plan: every call issues each kernel of
+ * the operation once per group for all of the group's boxes (box index in the grid),
+ * and the particle kernels read each box's particle arrays and its kick and drift
+ * from the group's device table, which a small kernel refreshes at every call (the
+ * calls can be captured in a HIP graph; the pointer arrays are read at call time).
+ * Groups are ordered by decreasing mesh size, then by side.
+ * n_mesh, box_mpch: host arrays of n_box (sizes as pm_plan_create); box i holds
+ * n_mesh[i]^3 particles on its lattice.  flags: PM_BATCH_CONCURRENT runs each group on
+ * a stream of its own (default priority), forked from and joined back into the call's
+ * stream, so that small groups' launches overlap large groups' kernels.  The batch
+ * owns its plans, force meshes and staging buffers (allocated here, freed by
+ * pm_batch_destroy).  Calls on one batch must not run concurrently.
+ * Errors: PM_ERR_SIZE for an unsupported mesh size, PM_ERR_ARG for bad arguments,
+ * PM_ERR_NOMEM / PM_ERR_HIP when an allocation fails. */
+typedef struct pm_batch pm_batch;
+#define PM_BATCH_CONCURRENT 1
+int pm_batch_create(pm_batch** out, int n_box, const int* n_mesh, const double* box_mpch, int dtype, int flags);
+int pm_batch_destroy(pm_batch* batch);
+/* Number of size groups, and group g's mesh size, side, number of boxes and internal
+ * plan (host outputs, each may be NULL).  The plan may be given to the FFT launch-shape
+ * tuning calls (pm_plan_autotune, pm_plan_{get,set}_tuning) and to the profiler only. */
+int pm_batch_num_groups(const pm_batch* batch);
+int pm_batch_group(const pm_batch* batch, int group, int* n_mesh, double* box_mpch, int* n_boxes, pm_plan** plan);
+/* One force-kick-drift cycle (Sec. 2's PM cycle, as pm_step) of every box, in place.
+ * pos, mom: host arrays of n_box device pointers to box i's [3][n_mesh[i]^3] arrays of
+ * the batch's dtype.  per_box: host array of n_box step parameters; kick and drift
+ * may differ between boxes; the solve parameters (PM_NEWTON only) and the flags must
+ * be equal within a size group (PM_ERR_ARG otherwise).  flags as pm_step:
+ * PM_STEP_DEPOSIT_NEXT leaves each group's density of the drifted positions for the
+ * next call; PM_STEP_DENSITY_READY requires the previous pm_batch_step to have left
+ * it for the same pointers (PM_ERR_STATE otherwise); any other call discards it. */
+int pm_batch_step(pm_batch* batch, void* const* pos, void* const* mom, const pm_step_params* per_box, void* stream);
+/* Zel'dovich initial conditions of every box (as pm_ic_zeldovich, same parameters for
+ * all boxes): noise[i] box i's [n^3] unit white noise (read only), pos[i], mom[i] its
+ * [3][n^3] outputs. */
+int pm_batch_ic_zeldovich(pm_batch* batch, const void* const* noise, const pm_ic_params* ic, void* const* pos,
+                          void* const* mom, void* stream);
+/* P(k) of every box (eq. powerspectrum, as pm_deposit then pk_estimate) from its
+ * particles pos[i]: n_bins[i] bins (host; equal within a size group, at most 4 N);
+ * box i's k_mean, pk (double) and n_modes (int64) are written at offset
+ * sum_{j<i} n_bins[j] of the device arrays. */
+int pm_batch_pk_estimate(pm_batch* batch, const void* const* pos, const int* n_bins, double* k_mean, double* pk,
+                         int64_t* n_modes, void* stream);
+
 /* Reads and clears the device guard counters (synchronises `stream`).
  * Returns PM_ERR_STATE if, since the last check, the deposit met a non-finite
  * position (skipped) or a position outside [0, N) (wrapped back in). */
@@ -221,14 +269,23 @@ int pm_deposit(pm_plan* plan, const void* pos, int64_t np, void* delta, void* st
 int pm_solve(pm_plan* plan, const void* delta, const pm_solve_params* sp, void* phi_state, void* force,
              void* stream);
 
-/* CIC interpolation of the three force meshes to the particles (same weights as the
- * deposit): acc[d][p] = sum_c W(x_p - c) force[d](c).  acc: [3][np]. */
+/* Force interpolation of the particle-mesh method (Sec. 2: the relativistic and the
+ * Newtonian run of the combination are made with a particle-mesh code, whose forces
+ * come from the mesh; Sec. 4.1 traces their small-scale deficit to it): CIC
+ * interpolation of the three force meshes to the
+ * particles with the deposit's weights, acc[d][p] = sum_c W(x_p - c) force[d](c).
+ * force: [3][N][N][N] real (read only); pos: [3][np] in [0, N); acc: [3][np]
+ * (written).  Single-box plans only (PM_ERR_ARG otherwise). */
 int pm_gather(pm_plan* plan, const void* force, const void* pos, int64_t np, void* acc, void* stream);
 
-/* One force-kick-drift cycle in place on (pos, mom) [3][np]: deposit -> solve ->
- * gather -> kick -> drift, with the periodic wrap x <- x - N floor(x/N) and a result
- * equal to N set to 0.  force_scratch: [3][N][N][N] real (holds the force meshes on
- * return); phi_state as in pm_solve. */
+/* One cycle of the particle-mesh method (Sec. 2: the relativistic and Newtonian runs
+ * are particle-mesh simulations; the time integrator is not stated and is read as
+ * a kick-drift-kick leapfrog, see pm_step_params) in place on (pos, mom) [3][np]:
+ * deposit -> solve (Newtonian, or the Poisson-gauge field of pm_solve) -> gather ->
+ * kick -> drift, with the periodic wrap x <- x - N floor(x/N) and a result equal to N
+ * set to 0.  force_scratch: [3][N][N][N] real (holds the force meshes on return);
+ * phi_state as in pm_solve.  Errors: PM_ERR_ARG for bad arguments or flags,
+ * PM_ERR_STATE for PM_STEP_DENSITY_READY without a handed-over density. */
 int pm_step(pm_plan* plan, void* pos, void* mom, int64_t np, const pm_step_params* st, void* force_scratch,
             void* phi_state, void* stream);
 

@@ -18,6 +18,7 @@ __all__ = [
     "PMError", "lib", "SolveParams", "StepParams", "Cosmology", "ICParams", "Plan",
     "pm_deposit", "pm_solve", "pm_gather", "pm_step", "displacement_combine", "displacement_add", "pm_xi_linear",
     "pk_estimate", "pk_cross_estimate", "bias_fit", "bk_estimate",
+    "Batch", "pm_batch_step", "pm_batch_ic_zeldovich", "pm_batch_pk_estimate", "PM_BATCH_CONCURRENT",
     "pm_step_adjoint", "pm_step_adjoint_noalloc", "pm_step_adjoint_noalloc_bytes", "PM_STATIC_SCRATCH_BYTES",
     "pk_adjoint", "pm_ic_zeldovich_adjoint", "pm_noise_truncate",
     "pm_ic_zeldovich", "pm_ic_2lpt", "pm_ic_2lpt_adjoint", "pm_ic_gauge", "pm_noise_fix",
@@ -37,6 +38,7 @@ PM_NEWTON, PM_POISSON_GAUGE = 0, 1
 PM_GRAD_SPECTRAL, PM_GRAD_FD2, PM_GRAD_FD1 = 0, 1, 2
 PM_PK_POWERLAW, PM_PK_EH98 = 0, 1
 PM_STATIC_SCRATCH_BYTES = 64 << 20
+PM_BATCH_CONCURRENT = 1
 
 _c_int, _c_double, _c_void_p, _c_int64, _c_size_t = (
     ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t)
@@ -104,6 +106,15 @@ def _declare(l):
                                  _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_size_t, _c_void_p]),
         "pm_step_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int64, P(StepParams), _c_void_p, _c_void_p, _c_void_p,
                                      _c_void_p, _c_void_p]),
+        "pm_batch_create": (_c_int, [P(_c_void_p), _c_int, P(_c_int), P(_c_double), _c_int, _c_int]),
+        "pm_batch_destroy": (_c_int, [_c_void_p]),
+        "pm_batch_num_groups": (_c_int, [_c_void_p]),
+        "pm_batch_group": (_c_int, [_c_void_p, _c_int, P(_c_int), P(_c_double), P(_c_int), P(_c_void_p)]),
+        "pm_batch_step": (_c_int, [_c_void_p, P(_c_void_p), P(_c_void_p), P(StepParams), _c_void_p]),
+        "pm_batch_ic_zeldovich": (_c_int, [_c_void_p, P(_c_void_p), P(ICParams), P(_c_void_p), P(_c_void_p),
+                                           _c_void_p]),
+        "pm_batch_pk_estimate": (_c_int, [_c_void_p, P(_c_void_p), P(_c_int), _c_void_p, _c_void_p, _c_void_p,
+                                          _c_void_p]),
         "pm_step_adjoint_noalloc": (_c_int, [_c_void_p, _c_void_p, _c_int64, P(StepParams), _c_void_p, _c_void_p,
                                              _c_void_p, _c_void_p]),
         "pm_step_adjoint_noalloc_bytes": (_c_size_t, [_c_int, _c_int, _c_int]),
@@ -309,6 +320,117 @@ def pm_step_adjoint(plan: Plan, pos, st: StepParams, lam_pos, lam_mom, force=Non
                                  _ptr(force, plan.dtype, "force"), _ptr(mesh_scratch, plan.dtype, "mesh_scratch"),
                                  _ptr(lam_pos, plan.dtype, "lam_pos"), _ptr(lam_mom, plan.dtype, "lam_mom"),
                                  _stream()))
+
+
+class _GroupPlan:
+    """The internal plan of one size group of a Batch, for the FFT launch-shape tuning
+    calls and the profiler only (the batch owns it)."""
+
+    def __init__(self, handle, n, box, dtype, batch, device):
+        self.handle, self.n, self.box, self.dtype, self.batch, self.device = handle, n, box, dtype, batch, device
+
+    def mesh(self, ncomp: int = 0):
+        shape = (self.batch,) + (self.n,) * 3
+        return torch.empty(((ncomp,) if ncomp else ()) + shape, dtype=self.dtype, device=self.device)
+
+
+class Batch:
+    """An uneven ensemble: box i has an n_mesh[i]^3 mesh and n_mesh[i]^3 particles in a
+    periodic box of side box[i] (pm_batch_create).  Boxes of equal mesh size and side
+    form a size group advanced by one launch per kernel."""
+
+    def __init__(self, n_mesh, box, dtype=torch.float32, device=None, concurrent: bool = False):
+        self.n_mesh = [int(v) for v in n_mesh]
+        self.box = [float(v) for v in box]
+        if len(self.n_mesh) != len(self.box) or not self.n_mesh:
+            raise PMError(PM_ERR_ARG, "n_mesh and box must be non-empty lists of equal length")
+        self.dtype = dtype
+        self.cdtype = PM_F32 if dtype == torch.float32 else PM_F64
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        nb = len(self.n_mesh)
+        h = _c_void_p()
+        _check(lib().pm_batch_create(ctypes.byref(h), nb, (_c_int * nb)(*self.n_mesh), (_c_double * nb)(*self.box),
+                                     self.cdtype, PM_BATCH_CONCURRENT if concurrent else 0))
+        self.handle = h
+
+    def __len__(self):
+        return len(self.n_mesh)
+
+    def groups(self):
+        """[(n_mesh, box, boxes in the group, group plan view)] in the batch's group order."""
+        out = []
+        for g in range(lib().pm_batch_num_groups(self.handle)):
+            n, box, cnt, ph = _c_int(), _c_double(), _c_int(), _c_void_p()
+            _check(lib().pm_batch_group(self.handle, g, ctypes.byref(n), ctypes.byref(box), ctypes.byref(cnt),
+                                        ctypes.byref(ph)))
+            out.append((n.value, box.value, cnt.value,
+                        _GroupPlan(ph, n.value, box.value, self.dtype, cnt.value, self.device)))
+        return out
+
+    def particles(self):
+        """Empty [3, n^3] arrays, one per box."""
+        return [torch.empty((3, n ** 3), dtype=self.dtype, device=self.device) for n in self.n_mesh]
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().pm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _box_ptrs(batch: Batch, arrays, per_box: int, name: str):
+    if len(arrays) != len(batch):
+        raise PMError(PM_ERR_ARG, f"{name}: {len(batch)} arrays expected")
+    ptrs = []
+    for i, (t, n) in enumerate(zip(arrays, batch.n_mesh)):
+        _need(t, per_box * n ** 3, f"{name}[{i}]")
+        ptrs.append(_ptr(t, batch.dtype, f"{name}[{i}]"))
+    return (_c_void_p * len(ptrs))(*ptrs)
+
+
+def pm_batch_step(batch: Batch, pos, mom, steps):
+    """One force-kick-drift cycle of every box in place; ``steps`` is one StepParams for
+    all boxes or one per box."""
+    nb = len(batch)
+    if isinstance(steps, StepParams):
+        steps = [steps] * nb
+    if len(steps) != nb:
+        raise PMError(PM_ERR_ARG, f"{nb} step parameters expected")
+    _check(lib().pm_batch_step(batch.handle, _box_ptrs(batch, pos, 3, "pos"), _box_ptrs(batch, mom, 3, "mom"),
+                               (StepParams * nb)(*steps), _stream()))
+
+
+def pm_batch_ic_zeldovich(batch: Batch, noise, ic: ICParams, pos, mom):
+    _check(lib().pm_batch_ic_zeldovich(batch.handle, _box_ptrs(batch, noise, 1, "noise"), ctypes.byref(ic),
+                                       _box_ptrs(batch, pos, 3, "pos"), _box_ptrs(batch, mom, 3, "mom"), _stream()))
+
+
+def pm_batch_pk_estimate(batch: Batch, pos, n_bins=None, out=None):
+    """P(k) of every box; ``n_bins`` per box (default N/2).  Returns [(k_mean, P,
+    n_modes) per box], views of three flat device arrays (``out`` may supply them)."""
+    nb = len(batch)
+    bins = [n // 2 for n in batch.n_mesh] if n_bins is None else [int(v) for v in n_bins]
+    total = sum(bins)
+    if out is None:
+        out = (torch.empty(total, dtype=torch.float64, device=batch.device),
+               torch.empty(total, dtype=torch.float64, device=batch.device),
+               torch.empty(total, dtype=torch.int64, device=batch.device))
+    k, p, c = out
+    for t, nm, dt in ((k, "k_mean", torch.float64), (p, "pk", torch.float64), (c, "n_modes", torch.int64)):
+        _need(t, total, nm)
+    _check(lib().pm_batch_pk_estimate(batch.handle, _box_ptrs(batch, pos, 3, "pos"), (_c_int * nb)(*bins),
+                                      _ptr(k, torch.float64, "k_mean"), _ptr(p, torch.float64, "pk"),
+                                      _ptr(c, torch.int64, "n_modes"), _stream()))
+    res, o = [], 0
+    for b in bins:
+        res.append((k[o:o + b], p[o:o + b], c[o:o + b]))
+        o += b
+    return res
 
 
 def pm_step_adjoint_noalloc_bytes(n: int, dtype, with_force: bool) -> int:

@@ -23,7 +23,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
-SOURCES = ["fft.hip", "deposit.hip", "particles.hip", "spectra.hip", "adjoint.hip", "api.cpp", "cosmo.cpp"]
+SOURCES = ["fft.hip", "deposit.hip", "particles.hip", "spectra.hip", "adjoint.hip", "api.cpp", "cosmo.cpp",
+           "batch.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -468,8 +468,7 @@ static int solve_from_c0(pm_plan* p, const pm_solve_params* sp, void* phi, void*
   const int64_t cs = cstride(p);
   PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, -1, p->nb, cs, s));
   PM_TRY(fft_pass_solve(p, sp, phi, s));
-  PM_TRY(fft_pass_cols(p, cbuf(p, 0), 1, 1, 3 * p->nb, cs, s));
-  return fft_pass_rows_c2r(p, 3 * p->nb, cbuf(p, 0), cs, force, s);
+  return fft_force_inverse(p, sp->grad, force, s);
 }
 
 static int check_solve_params(const pm_solve_params* sp, const void* phi, const char* who) {

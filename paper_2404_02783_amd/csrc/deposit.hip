@@ -24,11 +24,12 @@ constexpr int kBlock = 256;
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_deposit(const T* __restrict__ pos, int64_t np, T* __restrict__ mesh, int n,
-                                                    T w_scale, unsigned* __restrict__ guard) {
+                                                    T w_scale, unsigned* __restrict__ guard,
+                                                    const BoxEntry* __restrict__ tab) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = blk * kBlock + threadIdx.x;
   if (i >= np) return;
-  pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
+  pos = box_positions(tab, np, pos);  // box of the batch
   mesh += (int64_t)blockIdx.y * n * n * n;
   T x = pos[i], y = pos[np + i], z = pos[2 * np + i];
   if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
@@ -69,13 +70,14 @@ constexpr int WCAP = 8192;                  // LDS window cells (32-bit fixed po
 // go to global atomics.  All window arithmetic is integer on the base nodes floor(x).
 template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restrict__ pos, float* __restrict__ mesh,
-                                                          int n, double w_scale, unsigned* __restrict__ guard) {
+                                                          int n, double w_scale, unsigned* __restrict__ guard,
+                                                          const BoxEntry* __restrict__ tab) {
   static_assert((double)TX * TY * TZ * kFixW < 4294967296.0, "a window cell could wrap");  // 2^31 at most
   __shared__ unsigned win[WCAP];
   __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
   __shared__ float wsum[kBlock / 64][3];
   const int64_t np = (int64_t)n * n * n;
-  pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
+  pos = box_positions(tab, np, pos);  // box of the batch
   mesh += (int64_t)blockIdx.y * np;
   const int tpx = n / TX, tpy = n / TY, tpz = n / TZ;
   const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
@@ -186,13 +188,13 @@ int launch_deposit(const pm_plan* p, const void* pos, int64_t np, void* mesh, hi
     // a power-of-two N wraps without a division (same results)
     auto kern = (n & (n - 1)) == 0 ? k_deposit_tiled<true> : k_deposit_tiled<false>;
     hipLaunchKernelGGL(kern, dim3(tiles, (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const float*>(pos),
-                       static_cast<float*>(mesh), n, w, p->guard);
+                       static_cast<float*>(mesh), n, w, p->guard, p->box_tab);
   } else if (p->dtype == PM_F32) {
     hipLaunchKernelGGL(k_deposit<float>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const float*>(pos), np,
-                       static_cast<float*>(mesh), n, (float)w, p->guard);
+                       static_cast<float*>(mesh), n, (float)w, p->guard, p->box_tab);
   } else {
     hipLaunchKernelGGL(k_deposit<double>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s, static_cast<const double*>(pos), np,
-                       static_cast<double*>(mesh), n, w, p->guard);
+                       static_cast<double*>(mesh), n, w, p->guard, p->box_tab);
   }
   return hip_check(hipGetLastError(), "deposit");
 }

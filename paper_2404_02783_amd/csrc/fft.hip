@@ -48,7 +48,7 @@ void launch_r2c_t(const T* in, cx<T>* out, const RowArgs& g, int ncomp, const cx
   hipLaunchKernelGGL((k_fft_rows_r2c<T, L1, L2>), grid, block, (size_t)R * RS * sizeof(cx<T>), s, in, out, g, tw);
 }
 
-template <typename T, int L1, int L2, bool ZMASK = false>
+template <typename T, int L1, int L2, int MODE = C2R_PLAIN>
 void launch_c2r_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx<T>* tw, int rows, hipStream_t s) {
   constexpr int M = L1 * L2;
   constexpr int TPC = L1 > L2 ? L1 : L2;
@@ -57,14 +57,29 @@ void launch_c2r_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx
   const int R = rows > 0 ? rows : 256 / TPC;
   dim3 grid((unsigned)((g.nrows + R - 1) / R), (unsigned)ncomp);
   dim3 block((unsigned)(R * TPC));
-  hipLaunchKernelGGL((k_fft_rows_c2r<T, L1, L2, ZMASK>), grid, block, (size_t)R * XS * sizeof(cx<T>), s, in, out, g,
+  hipLaunchKernelGGL((k_fft_rows_c2r<T, L1, L2, MODE>), grid, block, (size_t)R * XS * sizeof(cx<T>), s, in, out, g,
                      tw);
+}
+
+template <typename T, int L1, int L2>
+void launch_c2r_force_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx<T>* tw, int rows,
+                        hipStream_t s) {
+  launch_c2r_t<T, L1, L2, C2R_FORCE>(in, out, g, ncomp, tw, rows, s);
+}
+
+template <typename T, int L1, int L2>
+void launch_cols_gform_t(cx<T>* data, const ColArgs& g, int nbox, int n, int grad, int outer, const cx<T>* tw,
+                         hipStream_t s) {
+  const int tpc = std::max(L1, L2);
+  size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
+  hipLaunchKernelGGL((k_fft_cols_gform<T, L1, L2>), dim3((unsigned)(outer * g.groups), (unsigned)(2 * nbox)),
+                     dim3((unsigned)(g.bcols * tpc)), shm, s, data, g, nbox, n, grad, tw);
 }
 
 template <typename T, int L1, int L2>
 void launch_c2r_zmask_t(const cx<T>* in, T* out, const RowArgs& g, int ncomp, const cx<T>* tw, int rows,
                         hipStream_t s) {
-  launch_c2r_t<T, L1, L2, true>(in, out, g, ncomp, tw, rows, s);
+  launch_c2r_t<T, L1, L2, C2R_ZMASK>(in, out, g, ncomp, tw, rows, s);
 }
 
 template <typename T, int L1, int L2>
@@ -86,7 +101,7 @@ void launch_cols_shell1_t(cx<T>* data, const ColArgs& g, const ShellArgs& sh, in
 }
 
 template <typename T, int L1, int L2>
-void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* o2, cx<T>* phi, const ColArgs& g, const SolveArgs& a, int outer,
+void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* phi, const ColArgs& g, const SolveArgs& a, int outer,
                     const cx<T>* tw, hipStream_t s) {
   const int tpc = std::max(L1, L2);
   dim3 grid((unsigned)(outer * g.groups), (unsigned)a.nbox);
@@ -94,10 +109,9 @@ void launch_solve_t(cx<T>* data, cx<T>* o1, cx<T>* o2, cx<T>* phi, const ColArgs
   size_t shm = (size_t)L1 * L2 * g.bcols * sizeof(cx<T>);
   // one launch: forward transform, symbol, both inverse transforms
   if (a.kind == PM_NEWTON)
-    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_NEWTON, 2>), grid, block, shm, s, data, o1, o2, phi, g, a, tw);
+    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_NEWTON>), grid, block, shm, s, data, o1, phi, g, a, tw);
   else
-    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_POISSON_GAUGE, 2>), grid, block, shm, s, data, o1, o2, phi, g,
-                       a, tw);
+    hipLaunchKernelGGL((k_fft_cols_solve<T, L1, L2, PM_POISSON_GAUGE>), grid, block, shm, s, data, o1, phi, g, a, tw);
 }
 
 #define PM_TRY_HIP(expr, what)                  \
@@ -229,9 +243,8 @@ int solve_t(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t 
   a.phi_stride = (int64_t)n * n * (n / 2 + 1);
   cx<T>* c0 = static_cast<cx<T>*>(cbuf(p, 0));
   cx<T>* c1 = static_cast<cx<T>*>(cbuf(p, 1));
-  cx<T>* c2 = static_cast<cx<T>*>(cbuf(p, 2));
   const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
-  PM_DISPATCH_LEN(n, launch_solve_t, c0, c1, c2, static_cast<cx<T>*>(phi), g, a, n, tw, s)
+  PM_DISPATCH_LEN(n, launch_solve_t, c0, c1, static_cast<cx<T>*>(phi), g, a, n, tw, s)
   return hip_check(hipGetLastError(), "fft solve pass");
 }
 
@@ -306,10 +319,43 @@ int fft_pass_rows_c2r(const pm_plan* p, int ncomp, const void* in, int64_t in_co
   return p->dtype == PM_F32 ? c2r_t<float>(p, ncomp, in, in_comp, out, s) : c2r_t<double>(p, ncomp, in, in_comp, out, s);
 }
 
+// Inverse passes of the solve's G form: along axis 1 (F_x in place; G read once, D_y G
+// to the third region and G in place), then the rows to the three real force meshes
+// [3][nb][N^3] with D_z applied to the transformed G on load.
+template <typename T>
+int force_inverse_t(const pm_plan* p, int grad, void* force, hipStream_t s) {
+  const int n = p->n;
+  const cx<T>* tw = static_cast<const cx<T>*>(p->tw);
+  ColArgs g = col_args(n, p->hp, 1, p->tune[0] > 0 ? p->tune[0] : cols_per_block<T>(n));
+  g.comp_stride = cstride(p);
+  {
+    ProfScope ps(p, PK_COLS_INV_AXIS1, s);
+    PM_DISPATCH_LEN(n, launch_cols_gform_t, static_cast<cx<T>*>(cbuf(p, 0)), g, p->nb, n, grad, n, tw, s)
+    PM_TRY_HIP(hipGetLastError(), "fft column pass (G form)");
+  }
+  ProfScope ps(p, PK_C2R_ROWS, s);
+  RowArgs r;
+  r.nrows = (int64_t)n * n;
+  r.in_comp = cstride(p);
+  r.out_comp = (int64_t)n * n * n;
+  r.n = n;
+  r.hs = p->hp;
+  r.zmask4 = 0.0;
+  r.nbox = p->nb;
+  r.grad = grad;
+  PM_DISPATCH_LEN(n / 2, launch_c2r_force_t, static_cast<const cx<T>*>(cbuf(p, 0)), static_cast<T*>(force), r,
+                  3 * p->nb, tw, p->tune[3], s)
+  return hip_check(hipGetLastError(), "fft c2r rows (force)");
+}
+
 int fft3_c2r_shell(const pm_plan* p, const void* src, void* work, void* out, double lo4, double hi4, hipStream_t s) {
   ProfScope ps(p, PK_BK, s);
   return p->dtype == PM_F32 ? shell_c2r_t<float>(p, src, work, out, lo4, hi4, s)
                             : shell_c2r_t<double>(p, src, work, out, lo4, hi4, s);
+}
+
+int fft_force_inverse(const pm_plan* p, int grad, void* force, hipStream_t s) {
+  return p->dtype == PM_F32 ? force_inverse_t<float>(p, grad, force, s) : force_inverse_t<double>(p, grad, force, s);
 }
 
 int fft_pass_solve(const pm_plan* p, const pm_solve_params* sp, void* phi, hipStream_t s) {

@@ -23,6 +23,22 @@ __device__ __forceinline__ cx<T> tw_mul(cx<T> a, const cx<T>* tw, int m_times_st
 }
 
 
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename T>
+__device__ __forceinline__ cx<T> grad_symbol(int nd, int n, int grad) {
+  // nd in [-N/2, N/2], k = 2 pi nd / N
+  if (grad == PM_GRAD_SPECTRAL) {
+    if (nd == -n / 2 || nd == n / 2) return mk(T(0), T(0));
+    return mk(T(0), T(2.0 * kPi / n) * T(nd));
+  }
+  T sk, ck;
+  sin_cos(T(2.0 * kPi / n) * T(nd), &sk, &ck);
+  if (grad == PM_GRAD_FD2) return mk(T(0), sk);
+  return mk(ck - T(1), sk);  // PM_GRAD_FD1
+}
+
 struct ColArgs {
   int64_t stride;        // element stride along the transform axis
   int64_t outer_stride;  // stride between outer indices
@@ -164,6 +180,67 @@ __global__ void __launch_bounds__(256) k_fft_cols_shell(const cx<T>* __restrict_
   }
 }
 
+// Inverse pass along axis 1 of the solve's G form: blockIdx.y = 2 b + kind for box b.
+// kind 0: the F_x spectrum (component 0), in place.  kind 1: the y-columns of G
+// (component 1) are read once and transformed twice: D_y(ny) G to component 2, and G
+// in place.  Components c of box b sit (c nbox + b) comp_stride elements from `data`.
+template <typename T, int L1, int L2>
+__device__ __forceinline__ void col_inverse_store(cx<T> (&a)[L1], cx<T>* lds, cx<T>* base, const ColArgs& g,
+                                                  const cx<T>* __restrict__ tw, int b, int u, int B, bool valid) {
+  if (u < L2) {
+    RegDFT<T, L1, 1>::run(a);
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1)
+      lds[col_lds_index<T, L1, L2>(k1, u, b, B)] = k1 == 0 ? a[k1] : tw_mul<true>(a[k1], tw, u * k1 * g.tw_step);
+  }
+  __syncthreads();
+  if (u < L1) {
+    cx<T> c[L2];
+#pragma unroll
+    for (int j2 = 0; j2 < L2; ++j2) c[j2] = lds[col_lds_index<T, L1, L2>(u, j2, b, B)];
+    RegDFT<T, L2, 1>::run(c);
+    if (valid) {
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) stc(base + (int64_t)(u + L1 * k2) * g.stride, c[k2]);
+    }
+  }
+}
+
+template <typename T, int L1, int L2>
+__global__ void __launch_bounds__(256) k_fft_cols_gform(cx<T>* __restrict__ data, ColArgs g, int nbox, int n, int grad,
+                                                      const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int B = g.bcols;
+  const int t = threadIdx.x;
+  const int b = t % B, u = t / B;
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t outer = lb / g.groups;
+  const int col = (int)(lb % g.groups) * B + b;
+  const bool valid = col < g.ncols;
+  const int box = (int)blockIdx.y >> 1, kind = (int)blockIdx.y & 1;
+  const int64_t off = outer * g.outer_stride + col;
+  cx<T>* c0 = data + (int64_t)(kind * nbox + box) * g.comp_stride + off;  // F_x, or G
+  cx<T> a[L1];
+  if (u < L2) {
+#pragma unroll
+    for (int j1 = 0; j1 < L1; ++j1) a[j1] = valid ? ldc(c0 + (int64_t)(u + L2 * j1) * g.stride) : mk(T(0), T(0));
+  }
+  if (kind == 1) {
+    cx<T> d[L1];
+    if (u < L2) {
+#pragma unroll
+      for (int j1 = 0; j1 < L1; ++j1) {
+        const int iy = u + L2 * j1;
+        d[j1] = grad_symbol<T>(iy < n / 2 ? iy : iy - n, n, grad) * a[j1];
+      }
+    }
+    col_inverse_store<T, L1, L2>(d, lds, data + (int64_t)(2 * nbox + box) * g.comp_stride + off, g, tw, b, u, B, valid);
+    __syncthreads();  // the exchange buffer is reused
+  }
+  col_inverse_store<T, L1, L2>(a, lds, c0, g, tw, b, u, B, valid);
+}
+
 // Real-to-complex along the contiguous axis: rows of N reals -> rows of N/2+1
 // complex.  M = N/2 = L1*L2 complex points z[n] = x[2n] + i x[2n+1];
 // X[k] = E[k] + W_N^k O[k] with E = (Z[k] + conj Z[M-k])/2, O = -i (Z[k] - conj Z[M-k])/2.
@@ -174,8 +251,13 @@ struct RowArgs {
   int64_t in_comp, out_comp;  // component strides (elements of the in/out type)
   int n;                      // N (real row length)
   int hs;                     // spectrum row stride (complex elements, >= N/2+1)
-  double zmask4;              // c2r with ZMASK: only coefficients k with 4 k^2 < zmask4 are read
+  double zmask4;              // c2r MODE 1: only coefficients k with 4 k^2 < zmask4 are read
+  int nbox;                   // c2r MODE 2: boxes per component
+  int grad;                   // c2r MODE 2: gradient symbol (PM_GRAD_*) of the z component
 };
+
+// Modes of the c2r rows pass.
+enum { C2R_PLAIN = 0, C2R_ZMASK = 1, C2R_FORCE = 2 };
 
 template <typename T, int L1, int L2>
 __global__ void __launch_bounds__(256) k_fft_rows_r2c(const T* __restrict__ in, cx<T>* __restrict__ out, RowArgs g,
@@ -235,7 +317,10 @@ __global__ void __launch_bounds__(256) k_fft_rows_r2c(const T* __restrict__ in, 
 // x[n] = sum_{k in full row} X[k] exp(+2 pi i n k / N)).
 // Z[k] = (X[k] + conj X[M-k]) + i conj(W_N^k) (X[k] - conj X[M-k]), z = IDFT_M(Z),
 // x[2n] = Re z[n], x[2n+1] = Im z[n].
-template <typename T, int L1, int L2, bool ZMASK = false>
+// MODE C2R_FORCE: the three force components of the solve's G form (see
+// k_fft_cols_solve): output component 0 from input component 0 (F_x), 1 from input 2
+// (the y-transformed D_y G), 2 from input 1 (the y-transformed G) times D_z(k) on load.
+template <typename T, int L1, int L2, int MODE = C2R_PLAIN>
 __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ in, T* __restrict__ out, RowArgs g,
                                                     const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
@@ -249,7 +334,14 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ 
   const int64_t row = (int64_t)blockIdx.x * R + r;
   const bool valid = row < g.nrows;
   const int N = g.n;
-  const cx<T>* src = in + (int64_t)blockIdx.y * g.in_comp + row * g.hs;
+  int64_t src_comp = blockIdx.y;
+  bool zgrad = false;
+  if (MODE == C2R_FORCE) {
+    const int c = (int)blockIdx.y / g.nbox, b = (int)blockIdx.y % g.nbox;
+    src_comp = (int64_t)(c == 0 ? 0 : (c == 1 ? 2 : 1)) * g.nbox + b;
+    zgrad = c == 2;
+  }
+  const cx<T>* src = in + src_comp * g.in_comp + row * g.hs;
   T* dst = out + (int64_t)blockIdx.y * g.out_comp + row * N;
   cx<T>* my = lds + r * XS;
 
@@ -261,12 +353,17 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ 
     for (int j1 = 0; j1 < L1; ++j1) {
       const int k = u + L2 * j1;
       bool vk = valid, vm = valid;
-      if (ZMASK) {  // coefficients beyond the shell's reach hold stale data
+      if (MODE == C2R_ZMASK) {  // coefficients beyond the shell's reach hold stale data
         vk = vk && 4.0 * (double)k * (double)k < g.zmask4;
         vm = vm && 4.0 * (double)(M - k) * (double)(M - k) < g.zmask4;
       }
-      const cx<T> xk = vk ? ldc(src + k) : mk(T(0), T(0));
-      const cx<T> xm = vm ? conjg(ldc(src + (M - k))) : mk(T(0), T(0));
+      cx<T> xk = vk ? ldc(src + k) : mk(T(0), T(0));
+      cx<T> xm = vm ? ldc(src + (M - k)) : mk(T(0), T(0));
+      if (MODE == C2R_FORCE && zgrad) {  // F_z = D_z(k) G, k the z frequency (0 <= k <= N/2)
+        xk = grad_symbol<T>(k, N, g.grad) * xk;
+        xm = grad_symbol<T>(M - k, N, g.grad) * xm;
+      }
+      xm = conjg(xm);
       const cx<T> s = xk + xm;
       const cx<T> d = twiddle<true>(xk - xm, tw[k]);  // d * conj(W_N^k)
       a[j1] = mk(s.x - d.y, s.y + d.x);               // s + i d
@@ -292,9 +389,9 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ 
 }
 
 // ------------------------------------------------------------------------
-// Fused k-space solve along axis 0: forward column transform, per-mode potential
-// and gradient symbols for the three force components, inverse column transform
-// of each component.  Component 0 is written in place; 1 and 2 go to out1/out2.
+// Fused k-space solve along axis 0: forward column transform, per-mode potential,
+// then the inverse column transforms of D_x G (in place) and of G (to out1), from
+// which the passes along y and z make the three force components.
 // ------------------------------------------------------------------------
 struct SolveArgs {
   int n;            // N
@@ -308,26 +405,10 @@ struct SolveArgs {
   int64_t phi_stride;  // complex elements between the boxes' potentials
 };
 
-__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
-
-template <typename T>
-__device__ __forceinline__ cx<T> grad_symbol(int nd, int n, int grad) {
-  // nd in [-N/2, N/2], k = 2 pi nd / N
-  if (grad == PM_GRAD_SPECTRAL) {
-    if (nd == -n / 2 || nd == n / 2) return mk(T(0), T(0));
-    return mk(T(0), T(2.0 * kPi / n) * T(nd));
-  }
-  T sk, ck;
-  sin_cos(T(2.0 * kPi / n) * T(nd), &sk, &ck);
-  if (grad == PM_GRAD_FD2) return mk(T(0), sk);
-  return mk(ck - T(1), sk);  // PM_GRAD_FD1
-}
-
-template <typename T, int L1, int L2, int KIND, int PASS>
+template <typename T, int L1, int L2, int KIND>
 __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data, cx<T>* __restrict__ out1,
-                                                      cx<T>* __restrict__ out2, cx<T>* __restrict__ phi, ColArgs g,
-                                                      SolveArgs s, const cx<T>* __restrict__ tw) {
+                                                      cx<T>* __restrict__ phi, ColArgs g, SolveArgs s,
+                                                      const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int B = g.bcols;
@@ -343,7 +424,6 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
     const int64_t bo = (int64_t)blockIdx.y * s.box_stride;
     data += bo;
     out1 += bo;
-    out2 += bo;
     if (KIND != PM_NEWTON) phi += (int64_t)blockIdx.y * s.phi_stride;
   }
 
@@ -382,26 +462,21 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
         // the carried potential keeps the unpadded [N][N][N/2+1] layout of the C ABI
         const int64_t pidx = ((int64_t)ix * N + outer) * (N / 2 + 1) + col;
         const cx<T> pstored = valid ? ldc(phi + pidx) : mk(T(0), T(0));
-        cx<T> pnew;
-        if (PASS != 0) {  // update phi_old -> phi_new (the second launch of the split form reads it)
-          const T h = T(s.h), h2 = T(s.h2);
-          const T den = -k2s - T(3) * h2 - T(3) * h * T(s.inv_dtau) - T(4.5) * h2 * T(s.om_a);
-          const cx<T> num = scale(X[k2], T(1.5) * h2 * T(s.om_a)) - scale(pstored, T(3) * h * T(s.inv_dtau));
-          pnew = zero ? mk(T(0), T(0)) : scale(num, T(1) / den);
-          if (valid) stc(phi + pidx, pnew);
-        } else {  // second launch: phi already holds phi_new
-          pnew = pstored;
-        }
+        const T h = T(s.h), h2 = T(s.h2);
+        const T den = -k2s - T(3) * h2 - T(3) * h * T(s.inv_dtau) - T(4.5) * h2 * T(s.om_a);
+        const cx<T> num = scale(X[k2], T(1.5) * h2 * T(s.om_a)) - scale(pstored, T(3) * h * T(s.inv_dtau));
+        const cx<T> pnew = zero ? mk(T(0), T(0)) : scale(num, T(1) / den);  // phi_old -> phi_new
+        if (valid) stc(phi + pidx, pnew);
         X[k2] = scale(pnew, -T(s.a_c2));
       }
     }
   }
-  // Inverse transform.  Along axis 0 the y and z gradient symbols are constants, so
-  //   F_x = IDFT(D_x G),  F_y = D_y IDFT(G),  F_z = D_z IDFT(G).
-  // PASS 2: one launch does both inverse transforms (F_x in place first, then F_y, F_z).
-  // Split form: PASS 1 (launched first) writes F_y, F_z to out1, out2; PASS 0
-  // (launched second, after the spectrum in `data` is no longer needed) writes F_x.
-  if (PASS == 2) {
+  // Inverse transforms.  Along axis 0 the y and z gradient symbols are constants, so
+  //   F_x = IDFT(D_x G),  F_y = D_y IDFT(G),  F_z = D_z IDFT(G)
+  // (G here the potential times its prefactor).  F_x is written in place and IDFT(G)
+  // to out1 (the "G form"): D_y is applied by the inverse pass along y and D_z by the
+  // c2r rows pass, so F_y and F_z never exist as spectra of their own.
+  {
     __syncthreads();  // every thread has read its forward data from LDS
     if (u < L1) {
       cx<T> Y[L2];
@@ -427,15 +502,8 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
       }
     }
   }
-  __syncthreads();  // every thread has read its forward data (or the F_x exchange) from LDS
+  __syncthreads();  // every thread has read the F_x exchange from LDS
   if (u < L1) {
-    if (PASS == 0) {
-#pragma unroll
-      for (int k2 = 0; k2 < L2; ++k2) {
-        const int ix = u + L1 * k2;
-        X[k2] = grad_symbol<T>(ix < N / 2 ? ix : ix - N, N, s.grad) * X[k2];
-      }
-    }
     RegDFT<T, L2, 1>::run(X);
 #pragma unroll
     for (int ja = 0; ja < L2; ++ja)
@@ -448,19 +516,8 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
     for (int k1 = 0; k1 < L1; ++k1) c[k1] = lds[col_lds_index<T, L1, L2>(k1, u, b, B)];
     RegDFT<T, L1, 1>::run(c);
     if (valid) {
-      if (PASS == 0) {
 #pragma unroll
-        for (int jb = 0; jb < L1; ++jb) stc(data + off + (int64_t)(u + L2 * jb) * g.stride, c[jb]);
-      } else {
-        const int ny = outer < N / 2 ? (int)outer : (int)outer - N;
-        const cx<T> dy = grad_symbol<T>(ny, N, s.grad), dz = grad_symbol<T>(col, N, s.grad);
-#pragma unroll
-        for (int jb = 0; jb < L1; ++jb) {
-          const int64_t o = off + (int64_t)(u + L2 * jb) * g.stride;
-          stc(out1 + o, dy * c[jb]);
-          stc(out2 + o, dz * c[jb]);
-        }
-      }
+      for (int jb = 0; jb < L1; ++jb) stc(out1 + off + (int64_t)(u + L2 * jb) * g.stride, c[jb]);
     }
   }
 }

@@ -65,12 +65,11 @@ __global__ void __launch_bounds__(kBlock) k_gather(const T* __restrict__ force, 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gather_kdk(const T* __restrict__ force, T* __restrict__ pos,
                                                        T* __restrict__ mom, int64_t np, int n, int64_t fstride, T kick,
-                                                       T drift) {
+                                                       T drift, const BoxEntry* __restrict__ tab) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = blk * kBlock + threadIdx.x;
   if (i >= np) return;
-  pos += (int64_t)blockIdx.y * 3 * np;
-  mom += (int64_t)blockIdx.y * 3 * np;
+  box_arrays(tab, np, pos, mom, kick, drift);
   force += (int64_t)blockIdx.y * n * n * n;
   T x = wrap(pos[i], n), y = wrap(pos[np + i], n), z = wrap(pos[2 * np + i], n);
   T fx, fy, fz;
@@ -230,14 +229,14 @@ template <bool DEPOSIT, bool P2>
 __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __restrict__ force, float* __restrict__ pos,
                                                              float* __restrict__ mom, int n, int64_t fstride,
                                                              float kick, float drift, float* __restrict__ dens,
-                                                             float w_scale, unsigned* __restrict__ guard) {
+                                                             float w_scale, unsigned* __restrict__ guard,
+                                                             const BoxEntry* __restrict__ tab) {
   constexpr int NT = DEPOSIT ? 2 : 1;
   __shared__ __attribute__((aligned(16))) float win[3 * GCAP];
   __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
   __shared__ float wsum[kBlock / 64][3];
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
-  pos += (int64_t)blockIdx.y * 3 * np;  // box of the batch
-  mom += (int64_t)blockIdx.y * 3 * np;
+  box_arrays(tab, np, pos, mom, kick, drift);  // box of the batch
   force += (int64_t)blockIdx.y * np;
   if (DEPOSIT) dens += (int64_t)blockIdx.y * np;
   const int tpy = n / GTY, tpz = n / GTZ;
@@ -388,14 +387,15 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, co
 // Box blockIdx.y of a batch of gridDim.y: disp is [3][nbox][N^3], pos/mom [nbox][3][N^3].
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ic_lattice(const T* __restrict__ disp, T* __restrict__ pos,
-                                                       T* __restrict__ mom, int n, T mom_factor) {
+                                                       T* __restrict__ mom, int n, T mom_factor,
+                                                       const BoxEntry* __restrict__ tab) {
   const int64_t np = (int64_t)n * n * n;
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= np) return;
   const int64_t dstride = (int64_t)gridDim.y * np;
   disp += (int64_t)blockIdx.y * np;
-  pos += (int64_t)blockIdx.y * 3 * np;
-  mom += (int64_t)blockIdx.y * 3 * np;
+  T unused_kick = T(0), unused_drift = T(0);
+  box_arrays(tab, np, pos, mom, unused_kick, unused_drift);
   const int q[3] = {(int)(j / ((int64_t)n * n)), (int)((j / n) % n), (int)(j % n)};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -495,15 +495,16 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
                      : (p2 ? k_gather_kdk_tiled<false, true> : k_gather_kdk_tiled<false, false>);
     hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, static_cast<const float*>(force), static_cast<float*>(pos),
                        static_cast<float*>(mom), n, fstride, (float)kick, (float)drift,
-                       dens ? static_cast<float*>(dens) : nullptr, dens ? w : 0.f, dens ? p->guard : nullptr);
+                       dens ? static_cast<float*>(dens) : nullptr, dens ? w : 0.f, dens ? p->guard : nullptr,
+                       p->box_tab);
   } else if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_gather_kdk<float>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s,
                        static_cast<const float*>(force), static_cast<float*>(pos), static_cast<float*>(mom), np, p->n,
-                       fstride, (float)kick, (float)drift);
+                       fstride, (float)kick, (float)drift, p->box_tab);
   else
     hipLaunchKernelGGL(k_gather_kdk<double>, dim3(nblocks(np), (unsigned)p->nb), dim3(kBlock), 0, s,
                        static_cast<const double*>(force), static_cast<double*>(pos), static_cast<double*>(mom), np, p->n,
-                       fstride, kick, drift);
+                       fstride, kick, drift, p->box_tab);
   return hip_check(hipGetLastError(), "gather-kick-drift");
 }
 
@@ -530,10 +531,10 @@ int launch_ic_lattice(const pm_plan* p, const void* disp, void* pos, void* mom, 
   const dim3 grid(nblocks(np), (unsigned)p->nb);
   if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_ic_lattice<float>, grid, dim3(kBlock), 0, s, static_cast<const float*>(disp),
-                       static_cast<float*>(pos), static_cast<float*>(mom), p->n, (float)mom_factor);
+                       static_cast<float*>(pos), static_cast<float*>(mom), p->n, (float)mom_factor, p->box_tab);
   else
     hipLaunchKernelGGL(k_ic_lattice<double>, grid, dim3(kBlock), 0, s, static_cast<const double*>(disp),
-                       static_cast<double*>(pos), static_cast<double*>(mom), p->n, mom_factor);
+                       static_cast<double*>(pos), static_cast<double*>(mom), p->n, mom_factor, p->box_tab);
   return hip_check(hipGetLastError(), "ic lattice");
 }
 

@@ -8,6 +8,16 @@
 
 namespace pm {
 
+// Particle arrays and kick/drift factors of one box of an uneven ensemble's size group
+// (pm_batch): the particle kernels of a group plan read box blockIdx.y's entry from a
+// device table instead of taking the plan's arrays at a stride of 3 N^3.
+struct BoxEntry {
+  void* pos;
+  void* mom;
+  double kick;
+  double drift;
+};
+
 // ------------------------------------------------------------------ complex --
 
 template <typename T>

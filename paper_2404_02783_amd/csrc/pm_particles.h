@@ -280,4 +280,25 @@ __device__ __forceinline__ TileWindow tile_window(const float (&x)[PP], const fl
   return w;
 }
 
+// Particle arrays (and, with a table, kick and drift) of box blockIdx.y: the table's
+// entry when a table is given, else the arrays at a stride of 3 np from the pointers.
+template <typename T>
+__device__ __forceinline__ void box_arrays(const BoxEntry* tab, int64_t np, T* __restrict__& pos, T* __restrict__& mom,
+                                           T& kick, T& drift) {
+  if (tab) {
+    const BoxEntry& e = tab[blockIdx.y];
+    pos = static_cast<T*>(e.pos);
+    mom = static_cast<T*>(e.mom);
+    kick = T(e.kick);
+    drift = T(e.drift);
+  } else {
+    pos += (int64_t)blockIdx.y * 3 * np;
+    mom += (int64_t)blockIdx.y * 3 * np;
+  }
+}
+template <typename T>
+__device__ __forceinline__ const T* box_positions(const BoxEntry* tab, int64_t np, const T* pos) {
+  return tab ? static_cast<const T*>(tab[blockIdx.y].pos) : pos + (int64_t)blockIdx.y * 3 * np;
+}
+
 }  // namespace pm

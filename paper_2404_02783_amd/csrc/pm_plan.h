@@ -122,9 +122,14 @@ int fft3_c2r_shell(const pm_plan* p, const void* src, void* work, void* out, dou
 int fft_pass_cols(const pm_plan* p, void* data, int axis, int dir, int ncomp, int64_t comp_stride, hipStream_t s);
 int fft_pass_rows_r2c(const pm_plan* p, int count, const void* in, void* out, hipStream_t s);
 int fft_pass_rows_c2r(const pm_plan* p, int ncomp, const void* in, int64_t in_comp, void* out, hipStream_t s);
-// Fused solve pass along axis 0 on cbuf(0) (all nb boxes): writes force spectra to
-// cbuf 0, 1, 2; phi_state holds nb unpadded [N][N][N/2+1] potentials.
+// Fused solve pass along axis 0 on cbuf(0) (all nb boxes): writes the F_x spectrum
+// in place and that of G (the potential times its prefactor) to cbuf 1, both
+// transformed back along axis 0; phi_state holds nb unpadded [N][N][N/2+1] potentials.
 int fft_pass_solve(const pm_plan* p, const pm_solve_params* sp, void* phi_state, hipStream_t s);
+// After fft_pass_solve: the inverse passes along axis 1 and the rows that turn its
+// output (F_x and G spectra in the first two regions; the third is scratch) into the
+// three real force meshes [3][nb][N^3], with the gradient symbols D_y, D_z applied.
+int fft_force_inverse(const pm_plan* p, int grad, void* force, hipStream_t s);
 
 // ---------------------------------------------------------- particles.hip --
 int launch_fill(const pm_plan* p, void* mesh, int64_t count, double value, hipStream_t s);

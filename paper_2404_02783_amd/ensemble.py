@@ -1,12 +1,13 @@
 """Batched ensembles of independent periodic boxes with uneven meshes (host loop
 over the C ABI; every step runs in the library's kernels).
 
-Boxes of equal mesh size form one batched plan, so each kernel of a leapfrog cycle
-is one launch per size group whatever the number of boxes.  The whole run of every
-group -- Zel'dovich ICs, the leapfrog cycles and the final P(k) -- can be captured
-once into a single HIP graph (``torch.cuda.CUDAGraph`` is HIP's graph API on ROCm)
-and replayed, which removes the per-launch host cost that dominates small boxes.
-Inputs (noise fields) are device-resident before the run.
+The boxes form one ``Batch`` (pm_batch_*): boxes of equal mesh size and side are a
+size group advanced by one launch per kernel whatever the number of boxes, and a
+whole run -- Zel'dovich ICs, the leapfrog cycles and the final P(k) -- is a handful of
+batch calls per cycle, which can be captured once into a single HIP graph
+(``torch.cuda.CUDAGraph`` is HIP's graph API on ROCm) and replayed, removing the
+per-launch host cost that dominates small boxes.  Inputs (noise fields) are
+device-resident before the run.
 
 Not part of the paper's pipeline: ensembles of independent realisations are what
 the paper's ensemble error bars on the scale-dependent bias would need (Sec. 5.2).
@@ -17,9 +18,9 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import (FIDUCIAL, ICParams, PM_PK_EH98, PM_STEP_DENSITY_READY, PM_STEP_DEPOSIT_NEXT, Plan, StepParams,
-               kdk_factors, newton_params, pk_estimate, pm_deposit, pm_ic_zeldovich, pm_noise_fix, pm_step,
-               power_eh98_amplitude)
+from . import (FIDUCIAL, Batch, ICParams, PM_PK_EH98, PM_STEP_DENSITY_READY, PM_STEP_DEPOSIT_NEXT, Plan,
+               StepParams, kdk_factors, newton_params, pk_estimate, pm_batch_ic_zeldovich, pm_batch_pk_estimate,
+               pm_batch_step, pm_deposit, pm_ic_zeldovich, pm_noise_fix, pm_step, power_eh98_amplitude)
 from .sim import log_steps
 from .tuning import tune
 
@@ -51,17 +52,12 @@ def default_groups(first_seed: int = 100):
 @dataclass
 class _State:
     group: Group
-    plan: Plan
-    noise: torch.Tensor
-    pos: torch.Tensor
+    noise: torch.Tensor    # [boxes, N, N, N]
+    pos: torch.Tensor      # [boxes, 3, N^3]
     mom: torch.Tensor
-    force: torch.Tensor
-    disp: torch.Tensor
-    delta: torch.Tensor
+    first: int             # index of the group's first box in the batch
     out: tuple = field(default=None)
     tuning: tuple = field(default=None)
-    pk_out: tuple = field(default=None)
-    stream: object = field(default=None)
 
 
 def schedule(a_start=0.02, a_end=1.0, n_steps=30, n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL):
@@ -80,14 +76,17 @@ def schedule(a_start=0.02, a_end=1.0, n_steps=30, n_s=0.965, sigma8=0.81, cosmo=
 
 
 class Ensemble:
-    """All groups of an ensemble with their device buffers.  ``noise_fn(n, seed)``
-    returns the host white-noise field of one box (float64 numpy [n, n, n]).
+    """All boxes of an ensemble as one Batch, with their device buffers.
+    ``noise_fn(n, seed)`` returns the host white-noise field of one box (float64 numpy
+    [n, n, n]).
 
     ``paired_fixed``: every seed gives two boxes, 2j and 2j + 1, run from the
     paired-and-fixed noise of that seed (fixed mode amplitudes; the partner's field
     negated); ``paired_power_spectra`` averages each pair.  ``autotune``: each size
     group's FFT launch shapes are measured for its batch (or read from
-    ``tuning_cache``, a JSON file) before the run."""
+    ``tuning_cache``, a JSON file) before the run.  ``concurrent``: each size group
+    runs on a stream of its own inside the batch calls (forked from and joined back
+    into the current stream)."""
 
     def __init__(self, groups, noise_fn, a_start=0.02, a_end=1.0, n_steps=30, dtype=torch.float32, device=None,
                  n_s=0.965, sigma8=0.81, cosmo=FIDUCIAL, paired_fixed: bool = False, autotune: bool = False,
@@ -95,65 +94,61 @@ class Ensemble:
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.dtype = dtype
         self.paired_fixed = paired_fixed
+        self.concurrent = concurrent
         self.a_steps, self.ic, self.cycles = schedule(a_start, a_end, n_steps, n_s, sigma8, cosmo)
+        reps = 2 if paired_fixed else 1
         self.states = []
+        n_mesh, sides, first = [], [], 0
         for g in groups:
-            reps = 2 if paired_fixed else 1
-            plan = Plan(g.n, g.box, dtype, self.device, batch=reps * len(g.seeds))
+            nb = reps * len(g.seeds)
             noise = torch.stack([torch.from_numpy(noise_fn(g.n, s)) for s in g.seeds for _ in range(reps)])
             noise = noise.to(dtype).to(self.device).contiguous()
-            if paired_fixed:
-                pm_noise_fix(plan, noise, 2, out=noise)
-            st = _State(g, plan, noise, plan.particles(), plan.particles(), plan.mesh(3), plan.mesh(3), plan.mesh())
-            if autotune:   # FFT launch shapes measured for this group's batch (delta as scratch)
-                st.tuning = tune(plan, tuning_cache, mesh_scratch=st.delta)
-            shape = (plan.batch, g.bins())
-            st.pk_out = (torch.empty(shape, dtype=torch.float64, device=self.device),
-                         torch.empty(shape, dtype=torch.float64, device=self.device),
-                         torch.empty(shape, dtype=torch.int64, device=self.device))
-            st.stream = torch.cuda.Stream(device=self.device) if concurrent else None
-            self.states.append(st)
-        self.concurrent = concurrent
+            if paired_fixed:   # setup: a temporary batched plan fixes and pairs the noise
+                fix_plan = Plan(g.n, g.box, dtype, self.device, batch=nb)
+                pm_noise_fix(fix_plan, noise, 2, out=noise)
+                torch.cuda.synchronize()
+                del fix_plan
+            pos = torch.empty((nb, 3, g.n ** 3), dtype=dtype, device=self.device)
+            self.states.append(_State(g, noise, pos, torch.empty_like(pos), first))
+            n_mesh += [g.n] * nb
+            sides += [g.box] * nb
+            first += nb
+        self.batch = Batch(n_mesh, sides, dtype, self.device, concurrent=concurrent)
+        self.noise = [st.noise[i] for st in self.states for i in range(st.noise.shape[0])]
+        self.pos = [st.pos[i] for st in self.states for i in range(st.pos.shape[0])]
+        self.mom = [st.mom[i] for st in self.states for i in range(st.mom.shape[0])]
+        self.bins = [st.group.bins() for st in self.states for _ in range(st.noise.shape[0])]
+        total = sum(self.bins)
+        self.pk_out = (torch.empty(total, dtype=torch.float64, device=self.device),
+                       torch.empty(total, dtype=torch.float64, device=self.device),
+                       torch.empty(total, dtype=torch.int64, device=self.device))
+        self.group_tuning = []
+        if autotune:   # FFT launch shapes measured for each size group of the batch
+            for n, box, cnt, gplan in self.batch.groups():
+                scratch = gplan.mesh()
+                self.group_tuning.append(((n, box, cnt), tune(gplan, tuning_cache, mesh_scratch=scratch)))
+                del scratch
+            by_size = {key[:2]: t for key, t in self.group_tuning}
+            for st in self.states:
+                st.tuning = by_size[(st.group.n, st.group.box)]
         self.graph = None
 
-    def _run_group(self, st):
-        """The whole run of one group, in order, on the current stream."""
-        pm_ic_zeldovich(st.plan, st.noise, self.ic, st.disp, st.pos, st.mom)
-        for j, cyc in enumerate(self.cycles):
-            fl = (PM_STEP_DENSITY_READY if j > 0 else 0) | (PM_STEP_DEPOSIT_NEXT if j + 1 < len(self.cycles) else 0)
-            pm_step(st.plan, st.pos, st.mom, StepParams(kick=cyc.kick, drift=cyc.drift, solve=cyc.solve, flags=fl),
-                    st.force)
-        pm_deposit(st.plan, st.pos, st.delta)
-        pk_estimate(st.plan, st.delta, st.group.bins(), out=st.pk_out)
-        st.out = st.pk_out
-
     def run(self):
-        """Issue the whole run of every group: ICs, the leapfrog cycles (without the
-        final half kick) and P(k) at a_end.  On the current stream, cycle by cycle
-        over the groups; with ``concurrent`` each group runs on a stream of its own
-        (forked from and joined back into the current stream), so that the groups'
-        kernels may overlap on the GPU."""
-        if self.concurrent:
-            cur = torch.cuda.current_stream()
-            for st in self.states:
-                st.stream.wait_stream(cur)
-                with torch.cuda.stream(st.stream):
-                    self._run_group(st)
-            for st in self.states:
-                cur.wait_stream(st.stream)
-            return
-        for st in self.states:
-            pm_ic_zeldovich(st.plan, st.noise, self.ic, st.disp, st.pos, st.mom)
+        """Issue the whole run of every box: ICs, the leapfrog cycles (without the
+        final half kick) and P(k) at a_end, as batch calls on the current stream."""
+        pm_batch_ic_zeldovich(self.batch, self.noise, self.ic, self.pos, self.mom)
         for j, cyc in enumerate(self.cycles):
             # each cycle leaves the density of the drifted positions for the next one
             fl = (PM_STEP_DENSITY_READY if j > 0 else 0) | (PM_STEP_DEPOSIT_NEXT if j + 1 < len(self.cycles) else 0)
-            c = StepParams(kick=cyc.kick, drift=cyc.drift, solve=cyc.solve, flags=fl)
-            for st in self.states:
-                pm_step(st.plan, st.pos, st.mom, c, st.force)
+            pm_batch_step(self.batch, self.pos, self.mom,
+                          StepParams(kick=cyc.kick, drift=cyc.drift, solve=cyc.solve, flags=fl))
+        pm_batch_pk_estimate(self.batch, self.pos, self.bins, out=self.pk_out)
+        k, p, c = self.pk_out
+        o = 0
         for st in self.states:
-            pm_deposit(st.plan, st.pos, st.delta)
-            pk_estimate(st.plan, st.delta, st.group.bins(), out=st.pk_out)
-            st.out = st.pk_out   # [boxes, bins], also for a one-box group
+            nb, b = st.noise.shape[0], st.group.bins()
+            st.out = (k[o:o + nb * b].view(nb, b), p[o:o + nb * b].view(nb, b), c[o:o + nb * b].view(nb, b))
+            o += nb * b
 
     def capture(self):
         """Capture run() into one HIP graph (after one eager warm-up run)."""

@@ -81,7 +81,9 @@ def test_host_power_amplitudes_match_oracle():
 def test_every_entry_point_has_a_binding_of_the_same_name():
     # plan lifetime and the error string are covered by Plan and PMError
     by_class = {"pm_plan_create", "pm_plan_create_batch", "pm_plan_destroy", "pm_plan_workspace_bytes",
-                "pm_plan_workspace_bytes_batch", "pm_last_error"}
+                "pm_plan_workspace_bytes_batch", "pm_last_error",
+                # batch lifetime and groups are covered by Batch
+                "pm_batch_create", "pm_batch_destroy", "pm_batch_num_groups", "pm_batch_group"}
     missing = []
     for n in _declared():
         if n in by_class:
@@ -90,4 +92,4 @@ def test_every_entry_point_has_a_binding_of_the_same_name():
         if not any(callable(getattr(pm, c, None)) for c in cands):
             missing.append(n)
     assert missing == []
-    assert callable(pm.Plan) and issubclass(pm.PMError, RuntimeError)
+    assert callable(pm.Plan) and callable(pm.Batch) and issubclass(pm.PMError, RuntimeError)

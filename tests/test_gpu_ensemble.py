@@ -139,7 +139,7 @@ def test_concurrent_groups_match_the_serial_run_eager_and_graphed():
     want = [o[1].clone() for o in serial.power_spectra()]
     del serial
     ens = ensemble.Ensemble(groups, _noise, 0.02, 0.06, 3, torch.float64, dev, concurrent=True)
-    assert len({id(st.stream) for st in ens.states}) == 3
+    assert len(ens.batch.groups()) == 3
     ens.run()
     torch.cuda.synchronize()
     for o, w in zip(ens.power_spectra(), want):
@@ -157,6 +157,111 @@ def test_concurrent_groups_match_the_serial_run_eager_and_graphed():
         x = torch.randn(1 << 20, device=dev)   # eager work between replays
         float(x.sum())
         torch.cuda.synchronize()
+
+
+# ------------------------------------------------- uneven batch entry points --
+
+def _uneven_batch_case(dt, seed):
+    """Boxes of three mesh sizes, two sides at one size, in interleaved order."""
+    sizes = [(64, 500.0), (32, 250.0), (64, 600.0), (128, 1000.0), (32, 250.0), (64, 500.0)]
+    g = si.rng(seed)
+    pos, mom = [], []
+    for i, (n, _) in enumerate(sizes):
+        x = torch.from_numpy(si.lattice_jitter_particles(n, seed + 10 + i, 0.6 + 0.8 * i)).to(dt)
+        x[x >= n] = 0
+        pos.append(x)
+        mom.append((0.2 * torch.from_numpy(g.standard_normal((3, n ** 3)))).to(dt))
+    return sizes, pos, mom
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_batch_step_boxes_match_their_single_box_runs(dt, concurrent):
+    """pm_batch_step on an uneven batch (three mesh sizes; per-box kicks and drifts;
+    density handed from cycle to cycle) against each box run alone with pm_step."""
+    dev = _dev()
+    sizes, pos0, mom0 = _uneven_batch_case(dt, 900)
+    batch = pm.Batch([n for n, _ in sizes], [b for _, b in sizes], dt, dev, concurrent=concurrent)
+    assert [(n, b, c) for n, b, c, _ in batch.groups()] == [(128, 1000.0, 1), (64, 500.0, 2), (64, 600.0, 1),
+                                                           (32, 250.0, 2)]
+    pos = [x.clone().to(dev).contiguous() for x in pos0]
+    mom = [p.clone().to(dev).contiguous() for p in mom0]
+    flags = [pm.PM_STEP_DEPOSIT_NEXT, pm.PM_STEP_DENSITY_READY | pm.PM_STEP_DEPOSIT_NEXT, pm.PM_STEP_DENSITY_READY]
+    kd = [[(0.2 + 0.05 * i + 0.1 * j, 0.3 + 0.02 * i) for i in range(len(sizes))] for j in range(3)]
+    for j, fl in enumerate(flags):
+        steps = [pm.StepParams(kick=k, drift=d, solve=pm.newton_params(), flags=fl) for k, d in kd[j]]
+        pm.pm_batch_step(batch, pos, mom, steps)
+    torch.cuda.synchronize()
+    tol = 1e-6 if dt == torch.float32 else 1e-12
+    for i, (n, box) in enumerate(sizes):
+        plan = pm.Plan(n, box, dt, dev)
+        x, p = pos0[i].clone().to(dev).contiguous(), mom0[i].clone().to(dev).contiguous()
+        force = plan.mesh(3)
+        for j, fl in enumerate(flags):
+            k, d = kd[j][i]
+            pm.pm_step(plan, x, p, pm.StepParams(kick=k, drift=d, solve=pm.newton_params(), flags=fl), force)
+        torch.cuda.synchronize()
+        assert rel(mom[i], p) < tol, i
+        dx = ((pos[i].double() - x.double() + n / 2) % n - n / 2).abs().max()
+        assert float(dx) < tol * n, i
+
+
+def test_batch_ic_and_pk_match_single_box_calls():
+    """pm_batch_ic_zeldovich and pm_batch_pk_estimate (bins differing between size
+    groups) against pm_ic_zeldovich and pm_deposit + pk_estimate box by box (FP64)."""
+    dev = _dev()
+    dt = torch.float64
+    sizes = [(32, 250.0), (64, 500.0), (32, 250.0)]
+    bins = [16, 20, 16]
+    batch = pm.Batch([n for n, _ in sizes], [b for _, b in sizes], dt, dev)
+    _, ic, _ = ensemble.schedule()
+    noise = [torch.from_numpy(_noise(n, 950 + i)).to(dev).contiguous() for i, (n, _) in enumerate(sizes)]
+    pos, mom = batch.particles(), batch.particles()
+    pm.pm_batch_ic_zeldovich(batch, noise, ic, pos, mom)
+    out = pm.pm_batch_pk_estimate(batch, pos, bins)
+    torch.cuda.synchronize()
+    for i, (n, box) in enumerate(sizes):
+        plan = pm.Plan(n, box, dt, dev)
+        x, p = plan.particles(), plan.particles()
+        pm.pm_ic_zeldovich(plan, noise[i], ic, plan.mesh(3), x, p)
+        k, pk, cnt = pm.pk_estimate(plan, pm.pm_deposit(plan, x), bins[i])
+        torch.cuda.synchronize()
+        assert rel(pos[i], x) < 1e-14 and rel(mom[i], p) < 1e-14
+        assert torch.equal(out[i][2], cnt)
+        assert rel(out[i][0], k) < 1e-14 and rel(out[i][1], pk) < 1e-12
+
+
+def test_batch_step_rejects_bad_arguments():
+    dev = _dev()
+    sizes = [(32, 250.0), (32, 250.0), (64, 500.0)]
+    batch = pm.Batch([n for n, _ in sizes], [b for _, b in sizes], torch.float32, dev)
+    pos, mom = batch.particles(), batch.particles()
+    for x, p in zip(pos, mom):
+        x.fill_(0.5)
+        p.zero_()
+    sp = pm.newton_params()
+    st = [pm.StepParams(kick=0.1, drift=0.1, solve=sp) for _ in sizes]
+    bad = list(st)
+    bad[1] = pm.StepParams(kick=0.1, drift=0.1, solve=sp, flags=pm.PM_STEP_DEPOSIT_NEXT)
+    with pytest.raises(pm.PMError) as e:       # flags differ within the 32^3 group
+        pm.pm_batch_step(batch, pos, mom, bad)
+    assert e.value.code == pm.PM_ERR_ARG
+    ready = [pm.StepParams(kick=0.1, drift=0.1, solve=sp, flags=pm.PM_STEP_DENSITY_READY) for _ in sizes]
+    with pytest.raises(pm.PMError) as e:       # no density left by a previous call
+        pm.pm_batch_step(batch, pos, mom, ready)
+    assert e.value.code == pm.PM_ERR_STATE
+    gauge = [pm.StepParams(kick=0.1, drift=0.1, solve=pm.gauge_params(250.0, 32, 0.1)) for _ in sizes]
+    with pytest.raises(pm.PMError):            # Newtonian only
+        pm.pm_batch_step(batch, pos, mom, gauge)
+    nxt = [pm.StepParams(kick=0.1, drift=0.1, solve=sp, flags=pm.PM_STEP_DEPOSIT_NEXT) for _ in sizes]
+    pm.pm_batch_step(batch, pos, mom, nxt)
+    other = [x.clone() for x in pos]
+    with pytest.raises(pm.PMError) as e:       # other positions than those deposited
+        pm.pm_batch_step(batch, other, mom, ready)
+    assert e.value.code == pm.PM_ERR_STATE
+    with pytest.raises(pm.PMError):            # unsupported mesh size
+        pm.Batch([32, 100], [250.0, 300.0], torch.float32, dev)
+    torch.cuda.synchronize()
 
 
 def test_single_box_entry_points_reject_batches():
