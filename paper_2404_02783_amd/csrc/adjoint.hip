@@ -87,8 +87,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
   __shared__ float wsum[4][3];
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
   const int tpy = n / AY, tpz = n / AZ;
-  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
-  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
+  int ti, tk, tl;
+  tile_coords(xcd_block(blockIdx.x, gridDim.x), n / AX, tpy, tpz, ti, tk, tl);
   const int org[3] = {ti * AX, tk * AY, tl * AZ};
   const int t = threadIdx.x;
   float x[APP], y[APP], z[APP];
@@ -175,41 +175,45 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
 constexpr int VX = 8, VY = 8, VZ = 16;
 constexpr int VPP = VX * VY * VZ / kBlock;
 constexpr int VCAP = 4096;
-// g[d] += sum_p W(x_p - c) v_{p,d}, v = kick * lam_mom, one tile per block: the
-// window is accumulated in LDS and added to g with one global atomic per non-empty
-// cell; particles outside their tile's window go to global atomics directly.
+// g[d] += sum_p W(x_p - c) v_{p,d}, v = kick * lam_mom, one tile per block.  The three
+// components are accumulated together in LDS windows of 32-bit fixed point with a
+// per-tile, per-component scale 2^(20 - e_d) (e_d the exponent of the tile's largest
+// |v_d|): every term is rounded to the nearest multiple of 2^(e_d - 20) (a relative
+// 1e-6 of the tile's largest |v_d|) and no window cell can overflow, since the tile's
+// 1024 particles add at most 2^30 in magnitude.  Then one global atomic per
+// non-empty cell and component; particles outside their tile's window go to global
+// atomics directly.
 template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict__ pos, const float* __restrict__ lam_mom,
                                                         float kick, int n, float* __restrict__ g) {
-  __shared__ unsigned long long win[VCAP];
+  static_assert(VX * VY * VZ <= 1024, "the fixed-point headroom assumes at most 2^10 particles per tile");
+  __shared__ unsigned win[3 * VCAP];
   __shared__ int wlo[4][3], whi[4][3];
   __shared__ float wsum[4][3];
   __shared__ float wmax[4][3];
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
   const int tpy = n / VY, tpz = n / VZ;
-  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
-  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
+  int ti, tk, tl;
+  tile_coords(xcd_block(blockIdx.x, gridDim.x), n / VX, tpy, tpz, ti, tk, tl);
   const int org[3] = {ti * VX, tk * VY, tl * VZ};
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   float x[VPP], y[VPP], z[VPP], v[3][VPP];
-  int64_t jj[VPP];
   float vmax[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int p = 0; p < VPP; ++p) {
     const int loc = t + kBlock * p;
     const int li = loc / (VY * VZ), lk = (loc / VZ) % VY, ll = loc % VZ;
-    jj[p] = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
-    x[p] = wrap_n<P2>(pos[jj[p]], n);
-    y[p] = wrap_n<P2>(pos[np + jj[p]], n);
-    z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
+    const int64_t j = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
+    x[p] = wrap_n<P2>(pos[j], n);
+    y[p] = wrap_n<P2>(pos[np + j], n);
+    z[p] = wrap_n<P2>(pos[2 * np + j], n);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      v[d][p] = kick * lam_mom[d * np + jj[p]];
+      v[d][p] = kick * lam_mom[d * np + j];
       vmax[d] = fmaxf(vmax[d], fabsf(v[d][p]));
     }
   }
   const TileWindow tw = tile_window<VPP, P2>(x, y, z, n, org, VCAP, VX * VY * VZ, wlo, whi, wsum);
-  // per-component fixed-point scale 2^(40 - e), |v| < 2^e over the tile
 #pragma unroll
   for (int d = 0; d < 3; ++d)
     for (int off = 32; off > 0; off >>= 1) vmax[d] = fmaxf(vmax[d], __shfl_xor(vmax[d], off, 64));
@@ -217,77 +221,65 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
 #pragma unroll
     for (int d = 0; d < 3; ++d) wmax[wave][d] = vmax[d];
   }
+  const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
+  const int wtot = W0 * W1 * W2;
+  const int sy = W2, sx = W1 * W2;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    for (int c = t; c < wtot; c += kBlock) win[d * VCAP + c] = 0u;
   __syncthreads();
-  double scale[3];
+  float scale[3], inv[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const float m = fmaxf(fmaxf(wmax[0][d], wmax[1][d]), fmaxf(wmax[2][d], wmax[3][d]));
     int e = 0;
     (void)frexpf(m, &e);  // m < 2^e
-    scale[d] = m > 0.f ? ldexp(1.0, 40 - e) : 0.0;
+    scale[d] = m > 0.f ? ldexpf(1.f, 20 - e) : 0.f;
+    inv[d] = m > 0.f ? ldexpf(1.f, e - 20) : 0.f;
   }
-  const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
-  const int wtot = W0 * W1 * W2;
-  const int sy = W2, sx = W1 * W2;
-  // which particles fit the window
-  bool inside[VPP];
-  int base[VPP];
-  Axis<float> axs[VPP], ays[VPP], azs[VPP];
 #pragma unroll
   for (int p = 0; p < VPP; ++p) {
-    axs[p] = cic_axis_n<P2>(x[p], n);
-    ays[p] = cic_axis_n<P2>(y[p], n);
-    azs[p] = cic_axis_n<P2>(z[p], n);
-    const int rx = idiff_n<P2>(axs[p].i0, org[0], n) - tw.o[0], ry = idiff_n<P2>(ays[p].i0, org[1], n) - tw.o[1],
-              rz = idiff_n<P2>(azs[p].i0, org[2], n) - tw.o[2];
-    inside[p] = rx >= 0 && rx <= W0 - 2 && ry >= 0 && ry <= W1 - 2 && rz >= 0 && rz <= W2 - 2;
-    base[p] = inside[p] ? rx * sx + ry * sy + rz : 0;
-    if (!inside[p]) {
+    const Axis<float> ax = cic_axis_n<P2>(x[p], n), ay = cic_axis_n<P2>(y[p], n), az = cic_axis_n<P2>(z[p], n);
+    const int rx = idiff_n<P2>(ax.i0, org[0], n) - tw.o[0], ry = idiff_n<P2>(ay.i0, org[1], n) - tw.o[1],
+              rz = idiff_n<P2>(az.i0, org[2], n) - tw.o[2];
+    const bool inside = rx >= 0 && rx <= W0 - 2 && ry >= 0 && ry <= W1 - 2 && rz >= 0 && rz <= W2 - 2;
+    const float wxy[4] = {ax.w0 * ay.w0, ax.w0 * ay.w1, ax.w1 * ay.w0, ax.w1 * ay.w1};
+    if (inside) {
+      const int base = rx * sx + ry * sy + rz;
+      const int off[4] = {0, sy, sx, sx + sy};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float vs = v[d][p] * scale[d];  // |vs| < 2^20, exact power-of-two scaling
+        unsigned* wd = win + d * VCAP + base;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          atomicAdd(wd + off[q], (unsigned)(int)rintf(wxy[q] * az.w0 * vs));
+          atomicAdd(wd + off[q] + 1, (unsigned)(int)rintf(wxy[q] * az.w1 * vs));
+        }
+      }
+    } else {
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
-        const int64_t idx = (bx ? axs[p].i1 : axs[p].i0) * n2 + (int64_t)(by ? ays[p].i1 : ays[p].i0) * n +
-                            (bz ? azs[p].i1 : azs[p].i0);
-        const float w = (bx ? axs[p].w1 : axs[p].w0) * (by ? ays[p].w1 : ays[p].w0) * (bz ? azs[p].w1 : azs[p].w0);
+        const int64_t idx = (bx ? ax.i1 : ax.i0) * n2 + (int64_t)(by ? ay.i1 : ay.i0) * n + (bz ? az.i1 : az.i0);
+        const float w = wxy[2 * bx + by] * (bz ? az.w1 : az.w0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) atomic_add(g + d * np + idx, w * v[d][p]);
       }
     }
   }
-  for (int d = 0; d < 3; ++d) {
-    for (int c = t; c < wtot; c += kBlock) win[c] = 0ull;
-    __syncthreads();
-    if (scale[d] > 0.0) {
-#pragma unroll
-      for (int p = 0; p < VPP; ++p) {
-        if (!inside[p]) continue;
-        const double vs = (double)v[d][p] * scale[d];
-        const float wxy[4] = {axs[p].w0 * ays[p].w0, axs[p].w0 * ays[p].w1, axs[p].w1 * ays[p].w0,
-                              axs[p].w1 * ays[p].w1};
-        const int off[4] = {0, sy, sx, sx + sy};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          atomicAdd(win + base[p] + off[q], (unsigned long long)llrint((double)(wxy[q] * azs[p].w0) * vs));
-          atomicAdd(win + base[p] + off[q] + 1, (unsigned long long)llrint((double)(wxy[q] * azs[p].w1) * vs));
-        }
-      }
-    }
-    __syncthreads();
-    if (scale[d] > 0.0) {
-      const double inv = 1.0 / scale[d];
-      float* gd = g + (int64_t)d * np;
-      const WinDiv qsx(sx), qsy(sy);
-      for (int c = t; c < wtot; c += kBlock) {
-        const long long q = (long long)win[c];
-        if (q == 0) continue;
-        int a, b, cz;
-        win_cell(c, qsx, qsy, a, b, cz);
-        const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + tw.o[0] + a, n), fold_n<P2>(org[1] + tw.o[1] + b, n),
-                                            fold_n<P2>(org[2] + tw.o[2] + cz, n), n);
-        atomic_add(gd + idx, (float)((double)q * inv));
-      }
-    }
-    __syncthreads();
+  __syncthreads();
+  const WinDiv qsx(sx), qsy(sy);
+  for (int c = t; c < wtot; c += kBlock) {
+    const int q0 = (int)win[c], q1 = (int)win[VCAP + c], q2 = (int)win[2 * VCAP + c];
+    if ((q0 | q1 | q2) == 0) continue;
+    int a, b, cz;
+    win_cell(c, qsx, qsy, a, b, cz);
+    const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + tw.o[0] + a, n), fold_n<P2>(org[1] + tw.o[1] + b, n),
+                                        fold_n<P2>(org[2] + tw.o[2] + cz, n), n);
+    if (q0) atomic_add(g + idx, (float)q0 * inv[0]);
+    if (q1) atomic_add(g + np + idx, (float)q1 * inv[1]);
+    if (q2) atomic_add(g + 2 * np + idx, (float)q2 * inv[2]);
   }
 }
 

@@ -163,9 +163,13 @@ extern "C" {
 
 const char* pm_last_error(void) { return g_err; }
 
+static size_t density_bytes(int n_mesh, int dtype, int n_batch) {
+  return align256((size_t)n_batch * n_mesh * n_mesh * n_mesh * (dtype == PM_F32 ? 4 : 8));
+}
+
 size_t pm_plan_workspace_bytes_batch(int n_mesh, int dtype, int n_batch) {
   if (!mesh_supported(n_mesh) || (dtype != PM_F32 && dtype != PM_F64) || n_batch < 1 || n_batch > kMaxBatch) return 0;
-  return 3 * (size_t)n_batch * complex_bytes(n_mesh, dtype);
+  return 3 * (size_t)n_batch * complex_bytes(n_mesh, dtype) + density_bytes(n_mesh, dtype, n_batch);
 }
 
 size_t pm_plan_workspace_bytes(int n_mesh, int dtype) { return pm_plan_workspace_bytes_batch(n_mesh, dtype, 1); }
@@ -237,6 +241,13 @@ int pm_plan_create_batch(pm_plan** out, int n_mesh, double box_mpch, int dtype, 
       rc = set_error(PM_ERR_NOMEM, "pm_plan_create: guard allocation");
     else
       rc = hip_check(hipMemset(p->guard, 0, 4 * sizeof(unsigned)), "pm_plan_create: guard init");
+  }
+  if (rc == PM_OK) {
+    p->dens = static_cast<char*>(p->ws) + 3 * (size_t)n_batch * p->cbytes;
+    // default priority: the stream only overlaps the density refill with the transforms
+    rc = hip_check(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking), "pm_plan_create: stream");
+    if (rc == PM_OK) rc = hip_check(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "pm_plan_create: event");
+    if (rc == PM_OK) rc = hip_check(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming), "pm_plan_create: event");
   }
   if (rc == PM_OK) rc = static_scratch_init(p->device);
   if (rc == PM_OK) {
@@ -432,6 +443,9 @@ int pm_plan_destroy(pm_plan* p) {
   if (p->tw) (void)hipFree(p->tw);
   if (p->guard) (void)hipFree(p->guard);
   if (p->sums) (void)hipFree(p->sums);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
   return PM_OK;
 }
@@ -531,25 +545,35 @@ namespace pm {
 
 // The launches of one force-kick-drift cycle on all of the plan's boxes (arguments
 // already checked; the density bookkeeping is the caller's): with
-// PM_STEP_DENSITY_READY the second workspace region must hold the density of `pos`;
-// with PM_STEP_DEPOSIT_NEXT it holds that of the drifted positions on return.
+// PM_STEP_DENSITY_READY the plan's density meshes must hold the density of `pos`;
+// with PM_STEP_DEPOSIT_NEXT they hold that of the drifted positions on return.  When
+// the next density is deposited by the fused gather kernel, the meshes are refilled
+// with -1 on the plan's second stream as soon as the r2c pass has read them, so the
+// refill overlaps the transforms (fork and join by events, which graph capture keeps).
 int step_cycle(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* st, void* force_scratch,
                void* phi_state, hipStream_t s) {
   const int64_t n3 = (int64_t)p->n * p->n * p->n;
-  void* delta = cbuf(p, 1);  // the density meshes live in the second spectrum region
+  void* delta = p->dens;
   if (!(st->flags & PM_STEP_DENSITY_READY)) {
     PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
     PM_TRY(launch_deposit(p, pos, np, delta, s));
   }
   PM_TRY(fft_pass_rows_r2c(p, p->nb, delta, cbuf(p, 0), s));
+  const bool fused = (st->flags & PM_STEP_DEPOSIT_NEXT) && gather_kdk_can_deposit(p, np);
+  if (fused) {
+    PM_TRY(hip_check(hipEventRecord(p->ev_fork, s), "pm_step: fork"));
+    PM_TRY(hip_check(hipStreamWaitEvent(p->aux, p->ev_fork, 0), "pm_step: fork"));
+    PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, p->aux));
+    PM_TRY(hip_check(hipEventRecord(p->ev_join, p->aux), "pm_step: join"));
+  }
   PM_TRY(solve_from_c0(p, &st->solve, phi_state, force_scratch, s));
   if (!(st->flags & PM_STEP_DEPOSIT_NEXT))
     return launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, nullptr, s);
-  // the second region is free again once the inverse transforms have run
-  PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
-  if (gather_kdk_can_deposit(p, np)) {
+  if (fused) {
+    PM_TRY(hip_check(hipStreamWaitEvent(s, p->ev_join, 0), "pm_step: join"));
     PM_TRY(launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, delta, s));
   } else {
+    PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
     PM_TRY(launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, nullptr, s));
     PM_TRY(launch_deposit(p, pos, np, delta, s));
   }
@@ -579,7 +603,7 @@ static int step_adjoint(pm_plan* p, const void* pos, int64_t np, const pm_step_p
   char* g = static_cast<char*>(mesh_scratch);
   if (!force) {
     void* fs = g + 3 * mesh_bytes;
-    void* delta = cbuf(p, 1);
+    void* delta = p->dens;
     PM_TRY(launch_fill(p, delta, n3, -1.0, s));
     PM_TRY(launch_deposit(p, pos, np, delta, s));
     PM_TRY(fft_pass_rows_r2c(p, 1, delta, cbuf(p, 0), s));
@@ -632,7 +656,7 @@ int pk_adjoint(pm_plan* p, const void* pos, int64_t np, int n_bins, const double
   if (np == 0) return PM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n3 = (int64_t)p->n * p->n * p->n;
-  void* delta = cbuf(p, 1);
+  void* delta = p->dens;
   PM_TRY(launch_fill(p, delta, n3, -1.0, s));
   PM_TRY(launch_deposit(p, pos, np, delta, s));
   PM_TRY(fft3_r2c(p, delta, cbuf(p, 0), s));

@@ -80,9 +80,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
   pos = box_positions(tab, np, pos);  // box of the batch
   mesh += (int64_t)blockIdx.y * np;
   const int tpx = n / TX, tpy = n / TY, tpz = n / TZ;
-  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
-  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
-  (void)tpx;
+  int ti, tk, tl;
+  tile_coords(xcd_block(blockIdx.x, gridDim.x), tpx, tpy, tpz, ti, tk, tl);
   const int org[3] = {ti * TX, tk * TY, tl * TZ};
   const int t = threadIdx.x;
   const float fn = float(n);

@@ -240,8 +240,8 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
   force += (int64_t)blockIdx.y * np;
   if (DEPOSIT) dens += (int64_t)blockIdx.y * np;
   const int tpy = n / GTY, tpz = n / GTZ;
-  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
-  const int tl = (int)(tile % tpz), tk = (int)((tile / tpz) % tpy), ti = (int)(tile / ((int64_t)tpz * tpy));
+  int ti, tk, tl;  // ti counts groups of NT tiles along x
+  tile_coords(xcd_block(blockIdx.x, gridDim.x), n / (GTX * NT), tpy, tpz, ti, tk, tl);
   const int t = threadIdx.x;
   float x[NT * GPP], y[NT * GPP], z[NT * GPP];
 #pragma unroll

@@ -301,4 +301,30 @@ __device__ __forceinline__ const T* box_positions(const BoxEntry* tab, int64_t n
   return tab ? static_cast<const T*>(tab[blockIdx.y].pos) : pos + (int64_t)blockIdx.y * 3 * np;
 }
 
+// Order of a tiled kernel's workgroups over its grid of tx x ty x tz Lagrangian tile
+// columns (z fastest).  Consecutive workgroups (of one XCD, after xcd_block) take the
+// z-run of one column, then the next column of a block of kTileBlock x kTileBlock
+// columns in (x, y), block after block: the columns whose windows share halo rows with
+// a column in x or y were processed at most about kTileBlock^2 z-runs earlier, so those
+// rows are still in the L2 or the last-level cache instead of being fetched from HBM
+// again (in plain z-y-x order the x neighbour comes ty z-runs later).  Grids whose tx
+// or ty is not a multiple of the block size keep the plain order.
+constexpr int kTileBlock = 8;
+__host__ __device__ __forceinline__ void tile_coords(int64_t lin, int tx, int ty, int tz, int& ti, int& tk, int& tl) {
+  tl = (int)(lin % tz);
+  int64_t r = lin / tz;
+  if (tx % kTileBlock == 0 && ty % kTileBlock == 0) {
+    const int xl = (int)(r % kTileBlock);
+    r /= kTileBlock;
+    const int yl = (int)(r % kTileBlock);
+    r /= kTileBlock;
+    const int nbx = tx / kTileBlock;
+    ti = (int)(r % nbx) * kTileBlock + xl;
+    tk = (int)(r / nbx) * kTileBlock + yl;
+  } else {
+    tk = (int)(r % ty);
+    ti = (int)(r / ty);
+  }
+}
+
 }  // namespace pm

@@ -45,7 +45,8 @@ struct pm_plan {
   int dtype;         // PM_F32 | PM_F64
   double box;        // Mpc/h
   size_t esize;      // sizeof(real)
-  void* ws;          // workspace: three regions of nb [N][N][hp] complex spectra
+  void* ws;          // workspace: three regions of nb [N][N][hp] complex spectra, then
+                     // the density meshes [nb][N^3] (real)
   size_t ws_bytes;
   size_t cbytes;     // bytes of one complex buffer (256-byte aligned)
   int hp;            // row stride of the internal spectra (padded N/2+1)
@@ -67,6 +68,11 @@ struct pm_plan {
   // device table of the boxes' particle arrays (a pm_batch size group), or null: the
   // particle kernels then take box b's arrays at b * 3 N^3 from the pointers passed
   const pm::BoxEntry* box_tab;
+  // the density meshes (in the workspace after the spectra), and a second stream with
+  // two events on which pm_step refills them while the transforms run
+  void* dens;
+  hipStream_t aux;
+  hipEvent_t ev_fork, ev_join;
 };
 
 namespace pm {

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <vector>
 
 #include "pm_particles.h"
 
@@ -22,6 +23,32 @@ static int fails = 0;
   } while (0)
 
 int main() {
+  // tile_coords: a bijection from workgroup order onto the tile grid, for the grids of
+  // the tiled kernels at every supported mesh size (blocked and plain orders)
+  {
+    const int sizes[] = {64, 128, 192, 256, 512, 1024};
+    const int shapes[][4] = {{4, 8, 32, 2}, {4, 8, 32, 1}, {8, 8, 16, 1}};  // tile x, y, z, tiles per workgroup in x
+    for (int n : sizes)
+      for (const auto& sh : shapes) {
+        const int tx = n / (sh[0] * sh[3]), ty = n / sh[1], tz = n / sh[2];
+        const int64_t total = (int64_t)tx * ty * tz;
+        std::vector<unsigned char> seen((size_t)total, 0);
+        for (int64_t lin = 0; lin < total; ++lin) {
+          int ti, tk, tl;
+          tile_coords(lin, tx, ty, tz, ti, tk, tl);
+          const bool in = ti >= 0 && ti < tx && tk >= 0 && tk < ty && tl >= 0 && tl < tz;
+          EXPECT(in, "tile_coords out of range: n %d lin %lld -> %d %d %d\n", n, (long long)lin, ti, tk, tl);
+          if (in) seen[((size_t)ti * ty + tk) * tz + tl] += 1;
+        }
+        for (int64_t i = 0; i < total; ++i) EXPECT(seen[(size_t)i] == 1, "tile_coords: tile %lld seen %d times\n", (long long)i, (int)seen[(size_t)i]);
+      }
+    // odd grids take the plain order
+    for (int tx : {3, 5, 8, 12}) {
+      int ti, tk, tl;
+      tile_coords(7 + 5 * 4, tx, 6, 5, ti, tk, tl);
+      if (tx % kTileBlock != 0) EXPECT(ti == (7 + 20) / 5 / 6 && tk == ((7 + 20) / 5) % 6 && tl == 2, "plain order\n");
+    }
+  }
   // WinDiv: floor(c / d) for every c, d in the window range (c < 2^14, 2 <= d < 2^14)
   for (unsigned d = 2; d < 16384; ++d) {
     const WinDiv q((int)d);
