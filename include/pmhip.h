@@ -135,9 +135,7 @@ size_t pm_plan_workspace_bytes(int n_mesh, int dtype);
 /* Create a plan for an N^3 mesh of a periodic box of side box_mpch (Mpc/h).
  * workspace: caller device buffer of ws_bytes >= pm_plan_workspace_bytes(), or NULL
  * to let the plan allocate (and free) its own.  The plan also allocates a few KB of
- * twiddle tables and counters, and creates one stream (default priority) and two
- * events with which pm_step overlaps the refill of its density mesh with the
- * transforms.  Errors: PM_ERR_SIZE for an unsupported N,
+ * twiddle tables and counters.  Errors: PM_ERR_SIZE for an unsupported N,
  * PM_ERR_NOMEM if ws_bytes is too small, PM_ERR_HIP if an allocation fails. */
 int pm_plan_create(pm_plan** out, int n_mesh, double box_mpch, int dtype, void* workspace, size_t ws_bytes);
 int pm_plan_destroy(pm_plan* plan);

@@ -242,13 +242,7 @@ int pm_plan_create_batch(pm_plan** out, int n_mesh, double box_mpch, int dtype, 
     else
       rc = hip_check(hipMemset(p->guard, 0, 4 * sizeof(unsigned)), "pm_plan_create: guard init");
   }
-  if (rc == PM_OK) {
-    p->dens = static_cast<char*>(p->ws) + 3 * (size_t)n_batch * p->cbytes;
-    // default priority: the stream only overlaps the density refill with the transforms
-    rc = hip_check(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking), "pm_plan_create: stream");
-    if (rc == PM_OK) rc = hip_check(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "pm_plan_create: event");
-    if (rc == PM_OK) rc = hip_check(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming), "pm_plan_create: event");
-  }
+  if (rc == PM_OK) p->dens = static_cast<char*>(p->ws) + 3 * (size_t)n_batch * p->cbytes;
   if (rc == PM_OK) rc = static_scratch_init(p->device);
   if (rc == PM_OK) {
     p->sums_cap = (size_t)n_batch * 3 * (size_t)std::max(n_mesh, 512) + 2 * 4096;
@@ -443,9 +437,6 @@ int pm_plan_destroy(pm_plan* p) {
   if (p->tw) (void)hipFree(p->tw);
   if (p->guard) (void)hipFree(p->guard);
   if (p->sums) (void)hipFree(p->sums);
-  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
-  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
-  if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
   return PM_OK;
 }
@@ -547,9 +538,8 @@ namespace pm {
 // already checked; the density bookkeeping is the caller's): with
 // PM_STEP_DENSITY_READY the plan's density meshes must hold the density of `pos`;
 // with PM_STEP_DEPOSIT_NEXT they hold that of the drifted positions on return.  When
-// the next density is deposited by the fused gather kernel, the meshes are refilled
-// with -1 on the plan's second stream as soon as the r2c pass has read them, so the
-// refill overlaps the transforms (fork and join by events, which graph capture keeps).
+// the fused gather kernel deposits the next density, the meshes are refilled with -1
+// as soon as the r2c pass has read them.
 int step_cycle(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_params* st, void* force_scratch,
                void* phi_state, hipStream_t s) {
   const int64_t n3 = (int64_t)p->n * p->n * p->n;
@@ -560,17 +550,11 @@ int step_cycle(pm_plan* p, void* pos, void* mom, int64_t np, const pm_step_param
   }
   PM_TRY(fft_pass_rows_r2c(p, p->nb, delta, cbuf(p, 0), s));
   const bool fused = (st->flags & PM_STEP_DEPOSIT_NEXT) && gather_kdk_can_deposit(p, np);
-  if (fused) {
-    PM_TRY(hip_check(hipEventRecord(p->ev_fork, s), "pm_step: fork"));
-    PM_TRY(hip_check(hipStreamWaitEvent(p->aux, p->ev_fork, 0), "pm_step: fork"));
-    PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, p->aux));
-    PM_TRY(hip_check(hipEventRecord(p->ev_join, p->aux), "pm_step: join"));
-  }
+  if (fused) PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));
   PM_TRY(solve_from_c0(p, &st->solve, phi_state, force_scratch, s));
   if (!(st->flags & PM_STEP_DEPOSIT_NEXT))
     return launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, nullptr, s);
   if (fused) {
-    PM_TRY(hip_check(hipStreamWaitEvent(s, p->ev_join, 0), "pm_step: join"));
     PM_TRY(launch_gather_kdk(p, force_scratch, pos, mom, np, st->kick, st->drift, delta, s));
   } else {
     PM_TRY(launch_fill(p, delta, n3 * p->nb, -1.0, s));

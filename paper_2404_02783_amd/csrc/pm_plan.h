@@ -68,11 +68,9 @@ struct pm_plan {
   // device table of the boxes' particle arrays (a pm_batch size group), or null: the
   // particle kernels then take box b's arrays at b * 3 N^3 from the pointers passed
   const pm::BoxEntry* box_tab;
-  // the density meshes (in the workspace after the spectra), and a second stream with
-  // two events on which pm_step refills them while the transforms run
+  // the density meshes [nb][N^3] (in the workspace after the spectra) that pm_step
+  // hands from one cycle to the next
   void* dens;
-  hipStream_t aux;
-  hipEvent_t ev_fork, ev_join;
 };
 
 namespace pm {
