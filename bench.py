@@ -21,6 +21,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -502,6 +503,47 @@ def ensemble_leg(pm):
     return out
 
 
+# Legs that need only the library (their own inputs and plans).  Each runs in a child
+# process of its own, started before this process touches the GPU (a process that has
+# initialised the GPU starts no programs) and released, one at a time, once the 1024^3
+# legs have freed their memory: a failure in one is recorded in its entry and costs
+# neither the other legs nor the headline line.
+CHILD_LEGS = ("gradient_order_study", "adjoint_128", "ensemble")
+CHILD_LEG_TIMEOUT_S = 600
+
+
+def start_child_leg(name: str):
+    return subprocess.Popen([sys.executable, "-u", os.path.abspath(__file__), "--leg", name], cwd=ROOT,
+                            stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
+
+
+def finish_child_leg(proc, name: str) -> dict:
+    """Release a waiting child leg and collect the JSON line it prints."""
+    print(f"[bench] {name} (child process {proc.pid})", file=sys.stderr, flush=True)
+    try:
+        out, _ = proc.communicate("go\n", timeout=CHILD_LEG_TIMEOUT_S)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        proc.communicate()
+        return {"error": f"no result within {CHILD_LEG_TIMEOUT_S} s (killed)"}
+    lines = [ln for ln in out.splitlines() if ln.startswith("{")]
+    if proc.returncode == 0 and lines:
+        return json.loads(lines[-1])
+    return {"error": f"child process ended with status {proc.returncode} before its result"}
+
+
+def run_child_leg(name: str) -> None:
+    """Body of a child leg: wait for the parent's go (end of input: the parent is gone),
+    then run the leg on cuda:0 and print its result as one JSON line."""
+    import torch  # noqa: F401  (loaded while waiting; the GPU is not touched before the go)
+    if sys.stdin.readline().strip() != "go":
+        return
+    import paper_2404_02783_amd as pm
+    torch.cuda.set_device(torch.device("cuda:0"))
+    leg = {"gradient_order_study": gradient_study, "adjoint_128": adjoint_small, "ensemble": ensemble_leg}[name]
+    print(json.dumps(leg(pm)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -522,11 +564,23 @@ def main():
                          "whole step than the built-in shapes, so off by default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for hardware byte counters)")
+    ap.add_argument("--legs", default=",".join(CHILD_LEGS),
+                    help="comma-separated child-process legs to run (of %s; ignored with --no-extras)"
+                         % ", ".join(CHILD_LEGS))
+    ap.add_argument("--leg", choices=CHILD_LEGS, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.leg:
+        run_child_leg(args.leg)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the multi-GPU (sharded) path is not implemented",
               file=sys.stderr)
         sys.exit(2)
+    legs = [] if args.no_extras else [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in CHILD_LEGS:
+            ap.error(f"unknown leg {x!r}")
+    children = {x: start_child_leg(x) for x in legs}   # before this process touches the GPU
 
     import numpy as np
     import torch
@@ -672,8 +726,8 @@ def main():
         out["estimators_combination_1024"] = estimators_and_combination(pm, plan, pos, noise, a_end)
         print("[bench] initial conditions at 1024^3", file=sys.stderr, flush=True)
         out["initial_conditions_1024"] = ic_leg(pm, plan, noise, icp)
+    del run, pos, mom
     if args.adjoint_cycles > 0:
-        del run, pos, mom
         torch.cuda.synchronize()
         print(f"[bench] adjoint: {args.adjoint_cycles} cycles, checkpoint every {args.adjoint_ckpt}",
               file=sys.stderr, flush=True)
@@ -686,14 +740,10 @@ def main():
             "forward_s": round(t_fwd, 4), "backward_s": round(t_bwd, 4),
             "kernels": {k: {"avg_ms": round(ms / c, 4), "launches": c} for k, (ms, c) in aprof.items()}}
     del noise, plan
-    if not args.no_extras:
-        torch.cuda.empty_cache()
-        print("[bench] gradient-order study at 256^3", file=sys.stderr, flush=True)
-        out["gradient_order_study"] = gradient_study(pm)
-        print("[bench] 128^3 adjoint configuration", file=sys.stderr, flush=True)
-        out["adjoint_128"] = adjoint_small(pm)
-        print("[bench] 64-box ensemble", file=sys.stderr, flush=True)
-        out["ensemble"] = ensemble_leg(pm)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    for x, proc in children.items():
+        out[x] = finish_child_leg(proc, x)
     if not args.no_cpu_baseline:
         print(f"[bench] CPU oracle baseline at {args.cpu_sample}^3 ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

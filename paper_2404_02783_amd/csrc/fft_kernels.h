@@ -346,24 +346,47 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ 
   cx<T>* my = lds + r * XS;
 
   cx<T> a[L1];
-  if (u < L2) {
-    // X[k] and its mirror X[M-k] come straight from the row (the mirrored loads hit
-    // the lines the neighbouring lanes fetch)
+  // coefficient k of the row as the split below uses it: masked (C2R_ZMASK: beyond the
+  // shell's reach the row holds stale data) or multiplied by D_z(k) (C2R_FORCE's z
+  // component: F_z = D_z(k) G, k the z frequency, 0 <= k <= N/2)
+  auto coeff = [&](int k) -> cx<T> {
+    bool vk = valid;
+    if (MODE == C2R_ZMASK) vk = vk && 4.0 * (double)k * (double)k < g.zmask4;
+    cx<T> x = vk ? ldc(src + k) : mk(T(0), T(0));
+    if (MODE == C2R_FORCE && zgrad) x = grad_symbol<T>(k, N, g.grad) * x;
+    return x;
+  };
+  if constexpr (64 % TPC == 0) {
+    // Every coefficient is loaded once: lane u holds X[u + L2 j1], and the mirror
+    // X[M - k] of its k = u + L2 j1 is X[(L2 - u) + L2 (L1 - 1 - j1)] of lane L2 - u
+    // (u >= 1) or X[L2 (L1 - j1)] of its own (u = 0; X[M] itself for j1 = 0), so the
+    // mirrors travel between the lanes of the row (one wave holds whole rows).
+    cx<T> xv[L1];
+#pragma unroll
+    for (int j1 = 0; j1 < L1; ++j1) xv[j1] = u < L2 ? coeff(u + L2 * j1) : mk(T(0), T(0));
+    const cx<T> xnyq = u == 0 ? coeff(M) : mk(T(0), T(0));
+    const int partner = u < L2 ? (L2 - u) % L2 : 0;
+#pragma unroll
+    for (int j1 = 0; j1 < L1; ++j1) {
+      cx<T> xm;
+      xm.x = __shfl(xv[L1 - 1 - j1].x, partner, TPC);
+      xm.y = __shfl(xv[L1 - 1 - j1].y, partner, TPC);
+      if (u == 0) xm = j1 == 0 ? xnyq : xv[(L1 - j1) % L1];
+      xm = conjg(xm);
+      const cx<T> xk = xv[j1];
+      const cx<T> s = xk + xm;
+      const cx<T> d = twiddle<true>(xk - xm, tw[u + L2 * j1]);  // d * conj(W_N^k)
+      a[j1] = mk(s.x - d.y, s.y + d.x);                         // s + i d
+    }
+    if (u < L2) RegDFT<T, L1, 1>::run(a);
+  } else if (u < L2) {
+    // rows that straddle waves: X[k] and its mirror X[M-k] come straight from the row
+    // (the mirrored loads hit the lines the neighbouring lanes fetch)
 #pragma unroll
     for (int j1 = 0; j1 < L1; ++j1) {
       const int k = u + L2 * j1;
-      bool vk = valid, vm = valid;
-      if (MODE == C2R_ZMASK) {  // coefficients beyond the shell's reach hold stale data
-        vk = vk && 4.0 * (double)k * (double)k < g.zmask4;
-        vm = vm && 4.0 * (double)(M - k) * (double)(M - k) < g.zmask4;
-      }
-      cx<T> xk = vk ? ldc(src + k) : mk(T(0), T(0));
-      cx<T> xm = vm ? ldc(src + (M - k)) : mk(T(0), T(0));
-      if (MODE == C2R_FORCE && zgrad) {  // F_z = D_z(k) G, k the z frequency (0 <= k <= N/2)
-        xk = grad_symbol<T>(k, N, g.grad) * xk;
-        xm = grad_symbol<T>(M - k, N, g.grad) * xm;
-      }
-      xm = conjg(xm);
+      const cx<T> xk = coeff(k);
+      const cx<T> xm = conjg(coeff(M - k));
       const cx<T> s = xk + xm;
       const cx<T> d = twiddle<true>(xk - xm, tw[k]);  // d * conj(W_N^k)
       a[j1] = mk(s.x - d.y, s.y + d.x);               // s + i d
