@@ -89,10 +89,17 @@ __global__ void __launch_bounds__(kBlock) k_gather_kdk(const T* __restrict__ for
 // (neighbouring tiles on the same XCD re-read overlapping rows from L2), and
 // interpolates from LDS.  If the box exceeds the LDS capacity, fit_box's smaller box
 // of the same proportions is staged and particles outside it read the meshes directly.
+// Once the particles have moved apart (late, clustered cycles) most of the bounding
+// box is cells no particle of the tile touches: a box of more than GSPARSE cells is
+// staged sparsely -- the particles first mark their eight CIC cells in a byte map of
+// the box, and only marked cells are loaded (the others are never read).
 // Weights and arithmetic are those of k_gather_kdk.
 constexpr int GTX = 4, GTY = 8, GTZ = 32;
 constexpr int GPP = GTX * GTY * GTZ / kBlock;  // particles per thread
 constexpr int GCAP = 4096;                     // staged cells (x3 components, float)
+// the dense box of an undisplaced tile is (GTX + 1)(GTY + 1)(GTZ + 1) = 1485 cells
+constexpr int GSPARSE = 2048;
+static_assert(GCAP == 16 * kBlock, "the byte map is cleared with one 16-byte store per thread");
 
 // DEPOSIT: after the drift, the tile's new positions are also deposited into `dens`
 // (pre-filled with -1, box offset N^3) like the standalone tiled deposit -- an LDS
@@ -110,9 +117,9 @@ constexpr int DCAP = 3 * GCAP * (int)sizeof(float) / (int)sizeof(unsigned);
 template <bool GUARD, bool P2>
 __device__ __forceinline__ void gather_tile(const float* __restrict__ force, float* __restrict__ pos,
                                             float* __restrict__ mom, int n, int64_t fstride, float kick, float drift,
-                                            const int (&org)[3], float* win, int (*wlo)[3], int (*whi)[3],
-                                            float (*wsum)[3], float (&x)[GPP], float (&y)[GPP], float (&z)[GPP],
-                                            unsigned* __restrict__ guard) {
+                                            const int (&org)[3], float* win, unsigned char* mark, int (*wlo)[3],
+                                            int (*whi)[3], float (*wsum)[3], float (&x)[GPP], float (&y)[GPP],
+                                            float (&z)[GPP], unsigned* __restrict__ guard) {
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
   const int t = threadIdx.x;
   int64_t jj[GPP];
@@ -139,9 +146,33 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
     }
   }
   int o[3], W[3];
+  reinterpret_cast<uint4*>(mark)[t] = make_uint4(0u, 0u, 0u, 0u);  // GCAP bytes, 16 per thread
   block_window(lo, hi, sum, GTX * GTY * GTZ, GCAP, wlo, whi, wsum, o, W);
   const int wtot = W[0] * W[1] * W[2];
   const int sy = W[2], sx = W[1] * W[2];
+  // sparse box: mark the CIC cells of the particles inside it (plain byte stores into
+  // the map cleared before block_window's barriers)
+  const bool sparse = wtot > GSPARSE;  // the same in every thread
+  if (sparse) {
+#pragma unroll
+    for (int p = 0; p < GPP; ++p) {
+      const int rx = idiff_n<P2>((int)floorf(x[p]), org[0], n) - o[0];
+      const int ry = idiff_n<P2>((int)floorf(y[p]), org[1], n) - o[1];
+      const int rz = idiff_n<P2>((int)floorf(z[p]), org[2], n) - o[2];
+      if (rx >= 0 && rx <= W[0] - 2 && ry >= 0 && ry <= W[1] - 2 && rz >= 0 && rz <= W[2] - 2) {
+        unsigned char* m = mark + win_index(rx, ry, rz, sx, sy);
+        m[0] = 1;
+        m[1] = 1;
+        m[sy] = 1;
+        m[sy + 1] = 1;
+        m[sx] = 1;
+        m[sx + 1] = 1;
+        m[sx + sy] = 1;
+        m[sx + sy + 1] = 1;
+      }
+    }
+    __syncthreads();
+  }
   // the momenta are needed only after the window: start their loads now
   float mx[GPP], my[GPP], mz[GPP];
 #pragma unroll
@@ -152,12 +183,13 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
   }
   // stage the force window (row-contiguous along z): all of a thread's loads are
   // issued before its first LDS store, so they are in flight together
-  float fa[GCAP / kBlock], fb[GCAP / kBlock], fc[GCAP / kBlock];
+  // (cells a sparse box skips are stored as zeros; no particle reads them)
+  float fa[GCAP / kBlock] = {}, fb[GCAP / kBlock] = {}, fc[GCAP / kBlock] = {};
   const WinDiv qsx(sx), qsy(sy);
 #pragma unroll
   for (int k = 0; k < GCAP / kBlock; ++k) {
     const int c = t + kBlock * k;
-    if (c < wtot) {
+    if (c < wtot && (!sparse || mark[c])) {
       int a, b, cz;
       win_cell(c, qsx, qsy, a, b, cz);
       const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + o[0] + a, n), fold_n<P2>(org[1] + o[1] + b, n),
@@ -233,6 +265,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
                                                              const BoxEntry* __restrict__ tab) {
   constexpr int NT = DEPOSIT ? 2 : 1;
   __shared__ __attribute__((aligned(16))) float win[3 * GCAP];
+  __shared__ __attribute__((aligned(16))) unsigned char mark[GCAP];  // sparse staging map
   __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
   __shared__ float wsum[kBlock / 64][3];
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
@@ -249,7 +282,8 @@ __global__ void __launch_bounds__(kBlock, 3) k_gather_kdk_tiled(const float* __r
     const int orgs[3] = {(ti * NT + sub) * GTX, tk * GTY, tl * GTZ};
     float xs[GPP], ys[GPP], zs[GPP];
     if (sub > 0) __syncthreads();  // the previous tile is done with the window
-    gather_tile<DEPOSIT, P2>(force, pos, mom, n, fstride, kick, drift, orgs, win, wlo, whi, wsum, xs, ys, zs, guard);
+    gather_tile<DEPOSIT, P2>(force, pos, mom, n, fstride, kick, drift, orgs, win, mark, wlo, whi, wsum, xs, ys, zs,
+                             guard);
 #pragma unroll
     for (int p = 0; p < GPP; ++p) {
       x[sub * GPP + p] = xs[p];

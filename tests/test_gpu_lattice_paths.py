@@ -4,10 +4,12 @@ benchmark's ensembles and late clustered steps take (Sec. 2's PM cycle):
 * N = 192, a mesh size that is not a power of two, so the kernels wrap, fold and take
   minimum images with divisions instead of masks (deposit, plain cycle, the cycle
   fused with the next cycle's deposit, the adjoint cycle);
-* jitters of 0.8 and 6 cells: at 0.8 every tile fits its LDS window; at 6 every tile
-  outgrows it, so the windows shrink to fit_box's box and the particles outside take
-  the direct global paths (global atomics for the deposit, direct force loads for the
-  gather).  A host count of the window volumes asserts which case each input is.
+* jitters of 0.4, 0.8 and 6 cells: at 0.4 every gather tile's box is the undisplaced
+  one and is staged whole; at 0.8 the boxes are larger than the sparse threshold, so
+  only the cells the particles touch are staged; at 6 every tile outgrows its window,
+  so the windows shrink to fit_box's box and the particles outside take the direct
+  global paths (global atomics for the deposit, direct force loads for the gather).
+  A host count of the window volumes asserts which case each input is.
 
 Each cycle is checked against the oracle's force-kick-drift cycle on the positions and
 momenta the GPU cycle started from (promoted exactly to FP64), so the density handed
@@ -32,6 +34,8 @@ F32_TOL = 1e-5
 DEPOSIT_TILE, DEPOSIT_CAP = (8, 8, 16), 8192
 GATHER_TILE, GATHER_CAP = (4, 8, 32), 4096
 FUSED_TILE, FUSED_CAP = (8, 8, 32), 12288
+# gather boxes of more cells than this are staged sparsely (marked cells only)
+GATHER_SPARSE = 2048
 
 
 def _dev():
@@ -50,10 +54,9 @@ def min_image(d, n):
     return (d + n / 2) % n - n / 2
 
 
-def overflow_fraction(pos: torch.Tensor, n: int, tile, cap: int) -> float:
-    """Fraction of Lagrangian tiles whose CIC bounding box (base cells floor(x) as
-    minimum images relative to the tile origin, widened by one cell) exceeds `cap`
-    cells: the tiles whose windows fit_box shrinks."""
+def window_volumes(pos: torch.Tensor, n: int, tile) -> torch.Tensor:
+    """Cells of each Lagrangian tile's CIC bounding box (base cells floor(x) as minimum
+    images relative to the tile origin, widened by one cell)."""
     tx, ty, tz = tile
     base = torch.floor(pos.double()).long().reshape(3, n, n, n)
     vol = torch.ones((n // tx, n // ty, n // tz), dtype=torch.int64)
@@ -65,7 +68,13 @@ def overflow_fraction(pos: torch.Tensor, n: int, tile, cap: int) -> float:
         lo = r.amin(dim=(1, 3, 5))
         hi = r.amax(dim=(1, 3, 5))
         vol = vol * (hi - lo + 2)
-    return float((vol > cap).double().mean())
+    return vol
+
+
+def overflow_fraction(pos: torch.Tensor, n: int, tile, cap: int) -> float:
+    """Fraction of Lagrangian tiles whose box exceeds `cap` cells: the tiles whose
+    windows fit_box shrinks."""
+    return float((window_volumes(pos, n, tile) > cap).double().mean())
 
 
 def _lattice(n, seed, amp, dt=torch.float32):
@@ -80,6 +89,11 @@ def _case_windows(x, n, amp):
                  ((DEPOSIT_TILE, DEPOSIT_CAP), (GATHER_TILE, GATHER_CAP), (FUSED_TILE, FUSED_CAP))]
     if amp < 1:
         assert max(fractions) == 0.0, fractions
+        vol = window_volumes(x, n, GATHER_TILE)
+        if amp < 0.5:
+            assert int(vol.max()) <= GATHER_SPARSE, int(vol.max())
+        else:
+            assert int(vol.min()) > GATHER_SPARSE, int(vol.min())
     else:
         assert min(fractions) == 1.0, fractions
     return fractions
@@ -101,7 +115,7 @@ def test_deposit_192(amp):
     assert abs(float(d.double().sum())) < 1e-3 * n ** 1.5
 
 
-@pytest.mark.parametrize("amp", [0.8, 6.0])
+@pytest.mark.parametrize("amp", [0.4, 0.8, 6.0])
 def test_plain_step_192(amp):
     dev = _dev()
     n = 192
@@ -150,9 +164,15 @@ def _handed_over_cycles(n, amp, seed, box):
         assert float(torch.linalg.norm(d)) / float(torch.linalg.norm(wx)) < F32_TOL, j
 
 
-@pytest.mark.parametrize("amp", [0.8, 6.0])
+@pytest.mark.parametrize("amp", [0.4, 0.8, 6.0])
 def test_density_handed_over_cycles_192(amp):
     _handed_over_cycles(192, amp, 94, 1500.0)
+
+
+@pytest.mark.parametrize("amp", [0.4, 0.8])
+def test_density_handed_over_cycles_128(amp):
+    """Power-of-two mesh (mask arithmetic) with whole and sparsely staged gather boxes."""
+    _handed_over_cycles(128, amp, 95, 1000.0)
 
 
 def test_density_handed_over_cycles_fit_box_128():

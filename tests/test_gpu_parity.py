@@ -210,10 +210,11 @@ def test_gather(dt):
 # -------------------------------------------------------------------- step --
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("n,amp", [(32, 0.8), (128, 0.8), (128, 6.0)])
+@pytest.mark.parametrize("n,amp", [(32, 0.8), (128, 0.4), (128, 0.8), (128, 6.0)])
 def test_step_matches_force_kick_drift(dt, n, amp):
-    # FP32 N^3 lattice runs at N >= 64 stage forces through LDS windows; amp = 6 pushes
-    # tiles past the window capacity so the direct-read fallback runs too.
+    # FP32 N^3 lattice runs at N >= 64 stage forces through LDS windows: whole at
+    # amp = 0.4, only the touched cells at 0.8 (boxes past the sparse threshold); amp = 6
+    # pushes tiles past the window capacity so the direct-read fallback runs too.
     dev = _dev()
     x = torch.from_numpy(si.lattice_jitter_particles(n, 9, amp))
     v = torch.from_numpy(si.rng(10).standard_normal((3, n ** 3))) * 0.05
