@@ -67,13 +67,18 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_kdk(const T* __restrict__
   lam_pos[2 * np + i] = lx[2] + gz;
 }
 
-// Full-lattice (np = N^3, FP32) variants.  The force-field term is computed per
-// Lagrangian tile of AX x AY x AZ particles with the three force meshes staged in LDS
-// over the tile's CIC bounding box (as in the forward gather); the deposit of v is
-// split off into k_deposit_vec, which works like the counting-density deposit: an
-// LDS window per tile in signed 64-bit fixed point with a per-tile, per-component
-// scale (so the window sums carry ~41 bits relative to the tile's largest |v|), then
-// one global atomic per non-empty window cell.
+// Full-lattice (np = N^3, FP32) variant, one workgroup per Lagrangian tile of
+// AX x AY x AZ particles.  The force-field term is computed with the three force
+// meshes staged in LDS over the tile's CIC bounding box (as in the forward gather);
+// then, with the positions still in registers, v = kick * lam_mom (the updated lam_mom)
+// is deposited like the counting density: the same box becomes an LDS window of the
+// three components in 32-bit fixed point with a per-tile, per-component scale
+// 2^(20 - e_d) (e_d the exponent of the tile's largest |v_d|): every term is rounded to
+// the nearest multiple of 2^(e_d - 20) (a relative 1e-6 of the tile's largest |v_d|)
+// and no window cell can overflow, since the tile's 1024 particles add at most 2^30 in
+// magnitude.  Then one global atomic per non-empty cell and component; particles
+// outside the window (a box past ACAP cells, shrunk by fit_box) read the force meshes
+// and deposit with global atomics directly.  g must not overlap force.
 constexpr int AX = 4, AY = 8, AZ = 32;
 constexpr int APP = AX * AY * AZ / kBlock;
 constexpr int ACAP = 4096;
@@ -81,16 +86,18 @@ constexpr int ACAP = 4096;
 template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __restrict__ force, const float* __restrict__ pos,
                                                              int n, float kick, float drift, float* __restrict__ lam_pos,
-                                                             float* __restrict__ lam_mom) {
+                                                             float* __restrict__ lam_mom, float* __restrict__ g) {
+  static_assert(AX * AY * AZ <= 1024, "the fixed-point headroom assumes at most 2^10 particles per tile");
   __shared__ float win[3 * ACAP];
   __shared__ int wlo[4][3], whi[4][3];
   __shared__ float wsum[4][3];
+  __shared__ float wmax[4][3];
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
   const int tpy = n / AY, tpz = n / AZ;
   int ti, tk, tl;
   tile_coords(xcd_block(blockIdx.x, gridDim.x), n / AX, tpy, tpz, ti, tk, tl);
   const int org[3] = {ti * AX, tk * AY, tl * AZ};
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   float x[APP], y[APP], z[APP];
   int64_t jj[APP];
 #pragma unroll
@@ -132,15 +139,18 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     }
   }
   __syncthreads();
+  float v[3][APP];
+  float vmax[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int p = 0; p < APP; ++p) {
     const int64_t j = jj[p];
-    float lx[3], lp[3], v[3];
+    float lx[3], lp[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       lx[d] = lam_pos[d * np + j];
       lp[d] = lam_mom[d * np + j] + drift * lx[d];
-      v[d] = kick * lp[d];
+      v[d][p] = kick * lp[d];
+      vmax[d] = fmaxf(vmax[d], fabsf(v[d][p]));
     }
     const Axis<float> ax = cic_axis_n<P2>(x[p], n), ay = cic_axis_n<P2>(y[p], n), az = cic_axis_n<P2>(z[p], n);
     const int rx = idiff_n<P2>(ax.i0, org[0], n) - tw.o[0], ry = idiff_n<P2>(ay.i0, org[1], n) - tw.o[1],
@@ -153,10 +163,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
       float s;
       if (inside) {
         const int w = (rx + bx) * sx + (ry + by) * sy + rz + bz;
-        s = v[0] * win[w] + v[1] * win[ACAP + w] + v[2] * win[2 * ACAP + w];
+        s = v[0][p] * win[w] + v[1][p] * win[ACAP + w] + v[2][p] * win[2 * ACAP + w];
       } else {
         const int64_t idx = (bx ? ax.i1 : ax.i0) * n2 + (int64_t)(by ? ay.i1 : ay.i0) * n + (bz ? az.i1 : az.i0);
-        s = v[0] * force[idx] + v[1] * force[np + idx] + v[2] * force[2 * np + idx];
+        s = v[0][p] * force[idx] + v[1][p] * force[np + idx] + v[2][p] * force[2 * np + idx];
       }
       const float wx = bx ? ax.w1 : ax.w0, wy = by ? ay.w1 : ay.w0, wz = bz ? az.w1 : az.w0;
       gx += (bx ? s : -s) * wy * wz;
@@ -170,50 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     lam_pos[np + j] = lx[1] + gy;
     lam_pos[2 * np + j] = lx[2] + gz;
   }
-}
-
-constexpr int VX = 8, VY = 8, VZ = 16;
-constexpr int VPP = VX * VY * VZ / kBlock;
-constexpr int VCAP = 4096;
-// g[d] += sum_p W(x_p - c) v_{p,d}, v = kick * lam_mom, one tile per block.  The three
-// components are accumulated together in LDS windows of 32-bit fixed point with a
-// per-tile, per-component scale 2^(20 - e_d) (e_d the exponent of the tile's largest
-// |v_d|): every term is rounded to the nearest multiple of 2^(e_d - 20) (a relative
-// 1e-6 of the tile's largest |v_d|) and no window cell can overflow, since the tile's
-// 1024 particles add at most 2^30 in magnitude.  Then one global atomic per
-// non-empty cell and component; particles outside their tile's window go to global
-// atomics directly.
-template <bool P2>
-__global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict__ pos, const float* __restrict__ lam_mom,
-                                                        float kick, int n, float* __restrict__ g) {
-  static_assert(VX * VY * VZ <= 1024, "the fixed-point headroom assumes at most 2^10 particles per tile");
-  __shared__ unsigned win[3 * VCAP];
-  __shared__ int wlo[4][3], whi[4][3];
-  __shared__ float wsum[4][3];
-  __shared__ float wmax[4][3];
-  const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
-  const int tpy = n / VY, tpz = n / VZ;
-  int ti, tk, tl;
-  tile_coords(xcd_block(blockIdx.x, gridDim.x), n / VX, tpy, tpz, ti, tk, tl);
-  const int org[3] = {ti * VX, tk * VY, tl * VZ};
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  float x[VPP], y[VPP], z[VPP], v[3][VPP];
-  float vmax[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-  for (int p = 0; p < VPP; ++p) {
-    const int loc = t + kBlock * p;
-    const int li = loc / (VY * VZ), lk = (loc / VZ) % VY, ll = loc % VZ;
-    const int64_t j = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
-    x[p] = wrap_n<P2>(pos[j], n);
-    y[p] = wrap_n<P2>(pos[np + j], n);
-    z[p] = wrap_n<P2>(pos[2 * np + j], n);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      v[d][p] = kick * lam_mom[d * np + j];
-      vmax[d] = fmaxf(vmax[d], fabsf(v[d][p]));
-    }
-  }
-  const TileWindow tw = tile_window<VPP, P2>(x, y, z, n, org, VCAP, VX * VY * VZ, wlo, whi, wsum);
+  // deposit of v over the same box: the force window's LDS becomes the fixed-point window
 #pragma unroll
   for (int d = 0; d < 3; ++d)
     for (int off = 32; off > 0; off >>= 1) vmax[d] = fmaxf(vmax[d], __shfl_xor(vmax[d], off, 64));
@@ -221,12 +188,11 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
 #pragma unroll
     for (int d = 0; d < 3; ++d) wmax[wave][d] = vmax[d];
   }
-  const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
-  const int wtot = W0 * W1 * W2;
-  const int sy = W2, sx = W1 * W2;
+  __syncthreads();  // every thread is done with the force window
+  unsigned* dwin = reinterpret_cast<unsigned*>(win);
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    for (int c = t; c < wtot; c += kBlock) win[d * VCAP + c] = 0u;
+    for (int c = t; c < wtot; c += kBlock) dwin[d * ACAP + c] = 0u;
   __syncthreads();
   float scale[3], inv[3];
 #pragma unroll
@@ -238,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
     inv[d] = m > 0.f ? ldexpf(1.f, e - 20) : 0.f;
   }
 #pragma unroll
-  for (int p = 0; p < VPP; ++p) {
+  for (int p = 0; p < APP; ++p) {
     const Axis<float> ax = cic_axis_n<P2>(x[p], n), ay = cic_axis_n<P2>(y[p], n), az = cic_axis_n<P2>(z[p], n);
     const int rx = idiff_n<P2>(ax.i0, org[0], n) - tw.o[0], ry = idiff_n<P2>(ay.i0, org[1], n) - tw.o[1],
               rz = idiff_n<P2>(az.i0, org[2], n) - tw.o[2];
@@ -250,7 +216,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const float vs = v[d][p] * scale[d];  // |vs| < 2^20, exact power-of-two scaling
-        unsigned* wd = win + d * VCAP + base;
+        unsigned* wd = dwin + d * ACAP + base;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           atomicAdd(wd + off[q], (unsigned)(int)rintf(wxy[q] * az.w0 * vs));
@@ -269,9 +235,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_vec(const float* __restrict_
     }
   }
   __syncthreads();
-  const WinDiv qsx(sx), qsy(sy);
   for (int c = t; c < wtot; c += kBlock) {
-    const int q0 = (int)win[c], q1 = (int)win[VCAP + c], q2 = (int)win[2 * VCAP + c];
+    const int q0 = (int)dwin[c], q1 = (int)dwin[ACAP + c], q2 = (int)dwin[2 * ACAP + c];
     if ((q0 | q1 | q2) == 0) continue;
     int a, b, cz;
     win_cell(c, qsx, qsy, a, b, cz);
@@ -399,20 +364,13 @@ int launch_adj_gather_kdk(const pm_plan* p, const void* force, const void* pos, 
   if (np <= 0) return PM_OK;
   const int n = p->n;
   if (p->dtype == PM_F32 && (int64_t)n * n * n == np && n >= 64 && n <= 1024 && n % AZ == 0) {
-    {
-      ProfScope ps(p, PK_ADJ_GATHER, s);
-      const unsigned tiles = (unsigned)((n / AX) * (n / AY) * (n / AZ));
-      // a power-of-two N wraps without a division (same results)
-      auto kern = (n & (n - 1)) == 0 ? k_adj_gather_tiled<true> : k_adj_gather_tiled<false>;
-      hipLaunchKernelGGL(kern, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(force),
-                         static_cast<const float*>(pos), n, (float)kick, (float)drift, static_cast<float*>(lam_pos),
-                         static_cast<float*>(lam_mom));
-    }
-    ProfScope ps(p, PK_ADJ_DEPOSIT, s);
-    const unsigned tiles = (unsigned)((n / VX) * (n / VY) * (n / VZ));
-    auto kern = (n & (n - 1)) == 0 ? k_deposit_vec<true> : k_deposit_vec<false>;
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(pos),
-                       static_cast<const float*>(lam_mom), (float)kick, n, static_cast<float*>(g));
+    ProfScope ps(p, PK_ADJ_GATHER, s);
+    const unsigned tiles = (unsigned)((n / AX) * (n / AY) * (n / AZ));
+    // a power-of-two N wraps without a division (same results)
+    auto kern = (n & (n - 1)) == 0 ? k_adj_gather_tiled<true> : k_adj_gather_tiled<false>;
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(kBlock), 0, s, static_cast<const float*>(force),
+                       static_cast<const float*>(pos), n, (float)kick, (float)drift, static_cast<float*>(lam_pos),
+                       static_cast<float*>(lam_mom), static_cast<float*>(g));
     return hip_check(hipGetLastError(), "adjoint gather-kick-drift");
   }
   ProfScope ps(p, PK_ADJ_GATHER, s);
