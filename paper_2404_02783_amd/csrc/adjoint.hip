@@ -82,6 +82,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_kdk(const T* __restrict__
 constexpr int AX = 4, AY = 8, AZ = 32;
 constexpr int APP = AX * AY * AZ / kBlock;
 constexpr int ACAP = 4096;
+// a box of more than ASPARSE cells (the undisplaced tile's is 1485) stages only the
+// cells its particles touch, marked in a byte map, as the forward gather does
+constexpr int ASPARSE = 2048;
+static_assert(ACAP == 16 * kBlock, "the byte map is cleared with one 16-byte store per thread");
 
 template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __restrict__ force, const float* __restrict__ pos,
@@ -89,6 +93,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
                                                              float* __restrict__ lam_mom, float* __restrict__ g) {
   static_assert(AX * AY * AZ <= 1024, "the fixed-point headroom assumes at most 2^10 particles per tile");
   __shared__ float win[3 * ACAP];
+  __shared__ __attribute__((aligned(16))) unsigned char mark[ACAP];
   __shared__ int wlo[4][3], whi[4][3];
   __shared__ float wsum[4][3];
   __shared__ float wmax[4][3];
@@ -109,17 +114,40 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     y[p] = wrap_n<P2>(pos[np + jj[p]], n);
     z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
   }
+  reinterpret_cast<uint4*>(mark)[t] = make_uint4(0u, 0u, 0u, 0u);  // before tile_window's barriers
   const TileWindow tw = tile_window<APP, P2>(x, y, z, n, org, ACAP, AX * AY * AZ, wlo, whi, wsum);
   const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];
   const int sy = W2, sx = W1 * W2;
   const int wtot = W0 * W1 * W2;
+  const bool sparse = wtot > ASPARSE;  // the same in every thread
+  if (sparse) {
+#pragma unroll
+    for (int p = 0; p < APP; ++p) {
+      const int rx = idiff_n<P2>((int)floorf(x[p]), org[0], n) - tw.o[0];
+      const int ry = idiff_n<P2>((int)floorf(y[p]), org[1], n) - tw.o[1];
+      const int rz = idiff_n<P2>((int)floorf(z[p]), org[2], n) - tw.o[2];
+      if (rx >= 0 && rx <= W0 - 2 && ry >= 0 && ry <= W1 - 2 && rz >= 0 && rz <= W2 - 2) {
+        unsigned char* m = mark + rx * sx + ry * sy + rz;
+        m[0] = 1;
+        m[1] = 1;
+        m[sy] = 1;
+        m[sy + 1] = 1;
+        m[sx] = 1;
+        m[sx + 1] = 1;
+        m[sx + sy] = 1;
+        m[sx + sy + 1] = 1;
+      }
+    }
+    __syncthreads();
+  }
   // stage the window: all of a thread's loads in flight before its first LDS store
-  float fa[ACAP / kBlock], fb[ACAP / kBlock], fc[ACAP / kBlock];
+  // (cells a sparse box skips are stored as zeros; no particle reads them)
+  float fa[ACAP / kBlock] = {}, fb[ACAP / kBlock] = {}, fc[ACAP / kBlock] = {};
   const WinDiv qsx(sx), qsy(sy);
 #pragma unroll
   for (int k = 0; k < ACAP / kBlock; ++k) {
     const int c = t + kBlock * k;
-    if (c < wtot) {
+    if (c < wtot && (!sparse || mark[c])) {
       int a, b, cz;
       win_cell(c, qsx, qsy, a, b, cz);
       const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + tw.o[0] + a, n), fold_n<P2>(org[1] + tw.o[1] + b, n),

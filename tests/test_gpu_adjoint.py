@@ -48,10 +48,11 @@ def test_step_adjoint_matches_oracle_vjp(dt, n, amp, cached_force):
     _step_adjoint_case(dt, n, amp, cached_force)
 
 
-@pytest.mark.parametrize("amp", [0.8, 6.0, 20.0])
+@pytest.mark.parametrize("amp", [0.4, 0.8, 6.0, 20.0])
 def test_step_adjoint_lattice_tiles(amp):
-    """A full 128^3 FP32 lattice takes the tiled adjoint gather and the tiled
-    fixed-point deposit of v; amplitudes 6 and 20 overflow the LDS windows, so the
+    """A full 128^3 FP32 lattice takes the tiled adjoint gather with its fixed-point
+    deposit of v: at amplitude 0.4 every box is staged whole, at 0.8 sparsely (only the
+    cells the particles touch); amplitudes 6 and 20 overflow the LDS windows, so the
     fallback boxes and the direct global paths run too."""
     _step_adjoint_case(torch.float32, 128, amp, True)
 

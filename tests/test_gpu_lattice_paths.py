@@ -181,7 +181,7 @@ def test_density_handed_over_cycles_fit_box_128():
     _handed_over_cycles(128, 6.0, 96, 1000.0)
 
 
-@pytest.mark.parametrize("amp", [0.8, 6.0])
+@pytest.mark.parametrize("amp", [0.4, 0.8, 6.0])
 def test_step_adjoint_192(amp):
     """Tiled adjoint gather and fixed-point vector deposit at N = 192 against the
     oracle's vector-Jacobian product of the cycle."""
