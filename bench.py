@@ -623,13 +623,10 @@ def main():
     total = max(50, args.warmup + args.steps)
     a_s = pm.sim.log_steps(0.02, 1.0, total)
     run = pm.sim.Run(plan, pos, mom)
-    k2_prev = 0.0
+    kicks, drifts = pm.leapfrog_factors(a_s)
 
     def cycle(j):
-        nonlocal k2_prev
-        k1, dr, k2 = pm.kdk_factors(a_s[j], a_s[j + 1])
-        run.cycle(a_s[j], k2_prev + k1, dr)
-        k2_prev = k2
+        run.cycle(a_s[j], kicks[j], drifts[j])
 
     # every cycle of the schedule is profiled (HIP events around each launch on the
     # library's stream); windows: warm-up, timed, the rest, and the late-time sample

@@ -488,6 +488,19 @@ double pm_cosmo_drift(const pm_cosmology* c, double a0, double a1);
 /* Leapfrog factors of one step a0 -> a1 with half step sqrt(a0 a1): out[0] = K(a0, ah),
  * out[1] = Dr(a0, a1), out[2] = K(ah, a1). */
 void pm_kdk_factors(const pm_cosmology* c, double a0, double a1, double out[3]);
+/* Scale factors of a run of n_steps steps equally spaced in ln a (the step-spacing
+ * reading of the PM runs of Sec. 2 and 4): a[j] = exp(ln a_start + (ln a_end -
+ * ln a_start) j / n_steps), j = 0..n_steps, into host array a[n_steps + 1].  Returns
+ * PM_OK, or PM_ERR_ARG for null a, n_steps < 1 or a_start, a_end not positive. */
+int pm_log_steps(double a_start, double a_end, int n_steps, double* a);
+/* The kick-drift-kick leapfrog over a[0..n_steps] (host, increasing) as the chain of
+ * pm_step cycles: cycle j < n_steps kicks by kick[j] = K(a_{j-1/2}, a_j) + K(a_j,
+ * a_{j+1/2}) (the first term 0 for j = 0) and drifts by drift[j] = Dr(a_j, a_{j+1});
+ * the closing cycle j = n_steps kicks by K(a_{n-1/2}, a_n) and has drift[n_steps] = 0
+ * (a_{j+1/2} = sqrt(a_j a_{j+1}), factors of pm_kdk_factors).  kick and drift: host
+ * arrays of n_steps + 1.  Returns PM_OK, or PM_ERR_ARG for null arrays, n_steps < 1
+ * or a not positive and increasing. */
+int pm_leapfrog_factors(const pm_cosmology* c, const double* a, int n_steps, double* kick, double* drift);
 /* Solve parameters of a Poisson-gauge evaluation at a (box side box_mpch, mesh n);
  * a_prev <= 0 marks the first (quasi-static) evaluation. */
 void pm_gauge_params(const pm_cosmology* c, double box_mpch, int n_mesh, double a, double a_prev,

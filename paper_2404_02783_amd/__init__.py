@@ -25,7 +25,7 @@ __all__ = [
     "pm_plan_tuning_candidates", "pm_plan_get_tuning", "pm_plan_set_tuning", "pm_plan_autotune", "TUNING_SLOTS",
     "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
-    "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH",
+    "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH", "log_steps", "leapfrog_factors",
     "PM_F32", "PM_F64", "PM_NEWTON", "PM_POISSON_GAUGE", "PM_GRAD_SPECTRAL", "PM_GRAD_FD2", "PM_GRAD_FD1",
     "PM_PK_POWERLAW", "PM_PK_EH98", "PM_STEP_DEPOSIT_NEXT", "PM_STEP_DENSITY_READY",
 ]
@@ -141,6 +141,8 @@ def _declare(l):
         "pm_cosmo_kick": (_c_double, [P(Cosmology), _c_double, _c_double]),
         "pm_cosmo_drift": (_c_double, [P(Cosmology), _c_double, _c_double]),
         "pm_kdk_factors": (None, [P(Cosmology), _c_double, _c_double, P(_c_double)]),
+        "pm_log_steps": (_c_int, [_c_double, _c_double, _c_int, P(_c_double)]),
+        "pm_leapfrog_factors": (_c_int, [P(Cosmology), P(_c_double), _c_int, P(_c_double), P(_c_double)]),
         "pm_gauge_params": (None, [P(Cosmology), _c_double, _c_int, _c_double, _c_double, P(SolveParams)]),
         "pm_power_eh98_amplitude": (_c_double, [P(Cosmology), _c_double, _c_double]),
         "pm_power_law_amplitude": (_c_double, [_c_int, _c_double, _c_double, _c_double]),
@@ -695,6 +697,25 @@ def kdk_factors(a0, a1, c=FIDUCIAL):
     out = (ctypes.c_double * 3)()
     lib().pm_kdk_factors(ctypes.byref(c), a0, a1, out)
     return out[0], out[1], out[2]
+
+
+def log_steps(a_start: float, a_end: float, n_steps: int):
+    """n_steps + 1 scale factors equally spaced in ln a (pm_log_steps)."""
+    out = (ctypes.c_double * (int(n_steps) + 1))()
+    _check(lib().pm_log_steps(float(a_start), float(a_end), int(n_steps), out))
+    return list(out)
+
+
+def leapfrog_factors(a_steps, c=FIDUCIAL):
+    """(kick, drift) of the chain of pm_step cycles that runs the kick-drift-kick
+    leapfrog over a_steps: cycle j < n kicks by K2(step j-1) + K1(step j) and drifts by
+    Dr(step j); the closing cycle n kicks by K2(step n-1) with drift 0
+    (pm_leapfrog_factors)."""
+    n = len(a_steps) - 1
+    a = (ctypes.c_double * (n + 1))(*[float(x) for x in a_steps])
+    kick, drift = (ctypes.c_double * (n + 1))(), (ctypes.c_double * (n + 1))()
+    _check(lib().pm_leapfrog_factors(ctypes.byref(c), a, n, kick, drift))
+    return list(kick), list(drift)
 
 
 def gauge_params(box, n, a, a_prev=0.0, c=FIDUCIAL) -> SolveParams:

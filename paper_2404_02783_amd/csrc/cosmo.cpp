@@ -139,6 +139,33 @@ void pm_kdk_factors(const pm_cosmology* c, double a0, double a1, double out[3]) 
   out[2] = pm_cosmo_kick(c, ah, a1);
 }
 
+int pm_log_steps(double a_start, double a_end, int n_steps, double* a) {
+  if (!a || n_steps < 1 || !(a_start > 0.0) || !(a_end > 0.0))
+    return pm::set_error(PM_ERR_ARG, "pm_log_steps: need a, n_steps >= 1 and positive a_start, a_end");
+  const double la = std::log(a_start), lb = std::log(a_end);
+  for (int j = 0; j <= n_steps; ++j) a[j] = std::exp(la + (lb - la) * j / n_steps);
+  return PM_OK;
+}
+
+int pm_leapfrog_factors(const pm_cosmology* c, const double* a, int n_steps, double* kick, double* drift) {
+  if (!c || !a || !kick || !drift || n_steps < 1)
+    return pm::set_error(PM_ERR_ARG, "pm_leapfrog_factors: null argument or n_steps < 1");
+  for (int j = 0; j <= n_steps; ++j)
+    if (!(a[j] > 0.0) || (j > 0 && !(a[j] > a[j - 1])))
+      return pm::set_error(PM_ERR_ARG, "pm_leapfrog_factors: a must be positive and increasing");
+  double k2_prev = 0.0;  // second half kick of the previous step
+  for (int j = 0; j < n_steps; ++j) {
+    double f[3];
+    pm_kdk_factors(c, a[j], a[j + 1], f);
+    kick[j] = k2_prev + f[0];
+    drift[j] = f[1];
+    k2_prev = f[2];
+  }
+  kick[n_steps] = k2_prev;
+  drift[n_steps] = 0.0;
+  return PM_OK;
+}
+
 void pm_gauge_params(const pm_cosmology* c, double box_mpch, int n_mesh, double a, double a_prev,
                      pm_solve_params* out) {
   const double dx = box_mpch / n_mesh;

@@ -21,7 +21,7 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (FIDUCIAL, ICParams, PM_GRAD_SPECTRAL, Plan, StepParams, kdk_factors, newton_params, pk_adjoint,
+from . import (FIDUCIAL, ICParams, PM_GRAD_SPECTRAL, Plan, StepParams, leapfrog_factors, newton_params, pk_adjoint,
                pk_estimate, pm_deposit, pm_ic_2lpt, pm_ic_2lpt_adjoint, pm_ic_zeldovich, pm_ic_zeldovich_adjoint,
                pm_step, pm_step_adjoint)
 
@@ -39,13 +39,9 @@ class Schedule:
     lpt_order: int = 1   # 1: Zel'dovich ICs, 2: second-order (2LPT) ICs
 
     def cycles(self):
-        out = []
-        k2_prev = 0.0
-        for j in range(len(self.a_steps) - 1):
-            k1, dr, k2 = kdk_factors(self.a_steps[j], self.a_steps[j + 1], self.cosmo)
-            out.append(StepParams(kick=k2_prev + k1, drift=dr, solve=newton_params(self.cosmo, self.grad)))
-            k2_prev = k2
-        return out
+        kick, drift = leapfrog_factors(self.a_steps, self.cosmo)
+        return [StepParams(kick=kick[j], drift=drift[j], solve=newton_params(self.cosmo, self.grad))
+                for j in range(len(self.a_steps) - 1)]
 
 
 @dataclass

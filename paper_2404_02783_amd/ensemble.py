@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 import torch
 
 from . import (FIDUCIAL, Batch, ICParams, PM_PK_EH98, PM_STEP_DENSITY_READY, PM_STEP_DEPOSIT_NEXT, Plan,
-               StepParams, kdk_factors, newton_params, pk_estimate, pm_batch_ic_zeldovich, pm_batch_pk_estimate,
+               StepParams, leapfrog_factors, newton_params, pk_estimate, pm_batch_ic_zeldovich, pm_batch_pk_estimate,
                pm_batch_step, pm_deposit, pm_ic_zeldovich, pm_noise_fix, pm_step, power_eh98_amplitude)
 from .sim import log_steps
 from .tuning import tune
@@ -66,12 +66,8 @@ def schedule(a_start=0.02, a_end=1.0, n_steps=30, n_s=0.965, sigma8=0.81, cosmo=
     a_steps = log_steps(a_start, a_end, n_steps)
     ic = ICParams(pk_kind=PM_PK_EH98, amp=power_eh98_amplitude(n_s, sigma8, cosmo), index=n_s, a_init=a_start,
                   a_norm=1.0, cosmo=cosmo)
-    cycles = []
-    k2_prev = 0.0
-    for j in range(n_steps):
-        k1, dr, k2 = kdk_factors(a_steps[j], a_steps[j + 1], cosmo)
-        cycles.append(StepParams(kick=k2_prev + k1, drift=dr, solve=newton_params(cosmo)))
-        k2_prev = k2
+    kick, drift = leapfrog_factors(a_steps, cosmo)
+    cycles = [StepParams(kick=kick[j], drift=drift[j], solve=newton_params(cosmo)) for j in range(n_steps)]
     return a_steps, ic, cycles
 
 

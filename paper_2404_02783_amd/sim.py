@@ -9,17 +9,16 @@ evaluation is quasi-static.
 """
 from __future__ import annotations
 
-import math
-
 from . import (FIDUCIAL, PM_GRAD_SPECTRAL, PM_STEP_DENSITY_READY, PM_STEP_DEPOSIT_NEXT, Plan, StepParams,
-               gauge_params, kdk_factors, newton_params, pm_step)
+               gauge_params, leapfrog_factors, newton_params, pm_step)
+from . import log_steps as _log_steps
 
 __all__ = ["log_steps", "Run"]
 
 
 def log_steps(a_start: float, a_end: float, n_steps: int):
-    la, lb = math.log(a_start), math.log(a_end)
-    return [math.exp(la + (lb - la) * j / n_steps) for j in range(n_steps + 1)]
+    """n_steps + 1 scale factors equally spaced in ln a (pm_log_steps)."""
+    return _log_steps(a_start, a_end, n_steps)
 
 
 class Run:
@@ -57,14 +56,13 @@ class Run:
 
     def leapfrog(self, a_steps, close: bool = True, on_cycle=None):
         """Run the whole schedule; ``on_cycle(j)`` is called after each cycle."""
-        k2_prev = 0.0
-        for j in range(len(a_steps) - 1):
-            k1, dr, k2 = kdk_factors(a_steps[j], a_steps[j + 1], self.cosmo)
-            self.cycle(a_steps[j], k2_prev + k1, dr)
-            k2_prev = k2
+        kick, drift = leapfrog_factors(a_steps, self.cosmo)
+        n = len(a_steps) - 1
+        for j in range(n):
+            self.cycle(a_steps[j], kick[j], drift[j])
             if on_cycle is not None:
                 on_cycle(j)
         if close:
-            self.cycle(a_steps[-1], k2_prev, 0.0, last=True)
+            self.cycle(a_steps[-1], kick[n], 0.0, last=True)
         else:
             self.invalidate()

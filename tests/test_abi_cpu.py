@@ -57,6 +57,37 @@ def test_host_kick_drift_match_oracle(a0, a1):
     assert (k1, dr, k2) == pytest.approx((o1, odr, o2), rel=1e-12)
 
 
+def test_host_log_steps_match_oracle():
+    got = pm.log_steps(0.02, 1.0, 50)
+    want = ocm.log_steps(0.02, 1.0, 50)
+    assert len(got) == 51
+    assert got == pytest.approx(want, rel=1e-15)
+    assert got[0] == pytest.approx(0.02, rel=1e-15) and got[-1] == pytest.approx(1.0, rel=1e-15)
+
+
+def test_host_leapfrog_chain_matches_oracle_steps():
+    """The cycle chain equals the oracle's kick-drift-kick step by step: kick_j =
+    K(a_{j-1/2}, a_j) + K(a_j, a_{j+1/2}), drift_j = Dr(a_j, a_{j+1}), closing kick
+    K(a_{n-1/2}, a_n) with no drift; the kicks add up to K(a_0, a_n)."""
+    a = ocm.log_steps(0.05, 1.0, 20)
+    kick, drift = pm.leapfrog_factors(a)
+    n = len(a) - 1
+    assert len(kick) == len(drift) == n + 1
+    for j in range(n + 1):
+        k_in = ocm.kick_factor(C, math.sqrt(a[j - 1] * a[j]), a[j]) if j > 0 else 0.0
+        k_out = ocm.kick_factor(C, a[j], math.sqrt(a[j] * a[j + 1])) if j < n else 0.0
+        assert kick[j] == pytest.approx(k_in + k_out, rel=1e-12), j
+        assert drift[j] == (pytest.approx(ocm.drift_factor(C, a[j], a[j + 1]), rel=1e-12) if j < n else 0.0), j
+    assert sum(kick) == pytest.approx(ocm.kick_factor(C, a[0], a[-1]), rel=1e-12)
+    assert sum(drift) == pytest.approx(ocm.drift_factor(C, a[0], a[-1]), rel=1e-12)
+
+
+@pytest.mark.parametrize("bad", [[0.1], [0.2, 0.1], [0.0, 0.5], [0.1, 0.1]])
+def test_host_leapfrog_factors_reject_bad_schedules(bad):
+    with pytest.raises(pm.PMError):
+        pm.leapfrog_factors(bad)
+
+
 def test_host_gauge_params_match_oracle():
     box, n, a, ap = 4000.0, 256, 0.3, 0.28
     sp = pm.gauge_params(box, n, a, ap)
