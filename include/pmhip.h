@@ -133,10 +133,11 @@ typedef struct {
 size_t pm_plan_workspace_bytes(int n_mesh, int dtype);
 
 /* Create a plan for an N^3 mesh of a periodic box of side box_mpch (Mpc/h).
- * workspace: caller device buffer of ws_bytes >= pm_plan_workspace_bytes(), or NULL
- * to let the plan allocate (and free) its own.  The plan also allocates a few KB of
- * twiddle tables and counters.  Errors: PM_ERR_SIZE for an unsupported N,
- * PM_ERR_NOMEM if ws_bytes is too small, PM_ERR_HIP if an allocation fails. */
+ * workspace: caller device buffer of ws_bytes >= pm_plan_workspace_bytes(), aligned
+ * to 256 bytes (as hipMalloc returns), or NULL to let the plan allocate (and free) its
+ * own.  The plan also allocates a few KB of twiddle tables and counters.  Errors:
+ * PM_ERR_SIZE for an unsupported N, PM_ERR_NOMEM if ws_bytes is too small,
+ * PM_ERR_ARG for a misaligned workspace, PM_ERR_HIP if an allocation fails. */
 int pm_plan_create(pm_plan** out, int n_mesh, double box_mpch, int dtype, void* workspace, size_t ws_bytes);
 int pm_plan_destroy(pm_plan* plan);
 

@@ -191,6 +191,8 @@ int pm_plan_create_batch(pm_plan** out, int n_mesh, double box_mpch, int dtype, 
   const size_t need = pm_plan_workspace_bytes_batch(n_mesh, dtype, n_batch);
   if (workspace && ws_bytes < need)
     return set_error(PM_ERR_NOMEM, "pm_plan_create: workspace of %zu bytes < %zu needed", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return set_error(PM_ERR_ARG, "pm_plan_create: workspace not aligned to 256 bytes");
   pm_plan* p = new (std::nothrow) pm_plan();
   if (!p) return set_error(PM_ERR_NOMEM, "pm_plan_create: host allocation failed");
   p->n = n_mesh;

@@ -57,6 +57,16 @@ def test_host_kick_drift_match_oracle(a0, a1):
     assert (k1, dr, k2) == pytest.approx((o1, odr, o2), rel=1e-12)
 
 
+def test_plan_rejects_misaligned_workspace():
+    """A caller workspace must be 256-byte aligned; the check precedes any device work."""
+    import ctypes
+    h = ctypes.c_void_p()
+    need = pm.lib().pm_plan_workspace_bytes(64, 0)
+    rc = pm.lib().pm_plan_create(ctypes.byref(h), 64, 100.0, 0, ctypes.c_void_p(0x10000010), need)
+    assert rc == -1 and not h.value
+    assert b"aligned" in pm.lib().pm_last_error()
+
+
 def test_host_log_steps_match_oracle():
     got = pm.log_steps(0.02, 1.0, 50)
     want = ocm.log_steps(0.02, 1.0, 50)
