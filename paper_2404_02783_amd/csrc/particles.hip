@@ -16,10 +16,27 @@ constexpr int kBlock = 256;
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// 16-byte stores over the 16-byte aligned body of p[0, count), element stores for the
+// head and the tail.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, int64_t count, T v) {
+  constexpr int V = 16 / (int)sizeof(T);
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+  const int64_t to_align = (int64_t)((16u - (unsigned)(reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) / (int64_t)sizeof(T);
+  const int64_t head = to_align < count ? to_align : count;
+  const int64_t nvec = (count - head) / V;
+  for (int64_t i = tid; i < head; i += stride) p[i] = v;
+  if constexpr (V == 4) {
+    float4* q = reinterpret_cast<float4*>(p + head);
+    const float4 w = make_float4(v, v, v, v);
+    for (int64_t i = tid; i < nvec; i += stride) q[i] = w;
+  } else {
+    double2* q = reinterpret_cast<double2*>(p + head);
+    const double2 w = make_double2(v, v);
+    for (int64_t i = tid; i < nvec; i += stride) q[i] = w;
+  }
+  for (int64_t i = head + nvec * V + tid; i < count; i += stride) p[i] = v;
 }
 
 // sum over the 8 CIC corners of the three force components
@@ -487,7 +504,9 @@ __global__ void __launch_bounds__(kBlock) k_ic_gauge_lattice(const T* __restrict
 int launch_fill(const pm_plan* p, void* mesh, int64_t count, double value, hipStream_t s) {
   ProfScope ps(p, PK_FILL, s);
   if (count <= 0) return PM_OK;
-  const unsigned g = (unsigned)std::min<int64_t>((count + kBlock - 1) / kBlock, 65536);
+  // one 16-byte store per thread and pass (4 floats or 2 doubles)
+  const int64_t vec = p->dtype == PM_F32 ? 4 : 2;
+  const unsigned g = (unsigned)std::min<int64_t>((count + vec * kBlock - 1) / (vec * kBlock), 65536);
   if (p->dtype == PM_F32)
     hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(kBlock), 0, s, static_cast<float*>(mesh), count, (float)value);
   else
