@@ -69,26 +69,50 @@ def kernel_source_digest(kernel: str = "gather_kick_drift") -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, n: int):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter's reading for
-    a plain device copy), or None when there is none for this kernel and mesh or the
-    kernel sources changed since the counters were taken."""
+def profile_values(kernel: str, n: int):
+    """The `- key: value` lines of the committed counter summary of ``kernel`` at mesh
+    n, or {} when there is none or the kernel's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_{n}.md")
     if kernel not in KERNEL_SOURCES or not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     with open(path) as f:
         for line in f:
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_sha256") != kernel_source_digest(kernel):
-        return None
+    return vals if vals.get("source_sha256") == kernel_source_digest(kernel) else {}
+
+
+def measured_traffic(kernel: str, n: int):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter's reading for
+    a plain device copy), or None when there is none for this kernel and mesh or the
+    kernel sources changed since the counters were taken."""
+    vals = profile_values(kernel, n)
     try:
         return int(float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"]))
     except (KeyError, ValueError):
         return None
+
+
+def l2_atomic_rate(pm, n: int = 1 << 28, passes: int = 4, reps: int = 3) -> float:
+    """Unreturned float atomics per second (G/s) of pm_microbench_atomics on n distinct
+    consecutive cells (the deposits' flush pattern), best of reps launches."""
+    import torch
+    buf = torch.zeros(n, dtype=torch.float32, device="cuda")
+    pm.pm_microbench_atomics(buf, passes=1)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(reps):
+        e0.record()
+        pm.pm_microbench_atomics(buf, passes=passes)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del buf
+    return n * passes / (best / 1000.0) / 1e9
 
 
 def cpu_baseline(n_sample: int, seed: int = 5, min_seconds: float = 10.0, max_cycles: int = 4):
@@ -717,6 +741,22 @@ def main():
                        "best_ms": [round(m, 4) for m in tuned_ms]},
         "adjoint_forward_ratio": None,
     }
+    # the deposit part's global atomics against the L2 atomic rate (microbenchmark on
+    # the flush pattern); the fused kernel's atomic requests per launch and the
+    # microbenchmark's requests per atomic come from the committed counter summary
+    rate = l2_atomic_rate(pm)
+    vals = profile_values(dom, n)
+    atom = {"l2_atomic_rate_G_per_s": round(rate, 1), "kernel": dom}
+    try:
+        req = float(vals["atomic_requests_per_launch"])
+        per_atomic = float(vals["microbench_requests_per_atomic"])
+        atom["atomic_requests_per_launch"] = int(req)
+        atom["atomics_per_launch_equiv"] = int(req / per_atomic)
+        atom["atomics_G_per_s_equiv"] = round(req / per_atomic / (dom_avg / 1000.0) / 1e9, 1)
+        atom["frac_of_l2_atomic_rate"] = round(atom["atomics_G_per_s_equiv"] / rate, 3)
+    except (KeyError, ValueError, ZeroDivisionError):
+        atom["atomic_requests_per_launch"] = None
+    out["deposit_atomics"] = atom
     if not args.no_extras:
         print("[bench] estimators and combination at 1024^3", file=sys.stderr, flush=True)
         a_end = float(a_s[total])

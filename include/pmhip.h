@@ -229,6 +229,15 @@ int pm_profile_enable(pm_plan* plan, int on);
  * written, or a negative error code (PM_ERR_ARG if profiling is off). */
 int pm_profile_read(pm_plan* plan, int n_max, char* names, double* ms, int64_t* count);
 
+/* ------------------------------------------------------------ measurement --- */
+/* Not in the paper: a reference rate for the deposits' global atomics.  Adds 1.0f to
+ * each of buf[0, n) (device floats, caller-owned) `passes` times with unreturned
+ * float atomics, consecutive threads on consecutive cells -- the pattern in which the
+ * deposits flush their LDS windows -- asynchronously on `stream`; atomics per second
+ * = n * passes / the launch's duration.  Errors: PM_ERR_ARG for null buf, n <= 0 or
+ * passes <= 0. */
+int pm_microbench_atomics(void* buf, int64_t n, int passes, void* stream);
+
 /* ------------------------------------------------- FFT launch-shape tuning --- */
 /* Not in the paper (the transforms are this library's).  Four tuning slots pick the
  * launch shape of the FFT passes of a plan: 0 columns per workgroup of the plain

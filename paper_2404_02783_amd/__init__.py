@@ -26,6 +26,7 @@ __all__ = [
     "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
     "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH", "log_steps", "leapfrog_factors",
+    "pm_microbench_atomics",
     "PM_F32", "PM_F64", "PM_NEWTON", "PM_POISSON_GAUGE", "PM_GRAD_SPECTRAL", "PM_GRAD_FD2", "PM_GRAD_FD1",
     "PM_PK_POWERLAW", "PM_PK_EH98", "PM_STEP_DEPOSIT_NEXT", "PM_STEP_DENSITY_READY",
 ]
@@ -142,6 +143,7 @@ def _declare(l):
         "pm_cosmo_drift": (_c_double, [P(Cosmology), _c_double, _c_double]),
         "pm_kdk_factors": (None, [P(Cosmology), _c_double, _c_double, P(_c_double)]),
         "pm_log_steps": (_c_int, [_c_double, _c_double, _c_int, P(_c_double)]),
+        "pm_microbench_atomics": (_c_int, [_c_void_p, _c_int64, _c_int, _c_void_p]),
         "pm_leapfrog_factors": (_c_int, [P(Cosmology), P(_c_double), _c_int, P(_c_double), P(_c_double)]),
         "pm_gauge_params": (None, [P(Cosmology), _c_double, _c_int, _c_double, _c_double, P(SolveParams)]),
         "pm_power_eh98_amplitude": (_c_double, [P(Cosmology), _c_double, _c_double]),
@@ -697,6 +699,15 @@ def kdk_factors(a0, a1, c=FIDUCIAL):
     out = (ctypes.c_double * 3)()
     lib().pm_kdk_factors(ctypes.byref(c), a0, a1, out)
     return out[0], out[1], out[2]
+
+
+def pm_microbench_atomics(buf, passes: int = 1):
+    """Unreturned float atomics (+1.0 each) over every element of the float32 device
+    tensor ``buf``, ``passes`` times, on the current stream (reference rate for the
+    deposits' global atomics)."""
+    if buf.dtype != torch.float32 or not buf.is_cuda or not buf.is_contiguous():
+        raise PMError(PM_ERR_ARG, "buf must be a contiguous float32 device tensor")
+    _check(lib().pm_microbench_atomics(_c_void_p(buf.data_ptr()), buf.numel(), int(passes), _stream()))
 
 
 def log_steps(a_start: float, a_end: float, n_steps: int):

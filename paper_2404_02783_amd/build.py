@@ -24,7 +24,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 SOURCES = ["fft.hip", "deposit.hip", "particles.hip", "spectra.hip", "adjoint.hip", "api.cpp", "cosmo.cpp",
-           "batch.cpp"]
+           "batch.cpp", "microbench.hip"]
 
 
 def _compile(src: str) -> str:
