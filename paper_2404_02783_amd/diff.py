@@ -21,7 +21,8 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (FIDUCIAL, ICParams, PM_GRAD_SPECTRAL, Plan, StepParams, leapfrog_factors, newton_params, pk_adjoint,
+from . import (FIDUCIAL, ICParams, PM_GRAD_SPECTRAL, PM_STEP_DENSITY_READY, PM_STEP_DEPOSIT_NEXT, Plan, StepParams,
+               leapfrog_factors, newton_params, pk_adjoint,
                pk_estimate, pm_deposit, pm_ic_2lpt, pm_ic_2lpt_adjoint, pm_ic_zeldovich, pm_ic_zeldovich_adjoint,
                pm_step, pm_step_adjoint)
 
@@ -57,6 +58,15 @@ class ForwardTape:
     lpt_order: int = 1
 
 
+def _chained(st: StepParams, first: bool, last: bool) -> StepParams:
+    """st as one cycle of a chain of consecutive cycles on one plan: every cycle but the
+    last leaves the density of its drifted positions for the next (PM_STEP_DEPOSIT_NEXT,
+    deposited by the fused gather kernel where it applies), every cycle but the first
+    starts from it (PM_STEP_DENSITY_READY)."""
+    fl = (0 if first else PM_STEP_DENSITY_READY) | (0 if last else PM_STEP_DEPOSIT_NEXT)
+    return StepParams(kick=st.kick, drift=st.drift, solve=st.solve, flags=fl)
+
+
 def forward(plan: Plan, noise: torch.Tensor, ic: ICParams, schedule: Schedule, n_bins: int, ckpt_every: int = 5):
     """Run the forward model; returns ((k_mean, pk, n_modes), tape)."""
     if ckpt_every < 1:
@@ -75,7 +85,7 @@ def forward(plan: Plan, noise: torch.Tensor, ic: ICParams, schedule: Schedule, n
     for j, st in enumerate(steps):
         if j % ckpt_every == 0:
             ckpts[j] = (pos.clone(), mom.clone())
-        pm_step(plan, pos, mom, st, force)
+        pm_step(plan, pos, mom, _chained(st, j == 0, j == len(steps) - 1), force)
     delta = pm_deposit(plan, pos)
     k, pk, cnt = pk_estimate(plan, delta, n_bins)
     return (k, pk, cnt), ForwardTape(plan, ic, steps, n_bins, ckpt_every, ckpts, pos,
@@ -99,7 +109,7 @@ def backward(tape: ForwardTape, dpk: torch.Tensor) -> torch.Tensor:
         for j in range(s0, s1):
             xs.append(pos.clone())
             f = plan.mesh(3)
-            pm_step(plan, pos, mom, tape.steps[j], f)
+            pm_step(plan, pos, mom, _chained(tape.steps[j], j == s0, j == s1 - 1), f)
             fs.append(f)
         del pos, mom
         for j in reversed(range(s0, s1)):
@@ -148,7 +158,7 @@ class GraphedModel:
             if j in self.ckpts:
                 self.ckpts[j][0].copy_(self.pos)
                 self.ckpts[j][1].copy_(self.mom)
-            pm_step(self.plan, self.pos, self.mom, st, self.force)
+            pm_step(self.plan, self.pos, self.mom, _chained(st, j == 0, j == len(self.steps) - 1), self.force)
         pm_deposit(self.plan, self.pos, self.delta)
         self.out = pk_estimate(self.plan, self.delta, self.n_bins)
 
@@ -163,7 +173,8 @@ class GraphedModel:
             self.wmom.copy_(self.ckpts[s0][1])
             for j in range(s0, s1):
                 self.seg_x[j - s0].copy_(self.wpos)
-                pm_step(plan, self.wpos, self.wmom, self.steps[j], self.seg_f[j - s0])
+                pm_step(plan, self.wpos, self.wmom, _chained(self.steps[j], j == s0, j == s1 - 1),
+                        self.seg_f[j - s0])
             for j in reversed(range(s0, s1)):
                 pm_step_adjoint(plan, self.seg_x[j - s0], self.steps[j], self.lam_pos, self.lam_mom,
                                 force=self.seg_f[j - s0], mesh_scratch=self.scratch)
