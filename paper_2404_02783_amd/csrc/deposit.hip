@@ -5,8 +5,9 @@
 //   k_deposit        one thread per particle, 8 global float atomics each (any np);
 //   k_deposit_tiled  for a full Lagrangian lattice run (np = N^3): a workgroup owns a
 //                    Lagrangian tile, accumulates its particles in an LDS window in
-//                    32-bit fixed point at scale 2^21 (LDS integer atomics run ~20x
-//                    faster than LDS float atomics on gfx950), then adds each non-empty
+//                    32-bit fixed point at scale 2^21, terms capped at 2^21 - 1 so that
+//                    the tile's 2048 particles cannot wrap a cell (LDS integer atomics
+//                    run ~20x faster than LDS float atomics on gfx950), then adds each non-empty
 //                    window cell to the mesh with one global float atomic.  A window
 //                    that would exceed the LDS capacity shrinks to fit_box's box of
 //                    the same proportions; particles outside it use global atomics.
@@ -59,10 +60,13 @@ __global__ void __launch_bounds__(kBlock) k_deposit(const T* __restrict__ pos, i
   atomic_add(mesh + r11 + az.i1, wxy11 * az.w1);
 }
 
-// Tile of TX x TY x TZ particles (Lagrangian indices), window capacity in cells.
-constexpr int TX = 8, TY = 8, TZ = 16;
+// Tile of TX x TY x TZ particles (Lagrangian indices), window capacity in cells.  The
+// tile is long in z so that the window's rows are long: the flush's atomics on one
+// row go to the L2 in requests of up to 16 consecutive cells, so a 33-cell row costs
+// 3 requests where two 17-cell rows (a 16-long tile) cost 4 or more.
+constexpr int TX = 8, TY = 8, TZ = 32;
 constexpr int TPP = TX * TY * TZ / kBlock;  // particles per thread
-constexpr int WCAP = 8192;                  // LDS window cells (32-bit fixed point, to_fix_w)
+constexpr int WCAP = 8192;                  // LDS window cells (32-bit fixed point, to_fix_w_capped)
 
 // np = N^3, particle (i N + k) N + l started in cell (i, k, l).  The window is the
 // bounding box of the tile's CIC cells when it fits in WCAP cells, else fit_box's
@@ -72,7 +76,7 @@ template <bool P2>
 __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restrict__ pos, float* __restrict__ mesh,
                                                           int n, double w_scale, unsigned* __restrict__ guard,
                                                           const BoxEntry* __restrict__ tab) {
-  static_assert((double)TX * TY * TZ * kFixW < 4294967296.0, "a window cell could wrap");  // 2^31 at most
+  static_assert((double)TX * TY * TZ * (kFixW - 1.0f) < 4294967296.0, "a window cell could wrap");
   __shared__ unsigned win[WCAP];
   __shared__ int wlo[kBlock / 64][3], whi[kBlock / 64][3];
   __shared__ float wsum[kBlock / 64][3];
@@ -136,14 +140,14 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
     const float wxy10 = ax.w1 * ay.w0, wxy11 = ax.w1 * ay.w1;
     if (rx >= 0 && rx <= W[0] - 2 && ry >= 0 && ry <= W[1] - 2 && rz >= 0 && rz <= W[2] - 2) {
       unsigned* w = win + win_index(rx, ry, rz, sx, sy);
-      atomicAdd(w, to_fix_w(wxy00 * az.w0));
-      atomicAdd(w + 1, to_fix_w(wxy00 * az.w1));
-      atomicAdd(w + sy, to_fix_w(wxy01 * az.w0));
-      atomicAdd(w + sy + 1, to_fix_w(wxy01 * az.w1));
-      atomicAdd(w + sx, to_fix_w(wxy10 * az.w0));
-      atomicAdd(w + sx + 1, to_fix_w(wxy10 * az.w1));
-      atomicAdd(w + sx + sy, to_fix_w(wxy11 * az.w0));
-      atomicAdd(w + sx + sy + 1, to_fix_w(wxy11 * az.w1));
+      atomicAdd(w, to_fix_w_capped(wxy00 * az.w0));
+      atomicAdd(w + 1, to_fix_w_capped(wxy00 * az.w1));
+      atomicAdd(w + sy, to_fix_w_capped(wxy01 * az.w0));
+      atomicAdd(w + sy + 1, to_fix_w_capped(wxy01 * az.w1));
+      atomicAdd(w + sx, to_fix_w_capped(wxy10 * az.w0));
+      atomicAdd(w + sx + 1, to_fix_w_capped(wxy10 * az.w1));
+      atomicAdd(w + sx + sy, to_fix_w_capped(wxy11 * az.w0));
+      atomicAdd(w + sx + sy + 1, to_fix_w_capped(wxy11 * az.w1));
     } else {
       const float ws = float(w_scale);
       const int64_t r00 = ax.i0 * n2 + (int64_t)ay.i0 * n, r01 = ax.i0 * n2 + (int64_t)ay.i1 * n;

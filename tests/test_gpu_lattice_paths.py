@@ -28,10 +28,10 @@ pm = pytest.importorskip("paper_2404_02783_amd")
 F32_TOL = 1e-5
 
 # Tile shapes and LDS window capacities (cells) of the tiled kernels: the deposit
-# tile is 8 x 8 x 16 particles (8192 cells); the gather tile 4 x 8 x 32 (4096 cells);
+# tile is 8 x 8 x 32 particles (8192 cells); the gather tile 4 x 8 x 32 (4096 cells);
 # the fused gather-deposit merges two x-adjacent gather tiles into one deposit
 # window (12288 cells).
-DEPOSIT_TILE, DEPOSIT_CAP = (8, 8, 16), 8192
+DEPOSIT_TILE, DEPOSIT_CAP = (8, 8, 32), 8192
 GATHER_TILE, GATHER_CAP = (4, 8, 32), 4096
 FUSED_TILE, FUSED_CAP = (8, 8, 32), 12288
 # gather boxes of more cells than this are staged sparsely (marked cells only)
