@@ -217,6 +217,10 @@ int pm_check(pm_plan* plan, void* stream);
 
 /* Thread-local description of the last error ("" if none). */
 const char* pm_last_error(void);
+/* Not in the paper: the build record, "pmhip <offload arch> sources <sha256>" with
+ * the digest of the library's sources taken when it was compiled (a static string;
+ * callers compare it with the sources they hold to tell a stale build). */
+const char* pm_build_info(void);
 
 /* Per-kernel timing.  While enabled, every kernel launch of the plan is bracketed by
  * a pair of HIP events recorded on the call's stream (so it also times work inside a

@@ -26,7 +26,7 @@ __all__ = [
     "pm_check", "pm_profile_enable", "pm_profile_read", "kdk_factors", "gauge_params", "newton_params",
     "cosmo_hubble_e", "cosmo_omega_m_a", "cosmo_growth", "cosmo_growth_rate", "cosmo_kick", "cosmo_drift",
     "power_eh98_amplitude", "power_law_amplitude", "FIDUCIAL", "LIB_PATH", "log_steps", "leapfrog_factors",
-    "pm_microbench_atomics",
+    "pm_microbench_atomics", "build_info", "build_is_current",
     "PM_F32", "PM_F64", "PM_NEWTON", "PM_POISSON_GAUGE", "PM_GRAD_SPECTRAL", "PM_GRAD_FD2", "PM_GRAD_FD1",
     "PM_PK_POWERLAW", "PM_PK_EH98", "PM_STEP_DEPOSIT_NEXT", "PM_STEP_DENSITY_READY",
 ]
@@ -82,6 +82,7 @@ def _declare(l):
     P = ctypes.POINTER
     sig = {
         "pm_last_error": (ctypes.c_char_p, []),
+        "pm_build_info": (ctypes.c_char_p, []),
         "pm_plan_workspace_bytes": (_c_size_t, [_c_int, _c_int]),
         "pm_plan_create": (_c_int, [P(_c_void_p), _c_int, _c_double, _c_int, _c_void_p, _c_size_t]),
         "pm_plan_workspace_bytes_batch": (_c_size_t, [_c_int, _c_int, _c_int]),
@@ -708,6 +709,17 @@ def pm_microbench_atomics(buf, passes: int = 1):
     if buf.dtype != torch.float32 or not buf.is_cuda or not buf.is_contiguous():
         raise PMError(PM_ERR_ARG, "buf must be a contiguous float32 device tensor")
     _check(lib().pm_microbench_atomics(_c_void_p(buf.data_ptr()), buf.numel(), int(passes), _stream()))
+
+
+def build_info() -> str:
+    """The loaded library's build record: "pmhip <arch> sources <sha256>"."""
+    return lib().pm_build_info().decode()
+
+
+def build_is_current() -> bool:
+    """Whether the loaded library was compiled from the sources in this tree."""
+    from .build import source_digest
+    return build_info().endswith(" sources " + source_digest())
 
 
 def log_steps(a_start: float, a_end: float, n_steps: int):

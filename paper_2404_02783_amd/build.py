@@ -27,9 +27,24 @@ SOURCES = ["fft.hip", "deposit.hip", "particles.hip", "spectra.hip", "adjoint.hi
            "batch.cpp", "microbench.hip"]
 
 
-def _compile(src: str) -> str:
+def source_digest() -> str:
+    """sha256 over every file of csrc/ and include/pmhip.h (names and contents): the
+    build record compiled into the library (pm_build_info) and compared with the
+    tree by the tests and smoke()."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if not f.startswith("."))
+    files.append(os.path.join(os.path.dirname(HERE), "include", "pmhip.h"))
+    for path in files:
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def _compile(src: str, digest: str = "unknown") -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, f'-DPM_SOURCE_DIGEST="{digest}"', f'-DPM_OFFLOAD_ARCH="{ARCH}"', "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -40,8 +55,9 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    digest = source_digest()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, digest), SOURCES))
     tmp = OUT + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,7 +65,7 @@ def build(verbose: bool = True) -> str:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
     if verbose:
-        print(f"built {OUT}")
+        print(f"built {OUT} (sources {digest[:16]})")
     return OUT
 
 

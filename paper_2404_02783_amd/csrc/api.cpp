@@ -161,6 +161,14 @@ using namespace pm;
 
 extern "C" {
 
+#ifndef PM_SOURCE_DIGEST
+#define PM_SOURCE_DIGEST "unknown"
+#endif
+#ifndef PM_OFFLOAD_ARCH
+#define PM_OFFLOAD_ARCH "unknown"
+#endif
+const char* pm_build_info(void) { return "pmhip " PM_OFFLOAD_ARCH " sources " PM_SOURCE_DIGEST; }
+
 const char* pm_last_error(void) { return g_err; }
 
 static size_t density_bytes(int n_mesh, int dtype, int n_batch) {

@@ -57,6 +57,14 @@ def test_host_kick_drift_match_oracle(a0, a1):
     assert (k1, dr, k2) == pytest.approx((o1, odr, o2), rel=1e-12)
 
 
+def test_library_is_built_from_this_tree():
+    """The build record compiled into the library names the digest of the sources in
+    the tree (a stale libpmhip.so fails here: rebuild with __graft_entry__.build())."""
+    info = pm.build_info()
+    assert info.startswith("pmhip gfx950 sources "), info
+    assert pm.build_is_current(), info
+
+
 def test_plan_rejects_misaligned_workspace():
     """A caller workspace must be 256-byte aligned; the check precedes any device work."""
     import ctypes
