@@ -397,7 +397,6 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, co
   __shared__ T xs[3][4][kCombineZ];
   const int jx = blockIdx.z, jy = blockIdx.y, jz0 = blockIdx.x * kBlock;
   const int jz = jz0 + threadIdx.x;
-  const int64_t npf = (int64_t)nf * nf * nf, npc = (int64_t)nc * nc * nc;
   T tx, ty, tz;
   const int qx = lagr_base(jx, nc, nf, tx), qy = lagr_base(jy, nc, nf, ty);
   const int ix[2] = {qx < 0 ? qx + nc : qx, qx + 1 >= nc ? qx + 1 - nc : (qx + 1 < 0 ? qx + 1 + nc : qx + 1)};
@@ -406,6 +405,12 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, co
   const int zlo = lagr_base(jz0, nc, nf, tdummy);
   const int jlast = min(jz0 + kBlock, nf) - 1;
   const int zc = lagr_base(jlast, nc, nf, tdummy) - zlo + 2;  // <= 256 nc/nf + 2
+  // the fine positions do not depend on the staging: load them first
+  const int64_t npf = (int64_t)nf * nf * nf, npc = (int64_t)nc * nc * nc;
+  const int64_t j = ((int64_t)jx * nf + jy) * nf + (jz < nf ? jz : nf - 1);
+  T xfj[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) xfj[d] = xf[d * npf + j];
   for (int e = threadIdx.x; e < 4 * zc; e += kBlock) {
     const int r = e / zc, k = e - r * zc;
     int zi = zlo + k;
@@ -418,7 +423,6 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, co
   __syncthreads();
   if (jz >= nf) return;
   const int kz = lagr_base(jz, nc, nf, tz) - zlo;
-  const int64_t j = ((int64_t)jx * nf + jy) * nf + jz;
   const T t[3] = {tx, ty, tz};
   T xi[3] = {0, 0, 0};
 #pragma unroll
@@ -430,7 +434,7 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, co
   }
   const T ratio = T(nf) / T(nc);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) out[d * npf + j] = wrap(xf[d * npf + j] + ratio * xi[d], nf);
+  for (int d = 0; d < 3; ++d) out[d * npf + j] = wrap(xfj[d] + ratio * xi[d], nf);
 }
 
 // Lattice step of the initial conditions: pos = wrap(q + disp), mom = c * disp,
