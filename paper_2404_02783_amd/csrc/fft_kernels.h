@@ -398,7 +398,26 @@ __global__ void __launch_bounds__(256) k_fft_rows_c2r(const cx<T>* __restrict__ 
     for (int k1 = 0; k1 < L1; ++k1) my[k1 * (L2 + 1) + u] = k1 == 0 ? a[k1] : tw_mul<true>(a[k1], tw, 2 * u * k1);
   }
   __syncthreads();
-  if (u < L1) {
+  if constexpr (L2 == 2 * L1 && TPC == L2) {
+    // stage 2 on every lane of the row: lane u = k1 + L1 s transforms the L1 values
+    // j2 = 2 m + s of column k1 (a half-length DFT), and one radix-2 step with lane
+    // u ^ L1, which holds the other half of the same column, gives outputs k2 = k + L1 s
+    const int k1 = u % L1, sh = u / L1;
+    cx<T> h[L1];
+#pragma unroll
+    for (int m = 0; m < L1; ++m) h[m] = my[k1 * (L2 + 1) + 2 * m + sh];
+    RegDFT<T, L1, 1>::run(h);
+    cx<T>* zdst = reinterpret_cast<cx<T>*>(dst);
+#pragma unroll
+    for (int k = 0; k < L1; ++k) {
+      cx<T> q;
+      q.x = __shfl_xor(h[k].x, L1, TPC);
+      q.y = __shfl_xor(h[k].y, L1, TPC);
+      const cx<T> e = sh ? q : h[k], o = sh ? h[k] : q;
+      const cx<T> wo = k == 0 ? o : tw_mul<true>(o, tw, k * 2 * L1);  // exp(+2 pi i k / L2) o
+      if (valid) stc(zdst + k1 + L1 * (k + sh * L1), sh ? e - wo : e + wo);
+    }
+  } else if (u < L1) {
     cx<T> c[L2];
 #pragma unroll
     for (int j2 = 0; j2 < L2; ++j2) c[j2] = my[u * (L2 + 1) + j2];
