@@ -110,10 +110,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
     const int loc = t + kBlock * p;
     const int li = loc / (AY * AZ), lk = (loc / AZ) % AY, ll = loc % AZ;
     jj[p] = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
-    x[p] = wrap_n<P2>(pos[jj[p]], n);
-    y[p] = wrap_n<P2>(pos[np + jj[p]], n);
-    z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
+    x[p] = pos[jj[p]];
+    y[p] = pos[np + jj[p]];
+    z[p] = pos[2 * np + jj[p]];
   }
+  wrap_all<P2>(x, y, z, n);
   reinterpret_cast<uint4*>(mark)[t] = make_uint4(0u, 0u, 0u, 0u);  // before tile_window's barriers
   const TileWindow tw = tile_window<APP, P2>(x, y, z, n, org, ACAP, AX * AY * AZ, wlo, whi, wsum);
   const int W0 = tw.W[0], W1 = tw.W[1], W2 = tw.W[2];

@@ -96,10 +96,10 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const float* __restric
   for (int p = 0; p < TPP; ++p) {
     const int loc = t + kBlock * p;
     const int li = loc / (TY * TZ), lk = (loc / TZ) % TY, ll = loc % TZ;
-    const int64_t j = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
-    x[p] = pos[j];
-    y[p] = pos[np + j];
-    z[p] = pos[2 * np + j];
+    const unsigned j = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
+    x[p] = ldg32(pos, j);
+    y[p] = ldg32(pos + np, j);
+    z[p] = ldg32(pos + 2 * np, j);
   }
 #pragma unroll
   for (int p = 0; p < TPP; ++p) {

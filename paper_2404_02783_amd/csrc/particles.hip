@@ -139,7 +139,9 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
                                             float (&z)[GPP], unsigned* __restrict__ guard) {
   const int64_t np = (int64_t)n * n * n, n2 = (int64_t)n * n;
   const int t = threadIdx.x;
-  int64_t jj[GPP];
+  unsigned jj[GPP];
+  float *const pos1 = pos + np, *const pos2 = pos + 2 * np, *const mom1 = mom + np, *const mom2 = mom + 2 * np;
+  const float *const force1 = force + fstride, *const force2 = force + 2 * fstride;
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
   float sum[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -147,10 +149,11 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
     const int loc = t + kBlock * p;
     const int li = loc / (GTY * GTZ), lk = (loc / GTZ) % GTY, ll = loc % GTZ;
     jj[p] = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
-    x[p] = wrap_n<P2>(pos[jj[p]], n);
-    y[p] = wrap_n<P2>(pos[np + jj[p]], n);
-    z[p] = wrap_n<P2>(pos[2 * np + jj[p]], n);
+    x[p] = ldg32(pos, jj[p]);
+    y[p] = ldg32(pos1, jj[p]);
+    z[p] = ldg32(pos2, jj[p]);
   }
+  wrap_all<P2>(x, y, z, n);
 #pragma unroll
   for (int p = 0; p < GPP; ++p) {
     const int r[3] = {idiff_n<P2>((int)floorf(x[p]), org[0], n), idiff_n<P2>((int)floorf(y[p]), org[1], n),
@@ -194,9 +197,9 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
   float mx[GPP], my[GPP], mz[GPP];
 #pragma unroll
   for (int p = 0; p < GPP; ++p) {
-    mx[p] = mom[jj[p]];
-    my[p] = mom[np + jj[p]];
-    mz[p] = mom[2 * np + jj[p]];
+    mx[p] = ldg32(mom, jj[p]);
+    my[p] = ldg32(mom1, jj[p]);
+    mz[p] = ldg32(mom2, jj[p]);
   }
   // stage the force window (row-contiguous along z): all of a thread's loads are
   // issued before its first LDS store, so they are in flight together
@@ -211,9 +214,9 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
       win_cell(c, qsx, qsy, a, b, cz);
       const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + o[0] + a, n), fold_n<P2>(org[1] + o[1] + b, n),
                                           fold_n<P2>(org[2] + o[2] + cz, n), n);
-      fa[k] = force[idx];
-      fb[k] = force[fstride + idx];
-      fc[k] = force[2 * fstride + idx];
+      fa[k] = ldg32(force, idx);
+      fb[k] = ldg32(force1, idx);
+      fc[k] = ldg32(force2, idx);
     }
   }
 #pragma unroll
@@ -255,20 +258,21 @@ __device__ __forceinline__ void gather_tile(const float* __restrict__ force, flo
         fz += w0 * force[2 * fstride + a0] + w1 * force[2 * fstride + a1];
       }
     }
-    const int64_t j = jj[p];
+    const unsigned j = jj[p];
     const float px = mx[p] + kick * fx, py = my[p] + kick * fy, pz = mz[p] + kick * fz;
-    mom[j] = px;
-    mom[np + j] = py;
-    mom[2 * np + j] = pz;
+    stg32(mom, j, px);
+    stg32(mom1, j, py);
+    stg32(mom2, j, pz);
     const float ux = x[p] + drift * px, uy = y[p] + drift * py, uz = z[p] + drift * pz;
     if (GUARD && !(isfinite(ux) && isfinite(uy) && isfinite(uz))) atomicAdd(&guard[0], 1u);
     // the new positions replace the old ones in registers (used by the deposit below)
-    x[p] = wrap_n<P2>(ux, n);
-    y[p] = wrap_n<P2>(uy, n);
-    z[p] = wrap_n<P2>(uz, n);
-    pos[j] = x[p];
-    pos[np + j] = y[p];
-    pos[2 * np + j] = z[p];
+    x[p] = ux;
+    y[p] = uy;
+    z[p] = uz;
+    wrap_one<P2>(x[p], y[p], z[p], n);
+    stg32(pos, j, x[p]);
+    stg32(pos1, j, y[p]);
+    stg32(pos2, j, z[p]);
   }
 }
 

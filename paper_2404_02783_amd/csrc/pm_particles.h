@@ -32,6 +32,51 @@ __device__ __forceinline__ T wrap_n(T x, int n) {
   else return wrap(x, n);
 }
 
+// wrap_n of one particle's coordinates (wrap_one) or of all of a thread's (wrap_all).
+// Both wraps return x unchanged for x in [0, N), so when every coordinate of the wave
+// is already there (positions this library wrote, and almost every drift) the wave
+// skips them: a wave-uniform branch on a few compares instead of ~10 operations per
+// coordinate.  Non-finite values fail the compares and take the wrap.
+template <bool P2>
+__device__ __forceinline__ void wrap_one(float& x, float& y, float& z, int n) {
+  const float fn = float(n);
+  if (__all(x >= 0.f && x < fn && y >= 0.f && y < fn && z >= 0.f && z < fn)) return;
+  x = wrap_n<P2>(x, n);
+  y = wrap_n<P2>(y, n);
+  z = wrap_n<P2>(z, n);
+}
+template <bool P2, int PP>
+__device__ __forceinline__ void wrap_all(float (&x)[PP], float (&y)[PP], float (&z)[PP], int n) {
+  const float fn = float(n);
+  bool in = true;
+#pragma unroll
+  for (int p = 0; p < PP; ++p)
+    in = in && x[p] >= 0.f && x[p] < fn && y[p] >= 0.f && y[p] < fn && z[p] >= 0.f && z[p] < fn;
+  if (__all(in)) return;
+#pragma unroll
+  for (int p = 0; p < PP; ++p) {
+    x[p] = wrap_n<P2>(x[p], n);
+    y[p] = wrap_n<P2>(y[p], n);
+    z[p] = wrap_n<P2>(z[p], n);
+  }
+}
+
+// Load and store of element i < 2^30 of a float array in device memory at a
+// wave-uniform base.  The access goes through a global-address-space pointer: a
+// pointer the compiler cannot trace to a kernel argument (e.g. one read from a box
+// table) would otherwise be accessed with flat instructions, which also count
+// against the LDS counter, so every wait for an LDS result would wait for them too.
+// The byte offset fits 32 bits, so the address is the scalar base plus a 32-bit lane
+// offset, without per-lane 64-bit address arithmetic.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ float ldg32(const float* base, unsigned i) {
+  return *reinterpret_cast<const gfloat*>((const gchar*)base + (i << 2));
+}
+__device__ __forceinline__ void stg32(float* base, unsigned i, float v) {
+  *reinterpret_cast<gfloat*>((gchar*)base + (i << 2)) = v;
+}
+
 // CIC base node and weights of one coordinate (x in [0, N)): node floor(x) gets
 // 1 - t and node floor(x) + 1 (mod N) gets t = x - floor(x).
 template <typename T>
