@@ -104,15 +104,15 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
   const int org[3] = {ti * AX, tk * AY, tl * AZ};
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   float x[APP], y[APP], z[APP];
-  int64_t jj[APP];
+  unsigned jj[APP];
 #pragma unroll
   for (int p = 0; p < APP; ++p) {
     const int loc = t + kBlock * p;
     const int li = loc / (AY * AZ), lk = (loc / AZ) % AY, ll = loc % AZ;
     jj[p] = node_index<P2>(org[0] + li, org[1] + lk, org[2] + ll, n);
-    x[p] = pos[jj[p]];
-    y[p] = pos[np + jj[p]];
-    z[p] = pos[2 * np + jj[p]];
+    x[p] = ldg32(pos, jj[p]);
+    y[p] = ldg32(pos + np, jj[p]);
+    z[p] = ldg32(pos + 2 * np, jj[p]);
   }
   wrap_all<P2>(x, y, z, n);
   reinterpret_cast<uint4*>(mark)[t] = make_uint4(0u, 0u, 0u, 0u);  // before tile_window's barriers
@@ -153,9 +153,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
       win_cell(c, qsx, qsy, a, b, cz);
       const unsigned idx = node_index<P2>(fold_n<P2>(org[0] + tw.o[0] + a, n), fold_n<P2>(org[1] + tw.o[1] + b, n),
                                           fold_n<P2>(org[2] + tw.o[2] + cz, n), n);
-      fa[k] = force[idx];
-      fb[k] = force[np + idx];
-      fc[k] = force[2 * np + idx];
+      fa[k] = ldg32(force, idx);
+      fb[k] = ldg32(force + np, idx);
+      fc[k] = ldg32(force + 2 * np, idx);
     }
   }
 #pragma unroll
@@ -172,12 +172,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
   float vmax[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int p = 0; p < APP; ++p) {
-    const int64_t j = jj[p];
+    const unsigned j = jj[p];
     float lx[3], lp[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      lx[d] = lam_pos[d * np + j];
-      lp[d] = lam_mom[d * np + j] + drift * lx[d];
+      lx[d] = ldg32(lam_pos + d * np, j);
+      lp[d] = ldg32(lam_mom + d * np, j) + drift * lx[d];
       v[d][p] = kick * lp[d];
       vmax[d] = fmaxf(vmax[d], fabsf(v[d][p]));
     }
@@ -202,12 +202,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_tiled(const float* __rest
       gy += (by ? s : -s) * wx * wz;
       gz += (bz ? s : -s) * wx * wy;
     }
-    lam_mom[j] = lp[0];
-    lam_mom[np + j] = lp[1];
-    lam_mom[2 * np + j] = lp[2];
-    lam_pos[j] = lx[0] + gx;
-    lam_pos[np + j] = lx[1] + gy;
-    lam_pos[2 * np + j] = lx[2] + gz;
+    stg32(lam_mom, j, lp[0]);
+    stg32(lam_mom + np, j, lp[1]);
+    stg32(lam_mom + 2 * np, j, lp[2]);
+    stg32(lam_pos, j, lx[0] + gx);
+    stg32(lam_pos + np, j, lx[1] + gy);
+    stg32(lam_pos + 2 * np, j, lx[2] + gz);
   }
   // deposit of v over the same box: the force window's LDS becomes the fixed-point window
 #pragma unroll

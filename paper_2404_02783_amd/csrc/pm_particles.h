@@ -121,8 +121,14 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
 // if all of them sit exactly on the same node (to_fix_w_capped, for such windows,
 // keeps every term below 2^21).  The quantum 2^-21 ~ 4.8e-7 of a particle is far
 // below the FP32 rounding of the density it is flushed into.
+// The rounding: for 0 <= w <= 1, w S + 2^23 in one fused multiply-add is rounded to
+// nearest-even once and lands in [2^23, 2^24), where the floats are the integers, so
+// its bits minus those of 2^23 are rint(w S) (one operation instead of a multiply, a
+// rounding and a conversion).
 constexpr float kFixW = 2097152.0f;
-__host__ __device__ __forceinline__ unsigned to_fix_w(float w) { return (unsigned)__builtin_rintf(w * kFixW); }
+__host__ __device__ __forceinline__ unsigned to_fix_w(float w) {
+  return __builtin_bit_cast(unsigned, __builtin_fmaf(w, kFixW, 8388608.0f)) - 0x4B000000u;
+}
 __host__ __device__ __forceinline__ unsigned to_fix_w_capped(float w) {
   const unsigned v = to_fix_w(w);
   return v < 2097151u ? v : 2097151u;
