@@ -159,6 +159,19 @@ class Ensemble:
     def replay(self):
         self.graph.replay()
 
+    def close(self):
+        """Release the captured graph before the batch whose plans, streams and device
+        tables it was captured from (and which it may still reference), then the batch."""
+        self.graph = None
+        if getattr(self, "batch", None) is not None:
+            self.batch.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
     def power_spectra(self):
         """[(k_mean, P, n_modes) per group], each [boxes, bins] on the device."""
         return [st.out for st in self.states]
