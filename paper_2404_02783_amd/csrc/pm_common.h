@@ -203,6 +203,8 @@ struct RegDFT {
       for (int r = 0; r < R; ++r) {
         if (r == 0 || k == 0) {
           t[r] = sub[r][k];
+        } else if (4L * r * k == N) {
+          t[r] = mul_i<DIR>(sub[r][k]);  // W_N^(N/4) = DIR i exactly: no multiply
         } else {
           const T wc = T(ct_cos(long(r) * k, N));
           const T ws = T(DIR * ct_sin(long(r) * k, N));
