@@ -181,6 +181,50 @@ def test_density_handed_over_cycles_fit_box_128():
     _handed_over_cycles(128, 6.0, 96, 1000.0)
 
 
+@pytest.mark.parametrize("n", [128, 192])
+def test_cycle_from_unwrapped_positions(n):
+    """Positions handed over outside [0, N) (about 5 % of the coordinates shifted by
+    +N, 5 % by -N, some exactly N): the tiled kernels wrap them on load (a wave whose
+    coordinates all lie inside skips the wrap, the others take it), so a deposit and a
+    cycle fused with the next deposit match the oracle's, which reads the same values
+    periodically.  The shifts are exact in FP32, so both sides see the same positions.
+    The deposit counts the particles it wrapped back in and pm_check reports them."""
+    dev = _dev()
+    x = _lattice(n, 97, 0.4)
+    r = torch.from_numpy(si.rng(98).random((3, n ** 3)))
+    xu = torch.where(r < 0.05, x + n, torch.where(r > 0.95, x - n, x)).float()
+    xu[0, 1000:1010] = float(n)
+    assert bool(((xu < 0) | (xu >= n)).any())
+    p0 = (0.2 * torch.from_numpy(si.rng(99).standard_normal((3, n ** 3)))).float()
+    box = 1000.0 * n / 128
+    plan = pm.Plan(n, box, torch.float32)
+    outside = int(((xu < 0) | (xu >= n)).any(dim=0).sum())
+    d = pm.pm_deposit(plan, xu.to(dev).contiguous())
+    torch.cuda.synchronize()
+    with pytest.raises(pm.PMError, match=f" {outside} positions outside"):
+        pm.pm_check(plan)
+    assert rel_l2(d, cic.deposit_delta(xu.double(), n)) < F32_TOL
+    force = plan.mesh(3)
+    pos, mom = xu.clone().to(dev).contiguous(), p0.clone().to(dev).contiguous()
+    oracle_force = integrate.NewtonForce(n)
+    xin, pin = xu.double(), p0.double()
+    for j, fl in enumerate([pm.PM_STEP_DEPOSIT_NEXT, pm.PM_STEP_DENSITY_READY]):
+        pm.pm_step(plan, pos, mom, pm.StepParams(kick=0.3, drift=0.4, solve=pm.newton_params(), flags=fl), force)
+        torch.cuda.synchronize()
+        if j == 0:   # this cycle's own deposit read the unwrapped positions
+            with pytest.raises(pm.PMError, match=f" {outside} positions outside"):
+                pm.pm_check(plan)
+        else:        # the handed-over density came from wrapped positions
+            pm.pm_check(plan)
+        wx, wv = integrate.force_then_kick_drift(xin, pin, 0.3, 0.4, oracle_force, 0.0, n)
+        assert rel_l2(mom, wv) < F32_TOL, j
+        px = pos.double().cpu()
+        assert bool(((px >= 0) & (px < n)).all()), j   # written back wrapped
+        dd = min_image(px - wx, n)
+        assert float(torch.linalg.norm(dd)) / float(torch.linalg.norm(wx)) < F32_TOL, j
+        xin, pin = px, mom.double().cpu()
+
+
 @pytest.mark.parametrize("amp", [0.4, 0.8, 6.0])
 def test_step_adjoint_192(amp):
     """Tiled adjoint gather and fixed-point vector deposit at N = 192 against the
