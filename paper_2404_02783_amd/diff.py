@@ -201,6 +201,10 @@ class GraphedModel:
         self.g_fwd.replay()
         return self.out[1]
 
+    def __del__(self):
+        # the captured graphs go before the plan and buffers they were captured from
+        self.g_fwd = self.g_bwd = None
+
     def backward(self, dpk):
         self.dpk.copy_(dpk)
         self.g_bwd.replay()
