@@ -498,7 +498,11 @@ __global__ void __launch_bounds__(256) k_fft_cols_solve(cx<T>* __restrict__ data
       const T k2s = kx * kx + kyz2;
       const bool zero = (nx == 0 && ny == 0 && nz == 0);
       if (KIND == PM_NEWTON) {
-        const T f = zero ? T(0) : T(s.newton) / k2s;
+        // FP32: the hardware reciprocal (1 ulp) instead of an IEEE division (~10 operations
+        // per mode): solve 4.30 -> 4.25 ms at 1024^3
+        T f;
+        if constexpr (sizeof(T) == 4) f = zero ? T(0) : T(s.newton) * __builtin_amdgcn_rcpf(k2s);
+        else f = zero ? T(0) : T(s.newton) / k2s;
         X[k2] = scale(X[k2], f);
       } else {
         // the carried potential keeps the unpadded [N][N][N/2+1] layout of the C ABI
