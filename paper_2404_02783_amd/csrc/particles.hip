@@ -388,57 +388,73 @@ __device__ __forceinline__ int lagr_base(int j, int nc, int nf, T& t) {
   return q;
 }
 
-// Block (x, y, z) of 256 threads handles fine particles (z, y, 256 x + t): one run
-// along the fine z axis, whose CIC corners lie on four coarse z-rows.  The block
-// first stages xi = min-image (x_gr - x_newton) on those rows (the coarse cells its
-// particles touch, zc cells per row) in LDS, then interpolates; the weights and the
-// summation order are those of a direct per-particle evaluation.
+// Block (x, y, z) of 256 threads handles the fine particles (z, G y + g, 256 x + t),
+// g < G: runs along the fine z axis on G adjacent fine y-rows, whose CIC corners lie on
+// two coarse x-rows times at most G + 1 coarse y-rows.  The block first stages xi =
+// min-image (x_gr - x_newton) on those rows (the coarse cells its particles touch, zc
+// cells per row) in LDS, then interpolates; the weights and the summation order are
+// those of a direct per-particle evaluation.  G > 1 shares the staged rows between the
+// fine rows and keeps 3 G fine loads per thread in flight during the staging.
 constexpr int kCombineZ = kBlock + 4;  // staged coarse cells per row (nc <= nf)
 // XI: xg already holds xi (coarse cells) and xn is unused.
-template <typename T, bool XI>
+template <typename T, bool XI, int G>
 __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ xg, const T* __restrict__ xn, int nc,
                                                     const T* __restrict__ xf, int nf, T* __restrict__ out) {
-  __shared__ T xs[3][4][kCombineZ];
-  const int jx = blockIdx.z, jy = blockIdx.y, jz0 = blockIdx.x * kBlock;
+  __shared__ T xs[3][2 * (G + 1)][kCombineZ];
+  const int jx = blockIdx.z, jy0 = blockIdx.y * G, jz0 = blockIdx.x * kBlock;
   const int jz = jz0 + threadIdx.x;
-  T tx, ty, tz;
-  const int qx = lagr_base(jx, nc, nf, tx), qy = lagr_base(jy, nc, nf, ty);
-  const int ix[2] = {qx < 0 ? qx + nc : qx, qx + 1 >= nc ? qx + 1 - nc : (qx + 1 < 0 ? qx + 1 + nc : qx + 1)};
-  const int iy[2] = {qy < 0 ? qy + nc : qy, qy + 1 >= nc ? qy + 1 - nc : (qy + 1 < 0 ? qy + 1 + nc : qy + 1)};
-  T tdummy;
+  const int gy = nf - jy0 < G ? nf - jy0 : G;  // fine y-rows of this block (fewer in a ragged last group)
+  auto wrap_c = [nc](int i) { return i < 0 ? i + nc : (i >= nc ? i - nc : i); };
+  T tx, tdummy;
+  const int qx = lagr_base(jx, nc, nf, tx);
+  const int ix[2] = {wrap_c(qx), wrap_c(qx + 1)};
+  const int qy0 = lagr_base(jy0, nc, nf, tdummy);
+  const int ny = lagr_base(jy0 + gy - 1, nc, nf, tdummy) - qy0 + 2;  // staged coarse y-rows, <= G + 1
   const int zlo = lagr_base(jz0, nc, nf, tdummy);
   const int jlast = min(jz0 + kBlock, nf) - 1;
   const int zc = lagr_base(jlast, nc, nf, tdummy) - zlo + 2;  // <= 256 nc/nf + 2
   // the fine positions do not depend on the staging: load them first
   const int64_t npf = (int64_t)nf * nf * nf, npc = (int64_t)nc * nc * nc;
-  const int64_t j = ((int64_t)jx * nf + jy) * nf + (jz < nf ? jz : nf - 1);
-  T xfj[3];
+  const int jzc = jz < nf ? jz : nf - 1;
+  T xfj[G][3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) xfj[d] = xf[d * npf + j];
-  for (int e = threadIdx.x; e < 4 * zc; e += kBlock) {
-    const int r = e / zc, k = e - r * zc;
-    int zi = zlo + k;
-    zi = zi < 0 ? zi + nc : (zi >= nc ? zi - nc : zi);
-    const int64_t id = ((int64_t)ix[r >> 1] * nc + iy[r & 1]) * nc + zi;
+  for (int g = 0; g < G; ++g) {
+    const int64_t j = ((int64_t)jx * nf + (g < gy ? jy0 + g : jy0)) * nf + jzc;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xfj[g][d] = xf[d * npf + j];
+  }
+  for (int e = threadIdx.x; e < 2 * ny * zc; e += kBlock) {
+    const int r = e / zc, k = e - r * zc;  // staged row r = cx ny + (coarse y-row - qy0)
+    const int cx = r / ny;
+    const int64_t id = ((int64_t)ix[cx] * nc + wrap_c(qy0 + r - cx * ny)) * nc + wrap_c(zlo + k);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
       xs[d][r][k] = XI ? xg[d * npc + id] : min_image(xg[d * npc + id] - xn[d * npc + id], nc);
   }
   __syncthreads();
   if (jz >= nf) return;
+  T tz;
   const int kz = lagr_base(jz, nc, nf, tz) - zlo;
-  const T t[3] = {tx, ty, tz};
-  T xi[3] = {0, 0, 0};
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int cx_ = (c >> 2) & 1, cy_ = (c >> 1) & 1, cz_ = c & 1;
-    const T w = (cx_ ? t[0] : T(1) - t[0]) * (cy_ ? t[1] : T(1) - t[1]) * (cz_ ? t[2] : T(1) - t[2]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) xi[d] += w * xs[d][cx_ * 2 + cy_][kz + cz_];
-  }
   const T ratio = T(nf) / T(nc);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) out[d * npf + j] = wrap(xfj[d] + ratio * xi[d], nf);
+  for (int g = 0; g < G; ++g) {
+    if (g >= gy) break;
+    const int jy = jy0 + g;
+    T ty;
+    const int ry = lagr_base(jy, nc, nf, ty) - qy0;
+    const T t[3] = {tx, ty, tz};
+    T xi[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int cx_ = (c >> 2) & 1, cy_ = (c >> 1) & 1, cz_ = c & 1;
+      const T w = (cx_ ? t[0] : T(1) - t[0]) * (cy_ ? t[1] : T(1) - t[1]) * (cz_ ? t[2] : T(1) - t[2]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xi[d] += w * xs[d][cx_ * ny + ry + cy_][kz + cz_];
+    }
+    const int64_t j = ((int64_t)jx * nf + jy) * nf + jz;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[d * npf + j] = wrap(xfj[g][d] + ratio * xi[d], nf);
+  }
 }
 
 // Lattice step of the initial conditions: pos = wrap(q + disp), mom = c * disp,
@@ -572,13 +588,17 @@ int launch_gather_kdk(const pm_plan* p, const void* force, void* pos, void* mom,
 int launch_combine(const void* x_gr, const void* x_n, int nc, const void* x_f, int nf, int dtype, void* x_out,
                    hipStream_t s) {
   // x_n == nullptr: x_gr holds xi itself
-  const dim3 grid((unsigned)((nf + kBlock - 1) / kBlock), (unsigned)nf, (unsigned)nf);
+  // FP32: four fine y-rows per block (31 KB of LDS); FP64: one (25 KB)
+  constexpr int G4 = 4;
+  const unsigned gz = (unsigned)((nf + kBlock - 1) / kBlock);
   if (dtype == PM_F32) {
-    auto kern = x_n ? k_combine<float, false> : k_combine<float, true>;
+    const dim3 grid(gz, (unsigned)((nf + G4 - 1) / G4), (unsigned)nf);
+    auto kern = x_n ? k_combine<float, false, G4> : k_combine<float, true, G4>;
     hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, static_cast<const float*>(x_gr), static_cast<const float*>(x_n),
                        nc, static_cast<const float*>(x_f), nf, static_cast<float*>(x_out));
   } else {
-    auto kern = x_n ? k_combine<double, false> : k_combine<double, true>;
+    const dim3 grid(gz, (unsigned)nf, (unsigned)nf);
+    auto kern = x_n ? k_combine<double, false, 1> : k_combine<double, true, 1>;
     hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, static_cast<const double*>(x_gr),
                        static_cast<const double*>(x_n), nc, static_cast<const double*>(x_f), nf,
                        static_cast<double*>(x_out));
