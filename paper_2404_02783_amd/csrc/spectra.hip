@@ -147,8 +147,9 @@ __global__ void __launch_bounds__(kBlock) k_ic_symbol(cx<T>* __restrict__ c0, cx
 __device__ __forceinline__ int pk_bin(int64_t n2, int n, int nb) {
   const int64_t s = 16LL * nb * nb * n2;
   const int64_t nn = (int64_t)n * n;
-  // (2b+1) <= 4 nb |n| / N  -> b ~ floor((4 nb |n|/N - 1)/2)
-  int b = (int)floor((4.0 * nb * sqrt((double)n2) / n - 1.0) * 0.5);
+  // (2b+1) <= 4 nb |n| / N  -> b ~ floor((4 nb |n|/N - 1)/2), a first guess that the
+  // exact integer tests below correct
+  int b = (int)floor((sqrt((double)n2) * (4.0 * nb / n) - 1.0) * 0.5);
   if (b < 0) b = 0;
   for (int it = 0; it < 3; ++it) {
     const int64_t lo = nn * (2LL * b + 1) * (2LL * b + 1);
@@ -183,43 +184,47 @@ __global__ void __launch_bounds__(kBlock) k_pk_reduce(const cx<T>* __restrict__ 
   }
   __syncthreads();
   const int h = hp;  // padded row stride; columns iz > N/2 are padding
-  const int64_t total = (int64_t)n * n * h;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // Each thread walks modes; runs of the same bin are merged in registers.
+  // One wave per spectrum row (ix, iy), its lanes along iz (coalesced): the row's
+  // coordinates are computed once, not recovered per mode by divisions.  Each thread's
+  // runs of the same bin are merged in registers.
+  const int lane = threadIdx.x & 63, waves = blockDim.x >> 6;
+  const int nrows = n * n;
   int cur = -1;
   double ap = 0.0, ak = 0.0;
   unsigned long long ac = 0;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-    const int iz = (int)(idx % h);
-    if (iz > n / 2) continue;
-    const int iy = (int)((idx / h) % n);
-    const int ix = (int)(idx / ((int64_t)h * n));
+  for (int row = blockIdx.x * waves + (threadIdx.x >> 6); row < nrows; row += gridDim.x * waves) {
+    const int ix = row / n, iy = row - ix * n;
     const int nx = signed_freq(ix, n), ny = signed_freq(iy, n);
-    const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)iz * iz;
-    const int b = n2 > 0 ? pk_bin(n2, n, nb) : -1;
-    if (b < 0) continue;
-    const int wgt = (iz == 0 || iz == n / 2) ? 1 : 2;
-    const cx<T> v = ldc(dhat + idx);
-    double p2;
-    if (CROSS) {
-      const cx<T> u = ldc(bhat + idx);
-      p2 = (double)v.x * u.x + (double)v.y * u.y;
-    } else {
-      p2 = (double)v.x * v.x + (double)v.y * v.y;
-    }
-    if (b != cur) {
-      if (cur >= 0) {
-        atomicAdd(&sp[cur], ap);
-        atomicAdd(&sk[cur], ak);
-        atomicAdd(&sc[cur], ac);
+    const int64_t nxy2 = (int64_t)nx * nx + (int64_t)ny * ny;
+    const cx<T>* drow = dhat + (int64_t)row * h;
+    const cx<T>* brow = CROSS ? bhat + (int64_t)row * h : nullptr;
+    for (int iz = lane; iz <= n / 2; iz += 64) {
+      const int64_t n2 = nxy2 + (int64_t)iz * iz;
+      const int b = n2 > 0 ? pk_bin(n2, n, nb) : -1;
+      if (b < 0) continue;
+      const int wgt = (iz == 0 || iz == n / 2) ? 1 : 2;
+      const cx<T> v = ldc(drow + iz);
+      double p2;
+      if (CROSS) {
+        const cx<T> u = ldc(brow + iz);
+        p2 = (double)v.x * u.x + (double)v.y * u.y;
+      } else {
+        p2 = (double)v.x * v.x + (double)v.y * v.y;
       }
-      cur = b;
-      ap = ak = 0.0;
-      ac = 0;
+      if (b != cur) {
+        if (cur >= 0) {
+          atomicAdd(&sp[cur], ap);
+          atomicAdd(&sk[cur], ak);
+          atomicAdd(&sc[cur], ac);
+        }
+        cur = b;
+        ap = ak = 0.0;
+        ac = 0;
+      }
+      ap += wgt * p2;
+      ak += wgt * sqrt((double)n2);
+      ac += (unsigned long long)wgt;
     }
-    ap += wgt * p2;
-    ak += wgt * sqrt((double)n2);
-    ac += (unsigned long long)wgt;
   }
   if (cur >= 0) {
     atomicAdd(&sp[cur], ap);
